@@ -1,0 +1,166 @@
+/*
+ * qsa.h -- C ABI of the MI355X quasistatic (QSA) particle-in-cell hot path.
+ *
+ * Physics and units (paper, "Quasistatic model" section): a relativistic beam
+ * of species s (charge Z_s e, mass M_s m_e, density ratio alpha_s = n_bs/n_p,
+ * common Lorentz factor gamma_b) crosses a plasma of initially cold or warm
+ * electrons over immobile ions.  Comoving coordinates (xi, tau) = (ct - z, t);
+ * the plasma/field response is quasistatic in xi at fixed tau and the beam
+ * evolves slowly in tau.  All quantities are normalized: lengths to c/omega_p,
+ * times to 1/omega_p, densities to n_p, momenta u = p/(M m_e c), fields to
+ * m_e c omega_p/e.  The propagation axis is z (the paper's x); transverse
+ * boundaries are periodic and xi is open ("PIC simulations" section).
+ *
+ * One context = one simulation box on one GPU.  Per xi slice the library
+ * deposits the plasma charge and current, solves the transverse
+ * Poisson/Helmholtz problems for psi = phi - A_z (minus the paper's Psi,
+ * defined after its Eq. (2)), E_z, B_z and B_perp by FFT, and advances the
+ * plasma macro-particles to the next slice with a predictor-corrector; the
+ * beam is then advanced by one Boris step of length dt in the stored 3D
+ * fields.
+ *
+ * Memory and ownership
+ *   - The caller owns one device workspace of qsa_workspace_bytes() bytes
+ *     (256-byte aligned) and the HIP stream; the library carves all of its
+ *     device state out of the workspace and allocates no device memory.
+ *   - The library owns only the host-side qsa_ctx; qsa_destroy frees it and
+ *     never touches the workspace.
+ *   - Every call enqueues work on the stream and returns without waiting,
+ *     except the calls documented as synchronizing.
+ *   - A context is used from one host thread at a time.
+ *
+ * Errors
+ *   - Invalid arguments, an undersized workspace or a wrong call order are
+ *     reported at once by the return code.
+ *   - Conditions found on the device (1 + psi <= 1e-3 at a plasma particle,
+ *     i.e. quasistatic breakdown, or a non-finite value there) set a sticky
+ *     device flag; the next synchronizing call returns QSA_E_BREAKDOWN and
+ *     every later call returns it too, until qsa_destroy.
+ *   - qsa_last_error() gives a readable reason for the last failure.
+ *
+ * Layouts
+ *   - Grids are row-major [xi][y][x] (x fastest), nx*ny values per slice.
+ *   - Particle arrays are structure-of-arrays, one float64 array per
+ *     component; the library converts to its working precision.
+ */
+#ifndef QSA_H
+#define QSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qsa_ctx qsa_ctx;
+
+typedef enum {
+  QSA_OK = 0,
+  QSA_E_INVALID = -1,    /* bad parameter or argument                      */
+  QSA_E_NOMEM = -2,      /* workspace smaller than qsa_workspace_bytes()   */
+  QSA_E_DEVICE = -3,     /* a HIP runtime call failed                       */
+  QSA_E_BREAKDOWN = -4,  /* 1 + psi <= 1e-3 or non-finite at a particle     */
+  QSA_E_NONFINITE = -5,  /* non-finite value in loaded particle data        */
+  QSA_E_STATE = -6       /* call out of order (e.g. no plasma loaded)       */
+} qsa_status;
+
+enum { QSA_FP64 = 0, QSA_FP32 = 1 };
+
+/* Field identifiers for qsa_fields().  The library stores psi, d_x psi,
+ * d_y psi, E_z, B_x, B_y, B_z per slice; E_x = -d_x psi + B_y and
+ * E_y = -d_y psi - B_x are formed on output.  QSA_SRC_* are the beam
+ * sources (rho - J_z, J_x, J_y, J_z) of the last sweep. */
+enum {
+  QSA_PSI = 0, QSA_EX = 1, QSA_EY = 2, QSA_EZ = 3, QSA_BX = 4, QSA_BY = 5,
+  QSA_BZ = 6, QSA_DXPSI = 7, QSA_DYPSI = 8,
+  QSA_SRC_S = 9, QSA_SRC_JX = 10, QSA_SRC_JY = 11, QSA_SRC_JZ = 12
+};
+
+#define QSA_MAX_SPECIES 4
+
+typedef struct {
+  int32_t Z;        /* charge number: -1 electron, +1 positron              */
+  int32_t pad_;
+  double M;         /* mass in electron masses                              */
+} qsa_species;
+
+/* Problem statement in normalized units (see header comment). */
+typedef struct {
+  int32_t nx, ny;        /* transverse cells, powers of two; nx in [8, 1024],
+                            ny = 1 (slab in x) or ny in [8, 1024]           */
+  int32_t nxi;           /* xi slices (>= 2); the head of the box is xi = 0  */
+  int32_t precision;     /* QSA_FP64 or QSA_FP32                             */
+  double dx, dy, dxi;    /* cell sizes in c/omega_p (dy is the slab depth)   */
+  double dt;             /* beam time step in 1/omega_p                      */
+  int32_t n_corr;        /* predictor-corrector iterations for B_perp (>= 0) */
+  int32_t n_species;     /* beam species, 1..QSA_MAX_SPECIES                 */
+  double kappa2;         /* Helmholtz shift of the B_perp iteration (> 0)    */
+  int64_t n_plasma;      /* plasma macro-particles per slice (> 0)           */
+  double plasma_w;       /* their common weight: area per particle (> 0)     */
+  qsa_species species[QSA_MAX_SPECIES];
+  int64_t beam_capacity[QSA_MAX_SPECIES]; /* max particles per species (>= 0) */
+} qsa_params;
+
+/* Bytes of device workspace a context with these parameters needs; 0 if the
+ * parameters are invalid. */
+size_t qsa_workspace_bytes(const qsa_params* p);
+
+/* Create a context.  dev_ws: device pointer to >= qsa_workspace_bytes(p)
+ * bytes, 256-byte aligned; hip_stream: a hipStream_t (NULL = default
+ * stream).  On success *out holds the context.  Synchronizing (it uploads
+ * transform tables). */
+qsa_status qsa_create(const qsa_params* p, void* dev_ws, size_t ws_bytes,
+                      void* hip_stream, qsa_ctx** out);
+
+/* Load the plasma template: the n = p->n_plasma macro-particles that enter
+ * every slice sweep at xi = 0 (positions x, y in [0, L), momenta u_x, u_y;
+ * u_z follows from gamma - u_z = 1).  Arrays are float64, host memory when
+ * on_device = 0 (the call then synchronizes), device memory otherwise.
+ * Returns QSA_E_NONFINITE for a non-finite host value. */
+qsa_status qsa_load_plasma(qsa_ctx* c, const double* x, const double* y,
+                           const double* ux, const double* uy, int64_t n,
+                           int32_t on_device);
+
+/* Load n (<= capacity) particles of beam species s: position (x, y, xi),
+ * momentum (u_x, u_y, u_z) and weight w (number of physical particles per
+ * unit n_p, i.e. alpha dV/ppc for a uniform beam).  A particle with w = 0 is
+ * inert.  Float64 arrays, host (synchronizing) or device memory. */
+qsa_status qsa_load_beam(qsa_ctx* c, int32_t s, const double* x,
+                         const double* y, const double* xi, const double* ux,
+                         const double* uy, const double* uz, const double* w,
+                         int64_t n, int32_t on_device);
+
+/* Copy the current particles of species s out as float64 (7 arrays of at
+ * least *n entries; cap = their length).  Synchronizing when on_device = 0. */
+qsa_status qsa_read_beam(qsa_ctx* c, int32_t s, double* x, double* y,
+                         double* xi, double* ux, double* uy, double* uz,
+                         double* w, int64_t cap, int64_t* n, int32_t on_device);
+
+/* One quasistatic sweep at the current tau: beam sources from the beam
+ * particles, then the plasma response slice by slice from xi = 0 to the
+ * tail.  Fields of every slice are kept until the next sweep. */
+qsa_status qsa_slice_sweep(qsa_ctx* c);
+
+/* n_steps x (qsa_slice_sweep; Boris push of every beam species by dt). */
+qsa_status qsa_beam_step(qsa_ctx* c, int32_t n_steps);
+
+/* Copy slices [xi0, xi1) of one field of the last sweep as float64 into dst
+ * (count >= (xi1 - xi0) * nx * ny values), host or device memory.
+ * Synchronizing; reports a pending device error. */
+qsa_status qsa_fields(qsa_ctx* c, int32_t field, int32_t xi0, int32_t xi1,
+                      double* dst, size_t count, int32_t dst_on_device);
+
+/* Wait for the stream and report any pending device error. */
+qsa_status qsa_sync(qsa_ctx* c);
+
+/* Free the host context (the workspace is not touched). */
+qsa_status qsa_destroy(qsa_ctx* c);
+
+const char* qsa_status_string(qsa_status s);
+const char* qsa_last_error(const qsa_ctx* c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSA_H */

@@ -1,0 +1,11 @@
+"""MI355X-native quasistatic particle-in-cell hot path (HIP, gfx950).
+
+The compute lives in libqsa.so (C ABI in include/qsa.h); this package is its
+thin Python binding.  Importing the binding does not need a GPU; creating a
+Sim does, and fails loudly if the library has not been built.
+"""
+from ._lib import FIELD_IDS, QSAError, QSAParams, lib  # noqa: F401
+from .sim import Sim, make_params, params_from_workload  # noqa: F401
+
+__all__ = ["Sim", "make_params", "params_from_workload", "QSAError", "QSAParams", "lib",
+           "FIELD_IDS"]

@@ -1,0 +1,50 @@
+"""Build libqsa.so (the HIP library behind include/qsa.h) in-tree for gfx950."""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB = os.path.join(HERE, "libqsa.so")
+SOURCES = [os.path.join(HERE, "csrc", "qsa.hip")]
+DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("qsa_device.h", "qsa_kernels.h")] + \
+    [os.path.join(ROOT, "include", "qsa.h")]
+
+
+def hipcc() -> str:
+    p = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    return p
+
+
+def command(out: str = LIB):
+    return [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+            "-munsafe-fp-atomics", "-ffp-contract=fast",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wno-unused-command-line-argument",
+            "-I", os.path.join(ROOT, "include"), *SOURCES, "-o", out]
+
+
+def build(verbose: bool = True) -> str:
+    """Compile libqsa.so (always; the build is the compile check)."""
+    tmp = LIB + ".tmp"
+    cmd = command(tmp)
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building libqsa.so")
+    if verbose and r.stderr.strip():
+        # hipcc's host pass warns about the device-only target feature
+        lines = [l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l]
+        if any(l.strip() for l in lines):
+            sys.stderr.write("\n".join(lines) + "\n")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()

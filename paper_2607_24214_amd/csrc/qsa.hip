@@ -1,0 +1,747 @@
+// Host runtime and C ABI of the QSA slice sweep (see include/qsa.h).
+//
+// The context carves every device array out of the caller's workspace, keeps
+// the host-side state (loaded particle counts, error state) and enqueues the
+// kernels of qsa_kernels.h on the caller's stream.  One sweep is
+// 4 + 4 + 4K + 1 dependent launches per xi slice.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qsa.h"
+#include "qsa_kernels.h"
+
+using namespace qsa;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxN = 512;
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// Byte offsets of every device array inside the workspace.
+struct Layout {
+  size_t twx, twy, kx2, kdx, ky2, kdy;
+  size_t tmpl[4], pl[4];
+  size_t beam[QSA_MAX_SPECIES][7];  // x, y, ux, uy, uz, w (real), xi (double)
+  size_t src, fields, dep, rowspec, colout, jring, jz, bring, ode, err, emit;
+  size_t total;
+};
+
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += (bytes + kAlign - 1) / kAlign * kAlign;
+    return o;
+  }
+};
+
+Layout make_layout(const qsa_params& p) {
+  const size_t rs = (p.precision == QSA_FP32) ? 4 : 8;
+  const size_t cs = 2 * rs;
+  const size_t nperp = (size_t)p.nx * p.ny;
+  const size_t nxh = (size_t)p.nx / 2 + 1;
+  const size_t spec = (size_t)p.ny * nxh * cs;
+  Layout L;
+  Carver c;
+  L.twx = c.take(p.nx * cs);
+  L.twy = c.take(p.ny * cs);
+  L.kx2 = c.take(nxh * rs);
+  L.kdx = c.take(nxh * rs);
+  L.ky2 = c.take(p.ny * rs);
+  L.kdy = c.take(p.ny * rs);
+  for (int i = 0; i < 4; ++i) L.tmpl[i] = c.take(p.n_plasma * rs);
+  for (int i = 0; i < 4; ++i) L.pl[i] = c.take(p.n_plasma * rs);
+  for (int s = 0; s < QSA_MAX_SPECIES; ++s) {
+    const size_t cap = (s < p.n_species) ? (size_t)p.beam_capacity[s] : 0;
+    for (int k = 0; k < 6; ++k) L.beam[s][k] = c.take(cap * rs);
+    L.beam[s][6] = c.take(cap * 8);
+  }
+  L.src = c.take(4 * (size_t)p.nxi * nperp * rs);
+  L.fields = c.take((size_t)N_STORED * p.nxi * nperp * rs);
+  L.dep = c.take(3 * nperp * rs);
+  L.rowspec = c.take(4 * spec);
+  L.colout = c.take(4 * spec);
+  L.jring = c.take(4 * spec);
+  L.jz = c.take(spec);
+  L.bring = c.take(6 * spec);
+  L.ode = c.take(2 * sizeof(double));
+  L.err = c.take(sizeof(int));
+  L.emit = c.take(nperp * sizeof(double));
+  L.total = c.off;
+  return L;
+}
+
+const char* validate(const qsa_params* p) {
+  if (!p) return "null parameters";
+  if (p->precision != QSA_FP64 && p->precision != QSA_FP32) return "precision must be QSA_FP64 or QSA_FP32";
+  if (!pow2(p->nx) || p->nx < 8 || p->nx > kMaxN) return "nx must be a power of two in [8, 512]";
+  if (!(p->ny == 1 || (pow2(p->ny) && p->ny >= 8 && p->ny <= kMaxN)))
+    return "ny must be 1 (slab) or a power of two in [8, 512]";
+  if (p->nxi < 2) return "nxi must be >= 2";
+  if (!(p->dx > 0) || !(p->dy > 0) || !(p->dxi > 0)) return "cell sizes must be > 0";
+  if (!(p->dt > 0) || !std::isfinite(p->dt)) return "dt must be finite and > 0";
+  if (p->n_corr < 0 || p->n_corr > 64) return "n_corr must be in [0, 64]";
+  if (!(p->kappa2 > 0)) return "kappa2 must be > 0";
+  if (p->n_plasma <= 0 || p->n_plasma > (int64_t)1 << 30) return "n_plasma must be in [1, 2^30]";
+  if (!(p->plasma_w > 0)) return "plasma_w must be > 0";
+  if (p->n_species < 1 || p->n_species > QSA_MAX_SPECIES) return "n_species must be in [1, 4]";
+  for (int s = 0; s < p->n_species; ++s) {
+    if (p->beam_capacity[s] < 0) return "beam capacity must be >= 0";
+    if (!(p->species[s].M > 0)) return "species mass must be > 0";
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+struct qsa_ctx {
+  qsa_params p;
+  Layout L;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int64_t beam_n[QSA_MAX_SPECIES] = {0, 0, 0, 0};
+  bool plasma_loaded = false;
+  bool swept = false;
+  qsa_status sticky = QSA_OK;
+  std::string err;
+  template <typename T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+static qsa_status fail(qsa_ctx* c, qsa_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIP_OK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      c->sticky = QSA_E_DEVICE;                                                        \
+      return fail(c, QSA_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    }                                                                                  \
+  } while (0)
+
+namespace {
+
+template <typename R>
+struct Engine {
+  static Geo<R> geo(const qsa_params& p) {
+    Geo<R> g;
+    g.nx = p.nx;
+    g.ny = p.ny;
+    g.nxi = p.nxi;
+    g.nxh = p.nx / 2 + 1;
+    g.nperp = p.nx * p.ny;
+    g.lgx = ilog2(p.nx);
+    g.lgy = ilog2(p.ny);
+    g.dx = (R)p.dx;
+    g.dy = (R)p.dy;
+    g.dxi = (R)p.dxi;
+    g.inv_dx = (R)(1.0 / p.dx);
+    g.inv_dy = (R)(1.0 / p.dy);
+    g.lx = (R)(p.nx * p.dx);
+    g.ly = (R)(p.ny * p.dy);
+    g.inv_lx = (R)(1.0 / (p.nx * p.dx));
+    g.inv_ly = (R)(1.0 / (p.ny * p.dy));
+    return g;
+  }
+
+  // transform and wavenumber tables, computed in long double on the host
+  static void tables(const qsa_params& p, std::vector<char>& twx, std::vector<char>& twy,
+                     std::vector<char>& kx2, std::vector<char>& kdx, std::vector<char>& ky2,
+                     std::vector<char>& kdy) {
+    auto tw = [](int n, std::vector<char>& out) {
+      out.resize(n * sizeof(C2<R>));
+      C2<R>* t = reinterpret_cast<C2<R>*>(out.data());
+      const long double pi = 3.141592653589793238462643383279502884L;
+      for (int m = 0; m < n; ++m) {
+        long double a = 2.0L * pi * (long double)m / (long double)n;
+        t[m].x = (R)cosl(a);
+        t[m].y = (R)(-sinl(a));
+      }
+    };
+    tw(p.nx, twx);
+    tw(p.ny, twy);
+    const int nxh = p.nx / 2 + 1;
+    kx2.resize(nxh * sizeof(R));
+    kdx.resize(nxh * sizeof(R));
+    ky2.resize(p.ny * sizeof(R));
+    kdy.resize(p.ny * sizeof(R));
+    R* a = reinterpret_cast<R*>(kx2.data());
+    R* b = reinterpret_cast<R*>(kdx.data());
+    const double twopi = 6.283185307179586;
+    for (int m = 0; m < nxh; ++m) {
+      const int ms = (m == p.nx / 2) ? -m : m;  // Nyquist index is m = -nx/2
+      const double k = 2.0 * M_PI * ms / (p.nx * p.dx);
+      a[m] = (R)(k * k);
+      b[m] = (m == p.nx / 2) ? R(0) : (R)k;
+    }
+    (void)twopi;
+    R* cc = reinterpret_cast<R*>(ky2.data());
+    R* d = reinterpret_cast<R*>(kdy.data());
+    for (int m = 0; m < p.ny; ++m) {
+      const int ms = (m < (p.ny + 1) / 2) ? m : m - p.ny;
+      const double k = 2.0 * M_PI * ms / (p.ny * p.dy);
+      cc[m] = (R)(k * k);
+      d[m] = (p.ny > 1 && m == p.ny / 2) ? R(0) : (R)k;
+    }
+  }
+
+  static int fill_blocks(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (int)b;
+  }
+
+  static qsa_status fill(qsa_ctx* c, R* p, int64_t n, R v) {
+    if (n <= 0) return QSA_OK;
+    hipLaunchKernelGGL(k_fill<R>, dim3(fill_blocks(n)), dim3(256), 0, c->stream, p, n, v);
+    HIP_OK(hipGetLastError());
+    return QSA_OK;
+  }
+
+  // ---- launches of the per-slice kernels --------------------------------
+  static void row_r2c(qsa_ctx* c, const Geo<R>& g, const RowR2CArgs<R>& a, int nf) {
+    const int tpt = g.nx >> 2;
+    const int ppw = (256 / tpt) > 0 ? 256 / tpt : 1;
+    const int npairs = (g.ny + 1) >> 1;
+    const dim3 grid((npairs + ppw - 1) / ppw, nf);
+    const size_t smem = 2 * (size_t)ppw * g.nx * sizeof(C2<R>);
+    hipLaunchKernelGGL(k_row_r2c<R>, grid, dim3(ppw * tpt), smem, c->stream, g, a,
+                       c->at<C2<R>>(c->L.twx), ppw);
+  }
+  static void row_c2r(qsa_ctx* c, const Geo<R>& g, const RowC2RArgs<R>& a, int nf) {
+    const int tpt = g.nx >> 2;
+    const int ppw = (256 / tpt) > 0 ? 256 / tpt : 1;
+    const int npairs = (g.ny + 1) >> 1;
+    const dim3 grid((npairs + ppw - 1) / ppw, nf);
+    const size_t smem = 2 * (size_t)ppw * g.nx * sizeof(C2<R>);
+    hipLaunchKernelGGL(k_row_c2r<R>, grid, dim3(ppw * tpt), smem, c->stream, g, a,
+                       c->at<C2<R>>(c->L.twx), ppw);
+  }
+  template <int MODE>
+  static void col(qsa_ctx* c, const Geo<R>& g, const ColArgs<R>& a) {
+    const int tpt = (g.ny >= 4) ? (g.ny >> 2) : 1;
+    const int cpw = (tpt >= 64) ? 1 : 64 / tpt;
+    const dim3 grid((g.nxh + cpw - 1) / cpw);
+    const size_t smem = (size_t)cpw * ColShape<MODE>::NB * g.ny * sizeof(C2<R>);
+    hipLaunchKernelGGL((k_col<R, MODE>), grid, dim3(cpw * tpt), smem, c->stream, g, a,
+                       c->at<C2<R>>(c->L.twy), cpw);
+  }
+
+  static qsa_status beam_deposit_all(qsa_ctx* c, const Geo<R>& g) {
+    const qsa_params& p = c->p;
+    R* src = c->at<R>(c->L.src);
+    qsa_status st = fill(c, src, 4 * (int64_t)p.nxi * g.nperp, R(0));
+    if (st != QSA_OK) return st;
+    for (int s = 0; s < p.n_species; ++s) {
+      if (c->beam_n[s] == 0) continue;
+      BeamArgs<R> a = beam_args(c, g, s);
+      const int64_t blocks = (a.n + 255) / 256;
+      hipLaunchKernelGGL(k_beam_deposit<R>, dim3((unsigned)blocks), dim3(256), 0, c->stream, g, a);
+    }
+    HIP_OK(hipGetLastError());
+    return QSA_OK;
+  }
+
+  static BeamArgs<R> beam_args(qsa_ctx* c, const Geo<R>& g, int s) {
+    const qsa_params& p = c->p;
+    BeamArgs<R> a;
+    a.x = c->at<R>(c->L.beam[s][0]);
+    a.y = c->at<R>(c->L.beam[s][1]);
+    a.ux = c->at<R>(c->L.beam[s][2]);
+    a.uy = c->at<R>(c->L.beam[s][3]);
+    a.uz = c->at<R>(c->L.beam[s][4]);
+    a.w = c->at<R>(c->L.beam[s][5]);
+    a.xi = c->at<double>(c->L.beam[s][6]);
+    a.n = c->beam_n[s];
+    a.src = c->at<R>(c->L.src);
+    a.fields = c->at<R>(c->L.fields);
+    a.zq = (R)(p.species[s].Z / (p.dx * p.dy * p.dxi));
+    a.qmh = (R)((double)p.species[s].Z / p.species[s].M * 0.5 * p.dt);
+    a.dt = (R)p.dt;
+    a.inv_dxi = 1.0 / p.dxi;
+    a.xi_max = (double)(p.nxi - 1) * p.dxi;
+    return a;
+  }
+
+  static qsa_status sweep(qsa_ctx* c) {
+    const qsa_params& p = c->p;
+    const Geo<R> g = geo(p);
+    const Layout& L = c->L;
+    const int64_t plane = (int64_t)p.nxi * g.nperp;
+    const size_t spec = (size_t)g.ny * g.nxh;  // complex elements per spectrum
+    qsa_status st = beam_deposit_all(c, g);
+    if (st != QSA_OK) return st;
+    // plasma enters unperturbed; rings and wake state start at zero
+    {
+      const int np = (int)p.n_plasma;
+      hipLaunchKernelGGL(k_copy4<R>, dim3((np + 255) / 256), dim3(256), 0, c->stream,
+                         c->at<R>(L.tmpl[0]), c->at<R>(L.tmpl[1]), c->at<R>(L.tmpl[2]),
+                         c->at<R>(L.tmpl[3]), c->at<R>(L.pl[0]), c->at<R>(L.pl[1]),
+                         c->at<R>(L.pl[2]), c->at<R>(L.pl[3]), np);
+      HIP_OK(hipGetLastError());
+    }
+    if ((st = fill(c, c->at<R>(L.jring), (int64_t)4 * spec * 2, R(0))) != QSA_OK) return st;
+    if ((st = fill(c, c->at<R>(L.bring), (int64_t)6 * spec * 2, R(0))) != QSA_OK) return st;
+    if ((st = fill(c, c->at<R>(L.dep), (int64_t)3 * g.nperp, R(0))) != QSA_OK) return st;
+    hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(64), 0, c->stream, c->at<double>(L.ode), (int64_t)2, 0.0);
+    HIP_OK(hipGetLastError());
+
+    R* fields = c->at<R>(L.fields);
+    R* src = c->at<R>(L.src);
+    R* dep = c->at<R>(L.dep);
+    C2<R>* rowspec = c->at<C2<R>>(L.rowspec);
+    C2<R>* colout = c->at<C2<R>>(L.colout);
+    C2<R>* jring = c->at<C2<R>>(L.jring);
+    C2<R>* bring = c->at<C2<R>>(L.bring);
+    C2<R>* jzs = c->at<C2<R>>(L.jz);
+
+    PlasmaArgs<R> pa;
+    pa.x = c->at<R>(L.pl[0]);
+    pa.y = c->at<R>(L.pl[1]);
+    pa.ux = c->at<R>(L.pl[2]);
+    pa.uy = c->at<R>(L.pl[3]);
+    pa.np = (int)p.n_plasma;
+    pa.q = (R)(-p.plasma_w / (p.dx * p.dy));
+    pa.dep0 = dep;
+    pa.dep1 = dep + g.nperp;
+    pa.dep2 = dep + 2 * g.nperp;
+    pa.err = c->at<int>(L.err);
+    pa.h = (R)p.dxi;
+    const dim3 pgrid((pa.np + 255) / 256), pblock(256);
+
+    ColArgs<R> ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.jz = jzs;
+    ca.ode = c->at<double>(L.ode);
+    ca.kx2 = c->at<R>(L.kx2);
+    ca.kdx = c->at<R>(L.kdx);
+    ca.ky2 = c->at<R>(L.ky2);
+    ca.kdy = c->at<R>(L.kdy);
+    ca.inv_n = (R)(1.0 / g.nperp);
+    ca.n_perp = (R)g.nperp;
+    ca.h = (R)p.dxi;
+    ca.kappa2 = (R)p.kappa2;
+
+    auto F = [&](int slot, int j) -> R* { return fields + slot * plane + (int64_t)j * g.nperp; };
+    const int fslot[6] = {F_PSI, F_DXPSI, F_DYPSI, F_BX, F_BY, F_BZ};
+
+    for (int j = 0; j < p.nxi; ++j) {
+      for (int q = 0; q < 6; ++q) {
+        pa.F0[q] = F(fslot[q], j);
+        pa.F1[q] = (j >= 1) ? F(fslot[q], j - 1) : nullptr;
+      }
+      pa.psi_m2 = (j >= 2) ? F(F_PSI, j - 2) : nullptr;
+      const int64_t srcj = (int64_t)j * g.nperp;
+      // ---- psi stage
+      hipLaunchKernelGGL(k_dep_S<R>, pgrid, pblock, 0, c->stream, g, pa);
+      {
+        RowR2CArgs<R> ra;
+        std::memset(&ra, 0, sizeof(ra));
+        ra.dep[0] = dep;
+        ra.add[0] = src + 0 * plane + srcj;
+        ra.addc[0] = R(1);
+        ra.out[0] = rowspec;
+        row_r2c(c, g, ra, 1);
+      }
+      ca.in[0] = rowspec;
+      for (int q = 0; q < 3; ++q) ca.out[q] = colout + q * spec;
+      col<COL_PSI>(c, g, ca);
+      {
+        RowC2RArgs<R> rc;
+        std::memset(&rc, 0, sizeof(rc));
+        for (int q = 0; q < 3; ++q) rc.in[q] = colout + q * spec;
+        rc.out[0] = F(F_PSI, j);
+        rc.out[1] = F(F_DXPSI, j);
+        rc.out[2] = F(F_DYPSI, j);
+        row_c2r(c, g, rc, 3);
+      }
+      // ---- J stage
+      hipLaunchKernelGGL(k_dep_J<R>, pgrid, pblock, 0, c->stream, g, pa);
+      {
+        RowR2CArgs<R> ra;
+        std::memset(&ra, 0, sizeof(ra));
+        for (int q = 0; q < 3; ++q) {
+          ra.dep[q] = dep + q * g.nperp;
+          ra.add[q] = src + (1 + q) * plane + srcj;
+          ra.out[q] = rowspec + q * spec;
+        }
+        row_r2c(c, g, ra, 3);
+      }
+      for (int q = 0; q < 3; ++q) ca.in[q] = rowspec + q * spec;
+      for (int q = 0; q < 4; ++q) ca.out[q] = colout + q * spec;
+      const int s2 = j & 1, s2m = (j + 1) & 1;           // J ring: slot j%2, slot (j-1)%2
+      const int s3 = j % 3, s3m1 = (j + 2) % 3, s3m2 = (j + 1) % 3;  // B ring
+      ca.jr_w[0] = jring + (2 * s2 + 0) * spec;
+      ca.jr_w[1] = jring + (2 * s2 + 1) * spec;
+      ca.jr_r[0] = jring + (2 * s2m + 0) * spec;
+      ca.jr_r[1] = jring + (2 * s2m + 1) * spec;
+      for (int q = 0; q < 2; ++q) {
+        ca.b_cur[q] = bring + (2 * s3 + q) * spec;
+        ca.b_m1[q] = bring + (2 * s3m1 + q) * spec;
+        ca.b_m2[q] = bring + (2 * s3m2 + q) * spec;
+      }
+      col<COL_J>(c, g, ca);
+      {
+        RowC2RArgs<R> rc;
+        std::memset(&rc, 0, sizeof(rc));
+        for (int q = 0; q < 4; ++q) rc.in[q] = colout + q * spec;
+        rc.out[0] = F(F_BZ, j);
+        rc.out[1] = F(F_EZ, j);
+        rc.out[2] = F(F_BX, j);
+        rc.out[3] = F(F_BY, j);
+        row_c2r(c, g, rc, 4);
+      }
+      // ---- B_perp predictor-corrector
+      for (int k = 0; k < p.n_corr; ++k) {
+        hipLaunchKernelGGL((k_push<R, false>), pgrid, pblock, 0, c->stream, g, pa);
+        {
+          RowR2CArgs<R> ra;
+          std::memset(&ra, 0, sizeof(ra));
+          for (int q = 0; q < 2; ++q) {
+            ra.dep[q] = dep + q * g.nperp;
+            ra.add[q] = (j + 1 < p.nxi) ? src + (1 + q) * plane + srcj + g.nperp : nullptr;
+            ra.out[q] = rowspec + q * spec;
+          }
+          row_r2c(c, g, ra, 2);
+        }
+        for (int q = 0; q < 2; ++q) ca.in[q] = rowspec + q * spec;
+        ca.in[2] = nullptr;
+        for (int q = 0; q < 2; ++q) ca.out[q] = colout + q * spec;
+        col<COL_B>(c, g, ca);
+        {
+          RowC2RArgs<R> rc;
+          std::memset(&rc, 0, sizeof(rc));
+          for (int q = 0; q < 2; ++q) rc.in[q] = colout + q * spec;
+          rc.out[0] = F(F_BX, j);
+          rc.out[1] = F(F_BY, j);
+          row_c2r(c, g, rc, 2);
+        }
+      }
+      // ---- advance the plasma to slice j+1
+      hipLaunchKernelGGL((k_push<R, true>), pgrid, pblock, 0, c->stream, g, pa);
+    }
+    HIP_OK(hipGetLastError());
+    c->swept = true;
+    return QSA_OK;
+  }
+
+  static qsa_status push(qsa_ctx* c) {
+    const Geo<R> g = geo(c->p);
+    for (int s = 0; s < c->p.n_species; ++s) {
+      if (c->beam_n[s] == 0) continue;
+      BeamArgs<R> a = beam_args(c, g, s);
+      const int64_t blocks = (a.n + 255) / 256;
+      hipLaunchKernelGGL(k_beam_push<R>, dim3((unsigned)blocks), dim3(256), 0, c->stream, g, a);
+    }
+    HIP_OK(hipGetLastError());
+    return QSA_OK;
+  }
+
+  // device float64 -> working precision; host float64 goes through a chunked
+  // staging copy
+  static qsa_status upload(qsa_ctx* c, const double* src, void* dst, int64_t n, int on_device,
+                           bool keep_f64) {
+    if (n == 0) return QSA_OK;
+    if (keep_f64 || sizeof(R) == 8) {
+      HIP_OK(hipMemcpyAsync(dst, src, n * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            c->stream));
+      if (!on_device) HIP_OK(hipStreamSynchronize(c->stream));
+      return QSA_OK;
+    }
+    if (on_device) {
+      hipLaunchKernelGGL(k_from_f64<R>, dim3(fill_blocks(n)), dim3(256), 0, c->stream, src,
+                         reinterpret_cast<R*>(dst), n);
+      HIP_OK(hipGetLastError());
+      return QSA_OK;
+    }
+    const int64_t chunk = 1 << 22;
+    std::vector<R> tmp((size_t)std::min<int64_t>(n, chunk));
+    for (int64_t o = 0; o < n; o += chunk) {
+      const int64_t m = std::min<int64_t>(chunk, n - o);
+      for (int64_t i = 0; i < m; ++i) tmp[i] = (R)src[o + i];
+      HIP_OK(hipMemcpyAsync(reinterpret_cast<R*>(dst) + o, tmp.data(), m * sizeof(R),
+                            hipMemcpyHostToDevice, c->stream));
+      HIP_OK(hipStreamSynchronize(c->stream));
+    }
+    return QSA_OK;
+  }
+
+  static qsa_status download(qsa_ctx* c, const void* src, double* dst, int64_t n, int on_device,
+                             bool is_f64) {
+    if (n == 0) return QSA_OK;
+    if (is_f64 || sizeof(R) == 8) {
+      HIP_OK(hipMemcpyAsync(dst, src, n * 8, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                            c->stream));
+      if (!on_device) HIP_OK(hipStreamSynchronize(c->stream));
+      return QSA_OK;
+    }
+    if (on_device) {
+      hipLaunchKernelGGL(k_to_f64<R>, dim3(fill_blocks(n)), dim3(256), 0, c->stream,
+                         reinterpret_cast<const R*>(src), dst, n);
+      HIP_OK(hipGetLastError());
+      return QSA_OK;
+    }
+    const int64_t chunk = 1 << 22;
+    std::vector<R> tmp((size_t)std::min<int64_t>(n, chunk));
+    for (int64_t o = 0; o < n; o += chunk) {
+      const int64_t m = std::min<int64_t>(chunk, n - o);
+      HIP_OK(hipMemcpyAsync(tmp.data(), reinterpret_cast<const R*>(src) + o, m * sizeof(R),
+                            hipMemcpyDeviceToHost, c->stream));
+      HIP_OK(hipStreamSynchronize(c->stream));
+      for (int64_t i = 0; i < m; ++i) dst[o + i] = (double)tmp[i];
+    }
+    return QSA_OK;
+  }
+
+  static qsa_status fields(qsa_ctx* c, int field, int xi0, int xi1, double* dst, int on_device) {
+    const qsa_params& p = c->p;
+    const int64_t nperp = (int64_t)p.nx * p.ny;
+    const int64_t plane = (int64_t)p.nxi * nperp;
+    const R* F = c->at<R>(c->L.fields);
+    const R* S = c->at<R>(c->L.src);
+    double* emit = c->at<double>(c->L.emit);
+    for (int j = xi0; j < xi1; ++j) {
+      const R* A = nullptr;
+      const R* B = nullptr;
+      R a = 1, b = 0;
+      const int64_t o = (int64_t)j * nperp;
+      switch (field) {
+        case QSA_PSI: A = F + F_PSI * plane + o; break;
+        case QSA_EX: A = F + F_DXPSI * plane + o; a = -1; B = F + F_BY * plane + o; b = 1; break;
+        case QSA_EY: A = F + F_DYPSI * plane + o; a = -1; B = F + F_BX * plane + o; b = -1; break;
+        case QSA_EZ: A = F + F_EZ * plane + o; break;
+        case QSA_BX: A = F + F_BX * plane + o; break;
+        case QSA_BY: A = F + F_BY * plane + o; break;
+        case QSA_BZ: A = F + F_BZ * plane + o; break;
+        case QSA_DXPSI: A = F + F_DXPSI * plane + o; break;
+        case QSA_DYPSI: A = F + F_DYPSI * plane + o; break;
+        default: A = S + (field - QSA_SRC_S) * plane + o; break;
+      }
+      double* out = on_device ? dst + (int64_t)(j - xi0) * nperp : emit;
+      hipLaunchKernelGGL(k_emit<R>, dim3(fill_blocks(nperp)), dim3(256), 0, c->stream, A, a, B, b,
+                         out, nperp);
+      HIP_OK(hipGetLastError());
+      if (!on_device)
+        HIP_OK(hipMemcpyAsync(dst + (int64_t)(j - xi0) * nperp, emit, nperp * 8, hipMemcpyDeviceToHost,
+                              c->stream));
+    }
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return QSA_OK;
+  }
+
+  static qsa_status upload_tables(qsa_ctx* c) {
+    std::vector<char> twx, twy, kx2, kdx, ky2, kdy;
+    tables(c->p, twx, twy, kx2, kdx, ky2, kdy);
+    HIP_OK(hipMemcpyAsync(c->ws + c->L.twx, twx.data(), twx.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->ws + c->L.twy, twy.data(), twy.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->ws + c->L.kx2, kx2.data(), kx2.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->ws + c->L.kdx, kdx.data(), kdx.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->ws + c->L.ky2, ky2.data(), ky2.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->ws + c->L.kdy, kdy.data(), kdy.size(), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, c->stream, c->at<int>(c->L.err), (int64_t)1, 0);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return QSA_OK;
+  }
+};
+
+// Pending device error -> status (synchronizing).
+qsa_status check_device(qsa_ctx* c) {
+  HIP_OK(hipStreamSynchronize(c->stream));
+  int e = 0;
+  HIP_OK(hipMemcpy(&e, c->ws + c->L.err, sizeof(int), hipMemcpyDeviceToHost));
+  if (e & ERR_BREAKDOWN) {
+    c->sticky = QSA_E_BREAKDOWN;
+    return fail(c, QSA_E_BREAKDOWN, "quasistatic breakdown: 1 + psi <= 1e-3 or non-finite at a plasma particle");
+  }
+  return QSA_OK;
+}
+
+template <typename F64, typename F32>
+qsa_status dispatch(qsa_ctx* c, F64 f64, F32 f32) {
+  return c->p.precision == QSA_FP32 ? f32() : f64();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t qsa_workspace_bytes(const qsa_params* p) {
+  if (validate(p)) return 0;
+  return make_layout(*p).total;
+}
+
+qsa_status qsa_create(const qsa_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                      qsa_ctx** out) {
+  if (!out) return QSA_E_INVALID;
+  *out = nullptr;
+  if (validate(p)) return QSA_E_INVALID;
+  const Layout L = make_layout(*p);
+  if (!dev_ws || ((uintptr_t)dev_ws % kAlign) != 0) return QSA_E_INVALID;
+  if (ws_bytes < L.total) return QSA_E_NOMEM;
+  qsa_ctx* c = new qsa_ctx();
+  c->p = *p;
+  c->L = L;
+  c->ws = reinterpret_cast<char*>(dev_ws);
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  qsa_status st = (p->precision == QSA_FP32) ? Engine<float>::upload_tables(c)
+                                             : Engine<double>::upload_tables(c);
+  if (st != QSA_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return QSA_OK;
+}
+
+static bool all_finite(const double* a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+qsa_status qsa_load_plasma(qsa_ctx* c, const double* x, const double* y, const double* ux,
+                           const double* uy, int64_t n, int32_t on_device) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (n != c->p.n_plasma) return fail(c, QSA_E_INVALID, "plasma count differs from n_plasma");
+  if (!x || !y || !ux || !uy) return fail(c, QSA_E_INVALID, "null plasma array");
+  const double* arr[4] = {x, y, ux, uy};
+  if (!on_device)
+    for (int i = 0; i < 4; ++i)
+      if (!all_finite(arr[i], n)) return fail(c, QSA_E_NONFINITE, "non-finite plasma value");
+  for (int i = 0; i < 4; ++i) {
+    qsa_status st = dispatch(
+        c, [&] { return Engine<double>::upload(c, arr[i], c->ws + c->L.tmpl[i], n, on_device, false); },
+        [&] { return Engine<float>::upload(c, arr[i], c->ws + c->L.tmpl[i], n, on_device, false); });
+    if (st != QSA_OK) return st;
+  }
+  c->plasma_loaded = true;
+  return QSA_OK;
+}
+
+qsa_status qsa_load_beam(qsa_ctx* c, int32_t s, const double* x, const double* y, const double* xi,
+                         const double* ux, const double* uy, const double* uz, const double* w,
+                         int64_t n, int32_t on_device) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (s < 0 || s >= c->p.n_species) return fail(c, QSA_E_INVALID, "species index out of range");
+  if (n < 0 || n > c->p.beam_capacity[s]) return fail(c, QSA_E_INVALID, "beam count exceeds capacity");
+  const double* arr[7] = {x, y, ux, uy, uz, w, xi};
+  for (int i = 0; i < 7; ++i)
+    if (n > 0 && !arr[i]) return fail(c, QSA_E_INVALID, "null beam array");
+  if (!on_device)
+    for (int i = 0; i < 7; ++i)
+      if (!all_finite(arr[i], n)) return fail(c, QSA_E_NONFINITE, "non-finite beam value");
+  for (int i = 0; i < 7; ++i) {
+    const bool f64 = (i == 6);
+    qsa_status st = dispatch(
+        c, [&] { return Engine<double>::upload(c, arr[i], c->ws + c->L.beam[s][i], n, on_device, f64); },
+        [&] { return Engine<float>::upload(c, arr[i], c->ws + c->L.beam[s][i], n, on_device, f64); });
+    if (st != QSA_OK) return st;
+  }
+  c->beam_n[s] = n;
+  return QSA_OK;
+}
+
+qsa_status qsa_read_beam(qsa_ctx* c, int32_t s, double* x, double* y, double* xi, double* ux,
+                         double* uy, double* uz, double* w, int64_t cap, int64_t* n,
+                         int32_t on_device) {
+  if (!c || !n) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (s < 0 || s >= c->p.n_species) return fail(c, QSA_E_INVALID, "species index out of range");
+  const int64_t m = c->beam_n[s];
+  *n = m;
+  if (cap < m) return fail(c, QSA_E_INVALID, "destination too small");
+  double* arr[7] = {x, y, ux, uy, uz, w, xi};
+  for (int i = 0; i < 7; ++i)
+    if (m > 0 && !arr[i]) return fail(c, QSA_E_INVALID, "null destination array");
+  for (int i = 0; i < 7; ++i) {
+    const bool f64 = (i == 6);
+    qsa_status st = dispatch(
+        c, [&] { return Engine<double>::download(c, c->ws + c->L.beam[s][i], arr[i], m, on_device, f64); },
+        [&] { return Engine<float>::download(c, c->ws + c->L.beam[s][i], arr[i], m, on_device, f64); });
+    if (st != QSA_OK) return st;
+  }
+  return check_device(c);
+}
+
+qsa_status qsa_slice_sweep(qsa_ctx* c) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
+  return dispatch(c, [&] { return Engine<double>::sweep(c); }, [&] { return Engine<float>::sweep(c); });
+}
+
+qsa_status qsa_beam_step(qsa_ctx* c, int32_t n_steps) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (n_steps < 0) return fail(c, QSA_E_INVALID, "n_steps must be >= 0");
+  if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
+  for (int i = 0; i < n_steps; ++i) {
+    qsa_status st = qsa_slice_sweep(c);
+    if (st != QSA_OK) return st;
+    st = dispatch(c, [&] { return Engine<double>::push(c); }, [&] { return Engine<float>::push(c); });
+    if (st != QSA_OK) return st;
+  }
+  return QSA_OK;
+}
+
+qsa_status qsa_fields(qsa_ctx* c, int32_t field, int32_t xi0, int32_t xi1, double* dst, size_t count,
+                      int32_t dst_on_device) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (!c->swept) return fail(c, QSA_E_STATE, "no sweep has run");
+  if (field < QSA_PSI || field > QSA_SRC_JZ) return fail(c, QSA_E_INVALID, "unknown field");
+  if (xi0 < 0 || xi1 > c->p.nxi || xi0 > xi1) return fail(c, QSA_E_INVALID, "slice range out of bounds");
+  const size_t need = (size_t)(xi1 - xi0) * c->p.nx * c->p.ny;
+  if (!dst || count < need) return fail(c, QSA_E_INVALID, "destination too small");
+  qsa_status st = dispatch(c, [&] { return Engine<double>::fields(c, field, xi0, xi1, dst, dst_on_device); },
+                           [&] { return Engine<float>::fields(c, field, xi0, xi1, dst, dst_on_device); });
+  if (st != QSA_OK) return st;
+  return check_device(c);
+}
+
+qsa_status qsa_sync(qsa_ctx* c) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  return check_device(c);
+}
+
+qsa_status qsa_destroy(qsa_ctx* c) {
+  delete c;
+  return QSA_OK;
+}
+
+const char* qsa_status_string(qsa_status s) {
+  switch (s) {
+    case QSA_OK: return "ok";
+    case QSA_E_INVALID: return "invalid argument";
+    case QSA_E_NOMEM: return "workspace too small";
+    case QSA_E_DEVICE: return "HIP runtime error";
+    case QSA_E_BREAKDOWN: return "quasistatic breakdown (1 + psi <= 1e-3) or non-finite plasma state";
+    case QSA_E_NONFINITE: return "non-finite input value";
+    case QSA_E_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* qsa_last_error(const qsa_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

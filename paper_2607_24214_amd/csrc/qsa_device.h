@@ -1,0 +1,207 @@
+// Device-side building blocks of the QSA slice sweep for gfx950 (wave64):
+// complex arithmetic, in-LDS Stockham FFT passes, the linear (cloud-in-cell)
+// particle shape on the periodic transverse grid, and atomics.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qsa {
+
+template <typename R>
+struct C2 {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ C2<R> cadd(C2<R> a, C2<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ C2<R> csub(C2<R> a, C2<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ C2<R> cmul(C2<R> a, C2<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ C2<R> cconj(C2<R> a) { return {a.x, -a.y}; }
+template <typename R>
+__device__ __forceinline__ C2<R> cscale(C2<R> a, R s) { return {a.x * s, a.y * s}; }
+// multiply by i*k (k real)
+template <typename R>
+__device__ __forceinline__ C2<R> cmul_ik(C2<R> a, R k) { return {-a.y * k, a.x * k}; }
+
+// Grid geometry passed by value to every kernel.
+template <typename R>
+struct Geo {
+  int nx, ny, nxi, nxh, nperp;  // nxh = nx/2 + 1 (half spectrum along x)
+  int lgx, lgy;                 // log2 nx, log2 ny
+  R dx, dy, dxi;
+  R inv_dx, inv_dy;
+  R lx, ly, inv_lx, inv_ly;
+};
+
+// Wrap an integer cell index into [0, n); any input (also from a non-finite
+// coordinate) lands inside the grid, so no access can leave the array.
+__device__ __forceinline__ int wrap_index(int v, int n) {
+  v %= n;
+  v += (v < 0) ? n : 0;
+  return ((unsigned)v < (unsigned)n) ? v : 0;
+}
+
+// Four nodes and weights of the linear shape at (x, y).
+template <typename R>
+struct Stencil {
+  int n00, n10, n01, n11;
+  R w00, w10, w01, w11;
+};
+
+template <typename R>
+__device__ __forceinline__ Stencil<R> stencil2(const Geo<R>& g, R x, R y) {
+  R gx = x * g.inv_dx;
+  R gy = y * g.inv_dy;
+  R fx0 = floor(gx);
+  R fy0 = floor(gy);
+  R fx = gx - fx0;
+  R fy = gy - fy0;
+  // coordinates are bounded (a few box lengths at most) for finite input;
+  // the clamp keeps the float->int conversion defined for any input
+  R cx = fmin(fmax(fx0, R(-1.0e9)), R(1.0e9));
+  R cy = fmin(fmax(fy0, R(-1.0e9)), R(1.0e9));
+  int i0 = wrap_index((int)cx, g.nx);
+  int l0 = wrap_index((int)cy, g.ny);
+  int i1 = (i0 + 1 == g.nx) ? 0 : i0 + 1;
+  int l1 = (l0 + 1 == g.ny) ? 0 : l0 + 1;
+  Stencil<R> s;
+  s.n00 = l0 * g.nx + i0;
+  s.n10 = l0 * g.nx + i1;
+  s.n01 = l1 * g.nx + i0;
+  s.n11 = l1 * g.nx + i1;
+  R ax = R(1) - fx, ay = R(1) - fy;
+  s.w00 = ax * ay;
+  s.w10 = fx * ay;
+  s.w01 = ax * fy;
+  s.w11 = fx * fy;
+  return s;
+}
+
+template <typename R>
+__device__ __forceinline__ R gather(const R* __restrict__ f, const Stencil<R>& s) {
+  return f[s.n00] * s.w00 + f[s.n10] * s.w10 + f[s.n01] * s.w01 + f[s.n11] * s.w11;
+}
+
+__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
+
+template <typename R>
+__device__ __forceinline__ void scatter(R* __restrict__ f, const Stencil<R>& s, R q) {
+  atomic_add(f + s.n00, q * s.w00);
+  atomic_add(f + s.n10, q * s.w10);
+  atomic_add(f + s.n01, q * s.w01);
+  atomic_add(f + s.n11, q * s.w11);
+}
+
+// Periodic wrap into [0, L); a value that rounds to L maps to 0.
+template <typename R>
+__device__ __forceinline__ R wrap_pos(R x, R L, R invL) {
+  R r = x - L * floor(x * invL);
+  return (r >= L) ? R(0) : r;
+}
+
+// ---------------------------------------------------------------------------
+// Stockham autosort FFT in LDS.  A transform of length n (power of two) is
+// worked by tpt threads (thread t in [0, tpt)); passes are radix 4 with one
+// final radix-2 pass when log2 n is odd.  tw[m] = exp(-2 pi i m/n); INV uses
+// the conjugate twiddles and is unnormalized.  Every pass ends with a
+// workgroup barrier, so all threads of the workgroup must call with the same
+// n (threads without a transform still take part).
+// ---------------------------------------------------------------------------
+template <typename R, bool INV>
+__device__ __forceinline__ void fft_pass4(const C2<R>* in, C2<R>* out, int n, int ns, int t,
+                                          int tpt, const C2<R>* __restrict__ tw) {
+  const int q = n >> 2;
+  const int stride = n / (4 * ns);
+  for (int jj = t; jj < q; jj += tpt) {
+    const int k = jj & (ns - 1);
+    C2<R> a0 = in[jj], a1 = in[jj + q], a2 = in[jj + 2 * q], a3 = in[jj + 3 * q];
+    if (ns > 1) {
+      C2<R> w1 = tw[k * stride], w2 = tw[2 * k * stride], w3 = tw[3 * k * stride];
+      if (INV) {
+        w1 = cconj(w1);
+        w2 = cconj(w2);
+        w3 = cconj(w3);
+      }
+      a1 = cmul(a1, w1);
+      a2 = cmul(a2, w2);
+      a3 = cmul(a3, w3);
+    }
+    C2<R> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), d = csub(a1, a3);
+    // t3 = -i d (forward) or +i d (inverse)
+    C2<R> t3 = INV ? C2<R>{-d.y, d.x} : C2<R>{d.y, -d.x};
+    const int o = 4 * (jj - k) + k;
+    out[o] = cadd(t0, t2);
+    out[o + ns] = cadd(t1, t3);
+    out[o + 2 * ns] = csub(t0, t2);
+    out[o + 3 * ns] = csub(t1, t3);
+  }
+}
+
+template <typename R, bool INV>
+__device__ __forceinline__ void fft_pass2(const C2<R>* in, C2<R>* out, int n, int ns, int t,
+                                          int tpt, const C2<R>* __restrict__ tw) {
+  const int h = n >> 1;
+  const int stride = n / (2 * ns);
+  for (int jj = t; jj < h; jj += tpt) {
+    const int k = jj & (ns - 1);
+    C2<R> a = in[jj], b = in[jj + h];
+    if (ns > 1) {
+      C2<R> w = tw[k * stride];
+      if (INV) w = cconj(w);
+      b = cmul(b, w);
+    }
+    const int o = 2 * (jj - k) + k;
+    out[o] = cadd(a, b);
+    out[o + ns] = csub(a, b);
+  }
+}
+
+// Returns the buffer (a or b) that holds the result.
+template <typename R, bool INV>
+__device__ __forceinline__ C2<R>* fft_lds(C2<R>* a, C2<R>* b, int n, int lg, int t, int tpt,
+                                          const C2<R>* __restrict__ tw) {
+  int ns = 1;
+  int s = lg;
+  while (s >= 2) {
+    fft_pass4<R, INV>(a, b, n, ns, t, tpt, tw);
+    __syncthreads();
+    C2<R>* tmp = a;
+    a = b;
+    b = tmp;
+    ns <<= 2;
+    s -= 2;
+  }
+  if (s == 1) {
+    fft_pass2<R, INV>(a, b, n, ns, t, tpt, tw);
+    __syncthreads();
+    C2<R>* tmp = a;
+    a = b;
+    b = tmp;
+  }
+  return a;
+}
+
+// Number of passes fft_lds takes for log2 n = lg (its result sits in the
+// input buffer when this is even).
+__host__ __device__ __forceinline__ int fft_passes(int lg) { return (lg >> 1) + (lg & 1); }
+
+// In-place variant: the result ends in `a` (one extra LDS copy when the pass
+// count is odd).
+template <typename R, bool INV>
+__device__ __forceinline__ void fft_lds_inplace(C2<R>* a, C2<R>* scratch, int n, int lg, int t,
+                                                int tpt, const C2<R>* __restrict__ tw) {
+  C2<R>* r = fft_lds<R, INV>(a, scratch, n, lg, t, tpt, tw);
+  if (r != a) {
+    for (int i = t; i < n; i += tpt) a[i] = r[i];
+    __syncthreads();
+  }
+}
+
+}  // namespace qsa

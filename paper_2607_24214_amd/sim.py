@@ -1,0 +1,151 @@
+"""Python binding of the QSA library: argument marshalling around libqsa.so.
+
+torch provides the device workspace and the stream; every step of the slice
+sweep and the beam push runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_PREC = {"f64": L.QSA_FP64, "fp64": L.QSA_FP64, "f32": L.QSA_FP32, "fp32": L.QSA_FP32}
+
+
+def _ptr(a) -> int:
+    return a.data_ptr() if isinstance(a, torch.Tensor) else a.ctypes.data
+
+
+def _f64(a):
+    """A float64 contiguous host array or device tensor (on_device flag)."""
+    if isinstance(a, torch.Tensor):
+        if a.is_cuda:
+            return a.to(torch.float64).contiguous(), 1
+        return np.ascontiguousarray(a.numpy(), dtype=np.float64), 0
+    return np.ascontiguousarray(a, dtype=np.float64), 0
+
+
+def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt: float,
+                species: Sequence, n_plasma: int, plasma_w: float,
+                beam_capacity: Sequence[int], precision: str = "f64", n_corr: int = 3,
+                kappa2: float = 0.75) -> L.QSAParams:
+    """species: sequence of (Z, M)."""
+    p = L.QSAParams()
+    p.nx, p.ny, p.nxi = nx, ny, nxi
+    p.precision = _PREC[precision]
+    p.dx, p.dy, p.dxi, p.dt = dx, dy, dxi, dt
+    p.n_corr, p.kappa2 = n_corr, kappa2
+    p.n_plasma, p.plasma_w = n_plasma, plasma_w
+    p.n_species = len(species)
+    for i, (Z, M) in enumerate(species):
+        p.species[i].Z = int(Z)
+        p.species[i].M = float(M)
+        p.beam_capacity[i] = int(beam_capacity[i])
+    return p
+
+
+def params_from_workload(wl, precision: Optional[str] = None,
+                         beam_capacity: Optional[Sequence[int]] = None) -> L.QSAParams:
+    """Parameters of a workload description (duck-typed: grid, species, loading)."""
+    caps = beam_capacity or [wl.n_beam(s) for s in range(len(wl.species))]
+    return make_params(wl.nx, wl.ny, wl.nxi, wl.dx, wl.dy, wl.dxi, wl.dt,
+                       [(s.Z, s.M) for s in wl.species], wl.n_plasma,
+                       wl.dx * wl.dy / wl.plasma_ppc, caps, precision or wl.precision,
+                       wl.n_corr, wl.kappa2)
+
+
+class Sim:
+    """One simulation box on the current CUDA (HIP) device."""
+
+    def __init__(self, params: L.QSAParams, device: str = "cuda",
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.lib = L.lib()
+        self.params = params
+        nbytes = self.lib.qsa_workspace_bytes(C.byref(params))
+        if nbytes == 0:
+            raise L.QSAError(-1, "invalid parameters")
+        self.device = torch.device(device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        # 256-byte aligned workspace owned by the caller (torch)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws = (base + 255) // 256 * 256
+        self.ws_bytes = nbytes
+        ctx = C.c_void_p()
+        self._check(self.lib.qsa_create(C.byref(params), C.c_void_p(self._ws), nbytes,
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(ctx)), None)
+        self.ctx = ctx
+        self.nperp = params.nx * params.ny
+
+    # ------------------------------------------------------------------
+    def _check(self, st: int, ctx=-1):
+        if st != L.QSA_OK:
+            c = self.ctx if ctx == -1 else ctx
+            msg = self.lib.qsa_last_error(c).decode() if c else L.STATUS.get(st, "")
+            raise L.QSAError(st, msg)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.qsa_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def load_plasma(self, plasma: Dict):
+        arrs = [_f64(plasma[k]) for k in ("x", "y", "ux", "uy")]
+        n = arrs[0][0].shape[0]
+        on_dev = arrs[0][1]
+        self._check(self.lib.qsa_load_plasma(self.ctx, *[C.c_void_p(_ptr(a)) for a, _ in arrs],
+                                             n, on_dev))
+
+    def load_beam(self, s: int, beam: Dict):
+        arrs = [_f64(beam[k]) for k in ("x", "y", "xi", "ux", "uy", "uz", "w")]
+        n = arrs[0][0].shape[0]
+        on_dev = arrs[0][1]
+        self._check(self.lib.qsa_load_beam(self.ctx, s, *[C.c_void_p(_ptr(a)) for a, _ in arrs],
+                                           n, on_dev))
+
+    def read_beam(self, s: int) -> Dict[str, np.ndarray]:
+        cap = int(self.params.beam_capacity[s])
+        out = {k: np.empty(cap) for k in ("x", "y", "xi", "ux", "uy", "uz", "w")}
+        n = C.c_int64()
+        self._check(self.lib.qsa_read_beam(
+            self.ctx, s, *[C.c_void_p(out[k].ctypes.data) for k in ("x", "y", "xi", "ux", "uy", "uz", "w")],
+            cap, C.byref(n), 0))
+        return {k: v[:n.value] for k, v in out.items()}
+
+    def slice_sweep(self):
+        self._check(self.lib.qsa_slice_sweep(self.ctx))
+
+    def beam_step(self, n: int = 1):
+        self._check(self.lib.qsa_beam_step(self.ctx, n))
+
+    def sync(self):
+        self._check(self.lib.qsa_sync(self.ctx))
+
+    def fields(self, name: str, xi0: int = 0, xi1: Optional[int] = None,
+               on_device: bool = False):
+        """Slices [xi0, xi1) of one field as float64 [nxi, ny, nx] (numpy, or a
+        device tensor with on_device)."""
+        p = self.params
+        xi1 = p.nxi if xi1 is None else xi1
+        shape = (xi1 - xi0, p.ny, p.nx)
+        n = int(np.prod(shape))
+        if on_device:
+            out = torch.empty(shape, dtype=torch.float64, device=self.device)
+            self._check(self.lib.qsa_fields(self.ctx, L.FIELD_IDS[name], xi0, xi1,
+                                            C.c_void_p(out.data_ptr()), n, 1))
+        else:
+            out = np.empty(shape)
+            self._check(self.lib.qsa_fields(self.ctx, L.FIELD_IDS[name], xi0, xi1,
+                                            C.c_void_p(out.ctypes.data), n, 0))
+        return out

@@ -1,0 +1,62 @@
+"""Shared test helpers: run a workload through the oracle and through the
+HIP library on the same seeded inputs, and compare slice by slice."""
+from __future__ import annotations
+
+import numpy as np
+
+import qsa_workloads as W
+
+OUT_FIELDS = ("psi", "Ex", "Ey", "Ez", "Bx", "By", "Bz")
+
+
+def oracle_fields(sim_o):
+    from oracle import qsa_pic as O
+    of = O.output_fields(sim_o.fields)
+    return {k: v.numpy() for k, v in of.items()}
+
+
+def run_oracle(wl, steps: int = 0, beams=None, plasma=None):
+    from oracle import qsa_pic as O
+    plasma = plasma if plasma is not None else W.plasma_template(wl)
+    beams = beams if beams is not None else W.beam(wl)
+    s = O.Sim(wl, plasma, beams)
+    if steps:
+        s.beam_step(steps)
+    s.sweep()
+    return s, oracle_fields(s)
+
+
+def run_gpu(wl, steps: int = 0, precision=None, beams=None, plasma=None):
+    import paper_2607_24214_amd as Q
+    plasma = plasma if plasma is not None else W.plasma_template(wl)
+    beams = beams if beams is not None else W.beam(wl)
+    caps = [len(b["x"]) for b in beams]
+    sim = Q.Sim(Q.params_from_workload(wl, precision=precision, beam_capacity=caps))
+    sim.load_plasma(plasma)
+    for s, b in enumerate(beams):
+        sim.load_beam(s, b)
+    if steps:
+        sim.beam_step(steps)
+    sim.slice_sweep()
+    out = {k: sim.fields(k) for k in OUT_FIELDS}
+    return sim, out
+
+
+def slice_errors(got: dict, ref: dict, j0: int = 0, j1=None):
+    """Per slice and field: ||got - ref||_2 / max_f ||ref_f||_2 over the slice
+    (the scale is the largest field of that slice, so that fields that are
+    identically zero in a geometry are judged on an absolute scale).
+    Returns (max error, worst (field, slice))."""
+    names = list(ref.keys())
+    nxi = ref[names[0]].shape[0]
+    j1 = nxi if j1 is None else j1
+    worst, where = 0.0, None
+    for j in range(j0, j1):
+        scale = max(float(np.linalg.norm(ref[f][j])) for f in names)
+        if scale == 0.0:
+            scale = 1.0
+        for f in names:
+            e = float(np.linalg.norm(got[f][j] - ref[f][j])) / scale
+            if e > worst:
+                worst, where = e, (f, j)
+    return worst, where

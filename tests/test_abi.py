@@ -1,0 +1,68 @@
+"""The C ABI: libqsa.so loads and exports every entry point include/qsa.h
+declares; host-side validation answers without a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qsa.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(qsa_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("qsa_create", "qsa_slice_sweep", "qsa_beam_step", "qsa_fields",
+                 "qsa_workspace_bytes", "qsa_load_plasma", "qsa_load_beam", "qsa_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2607_24214_amd import _lib as L
+    lib = L.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _params(**kw):
+    from paper_2607_24214_amd import make_params
+    base = dict(nx=64, ny=1, nxi=128, dx=0.1, dy=0.1, dxi=0.1, dt=5.0,
+                species=[(-1, 1.0)], n_plasma=256, plasma_w=0.0025, beam_capacity=[65024])
+    base.update(kw)
+    return make_params(**base)
+
+
+def test_workspace_bytes_validates_parameters():
+    from paper_2607_24214_amd import _lib as L
+    lib = L.lib()
+    ok = lib.qsa_workspace_bytes(C.byref(_params()))
+    assert ok > 0
+    # fields (7) + sources (4) per slice, float64, plus the beam: a lower bound
+    assert ok >= (7 + 4) * 128 * 64 * 8 + 65024 * 7 * 8
+    for bad in (dict(nx=48), dict(nx=4), dict(ny=2), dict(nxi=1), dict(dt=0.0),
+                dict(dx=-1.0), dict(n_plasma=0), dict(plasma_w=0.0), dict(species=[]),
+                dict(n_corr=-1), dict(kappa2=0.0), dict(nx=1024)):
+        kw = dict(bad)
+        if "species" in kw:
+            kw["beam_capacity"] = []
+        assert lib.qsa_workspace_bytes(C.byref(_params(**kw))) == 0, bad
+    f32 = lib.qsa_workspace_bytes(C.byref(_params(precision="f32")))
+    assert f32 < ok
+
+
+def test_create_rejects_without_touching_the_device():
+    from paper_2607_24214_amd import _lib as L
+    lib = L.lib()
+    p = _params()
+    ctx = C.c_void_p()
+    assert lib.qsa_create(C.byref(_params(nx=3)), C.c_void_p(256), 1 << 30, None, C.byref(ctx)) == -1
+    assert lib.qsa_create(C.byref(p), None, 1 << 30, None, C.byref(ctx)) == -1
+    assert lib.qsa_create(C.byref(p), C.c_void_p(257), 1 << 30, None, C.byref(ctx)) == -1
+    need = lib.qsa_workspace_bytes(C.byref(p))
+    assert lib.qsa_create(C.byref(p), C.c_void_p(256), need - 1, None, C.byref(ctx)) == -2
+    assert lib.qsa_status_string(-4).decode().startswith("quasistatic breakdown")
