@@ -1,0 +1,202 @@
+#!/usr/bin/env python
+"""Throughput of the QSA particle-in-cell hot path on one MI355X.
+
+A step is one beam step of the 3D workload 256 x 256 x 512 (dx = dy = dxi =
+0.05 c/omega_p, warm plasma u_th = 0.01, 2x2 plasma lattice, electron beam
+alpha = 1e-2, gamma_b = 1e3, 8 particles per cell): the beam source deposit,
+the full quasistatic sweep over 512 slices (K = 3 predictor-corrector
+iterations) and the Boris push of all 2.68e8 beam particles.  The metric is
+plasma particle-slice updates per second over whole steps.
+
+Prints one JSON line (rank 0) with the measured rate, a roofline entry for
+the dominant kernel (timed with HIP events on the library's stream inside
+the timed region) and the float64 oracle timed on a bounded sample of the
+same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def alg_bytes(kclass: str, wl, rsize: int) -> float:
+    """Algorithmic HBM bytes of one launch of a kernel class: every array the
+    kernel must touch, read or written once (particle state of rsize-byte
+    components, nx*ny grids)."""
+    npl = wl.n_plasma
+    ng = wl.nx * wl.ny
+    R = rsize
+    if kclass == "push_pred":     # read x,y,ux,uy; read F^j, F^{j-1} (6+6), psi^{j-2}; write 2 deposits
+        return 4 * R * npl + (13 + 2) * R * ng
+    if kclass == "push_final":    # read and write x,y,ux,uy; read F^j, F^{j-1}
+        return 8 * R * npl + 12 * R * ng
+    if kclass == "dep_S":
+        return 2 * R * npl + R * ng
+    if kclass == "dep_J":
+        return 4 * R * npl + 4 * R * ng
+    if kclass == "beam_push":     # read and write 6 real components + xi (float64)
+        return 2 * (6 * R + 8) * wl.n_beam_total + 6 * R * wl.nxi * ng
+    if kclass == "beam_deposit":
+        return (6 * R + 8) * wl.n_beam_total + 4 * R * wl.nxi * ng
+    raise KeyError(kclass)
+
+
+def cpu_baseline(wl, n_slices: int):
+    """The float64 oracle on the first n_slices slices of one sweep of the
+    same workload (full transverse grid, beam restricted to those slices)."""
+    import torch
+    import qsa_workloads as W
+    from oracle import qsa_pic as O
+    sub = wl.with_(nxi=n_slices)
+    g = O.Grid.of(sub)
+    plasma = O.to_torch(W.plasma_template(sub))
+    beams = [O.to_torch(b) for b in W.beam(sub)]
+    t0 = time.perf_counter()
+    src = O.beam_sources(g, beams, [s.Z for s in sub.species])
+    O.slice_sweep(g, plasma, src, sub.n_corr, sub.kappa2)
+    dt = time.perf_counter() - t0
+    return {
+        "value": sub.n_plasma * n_slices / dt,
+        "unit": "plasma particle-slice updates/s",
+        "cores": torch.get_num_threads(),
+        "kind": "oracle",
+        "sample": (f"first {n_slices} of {wl.nxi} slices of one sweep of {wl.name} "
+                   f"({wl.nx}x{wl.ny} grid, {sub.n_plasma} plasma particles/slice, beam "
+                   f"cells in those slices only), float64, beam sources included; {dt:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--workload", default="cube256")
+    ap.add_argument("--cpu-slices", type=int, default=96)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--breakdown", action="store_true",
+                    help="also time every kernel class over one extra step each")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the slice sweep runs on a single MI355X; "
+              "multi-GPU runs are not part of this build (--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import qsa_workloads as W
+    import paper_2607_24214_amd as Q
+
+    wl = W.CONFIGS[args.workload]().with_(precision=args.precision)
+    rsize = 8 if args.precision == "f64" else 4
+    log(f"workload {wl.name}: {wl.nx}x{wl.ny}x{wl.nxi}, plasma {wl.n_plasma}/slice, "
+        f"beam {wl.n_beam_total}, precision {args.precision}")
+
+    t = time.perf_counter()
+    plasma = W.plasma_template(wl)
+    beams = W.beam(wl)
+    log(f"inputs generated in {time.perf_counter() - t:.1f} s")
+    sim = Q.Sim(Q.params_from_workload(wl, precision=args.precision))
+    sim.load_plasma(plasma)
+    for s, b in enumerate(beams):
+        sim.load_beam(s, b)
+    del beams
+    log(f"loaded; workspace {sim.ws_bytes / 2**30:.2f} GiB")
+
+    # warmup
+    t = time.perf_counter()
+    sim.beam_step(args.warmup)
+    sim.sync()
+    log(f"warmup {args.warmup} steps: {time.perf_counter() - t:.2f} s")
+
+    breakdown = {}
+    if args.breakdown:
+        for kc in ("push_pred", "push_final", "dep_S", "dep_J", "row_r2c", "col", "row_c2r",
+                   "beam_deposit", "beam_push"):
+            sim.timing_begin(kc)
+            sim.beam_step(1)
+            ms, n = sim.timing_end()
+            breakdown[kc] = {"ms_per_step": ms, "launches": n, "us_per_launch": 1e3 * ms / max(n, 1)}
+            log(f"  {kc:13s} {ms:9.2f} ms/step  {n:6d} launches  {1e3 * ms / max(n, 1):8.2f} us/launch")
+
+    dominant = "push_pred"
+    # timed region: exactly K steps between synchronizations
+    torch.cuda.synchronize()
+    sim.timing_begin(dominant)
+    t0 = time.perf_counter()
+    sim.beam_step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dom_ms, dom_n = sim.timing_end()
+    sim.sync()
+    T = t1 - t0
+    ms_step = 1e3 * T / args.steps
+    updates = wl.n_plasma * wl.nxi * args.steps
+    value = updates / T
+    log(f"timed {args.steps} steps: {T:.3f} s, {ms_step:.2f} ms/step, {value:.3e} updates/s")
+
+    # sweep alone (the beam push excluded), for the record
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sim.slice_sweep()
+    torch.cuda.synchronize()
+    t_sweep = time.perf_counter() - t
+
+    avg_s = dom_ms / 1e3 / max(dom_n, 1)
+    achieved = alg_bytes(dominant, wl, rsize) / avg_s / 1e9
+    roofline = {
+        "kernel": "k_push<predictor> (plasma RK2 push + predicted J_perp deposit)",
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "avg_launch_us": avg_s * 1e6, "launches_timed": dom_n,
+        "alg_bytes_per_launch": alg_bytes(dominant, wl, rsize),
+    }
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"oracle baseline on {args.cpu_slices} slices ...")
+        cpu = cpu_baseline(wl, args.cpu_slices)
+        log(f"oracle: {cpu['value']:.3e} updates/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": "plasma particle-slice updates/s (push+deposit+solve)",
+        "value": value,
+        "unit": "plasma particle-slice updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic (seeded PCG64 plasma lattice + flat-top beam)",
+        "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nxi": wl.nxi,
+                   "dx": wl.dx, "plasma_per_slice": wl.n_plasma, "beam_particles": wl.n_beam_total,
+                   "alpha": wl.species[0].alpha, "gamma_b": wl.gamma_b, "n_corr": wl.n_corr,
+                   "step": "beam source deposit + 512-slice sweep + Boris beam push"},
+        "sweep_only": {"ms": 1e3 * t_sweep, "updates_per_s": wl.n_plasma * wl.nxi / t_sweep},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if breakdown:
+        out["kernel_breakdown_ms_per_step"] = {k: round(v["ms_per_step"], 3) for k, v in breakdown.items()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

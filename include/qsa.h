@@ -154,6 +154,30 @@ qsa_status qsa_fields(qsa_ctx* c, int32_t field, int32_t xi0, int32_t xi1,
 /* Wait for the stream and report any pending device error. */
 qsa_status qsa_sync(qsa_ctx* c);
 
+/* Kernel classes that qsa_timing_begin can time. */
+enum {
+  QSA_K_PUSH_PRED = 0,   /* plasma predictor push + predicted J_perp deposit  */
+  QSA_K_PUSH_FINAL = 1,  /* plasma advance to the next slice                  */
+  QSA_K_DEP_S = 2,       /* plasma rho - J_z deposit                          */
+  QSA_K_DEP_J = 3,       /* plasma J deposit                                  */
+  QSA_K_ROW_R2C = 4,     /* row transforms, real -> half spectrum             */
+  QSA_K_COL = 5,         /* column transforms with the spectral solves        */
+  QSA_K_ROW_C2R = 6,     /* row transforms, half spectrum -> real             */
+  QSA_K_BEAM_DEPOSIT = 7,/* beam source deposit                               */
+  QSA_K_BEAM_PUSH = 8,   /* beam Boris push                                   */
+  QSA_K_COUNT = 9
+};
+
+/* Start timing every launch of one kernel class with a pair of HIP events
+ * recorded on the context's stream around it (at most 1<<17 launches per
+ * window; later launches run untimed).  Instrumentation for measurement; it
+ * adds two event records per timed launch. */
+qsa_status qsa_timing_begin(qsa_ctx* c, int32_t kernel_class);
+
+/* Stop timing; synchronizing.  *total_ms = summed kernel time of the timed
+ * launches, *launches = their count. */
+qsa_status qsa_timing_end(qsa_ctx* c, double* total_ms, int64_t* launches);
+
 /* Free the host context (the workspace is not touched). */
 qsa_status qsa_destroy(qsa_ctx* c);
 

@@ -116,8 +116,35 @@ struct qsa_ctx {
   bool swept = false;
   qsa_status sticky = QSA_OK;
   std::string err;
+  // launch timing (qsa_timing_begin/end)
+  int timing_class = -1;
+  std::vector<hipEvent_t> events;
+  size_t ev_used = 0;
   template <typename T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  void tstart(int k) {
+    if (k != timing_class) return;
+    if (ev_used + 2 > events.size()) {
+      if (events.size() >= (size_t)2 << 17) return;
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+      }
+      events.push_back(a);
+      events.push_back(b);
+    }
+    (void)hipEventRecord(events[ev_used], stream);
+  }
+  void tstop(int k) {
+    if (k != timing_class || ev_used + 2 > events.size()) return;
+    (void)hipEventRecord(events[ev_used + 1], stream);
+    ev_used += 2;
+  }
+  ~qsa_ctx() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
 };
 
 static qsa_status fail(qsa_ctx* c, qsa_status s, const std::string& msg) {
@@ -221,8 +248,10 @@ struct Engine {
     const int npairs = (g.ny + 1) >> 1;
     const dim3 grid((npairs + ppw - 1) / ppw, nf);
     const size_t smem = 2 * (size_t)ppw * g.nx * sizeof(C2<R>);
+    c->tstart(QSA_K_ROW_R2C);
     hipLaunchKernelGGL(k_row_r2c<R>, grid, dim3(ppw * tpt), smem, c->stream, g, a,
                        c->at<C2<R>>(c->L.twx), ppw);
+    c->tstop(QSA_K_ROW_R2C);
   }
   static void row_c2r(qsa_ctx* c, const Geo<R>& g, const RowC2RArgs<R>& a, int nf) {
     const int tpt = g.nx >> 2;
@@ -230,8 +259,10 @@ struct Engine {
     const int npairs = (g.ny + 1) >> 1;
     const dim3 grid((npairs + ppw - 1) / ppw, nf);
     const size_t smem = 2 * (size_t)ppw * g.nx * sizeof(C2<R>);
+    c->tstart(QSA_K_ROW_C2R);
     hipLaunchKernelGGL(k_row_c2r<R>, grid, dim3(ppw * tpt), smem, c->stream, g, a,
                        c->at<C2<R>>(c->L.twx), ppw);
+    c->tstop(QSA_K_ROW_C2R);
   }
   template <int MODE>
   static void col(qsa_ctx* c, const Geo<R>& g, const ColArgs<R>& a) {
@@ -239,8 +270,10 @@ struct Engine {
     const int cpw = (tpt >= 64) ? 1 : 64 / tpt;
     const dim3 grid((g.nxh + cpw - 1) / cpw);
     const size_t smem = (size_t)cpw * ColShape<MODE>::NB * g.ny * sizeof(C2<R>);
+    c->tstart(QSA_K_COL);
     hipLaunchKernelGGL((k_col<R, MODE>), grid, dim3(cpw * tpt), smem, c->stream, g, a,
                        c->at<C2<R>>(c->L.twy), cpw);
+    c->tstop(QSA_K_COL);
   }
 
   static qsa_status beam_deposit_all(qsa_ctx* c, const Geo<R>& g) {
@@ -252,7 +285,9 @@ struct Engine {
       if (c->beam_n[s] == 0) continue;
       BeamArgs<R> a = beam_args(c, g, s);
       const int64_t blocks = (a.n + 255) / 256;
+      c->tstart(QSA_K_BEAM_DEPOSIT);
       hipLaunchKernelGGL(k_beam_deposit<R>, dim3((unsigned)blocks), dim3(256), 0, c->stream, g, a);
+      c->tstop(QSA_K_BEAM_DEPOSIT);
     }
     HIP_OK(hipGetLastError());
     return QSA_OK;
@@ -349,7 +384,9 @@ struct Engine {
       pa.psi_m2 = (j >= 2) ? F(F_PSI, j - 2) : nullptr;
       const int64_t srcj = (int64_t)j * g.nperp;
       // ---- psi stage
+      c->tstart(QSA_K_DEP_S);
       hipLaunchKernelGGL(k_dep_S<R>, pgrid, pblock, 0, c->stream, g, pa);
+      c->tstop(QSA_K_DEP_S);
       {
         RowR2CArgs<R> ra;
         std::memset(&ra, 0, sizeof(ra));
@@ -372,7 +409,9 @@ struct Engine {
         row_c2r(c, g, rc, 3);
       }
       // ---- J stage
+      c->tstart(QSA_K_DEP_J);
       hipLaunchKernelGGL(k_dep_J<R>, pgrid, pblock, 0, c->stream, g, pa);
+      c->tstop(QSA_K_DEP_J);
       {
         RowR2CArgs<R> ra;
         std::memset(&ra, 0, sizeof(ra));
@@ -409,7 +448,9 @@ struct Engine {
       }
       // ---- B_perp predictor-corrector
       for (int k = 0; k < p.n_corr; ++k) {
+        c->tstart(QSA_K_PUSH_PRED);
         hipLaunchKernelGGL((k_push<R, false>), pgrid, pblock, 0, c->stream, g, pa);
+        c->tstop(QSA_K_PUSH_PRED);
         {
           RowR2CArgs<R> ra;
           std::memset(&ra, 0, sizeof(ra));
@@ -434,7 +475,9 @@ struct Engine {
         }
       }
       // ---- advance the plasma to slice j+1
+      c->tstart(QSA_K_PUSH_FINAL);
       hipLaunchKernelGGL((k_push<R, true>), pgrid, pblock, 0, c->stream, g, pa);
+      c->tstop(QSA_K_PUSH_FINAL);
     }
     HIP_OK(hipGetLastError());
     c->swept = true;
@@ -447,7 +490,9 @@ struct Engine {
       if (c->beam_n[s] == 0) continue;
       BeamArgs<R> a = beam_args(c, g, s);
       const int64_t blocks = (a.n + 255) / 256;
+      c->tstart(QSA_K_BEAM_PUSH);
       hipLaunchKernelGGL(k_beam_push<R>, dim3((unsigned)blocks), dim3(256), 0, c->stream, g, a);
+      c->tstop(QSA_K_BEAM_PUSH);
     }
     HIP_OK(hipGetLastError());
     return QSA_OK;
@@ -722,6 +767,30 @@ qsa_status qsa_sync(qsa_ctx* c) {
   if (!c) return QSA_E_INVALID;
   if (c->sticky != QSA_OK) return c->sticky;
   return check_device(c);
+}
+
+qsa_status qsa_timing_begin(qsa_ctx* c, int32_t kernel_class) {
+  if (!c) return QSA_E_INVALID;
+  if (kernel_class < 0 || kernel_class >= QSA_K_COUNT) return fail(c, QSA_E_INVALID, "unknown kernel class");
+  c->timing_class = kernel_class;
+  c->ev_used = 0;
+  return QSA_OK;
+}
+
+qsa_status qsa_timing_end(qsa_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return QSA_E_INVALID;
+  HIP_OK(hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, c->events[i], c->events[i + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (int64_t)(c->ev_used / 2);
+  c->timing_class = -1;
+  c->ev_used = 0;
+  return QSA_OK;
 }
 
 qsa_status qsa_destroy(qsa_ctx* c) {

@@ -132,6 +132,17 @@ class Sim:
     def sync(self):
         self._check(self.lib.qsa_sync(self.ctx))
 
+    def timing_begin(self, kernel_class: str):
+        """Time every launch of one kernel class with HIP events on the stream."""
+        self._check(self.lib.qsa_timing_begin(self.ctx, L.KERNEL_CLASSES[kernel_class]))
+
+    def timing_end(self):
+        """-> (summed kernel milliseconds, number of timed launches)."""
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(self.lib.qsa_timing_end(self.ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
     def fields(self, name: str, xi0: int = 0, xi1: Optional[int] = None,
                on_device: bool = False):
         """Slices [xi0, xi1) of one field as float64 [nxi, ny, nx] (numpy, or a
