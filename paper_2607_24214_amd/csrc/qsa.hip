@@ -21,6 +21,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxN = 512;
+constexpr int kSortEvery = 8;   // plasma counting sort every kSortEvery slices
 
 bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 int ilog2(int v) {
@@ -32,7 +33,8 @@ int ilog2(int v) {
 // Byte offsets of every device array inside the workspace.
 struct Layout {
   size_t twx, twy, kx2, kdx, ky2, kdy;
-  size_t tmpl[4], pl[4];
+  size_t tmpl[4], pl[4], pl2[4];
+  size_t cell_of, count, bsum;
   size_t beam[QSA_MAX_SPECIES][7];  // x, y, ux, uy, uz, w (real), xi (double)
   size_t src, fields, dep, rowspec, colout, jring, jz, bring, ode, err, emit;
   size_t total;
@@ -63,6 +65,10 @@ Layout make_layout(const qsa_params& p) {
   L.kdy = c.take(p.ny * rs);
   for (int i = 0; i < 4; ++i) L.tmpl[i] = c.take(p.n_plasma * rs);
   for (int i = 0; i < 4; ++i) L.pl[i] = c.take(p.n_plasma * rs);
+  for (int i = 0; i < 4; ++i) L.pl2[i] = c.take(p.n_plasma * rs);
+  L.cell_of = c.take(p.n_plasma * sizeof(int));
+  L.count = c.take(nperp * sizeof(int));
+  L.bsum = c.take(256 * sizeof(int));
   for (int s = 0; s < QSA_MAX_SPECIES; ++s) {
     const size_t cap = (s < p.n_species) ? (size_t)p.beam_capacity[s] : 0;
     for (int k = 0; k < 6; ++k) L.beam[s][k] = c.take(cap * rs);
@@ -244,7 +250,7 @@ struct Engine {
   // ---- launches of the per-slice kernels --------------------------------
   static void row_r2c(qsa_ctx* c, const Geo<R>& g, const RowR2CArgs<R>& a, int nf) {
     const int tpt = g.nx >> 2;
-    const int ppw = (256 / tpt) > 0 ? 256 / tpt : 1;
+    const int ppw = (tpt >= 64) ? 1 : 64 / tpt;
     const int npairs = (g.ny + 1) >> 1;
     const dim3 grid((npairs + ppw - 1) / ppw, nf);
     const size_t smem = 2 * (size_t)ppw * g.nx * sizeof(C2<R>);
@@ -255,7 +261,7 @@ struct Engine {
   }
   static void row_c2r(qsa_ctx* c, const Geo<R>& g, const RowC2RArgs<R>& a, int nf) {
     const int tpt = g.nx >> 2;
-    const int ppw = (256 / tpt) > 0 ? 256 / tpt : 1;
+    const int ppw = (tpt >= 64) ? 1 : 64 / tpt;
     const int npairs = (g.ny + 1) >> 1;
     const dim3 grid((npairs + ppw - 1) / ppw, nf);
     const size_t smem = 2 * (size_t)ppw * g.nx * sizeof(C2<R>);
@@ -266,12 +272,12 @@ struct Engine {
   }
   template <int MODE>
   static void col(qsa_ctx* c, const Geo<R>& g, const ColArgs<R>& a) {
-    const int tpt = (g.ny >= 4) ? (g.ny >> 2) : 1;
-    const int cpw = (tpt >= 64) ? 1 : 64 / tpt;
+    const int per_col = ColShape<MODE>::G * col_tpt(g.ny);
+    const int cpw = (per_col >= 64) ? 1 : 64 / per_col;
     const dim3 grid((g.nxh + cpw - 1) / cpw);
-    const size_t smem = (size_t)cpw * ColShape<MODE>::NB * g.ny * sizeof(C2<R>);
+    const size_t smem = (size_t)cpw * 2 * ColShape<MODE>::G * g.ny * sizeof(C2<R>);
     c->tstart(QSA_K_COL);
-    hipLaunchKernelGGL((k_col<R, MODE>), grid, dim3(cpw * tpt), smem, c->stream, g, a,
+    hipLaunchKernelGGL((k_col<R, MODE>), grid, dim3(cpw * per_col), smem, c->stream, g, a,
                        c->at<C2<R>>(c->L.twy), cpw);
     c->tstop(QSA_K_COL);
   }
@@ -284,7 +290,7 @@ struct Engine {
     for (int s = 0; s < p.n_species; ++s) {
       if (c->beam_n[s] == 0) continue;
       BeamArgs<R> a = beam_args(c, g, s);
-      const int64_t blocks = (a.n + 255) / 256;
+      const int64_t blocks = (a.n + 256 * BEAM_PPT - 1) / (256 * BEAM_PPT);
       c->tstart(QSA_K_BEAM_DEPOSIT);
       hipLaunchKernelGGL(k_beam_deposit<R>, dim3((unsigned)blocks), dim3(256), 0, c->stream, g, a);
       c->tstop(QSA_K_BEAM_DEPOSIT);
@@ -376,7 +382,17 @@ struct Engine {
     auto F = [&](int slot, int j) -> R* { return fields + slot * plane + (int64_t)j * g.nperp; };
     const int fslot[6] = {F_PSI, F_DXPSI, F_DYPSI, F_BX, F_BY, F_BZ};
 
+    int cur = 0;   // which plasma buffer set holds the state
     for (int j = 0; j < p.nxi; ++j) {
+      if (j > 0 && j % kSortEvery == 0) {
+        if ((st = sort_plasma(c, g, cur)) != QSA_OK) return st;
+        cur ^= 1;
+        const size_t* P = cur ? L.pl2 : L.pl;
+        pa.x = c->at<R>(P[0]);
+        pa.y = c->at<R>(P[1]);
+        pa.ux = c->at<R>(P[2]);
+        pa.uy = c->at<R>(P[3]);
+      }
       for (int q = 0; q < 6; ++q) {
         pa.F0[q] = F(fslot[q], j);
         pa.F1[q] = (j >= 1) ? F(fslot[q], j - 1) : nullptr;
@@ -449,7 +465,7 @@ struct Engine {
       // ---- B_perp predictor-corrector
       for (int k = 0; k < p.n_corr; ++k) {
         c->tstart(QSA_K_PUSH_PRED);
-        hipLaunchKernelGGL((k_push<R, false>), pgrid, pblock, 0, c->stream, g, pa);
+        hipLaunchKernelGGL(k_push_pred<R>, pgrid, pblock, 0, c->stream, g, pa);
         c->tstop(QSA_K_PUSH_PRED);
         {
           RowR2CArgs<R> ra;
@@ -476,11 +492,34 @@ struct Engine {
       }
       // ---- advance the plasma to slice j+1
       c->tstart(QSA_K_PUSH_FINAL);
-      hipLaunchKernelGGL((k_push<R, true>), pgrid, pblock, 0, c->stream, g, pa);
+      hipLaunchKernelGGL(k_push_final<R>, pgrid, pblock, 0, c->stream, g, pa);
       c->tstop(QSA_K_PUSH_FINAL);
     }
     HIP_OK(hipGetLastError());
     c->swept = true;
+    return QSA_OK;
+  }
+
+  // Counting sort of the plasma state (buffer set cur -> cur ^ 1) by cell.
+  static qsa_status sort_plasma(qsa_ctx* c, const Geo<R>& g, int cur) {
+    const Layout& L = c->L;
+    const int np = (int)c->p.n_plasma;
+    const size_t* A = cur ? L.pl2 : L.pl;
+    const size_t* B = cur ? L.pl : L.pl2;
+    int* count = c->at<int>(L.count);
+    int* cell_of = c->at<int>(L.cell_of);
+    int* bsum = c->at<int>(L.bsum);
+    hipLaunchKernelGGL(k_fill<int>, dim3(fill_blocks(g.nperp)), dim3(256), 0, c->stream, count,
+                       (int64_t)g.nperp, 0);
+    hipLaunchKernelGGL(k_sort_count<R>, dim3((np + 255) / 256), dim3(256), 0, c->stream, g,
+                       c->at<R>(A[0]), c->at<R>(A[1]), np, cell_of, count);
+    const int nb = (g.nperp + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, c->stream, count, g.nperp, bsum);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, c->stream, bsum, nb);
+    hipLaunchKernelGGL(k_sort_scatter<R>, dim3((np + 255) / 256), dim3(256), 0, c->stream, np, cell_of,
+                       count, bsum, c->at<R>(A[0]), c->at<R>(A[1]), c->at<R>(A[2]), c->at<R>(A[3]),
+                       c->at<R>(B[0]), c->at<R>(B[1]), c->at<R>(B[2]), c->at<R>(B[3]));
+    HIP_OK(hipGetLastError());
     return QSA_OK;
   }
 

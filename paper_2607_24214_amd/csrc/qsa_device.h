@@ -83,6 +83,30 @@ __device__ __forceinline__ Stencil<R> stencil2(const Geo<R>& g, R x, R y) {
   return s;
 }
 
+// Cell (i0, l0), wrapped into the grid, and the fractional offsets of (x, y).
+template <typename R>
+__device__ __forceinline__ void cell2(const Geo<R>& g, R x, R y, int& i0, int& l0, R& fx, R& fy) {
+  R gx = x * g.inv_dx;
+  R gy = y * g.inv_dy;
+  R fx0 = floor(gx);
+  R fy0 = floor(gy);
+  fx = gx - fx0;
+  fy = gy - fy0;
+  R cx = fmin(fmax(fx0, R(-1.0e9)), R(1.0e9));
+  R cy = fmin(fmax(fy0, R(-1.0e9)), R(1.0e9));
+  i0 = wrap_index((int)cx, g.nx);
+  l0 = wrap_index((int)cy, g.ny);
+}
+
+// Logical block index for a launch of nb blocks, so that the blocks one XCD
+// runs (hardware dispatch is round-robin over the 8 XCDs) are consecutive:
+// neighbouring particle chunks then share that XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int per = nb >> 3, rem = nb & 7;
+  const int x = b & 7, k = b >> 3;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
 template <typename R>
 __device__ __forceinline__ R gather(const R* __restrict__ f, const Stencil<R>& s) {
   return f[s.n00] * s.w00 + f[s.n10] * s.w10 + f[s.n01] * s.w01 + f[s.n11] * s.w11;
@@ -97,6 +121,84 @@ __device__ __forceinline__ void scatter(R* __restrict__ f, const Stencil<R>& s, 
   atomic_add(f + s.n10, q * s.w10);
   atomic_add(f + s.n01, q * s.w01);
   atomic_add(f + s.n11, q * s.w11);
+}
+
+// ---------------------------------------------------------------------------
+// Block-level deposit through an LDS tile.  Each thread brings at most one
+// particle (live) with cell (i0, l0), offsets (fx, fy) and NC values.  The
+// block reduces the bounding box of its cells; when the box (plus the +1
+// nodes) fits the tile, the particles accumulate there with LDS atomics and
+// the block then adds the non-zero tile nodes to the grids with one global
+// atomic each.  Otherwise every particle adds its four nodes to the grids
+// directly.  Every thread of the block must call this (it has barriers).
+// ---------------------------------------------------------------------------
+template <typename R, int NC>
+struct TileCap {
+  static constexpr int BYTES = 32768;
+  static constexpr int NODES = BYTES / (NC * (int)sizeof(R));
+};
+
+template <typename R, int NC>
+__device__ __forceinline__ void block_deposit(const Geo<R>& g, bool live, int i0, int l0, R fx, R fy,
+                                              const R (&v)[NC], R* const (&dst)[NC], R* tile,
+                                              int* bb) {
+  constexpr int CAP = TileCap<R, NC>::NODES;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) {
+    bb[0] = 0x7fffffff;
+    bb[1] = 0x7fffffff;
+    bb[2] = -1;
+    bb[3] = -1;
+  }
+  for (int t = tid; t < NC * CAP; t += nt) tile[t] = R(0);
+  __syncthreads();
+  if (live) {
+    atomicMin(&bb[0], l0);
+    atomicMin(&bb[1], i0);
+    atomicMax(&bb[2], l0);
+    atomicMax(&bb[3], i0);
+  }
+  __syncthreads();
+  const int lmin = bb[0], imin = bb[1];
+  const bool any = bb[2] >= 0;
+  const int nl = any ? bb[2] - lmin + 2 : 0;
+  const int ni = any ? bb[3] - imin + 2 : 0;
+  const bool fits = any && nl * ni <= CAP;
+  if (live) {
+    const R ax = R(1) - fx, ay = R(1) - fy;
+    const R w[4] = {ax * ay, fx * ay, ax * fy, fx * fy};
+    if (fits) {
+      const int t00 = (l0 - lmin) * ni + (i0 - imin);
+      const int off[4] = {t00, t00 + 1, t00 + ni, t00 + ni + 1};
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) atomicAdd(&tile[c * CAP + off[q]], v[c] * w[q]);
+    } else {
+      const int i1 = (i0 + 1 == g.nx) ? 0 : i0 + 1;
+      const int l1 = (l0 + 1 == g.ny) ? 0 : l0 + 1;
+      const int nodes[4] = {l0 * g.nx + i0, l0 * g.nx + i1, l1 * g.nx + i0, l1 * g.nx + i1};
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) atomic_add(dst[c] + nodes[q], v[c] * w[q]);
+    }
+  }
+  __syncthreads();
+  if (fits) {
+    for (int t = tid; t < nl * ni; t += nt) {
+      const int ll = t / ni, ii = t - ll * ni;
+      int lg = lmin + ll;
+      lg -= (lg >= g.ny) ? g.ny : 0;
+      int ig = imin + ii;
+      ig -= (ig >= g.nx) ? g.nx : 0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const R val = tile[c * CAP + t];
+        if (val != R(0)) atomic_add(dst[c] + lg * g.nx + ig, val);
+      }
+    }
+  }
 }
 
 // Periodic wrap into [0, L); a value that rounds to L maps to 0.

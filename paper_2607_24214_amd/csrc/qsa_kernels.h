@@ -219,34 +219,43 @@ template <int MODE>
 struct ColShape {
   static constexpr int NIN = (MODE == COL_PSI) ? 1 : (MODE == COL_J ? 3 : 2);
   static constexpr int NOUT = (MODE == COL_PSI) ? 3 : (MODE == COL_J ? 4 : 2);
-  static constexpr int NB = (NIN > NOUT ? NIN : NOUT) + 1;  // + one FFT scratch
+  static constexpr int G = NIN > NOUT ? NIN : NOUT;   // thread groups per column
 };
 
+// Threads per column transform for ny rows (loops cover the rest).
+__host__ __device__ __forceinline__ int col_tpt(int ny) {
+  const int t = ny >> 2;
+  return t < 1 ? 1 : (t > 64 ? 64 : t);
+}
+
 // Forward transform along y of each input column, the spectral solve of the
-// mode, inverse transform along y of each output.  cpw columns per block,
-// tpt = max(1, ny/4) threads per column.
+// mode, inverse transform along y of each output.  Each column is worked by
+// G groups of tpt threads, one group per field transform, so the transforms
+// of one column run side by side; cpw columns per block.
 template <typename R, int MODE>
 __global__ void __launch_bounds__(256) k_col(Geo<R> g, ColArgs<R> a,
                                              const C2<R>* __restrict__ twy, int cpw) {
   using S = ColShape<MODE>;
+  constexpr int G = S::G;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* sm = reinterpret_cast<C2<R>*>(smem_raw);
   const int ny = g.ny;
-  const int tpt = (ny >= 4) ? (ny >> 2) : 1;
-  const int c = threadIdx.x / tpt, t = threadIdx.x - c * tpt;
+  const int tpt = col_tpt(ny);
+  const int per_col = G * tpt;
+  const int c = threadIdx.x / per_col;
+  const int r = threadIdx.x - c * per_col;
+  const int grp = r / tpt, t = r - grp * tpt;
   const int kx = blockIdx.x * cpw + c;
   const bool valid = kx < g.nxh;
-  C2<R>* buf = sm + (size_t)c * S::NB * ny;
-  C2<R>* scratch = buf + (S::NB - 1) * ny;
-#pragma unroll
-  for (int f = 0; f < S::NIN; ++f)
-    for (int y = t; y < ny; y += tpt)
-      buf[f * ny + y] = valid ? a.in[f][y * g.nxh + kx] : C2<R>{0, 0};
+  C2<R>* D = sm + (size_t)c * 2 * G * ny;   // G data columns
+  C2<R>* Sx = D + G * ny;                   // G scratch columns
+  C2<R>* mine = D + grp * ny;
+  for (int y = t; y < ny; y += tpt)
+    mine[y] = (valid && grp < S::NIN) ? a.in[grp][y * g.nxh + kx] : C2<R>{0, 0};
   __syncthreads();
-#pragma unroll
-  for (int f = 0; f < S::NIN; ++f) fft_lds_inplace<R, false>(buf + f * ny, scratch, ny, g.lgy, t, tpt, twy);
+  fft_lds_inplace<R, false>(mine, Sx + grp * ny, ny, g.lgy, t, tpt, twy);
 
-  for (int y = t; y < ny; y += tpt) {
+  for (int y = r; y < ny; y += per_col) {
     C2<R> o[S::NOUT];
 #pragma unroll
     for (int q = 0; q < S::NOUT; ++q) o[q] = C2<R>{0, 0};
@@ -258,13 +267,13 @@ __global__ void __launch_bounds__(256) k_col(Geo<R> g, ColArgs<R> a,
       const R iks = k0 ? R(0) : R(1) / ksq;
       if (MODE == COL_PSI) {
         // -lap psi = rho - J_z; the k = 0 value is the transverse-mean wake
-        C2<R> ph = cscale(buf[y], iks);
+        C2<R> ph = cscale(D[y], iks);
         if (k0) ph = C2<R>{(R)a.ode[1] * a.n_perp, R(0)};
         o[0] = cscale(ph, a.inv_n);
         o[1] = cscale(cmul_ik(ph, kdx), a.inv_n);
         o[2] = cscale(cmul_ik(ph, kdy), a.inv_n);
       } else if (MODE == COL_J) {
-        const C2<R> jx = buf[y], jy = buf[ny + y], jzv = buf[2 * ny + y];
+        const C2<R> jx = D[y], jy = D[ny + y], jzv = D[2 * ny + y];
         a.jr_w[0][e] = jx;
         a.jr_w[1][e] = jy;
         a.jz[e] = jzv;
@@ -294,8 +303,8 @@ __global__ void __launch_bounds__(256) k_col(Geo<R> g, ColArgs<R> a,
       } else {
         // D = d_xi J_perp ~ (J~_perp^{j+1} - J_perp^{j-1})/(2h)
         const R i2h = R(0.5) / a.h;
-        const C2<R> dx = cscale(csub(buf[y], a.jr_r[0][e]), i2h);
-        const C2<R> dy = cscale(csub(buf[ny + y], a.jr_r[1][e]), i2h);
+        const C2<R> dx = cscale(csub(D[y], a.jr_r[0][e]), i2h);
+        const C2<R> dy = cscale(csub(D[ny + y], a.jr_r[1][e]), i2h);
         const C2<R> jzv = a.jz[e];
         const C2<R> bxo = a.b_cur[0][e], byo = a.b_cur[1][e];
         const R iden = R(1) / (-ksq - a.kappa2);
@@ -309,17 +318,15 @@ __global__ void __launch_bounds__(256) k_col(Geo<R> g, ColArgs<R> a,
         o[1] = cscale(byn, a.inv_n);
       }
     }
+    // every thread of the column has read its inputs at row y before any
+    // output at row y is written: rows are owned by exactly one thread here
 #pragma unroll
-    for (int q = 0; q < S::NOUT; ++q) buf[q * ny + y] = o[q];
+    for (int q = 0; q < S::NOUT; ++q) D[q * ny + y] = o[q];
   }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < S::NOUT; ++q) fft_lds_inplace<R, true>(buf + q * ny, scratch, ny, g.lgy, t, tpt, twy);
-  if (valid) {
-#pragma unroll
-    for (int q = 0; q < S::NOUT; ++q)
-      for (int y = t; y < ny; y += tpt) a.out[q][y * g.nxh + kx] = buf[q * ny + y];
-  }
+  fft_lds_inplace<R, true>(mine, Sx + grp * ny, ny, g.lgy, t, tpt, twy);
+  if (valid && grp < S::NOUT)
+    for (int y = t; y < ny; y += tpt) a.out[grp][y * g.nxh + kx] = mine[y];
 }
 
 // ---------------------------------------------------------- plasma particles
@@ -341,28 +348,49 @@ struct PlasmaArgs {
   R h;
 };
 
+// Particle p of block b: the blocks of one XCD take consecutive chunks.
+__device__ __forceinline__ int plasma_index() {
+  return xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_dep_S(Geo<R> g, PlasmaArgs<R> a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.np) return;
-  const Stencil<R> s = stencil2(g, a.x[p], a.y[p]);
-  scatter(a.dep0, s, a.q);
+  __shared__ R tile[TileCap<R, 1>::NODES];
+  __shared__ int bb[4];
+  const int p = plasma_index();
+  const bool live = p < a.np;
+  int i0 = 0, l0 = 0;
+  R fx = 0, fy = 0;
+  if (live) cell2(g, a.x[p], a.y[p], i0, l0, fx, fy);
+  const R v[1] = {a.q};
+  R* const dst[1] = {a.dep0};
+  block_deposit<R, 1>(g, live, i0, l0, fx, fy, v, dst, tile, bb);
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_dep_J(Geo<R> g, PlasmaArgs<R> a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.np) return;
-  const R ux = a.ux[p], uy = a.uy[p];
-  const Stencil<R> s = stencil2(g, a.x[p], a.y[p]);
-  const R G = R(1) + gather(a.F0[0], s);
-  if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
-  const R gam = (R(1) + ux * ux + uy * uy + G * G) / (R(2) * G);
-  const R uz = gam - G;
-  const R qg = a.q / G;
-  scatter(a.dep0, s, qg * ux);
-  scatter(a.dep1, s, qg * uy);
-  scatter(a.dep2, s, qg * uz);
+  __shared__ R tile[3 * TileCap<R, 3>::NODES];
+  __shared__ int bb[4];
+  const int p = plasma_index();
+  const bool live = p < a.np;
+  int i0 = 0, l0 = 0;
+  R fx = 0, fy = 0;
+  R v[3] = {0, 0, 0};
+  if (live) {
+    const R ux = a.ux[p], uy = a.uy[p];
+    cell2(g, a.x[p], a.y[p], i0, l0, fx, fy);
+    const Stencil<R> s = stencil2(g, a.x[p], a.y[p]);
+    const R G = R(1) + gather(a.F0[0], s);
+    if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
+    const R gam = (R(1) + ux * ux + uy * uy + G * G) / (R(2) * G);
+    const R uz = gam - G;
+    const R qg = a.q / G;
+    v[0] = qg * ux;
+    v[1] = qg * uy;
+    v[2] = qg * uz;
+  }
+  R* const dst[3] = {a.dep0, a.dep1, a.dep2};
+  block_deposit<R, 3>(g, live, i0, l0, fx, fy, v, dst, tile, bb);
 }
 
 // d/dxi of (x, y, u_x, u_y) from the six gathered fields
@@ -379,13 +407,9 @@ __device__ __forceinline__ void plasma_rhs(const R f[6], R ux, R uy, R d[4], int
 }
 
 // RK2 (midpoint) push from slice j with F^j and F^{j+1/2} = (3F^j - F^{j-1})/2.
-// FINAL: store Y^{j+1}.  Otherwise deposit the predicted J_perp at j+1 with
-// 1 + psi~ from psi~^{j+1} = 3 psi^j - 3 psi^{j-1} + psi^{j-2}.
-template <typename R, bool FINAL>
-__global__ void __launch_bounds__(256) k_push(Geo<R> g, PlasmaArgs<R> a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.np) return;
-  const R x = a.x[p], y = a.y[p], ux = a.ux[p], uy = a.uy[p];
+template <typename R>
+__device__ __forceinline__ void rk2_push(const Geo<R>& g, const PlasmaArgs<R>& a, R x, R y, R ux,
+                                         R uy, R& xn, R& yn, R& uxn, R& uyn) {
   const R hh = a.h;
   R f[6], d1[4], d2[4];
   {
@@ -409,16 +433,27 @@ __global__ void __launch_bounds__(256) k_push(Geo<R> g, PlasmaArgs<R> a) {
     }
     plasma_rhs(f, uxs, uys, d2, a.err);
   }
-  const R xn = x + hh * d2[0];
-  const R yn = y + hh * d2[1];
-  const R uxn = ux + hh * d2[2];
-  const R uyn = uy + hh * d2[3];
-  if (FINAL) {
-    a.x[p] = wrap_pos(xn, g.lx, g.inv_lx);
-    a.y[p] = wrap_pos(yn, g.ly, g.inv_ly);
-    a.ux[p] = uxn;
-    a.uy[p] = uyn;
-  } else {
+  xn = x + hh * d2[0];
+  yn = y + hh * d2[1];
+  uxn = ux + hh * d2[2];
+  uyn = uy + hh * d2[3];
+}
+
+// Predictor: push a copy of Y^j to j+1 and deposit the predicted J_perp at
+// j+1 with 1 + psi~ from psi~^{j+1} = 3 psi^j - 3 psi^{j-1} + psi^{j-2}.
+template <typename R>
+__global__ void __launch_bounds__(256) k_push_pred(Geo<R> g, PlasmaArgs<R> a) {
+  __shared__ R tile[2 * TileCap<R, 2>::NODES];
+  __shared__ int bb[4];
+  const int p = plasma_index();
+  const bool live = p < a.np;
+  int i0 = 0, l0 = 0;
+  R fx = 0, fy = 0;
+  R v[2] = {0, 0};
+  if (live) {
+    R xn, yn, uxn, uyn;
+    rk2_push(g, a, a.x[p], a.y[p], a.ux[p], a.uy[p], xn, yn, uxn, uyn);
+    cell2(g, xn, yn, i0, l0, fx, fy);
     const Stencil<R> s = stencil2(g, xn, yn);
     R pt = R(3) * gather(a.F0[0], s);
     if (a.F1[0]) pt -= R(3) * gather(a.F1[0], s);
@@ -426,9 +461,102 @@ __global__ void __launch_bounds__(256) k_push(Geo<R> g, PlasmaArgs<R> a) {
     const R G = R(1) + pt;
     if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
     const R qg = a.q / G;
-    scatter(a.dep0, s, qg * uxn);
-    scatter(a.dep1, s, qg * uyn);
+    v[0] = qg * uxn;
+    v[1] = qg * uyn;
   }
+  R* const dst[2] = {a.dep0, a.dep1};
+  block_deposit<R, 2>(g, live, i0, l0, fx, fy, v, dst, tile, bb);
+}
+
+// Final advance: Y^{j+1} with the converged fields, positions wrapped.
+template <typename R>
+__global__ void __launch_bounds__(256) k_push_final(Geo<R> g, PlasmaArgs<R> a) {
+  const int p = plasma_index();
+  if (p >= a.np) return;
+  R xn, yn, uxn, uyn;
+  rk2_push(g, a, a.x[p], a.y[p], a.ux[p], a.uy[p], xn, yn, uxn, uyn);
+  a.x[p] = wrap_pos(xn, g.lx, g.inv_lx);
+  a.y[p] = wrap_pos(yn, g.ly, g.inv_ly);
+  a.ux[p] = uxn;
+  a.uy[p] = uyn;
+}
+
+// Counting sort of the plasma by cell (keeps the particles of a block close
+// together, which is what makes the tiled deposits pay).
+template <typename R>
+__global__ void __launch_bounds__(256) k_sort_count(Geo<R> g, const R* __restrict__ x,
+                                                    const R* __restrict__ y, int np,
+                                                    int* __restrict__ cell_of, int* __restrict__ count) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  int i0, l0;
+  R fx, fy;
+  cell2(g, x[p], y[p], i0, l0, fx, fy);
+  const int c = l0 * g.nx + i0;
+  cell_of[p] = c;
+  atomicAdd(&count[c], 1);
+}
+
+// Exclusive scan of v[0, n) in blocks of 1024: offsets within the block in
+// place, block totals in bsum[block].
+__global__ void __launch_bounds__(256) k_scan_local(int* __restrict__ v, int n, int* __restrict__ bsum) {
+  __shared__ int s[256];
+  const int t = threadIdx.x;
+  const int base = blockIdx.x * 1024 + t * 4;
+  int x[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) x[k] = (base + k < n) ? v[base + k] : 0;
+  const int tsum = x[0] + x[1] + x[2] + x[3];
+  s[t] = tsum;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int add = (t >= off) ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  int run = s[t] - tsum;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) v[base + k] = run;
+    run += x[k];
+  }
+  if (t == 255) bsum[blockIdx.x] = s[255];
+}
+
+// Exclusive scan of the (at most 256) block totals, one block.
+__global__ void __launch_bounds__(256) k_scan_blocks(int* __restrict__ bsum, int nb) {
+  __shared__ int s[256];
+  const int t = threadIdx.x;
+  const int x = (t < nb) ? bsum[t] : 0;
+  s[t] = x;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int add = (t >= off) ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  if (t < nb) bsum[t] = s[t] - x;
+}
+
+// cursor[c] + bsum[c / 1024] is the first free slot of cell c.
+template <typename R>
+__global__ void __launch_bounds__(256) k_sort_scatter(int np, const int* __restrict__ cell_of,
+                                                      int* __restrict__ cursor, const int* __restrict__ bsum,
+                                                      const R* __restrict__ x,
+                                                      const R* __restrict__ y, const R* __restrict__ ux,
+                                                      const R* __restrict__ uy, R* __restrict__ x2,
+                                                      R* __restrict__ y2, R* __restrict__ ux2,
+                                                      R* __restrict__ uy2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int c = cell_of[p];
+  const int d = atomicAdd(&cursor[c], 1) + bsum[c >> 10];
+  x2[d] = x[p];
+  y2[d] = y[p];
+  ux2[d] = ux[p];
+  uy2[d] = uy[p];
 }
 
 // -------------------------------------------------------------------- beam
@@ -451,34 +579,121 @@ struct BeamArgs {
   double xi_max;      // (nxi - 1) dxi: particles at or beyond it leave the box
 };
 
-// 3D linear-shape deposit of the beam sources.
+// 3D linear-shape deposit of the beam sources, staged through an LDS tile
+// over the bounding box of the block's cells (same scheme as block_deposit,
+// in (xi, y, x)); each thread brings BEAM_PPT particles.
+#define BEAM_PPT 2
 template <typename R>
 __global__ void __launch_bounds__(256) k_beam_deposit(Geo<R> g, BeamArgs<R> a) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.n) return;
-  const R w = a.w[p];
-  if (w == R(0)) return;
-  const R ux = a.ux[p], uy = a.uy[p], uz = a.uz[p];
-  const R up2 = ux * ux + uy * uy;
-  const R gam = sqrt(R(1) + up2 + uz * uz);
-  const R omvz = (R(1) + up2) / (gam * (gam + uz));   // 1 - v_z without cancellation
-  const R q = a.zq * w;
-  const double gz = a.xi[p] * a.inv_dxi;
-  if (!(gz > -1.0 && gz < (double)g.nxi)) return;      // no node inside the grid
-  const double fz0 = floor(gz);
-  const int j0 = (int)fz0;
-  const R fz = (R)(gz - fz0);
-  const Stencil<R> s = stencil2(g, a.x[p], a.y[p]);
+  constexpr int CAP = TileCap<R, 4>::NODES;
+  __shared__ R tile[4 * CAP];
+  __shared__ int bb[6];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (256 * BEAM_PPT);
+  bool live[BEAM_PPT];
+  int j0[BEAM_PPT], l0[BEAM_PPT], i0[BEAM_PPT];
+  R fz[BEAM_PPT], fx[BEAM_PPT], fy[BEAM_PPT], v[BEAM_PPT][4];
+  if (tid == 0) {
+    bb[0] = bb[1] = bb[2] = 0x7fffffff;
+    bb[3] = bb[4] = bb[5] = -0x7fffffff;
+  }
+  for (int t = tid; t < 4 * CAP; t += 256) tile[t] = R(0);
+#pragma unroll
+  for (int k = 0; k < BEAM_PPT; ++k) {
+    const int64_t p = base + k * 256 + tid;
+    live[k] = false;
+    j0[k] = l0[k] = i0[k] = 0;
+    fz[k] = fx[k] = fy[k] = R(0);
+    v[k][0] = v[k][1] = v[k][2] = v[k][3] = R(0);
+    if (p < a.n) {
+      const R w = a.w[p];
+      const double gz = a.xi[p] * a.inv_dxi;
+      if (w != R(0) && gz > -1.0 && gz < (double)g.nxi) {
+        live[k] = true;
+        const double fz0 = floor(gz);
+        j0[k] = (int)fz0;
+        fz[k] = (R)(gz - fz0);
+        cell2(g, a.x[p], a.y[p], i0[k], l0[k], fx[k], fy[k]);
+        const R ux = a.ux[p], uy = a.uy[p], uz = a.uz[p];
+        const R up2 = ux * ux + uy * uy;
+        const R gam = sqrt(R(1) + up2 + uz * uz);
+        const R q = a.zq * w;
+        v[k][0] = q * ((R(1) + up2) / (gam * (gam + uz)));   // 1 - v_z without cancellation
+        v[k][1] = q * ux / gam;
+        v[k][2] = q * uy / gam;
+        v[k][3] = q * uz / gam;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < BEAM_PPT; ++k)
+    if (live[k]) {
+      atomicMin(&bb[0], j0[k]);
+      atomicMin(&bb[1], l0[k]);
+      atomicMin(&bb[2], i0[k]);
+      atomicMax(&bb[3], j0[k]);
+      atomicMax(&bb[4], l0[k]);
+      atomicMax(&bb[5], i0[k]);
+    }
+  __syncthreads();
+  const bool any = bb[3] >= bb[0];
+  const int jmin = bb[0], lmin = bb[1], imin = bb[2];
+  const int nj = any ? bb[3] - jmin + 2 : 0;
+  const int nl = any ? bb[4] - lmin + 2 : 0;
+  const int ni = any ? bb[5] - imin + 2 : 0;
+  const bool fits = any && (int64_t)nj * nl * ni <= CAP;
   const int64_t plane = (int64_t)g.nxi * g.nperp;
-  const R vals[4] = {q * omvz, q * ux / gam, q * uy / gam, q * uz / gam};
 #pragma unroll
-  for (int dj = 0; dj < 2; ++dj) {
-    const int jj = j0 + dj;
-    if (jj < 0 || jj >= g.nxi) continue;
-    const R wz = dj ? fz : R(1) - fz;
-    R* base = a.src + (int64_t)jj * g.nperp;
+  for (int k = 0; k < BEAM_PPT; ++k) {
+    if (!live[k]) continue;
+    const R wx[2] = {R(1) - fx[k], fx[k]};
+    const R wy[2] = {R(1) - fy[k], fy[k]};
+    const R wz[2] = {R(1) - fz[k], fz[k]};
 #pragma unroll
-    for (int c = 0; c < 4; ++c) scatter(base + c * plane, s, vals[c] * wz);
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+      for (int dl = 0; dl < 2; ++dl)
+#pragma unroll
+        for (int di = 0; di < 2; ++di) {
+          const R wt = wz[dj] * wy[dl] * wx[di];
+          if (fits) {
+            const int t = ((j0[k] + dj - jmin) * nl + (l0[k] + dl - lmin)) * ni + (i0[k] + di - imin);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) atomicAdd(&tile[c * CAP + t], v[k][c] * wt);
+          } else {
+            const int jj = j0[k] + dj;
+            if (jj < 0 || jj >= g.nxi) continue;
+            int ll = l0[k] + dl;
+            ll -= (ll >= g.ny) ? g.ny : 0;
+            int ii = i0[k] + di;
+            ii -= (ii >= g.nx) ? g.nx : 0;
+            const int64_t node = (int64_t)jj * g.nperp + ll * g.nx + ii;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) atomic_add(a.src + c * plane + node, v[k][c] * wt);
+          }
+        }
+  }
+  __syncthreads();
+  if (fits) {
+    const int nplane = nl * ni;
+    for (int t = tid; t < nj * nplane; t += 256) {
+      const int tj = t / nplane;
+      const int r = t - tj * nplane;
+      const int tl = r / ni, ti = r - tl * ni;
+      const int jg = jmin + tj;
+      if (jg < 0 || jg >= g.nxi) continue;
+      int lg = lmin + tl;
+      lg -= (lg >= g.ny) ? g.ny : 0;
+      int ig = imin + ti;
+      ig -= (ig >= g.nx) ? g.nx : 0;
+      const int64_t node = (int64_t)jg * g.nperp + lg * g.nx + ig;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const R val = tile[c * CAP + t];
+        if (val != R(0)) atomic_add(a.src + c * plane + node, val);
+      }
+    }
   }
 }
 
