@@ -25,8 +25,12 @@
  *     device state out of the workspace and allocates no device memory.
  *   - The library owns only the host-side qsa_ctx; qsa_destroy frees it and
  *     never touches the workspace.
- *   - Every call enqueues work on the stream and returns without waiting,
- *     except the calls documented as synchronizing.
+ *   - Every call enqueues work and returns without waiting, except the
+ *     calls documented as synchronizing.  The library runs its kernels on
+ *     a stream of its own, ordered after the work enqueued on the caller's
+ *     stream before the call, and the caller's stream is ordered after the
+ *     call's work; the sweep and the beam step are captured once into HIP
+ *     graphs and replayed (QSA_OPT_GRAPHS).
  *   - A context is used from one host thread at a time.
  *
  * Errors
@@ -169,14 +173,24 @@ enum {
 };
 
 /* Start timing every launch of one kernel class with a pair of HIP events
- * recorded on the context's stream around it (at most 1<<17 launches per
- * window; later launches run untimed).  Instrumentation for measurement; it
- * adds two event records per timed launch. */
+ * recorded on the context's work stream around it (at most 1<<17 launches
+ * per window; later launches run untimed).  Instrumentation for
+ * measurement: while timing is on, the sweep and the beam step are enqueued
+ * launch by launch (no graph replay). */
 qsa_status qsa_timing_begin(qsa_ctx* c, int32_t kernel_class);
 
 /* Stop timing; synchronizing.  *total_ms = summed kernel time of the timed
  * launches, *launches = their count. */
 qsa_status qsa_timing_end(qsa_ctx* c, double* total_ms, int64_t* launches);
+
+/* Options for qsa_set_option. */
+enum {
+  QSA_OPT_GRAPHS = 0     /* 1 (default): replay a captured HIP graph of the sweep
+                            and of the beam step; 0: enqueue every launch   */
+};
+
+/* Set a context option (see QSA_OPT_*). */
+qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value);
 
 /* Free the host context (the workspace is not touched). */
 qsa_status qsa_destroy(qsa_ctx* c);

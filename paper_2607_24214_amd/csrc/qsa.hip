@@ -6,6 +6,7 @@
 // 4 + 4 + 4K + 1 dependent launches per xi slice.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -34,7 +35,9 @@ int ilog2(int v) {
 struct Layout {
   size_t twx, twy, kx2, kdx, ky2, kdy;
   size_t tmpl[4], pl[4], pl2[4];
-  size_t cell_of, count, bsum;
+  size_t cell_of, count, bsum, prow, ppart;
+  size_t rowoff[QSA_MAX_SPECIES], scan64, bpart, strays, ctl;
+  int64_t stray_cap;
   size_t beam[QSA_MAX_SPECIES][7];  // x, y, ux, uy, uz, w (real), xi (double)
   size_t src, fields, dep, rowspec, colout, jring, jz, bring, ode, err, emit;
   size_t total;
@@ -69,6 +72,19 @@ Layout make_layout(const qsa_params& p) {
   L.cell_of = c.take(p.n_plasma * sizeof(int));
   L.count = c.take(nperp * sizeof(int));
   L.bsum = c.take(256 * sizeof(int));
+  L.prow = c.take((p.ny + 1) * sizeof(int));
+  L.ppart = c.take((size_t)p.ny * 4 * 3 * p.nx * rs);
+  const size_t nrows = (size_t)p.nxi * p.ny;
+  int64_t total = 0;
+  for (int s = 0; s < QSA_MAX_SPECIES; ++s) {
+    L.rowoff[s] = c.take((nrows + 2) * sizeof(int64_t));
+    if (s < p.n_species) total += p.beam_capacity[s];
+  }
+  L.scan64 = c.take(((nrows + 2) / 1024 + 8) * 2 * sizeof(int64_t));
+  L.bpart = c.take(nrows * 2 * 4 * 4 * (size_t)p.nx * rs);   // up to 4 node rows per block
+  L.stray_cap = std::min<int64_t>(total, std::max<int64_t>((int64_t)1 << 20, total / 8));
+  L.strays = c.take((size_t)std::max<int64_t>(L.stray_cap, 1) * sizeof(int64_t));
+  L.ctl = c.take(4 * sizeof(int));
   for (int s = 0; s < QSA_MAX_SPECIES; ++s) {
     const size_t cap = (s < p.n_species) ? (size_t)p.beam_capacity[s] : 0;
     for (int k = 0; k < 6; ++k) L.beam[s][k] = c.take(cap * rs);
@@ -116,7 +132,12 @@ struct qsa_ctx {
   qsa_params p;
   Layout L;
   char* ws = nullptr;
-  hipStream_t stream = nullptr;
+  hipStream_t user = nullptr;     // the caller's stream
+  hipStream_t stream = nullptr;   // the library's work stream (ordered after `user` per call)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t gx_step = nullptr, gx_sweep = nullptr;   // captured beam step / sweep
+  bool use_graphs = true;
+  int bnl = 2;   // node rows per beam partial block along y (4 = one margin row each side)
   int64_t beam_n[QSA_MAX_SPECIES] = {0, 0, 0, 0};
   bool plasma_loaded = false;
   bool swept = false;
@@ -148,8 +169,17 @@ struct qsa_ctx {
     (void)hipEventRecord(events[ev_used + 1], stream);
     ev_used += 2;
   }
+  void drop_graphs() {
+    if (gx_step) (void)hipGraphExecDestroy(gx_step);
+    if (gx_sweep) (void)hipGraphExecDestroy(gx_sweep);
+    gx_step = gx_sweep = nullptr;
+  }
   ~qsa_ctx() {
+    drop_graphs();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (stream) (void)hipStreamDestroy(stream);
   }
 };
 
@@ -253,7 +283,7 @@ struct Engine {
     const int ppw = (tpt >= 64) ? 1 : 64 / tpt;
     const int npairs = (g.ny + 1) >> 1;
     const dim3 grid((npairs + ppw - 1) / ppw, nf);
-    const size_t smem = 2 * (size_t)ppw * g.nx * sizeof(C2<R>);
+    const size_t smem = (2 * (size_t)ppw + 1) * g.nx * sizeof(C2<R>);
     c->tstart(QSA_K_ROW_R2C);
     hipLaunchKernelGGL(k_row_r2c<R>, grid, dim3(ppw * tpt), smem, c->stream, g, a,
                        c->at<C2<R>>(c->L.twx), ppw);
@@ -264,7 +294,7 @@ struct Engine {
     const int ppw = (tpt >= 64) ? 1 : 64 / tpt;
     const int npairs = (g.ny + 1) >> 1;
     const dim3 grid((npairs + ppw - 1) / ppw, nf);
-    const size_t smem = 2 * (size_t)ppw * g.nx * sizeof(C2<R>);
+    const size_t smem = (2 * (size_t)ppw + 1) * g.nx * sizeof(C2<R>);
     c->tstart(QSA_K_ROW_C2R);
     hipLaunchKernelGGL(k_row_c2r<R>, grid, dim3(ppw * tpt), smem, c->stream, g, a,
                        c->at<C2<R>>(c->L.twx), ppw);
@@ -275,26 +305,85 @@ struct Engine {
     const int per_col = ColShape<MODE>::G * col_tpt(g.ny);
     const int cpw = (per_col >= 64) ? 1 : 64 / per_col;
     const dim3 grid((g.nxh + cpw - 1) / cpw);
-    const size_t smem = (size_t)cpw * 2 * ColShape<MODE>::G * g.ny * sizeof(C2<R>);
+    const size_t smem = ((size_t)cpw * 2 * ColShape<MODE>::G + 1) * g.ny * sizeof(C2<R>);
     c->tstart(QSA_K_COL);
     hipLaunchKernelGGL((k_col<R, MODE>), grid, dim3(cpw * per_col), smem, c->stream, g, a,
                        c->at<C2<R>>(c->L.twy), cpw);
     c->tstop(QSA_K_COL);
   }
 
+  static BeamDepArgs<R> beam_dep_args(qsa_ctx* c) {
+    const qsa_params& p = c->p;
+    BeamDepArgs<R> a;
+    std::memset(&a, 0, sizeof(a));
+    a.ns = p.n_species;
+    for (int s = 0; s < p.n_species; ++s) {
+      a.x[s] = c->at<R>(c->L.beam[s][0]);
+      a.y[s] = c->at<R>(c->L.beam[s][1]);
+      a.ux[s] = c->at<R>(c->L.beam[s][2]);
+      a.uy[s] = c->at<R>(c->L.beam[s][3]);
+      a.uz[s] = c->at<R>(c->L.beam[s][4]);
+      a.w[s] = c->at<R>(c->L.beam[s][5]);
+      a.xi[s] = c->at<double>(c->L.beam[s][6]);
+      a.rowoff[s] = c->at<int64_t>(c->L.rowoff[s]);
+      a.zq[s] = (R)(p.species[s].Z / (p.dx * p.dy * p.dxi));
+    }
+    a.bpart = c->at<R>(c->L.bpart);
+    a.strays = c->at<int64_t>(c->L.strays);
+    a.stray_cap = c->L.stray_cap;
+    a.ctl = c->at<int>(c->L.ctl);
+    a.inv_dxi = 1.0 / p.dxi;
+    a.nl = c->bnl;
+    return a;
+  }
+
+  // Exclusive scan of n int64 values in place (multi-level, workspace temp).
+  static qsa_status scan64(qsa_ctx* c, int64_t* v, int64_t n, int64_t* tmp) {
+    const int64_t nb = (n + 1023) / 1024;
+    hipLaunchKernelGGL(k_scan64_local, dim3((unsigned)nb), dim3(256), 0, c->stream, v, n, tmp);
+    HIP_OK(hipGetLastError());
+    if (nb > 1) {
+      qsa_status st = scan64(c, tmp, nb, tmp + nb);
+      if (st != QSA_OK) return st;
+      hipLaunchKernelGGL(k_scan64_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, v, n,
+                         (const int64_t*)tmp);
+      HIP_OK(hipGetLastError());
+    }
+    return QSA_OK;
+  }
+
+  // Cell-row offsets of beam species s (after a load).
+  static qsa_status beam_rows(qsa_ctx* c, int s) {
+    const qsa_params& p = c->p;
+    const Geo<R> g = geo(p);
+    const int64_t nrows = (int64_t)p.nxi * p.ny;
+    int64_t* off = c->at<int64_t>(c->L.rowoff[s]);
+    hipLaunchKernelGGL(k_fill<int64_t>, dim3(fill_blocks(nrows + 2)), dim3(256), 0, c->stream, off,
+                       nrows + 2, (int64_t)0);
+    const int64_t n = c->beam_n[s];
+    if (n > 0) {
+      BeamDepArgs<R> a = beam_dep_args(c);
+      hipLaunchKernelGGL(k_beam_rowcount<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
+                         a, s, n, off);
+    }
+    HIP_OK(hipGetLastError());
+    return scan64(c, off, nrows + 2, c->at<int64_t>(c->L.scan64));
+  }
+
+  // Beam sources as block-private partial rows (+ atomics for strays).
   static qsa_status beam_deposit_all(qsa_ctx* c, const Geo<R>& g) {
     const qsa_params& p = c->p;
-    R* src = c->at<R>(c->L.src);
-    qsa_status st = fill(c, src, 4 * (int64_t)p.nxi * g.nperp, R(0));
-    if (st != QSA_OK) return st;
-    for (int s = 0; s < p.n_species; ++s) {
-      if (c->beam_n[s] == 0) continue;
-      BeamArgs<R> a = beam_args(c, g, s);
-      const int64_t blocks = (a.n + 256 * BEAM_PPT - 1) / (256 * BEAM_PPT);
-      c->tstart(QSA_K_BEAM_DEPOSIT);
-      hipLaunchKernelGGL(k_beam_deposit<R>, dim3((unsigned)blocks), dim3(256), 0, c->stream, g, a);
-      c->tstop(QSA_K_BEAM_DEPOSIT);
-    }
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, c->stream, c->at<int>(c->L.ctl), (int64_t)4, 0);
+    BeamDepArgs<R> a = beam_dep_args(c);
+    const int nrows = p.nxi * p.ny;
+    c->tstart(QSA_K_BEAM_DEPOSIT);
+    hipLaunchKernelGGL(k_beam_rows<R>, dim3(nrows), dim3(256), 2 * a.nl * 4 * g.nx * sizeof(R), c->stream, g,
+                       a);
+    c->tstop(QSA_K_BEAM_DEPOSIT);
+    hipLaunchKernelGGL(k_beam_strays<R>, dim3(std::min(nrows, 2048)), dim3(256), 0, c->stream, g, a);
+    const int64_t plane = (int64_t)p.nxi * g.nperp;
+    hipLaunchKernelGGL(k_beam_reduce<R>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, c->stream, g,
+                       (const R*)a.bpart, a.nl, c->at<R>(c->L.src));
     HIP_OK(hipGetLastError());
     return QSA_OK;
   }
@@ -310,7 +399,6 @@ struct Engine {
     a.w = c->at<R>(c->L.beam[s][5]);
     a.xi = c->at<double>(c->L.beam[s][6]);
     a.n = c->beam_n[s];
-    a.src = c->at<R>(c->L.src);
     a.fields = c->at<R>(c->L.fields);
     a.zq = (R)(p.species[s].Z / (p.dx * p.dy * p.dxi));
     a.qmh = (R)((double)p.species[s].Z / p.species[s].M * 0.5 * p.dt);
@@ -318,6 +406,17 @@ struct Engine {
     a.inv_dxi = 1.0 / p.dxi;
     a.xi_max = (double)(p.nxi - 1) * p.dxi;
     return a;
+  }
+
+  template <int MODE>
+  static void plasma_rows(qsa_ctx* c, const Geo<R>& g, const PlasmaArgs<R>& pa, int kclass) {
+    const int per_row = (int)((c->p.n_plasma + g.ny - 1) / g.ny);
+    int nt = (per_row + 63) / 64 * 64;
+    nt = std::max(64, std::min(256, nt));
+    const size_t smem = 4 * PlasmaNC<MODE>::NC * (size_t)g.nx * sizeof(R);
+    c->tstart(kclass);
+    hipLaunchKernelGGL((k_plasma_rows<R, MODE>), dim3(g.ny), dim3(nt), smem, c->stream, g, pa);
+    c->tstop(kclass);
   }
 
   static qsa_status sweep(qsa_ctx* c) {
@@ -328,15 +427,8 @@ struct Engine {
     const size_t spec = (size_t)g.ny * g.nxh;  // complex elements per spectrum
     qsa_status st = beam_deposit_all(c, g);
     if (st != QSA_OK) return st;
-    // plasma enters unperturbed; rings and wake state start at zero
-    {
-      const int np = (int)p.n_plasma;
-      hipLaunchKernelGGL(k_copy4<R>, dim3((np + 255) / 256), dim3(256), 0, c->stream,
-                         c->at<R>(L.tmpl[0]), c->at<R>(L.tmpl[1]), c->at<R>(L.tmpl[2]),
-                         c->at<R>(L.tmpl[3]), c->at<R>(L.pl[0]), c->at<R>(L.pl[1]),
-                         c->at<R>(L.pl[2]), c->at<R>(L.pl[3]), np);
-      HIP_OK(hipGetLastError());
-    }
+    // plasma enters unperturbed (sorted from the template at slice 0);
+    // rings and wake state start at zero
     if ((st = fill(c, c->at<R>(L.jring), (int64_t)4 * spec * 2, R(0))) != QSA_OK) return st;
     if ((st = fill(c, c->at<R>(L.bring), (int64_t)6 * spec * 2, R(0))) != QSA_OK) return st;
     if ((st = fill(c, c->at<R>(L.dep), (int64_t)3 * g.nperp, R(0))) != QSA_OK) return st;
@@ -344,8 +436,9 @@ struct Engine {
     HIP_OK(hipGetLastError());
 
     R* fields = c->at<R>(L.fields);
-    R* src = c->at<R>(L.src);
     R* dep = c->at<R>(L.dep);
+    R* ppart = c->at<R>(L.ppart);
+    const R* src = c->at<R>(L.src);
     C2<R>* rowspec = c->at<C2<R>>(L.rowspec);
     C2<R>* colout = c->at<C2<R>>(L.colout);
     C2<R>* jring = c->at<C2<R>>(L.jring);
@@ -353,10 +446,7 @@ struct Engine {
     C2<R>* jzs = c->at<C2<R>>(L.jz);
 
     PlasmaArgs<R> pa;
-    pa.x = c->at<R>(L.pl[0]);
-    pa.y = c->at<R>(L.pl[1]);
-    pa.ux = c->at<R>(L.pl[2]);
-    pa.uy = c->at<R>(L.pl[3]);
+    std::memset(&pa, 0, sizeof(pa));
     pa.np = (int)p.n_plasma;
     pa.q = (R)(-p.plasma_w / (p.dx * p.dy));
     pa.dep0 = dep;
@@ -364,6 +454,8 @@ struct Engine {
     pa.dep2 = dep + 2 * g.nperp;
     pa.err = c->at<int>(L.err);
     pa.h = (R)p.dxi;
+    pa.prow = c->at<int>(L.prow);
+    pa.ppart = ppart;
     const dim3 pgrid((pa.np + 255) / 256), pblock(256);
 
     ColArgs<R> ca;
@@ -382,11 +474,27 @@ struct Engine {
     auto F = [&](int slot, int j) -> R* { return fields + slot * plane + (int64_t)j * g.nperp; };
     const int fslot[6] = {F_PSI, F_DXPSI, F_DYPSI, F_BX, F_BY, F_BZ};
 
-    int cur = 0;   // which plasma buffer set holds the state
+    auto r2c_args = [&](int nf, int pnc) {
+      RowR2CArgs<R> ra;
+      std::memset(&ra, 0, sizeof(ra));
+      ra.ppart = ppart;
+      ra.pnc = pnc;
+      for (int q = 0; q < 4; ++q) ra.pc[q] = -1;
+      for (int q = 0; q < nf; ++q) {
+        ra.dep[q] = dep + q * g.nperp;
+        ra.pc[q] = q;
+        ra.out[q] = rowspec + q * spec;
+      }
+      return ra;
+    };
+
+    int cur = 0;   // 0: state in pl, 1: state in pl2
     for (int j = 0; j < p.nxi; ++j) {
-      if (j > 0 && j % kSortEvery == 0) {
-        if ((st = sort_plasma(c, g, cur)) != QSA_OK) return st;
-        cur ^= 1;
+      if (j % kSortEvery == 0) {
+        const size_t* A = (j == 0) ? L.tmpl : (cur ? L.pl2 : L.pl);
+        const size_t* B = (j == 0) ? L.pl : (cur ? L.pl : L.pl2);
+        if ((st = sort_plasma(c, g, A, B)) != QSA_OK) return st;
+        cur = (j == 0) ? 0 : cur ^ 1;
         const size_t* P = cur ? L.pl2 : L.pl;
         pa.x = c->at<R>(P[0]);
         pa.y = c->at<R>(P[1]);
@@ -398,18 +506,12 @@ struct Engine {
         pa.F1[q] = (j >= 1) ? F(fslot[q], j - 1) : nullptr;
       }
       pa.psi_m2 = (j >= 2) ? F(F_PSI, j - 2) : nullptr;
-      const int64_t srcj = (int64_t)j * g.nperp;
       // ---- psi stage
-      c->tstart(QSA_K_DEP_S);
-      hipLaunchKernelGGL(k_dep_S<R>, pgrid, pblock, 0, c->stream, g, pa);
-      c->tstop(QSA_K_DEP_S);
+      plasma_rows<PL_DEP_S>(c, g, pa, QSA_K_DEP_S);
       {
-        RowR2CArgs<R> ra;
-        std::memset(&ra, 0, sizeof(ra));
-        ra.dep[0] = dep;
-        ra.add[0] = src + 0 * plane + srcj;
+        RowR2CArgs<R> ra = r2c_args(1, 1);
         ra.addc[0] = R(1);
-        ra.out[0] = rowspec;
+        ra.add[0] = src + (int64_t)j * g.nperp;
         row_r2c(c, g, ra, 1);
       }
       ca.in[0] = rowspec;
@@ -425,17 +527,10 @@ struct Engine {
         row_c2r(c, g, rc, 3);
       }
       // ---- J stage
-      c->tstart(QSA_K_DEP_J);
-      hipLaunchKernelGGL(k_dep_J<R>, pgrid, pblock, 0, c->stream, g, pa);
-      c->tstop(QSA_K_DEP_J);
+      plasma_rows<PL_DEP_J>(c, g, pa, QSA_K_DEP_J);
       {
-        RowR2CArgs<R> ra;
-        std::memset(&ra, 0, sizeof(ra));
-        for (int q = 0; q < 3; ++q) {
-          ra.dep[q] = dep + q * g.nperp;
-          ra.add[q] = src + (1 + q) * plane + srcj;
-          ra.out[q] = rowspec + q * spec;
-        }
+        RowR2CArgs<R> ra = r2c_args(3, 3);
+        for (int q = 0; q < 3; ++q) ra.add[q] = src + (1 + q) * plane + (int64_t)j * g.nperp;
         row_r2c(c, g, ra, 3);
       }
       for (int q = 0; q < 3; ++q) ca.in[q] = rowspec + q * spec;
@@ -464,17 +559,11 @@ struct Engine {
       }
       // ---- B_perp predictor-corrector
       for (int k = 0; k < p.n_corr; ++k) {
-        c->tstart(QSA_K_PUSH_PRED);
-        hipLaunchKernelGGL(k_push_pred<R>, pgrid, pblock, 0, c->stream, g, pa);
-        c->tstop(QSA_K_PUSH_PRED);
+        plasma_rows<PL_PRED>(c, g, pa, QSA_K_PUSH_PRED);
         {
-          RowR2CArgs<R> ra;
-          std::memset(&ra, 0, sizeof(ra));
-          for (int q = 0; q < 2; ++q) {
-            ra.dep[q] = dep + q * g.nperp;
-            ra.add[q] = (j + 1 < p.nxi) ? src + (1 + q) * plane + srcj + g.nperp : nullptr;
-            ra.out[q] = rowspec + q * spec;
-          }
+          RowR2CArgs<R> ra = r2c_args(2, 2);
+          if (j + 1 < p.nxi)
+            for (int q = 0; q < 2; ++q) ra.add[q] = src + (1 + q) * plane + (int64_t)(j + 1) * g.nperp;
           row_r2c(c, g, ra, 2);
         }
         for (int q = 0; q < 2; ++q) ca.in[q] = rowspec + q * spec;
@@ -500,12 +589,11 @@ struct Engine {
     return QSA_OK;
   }
 
-  // Counting sort of the plasma state (buffer set cur -> cur ^ 1) by cell.
-  static qsa_status sort_plasma(qsa_ctx* c, const Geo<R>& g, int cur) {
+  // Counting sort of the plasma state by cell (buffer set A -> B) and the
+  // first particle of every cell row.
+  static qsa_status sort_plasma(qsa_ctx* c, const Geo<R>& g, const size_t* A, const size_t* B) {
     const Layout& L = c->L;
     const int np = (int)c->p.n_plasma;
-    const size_t* A = cur ? L.pl2 : L.pl;
-    const size_t* B = cur ? L.pl : L.pl2;
     int* count = c->at<int>(L.count);
     int* cell_of = c->at<int>(L.cell_of);
     int* bsum = c->at<int>(L.bsum);
@@ -516,6 +604,8 @@ struct Engine {
     const int nb = (g.nperp + 1023) / 1024;
     hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, c->stream, count, g.nperp, bsum);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, c->stream, bsum, nb);
+    hipLaunchKernelGGL(k_row_offsets, dim3((g.ny + 1 + 255) / 256), dim3(256), 0, c->stream, count, bsum,
+                       g.nx, g.ny, np, c->at<int>(L.prow));
     hipLaunchKernelGGL(k_sort_scatter<R>, dim3((np + 255) / 256), dim3(256), 0, c->stream, np, cell_of,
                        count, bsum, c->at<R>(A[0]), c->at<R>(A[1]), c->at<R>(A[2]), c->at<R>(A[3]),
                        c->at<R>(B[0]), c->at<R>(B[1]), c->at<R>(B[2]), c->at<R>(B[3]));
@@ -598,9 +688,9 @@ struct Engine {
     const int64_t nperp = (int64_t)p.nx * p.ny;
     const int64_t plane = (int64_t)p.nxi * nperp;
     const R* F = c->at<R>(c->L.fields);
-    const R* S = c->at<R>(c->L.src);
     double* emit = c->at<double>(c->L.emit);
     for (int j = xi0; j < xi1; ++j) {
+      double* out = on_device ? dst + (int64_t)(j - xi0) * nperp : emit;
       const R* A = nullptr;
       const R* B = nullptr;
       R a = 1, b = 0;
@@ -615,9 +705,8 @@ struct Engine {
         case QSA_BZ: A = F + F_BZ * plane + o; break;
         case QSA_DXPSI: A = F + F_DXPSI * plane + o; break;
         case QSA_DYPSI: A = F + F_DYPSI * plane + o; break;
-        default: A = S + (field - QSA_SRC_S) * plane + o; break;
+        default: A = c->at<R>(c->L.src) + (field - QSA_SRC_S) * plane + o; break;
       }
-      double* out = on_device ? dst + (int64_t)(j - xi0) * nperp : emit;
       hipLaunchKernelGGL(k_emit<R>, dim3(fill_blocks(nperp)), dim3(256), 0, c->stream, A, a, B, b,
                          out, nperp);
       HIP_OK(hipGetLastError());
@@ -629,7 +718,41 @@ struct Engine {
     return QSA_OK;
   }
 
+  // Beam partial blocks carry one margin row on each side (so particles that
+  // drifted to a neighbouring cell row stay on the LDS path) when the tile
+  // 2*4*4*nx values plus the block's stray list fit the device's LDS.
+  static qsa_status choose_beam_tile(qsa_ctx* c) {
+    int dev = 0, optin = 0, plain = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
+    HIP_OK(hipDeviceGetAttribute(&plain, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int limit = std::max(optin, plain);
+    const int need = 2 * 4 * 4 * c->p.nx * (int)sizeof(R);
+    const int stat = 4096;   // block stray list and counters
+    c->bnl = 2;
+    if (c->p.ny > 1 && need + stat <= limit) {
+      if (need + stat > 65536)
+        HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_beam_rows<R>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, need));
+      c->bnl = 4;
+    }
+    // column transforms: (2G + 1) columns of ny complex values per block
+    const int colj = (2 * ColShape<COL_J>::G + 1) * c->p.ny * (int)sizeof(C2<R>);
+    if (colj > limit) return fail(c, QSA_E_INVALID, "ny too large for the device's LDS");
+    if (colj > 65536) {
+      HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_col<R, COL_PSI>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, colj));
+      HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_col<R, COL_J>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, colj));
+      HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_col<R, COL_B>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, colj));
+    }
+    return QSA_OK;
+  }
+
   static qsa_status upload_tables(qsa_ctx* c) {
+    qsa_status st0 = choose_beam_tile(c);
+    if (st0 != QSA_OK) return st0;
     std::vector<char> twx, twy, kx2, kdx, ky2, kdy;
     tables(c->p, twx, twy, kx2, kdx, ky2, kdy);
     HIP_OK(hipMemcpyAsync(c->ws + c->L.twx, twx.data(), twx.size(), hipMemcpyHostToDevice, c->stream));
@@ -639,6 +762,11 @@ struct Engine {
     HIP_OK(hipMemcpyAsync(c->ws + c->L.ky2, ky2.data(), ky2.size(), hipMemcpyHostToDevice, c->stream));
     HIP_OK(hipMemcpyAsync(c->ws + c->L.kdy, kdy.data(), kdy.size(), hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, c->stream, c->at<int>(c->L.err), (int64_t)1, 0);
+    // no beam loaded yet: every species has empty cell rows
+    const int64_t nrows = (int64_t)c->p.nxi * c->p.ny;
+    for (int s = 0; s < QSA_MAX_SPECIES; ++s)
+      hipLaunchKernelGGL(k_fill<int64_t>, dim3(fill_blocks(nrows + 2)), dim3(256), 0, c->stream,
+                         c->at<int64_t>(c->L.rowoff[s]), nrows + 2, (int64_t)0);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(c->stream));
     return QSA_OK;
@@ -662,6 +790,54 @@ qsa_status dispatch(qsa_ctx* c, F64 f64, F32 f32) {
   return c->p.precision == QSA_FP32 ? f32() : f64();
 }
 
+// Order the work stream after what the caller has enqueued so far, and the
+// caller's stream after the work a call enqueued.
+qsa_status enter(qsa_ctx* c) {
+  HIP_OK(hipEventRecord(c->ev_in, c->user));
+  HIP_OK(hipStreamWaitEvent(c->stream, c->ev_in, 0));
+  return QSA_OK;
+}
+qsa_status leave(qsa_ctx* c) {
+  HIP_OK(hipEventRecord(c->ev_out, c->stream));
+  HIP_OK(hipStreamWaitEvent(c->user, c->ev_out, 0));
+  return QSA_OK;
+}
+
+// Capture the launches `body` enqueues into an executable graph (once).  If
+// the runtime refuses the capture, graphs are switched off for the context
+// and the caller enqueues the launches directly (*gx stays null).
+template <typename Fn>
+qsa_status capture(qsa_ctx* c, hipGraphExec_t* gx, Fn body) {
+  if (*gx) return QSA_OK;
+  if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    c->use_graphs = false;
+    return QSA_OK;
+  }
+  const qsa_status st = body();
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  hipError_t ei = hipErrorUnknown;
+  if (st == QSA_OK && e == hipSuccess) ei = hipGraphInstantiate(gx, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (st != QSA_OK) return st;
+  if (e != hipSuccess || ei != hipSuccess) {
+    (void)hipGetLastError();
+    *gx = nullptr;
+    c->use_graphs = false;
+  }
+  return QSA_OK;
+}
+
+qsa_status run_sweep(qsa_ctx* c) {
+  return dispatch(c, [&] { return Engine<double>::sweep(c); }, [&] { return Engine<float>::sweep(c); });
+}
+qsa_status run_step(qsa_ctx* c) {
+  qsa_status st = run_sweep(c);
+  if (st != QSA_OK) return st;
+  return dispatch(c, [&] { return Engine<double>::push(c); }, [&] { return Engine<float>::push(c); });
+}
+
 }  // namespace
 
 extern "C" {
@@ -683,9 +859,16 @@ qsa_status qsa_create(const qsa_params* p, void* dev_ws, size_t ws_bytes, void* 
   c->p = *p;
   c->L = L;
   c->ws = reinterpret_cast<char*>(dev_ws);
-  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  qsa_status st = (p->precision == QSA_FP32) ? Engine<float>::upload_tables(c)
-                                             : Engine<double>::upload_tables(c);
+  c->user = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return QSA_E_DEVICE;
+  }
+  qsa_status st = enter(c);
+  if (st == QSA_OK)
+    st = (p->precision == QSA_FP32) ? Engine<float>::upload_tables(c) : Engine<double>::upload_tables(c);
   if (st != QSA_OK) {
     delete c;
     return st;
@@ -710,6 +893,8 @@ qsa_status qsa_load_plasma(qsa_ctx* c, const double* x, const double* y, const d
   if (!on_device)
     for (int i = 0; i < 4; ++i)
       if (!all_finite(arr[i], n)) return fail(c, QSA_E_NONFINITE, "non-finite plasma value");
+  qsa_status st0 = enter(c);
+  if (st0 != QSA_OK) return st0;
   for (int i = 0; i < 4; ++i) {
     qsa_status st = dispatch(
         c, [&] { return Engine<double>::upload(c, arr[i], c->ws + c->L.tmpl[i], n, on_device, false); },
@@ -717,7 +902,8 @@ qsa_status qsa_load_plasma(qsa_ctx* c, const double* x, const double* y, const d
     if (st != QSA_OK) return st;
   }
   c->plasma_loaded = true;
-  return QSA_OK;
+  c->drop_graphs();
+  return leave(c);
 }
 
 qsa_status qsa_load_beam(qsa_ctx* c, int32_t s, const double* x, const double* y, const double* xi,
@@ -733,6 +919,8 @@ qsa_status qsa_load_beam(qsa_ctx* c, int32_t s, const double* x, const double* y
   if (!on_device)
     for (int i = 0; i < 7; ++i)
       if (!all_finite(arr[i], n)) return fail(c, QSA_E_NONFINITE, "non-finite beam value");
+  qsa_status st0 = enter(c);
+  if (st0 != QSA_OK) return st0;
   for (int i = 0; i < 7; ++i) {
     const bool f64 = (i == 6);
     qsa_status st = dispatch(
@@ -741,7 +929,11 @@ qsa_status qsa_load_beam(qsa_ctx* c, int32_t s, const double* x, const double* y
     if (st != QSA_OK) return st;
   }
   c->beam_n[s] = n;
-  return QSA_OK;
+  c->drop_graphs();
+  qsa_status st = dispatch(c, [&] { return Engine<double>::beam_rows(c, s); },
+                           [&] { return Engine<float>::beam_rows(c, s); });
+  if (st != QSA_OK) return st;
+  return leave(c);
 }
 
 qsa_status qsa_read_beam(qsa_ctx* c, int32_t s, double* x, double* y, double* xi, double* ux,
@@ -756,6 +948,8 @@ qsa_status qsa_read_beam(qsa_ctx* c, int32_t s, double* x, double* y, double* xi
   double* arr[7] = {x, y, ux, uy, uz, w, xi};
   for (int i = 0; i < 7; ++i)
     if (m > 0 && !arr[i]) return fail(c, QSA_E_INVALID, "null destination array");
+  qsa_status st0 = enter(c);
+  if (st0 != QSA_OK) return st0;
   for (int i = 0; i < 7; ++i) {
     const bool f64 = (i == 6);
     qsa_status st = dispatch(
@@ -763,6 +957,7 @@ qsa_status qsa_read_beam(qsa_ctx* c, int32_t s, double* x, double* y, double* xi
         [&] { return Engine<float>::download(c, c->ws + c->L.beam[s][i], arr[i], m, on_device, f64); });
     if (st != QSA_OK) return st;
   }
+  if ((st0 = leave(c)) != QSA_OK) return st0;
   return check_device(c);
 }
 
@@ -770,7 +965,17 @@ qsa_status qsa_slice_sweep(qsa_ctx* c) {
   if (!c) return QSA_E_INVALID;
   if (c->sticky != QSA_OK) return c->sticky;
   if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
-  return dispatch(c, [&] { return Engine<double>::sweep(c); }, [&] { return Engine<float>::sweep(c); });
+  qsa_status st = enter(c);
+  if (st != QSA_OK) return st;
+  const bool graphs = c->use_graphs && c->timing_class < 0;
+  if (graphs && (st = capture(c, &c->gx_sweep, [&] { return run_sweep(c); })) != QSA_OK) return st;
+  if (graphs && c->gx_sweep) {
+    HIP_OK(hipGraphLaunch(c->gx_sweep, c->stream));
+    c->swept = true;
+  } else if ((st = run_sweep(c)) != QSA_OK) {
+    return st;
+  }
+  return leave(c);
 }
 
 qsa_status qsa_beam_step(qsa_ctx* c, int32_t n_steps) {
@@ -778,13 +983,29 @@ qsa_status qsa_beam_step(qsa_ctx* c, int32_t n_steps) {
   if (c->sticky != QSA_OK) return c->sticky;
   if (n_steps < 0) return fail(c, QSA_E_INVALID, "n_steps must be >= 0");
   if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
+  if (n_steps == 0) return QSA_OK;
+  qsa_status st = enter(c);
+  if (st != QSA_OK) return st;
+  const bool graphs = c->use_graphs && c->timing_class < 0;
+  if (graphs && (st = capture(c, &c->gx_step, [&] { return run_step(c); })) != QSA_OK) return st;
   for (int i = 0; i < n_steps; ++i) {
-    qsa_status st = qsa_slice_sweep(c);
-    if (st != QSA_OK) return st;
-    st = dispatch(c, [&] { return Engine<double>::push(c); }, [&] { return Engine<float>::push(c); });
-    if (st != QSA_OK) return st;
+    if (graphs && c->gx_step) {
+      HIP_OK(hipGraphLaunch(c->gx_step, c->stream));
+      c->swept = true;
+    } else if ((st = run_step(c)) != QSA_OK) {
+      return st;
+    }
   }
-  return QSA_OK;
+  return leave(c);
+}
+
+qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value) {
+  if (!c) return QSA_E_INVALID;
+  if (option == QSA_OPT_GRAPHS) {
+    c->use_graphs = value != 0;
+    return QSA_OK;
+  }
+  return fail(c, QSA_E_INVALID, "unknown option");
 }
 
 qsa_status qsa_fields(qsa_ctx* c, int32_t field, int32_t xi0, int32_t xi1, double* dst, size_t count,
@@ -796,9 +1017,12 @@ qsa_status qsa_fields(qsa_ctx* c, int32_t field, int32_t xi0, int32_t xi1, doubl
   if (xi0 < 0 || xi1 > c->p.nxi || xi0 > xi1) return fail(c, QSA_E_INVALID, "slice range out of bounds");
   const size_t need = (size_t)(xi1 - xi0) * c->p.nx * c->p.ny;
   if (!dst || count < need) return fail(c, QSA_E_INVALID, "destination too small");
-  qsa_status st = dispatch(c, [&] { return Engine<double>::fields(c, field, xi0, xi1, dst, dst_on_device); },
+  qsa_status st = enter(c);
+  if (st != QSA_OK) return st;
+  st = dispatch(c, [&] { return Engine<double>::fields(c, field, xi0, xi1, dst, dst_on_device); },
                            [&] { return Engine<float>::fields(c, field, xi0, xi1, dst, dst_on_device); });
   if (st != QSA_OK) return st;
+  if ((st = leave(c)) != QSA_OK) return st;
   return check_device(c);
 }
 
@@ -820,15 +1044,23 @@ qsa_status qsa_timing_end(qsa_ctx* c, double* total_ms, int64_t* launches) {
   if (!c || !total_ms || !launches) return QSA_E_INVALID;
   HIP_OK(hipStreamSynchronize(c->stream));
   double tot = 0.0;
+  bool ok = true;
   for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
     float ms = 0.f;
-    HIP_OK(hipEventElapsedTime(&ms, c->events[i], c->events[i + 1]));
+    if (hipEventElapsedTime(&ms, c->events[i], c->events[i + 1]) != hipSuccess) {
+      ok = false;
+      break;
+    }
     tot += ms;
   }
   *total_ms = tot;
   *launches = (int64_t)(c->ev_used / 2);
   c->timing_class = -1;
   c->ev_used = 0;
+  if (!ok) {
+    (void)hipGetLastError();
+    return fail(c, QSA_E_DEVICE, "hipEventElapsedTime failed");
+  }
   return QSA_OK;
 }
 

@@ -73,14 +73,85 @@ __global__ void k_copy4(const R* __restrict__ a0, const R* __restrict__ a1,
   }
 }
 
+// ------------------------------------------- block-private partial node rows
+// Deposits are owned: the block of plasma cell row r accumulates its
+// particles in LDS and writes node rows r-1 .. r+2 (k = 0..3) with plain
+// stores, ppart[((r*4 + k)*NC + c)*nx + i]; the block of beam cell row
+// (j, l) writes node rows (j + dj, l - m .. l + 1 + m) of the 4 beam sources
+// (layout below).  A grid value is the sum of the partial rows that cover
+// it: the plasma's is formed by the row transform that consumes it, the
+// beam's by one reduction pass before the sweep.  Particles that drifted
+// further than the margin go through atomics instead (the plasma into the
+// dep grids, the beam into the owning partial after all blocks have written).
+
+template <typename R>
+__device__ __forceinline__ R plasma_partial(const R* __restrict__ pp, int nc, int ny, int nx, int c,
+                                           int L, int i) {
+  R s = R(0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int r = L + 1 - k;
+    if (ny == 1) {
+      r = 0;
+    } else {
+      r += (r < 0) ? ny : 0;
+      r -= (r >= ny) ? ny : 0;
+    }
+    s += pp[((size_t)(r * 4 + k) * nc + c) * nx + i];
+  }
+  return s;
+}
+
+// Beam partial rows: block (j, l) holds node rows (j + dj, l - m + k), dj in
+// {0, 1}, k in [0, NL) with m = NL/2 - 1 margin rows on each side, for the
+// 4 sources: bpart[((((j*ny + l)*2 + dj)*NL + k)*4 + q)*nx + i].
+template <typename R>
+__device__ __forceinline__ R beam_partial(const R* __restrict__ bp, int nl, int ny, int nx, int q, int J,
+                                         int L, int i) {
+  const int m = nl / 2 - 1;
+  R s = R(0);
+#pragma unroll
+  for (int dj = 0; dj < 2; ++dj) {
+    const int jj = J - dj;
+    if (jj < 0) continue;
+    for (int k = 0; k < nl; ++k) {
+      int ll = L + m - k;
+      if (ny == 1) {
+        ll = 0;
+      } else {
+        ll += (ll < 0) ? ny : 0;
+        ll -= (ll >= ny) ? ny : 0;
+      }
+      s += bp[(((((int64_t)jj * ny + ll) * 2 + dj) * nl + k) * 4 + q) * nx + i];
+    }
+  }
+  return s;
+}
+
 // ------------------------------------------------------------ row transforms
 template <typename R>
 struct RowR2CArgs {
-  R* dep[4];          // deposit grid [nperp]: read, then cleared for the next deposit
-  const R* add[4];    // grid added on load (beam source slice) or null
-  R addc[4];          // constant added on load (ion background)
+  R* dep[4];          // stray grid [nperp] or null: read, then cleared
+  const R* ppart;     // plasma partial rows or null
+  int pc[4];          // plasma component of each field (-1: none)
+  int pnc;            // components in the plasma partial layout
+  const R* add[4];    // dense beam source row block of each field, or null
+  R addc[4];          // constant (ion background)
   C2<R>* out[4];      // half spectra [ny][nxh]
 };
+
+template <typename R>
+__device__ __forceinline__ R row_value(const Geo<R>& g, const RowR2CArgs<R>& a, int f, int r, int i) {
+  R v = a.addc[f];
+  const int o = r * g.nx + i;
+  if (a.dep[f]) {
+    v += a.dep[f][o];
+    a.dep[f][o] = R(0);
+  }
+  if (a.pc[f] >= 0) v += plasma_partial(a.ppart, a.pnc, g.ny, g.nx, a.pc[f], r, i);
+  if (a.add[f]) v += a.add[f][o];
+  return v;
+}
 
 // Real rows -> half spectra along x.  Rows 2p and 2p+1 are packed as the
 // real and imaginary parts of one complex transform and separated after it.
@@ -97,35 +168,17 @@ __global__ void __launch_bounds__(256) k_row_r2c(Geo<R> g, RowR2CArgs<R> a,
   const bool v0 = pair < npairs;
   const int r0 = 2 * pair, r1 = 2 * pair + 1;
   const bool v1 = v0 && r1 < g.ny;
-  C2<R>* A = sm + (size_t)slot * 2 * g.nx;
+  C2<R>* tw = sm;                       // twiddles, staged once per block
+  for (int i = threadIdx.x; i < g.nx; i += blockDim.x) tw[i] = twx[i];
+  C2<R>* A = sm + g.nx + (size_t)slot * 2 * g.nx;
   C2<R>* B = A + g.nx;
-  R* dep = a.dep[f];
-  const R* add = a.add[f];
-  const R c = a.addc[f];
   for (int i = t; i < g.nx; i += tpt) {
-    R va = 0, vb = 0;
-    if (v0) {
-      const int o = r0 * g.nx + i;
-      va = c;
-      if (dep) {
-        va += dep[o];
-        dep[o] = 0;
-      }
-      if (add) va += add[o];
-    }
-    if (v1) {
-      const int o = r1 * g.nx + i;
-      vb = c;
-      if (dep) {
-        vb += dep[o];
-        dep[o] = 0;
-      }
-      if (add) vb += add[o];
-    }
+    const R va = v0 ? row_value(g, a, f, r0, i) : R(0);
+    const R vb = v1 ? row_value(g, a, f, r1, i) : R(0);
     A[i] = C2<R>{va, vb};
   }
   __syncthreads();
-  C2<R>* res = fft_lds<R, false>(A, B, g.nx, g.lgx, t, tpt, twx);
+  C2<R>* res = fft_lds<R, false>(A, B, g.nx, g.lgx, t, tpt, tw);
   if (v0) {
     C2<R>* out = a.out[f];
     for (int k = t; k < g.nxh; k += tpt) {
@@ -159,7 +212,9 @@ __global__ void __launch_bounds__(256) k_row_c2r(Geo<R> g, RowC2RArgs<R> a,
   const bool v0 = pair < npairs;
   const int r0 = 2 * pair, r1 = 2 * pair + 1;
   const bool v1 = v0 && r1 < g.ny;
-  C2<R>* A = sm + (size_t)slot * 2 * g.nx;
+  C2<R>* tw = sm;                       // twiddles, staged once per block
+  for (int i = threadIdx.x; i < g.nx; i += blockDim.x) tw[i] = twx[i];
+  C2<R>* A = sm + g.nx + (size_t)slot * 2 * g.nx;
   C2<R>* B = A + g.nx;
   const C2<R>* in = a.in[f];
   const int half = g.nx >> 1;
@@ -182,7 +237,7 @@ __global__ void __launch_bounds__(256) k_row_c2r(Geo<R> g, RowC2RArgs<R> a,
     A[i] = C2<R>{av.x - bv.y, av.y + bv.x};
   }
   __syncthreads();
-  C2<R>* res = fft_lds<R, true>(A, B, g.nx, g.lgx, t, tpt, twx);
+  C2<R>* res = fft_lds<R, true>(A, B, g.nx, g.lgx, t, tpt, tw);
   if (v0) {
     R* out = a.out[f];
     for (int i = t; i < g.nx; i += tpt) {
@@ -247,13 +302,15 @@ __global__ void __launch_bounds__(256) k_col(Geo<R> g, ColArgs<R> a,
   const int grp = r / tpt, t = r - grp * tpt;
   const int kx = blockIdx.x * cpw + c;
   const bool valid = kx < g.nxh;
-  C2<R>* D = sm + (size_t)c * 2 * G * ny;   // G data columns
+  C2<R>* tw = sm;                          // twiddles, staged once per block
+  for (int i = threadIdx.x; i < ny; i += blockDim.x) tw[i] = twy[i];
+  C2<R>* D = sm + ny + (size_t)c * 2 * G * ny;   // G data columns
   C2<R>* Sx = D + G * ny;                   // G scratch columns
   C2<R>* mine = D + grp * ny;
   for (int y = t; y < ny; y += tpt)
     mine[y] = (valid && grp < S::NIN) ? a.in[grp][y * g.nxh + kx] : C2<R>{0, 0};
   __syncthreads();
-  fft_lds_inplace<R, false>(mine, Sx + grp * ny, ny, g.lgy, t, tpt, twy);
+  fft_lds_inplace<R, false>(mine, Sx + grp * ny, ny, g.lgy, t, tpt, tw);
 
   for (int y = r; y < ny; y += per_col) {
     C2<R> o[S::NOUT];
@@ -324,7 +381,7 @@ __global__ void __launch_bounds__(256) k_col(Geo<R> g, ColArgs<R> a,
     for (int q = 0; q < S::NOUT; ++q) D[q * ny + y] = o[q];
   }
   __syncthreads();
-  fft_lds_inplace<R, true>(mine, Sx + grp * ny, ny, g.lgy, t, tpt, twy);
+  fft_lds_inplace<R, true>(mine, Sx + grp * ny, ny, g.lgy, t, tpt, tw);
   if (valid && grp < S::NOUT)
     for (int y = t; y < ny; y += tpt) a.out[grp][y * g.nxh + kx] = mine[y];
 }
@@ -346,51 +403,13 @@ struct PlasmaArgs {
   const R* psi_m2;    // psi at j-2 (null when j < 2)
   int* err;
   R h;
+  const int* prow;    // [ny + 1] first particle of each cell row (state sorted by cell)
+  R* ppart;           // partial node rows [ny][4][NC][nx]
 };
 
 // Particle p of block b: the blocks of one XCD take consecutive chunks.
 __device__ __forceinline__ int plasma_index() {
   return xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_dep_S(Geo<R> g, PlasmaArgs<R> a) {
-  __shared__ R tile[TileCap<R, 1>::NODES];
-  __shared__ int bb[4];
-  const int p = plasma_index();
-  const bool live = p < a.np;
-  int i0 = 0, l0 = 0;
-  R fx = 0, fy = 0;
-  if (live) cell2(g, a.x[p], a.y[p], i0, l0, fx, fy);
-  const R v[1] = {a.q};
-  R* const dst[1] = {a.dep0};
-  block_deposit<R, 1>(g, live, i0, l0, fx, fy, v, dst, tile, bb);
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_dep_J(Geo<R> g, PlasmaArgs<R> a) {
-  __shared__ R tile[3 * TileCap<R, 3>::NODES];
-  __shared__ int bb[4];
-  const int p = plasma_index();
-  const bool live = p < a.np;
-  int i0 = 0, l0 = 0;
-  R fx = 0, fy = 0;
-  R v[3] = {0, 0, 0};
-  if (live) {
-    const R ux = a.ux[p], uy = a.uy[p];
-    cell2(g, a.x[p], a.y[p], i0, l0, fx, fy);
-    const Stencil<R> s = stencil2(g, a.x[p], a.y[p]);
-    const R G = R(1) + gather(a.F0[0], s);
-    if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
-    const R gam = (R(1) + ux * ux + uy * uy + G * G) / (R(2) * G);
-    const R uz = gam - G;
-    const R qg = a.q / G;
-    v[0] = qg * ux;
-    v[1] = qg * uy;
-    v[2] = qg * uz;
-  }
-  R* const dst[3] = {a.dep0, a.dep1, a.dep2};
-  block_deposit<R, 3>(g, live, i0, l0, fx, fy, v, dst, tile, bb);
 }
 
 // d/dxi of (x, y, u_x, u_y) from the six gathered fields
@@ -439,33 +458,149 @@ __device__ __forceinline__ void rk2_push(const Geo<R>& g, const PlasmaArgs<R>& a
   uyn = uy + hh * d2[3];
 }
 
-// Predictor: push a copy of Y^j to j+1 and deposit the predicted J_perp at
-// j+1 with 1 + psi~ from psi~^{j+1} = 3 psi^j - 3 psi^{j-1} + psi^{j-2}.
-template <typename R>
-__global__ void __launch_bounds__(256) k_push_pred(Geo<R> g, PlasmaArgs<R> a) {
-  __shared__ R tile[2 * TileCap<R, 2>::NODES];
-  __shared__ int bb[4];
-  const int p = plasma_index();
-  const bool live = p < a.np;
-  int i0 = 0, l0 = 0;
-  R fx = 0, fy = 0;
-  R v[2] = {0, 0};
-  if (live) {
-    R xn, yn, uxn, uyn;
-    rk2_push(g, a, a.x[p], a.y[p], a.ux[p], a.uy[p], xn, yn, uxn, uyn);
-    cell2(g, xn, yn, i0, l0, fx, fy);
-    const Stencil<R> s = stencil2(g, xn, yn);
-    R pt = R(3) * gather(a.F0[0], s);
-    if (a.F1[0]) pt -= R(3) * gather(a.F1[0], s);
-    if (a.psi_m2) pt += gather(a.psi_m2, s);
-    const R G = R(1) + pt;
-    if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
-    const R qg = a.q / G;
-    v[0] = qg * uxn;
-    v[1] = qg * uyn;
+enum { PL_DEP_S = 0, PL_DEP_J = 1, PL_PRED = 2 };
+
+template <int MODE>
+struct PlasmaNC {
+  static constexpr int NC = (MODE == PL_DEP_S) ? 1 : (MODE == PL_DEP_J ? 3 : 2);
+};
+
+// Add the four-node contribution acc (nodes 00, 10, 01, 11) of cell
+// (i0, l0) to the tile of block row r (node rows r-1 .. r+2), or, when the
+// cell is more than one row away, to the stray grids with atomics.
+template <typename R, int NC>
+__device__ __forceinline__ void row_tile_add(const Geo<R>& g, R* tile, int r, int i0, int l0,
+                                             const R (&acc)[4][NC], R* const* stray) {
+  int d = l0 - r;
+  if (g.ny == 1) {
+    d = 0;
+  } else {
+    if (d > (g.ny >> 1)) d -= g.ny;
+    if (d < -(g.ny >> 1)) d += g.ny;
   }
-  R* const dst[2] = {a.dep0, a.dep1};
-  block_deposit<R, 2>(g, live, i0, l0, fx, fy, v, dst, tile, bb);
+  const int i1 = (i0 + 1 == g.nx) ? 0 : i0 + 1;
+  if (d >= -1 && d <= 1) {
+    const int k0 = d + 1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      R* t0 = tile + (k0 * NC + c) * g.nx;
+      R* t1 = tile + ((k0 + 1) * NC + c) * g.nx;
+      atomicAdd(t0 + i0, acc[0][c]);
+      atomicAdd(t0 + i1, acc[1][c]);
+      atomicAdd(t1 + i0, acc[2][c]);
+      atomicAdd(t1 + i1, acc[3][c]);
+    }
+  } else {
+    const int l1 = (l0 + 1 == g.ny) ? 0 : l0 + 1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      atomic_add(stray[c] + l0 * g.nx + i0, acc[0][c]);
+      atomic_add(stray[c] + l0 * g.nx + i1, acc[1][c]);
+      atomic_add(stray[c] + l1 * g.nx + i0, acc[2][c]);
+      atomic_add(stray[c] + l1 * g.nx + i1, acc[3][c]);
+    }
+  }
+}
+
+// Plasma deposits owned by cell rows: block r takes the particles of cell
+// row r (state sorted by cell), each thread a contiguous run of them, and
+// adds them to its LDS tile of node rows r-1 .. r+2 with LDS atomics; the
+// tile is written out as partial rows.
+//   PL_DEP_S: rho - J_z at slice j (positions only)
+//   PL_DEP_J: J_x, J_y, J_z at slice j (gathers psi^j for 1 + psi)
+//   PL_PRED : predictor push to j+1 and J~_perp at j+1 with 1 + psi~^{j+1},
+//             psi~^{j+1} = 3 psi^j - 3 psi^{j-1} + psi^{j-2}
+template <typename R, int MODE>
+__global__ void __launch_bounds__(512) k_plasma_rows(Geo<R> g, PlasmaArgs<R> a) {
+  constexpr int NC = PlasmaNC<MODE>::NC;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* tile = reinterpret_cast<R*>(smem_raw);
+  const int r = blockIdx.x;
+  const int nt = blockDim.x, tid = threadIdx.x;
+  const int tn = 4 * NC * g.nx;
+  for (int t = tid; t < tn; t += nt) tile[t] = R(0);
+  __syncthreads();
+  const int p0 = a.prow[r], p1 = a.prow[r + 1];
+  const int run = (p1 - p0 + nt - 1) / nt;
+  const int q0 = p0 + tid * run;
+  const int q1 = min(q0 + run, p1);
+  R* stray[NC];
+  stray[0] = a.dep0;
+  if constexpr (NC > 1) stray[1] = a.dep1;
+  if constexpr (NC > 2) stray[2] = a.dep2;
+  // consecutive particles of one cell (the state is sorted by cell) add up
+  // in registers; the sum goes to the tile when the cell changes
+  R acc[4][NC];
+  int ci = -1, cl = -1;
+  for (int p = q0; p < q1; ++p) {
+    R px, py;
+    R v[NC];
+    if constexpr (MODE == PL_DEP_S) {
+      px = a.x[p];
+      py = a.y[p];
+      v[0] = a.q;
+    } else if constexpr (MODE == PL_DEP_J) {
+      px = a.x[p];
+      py = a.y[p];
+      const R ux = a.ux[p], uy = a.uy[p];
+      const Stencil<R> s = stencil2(g, px, py);
+      const R G = R(1) + gather(a.F0[0], s);
+      if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
+      const R gam = (R(1) + ux * ux + uy * uy + G * G) / (R(2) * G);
+      const R qg = a.q / G;
+      v[0] = qg * ux;
+      v[1] = qg * uy;
+      v[(NC > 2) ? 2 : 0] = qg * (gam - G);
+    } else {
+      R uxn, uyn;
+      rk2_push(g, a, a.x[p], a.y[p], a.ux[p], a.uy[p], px, py, uxn, uyn);
+      const Stencil<R> s = stencil2(g, px, py);
+      R pt = R(3) * gather(a.F0[0], s);
+      if (a.F1[0]) pt -= R(3) * gather(a.F1[0], s);
+      if (a.psi_m2) pt += gather(a.psi_m2, s);
+      const R G = R(1) + pt;
+      if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
+      const R qg = a.q / G;
+      v[0] = qg * uxn;
+      v[(NC > 1) ? 1 : 0] = qg * uyn;
+    }
+    int i0, l0;
+    R fx, fy;
+    cell2(g, px, py, i0, l0, fx, fy);
+    if (i0 != ci || l0 != cl) {
+      if (ci >= 0) row_tile_add<R, NC>(g, tile, r, ci, cl, acc, stray);
+      ci = i0;
+      cl = l0;
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[n][c] = R(0);
+    }
+    const R ax = R(1) - fx, ay = R(1) - fy;
+    const R w[4] = {ax * ay, fx * ay, ax * fy, fx * fy};
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[n][c] += v[c] * w[n];
+  }
+  if (ci >= 0) row_tile_add<R, NC>(g, tile, r, ci, cl, acc, stray);
+  __syncthreads();
+  R* out = a.ppart + (size_t)r * tn;
+  for (int t = tid; t < tn; t += nt) out[t] = tile[t];
+}
+
+// First particle of each cell row from the scanned cell counts (cell c
+// starts at count[c] + bsum[c / 1024]); prow[ny] = np.
+__global__ void k_row_offsets(const int* __restrict__ count, const int* __restrict__ bsum, int nx,
+                              int ny, int np, int* __restrict__ prow) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > ny) return;
+  if (r == ny) {
+    prow[r] = np;
+  } else {
+    const int c = r * nx;
+    prow[r] = count[c] + bsum[c >> 10];
+  }
 }
 
 // Final advance: Y^{j+1} with the converged fields, positions wrapped.
@@ -570,7 +705,6 @@ struct BeamArgs {
   R* uz;
   R* w;
   int64_t n;
-  R* src;             // [4][nxi][nperp]: rho - J_z, J_x, J_y, J_z
   const R* fields;    // [7][nxi][nperp]
   R zq;               // Z/(dx dy dxi)
   R qmh;              // (Z/M) dt/2
@@ -579,123 +713,257 @@ struct BeamArgs {
   double xi_max;      // (nxi - 1) dxi: particles at or beyond it leave the box
 };
 
-// 3D linear-shape deposit of the beam sources, staged through an LDS tile
-// over the bounding box of the block's cells (same scheme as block_deposit,
-// in (xi, y, x)); each thread brings BEAM_PPT particles.
-#define BEAM_PPT 2
+// ------------------------------------------------------- beam source deposit
 template <typename R>
-__global__ void __launch_bounds__(256) k_beam_deposit(Geo<R> g, BeamArgs<R> a) {
-  constexpr int CAP = TileCap<R, 4>::NODES;
-  __shared__ R tile[4 * CAP];
-  __shared__ int bb[6];
-  const int tid = threadIdx.x;
-  const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (256 * BEAM_PPT);
-  bool live[BEAM_PPT];
-  int j0[BEAM_PPT], l0[BEAM_PPT], i0[BEAM_PPT];
-  R fz[BEAM_PPT], fx[BEAM_PPT], fy[BEAM_PPT], v[BEAM_PPT][4];
-  if (tid == 0) {
-    bb[0] = bb[1] = bb[2] = 0x7fffffff;
-    bb[3] = bb[4] = bb[5] = -0x7fffffff;
-  }
-  for (int t = tid; t < 4 * CAP; t += 256) tile[t] = R(0);
-#pragma unroll
-  for (int k = 0; k < BEAM_PPT; ++k) {
-    const int64_t p = base + k * 256 + tid;
-    live[k] = false;
-    j0[k] = l0[k] = i0[k] = 0;
-    fz[k] = fx[k] = fy[k] = R(0);
-    v[k][0] = v[k][1] = v[k][2] = v[k][3] = R(0);
-    if (p < a.n) {
-      const R w = a.w[p];
-      const double gz = a.xi[p] * a.inv_dxi;
-      if (w != R(0) && gz > -1.0 && gz < (double)g.nxi) {
-        live[k] = true;
-        const double fz0 = floor(gz);
-        j0[k] = (int)fz0;
-        fz[k] = (R)(gz - fz0);
-        cell2(g, a.x[p], a.y[p], i0[k], l0[k], fx[k], fy[k]);
-        const R ux = a.ux[p], uy = a.uy[p], uz = a.uz[p];
-        const R up2 = ux * ux + uy * uy;
-        const R gam = sqrt(R(1) + up2 + uz * uz);
-        const R q = a.zq * w;
-        v[k][0] = q * ((R(1) + up2) / (gam * (gam + uz)));   // 1 - v_z without cancellation
-        v[k][1] = q * ux / gam;
-        v[k][2] = q * uy / gam;
-        v[k][3] = q * uz / gam;
+struct BeamDepArgs {
+  int ns;                     // species
+  const R* x[4];
+  const R* y[4];
+  const double* xi[4];
+  const R* ux[4];
+  const R* uy[4];
+  const R* uz[4];
+  const R* w[4];
+  const int64_t* rowoff[4];   // [nxi*ny + 2]: particles of cell row b start at rowoff[b]
+  R zq[4];                    // Z/(dx dy dxi)
+  R* bpart;                   // partial node rows
+  int64_t* strays;            // indices (species << 56 | particle) of out-of-row particles
+  int64_t stray_cap;
+  int* ctl;                   // [0..1] stray count (64-bit), [2] overflow flag
+  double inv_dxi;
+  int nl;                     // node rows per partial block along y (2 or 4)
+};
+
+// Beam particle p of species s: slice cell j, row/column cell, offsets and
+// the four sources (rho - J_z, J_x, J_y, J_z) times Z w/dV.  False when the
+// particle has no node inside the grid or is inert (w = 0).
+template <typename R>
+__device__ __forceinline__ bool beam_particle(const Geo<R>& g, const BeamDepArgs<R>& a, int s, int64_t p,
+                                              int& j, int& l, int& i, R& fz, R& fy, R& fx, R (&v)[4]) {
+  const R w = a.w[s][p];
+  const double gz = a.xi[s][p] * a.inv_dxi;
+  if (w == R(0) || !(gz > -1.0 && gz < (double)g.nxi)) return false;
+  const double fz0 = floor(gz);
+  j = (int)fz0;
+  fz = (R)(gz - fz0);
+  cell2(g, a.x[s][p], a.y[s][p], i, l, fx, fy);
+  const R ux = a.ux[s][p], uy = a.uy[s][p], uz = a.uz[s][p];
+  const R up2 = ux * ux + uy * uy;
+  const R gam = sqrt(R(1) + up2 + uz * uz);
+  const R q = a.zq[s] * w;
+  v[0] = q * ((R(1) + up2) / (gam * (gam + uz)));   // 1 - v_z without cancellation
+  v[1] = q * ux / gam;
+  v[2] = q * uy / gam;
+  v[3] = q * uz / gam;
+  return true;
+}
+
+// Beam deposit owned by cell rows (j, l) = (b / ny, b % ny): the block takes
+// the particles of its row of every species (consecutive threads take
+// consecutive particles) and adds those whose cell is (j, l +- m) to an LDS
+// tile of node rows (j..j+1, l-m .. l+1+m) with LDS atomics; the tile is
+// written out as partial rows.  The others are listed for k_beam_strays,
+// through a block-local list and one global reservation per block.
+template <typename R>
+__global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* tile = reinterpret_cast<R*>(smem_raw);
+  constexpr int SB = 256;
+  __shared__ int64_t sbuf[SB];
+  __shared__ int scount;
+  __shared__ unsigned long long sbase;
+  const int b = blockIdx.x;
+  const int jb = b / g.ny, lb = b - jb * g.ny;
+  const int nl = a.nl, m = nl / 2 - 1;
+  const int nt = blockDim.x, tid = threadIdx.x;
+  const int tn = 2 * nl * 4 * g.nx;
+  for (int t = tid; t < tn; t += nt) tile[t] = R(0);
+  if (tid == 0) scount = 0;
+  __syncthreads();
+  for (int s = 0; s < a.ns; ++s) {
+    const int64_t p1 = a.rowoff[s][b + 1];
+    for (int64_t p = a.rowoff[s][b] + tid; p < p1; p += nt) {
+      int j, l, i;
+      R fz, fy, fx, v[4];
+      if (!beam_particle(g, a, s, p, j, l, i, fz, fy, fx, v)) continue;
+      int d = l - lb;
+      if (g.ny == 1) {
+        d = 0;
+      } else {
+        if (d > (g.ny >> 1)) d -= g.ny;
+        if (d < -(g.ny >> 1)) d += g.ny;
       }
-    }
-  }
-  __syncthreads();
+      if (j != jb || d < -m || d > m) {
+        const int k = atomicAdd(&scount, 1);
+        if (k < SB) {
+          sbuf[k] = ((int64_t)s << 56) | p;
+        } else {
+          const int64_t e = atomicAdd((unsigned long long*)a.ctl, 1ull);
+          if (e < a.stray_cap) a.strays[e] = ((int64_t)s << 56) | p;
+          else atomicOr(a.ctl + 2, 1);
+        }
+        continue;
+      }
+      const int i1 = (i + 1 == g.nx) ? 0 : i + 1;
+      const R wz[2] = {R(1) - fz, fz}, wy[2] = {R(1) - fy, fy}, wx[2] = {R(1) - fx, fx};
 #pragma unroll
-  for (int k = 0; k < BEAM_PPT; ++k)
-    if (live[k]) {
-      atomicMin(&bb[0], j0[k]);
-      atomicMin(&bb[1], l0[k]);
-      atomicMin(&bb[2], i0[k]);
-      atomicMax(&bb[3], j0[k]);
-      atomicMax(&bb[4], l0[k]);
-      atomicMax(&bb[5], i0[k]);
-    }
-  __syncthreads();
-  const bool any = bb[3] >= bb[0];
-  const int jmin = bb[0], lmin = bb[1], imin = bb[2];
-  const int nj = any ? bb[3] - jmin + 2 : 0;
-  const int nl = any ? bb[4] - lmin + 2 : 0;
-  const int ni = any ? bb[5] - imin + 2 : 0;
-  const bool fits = any && (int64_t)nj * nl * ni <= CAP;
-  const int64_t plane = (int64_t)g.nxi * g.nperp;
+      for (int dj = 0; dj < 2; ++dj)
 #pragma unroll
-  for (int k = 0; k < BEAM_PPT; ++k) {
-    if (!live[k]) continue;
-    const R wx[2] = {R(1) - fx[k], fx[k]};
-    const R wy[2] = {R(1) - fy[k], fy[k]};
-    const R wz[2] = {R(1) - fz[k], fz[k]};
+        for (int dl = 0; dl < 2; ++dl) {
+          const int k = d + m + dl;
+          const R wc = wz[dj] * wy[dl];
+          const R w0 = wc * wx[0], w1 = wc * wx[1];
+          R* t = tile + ((dj * nl + k) * 4) * g.nx;
 #pragma unroll
-    for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-      for (int dl = 0; dl < 2; ++dl)
-#pragma unroll
-        for (int di = 0; di < 2; ++di) {
-          const R wt = wz[dj] * wy[dl] * wx[di];
-          if (fits) {
-            const int t = ((j0[k] + dj - jmin) * nl + (l0[k] + dl - lmin)) * ni + (i0[k] + di - imin);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) atomicAdd(&tile[c * CAP + t], v[k][c] * wt);
-          } else {
-            const int jj = j0[k] + dj;
-            if (jj < 0 || jj >= g.nxi) continue;
-            int ll = l0[k] + dl;
-            ll -= (ll >= g.ny) ? g.ny : 0;
-            int ii = i0[k] + di;
-            ii -= (ii >= g.nx) ? g.nx : 0;
-            const int64_t node = (int64_t)jj * g.nperp + ll * g.nx + ii;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) atomic_add(a.src + c * plane + node, v[k][c] * wt);
+          for (int q = 0; q < 4; ++q) {
+            atomicAdd(t + q * g.nx + i, v[q] * w0);
+            atomicAdd(t + q * g.nx + i1, v[q] * w1);
           }
         }
+    }
   }
   __syncthreads();
-  if (fits) {
-    const int nplane = nl * ni;
-    for (int t = tid; t < nj * nplane; t += 256) {
-      const int tj = t / nplane;
-      const int r = t - tj * nplane;
-      const int tl = r / ni, ti = r - tl * ni;
-      const int jg = jmin + tj;
-      if (jg < 0 || jg >= g.nxi) continue;
-      int lg = lmin + tl;
-      lg -= (lg >= g.ny) ? g.ny : 0;
-      int ig = imin + ti;
-      ig -= (ig >= g.nx) ? g.nx : 0;
-      const int64_t node = (int64_t)jg * g.nperp + lg * g.nx + ig;
+  const int nloc = scount < SB ? scount : SB;
+  if (tid == 0 && nloc > 0) sbase = atomicAdd((unsigned long long*)a.ctl, (unsigned long long)nloc);
+  R* out = a.bpart + (int64_t)b * tn;
+  for (int t = tid; t < tn; t += nt) out[t] = tile[t];
+  __syncthreads();
+  if (nloc > 0)
+    for (int t = tid; t < nloc; t += nt) {
+      const int64_t e = (int64_t)sbase + t;
+      if (e < a.stray_cap) a.strays[e] = sbuf[t];
+      else atomicOr(a.ctl + 2, 1);
+    }
+}
+
+// Out-of-row beam particles, after every block has written its partial
+// rows: atomics into corner 0 of the row that owns each node.  If the list
+// overflowed, every block rescans its rows instead.
+template <typename R>
+__device__ __forceinline__ void beam_stray_add(const Geo<R>& g, const BeamDepArgs<R>& a, int s, int64_t p) {
+  int j, l, i;
+  R fz, fy, fx, v[4];
+  if (!beam_particle(g, a, s, p, j, l, i, fz, fy, fx, v)) return;
+  const R wz[2] = {R(1) - fz, fz}, wy[2] = {R(1) - fy, fy}, wx[2] = {R(1) - fx, fx};
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const R val = tile[c * CAP + t];
-        if (val != R(0)) atomic_add(a.src + c * plane + node, val);
+  for (int dj = 0; dj < 2; ++dj) {
+    const int jj = j + dj;
+    if (jj < 0 || jj >= g.nxi) continue;
+#pragma unroll
+    for (int dl = 0; dl < 2; ++dl) {
+      const int ll = (l + dl == g.ny) ? 0 : l + dl;
+#pragma unroll
+      for (int di = 0; di < 2; ++di) {
+        const int ii = (i + di == g.nx) ? 0 : i + di;
+        const R wt = wz[dj] * wy[dl] * wx[di];
+        const int m = a.nl / 2 - 1;
+        R* base = a.bpart + (((((int64_t)jj * g.ny + ll) * 2) * a.nl + m) * 4) * g.nx + ii;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) atomic_add(base + q * g.nx, v[q] * wt);
       }
     }
   }
 }
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_beam_strays(Geo<R> g, BeamDepArgs<R> a) {
+  const int64_t count = *(const unsigned long long*)a.ctl;
+  const bool overflow = a.ctl[2] != 0;
+  if (!overflow) {
+    const int64_t n = count < a.stray_cap ? count : a.stray_cap;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t e = a.strays[k];
+      beam_stray_add(g, a, (int)(e >> 56), e & (((int64_t)1 << 56) - 1));
+    }
+    return;
+  }
+  const int nrows = g.nxi * g.ny;
+  for (int b = blockIdx.x; b < nrows; b += gridDim.x) {
+    const int jb = b / g.ny, lb = b - jb * g.ny;
+    for (int s = 0; s < a.ns; ++s)
+      for (int64_t p = a.rowoff[s][b] + threadIdx.x; p < a.rowoff[s][b + 1]; p += blockDim.x) {
+        int j, l, i;
+        R fz, fy, fx, v[4];
+        if (!beam_particle(g, a, s, p, j, l, i, fz, fy, fx, v)) continue;
+        const int m = a.nl / 2 - 1;
+        int d = l - lb;
+        if (g.ny == 1) {
+          d = 0;
+        } else {
+          if (d > (g.ny >> 1)) d -= g.ny;
+          if (d < -(g.ny >> 1)) d += g.ny;
+        }
+        if (j != jb || d < -m || d > m) beam_stray_add(g, a, s, p);
+      }
+  }
+}
+
+// Cell-row keys of the loaded beam, for the row offsets: row (j, l) of
+// particles with a node in the grid (j < 0 counts as row (0, l)); inert or
+// out-of-grid particles go to the extra key nxi*ny.
+template <typename R>
+__global__ void __launch_bounds__(256) k_beam_rowcount(Geo<R> g, BeamDepArgs<R> a, int s, int64_t n,
+                                                       int64_t* __restrict__ cnt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int j, l, i;
+  R fz, fy, fx, v[4];
+  int key = g.nxi * g.ny;
+  if (beam_particle(g, a, s, p, j, l, i, fz, fy, fx, v)) key = (j < 0 ? 0 : j) * g.ny + l;
+  atomicAdd((unsigned long long*)(cnt + key), 1ull);
+}
+
+// Exclusive scan of int64 values in blocks of 1024 (in place), block totals
+// to bsum; k_scan64_add adds the scanned totals back.
+__global__ void __launch_bounds__(256) k_scan64_local(int64_t* __restrict__ v, int64_t n,
+                                                      int64_t* __restrict__ bsum) {
+  __shared__ int64_t sh[256];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * 1024 + t * 4;
+  int64_t x[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) x[k] = (base + k < n) ? v[base + k] : 0;
+  const int64_t tsum = x[0] + x[1] + x[2] + x[3];
+  sh[t] = tsum;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int64_t add = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  int64_t acc = sh[t] - tsum;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) v[base + k] = acc;
+    acc += x[k];
+  }
+  if (t == 255) bsum[blockIdx.x] = sh[255];
+}
+
+__global__ void __launch_bounds__(256) k_scan64_add(int64_t* __restrict__ v, int64_t n,
+                                                    const int64_t* __restrict__ bsum) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] += bsum[i >> 10];
+}
+
+// Dense beam sources [4][nxi][ny][nx] from the partial rows (after the
+// out-of-row particles have been added): one pass before the sweep, so the
+// row transforms read one value per node.
+template <typename R>
+__global__ void __launch_bounds__(256) k_beam_reduce(Geo<R> g, const R* __restrict__ bpart, int nl,
+                                                     R* __restrict__ src) {
+  const int64_t plane = (int64_t)g.nxi * g.nperp;
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= plane) return;
+  const int J = (int)(o / g.nperp);
+  const int r = (int)(o - (int64_t)J * g.nperp);
+  const int L = r / g.nx, i = r - L * g.nx;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) src[q * plane + o] = beam_partial(bpart, nl, g.ny, g.nx, q, J, L, i);
+}
+
 
 // Boris push of the beam by dt in the stored fields, E = (-d_x psi + B_y,
 // -d_y psi - B_x, E_z), B = (B_x, B_y, B_z), 3D linear shape, zero outside.

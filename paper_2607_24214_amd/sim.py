@@ -132,6 +132,10 @@ class Sim:
     def sync(self):
         self._check(self.lib.qsa_sync(self.ctx))
 
+    def set_graphs(self, enable: bool):
+        """Replay captured HIP graphs (default) or enqueue every launch."""
+        self._check(self.lib.qsa_set_option(self.ctx, 0, int(bool(enable))))
+
     def timing_begin(self, kernel_class: str):
         """Time every launch of one kernel class with HIP events on the stream."""
         self._check(self.lib.qsa_timing_begin(self.ctx, L.KERNEL_CLASSES[kernel_class]))
