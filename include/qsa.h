@@ -192,6 +192,41 @@ enum {
 /* Set a context option (see QSA_OPT_*). */
 qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent boxes (a growth-rate parameter scan: different
+ * nx, ny, nxi, alpha, gamma_b, dt per box) advanced together.  The slice
+ * loops of all member contexts run as lanes of the same kernel launches (one
+ * launch per phase per slice for the whole batch; a box with fewer slices
+ * drops out), and the whole batched sweep or step is captured once into a
+ * HIP graph and replayed.  Members keep their own workspaces, beams and
+ * fields (read them with qsa_fields / qsa_read_beam on each context); they
+ * must share precision and n_corr, have their plasma loaded, and not be used
+ * on their own while the batch runs work.
+ * ------------------------------------------------------------------------- */
+typedef struct qsa_batch qsa_batch;
+
+/* Device bytes of the batch's lane table (256-byte aligned). */
+size_t qsa_batch_workspace_bytes(int32_t n_ctx);
+
+/* Create a batch over n_ctx distinct contexts.  dev_ws: device memory of
+ * qsa_batch_workspace_bytes(n_ctx) bytes; hip_stream: the caller's stream
+ * (the batch orders its work after it and it after the batch's work).
+ * Synchronizing. */
+qsa_status qsa_batch_create(qsa_ctx* const* ctxs, int32_t n_ctx, void* dev_ws, size_t ws_bytes,
+                            void* hip_stream, qsa_batch** out);
+
+/* One sweep of every member (beam deposit + slice loop). */
+qsa_status qsa_batch_sweep(qsa_batch* b);
+
+/* n_steps x (sweep of every member; Boris push of every member's beam). */
+qsa_status qsa_batch_step(qsa_batch* b, int32_t n_steps);
+
+/* Wait for the batch's work and report any member's pending device error. */
+qsa_status qsa_batch_sync(qsa_batch* b);
+
+/* Free the batch (member contexts and workspaces are not touched). */
+qsa_status qsa_batch_destroy(qsa_batch* b);
+
 /* Free the host context (the workspace is not touched). */
 qsa_status qsa_destroy(qsa_ctx* c);
 

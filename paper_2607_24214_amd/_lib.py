@@ -26,7 +26,8 @@ STATUS = {0: "QSA_OK", -1: "QSA_E_INVALID", -2: "QSA_E_NOMEM", -3: "QSA_E_DEVICE
 EXPORTS = ("qsa_workspace_bytes", "qsa_create", "qsa_load_plasma", "qsa_load_beam",
            "qsa_read_beam", "qsa_slice_sweep", "qsa_beam_step", "qsa_fields", "qsa_sync",
            "qsa_destroy", "qsa_status_string", "qsa_last_error", "qsa_timing_begin",
-           "qsa_timing_end", "qsa_set_option")
+           "qsa_timing_end", "qsa_set_option", "qsa_batch_workspace_bytes", "qsa_batch_create",
+           "qsa_batch_sweep", "qsa_batch_step", "qsa_batch_sync", "qsa_batch_destroy")
 
 KERNEL_CLASSES = {"push_pred": 0, "push_final": 1, "dep_S": 2, "dep_J": 3, "row_r2c": 4,
                   "col": 5, "row_c2r": 6, "beam_deposit": 7, "beam_push": 8}
@@ -80,13 +81,21 @@ def lib():
     L.qsa_timing_begin.argtypes = [vp, i32]
     L.qsa_timing_end.argtypes = [vp, dp, C.POINTER(i64)]
     L.qsa_set_option.argtypes = [vp, i32, i64]
+    L.qsa_batch_workspace_bytes.argtypes = [i32]
+    L.qsa_batch_workspace_bytes.restype = C.c_size_t
+    L.qsa_batch_create.argtypes = [C.POINTER(vp), i32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.qsa_batch_sweep.argtypes = [vp]
+    L.qsa_batch_step.argtypes = [vp, i32]
+    L.qsa_batch_sync.argtypes = [vp]
+    L.qsa_batch_destroy.argtypes = [vp]
     L.qsa_status_string.argtypes = [i32]
     L.qsa_status_string.restype = C.c_char_p
     L.qsa_last_error.argtypes = [vp]
     L.qsa_last_error.restype = C.c_char_p
     for name in ("qsa_create", "qsa_load_plasma", "qsa_load_beam", "qsa_read_beam",
                  "qsa_slice_sweep", "qsa_beam_step", "qsa_fields", "qsa_sync", "qsa_destroy",
-                 "qsa_timing_begin", "qsa_timing_end", "qsa_set_option"):
+                 "qsa_timing_begin", "qsa_timing_end", "qsa_set_option", "qsa_batch_create",
+                 "qsa_batch_sweep", "qsa_batch_step", "qsa_batch_sync", "qsa_batch_destroy"):
         getattr(L, name).restype = i32
     _lib = L
     return L

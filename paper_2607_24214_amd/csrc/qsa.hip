@@ -39,7 +39,7 @@ struct Layout {
   size_t rowoff[QSA_MAX_SPECIES], scan64, bpart, strays, ctl;
   int64_t stray_cap;
   size_t beam[QSA_MAX_SPECIES][7];  // x, y, ux, uy, uz, w (real), xi (double)
-  size_t src, fields, dep, rowspec, colout, jring, jz, bring, ode, err, emit;
+  size_t src, fields, dep, rowspec, colout, jring, jz, bring, ode, err, emit, lane;
   size_t total;
 };
 
@@ -101,6 +101,7 @@ Layout make_layout(const qsa_params& p) {
   L.ode = c.take(2 * sizeof(double));
   L.err = c.take(sizeof(int));
   L.emit = c.take(nperp * sizeof(double));
+  L.lane = c.take(sizeof(Lane<double>));
   L.total = c.off;
   return L;
 }
@@ -177,6 +178,25 @@ struct qsa_ctx {
   ~qsa_ctx() {
     drop_graphs();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+// A batch: the slice loops of several contexts run as lanes of the same
+// launches; beam deposits and pushes run per context on the batch's stream.
+struct qsa_batch {
+  std::vector<qsa_ctx*> ctxs;
+  int precision = QSA_FP64;
+  char* ws = nullptr;     // lane table
+  hipStream_t user = nullptr, stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t gx_step = nullptr, gx_sweep = nullptr;
+  bool use_graphs = true;
+  ~qsa_batch() {
+    if (gx_step) (void)hipGraphExecDestroy(gx_step);
+    if (gx_sweep) (void)hipGraphExecDestroy(gx_sweep);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (stream) (void)hipStreamDestroy(stream);
@@ -277,41 +297,6 @@ struct Engine {
     return QSA_OK;
   }
 
-  // ---- launches of the per-slice kernels --------------------------------
-  static void row_r2c(qsa_ctx* c, const Geo<R>& g, const RowR2CArgs<R>& a, int nf) {
-    const int tpt = g.nx >> 2;
-    const int ppw = (tpt >= 64) ? 1 : 64 / tpt;
-    const int npairs = (g.ny + 1) >> 1;
-    const dim3 grid((npairs + ppw - 1) / ppw, nf);
-    const size_t smem = (2 * (size_t)ppw + 1) * g.nx * sizeof(C2<R>);
-    c->tstart(QSA_K_ROW_R2C);
-    hipLaunchKernelGGL(k_row_r2c<R>, grid, dim3(ppw * tpt), smem, c->stream, g, a,
-                       c->at<C2<R>>(c->L.twx), ppw);
-    c->tstop(QSA_K_ROW_R2C);
-  }
-  static void row_c2r(qsa_ctx* c, const Geo<R>& g, const RowC2RArgs<R>& a, int nf) {
-    const int tpt = g.nx >> 2;
-    const int ppw = (tpt >= 64) ? 1 : 64 / tpt;
-    const int npairs = (g.ny + 1) >> 1;
-    const dim3 grid((npairs + ppw - 1) / ppw, nf);
-    const size_t smem = (2 * (size_t)ppw + 1) * g.nx * sizeof(C2<R>);
-    c->tstart(QSA_K_ROW_C2R);
-    hipLaunchKernelGGL(k_row_c2r<R>, grid, dim3(ppw * tpt), smem, c->stream, g, a,
-                       c->at<C2<R>>(c->L.twx), ppw);
-    c->tstop(QSA_K_ROW_C2R);
-  }
-  template <int MODE>
-  static void col(qsa_ctx* c, const Geo<R>& g, const ColArgs<R>& a) {
-    const int per_col = ColShape<MODE>::G * col_tpt(g.ny);
-    const int cpw = (per_col >= 64) ? 1 : 64 / per_col;
-    const dim3 grid((g.nxh + cpw - 1) / cpw);
-    const size_t smem = ((size_t)cpw * 2 * ColShape<MODE>::G + 1) * g.ny * sizeof(C2<R>);
-    c->tstart(QSA_K_COL);
-    hipLaunchKernelGGL((k_col<R, MODE>), grid, dim3(cpw * per_col), smem, c->stream, g, a,
-                       c->at<C2<R>>(c->L.twy), cpw);
-    c->tstop(QSA_K_COL);
-  }
-
   static BeamDepArgs<R> beam_dep_args(qsa_ctx* c) {
     const qsa_params& p = c->p;
     BeamDepArgs<R> a;
@@ -408,208 +393,182 @@ struct Engine {
     return a;
   }
 
-  template <int MODE>
-  static void plasma_rows(qsa_ctx* c, const Geo<R>& g, const PlasmaArgs<R>& pa, int kclass) {
-    const int per_row = (int)((c->p.n_plasma + g.ny - 1) / g.ny);
-    int nt = (per_row + 63) / 64 * 64;
-    nt = std::max(64, std::min(256, nt));
-    const size_t smem = 4 * PlasmaNC<MODE>::NC * (size_t)g.nx * sizeof(R);
-    c->tstart(kclass);
-    hipLaunchKernelGGL((k_plasma_rows<R, MODE>), dim3(g.ny), dim3(nt), smem, c->stream, g, pa);
-    c->tstop(kclass);
+  // ---- lanes ---------------------------------------------------------------
+  // Device-pointer descriptor of this context's box for the per-slice kernels.
+  static Lane<R> make_lane(qsa_ctx* c) {
+    const qsa_params& p = c->p;
+    const Layout& L = c->L;
+    Lane<R> a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = geo(p);
+    a.np = (int)p.n_plasma;
+    a.q = (R)(-p.plasma_w / (p.dx * p.dy));
+    a.h = (R)p.dxi;
+    a.kappa2 = (R)p.kappa2;
+    a.fields = c->at<R>(L.fields);
+    a.src = c->at<R>(L.src);
+    for (int i = 0; i < 4; ++i) {
+      a.tmpl[i] = c->at<R>(L.tmpl[i]);
+      a.pl[0][i] = c->at<R>(L.pl[i]);
+      a.pl[1][i] = c->at<R>(L.pl2[i]);
+    }
+    a.twx = c->at<C2<R>>(L.twx);
+    a.twy = c->at<C2<R>>(L.twy);
+    a.kx2 = c->at<R>(L.kx2);
+    a.kdx = c->at<R>(L.kdx);
+    a.ky2 = c->at<R>(L.ky2);
+    a.kdy = c->at<R>(L.kdy);
+    a.err = c->at<int>(L.err);
+    a.cell_of = c->at<int>(L.cell_of);
+    a.count = c->at<int>(L.count);
+    a.bsum = c->at<int>(L.bsum);
+    a.prow = c->at<int>(L.prow);
+    a.ppart = c->at<R>(L.ppart);
+    a.dep = c->at<R>(L.dep);
+    a.rowspec = c->at<C2<R>>(L.rowspec);
+    a.colout = c->at<C2<R>>(L.colout);
+    a.jring = c->at<C2<R>>(L.jring);
+    a.jz = c->at<C2<R>>(L.jz);
+    a.bring = c->at<C2<R>>(L.bring);
+    a.ode = c->at<double>(L.ode);
+    return a;
   }
 
-  static qsa_status sweep(qsa_ctx* c) {
-    const qsa_params& p = c->p;
-    const Geo<R> g = geo(p);
-    const Layout& L = c->L;
-    const int64_t plane = (int64_t)p.nxi * g.nperp;
-    const size_t spec = (size_t)g.ny * g.nxh;  // complex elements per spectrum
-    qsa_status st = beam_deposit_all(c, g);
-    if (st != QSA_OK) return st;
-    // plasma enters unperturbed (sorted from the template at slice 0);
-    // rings and wake state start at zero
-    if ((st = fill(c, c->at<R>(L.jring), (int64_t)4 * spec * 2, R(0))) != QSA_OK) return st;
-    if ((st = fill(c, c->at<R>(L.bring), (int64_t)6 * spec * 2, R(0))) != QSA_OK) return st;
-    if ((st = fill(c, c->at<R>(L.dep), (int64_t)3 * g.nperp, R(0))) != QSA_OK) return st;
-    hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(64), 0, c->stream, c->at<double>(L.ode), (int64_t)2, 0.0);
-    HIP_OK(hipGetLastError());
-
-    R* fields = c->at<R>(L.fields);
-    R* dep = c->at<R>(L.dep);
-    R* ppart = c->at<R>(L.ppart);
-    const R* src = c->at<R>(L.src);
-    C2<R>* rowspec = c->at<C2<R>>(L.rowspec);
-    C2<R>* colout = c->at<C2<R>>(L.colout);
-    C2<R>* jring = c->at<C2<R>>(L.jring);
-    C2<R>* bring = c->at<C2<R>>(L.bring);
-    C2<R>* jzs = c->at<C2<R>>(L.jz);
-
-    PlasmaArgs<R> pa;
-    std::memset(&pa, 0, sizeof(pa));
-    pa.np = (int)p.n_plasma;
-    pa.q = (R)(-p.plasma_w / (p.dx * p.dy));
-    pa.dep0 = dep;
-    pa.dep1 = dep + g.nperp;
-    pa.dep2 = dep + 2 * g.nperp;
-    pa.err = c->at<int>(L.err);
-    pa.h = (R)p.dxi;
-    pa.prow = c->at<int>(L.prow);
-    pa.ppart = ppart;
-    const dim3 pgrid((pa.np + 255) / 256), pblock(256);
-
-    ColArgs<R> ca;
-    std::memset(&ca, 0, sizeof(ca));
-    ca.jz = jzs;
-    ca.ode = c->at<double>(L.ode);
-    ca.kx2 = c->at<R>(L.kx2);
-    ca.kdx = c->at<R>(L.kdx);
-    ca.ky2 = c->at<R>(L.ky2);
-    ca.kdy = c->at<R>(L.kdy);
-    ca.inv_n = (R)(1.0 / g.nperp);
-    ca.n_perp = (R)g.nperp;
-    ca.h = (R)p.dxi;
-    ca.kappa2 = (R)p.kappa2;
-
-    auto F = [&](int slot, int j) -> R* { return fields + slot * plane + (int64_t)j * g.nperp; };
-    const int fslot[6] = {F_PSI, F_DXPSI, F_DYPSI, F_BX, F_BY, F_BZ};
-
-    auto r2c_args = [&](int nf, int pnc) {
-      RowR2CArgs<R> ra;
-      std::memset(&ra, 0, sizeof(ra));
-      ra.ppart = ppart;
-      ra.pnc = pnc;
-      for (int q = 0; q < 4; ++q) ra.pc[q] = -1;
-      for (int q = 0; q < nf; ++q) {
-        ra.dep[q] = dep + q * g.nperp;
-        ra.pc[q] = q;
-        ra.out[q] = rowspec + q * spec;
+  // Launch shapes of a set of lanes (maxima over the boxes).
+  struct Dims {
+    int n = 0, nx = 0, ny = 0, nxi = 0, nxh = 0, np = 0, per_row = 0, n_corr = 0;
+    int rows_r2c = 0, rt_rows = 64;   // row-pass grid and block size
+    int cols[3] = {0, 0, 0};          // column-pass grid per mode
+    size_t smem_col[3] = {0, 0, 0};
+    int64_t clear = 0;
+  };
+  static void add_dims(Dims& d, const qsa_params& p) {
+    d.n += 1;
+    d.nx = std::max(d.nx, p.nx);
+    d.ny = std::max(d.ny, p.ny);
+    d.nxi = std::max(d.nxi, p.nxi);
+    d.nxh = std::max(d.nxh, p.nx / 2 + 1);
+    d.np = std::max(d.np, (int)p.n_plasma);
+    d.per_row = std::max(d.per_row, (int)((p.n_plasma + p.ny - 1) / p.ny));
+    d.n_corr = std::max(d.n_corr, p.n_corr);
+    const int64_t spec = (int64_t)p.ny * (p.nx / 2 + 1);
+    d.clear = std::max<int64_t>(d.clear, std::max<int64_t>(6 * spec, 3 * (int64_t)p.nx * p.ny));
+  }
+  static void finish_dims(Dims& d, const qsa_params* const* ps, int n) {
+    d.rt_rows = std::max(64, d.nx / 4);
+    d.rows_r2c = 0;
+    for (int m = 0; m < 3; ++m) {
+      d.cols[m] = 0;
+      d.smem_col[m] = 0;
+    }
+    const int G[3] = {ColShape<COL_PSI>::G, ColShape<COL_J>::G, ColShape<COL_B>::G};
+    for (int i = 0; i < n; ++i) {
+      const qsa_params& p = *ps[i];
+      const int ppw = d.rt_rows / (p.nx / 4);
+      d.rows_r2c = std::max(d.rows_r2c, ((p.ny + 1) / 2 + ppw - 1) / ppw);
+      const int tpt = col_tpt(p.ny);
+      const int cpw = 64 / tpt;
+      for (int m = 0; m < 3; ++m) {
+        d.cols[m] = std::max(d.cols[m], (p.nx / 2 + 1 + cpw - 1) / cpw);
+        d.smem_col[m] = std::max(d.smem_col[m], ((size_t)cpw * 2 * G[m] + 1) * p.ny * sizeof(C2<R>));
       }
-      return ra;
-    };
+    }
+  }
 
-    int cur = 0;   // 0: state in pl, 1: state in pl2
-    for (int j = 0; j < p.nxi; ++j) {
-      if (j % kSortEvery == 0) {
-        const size_t* A = (j == 0) ? L.tmpl : (cur ? L.pl2 : L.pl);
-        const size_t* B = (j == 0) ? L.pl : (cur ? L.pl : L.pl2);
-        if ((st = sort_plasma(c, g, A, B)) != QSA_OK) return st;
-        cur = (j == 0) ? 0 : cur ^ 1;
-        const size_t* P = cur ? L.pl2 : L.pl;
-        pa.x = c->at<R>(P[0]);
-        pa.y = c->at<R>(P[1]);
-        pa.ux = c->at<R>(P[2]);
-        pa.uy = c->at<R>(P[3]);
+  // The slice loop of every lane: one launch per phase per slice, blockIdx.z
+  // = lane.  `tc` receives the kernel-class timing marks.
+  static qsa_status slices(qsa_ctx* tc, hipStream_t st, const Lane<R>* lanes, const Dims& d) {
+    const int n = d.n;
+    const int pb = (d.np + 255) / 256;
+    const size_t smem_rows = ((size_t)d.nx + 8 * (size_t)d.rt_rows) * sizeof(C2<R>);
+    int nt = (d.per_row + 63) / 64 * 64;
+    nt = std::max(64, std::min(256, nt));
+    {
+      const int blocks = (int)std::min<int64_t>(1024, (d.clear + 255) / 256);
+      hipLaunchKernelGGL((k_lane_clear<R, 0>), dim3(blocks, 1, n), dim3(256), 0, st, lanes, 0);
+    }
+    for (int j = 0; j < d.nxi; ++j) {
+      if (j % QSA_SORT_EVERY == 0) {
+        hipLaunchKernelGGL((k_lane_clear<R, 1>), dim3((d.nx * d.ny + 255) / 256, 1, n), dim3(256), 0, st, lanes,
+                           j);
+        hipLaunchKernelGGL(k_sort_count<R>, dim3(pb, 1, n), dim3(256), 0, st, lanes, j);
+        hipLaunchKernelGGL(k_scan_local<R>, dim3((d.nx * d.ny + 1023) / 1024, 1, n), dim3(256), 0, st, lanes, j);
+        hipLaunchKernelGGL(k_scan_blocks<R>, dim3(1, 1, n), dim3(256), 0, st, lanes, j);
+        hipLaunchKernelGGL(k_row_offsets<R>, dim3((d.ny + 1 + 255) / 256, 1, n), dim3(256), 0, st, lanes, j);
+        hipLaunchKernelGGL(k_sort_scatter<R>, dim3(pb, 1, n), dim3(256), 0, st, lanes, j);
       }
-      for (int q = 0; q < 6; ++q) {
-        pa.F0[q] = F(fslot[q], j);
-        pa.F1[q] = (j >= 1) ? F(fslot[q], j - 1) : nullptr;
-      }
-      pa.psi_m2 = (j >= 2) ? F(F_PSI, j - 2) : nullptr;
+      const dim3 rgrid_psi(d.rows_r2c, 1, n), rgrid_j(d.rows_r2c, 3, n), rgrid_b(d.rows_r2c, 2, n);
+      const dim3 rblock(d.rt_rows);
       // ---- psi stage
-      plasma_rows<PL_DEP_S>(c, g, pa, QSA_K_DEP_S);
-      {
-        RowR2CArgs<R> ra = r2c_args(1, 1);
-        ra.addc[0] = R(1);
-        ra.add[0] = src + (int64_t)j * g.nperp;
-        row_r2c(c, g, ra, 1);
-      }
-      ca.in[0] = rowspec;
-      for (int q = 0; q < 3; ++q) ca.out[q] = colout + q * spec;
-      col<COL_PSI>(c, g, ca);
-      {
-        RowC2RArgs<R> rc;
-        std::memset(&rc, 0, sizeof(rc));
-        for (int q = 0; q < 3; ++q) rc.in[q] = colout + q * spec;
-        rc.out[0] = F(F_PSI, j);
-        rc.out[1] = F(F_DXPSI, j);
-        rc.out[2] = F(F_DYPSI, j);
-        row_c2r(c, g, rc, 3);
-      }
+      tc->tstart(QSA_K_DEP_S);
+      hipLaunchKernelGGL((k_plasma_rows<R, PL_DEP_S>), dim3(d.ny, 1, n), dim3(nt),
+                         4 * 1 * (size_t)d.nx * sizeof(R), st, lanes, j);
+      tc->tstop(QSA_K_DEP_S);
+      tc->tstart(QSA_K_ROW_R2C);
+      hipLaunchKernelGGL(k_row_r2c<R>, rgrid_psi, rblock, smem_rows, st, lanes, j, (int)ST_PSI);
+      tc->tstop(QSA_K_ROW_R2C);
+      tc->tstart(QSA_K_COL);
+      hipLaunchKernelGGL((k_col<R, COL_PSI>), dim3(d.cols[0], 1, n), dim3(64 * ColShape<COL_PSI>::G),
+                         d.smem_col[0], st, lanes, j);
+      tc->tstop(QSA_K_COL);
+      tc->tstart(QSA_K_ROW_C2R);
+      hipLaunchKernelGGL(k_row_c2r<R>, dim3(d.rows_r2c, 3, n), rblock, smem_rows, st, lanes, j, (int)ST_PSI);
+      tc->tstop(QSA_K_ROW_C2R);
       // ---- J stage
-      plasma_rows<PL_DEP_J>(c, g, pa, QSA_K_DEP_J);
-      {
-        RowR2CArgs<R> ra = r2c_args(3, 3);
-        for (int q = 0; q < 3; ++q) ra.add[q] = src + (1 + q) * plane + (int64_t)j * g.nperp;
-        row_r2c(c, g, ra, 3);
-      }
-      for (int q = 0; q < 3; ++q) ca.in[q] = rowspec + q * spec;
-      for (int q = 0; q < 4; ++q) ca.out[q] = colout + q * spec;
-      const int s2 = j & 1, s2m = (j + 1) & 1;           // J ring: slot j%2, slot (j-1)%2
-      const int s3 = j % 3, s3m1 = (j + 2) % 3, s3m2 = (j + 1) % 3;  // B ring
-      ca.jr_w[0] = jring + (2 * s2 + 0) * spec;
-      ca.jr_w[1] = jring + (2 * s2 + 1) * spec;
-      ca.jr_r[0] = jring + (2 * s2m + 0) * spec;
-      ca.jr_r[1] = jring + (2 * s2m + 1) * spec;
-      for (int q = 0; q < 2; ++q) {
-        ca.b_cur[q] = bring + (2 * s3 + q) * spec;
-        ca.b_m1[q] = bring + (2 * s3m1 + q) * spec;
-        ca.b_m2[q] = bring + (2 * s3m2 + q) * spec;
-      }
-      col<COL_J>(c, g, ca);
-      {
-        RowC2RArgs<R> rc;
-        std::memset(&rc, 0, sizeof(rc));
-        for (int q = 0; q < 4; ++q) rc.in[q] = colout + q * spec;
-        rc.out[0] = F(F_BZ, j);
-        rc.out[1] = F(F_EZ, j);
-        rc.out[2] = F(F_BX, j);
-        rc.out[3] = F(F_BY, j);
-        row_c2r(c, g, rc, 4);
-      }
+      tc->tstart(QSA_K_DEP_J);
+      hipLaunchKernelGGL((k_plasma_rows<R, PL_DEP_J>), dim3(d.ny, 1, n), dim3(nt),
+                         4 * 3 * (size_t)d.nx * sizeof(R), st, lanes, j);
+      tc->tstop(QSA_K_DEP_J);
+      tc->tstart(QSA_K_ROW_R2C);
+      hipLaunchKernelGGL(k_row_r2c<R>, rgrid_j, rblock, smem_rows, st, lanes, j, (int)ST_J);
+      tc->tstop(QSA_K_ROW_R2C);
+      tc->tstart(QSA_K_COL);
+      hipLaunchKernelGGL((k_col<R, COL_J>), dim3(d.cols[1], 1, n), dim3(64 * ColShape<COL_J>::G),
+                         d.smem_col[1], st, lanes, j);
+      tc->tstop(QSA_K_COL);
+      tc->tstart(QSA_K_ROW_C2R);
+      hipLaunchKernelGGL(k_row_c2r<R>, dim3(d.rows_r2c, 4, n), rblock, smem_rows, st, lanes, j, (int)ST_J);
+      tc->tstop(QSA_K_ROW_C2R);
       // ---- B_perp predictor-corrector
-      for (int k = 0; k < p.n_corr; ++k) {
-        plasma_rows<PL_PRED>(c, g, pa, QSA_K_PUSH_PRED);
-        {
-          RowR2CArgs<R> ra = r2c_args(2, 2);
-          if (j + 1 < p.nxi)
-            for (int q = 0; q < 2; ++q) ra.add[q] = src + (1 + q) * plane + (int64_t)(j + 1) * g.nperp;
-          row_r2c(c, g, ra, 2);
-        }
-        for (int q = 0; q < 2; ++q) ca.in[q] = rowspec + q * spec;
-        ca.in[2] = nullptr;
-        for (int q = 0; q < 2; ++q) ca.out[q] = colout + q * spec;
-        col<COL_B>(c, g, ca);
-        {
-          RowC2RArgs<R> rc;
-          std::memset(&rc, 0, sizeof(rc));
-          for (int q = 0; q < 2; ++q) rc.in[q] = colout + q * spec;
-          rc.out[0] = F(F_BX, j);
-          rc.out[1] = F(F_BY, j);
-          row_c2r(c, g, rc, 2);
-        }
+      for (int k = 0; k < d.n_corr; ++k) {
+        tc->tstart(QSA_K_PUSH_PRED);
+        hipLaunchKernelGGL((k_plasma_rows<R, PL_PRED>), dim3(d.ny, 1, n), dim3(nt),
+                           4 * 2 * (size_t)d.nx * sizeof(R), st, lanes, j);
+        tc->tstop(QSA_K_PUSH_PRED);
+        tc->tstart(QSA_K_ROW_R2C);
+        hipLaunchKernelGGL(k_row_r2c<R>, rgrid_b, rblock, smem_rows, st, lanes, j, (int)ST_B);
+        tc->tstop(QSA_K_ROW_R2C);
+        tc->tstart(QSA_K_COL);
+        hipLaunchKernelGGL((k_col<R, COL_B>), dim3(d.cols[2], 1, n), dim3(64 * ColShape<COL_B>::G),
+                           d.smem_col[2], st, lanes, j);
+        tc->tstop(QSA_K_COL);
+        tc->tstart(QSA_K_ROW_C2R);
+        hipLaunchKernelGGL(k_row_c2r<R>, rgrid_b, rblock, smem_rows, st, lanes, j, (int)ST_B);
+        tc->tstop(QSA_K_ROW_C2R);
       }
       // ---- advance the plasma to slice j+1
-      c->tstart(QSA_K_PUSH_FINAL);
-      hipLaunchKernelGGL(k_push_final<R>, pgrid, pblock, 0, c->stream, g, pa);
-      c->tstop(QSA_K_PUSH_FINAL);
+      tc->tstart(QSA_K_PUSH_FINAL);
+      hipLaunchKernelGGL(k_push_final<R>, dim3(pb, 1, n), dim3(256), 0, st, lanes, j);
+      tc->tstop(QSA_K_PUSH_FINAL);
     }
-    HIP_OK(hipGetLastError());
-    c->swept = true;
     return QSA_OK;
   }
 
-  // Counting sort of the plasma state by cell (buffer set A -> B) and the
-  // first particle of every cell row.
-  static qsa_status sort_plasma(qsa_ctx* c, const Geo<R>& g, const size_t* A, const size_t* B) {
-    const Layout& L = c->L;
-    const int np = (int)c->p.n_plasma;
-    int* count = c->at<int>(L.count);
-    int* cell_of = c->at<int>(L.cell_of);
-    int* bsum = c->at<int>(L.bsum);
-    hipLaunchKernelGGL(k_fill<int>, dim3(fill_blocks(g.nperp)), dim3(256), 0, c->stream, count,
-                       (int64_t)g.nperp, 0);
-    hipLaunchKernelGGL(k_sort_count<R>, dim3((np + 255) / 256), dim3(256), 0, c->stream, g,
-                       c->at<R>(A[0]), c->at<R>(A[1]), np, cell_of, count);
-    const int nb = (g.nperp + 1023) / 1024;
-    hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, c->stream, count, g.nperp, bsum);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, c->stream, bsum, nb);
-    hipLaunchKernelGGL(k_row_offsets, dim3((g.ny + 1 + 255) / 256), dim3(256), 0, c->stream, count, bsum,
-                       g.nx, g.ny, np, c->at<int>(L.prow));
-    hipLaunchKernelGGL(k_sort_scatter<R>, dim3((np + 255) / 256), dim3(256), 0, c->stream, np, cell_of,
-                       count, bsum, c->at<R>(A[0]), c->at<R>(A[1]), c->at<R>(A[2]), c->at<R>(A[3]),
-                       c->at<R>(B[0]), c->at<R>(B[1]), c->at<R>(B[2]), c->at<R>(B[3]));
+  static Dims dims_of(qsa_ctx* c) {
+    Dims d;
+    add_dims(d, c->p);
+    const qsa_params* ps[1] = {&c->p};
+    finish_dims(d, ps, 1);
+    return d;
+  }
+
+  static qsa_status sweep(qsa_ctx* c) {
+    const Geo<R> g = geo(c->p);
+    qsa_status st = beam_deposit_all(c, g);
+    if (st != QSA_OK) return st;
+    if ((st = slices(c, c->stream, c->at<Lane<R>>(c->L.lane), dims_of(c))) != QSA_OK) return st;
     HIP_OK(hipGetLastError());
+    c->swept = true;
     return QSA_OK;
   }
 
@@ -762,6 +721,10 @@ struct Engine {
     HIP_OK(hipMemcpyAsync(c->ws + c->L.ky2, ky2.data(), ky2.size(), hipMemcpyHostToDevice, c->stream));
     HIP_OK(hipMemcpyAsync(c->ws + c->L.kdy, kdy.data(), kdy.size(), hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, c->stream, c->at<int>(c->L.err), (int64_t)1, 0);
+    {
+      const Lane<R> lane = make_lane(c);
+      HIP_OK(hipMemcpyAsync(c->ws + c->L.lane, &lane, sizeof(lane), hipMemcpyHostToDevice, c->stream));
+    }
     // no beam loaded yet: every species has empty cell rows
     const int64_t nrows = (int64_t)c->p.nxi * c->p.ny;
     for (int s = 0; s < QSA_MAX_SPECIES; ++s)
@@ -836,6 +799,39 @@ qsa_status run_step(qsa_ctx* c) {
   qsa_status st = run_sweep(c);
   if (st != QSA_OK) return st;
   return dispatch(c, [&] { return Engine<double>::push(c); }, [&] { return Engine<float>::push(c); });
+}
+
+// Batched sweep (and push): every context's beam deposit on the batch's
+// stream, then one slice loop over all lanes.
+template <typename R>
+qsa_status batch_run(qsa_batch* b, bool push) {
+  qsa_ctx* c0 = b->ctxs[0];
+  typename Engine<R>::Dims d;
+  std::vector<const qsa_params*> ps;
+  for (qsa_ctx* c : b->ctxs) {
+    Engine<R>::add_dims(d, c->p);
+    ps.push_back(&c->p);
+  }
+  Engine<R>::finish_dims(d, ps.data(), (int)ps.size());
+  for (qsa_ctx* c : b->ctxs) {
+    hipStream_t own = c->stream;
+    c->stream = b->stream;
+    const qsa_status st = Engine<R>::beam_deposit_all(c, Engine<R>::geo(c->p));
+    c->stream = own;
+    if (st != QSA_OK) return st;
+  }
+  qsa_status st = Engine<R>::slices(c0, b->stream, reinterpret_cast<const Lane<R>*>(b->ws), d);
+  if (st != QSA_OK) return st;
+  for (qsa_ctx* c : b->ctxs) {
+    c->swept = true;
+    if (!push) continue;
+    hipStream_t own = c->stream;
+    c->stream = b->stream;
+    st = Engine<R>::push(c);
+    c->stream = own;
+    if (st != QSA_OK) return st;
+  }
+  return QSA_OK;
 }
 
 }  // namespace
@@ -1061,6 +1057,127 @@ qsa_status qsa_timing_end(qsa_ctx* c, double* total_ms, int64_t* launches) {
     (void)hipGetLastError();
     return fail(c, QSA_E_DEVICE, "hipEventElapsedTime failed");
   }
+  return QSA_OK;
+}
+
+size_t qsa_batch_workspace_bytes(int32_t n_ctx) {
+  if (n_ctx < 1) return 0;
+  return ((size_t)n_ctx * sizeof(Lane<double>) + kAlign - 1) / kAlign * kAlign;
+}
+
+qsa_status qsa_batch_create(qsa_ctx* const* ctxs, int32_t n_ctx, void* dev_ws, size_t ws_bytes,
+                            void* hip_stream, qsa_batch** out) {
+  if (!out || !ctxs || n_ctx < 1) return QSA_E_INVALID;
+  *out = nullptr;
+  if (!dev_ws || ((uintptr_t)dev_ws % kAlign) != 0) return QSA_E_INVALID;
+  if (ws_bytes < qsa_batch_workspace_bytes(n_ctx)) return QSA_E_NOMEM;
+  for (int i = 0; i < n_ctx; ++i) {
+    qsa_ctx* c = ctxs[i];
+    if (!c) return QSA_E_INVALID;
+    if (c->p.precision != ctxs[0]->p.precision || c->p.n_corr != ctxs[0]->p.n_corr) return QSA_E_INVALID;
+    if (!c->plasma_loaded) return QSA_E_STATE;
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == c) return QSA_E_INVALID;
+  }
+  qsa_batch* b = new qsa_batch();
+  b->ctxs.assign(ctxs, ctxs + n_ctx);
+  b->precision = ctxs[0]->p.precision;
+  b->ws = reinterpret_cast<char*>(dev_ws);
+  b->user = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+    delete b;
+    return QSA_E_DEVICE;
+  }
+  // lane table: one descriptor per context
+  std::vector<char> host(qsa_batch_workspace_bytes(n_ctx), 0);
+  for (int i = 0; i < n_ctx; ++i) {
+    if (b->precision == QSA_FP32) {
+      const Lane<float> l = Engine<float>::make_lane(ctxs[i]);
+      std::memcpy(host.data() + i * sizeof(Lane<float>), &l, sizeof(l));
+    } else {
+      const Lane<double> l = Engine<double>::make_lane(ctxs[i]);
+      std::memcpy(host.data() + i * sizeof(Lane<double>), &l, sizeof(l));
+    }
+  }
+  if (hipMemcpyAsync(b->ws, host.data(), host.size(), hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess) {
+    delete b;
+    return QSA_E_DEVICE;
+  }
+  *out = b;
+  return QSA_OK;
+}
+
+static qsa_status batch_call(qsa_batch* b, int32_t n_steps, bool push) {
+  qsa_ctx* c = b->ctxs[0];   // error reporting
+  for (qsa_ctx* m : b->ctxs)
+    if (m->sticky != QSA_OK) return m->sticky;
+  HIP_OK(hipEventRecord(b->ev_in, b->user));
+  HIP_OK(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+  hipGraphExec_t* gx = push ? &b->gx_step : &b->gx_sweep;
+  auto body = [&] { return b->precision == QSA_FP32 ? batch_run<float>(b, push) : batch_run<double>(b, push); };
+  const bool graphs = b->use_graphs && c->timing_class < 0;
+  if (graphs && !*gx) {
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const qsa_status st = body();
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(b->stream, &graph);
+      hipError_t ei = hipErrorUnknown;
+      if (st == QSA_OK && e == hipSuccess) ei = hipGraphInstantiate(gx, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (st != QSA_OK) return st;
+      if (e != hipSuccess || ei != hipSuccess) {
+        (void)hipGetLastError();
+        *gx = nullptr;
+        b->use_graphs = false;
+      }
+    } else {
+      (void)hipGetLastError();
+      b->use_graphs = false;
+    }
+  }
+  for (int i = 0; i < n_steps; ++i) {
+    if (graphs && *gx) {
+      HIP_OK(hipGraphLaunch(*gx, b->stream));
+      for (qsa_ctx* m : b->ctxs) m->swept = true;
+    } else {
+      const qsa_status st = body();
+      if (st != QSA_OK) return st;
+    }
+  }
+  HIP_OK(hipEventRecord(b->ev_out, b->stream));
+  HIP_OK(hipStreamWaitEvent(b->user, b->ev_out, 0));
+  return QSA_OK;
+}
+
+qsa_status qsa_batch_sweep(qsa_batch* b) {
+  if (!b) return QSA_E_INVALID;
+  return batch_call(b, 1, false);
+}
+
+qsa_status qsa_batch_step(qsa_batch* b, int32_t n_steps) {
+  if (!b || n_steps < 0) return QSA_E_INVALID;
+  if (n_steps == 0) return QSA_OK;
+  return batch_call(b, n_steps, true);
+}
+
+qsa_status qsa_batch_sync(qsa_batch* b) {
+  if (!b) return QSA_E_INVALID;
+  {
+    qsa_ctx* c = b->ctxs[0];
+    HIP_OK(hipStreamSynchronize(b->stream));
+  }
+  for (qsa_ctx* c : b->ctxs) {
+    const qsa_status st = qsa_sync(c);
+    if (st != QSA_OK) return st;
+  }
+  return QSA_OK;
+}
+
+qsa_status qsa_batch_destroy(qsa_batch* b) {
+  delete b;
   return QSA_OK;
 }
 

@@ -24,6 +24,49 @@ enum { F_PSI = 0, F_DXPSI = 1, F_DYPSI = 2, F_EZ = 3, F_BX = 4, F_BY = 5, F_BZ =
 enum { ERR_BREAKDOWN = 1 };
 
 #define QSA_GMIN 1.0e-3
+#define QSA_SORT_EVERY 8   // the plasma is counting-sorted by cell every this many slices
+
+// One box's slice loop: geometry, constants and every array the per-slice
+// kernels touch.  The per-slice kernels take an array of lanes and the slice
+// index j; blockIdx.z selects the lane, so one launch advances many
+// independent boxes (a batched parameter scan) by one slice.  A lane whose
+// box has fewer slices than j returns at once.
+template <typename R>
+struct Lane {
+  Geo<R> g;
+  int np;               // plasma macro-particles per slice
+  R q;                  // -w/(dx dy): plasma rho - J_z per particle per unit area
+  R h;                  // dxi
+  R kappa2;             // Helmholtz shift of the B_perp iteration
+  R* fields;            // [7][nxi][ny][nx]
+  const R* src;         // beam sources [4][nxi][ny][nx]
+  const R* tmpl[4];     // plasma template x, y, ux, uy
+  const C2<R>* twx;     // transform tables
+  const C2<R>* twy;
+  const R* kx2;
+  const R* kdx;
+  const R* ky2;
+  const R* kdy;
+  int* err;             // sticky device error flags
+  R* pl[2][4];          // plasma state, two buffer sets (sorts ping-pong)
+  int* cell_of;         // sort scratch
+  int* count;
+  int* bsum;
+  int* prow;            // [ny + 1] first particle of each cell row
+  R* ppart;             // plasma partial node rows [ny][4][3][nx]
+  R* dep;               // out-of-row plasma deposits [3][nperp]
+  C2<R>* rowspec;       // row-pass half spectra [4][ny][nxh]
+  C2<R>* colout;        // column-pass outputs [4][ny][nxh]
+  C2<R>* jring;         // J_perp spectra, ring of 2 slices [2][2][ny][nxh]
+  C2<R>* jz;            // J_z spectrum [ny][nxh]
+  C2<R>* bring;         // B_perp spectra, ring of 3 slices [3][2][ny][nxh]
+  double* ode;          // [<E_z> at j-1/2, <psi> at j]
+};
+
+// plasma buffer set that holds the state at slice j
+__device__ __forceinline__ int plasma_set(int j) { return (j / QSA_SORT_EVERY) & 1; }
+
+enum { ST_PSI = 0, ST_J = 1, ST_B = 2 };   // the three solve stages of a slice
 
 // ----------------------------------------------------------------- utility
 template <typename R>
@@ -71,6 +114,27 @@ __global__ void k_copy4(const R* __restrict__ a0, const R* __restrict__ a1,
     b2[i] = a2[i];
     b3[i] = a3[i];
   }
+}
+
+// Per-lane clears: WHAT = 0 zeroes the sweep state (J and B rings, the
+// out-of-row grids, the transverse-mean wake), WHAT = 1 the sort counts.
+template <typename R, int WHAT>
+__global__ void k_lane_clear(const Lane<R>* __restrict__ lanes, int j) {
+  const Lane<R>& L = lanes[blockIdx.z];
+  const Geo<R>& g = L.g;
+  if (j >= g.nxi) return;
+  const int64_t spec = (int64_t)g.ny * g.nxh;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  if (WHAT == 1) {
+    for (int64_t i = i0; i < g.nperp; i += st) L.count[i] = 0;
+    return;
+  }
+  const C2<R> z{R(0), R(0)};
+  for (int64_t i = i0; i < 4 * spec; i += st) L.jring[i] = z;
+  for (int64_t i = i0; i < 6 * spec; i += st) L.bring[i] = z;
+  for (int64_t i = i0; i < 3 * (int64_t)g.nperp; i += st) L.dep[i] = R(0);
+  if (i0 < 2) L.ode[i0] = 0.0;
 }
 
 // ------------------------------------------- block-private partial node rows
@@ -129,39 +193,76 @@ __device__ __forceinline__ R beam_partial(const R* __restrict__ bp, int nl, int 
 }
 
 // ------------------------------------------------------------ row transforms
+// Row-pass inputs of field f of a stage at slice j: the plasma partial rows
+// and out-of-row grid of the stage's deposit, the beam source (of slice j+1
+// for the predicted J_perp) and the ion background.
 template <typename R>
-struct RowR2CArgs {
-  R* dep[4];          // stray grid [nperp] or null: read, then cleared
-  const R* ppart;     // plasma partial rows or null
-  int pc[4];          // plasma component of each field (-1: none)
-  int pnc;            // components in the plasma partial layout
-  const R* add[4];    // dense beam source row block of each field, or null
-  R addc[4];          // constant (ion background)
-  C2<R>* out[4];      // half spectra [ny][nxh]
+struct RowIn {
+  R* dep;             // out-of-row deposits of this field: read, then cleared
+  const R* pp;        // plasma partial rows, component offset applied
+  int pnc;            // components per plasma partial row block
+  const R* add;       // beam source slice or null
+  R addc;             // ion background
+  C2<R>* out;         // half spectra [ny][nxh]
 };
 
 template <typename R>
-__device__ __forceinline__ R row_value(const Geo<R>& g, const RowR2CArgs<R>& a, int f, int r, int i) {
-  R v = a.addc[f];
+__device__ __forceinline__ int stage_fields_in(int stage) {
+  return (stage == ST_PSI) ? 1 : (stage == ST_J ? 3 : 2);
+}
+
+template <typename R>
+__device__ __forceinline__ RowIn<R> row_in(const Lane<R>& L, int j, int stage, int f) {
+  const Geo<R>& g = L.g;
+  const int64_t plane = (int64_t)g.nxi * g.nperp;
+  RowIn<R> a;
+  a.pnc = stage_fields_in<R>(stage);
+  a.dep = L.dep + f * g.nperp;
+  a.pp = L.ppart + (size_t)f * g.nx;
+  a.out = L.rowspec + (size_t)f * g.ny * g.nxh;
+  a.addc = (stage == ST_PSI) ? R(1) : R(0);
+  if (stage == ST_PSI) a.add = L.src + (int64_t)j * g.nperp;
+  else if (stage == ST_J) a.add = L.src + (1 + f) * plane + (int64_t)j * g.nperp;
+  else a.add = (j + 1 < g.nxi) ? L.src + (1 + f) * plane + (int64_t)(j + 1) * g.nperp : nullptr;
+  return a;
+}
+
+template <typename R>
+__device__ __forceinline__ R row_value(const Geo<R>& g, const RowIn<R>& a, int r, int i) {
   const int o = r * g.nx + i;
-  if (a.dep[f]) {
-    v += a.dep[f][o];
-    a.dep[f][o] = R(0);
+  R v = a.addc + a.dep[o];
+  a.dep[o] = R(0);
+  // partial rows: block rr covers node rows rr-1 .. rr+2 (k = 0..3)
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int rr = r + 1 - k;
+    if (g.ny == 1) {
+      rr = 0;
+    } else {
+      rr += (rr < 0) ? g.ny : 0;
+      rr -= (rr >= g.ny) ? g.ny : 0;
+    }
+    v += a.pp[((size_t)(rr * 4 + k) * a.pnc) * g.nx + i];
   }
-  if (a.pc[f] >= 0) v += plasma_partial(a.ppart, a.pnc, g.ny, g.nx, a.pc[f], r, i);
-  if (a.add[f]) v += a.add[f][o];
+  if (a.add) v += a.add[o];
   return v;
 }
 
 // Real rows -> half spectra along x.  Rows 2p and 2p+1 are packed as the
 // real and imaginary parts of one complex transform and separated after it.
 template <typename R>
-__global__ void __launch_bounds__(256) k_row_r2c(Geo<R> g, RowR2CArgs<R> a,
-                                                 const C2<R>* __restrict__ twx, int ppw) {
+__global__ void __launch_bounds__(256) k_row_r2c(const Lane<R>* __restrict__ lanes, int j, int stage) {
+  const Lane<R>& L = lanes[blockIdx.z];
+  const Geo<R> g = L.g;
+  const int f = blockIdx.y;
+  if (j >= g.nxi || f >= stage_fields_in<R>(stage)) return;
+  const RowIn<R> a = row_in(L, j, stage, f);
+  const C2<R>* __restrict__ twx = L.twx;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* sm = reinterpret_cast<C2<R>*>(smem_raw);
-  const int f = blockIdx.y;
   const int tpt = g.nx >> 2;
+  const int ppw = blockDim.x / tpt;
+  if (blockIdx.x * ppw >= ((g.ny + 1) >> 1)) return;
   const int slot = threadIdx.x / tpt, t = threadIdx.x - slot * tpt;
   const int npairs = (g.ny + 1) >> 1;
   const int pair = blockIdx.x * ppw + slot;
@@ -173,14 +274,14 @@ __global__ void __launch_bounds__(256) k_row_r2c(Geo<R> g, RowR2CArgs<R> a,
   C2<R>* A = sm + g.nx + (size_t)slot * 2 * g.nx;
   C2<R>* B = A + g.nx;
   for (int i = t; i < g.nx; i += tpt) {
-    const R va = v0 ? row_value(g, a, f, r0, i) : R(0);
-    const R vb = v1 ? row_value(g, a, f, r1, i) : R(0);
+    const R va = v0 ? row_value(g, a, r0, i) : R(0);
+    const R vb = v1 ? row_value(g, a, r1, i) : R(0);
     A[i] = C2<R>{va, vb};
   }
   __syncthreads();
   C2<R>* res = fft_lds<R, false>(A, B, g.nx, g.lgx, t, tpt, tw);
   if (v0) {
-    C2<R>* out = a.out[f];
+    C2<R>* out = a.out;
     for (int k = t; k < g.nxh; k += tpt) {
       const C2<R> z = res[k];
       const C2<R> zc = cconj(res[(g.nx - k) & (g.nx - 1)]);
@@ -191,21 +292,33 @@ __global__ void __launch_bounds__(256) k_row_r2c(Geo<R> g, RowR2CArgs<R> a,
   }
 }
 
-template <typename R>
-struct RowC2RArgs {
-  const C2<R>* in[4];  // half spectra [ny][nxh]
-  R* out[4];           // real grids [nperp]
-};
-
 // Half spectra -> real rows (unnormalized inverse; the 1/(nx ny) factor is
 // applied in the column pass).  Two rows are packed as A + iB.
+// Row-pass output slot of field f of a stage: psi, d_x psi, d_y psi; or
+// B_z, E_z and B_perp^(0); or the B_perp iterate.
+__device__ __forceinline__ int stage_fields_out(int stage) {
+  return (stage == ST_PSI) ? 3 : (stage == ST_J ? 4 : 2);
+}
+__device__ __forceinline__ int stage_slot(int stage, int f) {
+  if (stage == ST_PSI) return f == 0 ? F_PSI : (f == 1 ? F_DXPSI : F_DYPSI);
+  if (stage == ST_J) return f == 0 ? F_BZ : (f == 1 ? F_EZ : (f == 2 ? F_BX : F_BY));
+  return f == 0 ? F_BX : F_BY;
+}
+
 template <typename R>
-__global__ void __launch_bounds__(256) k_row_c2r(Geo<R> g, RowC2RArgs<R> a,
-                                                 const C2<R>* __restrict__ twx, int ppw) {
+__global__ void __launch_bounds__(256) k_row_c2r(const Lane<R>* __restrict__ lanes, int j, int stage) {
+  const Lane<R>& L = lanes[blockIdx.z];
+  const Geo<R> g = L.g;
+  const int f = blockIdx.y;
+  if (j >= g.nxi || f >= stage_fields_out(stage)) return;
+  const C2<R>* __restrict__ in = L.colout + (size_t)f * g.ny * g.nxh;
+  R* __restrict__ outp = L.fields + (int64_t)stage_slot(stage, f) * g.nxi * g.nperp + (int64_t)j * g.nperp;
+  const C2<R>* __restrict__ twx = L.twx;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* sm = reinterpret_cast<C2<R>*>(smem_raw);
-  const int f = blockIdx.y;
   const int tpt = g.nx >> 2;
+  const int ppw = blockDim.x / tpt;
+  if (blockIdx.x * ppw >= ((g.ny + 1) >> 1)) return;
   const int slot = threadIdx.x / tpt, t = threadIdx.x - slot * tpt;
   const int npairs = (g.ny + 1) >> 1;
   const int pair = blockIdx.x * ppw + slot;
@@ -216,7 +329,6 @@ __global__ void __launch_bounds__(256) k_row_c2r(Geo<R> g, RowC2RArgs<R> a,
   for (int i = threadIdx.x; i < g.nx; i += blockDim.x) tw[i] = twx[i];
   C2<R>* A = sm + g.nx + (size_t)slot * 2 * g.nx;
   C2<R>* B = A + g.nx;
-  const C2<R>* in = a.in[f];
   const int half = g.nx >> 1;
   for (int i = t; i < g.nx; i += tpt) {
     C2<R> av{0, 0}, bv{0, 0};
@@ -239,7 +351,7 @@ __global__ void __launch_bounds__(256) k_row_c2r(Geo<R> g, RowC2RArgs<R> a,
   __syncthreads();
   C2<R>* res = fft_lds<R, true>(A, B, g.nx, g.lgx, t, tpt, tw);
   if (v0) {
-    R* out = a.out[f];
+    R* out = outp;
     for (int i = t; i < g.nx; i += tpt) {
       const C2<R> z = res[i];
       out[r0 * g.nx + i] = z.x;
@@ -251,8 +363,6 @@ __global__ void __launch_bounds__(256) k_row_c2r(Geo<R> g, RowC2RArgs<R> a,
 // ---------------------------------------------------------- column transforms
 template <typename R>
 struct ColArgs {
-  const C2<R>* in[3];     // half spectra [ny][nxh] after the row pass
-  C2<R>* out[4];          // outputs, y-inverse-transformed, for k_row_c2r
   C2<R>* jr_w[2];         // COL_J: spectra of J_x, J_y at slice j (ring slot j%2)
   const C2<R>* jr_r[2];   // COL_B: spectra of J_x, J_y at slice j-1
   C2<R>* jz;              // spectrum of J_z at slice j
@@ -287,16 +397,50 @@ __host__ __device__ __forceinline__ int col_tpt(int ny) {
 // mode, inverse transform along y of each output.  Each column is worked by
 // G groups of tpt threads, one group per field transform, so the transforms
 // of one column run side by side; cpw columns per block.
+// Column-pass arguments at slice j (ring slots follow j).
+template <typename R>
+__device__ __forceinline__ ColArgs<R> col_args(const Lane<R>& L, int j) {
+  const Geo<R>& g = L.g;
+  const size_t spec = (size_t)g.ny * g.nxh;
+  ColArgs<R> a;
+  const int s2 = j & 1, s2m = (j + 1) & 1;                       // J ring: j % 2, (j - 1) % 2
+  const int s3 = j % 3, s3m1 = (j + 2) % 3, s3m2 = (j + 1) % 3;  // B ring: j, j - 1, j - 2
+  for (int q = 0; q < 2; ++q) {
+    a.jr_w[q] = L.jring + (2 * s2 + q) * spec;
+    a.jr_r[q] = L.jring + (2 * s2m + q) * spec;
+    a.b_cur[q] = L.bring + (2 * s3 + q) * spec;
+    a.b_m1[q] = L.bring + (2 * s3m1 + q) * spec;
+    a.b_m2[q] = L.bring + (2 * s3m2 + q) * spec;
+  }
+  a.jz = L.jz;
+  a.ode = L.ode;
+  a.kx2 = L.kx2;
+  a.kdx = L.kdx;
+  a.ky2 = L.ky2;
+  a.kdy = L.kdy;
+  a.inv_n = R(1) / (R)g.nperp;
+  a.n_perp = (R)g.nperp;
+  a.h = L.h;
+  a.kappa2 = L.kappa2;
+  return a;
+}
+
 template <typename R, int MODE>
-__global__ void __launch_bounds__(256) k_col(Geo<R> g, ColArgs<R> a,
-                                             const C2<R>* __restrict__ twy, int cpw) {
+__global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, int j) {
   using S = ColShape<MODE>;
   constexpr int G = S::G;
+  const Lane<R>& L = lanes[blockIdx.z];
+  const Geo<R> g = L.g;
+  if (j >= g.nxi) return;
+  const ColArgs<R> a = col_args(L, j);
+  const C2<R>* __restrict__ twy = L.twy;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* sm = reinterpret_cast<C2<R>*>(smem_raw);
   const int ny = g.ny;
   const int tpt = col_tpt(ny);
   const int per_col = G * tpt;
+  const int cpw = blockDim.x / per_col;
+  if (blockIdx.x * cpw >= g.nxh) return;
   const int c = threadIdx.x / per_col;
   const int r = threadIdx.x - c * per_col;
   const int grp = r / tpt, t = r - grp * tpt;
@@ -308,7 +452,7 @@ __global__ void __launch_bounds__(256) k_col(Geo<R> g, ColArgs<R> a,
   C2<R>* Sx = D + G * ny;                   // G scratch columns
   C2<R>* mine = D + grp * ny;
   for (int y = t; y < ny; y += tpt)
-    mine[y] = (valid && grp < S::NIN) ? a.in[grp][y * g.nxh + kx] : C2<R>{0, 0};
+    mine[y] = (valid && grp < S::NIN) ? L.rowspec[(size_t)grp * g.ny * g.nxh + y * g.nxh + kx] : C2<R>{0, 0};
   __syncthreads();
   fft_lds_inplace<R, false>(mine, Sx + grp * ny, ny, g.lgy, t, tpt, tw);
 
@@ -383,7 +527,7 @@ __global__ void __launch_bounds__(256) k_col(Geo<R> g, ColArgs<R> a,
   __syncthreads();
   fft_lds_inplace<R, true>(mine, Sx + grp * ny, ny, g.lgy, t, tpt, tw);
   if (valid && grp < S::NOUT)
-    for (int y = t; y < ny; y += tpt) a.out[grp][y * g.nxh + kx] = mine[y];
+    for (int y = t; y < ny; y += tpt) L.colout[(size_t)grp * g.ny * g.nxh + y * g.nxh + kx] = mine[y];
 }
 
 // ---------------------------------------------------------- plasma particles
@@ -406,6 +550,34 @@ struct PlasmaArgs {
   const int* prow;    // [ny + 1] first particle of each cell row (state sorted by cell)
   R* ppart;           // partial node rows [ny][4][NC][nx]
 };
+
+template <typename R>
+__device__ __forceinline__ PlasmaArgs<R> plasma_args(const Lane<R>& L, int j) {
+  const Geo<R>& g = L.g;
+  const int64_t plane = (int64_t)g.nxi * g.nperp;
+  PlasmaArgs<R> a;
+  R* const* P = L.pl[plasma_set(j)];
+  a.x = P[0];
+  a.y = P[1];
+  a.ux = P[2];
+  a.uy = P[3];
+  a.np = L.np;
+  a.q = L.q;
+  a.dep0 = L.dep;
+  a.dep1 = L.dep + g.nperp;
+  a.dep2 = L.dep + 2 * g.nperp;
+  const int fs[6] = {F_PSI, F_DXPSI, F_DYPSI, F_BX, F_BY, F_BZ};
+  for (int q = 0; q < 6; ++q) {
+    a.F0[q] = L.fields + fs[q] * plane + (int64_t)j * g.nperp;
+    a.F1[q] = (j >= 1) ? L.fields + fs[q] * plane + (int64_t)(j - 1) * g.nperp : nullptr;
+  }
+  a.psi_m2 = (j >= 2) ? L.fields + F_PSI * plane + (int64_t)(j - 2) * g.nperp : nullptr;
+  a.err = L.err;
+  a.h = L.h;
+  a.prow = L.prow;
+  a.ppart = L.ppart;
+  return a;
+}
 
 // Particle p of block b: the blocks of one XCD take consecutive chunks.
 __device__ __forceinline__ int plasma_index() {
@@ -511,8 +683,12 @@ __device__ __forceinline__ void row_tile_add(const Geo<R>& g, R* tile, int r, in
 //   PL_PRED : predictor push to j+1 and J~_perp at j+1 with 1 + psi~^{j+1},
 //             psi~^{j+1} = 3 psi^j - 3 psi^{j-1} + psi^{j-2}
 template <typename R, int MODE>
-__global__ void __launch_bounds__(512) k_plasma_rows(Geo<R> g, PlasmaArgs<R> a) {
+__global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__ lanes, int j) {
   constexpr int NC = PlasmaNC<MODE>::NC;
+  const Lane<R>& L = lanes[blockIdx.z];
+  const Geo<R> g = L.g;
+  if (j >= g.nxi || (int)blockIdx.x >= g.ny) return;
+  const PlasmaArgs<R> a = plasma_args(L, j);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
   const int r = blockIdx.x;
@@ -591,23 +767,30 @@ __global__ void __launch_bounds__(512) k_plasma_rows(Geo<R> g, PlasmaArgs<R> a) 
 
 // First particle of each cell row from the scanned cell counts (cell c
 // starts at count[c] + bsum[c / 1024]); prow[ny] = np.
-__global__ void k_row_offsets(const int* __restrict__ count, const int* __restrict__ bsum, int nx,
-                              int ny, int np, int* __restrict__ prow) {
+template <typename R>
+__global__ void k_row_offsets(const Lane<R>* __restrict__ lanes, int j) {
+  const Lane<R>& L = lanes[blockIdx.z];
+  if (j >= L.g.nxi) return;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nx = L.g.nx, ny = L.g.ny;
   if (r > ny) return;
   if (r == ny) {
-    prow[r] = np;
+    L.prow[r] = L.np;
   } else {
     const int c = r * nx;
-    prow[r] = count[c] + bsum[c >> 10];
+    L.prow[r] = L.count[c] + L.bsum[c >> 10];
   }
 }
 
 // Final advance: Y^{j+1} with the converged fields, positions wrapped.
 template <typename R>
-__global__ void __launch_bounds__(256) k_push_final(Geo<R> g, PlasmaArgs<R> a) {
+__global__ void __launch_bounds__(256) k_push_final(const Lane<R>* __restrict__ lanes, int j) {
+  const Lane<R>& L = lanes[blockIdx.z];
+  const Geo<R> g = L.g;
+  if (j >= g.nxi) return;
   const int p = plasma_index();
-  if (p >= a.np) return;
+  if (p >= L.np) return;
+  const PlasmaArgs<R> a = plasma_args(L, j);
   R xn, yn, uxn, uyn;
   rk2_push(g, a, a.x[p], a.y[p], a.ux[p], a.uy[p], xn, yn, uxn, uyn);
   a.x[p] = wrap_pos(xn, g.lx, g.inv_lx);
@@ -618,12 +801,29 @@ __global__ void __launch_bounds__(256) k_push_final(Geo<R> g, PlasmaArgs<R> a) {
 
 // Counting sort of the plasma by cell (keeps the particles of a block close
 // together, which is what makes the tiled deposits pay).
+// Sort at slice j (a multiple of QSA_SORT_EVERY): source buffers (the
+// template at j = 0) and destination buffers.
 template <typename R>
-__global__ void __launch_bounds__(256) k_sort_count(Geo<R> g, const R* __restrict__ x,
-                                                    const R* __restrict__ y, int np,
-                                                    int* __restrict__ cell_of, int* __restrict__ count) {
+__device__ __forceinline__ void sort_buffers(const Lane<R>& L, int j, const R* const*& A, R* const*& B) {
+  const int m = j / QSA_SORT_EVERY;
+  A = (m == 0) ? L.tmpl : (const R* const*)L.pl[(m - 1) & 1];
+  B = L.pl[m & 1];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_sort_count(const Lane<R>* __restrict__ lanes, int j) {
+  const Lane<R>& L = lanes[blockIdx.z];
+  const Geo<R> g = L.g;
+  if (j >= g.nxi) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np) return;
+  if (p >= L.np) return;
+  const R* const* A;
+  R* const* B;
+  sort_buffers(L, j, A, B);
+  const R* __restrict__ x = A[0];
+  const R* __restrict__ y = A[1];
+  int* __restrict__ cell_of = L.cell_of;
+  int* __restrict__ count = L.count;
   int i0, l0;
   R fx, fy;
   cell2(g, x[p], y[p], i0, l0, fx, fy);
@@ -634,7 +834,14 @@ __global__ void __launch_bounds__(256) k_sort_count(Geo<R> g, const R* __restric
 
 // Exclusive scan of v[0, n) in blocks of 1024: offsets within the block in
 // place, block totals in bsum[block].
-__global__ void __launch_bounds__(256) k_scan_local(int* __restrict__ v, int n, int* __restrict__ bsum) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_scan_local(const Lane<R>* __restrict__ lanes, int j) {
+  const Lane<R>& L = lanes[blockIdx.z];
+  if (j >= L.g.nxi) return;
+  int* __restrict__ v = L.count;
+  int* __restrict__ bsum = L.bsum;
+  const int n = L.g.nperp;
+  if ((int)blockIdx.x * 1024 >= n) return;
   __shared__ int s[256];
   const int t = threadIdx.x;
   const int base = blockIdx.x * 1024 + t * 4;
@@ -660,7 +867,12 @@ __global__ void __launch_bounds__(256) k_scan_local(int* __restrict__ v, int n, 
 }
 
 // Exclusive scan of the (at most 256) block totals, one block.
-__global__ void __launch_bounds__(256) k_scan_blocks(int* __restrict__ bsum, int nb) {
+template <typename R>
+__global__ void __launch_bounds__(256) k_scan_blocks(const Lane<R>* __restrict__ lanes, int j) {
+  const Lane<R>& L = lanes[blockIdx.z];
+  if (j >= L.g.nxi) return;
+  int* __restrict__ bsum = L.bsum;
+  const int nb = (L.g.nperp + 1023) / 1024;
   __shared__ int s[256];
   const int t = threadIdx.x;
   const int x = (t < nb) ? bsum[t] : 0;
@@ -677,15 +889,25 @@ __global__ void __launch_bounds__(256) k_scan_blocks(int* __restrict__ bsum, int
 
 // cursor[c] + bsum[c / 1024] is the first free slot of cell c.
 template <typename R>
-__global__ void __launch_bounds__(256) k_sort_scatter(int np, const int* __restrict__ cell_of,
-                                                      int* __restrict__ cursor, const int* __restrict__ bsum,
-                                                      const R* __restrict__ x,
-                                                      const R* __restrict__ y, const R* __restrict__ ux,
-                                                      const R* __restrict__ uy, R* __restrict__ x2,
-                                                      R* __restrict__ y2, R* __restrict__ ux2,
-                                                      R* __restrict__ uy2) {
+__global__ void __launch_bounds__(256) k_sort_scatter(const Lane<R>* __restrict__ lanes, int j) {
+  const Lane<R>& L = lanes[blockIdx.z];
+  if (j >= L.g.nxi) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np) return;
+  if (p >= L.np) return;
+  const R* const* A;
+  R* const* B;
+  sort_buffers(L, j, A, B);
+  const int* __restrict__ cell_of = L.cell_of;
+  int* __restrict__ cursor = L.count;
+  const int* __restrict__ bsum = L.bsum;
+  const R* __restrict__ x = A[0];
+  const R* __restrict__ y = A[1];
+  const R* __restrict__ ux = A[2];
+  const R* __restrict__ uy = A[3];
+  R* __restrict__ x2 = B[0];
+  R* __restrict__ y2 = B[1];
+  R* __restrict__ ux2 = B[2];
+  R* __restrict__ uy2 = B[3];
   const int c = cell_of[p];
   const int d = atomicAdd(&cursor[c], 1) + bsum[c >> 10];
   x2[d] = x[p];

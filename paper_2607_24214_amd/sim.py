@@ -164,3 +164,52 @@ class Sim:
             self._check(self.lib.qsa_fields(self.ctx, L.FIELD_IDS[name], xi0, xi1,
                                             C.c_void_p(out.ctypes.data), n, 0))
         return out
+
+
+class Batch:
+    """Several Sims advanced together: their slice loops run as lanes of the
+    same kernel launches (one launch per phase per slice for the batch)."""
+
+    def __init__(self, sims: Sequence[Sim], stream: Optional[torch.cuda.Stream] = None):
+        if not sims:
+            raise ValueError("empty batch")
+        self.lib = L.lib()
+        self.sims = list(sims)
+        n = len(self.sims)
+        nbytes = self.lib.qsa_batch_workspace_bytes(n)
+        dev = self.sims[0].device
+        self.stream = stream or torch.cuda.current_stream(dev)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        ws = (self.workspace.data_ptr() + 255) // 256 * 256
+        arr = (C.c_void_p * n)(*[s.ctx.value for s in self.sims])
+        b = C.c_void_p()
+        st = self.lib.qsa_batch_create(arr, n, C.c_void_p(ws), nbytes,
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(b))
+        if st != L.QSA_OK:
+            raise L.QSAError(st, "qsa_batch_create failed")
+        self.b = b
+
+    def _check(self, st):
+        if st != L.QSA_OK:
+            msg = self.lib.qsa_last_error(self.sims[0].ctx).decode()
+            raise L.QSAError(st, msg)
+
+    def sweep(self):
+        self._check(self.lib.qsa_batch_sweep(self.b))
+
+    def step(self, n: int = 1):
+        self._check(self.lib.qsa_batch_step(self.b, n))
+
+    def sync(self):
+        self._check(self.lib.qsa_batch_sync(self.b))
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.lib.qsa_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -117,3 +117,43 @@ def test_graph_replays_match_eager_fp64():
         err, where = slice_errors(a, b)
         print(f"[graph] replay {step}: max slice difference {err:.3e} at {where}", flush=True)
         assert err <= 1e-12, (step, err, where)
+
+
+def _scan_like(i, nx, ny, nxi, alpha, gamma, dt):
+    return W.Workload(
+        name=f"batch{i}", nx=nx, ny=ny, nxi=nxi, dx=0.1, dy=0.1, dxi=0.1, gamma_b=gamma,
+        species=(W.Species(Z=-1, alpha=alpha, ppc=2, sigma_par=1e-3, sigma_perp=1e-3),),
+        plasma_mx=2, plasma_my=2, plasma_uth=0.005, dt=dt, seed=900 + i)
+
+
+def test_batch_of_uneven_instances_fp64():
+    """Uneven boxes (different nx, ny, nxi, alpha, gamma_b, dt) advanced as one
+    batch: each member matches the same box run alone (1e-12) and the oracle."""
+    import paper_2607_24214_amd as Q
+    wls = [_scan_like(0, 32, 16, 20, 0.02, 50.0, 10.0),
+           _scan_like(1, 16, 32, 12, 0.05, 200.0, 5.0),
+           _scan_like(2, 64, 8, 28, 0.01, 30.0, 20.0)]
+    sims, alone = [], []
+    for wl in wls:
+        plasma, beams = W.plasma_template(wl), W.beam(wl)
+        for lst in (sims, alone):
+            s = Q.Sim(Q.params_from_workload(wl, precision="f64"))
+            s.load_plasma(plasma)
+            s.load_beam(0, beams[0])
+            lst.append(s)
+    batch = Q.Batch(sims)
+    batch.step(1)
+    batch.sweep()
+    batch.sync()
+    for wl, sb, sa in zip(wls, sims, alone):
+        sa.beam_step(1)
+        sa.slice_sweep()
+        got = {k: sb.fields(k) for k in OUT_FIELDS}
+        ref1 = {k: sa.fields(k) for k in OUT_FIELDS}
+        err, where = slice_errors(got, ref1)
+        print(f"[batch] {wl.name}: member vs alone {err:.3e} at {where}", flush=True)
+        assert err <= 1e-12, (wl.name, err, where)
+        so, ref = run_oracle(wl, 1)
+        err, where = slice_errors(got, ref)
+        print(f"[batch] {wl.name}: member vs oracle {err:.3e} at {where}", flush=True)
+        assert err <= 1e-10, (wl.name, err, where)
