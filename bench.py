@@ -6,7 +6,9 @@ A step is one beam step of the 3D workload 256 x 256 x 512 (dx = dy = dxi =
 alpha = 1e-2, gamma_b = 1e3, 8 particles per cell): the beam source deposit,
 the full quasistatic sweep over 512 slices (K = 3 predictor-corrector
 iterations) and the Boris push of all 2.68e8 beam particles.  The metric is
-plasma particle-slice updates per second over whole steps.
+plasma particle-slice updates per second over whole steps.  Beam steps run
+--pipeline at a time in flight (lane k of a group sweeps 8 slices behind lane
+k - 1 in the same launches); the results equal those of one step at a time.
 
 Prints one JSON line (rank 0) with the measured rate, a roofline entry for
 the dominant kernel (timed with HIP events on the library's stream inside
@@ -90,14 +92,15 @@ def cpu_baseline(wl, n_slices: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--pipeline", type=int, default=8, help="beam steps in flight (1 = one at a time)")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--workload", default="cube256")
     ap.add_argument("--cpu-slices", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true",
-                    help="also time every kernel class over one extra step each")
+                    help="also time every kernel class over one extra group of steps each")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -119,7 +122,7 @@ def main():
     plasma = W.plasma_template(wl)
     beams = W.beam(wl)
     log(f"inputs generated in {time.perf_counter() - t:.1f} s")
-    sim = Q.Sim(Q.params_from_workload(wl, precision=args.precision))
+    sim = Q.Sim(Q.params_from_workload(wl, precision=args.precision, pipeline=args.pipeline))
     sim.load_plasma(plasma)
     for s, b in enumerate(beams):
         sim.load_beam(s, b)
@@ -136,12 +139,15 @@ def main():
     if args.breakdown:
         for kc in ("push_pred", "push_final", "dep_S", "dep_J", "row_r2c", "col", "row_c2r",
                    "beam_deposit", "beam_push"):
-            ms, n = timed_step(sim, kc, 1)
-            breakdown[kc] = {"ms_per_step": ms, "launches": n, "us_per_launch": 1e3 * ms / max(n, 1)}
-            log(f"  {kc:13s} {ms:9.2f} ms/step  {n:6d} launches  {1e3 * ms / max(n, 1):8.2f} us/launch")
+            nst = max(1, args.pipeline)
+            ms, n = timed_step(sim, kc, nst)
+            breakdown[kc] = {"ms_per_step": ms / nst, "launches": n, "us_per_launch": 1e3 * ms / max(n, 1)}
+            log(f"  {kc:13s} {ms / nst:9.2f} ms/step  {n:6d} launches  {1e3 * ms / max(n, 1):8.2f} us/launch")
 
     dominant = "push_pred"
-    sim.beam_step(1)          # the step graph is captured here, outside the timed region
+    # the step graphs (a whole group when pipelined) are captured here,
+    # outside the timed region
+    sim.beam_step(max(1, args.pipeline))
     sim.sync()
     # timed region: exactly K steps (graph replays) between synchronizations
     torch.cuda.synchronize()
@@ -149,6 +155,8 @@ def main():
     sim.beam_step(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if sim.pipeline != max(1, args.pipeline):
+        raise RuntimeError(f"pipelining fell back to depth {sim.pipeline}")
     # the dominant kernel's launch duration: HIP events around each of its
     # launches over the same number of steps, enqueued launch by launch
     dom_ms, dom_n = timed_step(sim, dominant, args.steps)
@@ -171,14 +179,19 @@ def main():
     t_sweep = time.perf_counter() - t
 
     avg_s = dom_ms / 1e3 / max(dom_n, 1)
-    achieved = alg_bytes(dominant, wl, rsize) / avg_s / 1e9
+    # one launch advances every step in flight by a slice: algorithmic bytes
+    # per launch = per-slice bytes x lane-slices the launches covered / launches
+    lane_slices = args.steps * wl.nxi * wl.n_corr
+    per_launch = alg_bytes(dominant, wl, rsize) * lane_slices / max(dom_n, 1)
+    achieved = per_launch / avg_s / 1e9
     roofline = {
         "kernel": "k_push<predictor> (plasma RK2 push + predicted J_perp deposit)",
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
         "avg_launch_us": avg_s * 1e6, "launches_timed": dom_n,
         "timing": timing_note,
-        "alg_bytes_per_launch": alg_bytes(dominant, wl, rsize),
+        "alg_bytes_per_launch": per_launch,
+        "slices_per_launch": lane_slices / max(dom_n, 1),
     }
     cpu = None
     if not args.no_cpu_baseline:
@@ -202,6 +215,7 @@ def main():
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nxi": wl.nxi,
                    "dx": wl.dx, "plasma_per_slice": wl.n_plasma, "beam_particles": wl.n_beam_total,
                    "alpha": wl.species[0].alpha, "gamma_b": wl.gamma_b, "n_corr": wl.n_corr,
+                   "steps_in_flight": max(1, args.pipeline),
                    "step": "beam source deposit + 512-slice sweep + Boris beam push"},
         "sweep_only": {"ms": 1e3 * t_sweep, "updates_per_s": wl.n_plasma * wl.nxi / t_sweep},
         "roofline": roofline,

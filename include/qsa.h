@@ -82,6 +82,7 @@ enum {
 };
 
 #define QSA_MAX_SPECIES 4
+#define QSA_MAX_PIPELINE 8
 
 typedef struct {
   int32_t Z;        /* charge number: -1 electron, +1 positron              */
@@ -91,8 +92,8 @@ typedef struct {
 
 /* Problem statement in normalized units (see header comment). */
 typedef struct {
-  int32_t nx, ny;        /* transverse cells, powers of two; nx in [8, 1024],
-                            ny = 1 (slab in x) or ny in [8, 1024]           */
+  int32_t nx, ny;        /* transverse cells, powers of two; nx in [8, 512],
+                            ny = 1 (slab in x) or ny in [8, 512]            */
   int32_t nxi;           /* xi slices (>= 2); the head of the box is xi = 0  */
   int32_t precision;     /* QSA_FP64 or QSA_FP32                             */
   double dx, dy, dxi;    /* cell sizes in c/omega_p (dy is the slab depth)   */
@@ -104,6 +105,11 @@ typedef struct {
   double plasma_w;       /* their common weight: area per particle (> 0)     */
   qsa_species species[QSA_MAX_SPECIES];
   int64_t beam_capacity[QSA_MAX_SPECIES]; /* max particles per species (>= 0) */
+  int32_t pipeline;      /* beam steps in flight in qsa_beam_step, 0..8 (0 and 1:
+                            one step at a time).  With P > 1 the workspace holds
+                            P working sets (sources, fields, plasma state) and a
+                            copy of the beam; see qsa_beam_step.             */
+  int32_t reserved_;     /* must be 0                                        */
 } qsa_params;
 
 /* Bytes of device workspace a context with these parameters needs; 0 if the
@@ -129,7 +135,10 @@ qsa_status qsa_load_plasma(qsa_ctx* c, const double* x, const double* y,
 /* Load n (<= capacity) particles of beam species s: position (x, y, xi),
  * momentum (u_x, u_y, u_z) and weight w (number of physical particles per
  * unit n_p, i.e. alpha dV/ppc for a uniform beam).  A particle with w = 0 is
- * inert.  Float64 arrays, host (synchronizing) or device memory. */
+ * inert.  Float64 arrays, host (synchronizing) or device memory.  Any order;
+ * with pipeline > 1 the library keeps the particles sorted by cell row
+ * internally (each group of steps starts with that sort), and qsa_read_beam
+ * still returns them in the order they were loaded. */
 qsa_status qsa_load_beam(qsa_ctx* c, int32_t s, const double* x,
                          const double* y, const double* xi, const double* ux,
                          const double* uy, const double* uz, const double* w,
@@ -146,7 +155,20 @@ qsa_status qsa_read_beam(qsa_ctx* c, int32_t s, double* x, double* y,
  * tail.  Fields of every slice are kept until the next sweep. */
 qsa_status qsa_slice_sweep(qsa_ctx* c);
 
-/* n_steps x (qsa_slice_sweep; Boris push of every beam species by dt). */
+/* n_steps x (qsa_slice_sweep; Boris push of every beam species by dt).
+ *
+ * With pipeline = P > 1 the steps run in groups of up to P steps in flight:
+ * step n0 + k sweeps QSA_PIPE_LAG = 8 slices behind step n0 + k - 1 in the
+ * same kernel launches.  This relies on the beam drifting only backwards in
+ * xi by less than a few cells per step: each beam particle is pushed by step
+ * n0 + k as soon as that step has finished the slices around the cell row it
+ * was loaded in, and deposited for step n0 + k + 1 right away.  The results
+ * are those of one step at a time (up to the order of floating-point
+ * additions).  If a particle has moved too far from the cell row it was
+ * loaded in, the group is detected on the device, the beam is restored from
+ * the copy taken at the group's start, the group is repeated one step at a
+ * time and pipelining stays off until the next qsa_load_beam.  Pipelined
+ * calls synchronize once per group (to read that flag). */
 qsa_status qsa_beam_step(qsa_ctx* c, int32_t n_steps);
 
 /* Copy slices [xi0, xi1) of one field of the last sweep as float64 into dst
@@ -183,14 +205,22 @@ qsa_status qsa_timing_begin(qsa_ctx* c, int32_t kernel_class);
  * launches, *launches = their count. */
 qsa_status qsa_timing_end(qsa_ctx* c, double* total_ms, int64_t* launches);
 
-/* Options for qsa_set_option. */
+/* Options for qsa_set_option / qsa_get_option. */
 enum {
-  QSA_OPT_GRAPHS = 0     /* 1 (default): replay a captured HIP graph of the sweep
+  QSA_OPT_GRAPHS = 0,    /* 1 (default): replay a captured HIP graph of the sweep
                             and of the beam step; 0: enqueue every launch   */
+  QSA_OPT_PIPELINE = 1   /* beam steps in flight in qsa_beam_step: set 1..P
+                            (values above the parameter's pipeline = P are
+                            clamped to P; setting also re-enables pipelining
+                            after a drift fallback); get: the depth in use,
+                            1 when pipelining is off                        */
 };
 
 /* Set a context option (see QSA_OPT_*). */
 qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value);
+
+/* Read a context option (see QSA_OPT_*) into *value. */
+qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent boxes (a growth-rate parameter scan: different

@@ -31,15 +31,29 @@ int ilog2(int v) {
   return l;
 }
 
+// Byte offsets of one sweep's working set: plasma state, sources, fields and
+// the spectral rings.  Set 0 is the only set without pipelining; with beam
+// steps in flight, lane k of a group works in set k.
+struct SetLayout {
+  size_t pl[4], pl2[4];
+  size_t cell_of, count, bsum, prow, ppart;
+  size_t src, fields, dep, rowspec, colout, jring, jz, bring, ode;
+  size_t ring;   // slab ring of the deposits this set receives from the lane before it
+};
+
 // Byte offsets of every device array inside the workspace.
 struct Layout {
   size_t twx, twy, kx2, kdx, ky2, kdy;
-  size_t tmpl[4], pl[4], pl2[4];
-  size_t cell_of, count, bsum, prow, ppart;
-  size_t rowoff[QSA_MAX_SPECIES], scan64, bpart, strays, ctl;
-  int64_t stray_cap;
-  size_t beam[QSA_MAX_SPECIES][7];  // x, y, ux, uy, uz, w (real), xi (double)
-  size_t src, fields, dep, rowspec, colout, jring, jz, bring, ode, err, emit, lane;
+  size_t tmpl[4];
+  int nset;                         // working sets (beam steps in flight)
+  SetLayout set[QSA_MAX_PIPELINE];
+  size_t rowoff[QSA_MAX_SPECIES];   // slab partition of the sorted beam (pipelining)
+  size_t doff[QSA_MAX_SPECIES];     // row offsets into perm of the current deposit
+  size_t key[QSA_MAX_SPECIES], perm[QSA_MAX_SPECIES];
+  size_t cursor, scan64, bpart;
+  size_t beam[QSA_MAX_SPECIES][8];  // x, y, ux, uy, uz, w (real), xi (double), id (int64, pipelining)
+  size_t snap[QSA_MAX_SPECIES][8];  // sort target and the beam at the start of a pipelined group
+  size_t err, emit, lane, pipe;
   size_t total;
 };
 
@@ -52,6 +66,8 @@ struct Carver {
   }
 };
 
+int pipeline_depth(const qsa_params& p) { return std::max(1, (int)p.pipeline); }
+
 Layout make_layout(const qsa_params& p) {
   const size_t rs = (p.precision == QSA_FP32) ? 4 : 8;
   const size_t cs = 2 * rs;
@@ -59,6 +75,7 @@ Layout make_layout(const qsa_params& p) {
   const size_t nxh = (size_t)p.nx / 2 + 1;
   const size_t spec = (size_t)p.ny * nxh * cs;
   Layout L;
+  std::memset(&L, 0, sizeof(L));
   Carver c;
   L.twx = c.take(p.nx * cs);
   L.twy = c.take(p.ny * cs);
@@ -67,41 +84,54 @@ Layout make_layout(const qsa_params& p) {
   L.ky2 = c.take(p.ny * rs);
   L.kdy = c.take(p.ny * rs);
   for (int i = 0; i < 4; ++i) L.tmpl[i] = c.take(p.n_plasma * rs);
-  for (int i = 0; i < 4; ++i) L.pl[i] = c.take(p.n_plasma * rs);
-  for (int i = 0; i < 4; ++i) L.pl2[i] = c.take(p.n_plasma * rs);
-  L.cell_of = c.take(p.n_plasma * sizeof(int));
-  L.count = c.take(nperp * sizeof(int));
-  L.bsum = c.take(256 * sizeof(int));
-  L.prow = c.take((p.ny + 1) * sizeof(int));
-  L.ppart = c.take((size_t)p.ny * 4 * 3 * p.nx * rs);
-  const size_t nrows = (size_t)p.nxi * p.ny;
-  int64_t total = 0;
-  for (int s = 0; s < QSA_MAX_SPECIES; ++s) {
-    L.rowoff[s] = c.take((nrows + 2) * sizeof(int64_t));
-    if (s < p.n_species) total += p.beam_capacity[s];
+  L.nset = pipeline_depth(p);
+  for (int k = 0; k < L.nset; ++k) {
+    SetLayout& S = L.set[k];
+    for (int i = 0; i < 4; ++i) S.pl[i] = c.take(p.n_plasma * rs);
+    for (int i = 0; i < 4; ++i) S.pl2[i] = c.take(p.n_plasma * rs);
+    S.cell_of = c.take(p.n_plasma * sizeof(int));
+    S.count = c.take(nperp * sizeof(int));
+    S.bsum = c.take(256 * sizeof(int));
+    S.prow = c.take((p.ny + 1) * sizeof(int));
+    S.ppart = c.take((size_t)p.ny * 4 * 3 * p.nx * rs);
+    S.src = c.take(4 * (size_t)p.nxi * nperp * rs);
+    S.fields = c.take((size_t)N_STORED * p.nxi * nperp * rs);
+    S.dep = c.take(3 * nperp * rs);
+    S.rowspec = c.take(4 * spec);
+    S.colout = c.take(4 * spec);
+    S.jring = c.take(4 * spec);
+    S.jz = c.take(spec);
+    S.bring = c.take(6 * spec);
+    S.ode = c.take(2 * sizeof(double));
+    // two slabs x ny cell rows x (2 node slices x 2 node rows x 4 sources x nx)
+    S.ring = (k > 0) ? c.take(2 * (size_t)p.ny * 2 * 2 * 4 * p.nx * rs) : 0;
   }
+  const size_t nrows = (size_t)p.nxi * p.ny;
+  for (int s = 0; s < QSA_MAX_SPECIES; ++s) {
+    const size_t cap = (s < p.n_species) ? (size_t)p.beam_capacity[s] : 0;
+    L.rowoff[s] = c.take((nrows + 2) * sizeof(int64_t));
+    L.doff[s] = c.take((nrows + 2) * sizeof(int64_t));
+    L.key[s] = c.take(cap * sizeof(int));
+    L.perm[s] = c.take(cap * sizeof(int));
+  }
+  L.cursor = c.take((nrows + 2) * sizeof(int64_t));
   L.scan64 = c.take(((nrows + 2) / 1024 + 8) * 2 * sizeof(int64_t));
-  L.bpart = c.take(nrows * 2 * 4 * 4 * (size_t)p.nx * rs);   // up to 4 node rows per block
-  L.stray_cap = std::min<int64_t>(total, std::max<int64_t>((int64_t)1 << 20, total / 8));
-  L.strays = c.take((size_t)std::max<int64_t>(L.stray_cap, 1) * sizeof(int64_t));
-  L.ctl = c.take(4 * sizeof(int));
+  L.bpart = c.take(nrows * 2 * 2 * 4 * (size_t)p.nx * rs);
   for (int s = 0; s < QSA_MAX_SPECIES; ++s) {
     const size_t cap = (s < p.n_species) ? (size_t)p.beam_capacity[s] : 0;
     for (int k = 0; k < 6; ++k) L.beam[s][k] = c.take(cap * rs);
     L.beam[s][6] = c.take(cap * 8);
+    if (L.nset > 1) {
+      L.beam[s][7] = c.take(cap * 8);
+      for (int k = 0; k < 6; ++k) L.snap[s][k] = c.take(cap * rs);
+      L.snap[s][6] = c.take(cap * 8);
+      L.snap[s][7] = c.take(cap * 8);
+    }
   }
-  L.src = c.take(4 * (size_t)p.nxi * nperp * rs);
-  L.fields = c.take((size_t)N_STORED * p.nxi * nperp * rs);
-  L.dep = c.take(3 * nperp * rs);
-  L.rowspec = c.take(4 * spec);
-  L.colout = c.take(4 * spec);
-  L.jring = c.take(4 * spec);
-  L.jz = c.take(spec);
-  L.bring = c.take(6 * spec);
-  L.ode = c.take(2 * sizeof(double));
   L.err = c.take(sizeof(int));
   L.emit = c.take(nperp * sizeof(double));
-  L.lane = c.take(sizeof(Lane<double>));
+  L.lane = c.take(L.nset * sizeof(Lane<double>));
+  L.pipe = c.take(L.nset * sizeof(PipeBeam<double>));
   L.total = c.off;
   return L;
 }
@@ -120,8 +150,11 @@ const char* validate(const qsa_params* p) {
   if (p->n_plasma <= 0 || p->n_plasma > (int64_t)1 << 30) return "n_plasma must be in [1, 2^30]";
   if (!(p->plasma_w > 0)) return "plasma_w must be > 0";
   if (p->n_species < 1 || p->n_species > QSA_MAX_SPECIES) return "n_species must be in [1, 4]";
+  if ((int64_t)p->nxi * p->ny > ((int64_t)1 << 30)) return "nxi * ny must be <= 2^30";
+  if (p->pipeline < 0 || p->pipeline > QSA_MAX_PIPELINE) return "pipeline must be in [0, 8]";
+  if (p->reserved_ != 0) return "reserved_ must be 0";
   for (int s = 0; s < p->n_species; ++s) {
-    if (p->beam_capacity[s] < 0) return "beam capacity must be >= 0";
+    if (p->beam_capacity[s] < 0 || p->beam_capacity[s] > INT32_MAX) return "beam capacity must be in [0, 2^31)";
     if (!(p->species[s].M > 0)) return "species mass must be > 0";
   }
   return nullptr;
@@ -137,8 +170,11 @@ struct qsa_ctx {
   hipStream_t stream = nullptr;   // the library's work stream (ordered after `user` per call)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipGraphExec_t gx_step = nullptr, gx_sweep = nullptr;   // captured beam step / sweep
+  hipGraphExec_t gx_group[QSA_MAX_PIPELINE + 1] = {};     // captured pipelined groups by size
   bool use_graphs = true;
-  int bnl = 2;   // node rows per beam partial block along y (4 = one margin row each side)
+  bool pipe_ok = true;   // off after a drift violation, until the next beam load
+  int pipe_max = 1;      // beam steps in flight when pipelining (<= L.nset)
+  int cur_set = 0;       // working set holding the last sweep's sources and fields
   int64_t beam_n[QSA_MAX_SPECIES] = {0, 0, 0, 0};
   bool plasma_loaded = false;
   bool swept = false;
@@ -174,6 +210,10 @@ struct qsa_ctx {
     if (gx_step) (void)hipGraphExecDestroy(gx_step);
     if (gx_sweep) (void)hipGraphExecDestroy(gx_sweep);
     gx_step = gx_sweep = nullptr;
+    for (hipGraphExec_t& g : gx_group) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
   }
   ~qsa_ctx() {
     drop_graphs();
@@ -310,15 +350,13 @@ struct Engine {
       a.uz[s] = c->at<R>(c->L.beam[s][4]);
       a.w[s] = c->at<R>(c->L.beam[s][5]);
       a.xi[s] = c->at<double>(c->L.beam[s][6]);
-      a.rowoff[s] = c->at<int64_t>(c->L.rowoff[s]);
+      a.key[s] = c->at<int>(c->L.key[s]);
+      a.perm[s] = c->at<int>(c->L.perm[s]);
+      a.doff[s] = c->at<int64_t>(c->L.doff[s]);
       a.zq[s] = (R)(p.species[s].Z / (p.dx * p.dy * p.dxi));
     }
     a.bpart = c->at<R>(c->L.bpart);
-    a.strays = c->at<int64_t>(c->L.strays);
-    a.stray_cap = c->L.stray_cap;
-    a.ctl = c->at<int>(c->L.ctl);
     a.inv_dxi = 1.0 / p.dxi;
-    a.nl = c->bnl;
     return a;
   }
 
@@ -337,38 +375,99 @@ struct Engine {
     return QSA_OK;
   }
 
-  // Cell-row offsets of beam species s (after a load).
-  static qsa_status beam_rows(qsa_ctx* c, int s) {
+  // Cell-row keys of species s and their exclusive row offsets in doff[s];
+  // cursor <- doff[s].
+  static qsa_status keys(qsa_ctx* c, int s) {
     const qsa_params& p = c->p;
     const Geo<R> g = geo(p);
     const int64_t nrows = (int64_t)p.nxi * p.ny;
-    int64_t* off = c->at<int64_t>(c->L.rowoff[s]);
-    hipLaunchKernelGGL(k_fill<int64_t>, dim3(fill_blocks(nrows + 2)), dim3(256), 0, c->stream, off,
-                       nrows + 2, (int64_t)0);
+    int64_t* off = c->at<int64_t>(c->L.doff[s]);
+    hipLaunchKernelGGL(k_fill<int64_t>, dim3(fill_blocks(nrows + 2)), dim3(256), 0, c->stream, off, nrows + 2,
+                       (int64_t)0);
     const int64_t n = c->beam_n[s];
-    if (n > 0) {
-      BeamDepArgs<R> a = beam_dep_args(c);
-      hipLaunchKernelGGL(k_beam_rowcount<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
-                         a, s, n, off);
-    }
+    if (n > 0)
+      hipLaunchKernelGGL(k_beam_keys<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
+                         beam_dep_args(c), s, n, off);
     HIP_OK(hipGetLastError());
-    return scan64(c, off, nrows + 2, c->at<int64_t>(c->L.scan64));
+    qsa_status st = scan64(c, off, nrows + 2, c->at<int64_t>(c->L.scan64));
+    if (st != QSA_OK) return st;
+    HIP_OK(hipMemcpyAsync(c->ws + c->L.cursor, off, (nrows + 2) * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                          c->stream));
+    return QSA_OK;
   }
 
-  // Beam sources as block-private partial rows (+ atomics for strays).
+  // Reorder the particles of species s by cell row (pipelining only): the
+  // slab partition rowoff[s] then holds every slab's index range.
+  static qsa_status sort_species(qsa_ctx* c, int s) {
+    const qsa_params& p = c->p;
+    const Layout& L = c->L;
+    const int64_t nrows = (int64_t)p.nxi * p.ny;
+    const int64_t n = c->beam_n[s];
+    qsa_status st = keys(c, s);
+    if (st != QSA_OK) return st;
+    HIP_OK(hipMemcpyAsync(c->ws + L.rowoff[s], c->ws + L.doff[s], (nrows + 2) * sizeof(int64_t),
+                          hipMemcpyDeviceToDevice, c->stream));
+    if (n == 0) return QSA_OK;
+    BeamMove<R> m;
+    for (int k = 0; k < 6; ++k) {
+      m.src[k] = c->at<R>(L.beam[s][k]);
+      m.dst[k] = c->at<R>(L.snap[s][k]);
+    }
+    m.sxi = c->at<double>(L.beam[s][6]);
+    m.dxi = c->at<double>(L.snap[s][6]);
+    m.sid = c->at<int64_t>(L.beam[s][7]);
+    m.did = c->at<int64_t>(L.snap[s][7]);
+    m.key = c->at<int>(L.key[s]);
+    m.cur = c->at<int64_t>(L.cursor);
+    m.n = n;
+    hipLaunchKernelGGL(k_beam_sort<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, m);
+    HIP_OK(hipGetLastError());
+    for (int k = 0; k < 8; ++k)
+      HIP_OK(hipMemcpyAsync(c->ws + L.beam[s][k], c->ws + L.snap[s][k], (size_t)n * (k < 6 ? sizeof(R) : 8),
+                            hipMemcpyDeviceToDevice, c->stream));
+    return QSA_OK;
+  }
+
+  // After a load: identities, and the sort by cell row when pipelining.
+  static qsa_status loaded(qsa_ctx* c, int s) {
+    if (c->L.nset < 2) return QSA_OK;
+    const int64_t n = c->beam_n[s];
+    if (n > 0) {
+      hipLaunchKernelGGL(k_iota64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                         c->at<int64_t>(c->L.beam[s][7]), n);
+      HIP_OK(hipGetLastError());
+    }
+    return sort_species(c, s);
+  }
+
+  static qsa_status sort_all(qsa_ctx* c) {
+    for (int s = 0; s < c->p.n_species; ++s) {
+      const qsa_status st = sort_species(c, s);
+      if (st != QSA_OK) return st;
+    }
+    return QSA_OK;
+  }
+
+  // Beam sources: particles grouped by cell row, each row deposited by one
+  // block into its partial node rows, then reduced to dense sources.
   static qsa_status beam_deposit_all(qsa_ctx* c, const Geo<R>& g) {
     const qsa_params& p = c->p;
-    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, c->stream, c->at<int>(c->L.ctl), (int64_t)4, 0);
-    BeamDepArgs<R> a = beam_dep_args(c);
+    for (int s = 0; s < p.n_species; ++s) {
+      qsa_status st = keys(c, s);
+      if (st != QSA_OK) return st;
+      const int64_t n = c->beam_n[s];
+      if (n > 0)
+        hipLaunchKernelGGL(k_beam_perm<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                           beam_dep_args(c), s, n, c->at<int64_t>(c->L.cursor));
+    }
+    const BeamDepArgs<R> a = beam_dep_args(c);
     const int nrows = p.nxi * p.ny;
     c->tstart(QSA_K_BEAM_DEPOSIT);
-    hipLaunchKernelGGL(k_beam_rows<R>, dim3(nrows), dim3(256), 2 * a.nl * 4 * g.nx * sizeof(R), c->stream, g,
-                       a);
+    hipLaunchKernelGGL(k_beam_rows<R>, dim3(nrows), dim3(256), 2 * 2 * 4 * g.nx * sizeof(R), c->stream, g, a);
     c->tstop(QSA_K_BEAM_DEPOSIT);
-    hipLaunchKernelGGL(k_beam_strays<R>, dim3(std::min(nrows, 2048)), dim3(256), 0, c->stream, g, a);
     const int64_t plane = (int64_t)p.nxi * g.nperp;
     hipLaunchKernelGGL(k_beam_reduce<R>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, c->stream, g,
-                       (const R*)a.bpart, a.nl, c->at<R>(c->L.src));
+                       (const R*)a.bpart, c->at<R>(c->L.set[0].src));
     HIP_OK(hipGetLastError());
     return QSA_OK;
   }
@@ -384,7 +483,7 @@ struct Engine {
     a.w = c->at<R>(c->L.beam[s][5]);
     a.xi = c->at<double>(c->L.beam[s][6]);
     a.n = c->beam_n[s];
-    a.fields = c->at<R>(c->L.fields);
+    a.fields = c->at<R>(c->L.set[0].fields);
     a.zq = (R)(p.species[s].Z / (p.dx * p.dy * p.dxi));
     a.qmh = (R)((double)p.species[s].Z / p.species[s].M * 0.5 * p.dt);
     a.dt = (R)p.dt;
@@ -394,23 +493,26 @@ struct Engine {
   }
 
   // ---- lanes ---------------------------------------------------------------
-  // Device-pointer descriptor of this context's box for the per-slice kernels.
-  static Lane<R> make_lane(qsa_ctx* c) {
+  // Device-pointer descriptor of this context's box for the per-slice kernels,
+  // working in set k with a lag of k * QSA_PIPE_LAG slices.
+  static Lane<R> make_lane(qsa_ctx* c, int k = 0) {
     const qsa_params& p = c->p;
     const Layout& L = c->L;
+    const SetLayout& S = L.set[k];
     Lane<R> a;
     std::memset(&a, 0, sizeof(a));
     a.g = geo(p);
+    a.lag = k * QSA_PIPE_LAG;
     a.np = (int)p.n_plasma;
     a.q = (R)(-p.plasma_w / (p.dx * p.dy));
     a.h = (R)p.dxi;
     a.kappa2 = (R)p.kappa2;
-    a.fields = c->at<R>(L.fields);
-    a.src = c->at<R>(L.src);
+    a.fields = c->at<R>(S.fields);
+    a.src = c->at<R>(S.src);
     for (int i = 0; i < 4; ++i) {
       a.tmpl[i] = c->at<R>(L.tmpl[i]);
-      a.pl[0][i] = c->at<R>(L.pl[i]);
-      a.pl[1][i] = c->at<R>(L.pl2[i]);
+      a.pl[0][i] = c->at<R>(S.pl[i]);
+      a.pl[1][i] = c->at<R>(S.pl2[i]);
     }
     a.twx = c->at<C2<R>>(L.twx);
     a.twy = c->at<C2<R>>(L.twy);
@@ -419,18 +521,53 @@ struct Engine {
     a.ky2 = c->at<R>(L.ky2);
     a.kdy = c->at<R>(L.kdy);
     a.err = c->at<int>(L.err);
-    a.cell_of = c->at<int>(L.cell_of);
-    a.count = c->at<int>(L.count);
-    a.bsum = c->at<int>(L.bsum);
-    a.prow = c->at<int>(L.prow);
-    a.ppart = c->at<R>(L.ppart);
-    a.dep = c->at<R>(L.dep);
-    a.rowspec = c->at<C2<R>>(L.rowspec);
-    a.colout = c->at<C2<R>>(L.colout);
-    a.jring = c->at<C2<R>>(L.jring);
-    a.jz = c->at<C2<R>>(L.jz);
-    a.bring = c->at<C2<R>>(L.bring);
-    a.ode = c->at<double>(L.ode);
+    a.cell_of = c->at<int>(S.cell_of);
+    a.count = c->at<int>(S.count);
+    a.bsum = c->at<int>(S.bsum);
+    a.prow = c->at<int>(S.prow);
+    a.ppart = c->at<R>(S.ppart);
+    a.dep = c->at<R>(S.dep);
+    a.rowspec = c->at<C2<R>>(S.rowspec);
+    a.colout = c->at<C2<R>>(S.colout);
+    a.jring = c->at<C2<R>>(S.jring);
+    a.jz = c->at<C2<R>>(S.jz);
+    a.bring = c->at<C2<R>>(S.bring);
+    a.ode = c->at<double>(S.ode);
+    return a;
+  }
+
+  // Beam push and hand-over of lane k of a pipelined group.
+  static PipeBeam<R> make_pipe(qsa_ctx* c, int k) {
+    const qsa_params& p = c->p;
+    const Layout& L = c->L;
+    PipeBeam<R> a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = geo(p);
+    a.lag = k * QSA_PIPE_LAG;
+    a.ns = p.n_species;
+    a.dy = (p.ny == 1) ? 0 : QSA_PIPE_DY;
+    for (int s = 0; s < p.n_species; ++s) {
+      a.x[s] = c->at<R>(L.beam[s][0]);
+      a.y[s] = c->at<R>(L.beam[s][1]);
+      a.ux[s] = c->at<R>(L.beam[s][2]);
+      a.uy[s] = c->at<R>(L.beam[s][3]);
+      a.uz[s] = c->at<R>(L.beam[s][4]);
+      a.w[s] = c->at<R>(L.beam[s][5]);
+      a.xi[s] = c->at<double>(L.beam[s][6]);
+      a.rowoff[s] = c->at<int64_t>(L.rowoff[s]);
+      a.tag[s] = c->at<int>(L.key[s]);
+      a.qmh[s] = (R)((double)p.species[s].Z / p.species[s].M * 0.5 * p.dt);
+      a.zq[s] = (R)(p.species[s].Z / (p.dx * p.dy * p.dxi));
+    }
+    a.dt = (R)p.dt;
+    a.inv_dxi = 1.0 / p.dxi;
+    a.xi_max = (double)(p.nxi - 1) * p.dxi;
+    a.fields = c->at<R>(L.set[k].fields);
+    if (k + 1 < L.nset) {
+      a.ring_next = c->at<R>(L.set[k + 1].ring);
+      a.src_next = c->at<R>(L.set[k + 1].src);
+    }
+    a.err = c->at<int>(L.err);
     return a;
   }
 
@@ -475,19 +612,17 @@ struct Engine {
     }
   }
 
-  // The slice loop of every lane: one launch per phase per slice, blockIdx.z
-  // = lane.  `tc` receives the kernel-class timing marks.
-  static qsa_status slices(qsa_ctx* tc, hipStream_t st, const Lane<R>* lanes, const Dims& d) {
+  // One tick of the slice loops of every lane: one launch per phase, blockIdx.z
+  // = lane, lane l working on slice t - lag(l).  `tc` receives the
+  // kernel-class timing marks.
+  static qsa_status tick(qsa_ctx* tc, hipStream_t st, const Lane<R>* lanes, const Dims& d, int t) {
     const int n = d.n;
     const int pb = (d.np + 255) / 256;
     const size_t smem_rows = ((size_t)d.nx + 8 * (size_t)d.rt_rows) * sizeof(C2<R>);
     int nt = (d.per_row + 63) / 64 * 64;
     nt = std::max(64, std::min(256, nt));
+    const int j = t;   // every lag is a multiple of QSA_SORT_EVERY
     {
-      const int blocks = (int)std::min<int64_t>(1024, (d.clear + 255) / 256);
-      hipLaunchKernelGGL((k_lane_clear<R, 0>), dim3(blocks, 1, n), dim3(256), 0, st, lanes, 0);
-    }
-    for (int j = 0; j < d.nxi; ++j) {
       if (j % QSA_SORT_EVERY == 0) {
         hipLaunchKernelGGL((k_lane_clear<R, 1>), dim3((d.nx * d.ny + 255) / 256, 1, n), dim3(256), 0, st, lanes,
                            j);
@@ -554,6 +689,21 @@ struct Engine {
     return QSA_OK;
   }
 
+  static void clear_lanes(hipStream_t st, const Lane<R>* lanes, const Dims& d, int t) {
+    const int blocks = (int)std::min<int64_t>(1024, (d.clear + 255) / 256);
+    hipLaunchKernelGGL((k_lane_clear<R, 0>), dim3(blocks, 1, d.n), dim3(256), 0, st, lanes, t);
+  }
+
+  // The slice loop of every lane (all with lag 0).
+  static qsa_status slices(qsa_ctx* tc, hipStream_t st, const Lane<R>* lanes, const Dims& d) {
+    clear_lanes(st, lanes, d, 0);
+    for (int t = 0; t < d.nxi; ++t) {
+      const qsa_status s = tick(tc, st, lanes, d, t);
+      if (s != QSA_OK) return s;
+    }
+    return QSA_OK;
+  }
+
   static Dims dims_of(qsa_ctx* c) {
     Dims d;
     add_dims(d, c->p);
@@ -583,6 +733,65 @@ struct Engine {
       c->tstop(QSA_K_BEAM_PUSH);
     }
     HIP_OK(hipGetLastError());
+    return QSA_OK;
+  }
+
+  // n beam steps in flight (n <= nset): lane k sweeps step n0 + k in set k,
+  // QSA_PIPE_LAG slices behind lane k - 1, pushes each beam slab as soon as
+  // its fields are final there and deposits it as lane k + 1's sources.
+  static qsa_status group(qsa_ctx* c, int n) {
+    const qsa_params& p = c->p;
+    const Layout& L = c->L;
+    const Geo<R> g = geo(p);
+    // the beam sorted by cell row; the sort buffer keeps a copy of it
+    qsa_status st = sort_all(c);
+    if (st != QSA_OK) return st;
+    if ((st = beam_deposit_all(c, g)) != QSA_OK) return st;   // lane 0's sources
+    for (int k = 1; k < n; ++k)
+      if ((st = fill(c, c->at<R>(L.set[k].src), 4 * (int64_t)p.nxi * g.nperp, R(0))) != QSA_OK) return st;
+    Dims d = dims_of(c);
+    d.n = n;
+    const Lane<R>* lanes = c->at<Lane<R>>(L.lane);
+    const PipeBeam<R>* pipes = c->at<PipeBeam<R>>(L.pipe);
+    const size_t tile = (size_t)2 * 2 * 4 * g.nx * sizeof(R);
+    const int nperp_blocks = (g.nperp + 255) / 256;
+    const int T = p.nxi + 2 + (n - 1) * QSA_PIPE_LAG;
+    for (int t = 0; t < T; ++t) {
+      if (t % QSA_PIPE_LAG == 0 && t < n * QSA_PIPE_LAG) clear_lanes(c->stream, lanes, d, t);
+      if ((st = tick(c, c->stream, lanes, d, t)) != QSA_OK) return st;
+      if (t < QSA_PUSH_LAG) continue;
+      c->tstart(QSA_K_BEAM_PUSH);
+      hipLaunchKernelGGL(k_pipe_push<R>, dim3(g.ny, 1, n), dim3(256), 0, c->stream, pipes, t, n);
+      c->tstop(QSA_K_BEAM_PUSH);
+      c->tstart(QSA_K_BEAM_DEPOSIT);
+      hipLaunchKernelGGL(k_pipe_deposit<R>, dim3(g.ny, 1, n - 1), dim3(256), tile, c->stream, pipes, t, n);
+      hipLaunchKernelGGL(k_pipe_reduce<R>, dim3(nperp_blocks, 1, n - 1), dim3(256), 0, c->stream, pipes, t, n);
+      c->tstop(QSA_K_BEAM_DEPOSIT);
+    }
+    HIP_OK(hipGetLastError());
+    c->swept = true;
+    return QSA_OK;
+  }
+
+  // Copy every beam array (with identities) of every species.
+  static qsa_status copy_beam(qsa_ctx* c, const size_t (&dst)[QSA_MAX_SPECIES][8],
+                              const size_t (&src)[QSA_MAX_SPECIES][8]) {
+    for (int s = 0; s < c->p.n_species; ++s) {
+      const int64_t m = c->beam_n[s];
+      for (int k = 0; k < 8 && m > 0; ++k)
+        HIP_OK(hipMemcpyAsync(c->ws + dst[s][k], c->ws + src[s][k], (size_t)m * (k < 6 ? sizeof(R) : 8),
+                              hipMemcpyDeviceToDevice, c->stream));
+    }
+    return QSA_OK;
+  }
+
+  // Put back the beam of the group's start, with clear device flags.
+  static qsa_status restore(qsa_ctx* c) {
+    qsa_status st = copy_beam(c, c->L.beam, c->L.snap);
+    if (st != QSA_OK) return st;
+    hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, c->stream, c->at<int>(c->L.err), (int64_t)1, 0);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(c->stream));
     return QSA_OK;
   }
 
@@ -642,11 +851,35 @@ struct Engine {
     return QSA_OK;
   }
 
+  // Beam array k of species s in load order (the pipelined path keeps the
+  // particles sorted by cell row, with their load index): scattered by
+  // identity straight into a device destination, or through the sort buffer
+  // for a host one.
+  static qsa_status read_beam_array(qsa_ctx* c, int s, int k, double* dst, int64_t n, int on_device) {
+    if (c->L.nset < 2) return download(c, c->ws + c->L.beam[s][k], dst, n, on_device, k == 6);
+    if (n == 0) return QSA_OK;
+    double* out = on_device ? dst : c->at<double>(c->L.snap[s][6]);
+    const int64_t* id = c->at<int64_t>(c->L.beam[s][7]);
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (k == 6)
+      hipLaunchKernelGGL(k_unpermute<double>, grid, dim3(256), 0, c->stream, c->at<double>(c->L.beam[s][6]), id,
+                         out, n);
+    else
+      hipLaunchKernelGGL(k_unpermute<R>, grid, dim3(256), 0, c->stream, c->at<R>(c->L.beam[s][k]), id, out, n);
+    HIP_OK(hipGetLastError());
+    if (!on_device) {
+      HIP_OK(hipMemcpyAsync(dst, out, n * 8, hipMemcpyDeviceToHost, c->stream));
+      HIP_OK(hipStreamSynchronize(c->stream));
+    }
+    return QSA_OK;
+  }
+
   static qsa_status fields(qsa_ctx* c, int field, int xi0, int xi1, double* dst, int on_device) {
     const qsa_params& p = c->p;
     const int64_t nperp = (int64_t)p.nx * p.ny;
     const int64_t plane = (int64_t)p.nxi * nperp;
-    const R* F = c->at<R>(c->L.fields);
+    const SetLayout& S = c->L.set[c->cur_set];
+    const R* F = c->at<R>(S.fields);
     double* emit = c->at<double>(c->L.emit);
     for (int j = xi0; j < xi1; ++j) {
       double* out = on_device ? dst + (int64_t)(j - xi0) * nperp : emit;
@@ -664,7 +897,7 @@ struct Engine {
         case QSA_BZ: A = F + F_BZ * plane + o; break;
         case QSA_DXPSI: A = F + F_DXPSI * plane + o; break;
         case QSA_DYPSI: A = F + F_DYPSI * plane + o; break;
-        default: A = c->at<R>(c->L.src) + (field - QSA_SRC_S) * plane + o; break;
+        default: A = c->at<R>(S.src) + (field - QSA_SRC_S) * plane + o; break;
       }
       hipLaunchKernelGGL(k_emit<R>, dim3(fill_blocks(nperp)), dim3(256), 0, c->stream, A, a, B, b,
                          out, nperp);
@@ -677,24 +910,16 @@ struct Engine {
     return QSA_OK;
   }
 
-  // Beam partial blocks carry one margin row on each side (so particles that
-  // drifted to a neighbouring cell row stay on the LDS path) when the tile
-  // 2*4*4*nx values plus the block's stray list fit the device's LDS.
-  static qsa_status choose_beam_tile(qsa_ctx* c) {
+  // Launch limits on LDS: beam tiles (2 node slices x 2 node rows x 4
+  // sources x nx) stay within 64 KiB for nx <= 512; the column transforms of
+  // tall grids opt in to more.
+  static qsa_status set_lds_limits(qsa_ctx* c) {
     int dev = 0, optin = 0, plain = 0;
     HIP_OK(hipGetDevice(&dev));
     if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
     HIP_OK(hipDeviceGetAttribute(&plain, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const int limit = std::max(optin, plain);
-    const int need = 2 * 4 * 4 * c->p.nx * (int)sizeof(R);
-    const int stat = 4096;   // block stray list and counters
-    c->bnl = 2;
-    if (c->p.ny > 1 && need + stat <= limit) {
-      if (need + stat > 65536)
-        HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_beam_rows<R>),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, need));
-      c->bnl = 4;
-    }
+    static_assert(2 * 2 * 4 * 512 * 8 <= 65536, "beam tile");
     // column transforms: (2G + 1) columns of ny complex values per block
     const int colj = (2 * ColShape<COL_J>::G + 1) * c->p.ny * (int)sizeof(C2<R>);
     if (colj > limit) return fail(c, QSA_E_INVALID, "ny too large for the device's LDS");
@@ -710,7 +935,7 @@ struct Engine {
   }
 
   static qsa_status upload_tables(qsa_ctx* c) {
-    qsa_status st0 = choose_beam_tile(c);
+    qsa_status st0 = set_lds_limits(c);
     if (st0 != QSA_OK) return st0;
     std::vector<char> twx, twy, kx2, kdx, ky2, kdy;
     tables(c->p, twx, twy, kx2, kdx, ky2, kdy);
@@ -722,8 +947,17 @@ struct Engine {
     HIP_OK(hipMemcpyAsync(c->ws + c->L.kdy, kdy.data(), kdy.size(), hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, c->stream, c->at<int>(c->L.err), (int64_t)1, 0);
     {
-      const Lane<R> lane = make_lane(c);
-      HIP_OK(hipMemcpyAsync(c->ws + c->L.lane, &lane, sizeof(lane), hipMemcpyHostToDevice, c->stream));
+      std::vector<Lane<R>> lanes;
+      std::vector<PipeBeam<R>> pipes;
+      for (int k = 0; k < c->L.nset; ++k) {
+        lanes.push_back(make_lane(c, k));
+        pipes.push_back(make_pipe(c, k));
+      }
+      HIP_OK(hipMemcpyAsync(c->ws + c->L.lane, lanes.data(), lanes.size() * sizeof(Lane<R>),
+                            hipMemcpyHostToDevice, c->stream));
+      HIP_OK(hipMemcpyAsync(c->ws + c->L.pipe, pipes.data(), pipes.size() * sizeof(PipeBeam<R>),
+                            hipMemcpyHostToDevice, c->stream));
+      HIP_OK(hipStreamSynchronize(c->stream));
     }
     // no beam loaded yet: every species has empty cell rows
     const int64_t nrows = (int64_t)c->p.nxi * c->p.ny;
@@ -800,6 +1034,51 @@ qsa_status run_step(qsa_ctx* c) {
   if (st != QSA_OK) return st;
   return dispatch(c, [&] { return Engine<double>::push(c); }, [&] { return Engine<float>::push(c); });
 }
+qsa_status run_group(qsa_ctx* c, int n) {
+  return dispatch(c, [&] { return Engine<double>::group(c, n); }, [&] { return Engine<float>::group(c, n); });
+}
+
+// One beam step at a time (graph replay unless timing or graphs are off).
+qsa_status step_one(qsa_ctx* c, bool graphs) {
+  qsa_status st = QSA_OK;
+  if (graphs && (st = capture(c, &c->gx_step, [&] { return run_step(c); })) != QSA_OK) return st;
+  if (graphs && c->gx_step) {
+    HIP_OK(hipGraphLaunch(c->gx_step, c->stream));
+    c->swept = true;
+  } else if ((st = run_step(c)) != QSA_OK) {
+    return st;
+  }
+  c->cur_set = 0;
+  return QSA_OK;
+}
+
+// n > 1 beam steps in flight; false in *done when the group broke the
+// schedule (the beam is then back at the group's start and pipelining off:
+// the group sorted the beam first, so its drift within a group is too large).
+qsa_status step_group(qsa_ctx* c, int n, bool graphs, bool* done) {
+  *done = false;
+  qsa_status st = check_device(c);   // the group starts with clear device flags
+  if (st != QSA_OK) return st;
+  if (graphs && (st = capture(c, &c->gx_group[n], [&] { return run_group(c, n); })) != QSA_OK) return st;
+  if (graphs && c->gx_group[n]) {
+    HIP_OK(hipGraphLaunch(c->gx_group[n], c->stream));
+    c->swept = true;
+  } else if ((st = run_group(c, n)) != QSA_OK) {
+    return st;
+  }
+  HIP_OK(hipStreamSynchronize(c->stream));
+  int e = 0;
+  HIP_OK(hipMemcpy(&e, c->ws + c->L.err, sizeof(int), hipMemcpyDeviceToHost));
+  if (e & ERR_DRIFT) {
+    st = dispatch(c, [&] { return Engine<double>::restore(c); }, [&] { return Engine<float>::restore(c); });
+    if (st != QSA_OK) return st;
+    c->pipe_ok = false;
+    return QSA_OK;
+  }
+  c->cur_set = n - 1;
+  *done = true;
+  return QSA_OK;
+}
 
 // Batched sweep (and push): every context's beam deposit on the batch's
 // stream, then one slice loop over all lanes.
@@ -824,6 +1103,7 @@ qsa_status batch_run(qsa_batch* b, bool push) {
   if (st != QSA_OK) return st;
   for (qsa_ctx* c : b->ctxs) {
     c->swept = true;
+    c->cur_set = 0;
     if (!push) continue;
     hipStream_t own = c->stream;
     c->stream = b->stream;
@@ -854,6 +1134,7 @@ qsa_status qsa_create(const qsa_params* p, void* dev_ws, size_t ws_bytes, void* 
   qsa_ctx* c = new qsa_ctx();
   c->p = *p;
   c->L = L;
+  c->pipe_max = L.nset;
   c->ws = reinterpret_cast<char*>(dev_ws);
   c->user = reinterpret_cast<hipStream_t>(hip_stream);
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
@@ -925,9 +1206,10 @@ qsa_status qsa_load_beam(qsa_ctx* c, int32_t s, const double* x, const double* y
     if (st != QSA_OK) return st;
   }
   c->beam_n[s] = n;
+  c->pipe_ok = true;
   c->drop_graphs();
-  qsa_status st = dispatch(c, [&] { return Engine<double>::beam_rows(c, s); },
-                           [&] { return Engine<float>::beam_rows(c, s); });
+  qsa_status st = dispatch(c, [&] { return Engine<double>::loaded(c, s); },
+                           [&] { return Engine<float>::loaded(c, s); });
   if (st != QSA_OK) return st;
   return leave(c);
 }
@@ -947,10 +1229,8 @@ qsa_status qsa_read_beam(qsa_ctx* c, int32_t s, double* x, double* y, double* xi
   qsa_status st0 = enter(c);
   if (st0 != QSA_OK) return st0;
   for (int i = 0; i < 7; ++i) {
-    const bool f64 = (i == 6);
-    qsa_status st = dispatch(
-        c, [&] { return Engine<double>::download(c, c->ws + c->L.beam[s][i], arr[i], m, on_device, f64); },
-        [&] { return Engine<float>::download(c, c->ws + c->L.beam[s][i], arr[i], m, on_device, f64); });
+    qsa_status st = dispatch(c, [&] { return Engine<double>::read_beam_array(c, s, i, arr[i], m, on_device); },
+                             [&] { return Engine<float>::read_beam_array(c, s, i, arr[i], m, on_device); });
     if (st != QSA_OK) return st;
   }
   if ((st0 = leave(c)) != QSA_OK) return st0;
@@ -971,6 +1251,7 @@ qsa_status qsa_slice_sweep(qsa_ctx* c) {
   } else if ((st = run_sweep(c)) != QSA_OK) {
     return st;
   }
+  c->cur_set = 0;
   return leave(c);
 }
 
@@ -983,14 +1264,16 @@ qsa_status qsa_beam_step(qsa_ctx* c, int32_t n_steps) {
   qsa_status st = enter(c);
   if (st != QSA_OK) return st;
   const bool graphs = c->use_graphs && c->timing_class < 0;
-  if (graphs && (st = capture(c, &c->gx_step, [&] { return run_step(c); })) != QSA_OK) return st;
-  for (int i = 0; i < n_steps; ++i) {
-    if (graphs && c->gx_step) {
-      HIP_OK(hipGraphLaunch(c->gx_step, c->stream));
-      c->swept = true;
-    } else if ((st = run_step(c)) != QSA_OK) {
-      return st;
+  for (int i = 0; i < n_steps;) {
+    const int n = c->pipe_ok ? std::min(c->pipe_max, n_steps - i) : 1;
+    if (n == 1) {
+      if ((st = step_one(c, graphs && c->use_graphs)) != QSA_OK) return st;
+      i += 1;
+      continue;
     }
+    bool done = false;
+    if ((st = step_group(c, n, graphs && c->use_graphs, &done)) != QSA_OK) return st;
+    if (done) i += n;   // else: repeated one step at a time
   }
   return leave(c);
 }
@@ -1001,7 +1284,26 @@ qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value) {
     c->use_graphs = value != 0;
     return QSA_OK;
   }
+  if (option == QSA_OPT_PIPELINE) {
+    if (value < 1) return fail(c, QSA_E_INVALID, "pipeline depth must be >= 1");
+    c->pipe_max = (int)std::min<int64_t>(value, c->L.nset);
+    c->pipe_ok = true;
+    return QSA_OK;
+  }
   return fail(c, QSA_E_INVALID, "unknown option");
+}
+
+qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value) {
+  if (!c || !value) return QSA_E_INVALID;
+  if (option == QSA_OPT_GRAPHS) {
+    *value = c->use_graphs ? 1 : 0;
+    return QSA_OK;
+  }
+  if (option == QSA_OPT_PIPELINE) {
+    *value = c->pipe_ok ? c->pipe_max : 1;
+    return QSA_OK;
+  }
+  return QSA_E_INVALID;
 }
 
 qsa_status qsa_fields(qsa_ctx* c, int32_t field, int32_t xi0, int32_t xi1, double* dst, size_t count,
@@ -1141,7 +1443,10 @@ static qsa_status batch_call(qsa_batch* b, int32_t n_steps, bool push) {
   for (int i = 0; i < n_steps; ++i) {
     if (graphs && *gx) {
       HIP_OK(hipGraphLaunch(*gx, b->stream));
-      for (qsa_ctx* m : b->ctxs) m->swept = true;
+      for (qsa_ctx* m : b->ctxs) {
+        m->swept = true;
+        m->cur_set = 0;
+      }
     } else {
       const qsa_status st = body();
       if (st != QSA_OK) return st;

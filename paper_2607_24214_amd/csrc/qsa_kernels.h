@@ -21,19 +21,26 @@ namespace qsa {
 enum { COL_PSI = 0, COL_J = 1, COL_B = 2 };
 // stored field slots
 enum { F_PSI = 0, F_DXPSI = 1, F_DYPSI = 2, F_EZ = 3, F_BX = 4, F_BY = 5, F_BZ = 6, N_STORED = 7 };
-enum { ERR_BREAKDOWN = 1 };
+enum { ERR_BREAKDOWN = 1, ERR_DRIFT = 2 };
 
 #define QSA_GMIN 1.0e-3
 #define QSA_SORT_EVERY 8   // the plasma is counting-sorted by cell every this many slices
+#define QSA_PIPE_LAG 8     // slices between successive beam steps in flight
+#define QSA_PUSH_LAG 3     // a lane pushes beam slab j once it has finished slice j + 3
+// A deposit may land up to 3 slices behind its slab and must still precede
+// the next lane's use of that slice (one slice ahead of its sweep).
+static_assert(QSA_PIPE_LAG % QSA_SORT_EVERY == 0 && QSA_PIPE_LAG > QSA_PUSH_LAG + 4, "pipeline lag");
 
 // One box's slice loop: geometry, constants and every array the per-slice
-// kernels touch.  The per-slice kernels take an array of lanes and the slice
-// index j; blockIdx.z selects the lane, so one launch advances many
-// independent boxes (a batched parameter scan) by one slice.  A lane whose
-// box has fewer slices than j returns at once.
+// kernels touch.  The per-slice kernels take an array of lanes and a tick t;
+// blockIdx.z selects the lane, which works on slice j = t - lag, so one
+// launch advances many slice loops by one slice: independent boxes of a
+// batched scan (lag 0), or successive beam steps of one box in flight at
+// once (lag = k * QSA_PIPE_LAG).  A lane with j outside [0, nxi) returns.
 template <typename R>
 struct Lane {
   Geo<R> g;
+  int lag;              // the lane works on slice j = t - lag at tick t
   int np;               // plasma macro-particles per slice
   R q;                  // -w/(dx dy): plasma rho - J_z per particle per unit area
   R h;                  // dxi
@@ -119,17 +126,20 @@ __global__ void k_copy4(const R* __restrict__ a0, const R* __restrict__ a1,
 // Per-lane clears: WHAT = 0 zeroes the sweep state (J and B rings, the
 // out-of-row grids, the transverse-mean wake), WHAT = 1 the sort counts.
 template <typename R, int WHAT>
-__global__ void k_lane_clear(const Lane<R>* __restrict__ lanes, int j) {
+__global__ void k_lane_clear(const Lane<R>* __restrict__ lanes, int tick) {
   const Lane<R>& L = lanes[blockIdx.z];
+  const int j = tick - L.lag;
   const Geo<R>& g = L.g;
-  if (j >= g.nxi) return;
+  if (j < 0 || j >= g.nxi) return;
   const int64_t spec = (int64_t)g.ny * g.nxh;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   if (WHAT == 1) {
+    if (j % QSA_SORT_EVERY != 0) return;
     for (int64_t i = i0; i < g.nperp; i += st) L.count[i] = 0;
     return;
   }
+  if (j != 0) return;
   const C2<R> z{R(0), R(0)};
   for (int64_t i = i0; i < 4 * spec; i += st) L.jring[i] = z;
   for (int64_t i = i0; i < 6 * spec; i += st) L.bring[i] = z;
@@ -166,27 +176,21 @@ __device__ __forceinline__ R plasma_partial(const R* __restrict__ pp, int nc, in
   return s;
 }
 
-// Beam partial rows: block (j, l) holds node rows (j + dj, l - m + k), dj in
-// {0, 1}, k in [0, NL) with m = NL/2 - 1 margin rows on each side, for the
-// 4 sources: bpart[((((j*ny + l)*2 + dj)*NL + k)*4 + q)*nx + i].
+// Beam partial rows: block (j, l) holds node rows (j + dj, l + k), dj, k in
+// {0, 1}, for the 4 sources: bpart[((((j*ny + l)*2 + dj)*2 + k)*4 + q)*nx + i].
+// Node (J, L) collects corner (dj, k) of cell rows (J - dj, L - k).
 template <typename R>
-__device__ __forceinline__ R beam_partial(const R* __restrict__ bp, int nl, int ny, int nx, int q, int J,
-                                         int L, int i) {
-  const int m = nl / 2 - 1;
+__device__ __forceinline__ R beam_partial(const R* __restrict__ bp, int ny, int nx, int q, int J, int L, int i) {
   R s = R(0);
 #pragma unroll
   for (int dj = 0; dj < 2; ++dj) {
     const int jj = J - dj;
     if (jj < 0) continue;
-    for (int k = 0; k < nl; ++k) {
-      int ll = L + m - k;
-      if (ny == 1) {
-        ll = 0;
-      } else {
-        ll += (ll < 0) ? ny : 0;
-        ll -= (ll >= ny) ? ny : 0;
-      }
-      s += bp[(((((int64_t)jj * ny + ll) * 2 + dj) * nl + k) * 4 + q) * nx + i];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      int ll = L - k;
+      ll = (ny == 1) ? 0 : ((ll < 0) ? ll + ny : ll);
+      s += bp[(((((int64_t)jj * ny + ll) * 2 + dj) * 2 + k) * 4 + q) * nx + i];
     }
   }
   return s;
@@ -251,11 +255,12 @@ __device__ __forceinline__ R row_value(const Geo<R>& g, const RowIn<R>& a, int r
 // Real rows -> half spectra along x.  Rows 2p and 2p+1 are packed as the
 // real and imaginary parts of one complex transform and separated after it.
 template <typename R>
-__global__ void __launch_bounds__(256) k_row_r2c(const Lane<R>* __restrict__ lanes, int j, int stage) {
+__global__ void __launch_bounds__(256) k_row_r2c(const Lane<R>* __restrict__ lanes, int tick, int stage) {
   const Lane<R>& L = lanes[blockIdx.z];
+  const int j = tick - L.lag;
   const Geo<R> g = L.g;
   const int f = blockIdx.y;
-  if (j >= g.nxi || f >= stage_fields_in<R>(stage)) return;
+  if (j < 0 || j >= g.nxi || f >= stage_fields_in<R>(stage)) return;
   const RowIn<R> a = row_in(L, j, stage, f);
   const C2<R>* __restrict__ twx = L.twx;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -306,11 +311,12 @@ __device__ __forceinline__ int stage_slot(int stage, int f) {
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_row_c2r(const Lane<R>* __restrict__ lanes, int j, int stage) {
+__global__ void __launch_bounds__(256) k_row_c2r(const Lane<R>* __restrict__ lanes, int tick, int stage) {
   const Lane<R>& L = lanes[blockIdx.z];
+  const int j = tick - L.lag;
   const Geo<R> g = L.g;
   const int f = blockIdx.y;
-  if (j >= g.nxi || f >= stage_fields_out(stage)) return;
+  if (j < 0 || j >= g.nxi || f >= stage_fields_out(stage)) return;
   const C2<R>* __restrict__ in = L.colout + (size_t)f * g.ny * g.nxh;
   R* __restrict__ outp = L.fields + (int64_t)stage_slot(stage, f) * g.nxi * g.nperp + (int64_t)j * g.nperp;
   const C2<R>* __restrict__ twx = L.twx;
@@ -426,12 +432,13 @@ __device__ __forceinline__ ColArgs<R> col_args(const Lane<R>& L, int j) {
 }
 
 template <typename R, int MODE>
-__global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, int j) {
+__global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, int tick) {
   using S = ColShape<MODE>;
   constexpr int G = S::G;
   const Lane<R>& L = lanes[blockIdx.z];
+  const int j = tick - L.lag;
   const Geo<R> g = L.g;
-  if (j >= g.nxi) return;
+  if (j < 0 || j >= g.nxi) return;
   const ColArgs<R> a = col_args(L, j);
   const C2<R>* __restrict__ twy = L.twy;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -683,11 +690,12 @@ __device__ __forceinline__ void row_tile_add(const Geo<R>& g, R* tile, int r, in
 //   PL_PRED : predictor push to j+1 and J~_perp at j+1 with 1 + psi~^{j+1},
 //             psi~^{j+1} = 3 psi^j - 3 psi^{j-1} + psi^{j-2}
 template <typename R, int MODE>
-__global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__ lanes, int j) {
+__global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__ lanes, int tick) {
   constexpr int NC = PlasmaNC<MODE>::NC;
   const Lane<R>& L = lanes[blockIdx.z];
+  const int j = tick - L.lag;
   const Geo<R> g = L.g;
-  if (j >= g.nxi || (int)blockIdx.x >= g.ny) return;
+  if (j < 0 || j >= g.nxi || (int)blockIdx.x >= g.ny) return;
   const PlasmaArgs<R> a = plasma_args(L, j);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
@@ -768,9 +776,11 @@ __global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__
 // First particle of each cell row from the scanned cell counts (cell c
 // starts at count[c] + bsum[c / 1024]); prow[ny] = np.
 template <typename R>
-__global__ void k_row_offsets(const Lane<R>* __restrict__ lanes, int j) {
+__global__ void k_row_offsets(const Lane<R>* __restrict__ lanes, int tick) {
   const Lane<R>& L = lanes[blockIdx.z];
-  if (j >= L.g.nxi) return;
+  const int j = tick - L.lag;
+  if (j < 0 || j >= L.g.nxi) return;
+  if (j % QSA_SORT_EVERY != 0) return;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int nx = L.g.nx, ny = L.g.ny;
   if (r > ny) return;
@@ -784,10 +794,11 @@ __global__ void k_row_offsets(const Lane<R>* __restrict__ lanes, int j) {
 
 // Final advance: Y^{j+1} with the converged fields, positions wrapped.
 template <typename R>
-__global__ void __launch_bounds__(256) k_push_final(const Lane<R>* __restrict__ lanes, int j) {
+__global__ void __launch_bounds__(256) k_push_final(const Lane<R>* __restrict__ lanes, int tick) {
   const Lane<R>& L = lanes[blockIdx.z];
+  const int j = tick - L.lag;
   const Geo<R> g = L.g;
-  if (j >= g.nxi) return;
+  if (j < 0 || j >= g.nxi) return;
   const int p = plasma_index();
   if (p >= L.np) return;
   const PlasmaArgs<R> a = plasma_args(L, j);
@@ -811,10 +822,12 @@ __device__ __forceinline__ void sort_buffers(const Lane<R>& L, int j, const R* c
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_sort_count(const Lane<R>* __restrict__ lanes, int j) {
+__global__ void __launch_bounds__(256) k_sort_count(const Lane<R>* __restrict__ lanes, int tick) {
   const Lane<R>& L = lanes[blockIdx.z];
+  const int j = tick - L.lag;
   const Geo<R> g = L.g;
-  if (j >= g.nxi) return;
+  if (j < 0 || j >= g.nxi) return;
+  if (j % QSA_SORT_EVERY != 0) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= L.np) return;
   const R* const* A;
@@ -835,9 +848,11 @@ __global__ void __launch_bounds__(256) k_sort_count(const Lane<R>* __restrict__ 
 // Exclusive scan of v[0, n) in blocks of 1024: offsets within the block in
 // place, block totals in bsum[block].
 template <typename R>
-__global__ void __launch_bounds__(256) k_scan_local(const Lane<R>* __restrict__ lanes, int j) {
+__global__ void __launch_bounds__(256) k_scan_local(const Lane<R>* __restrict__ lanes, int tick) {
   const Lane<R>& L = lanes[blockIdx.z];
-  if (j >= L.g.nxi) return;
+  const int j = tick - L.lag;
+  if (j < 0 || j >= L.g.nxi) return;
+  if (j % QSA_SORT_EVERY != 0) return;
   int* __restrict__ v = L.count;
   int* __restrict__ bsum = L.bsum;
   const int n = L.g.nperp;
@@ -868,9 +883,11 @@ __global__ void __launch_bounds__(256) k_scan_local(const Lane<R>* __restrict__ 
 
 // Exclusive scan of the (at most 256) block totals, one block.
 template <typename R>
-__global__ void __launch_bounds__(256) k_scan_blocks(const Lane<R>* __restrict__ lanes, int j) {
+__global__ void __launch_bounds__(256) k_scan_blocks(const Lane<R>* __restrict__ lanes, int tick) {
   const Lane<R>& L = lanes[blockIdx.z];
-  if (j >= L.g.nxi) return;
+  const int j = tick - L.lag;
+  if (j < 0 || j >= L.g.nxi) return;
+  if (j % QSA_SORT_EVERY != 0) return;
   int* __restrict__ bsum = L.bsum;
   const int nb = (L.g.nperp + 1023) / 1024;
   __shared__ int s[256];
@@ -889,9 +906,11 @@ __global__ void __launch_bounds__(256) k_scan_blocks(const Lane<R>* __restrict__
 
 // cursor[c] + bsum[c / 1024] is the first free slot of cell c.
 template <typename R>
-__global__ void __launch_bounds__(256) k_sort_scatter(const Lane<R>* __restrict__ lanes, int j) {
+__global__ void __launch_bounds__(256) k_sort_scatter(const Lane<R>* __restrict__ lanes, int tick) {
   const Lane<R>& L = lanes[blockIdx.z];
-  if (j >= L.g.nxi) return;
+  const int j = tick - L.lag;
+  if (j < 0 || j >= L.g.nxi) return;
+  if (j % QSA_SORT_EVERY != 0) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= L.np) return;
   const R* const* A;
@@ -936,6 +955,46 @@ struct BeamArgs {
 };
 
 // ------------------------------------------------------- beam source deposit
+// Run-aggregated counter increments: every active lane of a wavefront takes
+// the next slot of counter cnt[key]; consecutive lanes with equal keys (the
+// usual case, as beam particles come nearly sorted) share one atomic.
+// Returns the lane's slot.  All 64 lanes of the wavefront must call it.
+__device__ __forceinline__ int lane_atomic_add(int* p, int v) { return atomicAdd(p, v); }
+__device__ __forceinline__ int64_t lane_atomic_add(int64_t* p, int64_t v) {
+  return (int64_t)atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+}
+template <typename T>
+__device__ __forceinline__ T wave_run_add(T* cnt, int key, bool active) {
+  const int lane = threadIdx.x & 63;
+  const int k = active ? key : -1;
+  const int prev = __shfl_up(k, 1);
+  const bool brk = (lane == 0) || (prev != k);
+  const unsigned long long b = __ballot(brk);
+  const unsigned long long above = (lane == 63) ? 0ull : (b >> (lane + 1)) << (lane + 1);
+  const int next = above ? __ffsll((long long)above) - 1 : 64;
+  const unsigned long long upto = (lane == 63) ? b : (b & ((2ull << lane) - 1ull));
+  const int head = 63 - __clzll((long long)upto);
+  T base = 0;
+  if (active && brk) base = lane_atomic_add(cnt + key, (T)(next - lane));
+  base = __shfl(base, head);
+  return base + (T)(lane - head);
+}
+
+// Cell-row key of a beam particle: row (j, l), j = floor(xi/dxi), where a
+// particle with j = -1 (node slice 0 only) counts as row (0, l); nxi*ny for a
+// particle without a node in the grid or with nothing to deposit (w = 0).
+template <typename R>
+__device__ __forceinline__ int beam_key(const Geo<R>& g, R x, R y, double xi, R w, double inv_dxi) {
+  const double gz = xi * inv_dxi;
+  if (w == R(0) || !(gz > -1.0 && gz < (double)g.nxi)) return g.nxi * g.ny;
+  int j = (int)floor(gz);
+  j = j < 0 ? 0 : j;
+  int i, l;
+  R fx, fy;
+  cell2(g, x, y, i, l, fx, fy);
+  return j * g.ny + l;
+}
+
 template <typename R>
 struct BeamDepArgs {
   int ns;                     // species
@@ -946,194 +1005,151 @@ struct BeamDepArgs {
   const R* uy[4];
   const R* uz[4];
   const R* w[4];
-  const int64_t* rowoff[4];   // [nxi*ny + 2]: particles of cell row b start at rowoff[b]
+  int* key[4];                // per particle: cell-row key
+  int* perm[4];               // particles of each cell row, row after row
+  const int64_t* doff[4];     // [nxi*ny + 2]: row b's particles are perm[doff[b] .. doff[b+1])
   R zq[4];                    // Z/(dx dy dxi)
-  R* bpart;                   // partial node rows
-  int64_t* strays;            // indices (species << 56 | particle) of out-of-row particles
-  int64_t stray_cap;
-  int* ctl;                   // [0..1] stray count (64-bit), [2] overflow flag
+  R* bpart;                   // partial node rows [nxi*ny][2][2][4][nx]
   double inv_dxi;
-  int nl;                     // node rows per partial block along y (2 or 4)
 };
 
-// Beam particle p of species s: slice cell j, row/column cell, offsets and
-// the four sources (rho - J_z, J_x, J_y, J_z) times Z w/dV.  False when the
-// particle has no node inside the grid or is inert (w = 0).
+// Keys of species s and their counts per row (cnt zeroed by the caller).
 template <typename R>
-__device__ __forceinline__ bool beam_particle(const Geo<R>& g, const BeamDepArgs<R>& a, int s, int64_t p,
-                                              int& j, int& l, int& i, R& fz, R& fy, R& fx, R (&v)[4]) {
-  const R w = a.w[s][p];
-  const double gz = a.xi[s][p] * a.inv_dxi;
-  if (w == R(0) || !(gz > -1.0 && gz < (double)g.nxi)) return false;
-  const double fz0 = floor(gz);
-  j = (int)fz0;
-  fz = (R)(gz - fz0);
-  cell2(g, a.x[s][p], a.y[s][p], i, l, fx, fy);
-  const R ux = a.ux[s][p], uy = a.uy[s][p], uz = a.uz[s][p];
-  const R up2 = ux * ux + uy * uy;
-  const R gam = sqrt(R(1) + up2 + uz * uz);
-  const R q = a.zq[s] * w;
-  v[0] = q * ((R(1) + up2) / (gam * (gam + uz)));   // 1 - v_z without cancellation
-  v[1] = q * ux / gam;
-  v[2] = q * uy / gam;
-  v[3] = q * uz / gam;
-  return true;
+__global__ void __launch_bounds__(256) k_beam_keys(Geo<R> g, BeamDepArgs<R> a, int s, int64_t n,
+                                                   int64_t* __restrict__ cnt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = p < n;
+  int key = 0;
+  if (act) {
+    key = beam_key(g, a.x[s][p], a.y[s][p], a.xi[s][p], a.w[s][p], a.inv_dxi);
+    a.key[s][p] = key;
+  }
+  (void)wave_run_add(cnt, key, act);
 }
 
-// Beam deposit owned by cell rows (j, l) = (b / ny, b % ny): the block takes
-// the particles of its row of every species (consecutive threads take
-// consecutive particles) and adds those whose cell is (j, l +- m) to an LDS
-// tile of node rows (j..j+1, l-m .. l+1+m) with LDS atomics; the tile is
-// written out as partial rows.  The others are listed for k_beam_strays,
-// through a block-local list and one global reservation per block.
+// Particle indices grouped by key: cur holds the exclusive offsets on entry.
+template <typename R>
+__global__ void __launch_bounds__(256) k_beam_perm(BeamDepArgs<R> a, int s, int64_t n,
+                                                   int64_t* __restrict__ cur) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = p < n;
+  const int key = act ? a.key[s][p] : 0;
+  const int64_t slot = wave_run_add(cur, key, act);
+  if (act) a.perm[s][slot] = (int)p;
+}
+
+// Sources of one beam particle: (rho - J_z, J_x, J_y, J_z) times Z w/dV, its
+// cell and offsets.
+template <typename R>
+__device__ __forceinline__ void beam_sources_of(const Geo<R>& g, R x, R y, double xi, R ux, R uy, R uz, R qw,
+                                                double inv_dxi, int& jc, int& i, int& l, R& fz, R& fy, R& fx,
+                                                R (&v)[4]) {
+  const double gz = xi * inv_dxi;
+  const double fz0 = floor(gz);
+  jc = (int)fz0;
+  fz = (R)(gz - fz0);
+  cell2(g, x, y, i, l, fx, fy);
+  const R up2 = ux * ux + uy * uy;
+  const R gam = sqrt(R(1) + up2 + uz * uz);
+  v[0] = qw * ((R(1) + up2) / (gam * (gam + uz)));   // 1 - v_z without cancellation
+  v[1] = qw * ux / gam;
+  v[2] = qw * uy / gam;
+  v[3] = qw * uz / gam;
+}
+
+// Add one particle to a tile of node slices (j0, j0+1) x node rows (l, l+1)
+// x 4 sources x nx held in LDS (the particle's cell row is (j0 or j0-1, l)).
+template <typename R>
+__device__ __forceinline__ void tile_add(R* __restrict__ tile, int nx, int j0, int jc, int i, R fz, R fy, R fx,
+                                         const R (&v)[4]) {
+  const int i1 = (i + 1 == nx) ? 0 : i + 1;
+  const R wz[2] = {R(1) - fz, fz}, wy[2] = {R(1) - fy, fy}, wx[2] = {R(1) - fx, fx};
+#pragma unroll
+  for (int dj = 0; dj < 2; ++dj) {
+    const int t = jc + dj - j0;
+    if (t < 0) continue;   // node slice -1 of a particle in front of the grid
+#pragma unroll
+    for (int dl = 0; dl < 2; ++dl) {
+      const R wc = wz[dj] * wy[dl];
+      R* tt = tile + ((t * 2 + dl) * 4) * nx;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        atomicAdd(tt + c * nx + i, v[c] * wc * wx[0]);
+        atomicAdd(tt + c * nx + i1, v[c] * wc * wx[1]);
+      }
+    }
+  }
+}
+
+// Beam deposit owned by cell rows b = (j, l): the block takes exactly the
+// particles of its row (through the permutation), adds them to an LDS tile
+// of node slices (j, j+1) x node rows (l, l+1) with LDS atomics and writes
+// the tile out as the row's partial node rows.
 template <typename R>
 __global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
-  constexpr int SB = 256;
-  __shared__ int64_t sbuf[SB];
-  __shared__ int scount;
-  __shared__ unsigned long long sbase;
   const int b = blockIdx.x;
-  const int jb = b / g.ny, lb = b - jb * g.ny;
-  const int nl = a.nl, m = nl / 2 - 1;
-  const int nt = blockDim.x, tid = threadIdx.x;
-  const int tn = 2 * nl * 4 * g.nx;
-  for (int t = tid; t < tn; t += nt) tile[t] = R(0);
-  if (tid == 0) scount = 0;
+  const int jb = b / g.ny;
+  const int tn = 2 * 2 * 4 * g.nx;
+  for (int t = threadIdx.x; t < tn; t += blockDim.x) tile[t] = R(0);
   __syncthreads();
   for (int s = 0; s < a.ns; ++s) {
-    const int64_t p1 = a.rowoff[s][b + 1];
-    for (int64_t p = a.rowoff[s][b] + tid; p < p1; p += nt) {
-      int j, l, i;
+    const int64_t q1 = a.doff[s][b + 1];
+    for (int64_t q = a.doff[s][b] + threadIdx.x; q < q1; q += blockDim.x) {
+      const int p = a.perm[s][q];
+      int jc, i, l;
       R fz, fy, fx, v[4];
-      if (!beam_particle(g, a, s, p, j, l, i, fz, fy, fx, v)) continue;
-      int d = l - lb;
-      if (g.ny == 1) {
-        d = 0;
-      } else {
-        if (d > (g.ny >> 1)) d -= g.ny;
-        if (d < -(g.ny >> 1)) d += g.ny;
-      }
-      if (j != jb || d < -m || d > m) {
-        const int k = atomicAdd(&scount, 1);
-        if (k < SB) {
-          sbuf[k] = ((int64_t)s << 56) | p;
-        } else {
-          const int64_t e = atomicAdd((unsigned long long*)a.ctl, 1ull);
-          if (e < a.stray_cap) a.strays[e] = ((int64_t)s << 56) | p;
-          else atomicOr(a.ctl + 2, 1);
-        }
-        continue;
-      }
-      const int i1 = (i + 1 == g.nx) ? 0 : i + 1;
-      const R wz[2] = {R(1) - fz, fz}, wy[2] = {R(1) - fy, fy}, wx[2] = {R(1) - fx, fx};
-#pragma unroll
-      for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-        for (int dl = 0; dl < 2; ++dl) {
-          const int k = d + m + dl;
-          const R wc = wz[dj] * wy[dl];
-          const R w0 = wc * wx[0], w1 = wc * wx[1];
-          R* t = tile + ((dj * nl + k) * 4) * g.nx;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            atomicAdd(t + q * g.nx + i, v[q] * w0);
-            atomicAdd(t + q * g.nx + i1, v[q] * w1);
-          }
-        }
+      beam_sources_of(g, a.x[s][p], a.y[s][p], a.xi[s][p], a.ux[s][p], a.uy[s][p], a.uz[s][p],
+                      a.zq[s] * a.w[s][p], a.inv_dxi, jc, i, l, fz, fy, fx, v);
+      tile_add(tile, g.nx, jb, jc, i, fz, fy, fx, v);
     }
   }
   __syncthreads();
-  const int nloc = scount < SB ? scount : SB;
-  if (tid == 0 && nloc > 0) sbase = atomicAdd((unsigned long long*)a.ctl, (unsigned long long)nloc);
   R* out = a.bpart + (int64_t)b * tn;
-  for (int t = tid; t < tn; t += nt) out[t] = tile[t];
-  __syncthreads();
-  if (nloc > 0)
-    for (int t = tid; t < nloc; t += nt) {
-      const int64_t e = (int64_t)sbase + t;
-      if (e < a.stray_cap) a.strays[e] = sbuf[t];
-      else atomicOr(a.ctl + 2, 1);
-    }
+  for (int t = threadIdx.x; t < tn; t += blockDim.x) out[t] = tile[t];
 }
 
-// Out-of-row beam particles, after every block has written its partial
-// rows: atomics into corner 0 of the row that owns each node.  If the list
-// overflowed, every block rescans its rows instead.
+// Beam particles reordered by cell row (a stable-in-runs counting sort):
+// particle p moves from the src arrays to slot cur[key[p]]++ of the dst
+// arrays, with its identity (index at load).
 template <typename R>
-__device__ __forceinline__ void beam_stray_add(const Geo<R>& g, const BeamDepArgs<R>& a, int s, int64_t p) {
-  int j, l, i;
-  R fz, fy, fx, v[4];
-  if (!beam_particle(g, a, s, p, j, l, i, fz, fy, fx, v)) return;
-  const R wz[2] = {R(1) - fz, fz}, wy[2] = {R(1) - fy, fy}, wx[2] = {R(1) - fx, fx};
-#pragma unroll
-  for (int dj = 0; dj < 2; ++dj) {
-    const int jj = j + dj;
-    if (jj < 0 || jj >= g.nxi) continue;
-#pragma unroll
-    for (int dl = 0; dl < 2; ++dl) {
-      const int ll = (l + dl == g.ny) ? 0 : l + dl;
-#pragma unroll
-      for (int di = 0; di < 2; ++di) {
-        const int ii = (i + di == g.nx) ? 0 : i + di;
-        const R wt = wz[dj] * wy[dl] * wx[di];
-        const int m = a.nl / 2 - 1;
-        R* base = a.bpart + (((((int64_t)jj * g.ny + ll) * 2) * a.nl + m) * 4) * g.nx + ii;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) atomic_add(base + q * g.nx, v[q] * wt);
-      }
-    }
-  }
-}
+struct BeamMove {
+  const R* src[6];        // x, y, ux, uy, uz, w
+  const double* sxi;
+  const int64_t* sid;
+  R* dst[6];
+  double* dxi;
+  int64_t* did;
+  const int* key;
+  int64_t* cur;
+  int64_t n;
+};
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_beam_strays(Geo<R> g, BeamDepArgs<R> a) {
-  const int64_t count = *(const unsigned long long*)a.ctl;
-  const bool overflow = a.ctl[2] != 0;
-  if (!overflow) {
-    const int64_t n = count < a.stray_cap ? count : a.stray_cap;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * blockDim.x) {
-      const int64_t e = a.strays[k];
-      beam_stray_add(g, a, (int)(e >> 56), e & (((int64_t)1 << 56) - 1));
-    }
-    return;
-  }
-  const int nrows = g.nxi * g.ny;
-  for (int b = blockIdx.x; b < nrows; b += gridDim.x) {
-    const int jb = b / g.ny, lb = b - jb * g.ny;
-    for (int s = 0; s < a.ns; ++s)
-      for (int64_t p = a.rowoff[s][b] + threadIdx.x; p < a.rowoff[s][b + 1]; p += blockDim.x) {
-        int j, l, i;
-        R fz, fy, fx, v[4];
-        if (!beam_particle(g, a, s, p, j, l, i, fz, fy, fx, v)) continue;
-        const int m = a.nl / 2 - 1;
-        int d = l - lb;
-        if (g.ny == 1) {
-          d = 0;
-        } else {
-          if (d > (g.ny >> 1)) d -= g.ny;
-          if (d < -(g.ny >> 1)) d += g.ny;
-        }
-        if (j != jb || d < -m || d > m) beam_stray_add(g, a, s, p);
-      }
-  }
-}
-
-// Cell-row keys of the loaded beam, for the row offsets: row (j, l) of
-// particles with a node in the grid (j < 0 counts as row (0, l)); inert or
-// out-of-grid particles go to the extra key nxi*ny.
-template <typename R>
-__global__ void __launch_bounds__(256) k_beam_rowcount(Geo<R> g, BeamDepArgs<R> a, int s, int64_t n,
-                                                       int64_t* __restrict__ cnt) {
+__global__ void __launch_bounds__(256) k_beam_sort(BeamMove<R> m) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  int j, l, i;
-  R fz, fy, fx, v[4];
-  int key = g.nxi * g.ny;
-  if (beam_particle(g, a, s, p, j, l, i, fz, fy, fx, v)) key = (j < 0 ? 0 : j) * g.ny + l;
-  atomicAdd((unsigned long long*)(cnt + key), 1ull);
+  const bool act = p < m.n;
+  const int key = act ? m.key[p] : 0;
+  const int64_t slot = wave_run_add(m.cur, key, act);
+  if (!act) return;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) m.dst[k][slot] = m.src[k][p];
+  m.dxi[slot] = m.sxi[p];
+  m.did[slot] = m.sid[p];
+}
+
+__global__ void __launch_bounds__(256) k_iota64(int64_t* __restrict__ v, int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) v[p] = p;
+}
+
+// Back to load order as float64: dst[id[p]] = src[p].
+template <typename T>
+__global__ void __launch_bounds__(256) k_unpermute(const T* __restrict__ src, const int64_t* __restrict__ id,
+                                                   double* __restrict__ dst, int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) dst[id[p]] = (double)src[p];
 }
 
 // Exclusive scan of int64 values in blocks of 1024 (in place), block totals
@@ -1170,12 +1186,10 @@ __global__ void __launch_bounds__(256) k_scan64_add(int64_t* __restrict__ v, int
   if (i < n) v[i] += bsum[i >> 10];
 }
 
-// Dense beam sources [4][nxi][ny][nx] from the partial rows (after the
-// out-of-row particles have been added): one pass before the sweep, so the
-// row transforms read one value per node.
+// Dense beam sources [4][nxi][ny][nx] from the partial rows: one pass before
+// the sweep, so the row transforms read one value per node.
 template <typename R>
-__global__ void __launch_bounds__(256) k_beam_reduce(Geo<R> g, const R* __restrict__ bpart, int nl,
-                                                     R* __restrict__ src) {
+__global__ void __launch_bounds__(256) k_beam_reduce(Geo<R> g, const R* __restrict__ bpart, R* __restrict__ src) {
   const int64_t plane = (int64_t)g.nxi * g.nperp;
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= plane) return;
@@ -1183,21 +1197,25 @@ __global__ void __launch_bounds__(256) k_beam_reduce(Geo<R> g, const R* __restri
   const int r = (int)(o - (int64_t)J * g.nperp);
   const int L = r / g.nx, i = r - L * g.nx;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) src[q * plane + o] = beam_partial(bpart, nl, g.ny, g.nx, q, J, L, i);
+  for (int q = 0; q < 4; ++q) src[q * plane + o] = beam_partial(bpart, g.ny, g.nx, q, J, L, i);
 }
 
 
-// Boris push of the beam by dt in the stored fields, E = (-d_x psi + B_y,
-// -d_y psi - B_x, E_z), B = (B_x, B_y, B_z), 3D linear shape, zero outside.
+// Boris push of one beam particle by dt in the stored fields, E = (-d_x psi
+// + B_y, -d_y psi - B_x, E_z), B = (B_x, B_y, B_z), 3D linear shape, zero
+// outside the xi grid.  Positions use the new momentum; dxi/dtau = 1 - v_z.
+// A particle reaching xi >= (nxi - 1) dxi leaves the box (weight 0).
 template <typename R>
-__global__ void __launch_bounds__(256) k_beam_push(Geo<R> g, BeamArgs<R> a) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.n) return;
-  const R x = a.x[p], y = a.y[p];
-  const double xi = a.xi[p];
-  R ux = a.ux[p], uy = a.uy[p], uz = a.uz[p];
+__device__ __forceinline__ void boris_one(const Geo<R>& g, const R* __restrict__ fields, R qh, R dt,
+                                          double inv_dxi, double xi_max, R* __restrict__ px,
+                                          R* __restrict__ py, double* __restrict__ pxi, R* __restrict__ pux,
+                                          R* __restrict__ puy, R* __restrict__ puz, R* __restrict__ pw,
+                                          int64_t p) {
+  const R x = px[p], y = py[p];
+  const double xi = pxi[p];
+  R ux = pux[p], uy = puy[p], uz = puz[p];
   R fd[6] = {0, 0, 0, 0, 0, 0};   // d_x psi, d_y psi, E_z, B_x, B_y, B_z
-  const double gz = xi * a.inv_dxi;
+  const double gz = xi * inv_dxi;
   if (gz > -1.0 && gz < (double)g.nxi) {
     const double fz0 = floor(gz);
     const int j0 = (int)fz0;
@@ -1211,15 +1229,13 @@ __global__ void __launch_bounds__(256) k_beam_push(Geo<R> g, BeamArgs<R> a) {
       if (jj < 0 || jj >= g.nxi) continue;
       const R wz = dj ? fz : R(1) - fz;
 #pragma unroll
-      for (int q = 0; q < 6; ++q)
-        fd[q] += wz * gather(a.fields + slot[q] * plane + (int64_t)jj * g.nperp, s);
+      for (int q = 0; q < 6; ++q) fd[q] += wz * gather(fields + slot[q] * plane + (int64_t)jj * g.nperp, s);
     }
   }
   const R ex = -fd[0] + fd[4];
   const R ey = -fd[1] - fd[3];
   const R ez = fd[2];
   const R bx = fd[3], by = fd[4], bz = fd[5];
-  const R qh = a.qmh;
   // half electric kick
   const R umx = ux + qh * ex, umy = uy + qh * ey, umz = uz + qh * ez;
   const R gm = sqrt(R(1) + umx * umx + umy * umy + umz * umz);
@@ -1239,14 +1255,235 @@ __global__ void __launch_bounds__(256) k_beam_push(Geo<R> g, BeamArgs<R> a) {
   uz = uqz + qh * ez;
   const R up2 = ux * ux + uy * uy;
   const R gam = sqrt(R(1) + up2 + uz * uz);
-  a.x[p] = wrap_pos(x + a.dt * ux / gam, g.lx, g.inv_lx);
-  a.y[p] = wrap_pos(y + a.dt * uy / gam, g.ly, g.inv_ly);
-  const double xin = xi + (double)(a.dt * (R(1) + up2) / (gam * (gam + uz)));
-  a.xi[p] = xin;
-  a.ux[p] = ux;
-  a.uy[p] = uy;
-  a.uz[p] = uz;
-  if (xin >= a.xi_max) a.w[p] = R(0);
+  px[p] = wrap_pos(x + dt * ux / gam, g.lx, g.inv_lx);
+  py[p] = wrap_pos(y + dt * uy / gam, g.ly, g.inv_ly);
+  const double xin = xi + (double)(dt * (R(1) + up2) / (gam * (gam + uz)));
+  pxi[p] = xin;
+  pux[p] = ux;
+  puy[p] = uy;
+  puz[p] = uz;
+  if (xin >= xi_max) pw[p] = R(0);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_beam_push(Geo<R> g, BeamArgs<R> a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n) return;
+  boris_one(g, a.fields, a.qmh, a.dt, a.inv_dxi, a.xi_max, a.x, a.y, a.xi, a.ux, a.uy, a.uz, a.w, p);
+}
+
+// ---------------------------------------------------------------------------
+// Beam steps in flight.  Lane k of a pipelined group sweeps beam step n0 + k
+// QSA_PIPE_LAG slices behind lane k - 1.  Beam particles only drift to larger
+// xi (1 - v_z > 0), so once lane k has finished slice jp + 3 it can push the
+// particles of beam slab jp (the particles the group's opening sort put in
+// cell rows (jp, *)) with its own fields and deposit them, now at step
+// n0 + k + 1, as the sources of lane k + 1, which reaches those slices
+// QSA_PIPE_LAG ticks later.  The push tags every particle with the shift d of
+// its new cell row from the row it is stored under (|d| <= QSA_PIPE_DY, in
+// slice cell jp); block l of the deposit then gathers the particles of rows
+// l - d tagged d, i.e. exactly the particles now in cell row (jp, l), into an
+// LDS tile of node slices (jp, jp+1) x node rows (l, l+1), stored to a
+// two-slab ring; node slice s of the next lane's sources is reduced from the
+// ring once slab s is in.  The rare particle outside that window deposits
+// with atomics straight from the push.  No counters, no atomics otherwise.
+//
+// The schedule holds while every particle of slab jp sits in
+// [jp - 3, jp + 3) cells when pushed; a violation sets ERR_DRIFT and the host
+// repeats the group from a copy of the beam.
+// ---------------------------------------------------------------------------
+#define QSA_PIPE_DY 2
+constexpr int PIPE_NO_TAG = 1 << 20;
+
+template <typename R>
+struct PipeBeam {
+  Geo<R> g;
+  int lag;                  // this lane's slice lag
+  int ns;
+  int dy;                   // row shifts gathered by the deposit (QSA_PIPE_DY, 0 for a slab)
+  R* x[4];
+  R* y[4];
+  double* xi[4];
+  R* ux[4];
+  R* uy[4];
+  R* uz[4];
+  R* w[4];
+  const int64_t* rowoff[4]; // slab partition [nxi*ny + 2]; rowoff[nxi*ny + 1] = particle count
+  int* tag[4];              // row shift of a pushed particle (PIPE_NO_TAG: none)
+  R qmh[4];                 // (Z/M) dt/2
+  R zq[4];                  // Z/(dx dy dxi)
+  R dt;
+  double inv_dxi;
+  double xi_max;
+  const R* fields;          // this lane's fields (the push)
+  R* ring_next;             // next lane's slab ring [2][ny][2][2][4][nx]
+  R* src_next;              // next lane's sources [4][nxi][ny][nx]
+  int* err;
+};
+
+// Atomic deposit of one particle into dense sources [4][nxi][ny][nx].
+template <typename R>
+__device__ __forceinline__ void dense_add(const Geo<R>& g, R* __restrict__ src, int jc, int i, int l, R fz, R fy,
+                                          R fx, const R (&v)[4]) {
+  const int64_t plane = (int64_t)g.nxi * g.nperp;
+  const int i1 = (i + 1 == g.nx) ? 0 : i + 1;
+  const R wz[2] = {R(1) - fz, fz}, wy[2] = {R(1) - fy, fy}, wx[2] = {R(1) - fx, fx};
+#pragma unroll
+  for (int dj = 0; dj < 2; ++dj) {
+    const int jj = jc + dj;
+    if (jj < 0 || jj >= g.nxi) continue;
+#pragma unroll
+    for (int dl = 0; dl < 2; ++dl) {
+      const int ll = (l + dl == g.ny) ? 0 : l + dl;
+      const R wc = wz[dj] * wy[dl];
+      R* base = src + (int64_t)jj * g.nperp + (int64_t)ll * g.nx;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        atomic_add(base + c * plane + i, v[c] * wc * wx[0]);
+        atomic_add(base + c * plane + i1, v[c] * wc * wx[1]);
+      }
+    }
+  }
+}
+
+// Push (and tag) particle p of species s stored under cell row (jp, lrow).
+template <typename R>
+__device__ __forceinline__ bool pipe_push_one(const PipeBeam<R>& B, int s, int64_t p, int jp, int lrow, bool slab,
+                                              bool feeds) {
+  const Geo<R>& g = B.g;
+  bool bad = false;
+  const double gz = B.xi[s][p] * B.inv_dxi;
+  if (slab) {
+    // fields are final up to slice jp + 3; a deposit must reach the next
+    // lane before it sweeps slice jp - 3
+    if (gz > -1.0 && gz < (double)g.nxi && gz >= (double)(jp + 3)) bad = true;
+    if (feeds && B.w[s][p] != R(0) && gz < (double)(jp - 3)) bad = true;
+  }
+  boris_one(g, B.fields, B.qmh[s], B.dt, B.inv_dxi, B.xi_max, B.x[s], B.y[s], B.xi[s], B.ux[s], B.uy[s], B.uz[s],
+            B.w[s], p);
+  if (!feeds) return bad;
+  const R w = B.w[s][p];
+  const double gn = B.xi[s][p] * B.inv_dxi;
+  const bool deposits = w != R(0) && gn > -1.0 && gn < (double)g.nxi;
+  if (!slab) return bad || deposits;   // not deposited for the next lane: must carry nothing
+  int tag = PIPE_NO_TAG;
+  if (deposits) {
+    int jc, i, l;
+    R fz, fy, fx, v[4];
+    beam_sources_of(g, B.x[s][p], B.y[s][p], B.xi[s][p], B.ux[s][p], B.uy[s][p], B.uz[s][p], B.zq[s] * w,
+                    B.inv_dxi, jc, i, l, fz, fy, fx, v);
+    int d = l - lrow;
+    if (d > (g.ny >> 1)) d -= g.ny;
+    if (d < -(g.ny >> 1)) d += g.ny;
+    if (jc == jp && d >= -B.dy && d <= B.dy) tag = d;
+    else dense_add(g, B.src_next, jc, i, l, fz, fy, fx, v);
+  }
+  B.tag[s][p] = tag;
+  return bad;
+}
+
+// Block l pushes the particles stored under cell row (jp, l); at the last
+// slab the blocks also share slab nxi - 1 and the out-of-grid tail.
+template <typename R>
+__global__ void __launch_bounds__(256) k_pipe_push(const PipeBeam<R>* __restrict__ tab, int tick, int nlanes) {
+  const PipeBeam<R>& B = tab[blockIdx.z];
+  const Geo<R>& g = B.g;
+  const int jp = tick - B.lag - QSA_PUSH_LAG;
+  const int l = blockIdx.x;
+  if (jp < 0 || jp > g.nxi - 2 || l >= g.ny) return;
+  const bool feeds = (int)blockIdx.z + 1 < nlanes;
+  const int64_t row = (int64_t)jp * g.ny + l;
+  bool bad = false;
+  for (int s = 0; s < B.ns; ++s) {
+    const int64_t p1 = B.rowoff[s][row + 1];
+    for (int64_t p = B.rowoff[s][row] + threadIdx.x; p < p1; p += blockDim.x)
+      bad |= pipe_push_one(B, s, p, jp, l, true, feeds);
+    if (jp == g.nxi - 2) {
+      const int64_t nrows = (int64_t)g.nxi * g.ny;
+      const int64_t t1 = B.rowoff[s][nrows + 1];
+      for (int64_t p = B.rowoff[s][(int64_t)(jp + 1) * g.ny] + (int64_t)l * blockDim.x + threadIdx.x; p < t1;
+           p += (int64_t)g.ny * blockDim.x)
+        bad |= pipe_push_one(B, s, p, jp, 0, false, feeds);
+    }
+  }
+  if (bad) atomicOr(B.err, ERR_DRIFT);
+}
+
+// Block l deposits the particles now in cell row (jp, l): those stored under
+// rows l - d and tagged d.
+template <typename R>
+__global__ void __launch_bounds__(256) k_pipe_deposit(const PipeBeam<R>* __restrict__ tab, int tick, int nlanes) {
+  if ((int)blockIdx.z + 1 >= nlanes) return;   // the last lane feeds no one
+  const PipeBeam<R>& B = tab[blockIdx.z];
+  const Geo<R>& g = B.g;
+  const int jp = tick - B.lag - QSA_PUSH_LAG;
+  const int l = blockIdx.x;
+  if (jp < 0 || jp > g.nxi - 2 || l >= g.ny) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* tile = reinterpret_cast<R*>(smem_raw);
+  const int tn = 2 * 2 * 4 * g.nx;
+  for (int i = threadIdx.x; i < tn; i += blockDim.x) tile[i] = R(0);
+  __syncthreads();
+  for (int s = 0; s < B.ns; ++s) {
+    for (int d = -B.dy; d <= B.dy; ++d) {
+      int src_row = l - d;
+      src_row += (src_row < 0) ? g.ny : 0;
+      src_row -= (src_row >= g.ny) ? g.ny : 0;
+      const int64_t row = (int64_t)jp * g.ny + src_row;
+      const int64_t q1 = B.rowoff[s][row + 1];
+      for (int64_t q = B.rowoff[s][row] + threadIdx.x; q < q1; q += blockDim.x) {
+        if (B.tag[s][q] != d) continue;
+        int jc, i, lc;
+        R fz, fy, fx, v[4];
+        beam_sources_of(g, B.x[s][q], B.y[s][q], B.xi[s][q], B.ux[s][q], B.uy[s][q], B.uz[s][q],
+                        B.zq[s] * B.w[s][q], B.inv_dxi, jc, i, lc, fz, fy, fx, v);
+        tile_add(tile, g.nx, jp, jc, i, fz, fy, fx, v);
+      }
+    }
+  }
+  __syncthreads();
+  R* out = B.ring_next + ((int64_t)(jp & 1) * g.ny + l) * tn;
+  for (int i = threadIdx.x; i < tn; i += blockDim.x) out[i] = tile[i];
+}
+
+// Node slice s of the next lane gets corner dj of slabs s - dj and corner k
+// of cell rows L - k; slab nxi - 1 deposits nothing.
+template <typename R>
+__device__ __forceinline__ void pipe_reduce_slice(const PipeBeam<R>& B, int s, int o) {
+  const Geo<R>& g = B.g;
+  const int L = o / g.nx, i = o - L * g.nx;
+  const int64_t plane = (int64_t)g.nxi * g.nperp;
+  const int tn = 2 * 2 * 4 * g.nx;
+  R acc[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int dj = 0; dj < 2; ++dj) {
+    const int sj = s - dj;
+    if (sj < 0 || sj > g.nxi - 2) continue;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      int ll = L - k;
+      ll = (g.ny == 1) ? 0 : ((ll < 0) ? ll + g.ny : ll);
+      const R* r = B.ring_next + ((int64_t)(sj & 1) * g.ny + ll) * tn + ((dj * 2 + k) * 4) * g.nx + i;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] += r[c * g.nx];
+    }
+  }
+  R* dst = B.src_next + (int64_t)s * g.nperp + o;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) dst[c * plane] += acc[c];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_pipe_reduce(const PipeBeam<R>* __restrict__ tab, int tick, int nlanes) {
+  if ((int)blockIdx.z + 1 >= nlanes) return;
+  const PipeBeam<R>& B = tab[blockIdx.z];
+  const Geo<R>& g = B.g;
+  const int jp = tick - B.lag - QSA_PUSH_LAG;
+  if (jp < 0 || jp > g.nxi - 2) return;
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= g.nperp) return;
+  pipe_reduce_slice(B, jp, o);
+  if (jp == g.nxi - 2) pipe_reduce_slice(B, jp + 1, o);   // the last node slice has no slab of its own
 }
 
 }  // namespace qsa

@@ -32,8 +32,8 @@ def _f64(a):
 def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt: float,
                 species: Sequence, n_plasma: int, plasma_w: float,
                 beam_capacity: Sequence[int], precision: str = "f64", n_corr: int = 3,
-                kappa2: float = 0.75) -> L.QSAParams:
-    """species: sequence of (Z, M)."""
+                kappa2: float = 0.75, pipeline: int = 1) -> L.QSAParams:
+    """species: sequence of (Z, M); pipeline: beam steps in flight (1 = off)."""
     p = L.QSAParams()
     p.nx, p.ny, p.nxi = nx, ny, nxi
     p.precision = _PREC[precision]
@@ -41,6 +41,7 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
     p.n_corr, p.kappa2 = n_corr, kappa2
     p.n_plasma, p.plasma_w = n_plasma, plasma_w
     p.n_species = len(species)
+    p.pipeline = int(pipeline)
     for i, (Z, M) in enumerate(species):
         p.species[i].Z = int(Z)
         p.species[i].M = float(M)
@@ -49,13 +50,14 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
 
 
 def params_from_workload(wl, precision: Optional[str] = None,
-                         beam_capacity: Optional[Sequence[int]] = None) -> L.QSAParams:
+                         beam_capacity: Optional[Sequence[int]] = None,
+                         pipeline: int = 1) -> L.QSAParams:
     """Parameters of a workload description (duck-typed: grid, species, loading)."""
     caps = beam_capacity or [wl.n_beam(s) for s in range(len(wl.species))]
     return make_params(wl.nx, wl.ny, wl.nxi, wl.dx, wl.dy, wl.dxi, wl.dt,
                        [(s.Z, s.M) for s in wl.species], wl.n_plasma,
                        wl.dx * wl.dy / wl.plasma_ppc, caps, precision or wl.precision,
-                       wl.n_corr, wl.kappa2)
+                       wl.n_corr, wl.kappa2, pipeline)
 
 
 class Sim:
@@ -135,6 +137,17 @@ class Sim:
     def set_graphs(self, enable: bool):
         """Replay captured HIP graphs (default) or enqueue every launch."""
         self._check(self.lib.qsa_set_option(self.ctx, 0, int(bool(enable))))
+
+    def set_pipeline(self, depth: int):
+        """Beam steps in flight (1 .. the pipeline parameter)."""
+        self._check(self.lib.qsa_set_option(self.ctx, 1, int(depth)))
+
+    @property
+    def pipeline(self) -> int:
+        """Beam steps in flight in use (1 after a drift fallback)."""
+        v = C.c_int64(0)
+        self._check(self.lib.qsa_get_option(self.ctx, 1, C.byref(v)))
+        return int(v.value)
 
     def timing_begin(self, kernel_class: str):
         """Time every launch of one kernel class with HIP events on the stream."""

@@ -66,3 +66,22 @@ def test_create_rejects_without_touching_the_device():
     need = lib.qsa_workspace_bytes(C.byref(p))
     assert lib.qsa_create(C.byref(p), C.c_void_p(256), need - 1, None, C.byref(ctx)) == -2
     assert lib.qsa_status_string(-4).decode().startswith("quasistatic breakdown")
+
+
+def test_pipeline_workspace_and_validation():
+    """Steps in flight hold one working set each (sources, fields, plasma
+    state) and a copy of the beam; depth 0 and 1 mean the same."""
+    from paper_2607_24214_amd import _lib as L
+    lib = L.lib()
+    one = lib.qsa_workspace_bytes(C.byref(_params()))
+    assert lib.qsa_workspace_bytes(C.byref(_params(pipeline=0))) == one
+    four = lib.qsa_workspace_bytes(C.byref(_params(pipeline=4)))
+    # three more sets of fields (7) and sources (4), and the beam copy
+    assert four >= one + 3 * (7 + 4) * 128 * 64 * 8 + 65024 * 7 * 8
+    assert lib.qsa_workspace_bytes(C.byref(_params(pipeline=9))) == 0
+    assert lib.qsa_workspace_bytes(C.byref(_params(pipeline=-1))) == 0
+    p = _params()
+    p.reserved_ = 1
+    assert lib.qsa_workspace_bytes(C.byref(p)) == 0
+    v = C.c_int64()
+    assert lib.qsa_get_option(None, 1, C.byref(v)) == -1
