@@ -18,6 +18,7 @@ same workload on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -28,6 +29,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_push_pred_cube256_f64.json")
+KERNEL_SOURCES = ("paper_2607_24214_amd/csrc/qsa_kernels.h", "paper_2607_24214_amd/csrc/qsa_device.h")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, precision: str, pipeline: int):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE record, if it was taken on the same
+    kernel sources and configuration; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if (rec.get("source_sha256") != kernel_source_hash() or rec.get("workload") != workload
+            or rec.get("precision") != precision or rec.get("steps_in_flight") != pipeline):
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def log(msg):
@@ -95,10 +121,16 @@ def main():
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--pipeline", type=int, default=8, help="beam steps in flight (1 = one at a time)")
+    ap.add_argument("--pre-steps", type=int, default=0,
+                    help="untimed beam steps after the warmup (time a more evolved beam)")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--workload", default="cube256")
     ap.add_argument("--cpu-slices", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="enqueue every launch instead of replaying HIP graphs (for counter runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 2 GiB three times (scale for HBM counters)")
     ap.add_argument("--breakdown", action="store_true",
                     help="also time every kernel class over one extra group of steps each")
     args = ap.parse_args()
@@ -110,6 +142,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": a.numel() * 8, "launches": 3}), flush=True)
+        return
     import qsa_workloads as W
     import paper_2607_24214_amd as Q
 
@@ -127,6 +168,8 @@ def main():
     for s, b in enumerate(beams):
         sim.load_beam(s, b)
     del beams
+    if args.no_graphs:
+        sim.set_graphs(False)
     log(f"loaded; workspace {sim.ws_bytes / 2**30:.2f} GiB")
 
     # warmup
@@ -134,15 +177,11 @@ def main():
     sim.beam_step(args.warmup)
     sim.sync()
     log(f"warmup {args.warmup} steps: {time.perf_counter() - t:.2f} s")
-
-    breakdown = {}
-    if args.breakdown:
-        for kc in ("push_pred", "push_final", "dep_S", "dep_J", "row_r2c", "col", "row_c2r",
-                   "beam_deposit", "beam_push"):
-            nst = max(1, args.pipeline)
-            ms, n = timed_step(sim, kc, nst)
-            breakdown[kc] = {"ms_per_step": ms / nst, "launches": n, "us_per_launch": 1e3 * ms / max(n, 1)}
-            log(f"  {kc:13s} {ms / nst:9.2f} ms/step  {n:6d} launches  {1e3 * ms / max(n, 1):8.2f} us/launch")
+    if args.pre_steps:
+        t = time.perf_counter()
+        sim.beam_step(args.pre_steps)
+        sim.sync()
+        log(f"{args.pre_steps} further untimed steps: {time.perf_counter() - t:.2f} s")
 
     dominant = "push_pred"
     # the step graphs (a whole group when pipelined) are captured here,
@@ -160,8 +199,9 @@ def main():
     # the dominant kernel's launch duration: HIP events around each of its
     # launches over the same number of steps, enqueued launch by launch
     dom_ms, dom_n = timed_step(sim, dominant, args.steps)
-    timing_note = ("HIP events on the library's work stream around every launch of the kernel, "
-                   f"over {args.steps} steps enqueued launch by launch right after the timed region")
+    timing_note = ("HIP events recorded at the start and end of every launch of the kernel "
+                   "(hipExtLaunchKernelGGL on the library's work stream), over "
+                   f"{args.steps} steps enqueued launch by launch right after the timed region")
     T = t1 - t0
     ms_step = 1e3 * T / args.steps
     updates = wl.n_plasma * wl.nxi * args.steps
@@ -178,6 +218,17 @@ def main():
     torch.cuda.synchronize()
     t_sweep = time.perf_counter() - t
 
+    # per-class times over further groups of steps (after the timed region,
+    # which they would otherwise move to a later, more evolved beam)
+    breakdown = {}
+    if args.breakdown:
+        for kc in ("push_pred", "push_final", "dep_S", "dep_J", "row_r2c", "col", "row_c2r",
+                   "beam_deposit", "beam_push"):
+            nst = max(1, args.pipeline)
+            ms, n = timed_step(sim, kc, nst)
+            breakdown[kc] = {"ms_per_step": ms / nst, "launches": n, "us_per_launch": 1e3 * ms / max(n, 1)}
+            log(f"  {kc:13s} {ms / nst:9.2f} ms/step  {n:6d} launches  {1e3 * ms / max(n, 1):8.2f} us/launch")
+
     avg_s = dom_ms / 1e3 / max(dom_n, 1)
     # one launch advances every step in flight by a slice: algorithmic bytes
     # per launch = per-slice bytes x lane-slices the launches covered / launches
@@ -185,9 +236,11 @@ def main():
     per_launch = alg_bytes(dominant, wl, rsize) * lane_slices / max(dom_n, 1)
     achieved = per_launch / avg_s / 1e9
     roofline = {
-        "kernel": "k_push<predictor> (plasma RK2 push + predicted J_perp deposit)",
+        "kernel": (f"k_plasma_rows<{'double' if rsize == 8 else 'float'}, 2> (predictor: plasma RK2 push "
+                   "+ predicted J_perp deposit)"),
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": measured_traffic(wl.name, args.precision, max(1, args.pipeline)),
         "avg_launch_us": avg_s * 1e6, "launches_timed": dom_n,
         "timing": timing_note,
         "alg_bytes_per_launch": per_launch,

@@ -4,6 +4,7 @@
 // the host-side state (loaded particle counts, error state) and enqueues the
 // kernels of qsa_kernels.h on the caller's stream.  One sweep is
 // 4 + 4 + 4K + 1 dependent launches per xi slice.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,6 +40,8 @@ struct SetLayout {
   size_t cell_of, count, bsum, prow, ppart;
   size_t src, fields, dep, rowspec, colout, jring, jz, bring, ode;
   size_t ring;   // slab ring of the deposits this set receives from the lane before it
+  size_t hist;   // new-row count matrix of this set's slab pushes, and row starts
+  size_t base;
 };
 
 // Byte offsets of every device array inside the workspace.
@@ -48,7 +51,7 @@ struct Layout {
   int nset;                         // working sets (beam steps in flight)
   SetLayout set[QSA_MAX_PIPELINE];
   size_t rowoff[QSA_MAX_SPECIES];   // slab partition of the sorted beam (pipelining)
-  size_t doff[QSA_MAX_SPECIES];     // row offsets into perm of the current deposit
+  size_t doff[QSA_MAX_SPECIES];     // sort-key offsets into perm of the current deposit
   size_t key[QSA_MAX_SPECIES], perm[QSA_MAX_SPECIES];
   size_t cursor, scan64, bpart;
   size_t beam[QSA_MAX_SPECIES][8];  // x, y, ux, uy, uz, w (real), xi (double), id (int64, pipelining)
@@ -105,17 +108,20 @@ Layout make_layout(const qsa_params& p) {
     S.ode = c.take(2 * sizeof(double));
     // two slabs x ny cell rows x (2 node slices x 2 node rows x 4 sources x nx)
     S.ring = (k > 0) ? c.take(2 * (size_t)p.ny * 2 * 2 * 4 * p.nx * rs) : 0;
+    S.hist = (L.nset > 1) ? c.take((size_t)QSA_MAX_SPECIES * p.ny * p.ny * sizeof(int)) : 0;
+    S.base = (L.nset > 1) ? c.take((size_t)QSA_MAX_SPECIES * (p.ny + 1) * sizeof(int)) : 0;
   }
   const size_t nrows = (size_t)p.nxi * p.ny;
+  const size_t nkeys = nrows * (p.nx / QSA_BEAM_XCHUNK) + 1;   // sort keys, the last for inert particles
   for (int s = 0; s < QSA_MAX_SPECIES; ++s) {
     const size_t cap = (s < p.n_species) ? (size_t)p.beam_capacity[s] : 0;
     L.rowoff[s] = c.take((nrows + 2) * sizeof(int64_t));
-    L.doff[s] = c.take((nrows + 2) * sizeof(int64_t));
+    L.doff[s] = c.take((nkeys + 2) * sizeof(int64_t));
     L.key[s] = c.take(cap * sizeof(int));
     L.perm[s] = c.take(cap * sizeof(int));
   }
-  L.cursor = c.take((nrows + 2) * sizeof(int64_t));
-  L.scan64 = c.take(((nrows + 2) / 1024 + 8) * 2 * sizeof(int64_t));
+  L.cursor = c.take((nkeys + 2) * sizeof(int64_t));
+  L.scan64 = c.take(((nkeys + 2) / 1024 + 64) * 2 * sizeof(int64_t));
   L.bpart = c.take(nrows * 2 * 2 * 4 * (size_t)p.nx * rs);
   for (int s = 0; s < QSA_MAX_SPECIES; ++s) {
     const size_t cap = (s < p.n_species) ? (size_t)p.beam_capacity[s] : 0;
@@ -150,7 +156,8 @@ const char* validate(const qsa_params* p) {
   if (p->n_plasma <= 0 || p->n_plasma > (int64_t)1 << 30) return "n_plasma must be in [1, 2^30]";
   if (!(p->plasma_w > 0)) return "plasma_w must be > 0";
   if (p->n_species < 1 || p->n_species > QSA_MAX_SPECIES) return "n_species must be in [1, 4]";
-  if ((int64_t)p->nxi * p->ny > ((int64_t)1 << 30)) return "nxi * ny must be <= 2^30";
+  if ((int64_t)p->nxi * p->ny * (p->nx / QSA_BEAM_XCHUNK) > ((int64_t)1 << 30))
+    return "nxi * ny * nx / 8 must be <= 2^30";
   if (p->pipeline < 0 || p->pipeline > QSA_MAX_PIPELINE) return "pipeline must be in [0, 8]";
   if (p->reserved_ != 0) return "reserved_ must be 0";
   for (int s = 0; s < p->n_species; ++s) {
@@ -186,20 +193,31 @@ struct qsa_ctx {
   size_t ev_used = 0;
   template <typename T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
-  void tstart(int k) {
-    if (k != timing_class) return;
-    if (ev_used + 2 > events.size()) {
-      if (events.size() >= (size_t)2 << 17) return;
-      hipEvent_t a, b;
-      if (hipEventCreate(&a) != hipSuccess) return;
-      if (hipEventCreate(&b) != hipSuccess) {
-        (void)hipEventDestroy(a);
-        return;
-      }
-      events.push_back(a);
-      events.push_back(b);
+  bool event_pair() {
+    if (ev_used + 2 <= events.size()) return true;
+    if (events.size() >= (size_t)2 << 17) return false;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return false;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return false;
     }
+    events.push_back(a);
+    events.push_back(b);
+    return true;
+  }
+  void tstart(int k) {
+    if (k != timing_class || !event_pair()) return;
     (void)hipEventRecord(events[ev_used], stream);
+  }
+  // Events for one launch of class k when that class is timed: the launch
+  // records them at the kernel's own start and end.
+  bool timing_pair(int k, hipEvent_t* a, hipEvent_t* b) {
+    if (k != timing_class || !event_pair()) return false;
+    *a = events[ev_used];
+    *b = events[ev_used + 1];
+    ev_used += 2;
+    return true;
   }
   void tstop(int k) {
     if (k != timing_class || ev_used + 2 > events.size()) return;
@@ -242,6 +260,17 @@ struct qsa_batch {
     if (stream) (void)hipStreamDestroy(stream);
   }
 };
+
+// Launch a kernel; when its class is being timed, with events recorded at
+// the kernel's own start and end.
+#define QSA_LAUNCH(ctx, cls, kern, grid, block, shmem, st, ...)                      \
+  do {                                                                               \
+    hipEvent_t qe0_ = nullptr, qe1_ = nullptr;                                       \
+    if ((ctx)->timing_pair((cls), &qe0_, &qe1_))                                     \
+      hipExtLaunchKernelGGL(kern, grid, block, shmem, st, qe0_, qe1_, 0, __VA_ARGS__); \
+    else                                                                             \
+      hipLaunchKernelGGL(kern, grid, block, shmem, st, __VA_ARGS__);                 \
+  } while (0)
 
 static qsa_status fail(qsa_ctx* c, qsa_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -375,23 +404,23 @@ struct Engine {
     return QSA_OK;
   }
 
-  // Cell-row keys of species s and their exclusive row offsets in doff[s];
+  // Sort keys of species s and their exclusive offsets in doff[s];
   // cursor <- doff[s].
   static qsa_status keys(qsa_ctx* c, int s) {
     const qsa_params& p = c->p;
     const Geo<R> g = geo(p);
-    const int64_t nrows = (int64_t)p.nxi * p.ny;
+    const int64_t nkeys = (int64_t)p.nxi * p.ny * (p.nx / QSA_BEAM_XCHUNK) + 1;
     int64_t* off = c->at<int64_t>(c->L.doff[s]);
-    hipLaunchKernelGGL(k_fill<int64_t>, dim3(fill_blocks(nrows + 2)), dim3(256), 0, c->stream, off, nrows + 2,
+    hipLaunchKernelGGL(k_fill<int64_t>, dim3(fill_blocks(nkeys + 1)), dim3(256), 0, c->stream, off, nkeys + 1,
                        (int64_t)0);
     const int64_t n = c->beam_n[s];
     if (n > 0)
       hipLaunchKernelGGL(k_beam_keys<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
                          beam_dep_args(c), s, n, off);
     HIP_OK(hipGetLastError());
-    qsa_status st = scan64(c, off, nrows + 2, c->at<int64_t>(c->L.scan64));
+    qsa_status st = scan64(c, off, nkeys + 1, c->at<int64_t>(c->L.scan64));
     if (st != QSA_OK) return st;
-    HIP_OK(hipMemcpyAsync(c->ws + c->L.cursor, off, (nrows + 2) * sizeof(int64_t), hipMemcpyDeviceToDevice,
+    HIP_OK(hipMemcpyAsync(c->ws + c->L.cursor, off, (nkeys + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
                           c->stream));
     return QSA_OK;
   }
@@ -405,8 +434,9 @@ struct Engine {
     const int64_t n = c->beam_n[s];
     qsa_status st = keys(c, s);
     if (st != QSA_OK) return st;
-    HIP_OK(hipMemcpyAsync(c->ws + L.rowoff[s], c->ws + L.doff[s], (nrows + 2) * sizeof(int64_t),
-                          hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(k_row_starts<R>, dim3((unsigned)((nrows + 2 + 255) / 256)), dim3(256), 0, c->stream,
+                       geo(p), (const int64_t*)c->at<int64_t>(L.doff[s]), c->at<int64_t>(L.rowoff[s]));
+    HIP_OK(hipGetLastError());
     if (n == 0) return QSA_OK;
     BeamMove<R> m;
     for (int k = 0; k < 6; ++k) {
@@ -462,9 +492,8 @@ struct Engine {
     }
     const BeamDepArgs<R> a = beam_dep_args(c);
     const int nrows = p.nxi * p.ny;
-    c->tstart(QSA_K_BEAM_DEPOSIT);
-    hipLaunchKernelGGL(k_beam_rows<R>, dim3(nrows), dim3(256), 2 * 2 * 4 * g.nx * sizeof(R), c->stream, g, a);
-    c->tstop(QSA_K_BEAM_DEPOSIT);
+    QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_beam_rows<R>, dim3(nrows), dim3(256), 2 * 2 * 4 * g.nx * sizeof(R),
+               c->stream, g, a);
     const int64_t plane = (int64_t)p.nxi * g.nperp;
     hipLaunchKernelGGL(k_beam_reduce<R>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, c->stream, g,
                        (const R*)a.bpart, c->at<R>(c->L.set[0].src));
@@ -545,7 +574,6 @@ struct Engine {
     a.g = geo(p);
     a.lag = k * QSA_PIPE_LAG;
     a.ns = p.n_species;
-    a.dy = (p.ny == 1) ? 0 : QSA_PIPE_DY;
     for (int s = 0; s < p.n_species; ++s) {
       a.x[s] = c->at<R>(L.beam[s][0]);
       a.y[s] = c->at<R>(L.beam[s][1]);
@@ -556,6 +584,7 @@ struct Engine {
       a.xi[s] = c->at<double>(L.beam[s][6]);
       a.rowoff[s] = c->at<int64_t>(L.rowoff[s]);
       a.tag[s] = c->at<int>(L.key[s]);
+      a.perm[s] = c->at<int>(L.perm[s]);
       a.qmh[s] = (R)((double)p.species[s].Z / p.species[s].M * 0.5 * p.dt);
       a.zq[s] = (R)(p.species[s].Z / (p.dx * p.dy * p.dxi));
     }
@@ -563,6 +592,8 @@ struct Engine {
     a.inv_dxi = 1.0 / p.dxi;
     a.xi_max = (double)(p.nxi - 1) * p.dxi;
     a.fields = c->at<R>(L.set[k].fields);
+    a.hist = L.set[k].hist ? c->at<int>(L.set[k].hist) : nullptr;
+    a.base = L.set[k].base ? c->at<int>(L.set[k].base) : nullptr;
     if (k + 1 < L.nset) {
       a.ring_next = c->at<R>(L.set[k + 1].ring);
       a.src_next = c->at<R>(L.set[k + 1].src);
@@ -635,56 +666,31 @@ struct Engine {
       const dim3 rgrid_psi(d.rows_r2c, 1, n), rgrid_j(d.rows_r2c, 3, n), rgrid_b(d.rows_r2c, 2, n);
       const dim3 rblock(d.rt_rows);
       // ---- psi stage
-      tc->tstart(QSA_K_DEP_S);
-      hipLaunchKernelGGL((k_plasma_rows<R, PL_DEP_S>), dim3(d.ny, 1, n), dim3(nt),
+      QSA_LAUNCH(tc, QSA_K_DEP_S, (k_plasma_rows<R, PL_DEP_S>), dim3(d.ny, 1, n), dim3(nt),
                          4 * 1 * (size_t)d.nx * sizeof(R), st, lanes, j);
-      tc->tstop(QSA_K_DEP_S);
-      tc->tstart(QSA_K_ROW_R2C);
-      hipLaunchKernelGGL(k_row_r2c<R>, rgrid_psi, rblock, smem_rows, st, lanes, j, (int)ST_PSI);
-      tc->tstop(QSA_K_ROW_R2C);
-      tc->tstart(QSA_K_COL);
-      hipLaunchKernelGGL((k_col<R, COL_PSI>), dim3(d.cols[0], 1, n), dim3(64 * ColShape<COL_PSI>::G),
+      QSA_LAUNCH(tc, QSA_K_ROW_R2C, k_row_r2c<R>, rgrid_psi, rblock, smem_rows, st, lanes, j, (int)ST_PSI);
+      QSA_LAUNCH(tc, QSA_K_COL, (k_col<R, COL_PSI>), dim3(d.cols[0], 1, n), dim3(64 * ColShape<COL_PSI>::G),
                          d.smem_col[0], st, lanes, j);
-      tc->tstop(QSA_K_COL);
-      tc->tstart(QSA_K_ROW_C2R);
-      hipLaunchKernelGGL(k_row_c2r<R>, dim3(d.rows_r2c, 3, n), rblock, smem_rows, st, lanes, j, (int)ST_PSI);
-      tc->tstop(QSA_K_ROW_C2R);
+      QSA_LAUNCH(tc, QSA_K_ROW_C2R, k_row_c2r<R>, dim3(d.rows_r2c, 3, n), rblock, smem_rows, st, lanes, j,
+                 (int)ST_PSI);
       // ---- J stage
-      tc->tstart(QSA_K_DEP_J);
-      hipLaunchKernelGGL((k_plasma_rows<R, PL_DEP_J>), dim3(d.ny, 1, n), dim3(nt),
+      QSA_LAUNCH(tc, QSA_K_DEP_J, (k_plasma_rows<R, PL_DEP_J>), dim3(d.ny, 1, n), dim3(nt),
                          4 * 3 * (size_t)d.nx * sizeof(R), st, lanes, j);
-      tc->tstop(QSA_K_DEP_J);
-      tc->tstart(QSA_K_ROW_R2C);
-      hipLaunchKernelGGL(k_row_r2c<R>, rgrid_j, rblock, smem_rows, st, lanes, j, (int)ST_J);
-      tc->tstop(QSA_K_ROW_R2C);
-      tc->tstart(QSA_K_COL);
-      hipLaunchKernelGGL((k_col<R, COL_J>), dim3(d.cols[1], 1, n), dim3(64 * ColShape<COL_J>::G),
+      QSA_LAUNCH(tc, QSA_K_ROW_R2C, k_row_r2c<R>, rgrid_j, rblock, smem_rows, st, lanes, j, (int)ST_J);
+      QSA_LAUNCH(tc, QSA_K_COL, (k_col<R, COL_J>), dim3(d.cols[1], 1, n), dim3(64 * ColShape<COL_J>::G),
                          d.smem_col[1], st, lanes, j);
-      tc->tstop(QSA_K_COL);
-      tc->tstart(QSA_K_ROW_C2R);
-      hipLaunchKernelGGL(k_row_c2r<R>, dim3(d.rows_r2c, 4, n), rblock, smem_rows, st, lanes, j, (int)ST_J);
-      tc->tstop(QSA_K_ROW_C2R);
+      QSA_LAUNCH(tc, QSA_K_ROW_C2R, k_row_c2r<R>, dim3(d.rows_r2c, 4, n), rblock, smem_rows, st, lanes, j, (int)ST_J);
       // ---- B_perp predictor-corrector
       for (int k = 0; k < d.n_corr; ++k) {
-        tc->tstart(QSA_K_PUSH_PRED);
-        hipLaunchKernelGGL((k_plasma_rows<R, PL_PRED>), dim3(d.ny, 1, n), dim3(nt),
+        QSA_LAUNCH(tc, QSA_K_PUSH_PRED, (k_plasma_rows<R, PL_PRED>), dim3(d.ny, 1, n), dim3(nt),
                            4 * 2 * (size_t)d.nx * sizeof(R), st, lanes, j);
-        tc->tstop(QSA_K_PUSH_PRED);
-        tc->tstart(QSA_K_ROW_R2C);
-        hipLaunchKernelGGL(k_row_r2c<R>, rgrid_b, rblock, smem_rows, st, lanes, j, (int)ST_B);
-        tc->tstop(QSA_K_ROW_R2C);
-        tc->tstart(QSA_K_COL);
-        hipLaunchKernelGGL((k_col<R, COL_B>), dim3(d.cols[2], 1, n), dim3(64 * ColShape<COL_B>::G),
+        QSA_LAUNCH(tc, QSA_K_ROW_R2C, k_row_r2c<R>, rgrid_b, rblock, smem_rows, st, lanes, j, (int)ST_B);
+        QSA_LAUNCH(tc, QSA_K_COL, (k_col<R, COL_B>), dim3(d.cols[2], 1, n), dim3(64 * ColShape<COL_B>::G),
                            d.smem_col[2], st, lanes, j);
-        tc->tstop(QSA_K_COL);
-        tc->tstart(QSA_K_ROW_C2R);
-        hipLaunchKernelGGL(k_row_c2r<R>, rgrid_b, rblock, smem_rows, st, lanes, j, (int)ST_B);
-        tc->tstop(QSA_K_ROW_C2R);
+        QSA_LAUNCH(tc, QSA_K_ROW_C2R, k_row_c2r<R>, rgrid_b, rblock, smem_rows, st, lanes, j, (int)ST_B);
       }
       // ---- advance the plasma to slice j+1
-      tc->tstart(QSA_K_PUSH_FINAL);
-      hipLaunchKernelGGL(k_push_final<R>, dim3(pb, 1, n), dim3(256), 0, st, lanes, j);
-      tc->tstop(QSA_K_PUSH_FINAL);
+      QSA_LAUNCH(tc, QSA_K_PUSH_FINAL, k_push_final<R>, dim3(pb, 1, n), dim3(256), 0, st, lanes, j);
     }
     return QSA_OK;
   }
@@ -728,9 +734,7 @@ struct Engine {
       if (c->beam_n[s] == 0) continue;
       BeamArgs<R> a = beam_args(c, g, s);
       const int64_t blocks = (a.n + 255) / 256;
-      c->tstart(QSA_K_BEAM_PUSH);
-      hipLaunchKernelGGL(k_beam_push<R>, dim3((unsigned)blocks), dim3(256), 0, c->stream, g, a);
-      c->tstop(QSA_K_BEAM_PUSH);
+      QSA_LAUNCH(c, QSA_K_BEAM_PUSH, k_beam_push<R>, dim3((unsigned)blocks), dim3(256), 0, c->stream, g, a);
     }
     HIP_OK(hipGetLastError());
     return QSA_OK;
@@ -760,13 +764,12 @@ struct Engine {
       if (t % QSA_PIPE_LAG == 0 && t < n * QSA_PIPE_LAG) clear_lanes(c->stream, lanes, d, t);
       if ((st = tick(c, c->stream, lanes, d, t)) != QSA_OK) return st;
       if (t < QSA_PUSH_LAG) continue;
-      c->tstart(QSA_K_BEAM_PUSH);
-      hipLaunchKernelGGL(k_pipe_push<R>, dim3(g.ny, 1, n), dim3(256), 0, c->stream, pipes, t, n);
-      c->tstop(QSA_K_BEAM_PUSH);
-      c->tstart(QSA_K_BEAM_DEPOSIT);
-      hipLaunchKernelGGL(k_pipe_deposit<R>, dim3(g.ny, 1, n - 1), dim3(256), tile, c->stream, pipes, t, n);
+      QSA_LAUNCH(c, QSA_K_BEAM_PUSH, k_pipe_push<R>, dim3(g.ny, 1, n), dim3(256), 0, c->stream, pipes, t, n);
+      hipLaunchKernelGGL(k_pipe_scan<R>, dim3(1, 1, n - 1), dim3(512), 0, c->stream, pipes, t, n);
+      hipLaunchKernelGGL(k_pipe_place<R>, dim3(g.ny, 1, n - 1), dim3(256), 0, c->stream, pipes, t, n);
+      QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_pipe_deposit<R>, dim3(g.ny, 1, n - 1), dim3(256), tile, c->stream, pipes,
+                 t, n);
       hipLaunchKernelGGL(k_pipe_reduce<R>, dim3(nperp_blocks, 1, n - 1), dim3(256), 0, c->stream, pipes, t, n);
-      c->tstop(QSA_K_BEAM_DEPOSIT);
     }
     HIP_OK(hipGetLastError());
     c->swept = true;

@@ -586,9 +586,15 @@ __device__ __forceinline__ PlasmaArgs<R> plasma_args(const Lane<R>& L, int j) {
   return a;
 }
 
-// Particle p of block b: the blocks of one XCD take consecutive chunks.
-__device__ __forceinline__ int plasma_index() {
-  return xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+// Lane and block within it for a launch of gridDim.x blocks per lane and
+// gridDim.z lanes: workgroups go round-robin to the 8 XCDs in linear order,
+// so the linear index is remapped for each XCD to take consecutive blocks of
+// as few lanes as possible, keeping the fields its blocks gather in its L2.
+__device__ __forceinline__ void lane_block(int& lane, int& b) {
+  const int per = gridDim.x;
+  const int lg = xcd_block(blockIdx.x + blockIdx.z * per, per * gridDim.z);
+  lane = lg / per;
+  b = lg - lane * per;
 }
 
 // d/dxi of (x, y, u_x, u_y) from the six gathered fields
@@ -692,14 +698,15 @@ __device__ __forceinline__ void row_tile_add(const Geo<R>& g, R* tile, int r, in
 template <typename R, int MODE>
 __global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__ lanes, int tick) {
   constexpr int NC = PlasmaNC<MODE>::NC;
-  const Lane<R>& L = lanes[blockIdx.z];
+  int lane, r;
+  lane_block(lane, r);
+  const Lane<R>& L = lanes[lane];
   const int j = tick - L.lag;
   const Geo<R> g = L.g;
-  if (j < 0 || j >= g.nxi || (int)blockIdx.x >= g.ny) return;
+  if (j < 0 || j >= g.nxi || r >= g.ny) return;
   const PlasmaArgs<R> a = plasma_args(L, j);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
-  const int r = blockIdx.x;
   const int nt = blockDim.x, tid = threadIdx.x;
   const int tn = 4 * NC * g.nx;
   for (int t = tid; t < tn; t += nt) tile[t] = R(0);
@@ -795,11 +802,13 @@ __global__ void k_row_offsets(const Lane<R>* __restrict__ lanes, int tick) {
 // Final advance: Y^{j+1} with the converged fields, positions wrapped.
 template <typename R>
 __global__ void __launch_bounds__(256) k_push_final(const Lane<R>* __restrict__ lanes, int tick) {
-  const Lane<R>& L = lanes[blockIdx.z];
+  int lane, b;
+  lane_block(lane, b);
+  const Lane<R>& L = lanes[lane];
   const int j = tick - L.lag;
   const Geo<R> g = L.g;
   if (j < 0 || j >= g.nxi) return;
-  const int p = plasma_index();
+  const int p = b * blockDim.x + threadIdx.x;
   if (p >= L.np) return;
   const PlasmaArgs<R> a = plasma_args(L, j);
   R xn, yn, uxn, uyn;
@@ -980,19 +989,37 @@ __device__ __forceinline__ T wave_run_add(T* cnt, int key, bool active) {
   return base + (T)(lane - head);
 }
 
-// Cell-row key of a beam particle: row (j, l), j = floor(xi/dxi), where a
-// particle with j = -1 (node slice 0 only) counts as row (0, l); nxi*ny for a
-// particle without a node in the grid or with nothing to deposit (w = 0).
+// Sort key of a beam particle: cell row (j, l), j = floor(xi/dxi), then the
+// chunk of QSA_BEAM_XCHUNK cells along x holding its cell, so that a
+// wavefront of sorted particles gathers and deposits around a few cells.  A
+// particle with j = -1 (node slice 0 only) counts as row (0, l); nxi*ny*nxc
+// for a particle without a node in the grid or with nothing to deposit.
+#define QSA_BEAM_XCHUNK 8
+template <typename R>
+__device__ __forceinline__ int nx_chunks(const Geo<R>& g) { return g.nx / QSA_BEAM_XCHUNK; }
 template <typename R>
 __device__ __forceinline__ int beam_key(const Geo<R>& g, R x, R y, double xi, R w, double inv_dxi) {
+  const int nxc = nx_chunks(g);
   const double gz = xi * inv_dxi;
-  if (w == R(0) || !(gz > -1.0 && gz < (double)g.nxi)) return g.nxi * g.ny;
+  if (w == R(0) || !(gz > -1.0 && gz < (double)g.nxi)) return g.nxi * g.ny * nxc;
   int j = (int)floor(gz);
   j = j < 0 ? 0 : j;
   int i, l;
   R fx, fy;
   cell2(g, x, y, i, l, fx, fy);
-  return j * g.ny + l;
+  return (j * g.ny + l) * nxc + i / QSA_BEAM_XCHUNK;
+}
+
+// Start of every cell row among the chunk offsets: rowoff[b] = off[b*nxc]
+// for b <= nrows, and the particle count after them.
+template <typename R>
+__global__ void __launch_bounds__(256) k_row_starts(Geo<R> g, const int64_t* __restrict__ off,
+                                                    int64_t* __restrict__ rowoff) {
+  const int64_t nrows = (int64_t)g.nxi * g.ny;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nxc = nx_chunks(g);
+  if (b <= nrows) rowoff[b] = off[b * nxc];
+  if (b == nrows + 1) rowoff[b] = off[nrows * nxc + 1];
 }
 
 template <typename R>
@@ -1007,7 +1034,8 @@ struct BeamDepArgs {
   const R* w[4];
   int* key[4];                // per particle: cell-row key
   int* perm[4];               // particles of each cell row, row after row
-  const int64_t* doff[4];     // [nxi*ny + 2]: row b's particles are perm[doff[b] .. doff[b+1])
+  const int64_t* doff[4];     // chunk offsets [nxi*ny*nxc + 2]: row b's particles are
+                              // perm[doff[b*nxc] .. doff[(b+1)*nxc])
   R zq[4];                    // Z/(dx dy dxi)
   R* bpart;                   // partial node rows [nxi*ny][2][2][4][nx]
   double inv_dxi;
@@ -1095,8 +1123,9 @@ __global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a) {
   for (int t = threadIdx.x; t < tn; t += blockDim.x) tile[t] = R(0);
   __syncthreads();
   for (int s = 0; s < a.ns; ++s) {
-    const int64_t q1 = a.doff[s][b + 1];
-    for (int64_t q = a.doff[s][b] + threadIdx.x; q < q1; q += blockDim.x) {
+    const int nxc = nx_chunks(g);
+    const int64_t q1 = a.doff[s][(int64_t)(b + 1) * nxc];
+    for (int64_t q = a.doff[s][(int64_t)b * nxc] + threadIdx.x; q < q1; q += blockDim.x) {
       const int p = a.perm[s][q];
       int jc, i, l;
       R fz, fy, fx, v[4];
@@ -1279,28 +1308,29 @@ __global__ void __launch_bounds__(256) k_beam_push(Geo<R> g, BeamArgs<R> a) {
 // particles of beam slab jp (the particles the group's opening sort put in
 // cell rows (jp, *)) with its own fields and deposit them, now at step
 // n0 + k + 1, as the sources of lane k + 1, which reaches those slices
-// QSA_PIPE_LAG ticks later.  The push tags every particle with the shift d of
-// its new cell row from the row it is stored under (|d| <= QSA_PIPE_DY, in
-// slice cell jp); block l of the deposit then gathers the particles of rows
-// l - d tagged d, i.e. exactly the particles now in cell row (jp, l), into an
-// LDS tile of node slices (jp, jp+1) x node rows (l, l+1), stored to a
+// QSA_PIPE_LAG ticks later.
+//
+// Per tick and lane the slab's particles are counting-sorted by their new
+// cell row, without global atomics: block l of the push takes the particles
+// stored under cell row (jp, l), ranks them per new row in LDS and writes
+// its row of the count matrix hist[l][L]; one block per lane scans the
+// matrix (start of new row L, and of source row l's share in it); the place
+// pass writes every particle's index to its slot of perm; block L of the
+// deposit then reads exactly the particles now in cell row (jp, L) into an
+// LDS tile of node slices (jp, jp+1) x node rows (L, L+1), stored to a
 // two-slab ring; node slice s of the next lane's sources is reduced from the
-// ring once slab s is in.  The rare particle outside that window deposits
-// with atomics straight from the push.  No counters, no atomics otherwise.
+// ring once slab s is in.  A particle that left slice cell jp (rare: the
+// drift in xi is slow) deposits with atomics straight from the push.
 //
 // The schedule holds while every particle of slab jp sits in
 // [jp - 3, jp + 3) cells when pushed; a violation sets ERR_DRIFT and the host
 // repeats the group from a copy of the beam.
 // ---------------------------------------------------------------------------
-#define QSA_PIPE_DY 2
-constexpr int PIPE_NO_TAG = 1 << 20;
-
 template <typename R>
 struct PipeBeam {
   Geo<R> g;
   int lag;                  // this lane's slice lag
   int ns;
-  int dy;                   // row shifts gathered by the deposit (QSA_PIPE_DY, 0 for a slab)
   R* x[4];
   R* y[4];
   double* xi[4];
@@ -1309,13 +1339,16 @@ struct PipeBeam {
   R* uz[4];
   R* w[4];
   const int64_t* rowoff[4]; // slab partition [nxi*ny + 2]; rowoff[nxi*ny + 1] = particle count
-  int* tag[4];              // row shift of a pushed particle (PIPE_NO_TAG: none)
+  int* tag[4];              // new row and rank of a pushed particle (-1: none)
+  int* perm[4];             // the slab's particles by new row
   R qmh[4];                 // (Z/M) dt/2
   R zq[4];                  // Z/(dx dy dxi)
   R dt;
   double inv_dxi;
   double xi_max;
   const R* fields;          // this lane's fields (the push)
+  int* hist;                // [4 species][ny source rows][ny new rows]: counts, then slots
+  int* base;                // [4 species][ny + 1]: start of each new row in the slab
   R* ring_next;             // next lane's slab ring [2][ny][2][2][4][nx]
   R* src_next;              // next lane's sources [4][nxi][ny][nx]
   int* err;
@@ -1346,12 +1379,36 @@ __device__ __forceinline__ void dense_add(const Geo<R>& g, R* __restrict__ src, 
   }
 }
 
-// Push (and tag) particle p of species s stored under cell row (jp, lrow).
+// Rank of each active lane among the lanes of its wavefront and of earlier
+// calls with the same class c (LDS counters cnt[c]): one LDS atomic per class
+// present in the wavefront.  All 64 lanes must call it together.
+__device__ __forceinline__ int wave_class_rank(int* cnt, int c, bool act) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long rem = __ballot(act);
+  int rank = 0;
+  while (rem) {
+    const int leader = __ffsll((long long)rem) - 1;
+    const int cl = __shfl(c, leader);
+    const bool mine = act && c == cl;
+    const unsigned long long m = __ballot(mine);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cnt + cl, __popcll(m));
+    base = __shfl(base, leader);
+    if (mine) rank = base + __popcll(m & below);
+    rem &= ~m;
+  }
+  return rank;
+}
+
+// Push particle p of species s; with feeds, also its new cell row (-1: none,
+// or deposited here).  Returns whether the schedule is broken.
 template <typename R>
-__device__ __forceinline__ bool pipe_push_one(const PipeBeam<R>& B, int s, int64_t p, int jp, int lrow, bool slab,
-                                              bool feeds) {
+__device__ __forceinline__ bool pipe_push_one(const PipeBeam<R>& B, int s, int64_t p, int jp, bool slab, bool feeds,
+                                              int& row) {
   const Geo<R>& g = B.g;
   bool bad = false;
+  row = -1;
   const double gz = B.xi[s][p] * B.inv_dxi;
   if (slab) {
     // fields are final up to slice jp + 3; a deposit must reach the next
@@ -1366,83 +1423,154 @@ __device__ __forceinline__ bool pipe_push_one(const PipeBeam<R>& B, int s, int64
   const double gn = B.xi[s][p] * B.inv_dxi;
   const bool deposits = w != R(0) && gn > -1.0 && gn < (double)g.nxi;
   if (!slab) return bad || deposits;   // not deposited for the next lane: must carry nothing
-  int tag = PIPE_NO_TAG;
   if (deposits) {
     int jc, i, l;
     R fz, fy, fx, v[4];
     beam_sources_of(g, B.x[s][p], B.y[s][p], B.xi[s][p], B.ux[s][p], B.uy[s][p], B.uz[s][p], B.zq[s] * w,
                     B.inv_dxi, jc, i, l, fz, fy, fx, v);
-    int d = l - lrow;
-    if (d > (g.ny >> 1)) d -= g.ny;
-    if (d < -(g.ny >> 1)) d += g.ny;
-    if (jc == jp && d >= -B.dy && d <= B.dy) tag = d;
+    if (jc == jp) row = l;
     else dense_add(g, B.src_next, jc, i, l, fz, fy, fx, v);
   }
-  B.tag[s][p] = tag;
   return bad;
 }
 
-// Block l pushes the particles stored under cell row (jp, l); at the last
-// slab the blocks also share slab nxi - 1 and the out-of-grid tail.
 template <typename R>
 __global__ void __launch_bounds__(256) k_pipe_push(const PipeBeam<R>* __restrict__ tab, int tick, int nlanes) {
-  const PipeBeam<R>& B = tab[blockIdx.z];
+  // blocks in launch order (all XCDs on the rows of one lane at a time)
+  const int lane = blockIdx.z, l = blockIdx.x;
+  const PipeBeam<R>& B = tab[lane];
   const Geo<R>& g = B.g;
   const int jp = tick - B.lag - QSA_PUSH_LAG;
-  const int l = blockIdx.x;
   if (jp < 0 || jp > g.nxi - 2 || l >= g.ny) return;
-  const bool feeds = (int)blockIdx.z + 1 < nlanes;
+  const bool feeds = lane + 1 < nlanes;
   const int64_t row = (int64_t)jp * g.ny + l;
+  __shared__ int cnt[512];
   bool bad = false;
   for (int s = 0; s < B.ns; ++s) {
-    const int64_t p1 = B.rowoff[s][row + 1];
-    for (int64_t p = B.rowoff[s][row] + threadIdx.x; p < p1; p += blockDim.x)
-      bad |= pipe_push_one(B, s, p, jp, l, true, feeds);
+    for (int i = threadIdx.x; i < g.ny; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    const int64_t p0 = B.rowoff[s][row], p1 = B.rowoff[s][row + 1];
+    for (int64_t b0 = p0; b0 < p1; b0 += blockDim.x) {
+      const int64_t p = b0 + threadIdx.x;
+      const bool act = p < p1;
+      int L = -1;
+      if (act) bad |= pipe_push_one(B, s, p, jp, true, feeds, L);
+      if (!feeds) continue;
+      const int r = wave_class_rank(cnt, L, act && L >= 0);
+      if (act) B.tag[s][p] = (L >= 0) ? ((r << 9) | L) : -1;
+    }
+    if (feeds) {
+      __syncthreads();
+      int* h = B.hist + ((int64_t)s * g.ny + l) * g.ny;
+      for (int i = threadIdx.x; i < g.ny; i += blockDim.x) h[i] = cnt[i];
+    }
     if (jp == g.nxi - 2) {
+      // the last pushable slab also takes slab nxi - 1 and the out-of-grid tail
       const int64_t nrows = (int64_t)g.nxi * g.ny;
       const int64_t t1 = B.rowoff[s][nrows + 1];
       for (int64_t p = B.rowoff[s][(int64_t)(jp + 1) * g.ny] + (int64_t)l * blockDim.x + threadIdx.x; p < t1;
-           p += (int64_t)g.ny * blockDim.x)
-        bad |= pipe_push_one(B, s, p, jp, 0, false, feeds);
+           p += (int64_t)g.ny * blockDim.x) {
+        int L;
+        bad |= pipe_push_one(B, s, p, jp, false, feeds, L);
+      }
     }
+    __syncthreads();
   }
   if (bad) atomicOr(B.err, ERR_DRIFT);
 }
 
-// Block l deposits the particles now in cell row (jp, l): those stored under
-// rows l - d and tagged d.
+// One block per lane: hist[l][L] <- first slot of source row l's particles
+// within new row L; base[L] <- start of new row L in the slab.
 template <typename R>
-__global__ void __launch_bounds__(256) k_pipe_deposit(const PipeBeam<R>* __restrict__ tab, int tick, int nlanes) {
-  if ((int)blockIdx.z + 1 >= nlanes) return;   // the last lane feeds no one
-  const PipeBeam<R>& B = tab[blockIdx.z];
+__global__ void __launch_bounds__(512) k_pipe_scan(const PipeBeam<R>* __restrict__ tab, int tick, int nlanes) {
+  const int lane = blockIdx.z;
+  if (lane + 1 >= nlanes) return;
+  const PipeBeam<R>& B = tab[lane];
   const Geo<R>& g = B.g;
   const int jp = tick - B.lag - QSA_PUSH_LAG;
-  const int l = blockIdx.x;
+  if (jp < 0 || jp > g.nxi - 2) return;
+  __shared__ int red[512];
+  const int L = threadIdx.x;
+  for (int s = 0; s < B.ns; ++s) {
+    int* h = B.hist + (int64_t)s * g.ny * g.ny;
+    int acc = 0;
+    if (L < g.ny) {
+      for (int l = 0; l < g.ny; ++l) {
+        const int c = h[(int64_t)l * g.ny + L];
+        h[(int64_t)l * g.ny + L] = acc;
+        acc += c;
+      }
+    }
+    red[L] = acc;
+    __syncthreads();
+    for (int o = 1; o < 512; o <<= 1) {
+      const int add = (L >= o) ? red[L - o] : 0;
+      __syncthreads();
+      red[L] += add;
+      __syncthreads();
+    }
+    int* base = B.base + s * (g.ny + 1);
+    if (L < g.ny) base[L] = red[L] - acc;
+    if (L == g.ny - 1) base[g.ny] = red[L];
+    __syncthreads();
+  }
+}
+
+// Block l writes the index of every particle stored under cell row (jp, l)
+// to its slot in the slab's permutation by new row.
+template <typename R>
+__global__ void __launch_bounds__(256) k_pipe_place(const PipeBeam<R>* __restrict__ tab, int tick, int nlanes) {
+  const int lane = blockIdx.z, l = blockIdx.x;
+  if (lane + 1 >= nlanes) return;
+  const PipeBeam<R>& B = tab[lane];
+  const Geo<R>& g = B.g;
+  const int jp = tick - B.lag - QSA_PUSH_LAG;
   if (jp < 0 || jp > g.nxi - 2 || l >= g.ny) return;
+  const int64_t row = (int64_t)jp * g.ny + l;
+  for (int s = 0; s < B.ns; ++s) {
+    const int64_t s0 = B.rowoff[s][(int64_t)jp * g.ny];
+    const int* h = B.hist + ((int64_t)s * g.ny + l) * g.ny;
+    const int* base = B.base + s * (g.ny + 1);
+    const int64_t p1 = B.rowoff[s][row + 1];
+    for (int64_t p = B.rowoff[s][row] + threadIdx.x; p < p1; p += blockDim.x) {
+      const int t = B.tag[s][p];
+      if (t < 0) continue;
+      const int L = t & 511;
+      B.perm[s][s0 + base[L] + h[L] + (t >> 9)] = (int)p;
+    }
+  }
+}
+
+// Block L deposits the particles now in cell row (jp, L).
+template <typename R>
+__global__ void __launch_bounds__(256) k_pipe_deposit(const PipeBeam<R>* __restrict__ tab, int tick, int nlanes) {
+  int lane, L;
+  lane_block(lane, L);
+  if (lane + 1 >= nlanes) return;   // the last lane feeds no one
+  const PipeBeam<R>& B = tab[lane];
+  const Geo<R>& g = B.g;
+  const int jp = tick - B.lag - QSA_PUSH_LAG;
+  if (jp < 0 || jp > g.nxi - 2 || L >= g.ny) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
   const int tn = 2 * 2 * 4 * g.nx;
   for (int i = threadIdx.x; i < tn; i += blockDim.x) tile[i] = R(0);
   __syncthreads();
   for (int s = 0; s < B.ns; ++s) {
-    for (int d = -B.dy; d <= B.dy; ++d) {
-      int src_row = l - d;
-      src_row += (src_row < 0) ? g.ny : 0;
-      src_row -= (src_row >= g.ny) ? g.ny : 0;
-      const int64_t row = (int64_t)jp * g.ny + src_row;
-      const int64_t q1 = B.rowoff[s][row + 1];
-      for (int64_t q = B.rowoff[s][row] + threadIdx.x; q < q1; q += blockDim.x) {
-        if (B.tag[s][q] != d) continue;
-        int jc, i, lc;
-        R fz, fy, fx, v[4];
-        beam_sources_of(g, B.x[s][q], B.y[s][q], B.xi[s][q], B.ux[s][q], B.uy[s][q], B.uz[s][q],
-                        B.zq[s] * B.w[s][q], B.inv_dxi, jc, i, lc, fz, fy, fx, v);
-        tile_add(tile, g.nx, jp, jc, i, fz, fy, fx, v);
-      }
+    const int* base = B.base + s * (g.ny + 1);
+    const int64_t s0 = B.rowoff[s][(int64_t)jp * g.ny];
+    const int64_t q1 = s0 + base[L + 1];
+    for (int64_t q = s0 + base[L] + threadIdx.x; q < q1; q += blockDim.x) {
+      const int p = B.perm[s][q];
+      int jc, i, lc;
+      R fz, fy, fx, v[4];
+      beam_sources_of(g, B.x[s][p], B.y[s][p], B.xi[s][p], B.ux[s][p], B.uy[s][p], B.uz[s][p],
+                      B.zq[s] * B.w[s][p], B.inv_dxi, jc, i, lc, fz, fy, fx, v);
+      tile_add(tile, g.nx, jp, jc, i, fz, fy, fx, v);
     }
   }
   __syncthreads();
-  R* out = B.ring_next + ((int64_t)(jp & 1) * g.ny + l) * tn;
+  R* out = B.ring_next + ((int64_t)(jp & 1) * g.ny + L) * tn;
   for (int i = threadIdx.x; i < tn; i += blockDim.x) out[i] = tile[i];
 }
 
