@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--pipeline", type=int, default=8, help="beam steps in flight (1 = one at a time)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library time its launch shapes and steps in flight first")
     ap.add_argument("--pre-steps", type=int, default=0,
                     help="untimed beam steps after the warmup (time a more evolved beam)")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
@@ -170,6 +172,14 @@ def main():
     del beams
     if args.no_graphs:
         sim.set_graphs(False)
+    tuned = None
+    if args.autotune:
+        t = time.perf_counter()
+        best = sim.autotune()
+        nt, rt = sim.shapes()
+        tuned = {"plasma_threads": nt, "row_threads": rt, "steps_in_flight": sim.pipeline,
+                 "best_trial_ms_per_step": best}
+        log(f"autotune {time.perf_counter() - t:.1f} s: {tuned}")
     log(f"loaded; workspace {sim.ws_bytes / 2**30:.2f} GiB")
 
     # warmup
@@ -186,7 +196,8 @@ def main():
     dominant = "push_pred"
     # the step graphs (a whole group when pipelined) are captured here,
     # outside the timed region
-    sim.beam_step(max(1, args.pipeline))
+    depth = sim.pipeline
+    sim.beam_step(depth)
     sim.sync()
     # timed region: exactly K steps (graph replays) between synchronizations
     torch.cuda.synchronize()
@@ -194,7 +205,7 @@ def main():
     sim.beam_step(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    if sim.pipeline != max(1, args.pipeline):
+    if sim.pipeline != depth:
         raise RuntimeError(f"pipelining fell back to depth {sim.pipeline}")
     # the dominant kernel's launch duration: HIP events around each of its
     # launches over the same number of steps, enqueued launch by launch
@@ -224,7 +235,7 @@ def main():
     if args.breakdown:
         for kc in ("push_pred", "push_final", "dep_S", "dep_J", "row_r2c", "col", "row_c2r",
                    "beam_deposit", "beam_push"):
-            nst = max(1, args.pipeline)
+            nst = depth
             ms, n = timed_step(sim, kc, nst)
             breakdown[kc] = {"ms_per_step": ms / nst, "launches": n, "us_per_launch": 1e3 * ms / max(n, 1)}
             log(f"  {kc:13s} {ms / nst:9.2f} ms/step  {n:6d} launches  {1e3 * ms / max(n, 1):8.2f} us/launch")
@@ -240,7 +251,7 @@ def main():
                    "+ predicted J_perp deposit)"),
         "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
-        "traffic": measured_traffic(wl.name, args.precision, max(1, args.pipeline)),
+        "traffic": measured_traffic(wl.name, args.precision, depth) if not tuned else None,
         "avg_launch_us": avg_s * 1e6, "launches_timed": dom_n,
         "timing": timing_note,
         "alg_bytes_per_launch": per_launch,
@@ -268,7 +279,7 @@ def main():
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nxi": wl.nxi,
                    "dx": wl.dx, "plasma_per_slice": wl.n_plasma, "beam_particles": wl.n_beam_total,
                    "alpha": wl.species[0].alpha, "gamma_b": wl.gamma_b, "n_corr": wl.n_corr,
-                   "steps_in_flight": max(1, args.pipeline),
+                   "steps_in_flight": depth, "autotuned": tuned,
                    "step": "beam source deposit + 512-slice sweep + Boris beam push"},
         "sweep_only": {"ms": 1e3 * t_sweep, "updates_per_s": wl.n_plasma * wl.nxi / t_sweep},
         "roofline": roofline,

@@ -209,11 +209,17 @@ qsa_status qsa_timing_end(qsa_ctx* c, double* total_ms, int64_t* launches);
 enum {
   QSA_OPT_GRAPHS = 0,    /* 1 (default): replay a captured HIP graph of the sweep
                             and of the beam step; 0: enqueue every launch   */
-  QSA_OPT_PIPELINE = 1   /* beam steps in flight in qsa_beam_step: set 1..P
+  QSA_OPT_PIPELINE = 1,  /* beam steps in flight in qsa_beam_step: set 1..P
                             (values above the parameter's pipeline = P are
                             clamped to P; setting also re-enables pipelining
                             after a drift fallback); get: the depth in use,
                             1 when pipelining is off                        */
+  QSA_OPT_PLASMA_THREADS = 2, /* threads per plasma cell-row block: 64, 128,
+                            256, or 0 for the default (from the particles per
+                            row); get: the value in use                     */
+  QSA_OPT_ROW_THREADS = 3 /* threads per row-transform block: 64, 128, 256
+                            (a multiple of nx/4), or 0 for max(64, nx/4);
+                            get: the value in use                           */
 };
 
 /* Set a context option (see QSA_OPT_*). */
@@ -221,6 +227,18 @@ qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value);
 
 /* Read a context option (see QSA_OPT_*) into *value. */
 qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value);
+
+/* Autotuner: times real work on this context's data (direct launches, HIP
+ * events) and keeps the fastest threads per plasma-row block (64/128/256),
+ * threads per row-transform block (64/128/256, multiples of nx/4) and, with
+ * pipeline > 1, beam steps in flight (2, 4, ... up to pipeline).  A trial is
+ * a group of steps in flight, after which the beam is restored, or (pipeline
+ * <= 1) one sweep.  The beam and the device flags are as before the call;
+ * fields are invalid until the next sweep.  *ms_per_step (may be NULL)
+ * receives the best time per step (per sweep without pipelining).
+ * Synchronizing; about 10 trials.  The shapes chosen change the order of
+ * floating-point additions only. */
+qsa_status qsa_autotune(qsa_ctx* c, double* ms_per_step);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent boxes (a growth-rate parameter scan: different

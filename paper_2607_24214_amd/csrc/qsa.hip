@@ -181,6 +181,8 @@ struct qsa_ctx {
   bool use_graphs = true;
   bool pipe_ok = true;   // off after a drift violation, until the next beam load
   int pipe_max = 1;      // beam steps in flight when pipelining (<= L.nset)
+  int tune_nt = 0;       // threads per plasma-row block (0: from the particles per row)
+  int tune_rt = 0;       // threads per row-transform block (0: max(64, nx/4))
   int cur_set = 0;       // working set holding the last sweep's sources and fields
   int64_t beam_n[QSA_MAX_SPECIES] = {0, 0, 0, 0};
   bool plasma_loaded = false;
@@ -605,6 +607,7 @@ struct Engine {
   // Launch shapes of a set of lanes (maxima over the boxes).
   struct Dims {
     int n = 0, nx = 0, ny = 0, nxi = 0, nxh = 0, np = 0, per_row = 0, n_corr = 0;
+    int nt = 64;                      // plasma-row block size
     int rows_r2c = 0, rt_rows = 64;   // row-pass grid and block size
     int cols[3] = {0, 0, 0};          // column-pass grid per mode
     size_t smem_col[3] = {0, 0, 0};
@@ -622,8 +625,11 @@ struct Engine {
     const int64_t spec = (int64_t)p.ny * (p.nx / 2 + 1);
     d.clear = std::max<int64_t>(d.clear, std::max<int64_t>(6 * spec, 3 * (int64_t)p.nx * p.ny));
   }
-  static void finish_dims(Dims& d, const qsa_params* const* ps, int n) {
+  static void finish_dims(Dims& d, const qsa_params* const* ps, int n, int nt = 0, int rt = 0) {
     d.rt_rows = std::max(64, d.nx / 4);
+    if (rt >= d.nx / 4 && rt % (d.nx / 4) == 0 && rt <= 256) d.rt_rows = rt;
+    d.nt = std::max(64, std::min(256, (d.per_row + 63) / 64 * 64));
+    if (nt == 64 || nt == 128 || nt == 256) d.nt = nt;
     d.rows_r2c = 0;
     for (int m = 0; m < 3; ++m) {
       d.cols[m] = 0;
@@ -650,8 +656,7 @@ struct Engine {
     const int n = d.n;
     const int pb = (d.np + 255) / 256;
     const size_t smem_rows = ((size_t)d.nx + 8 * (size_t)d.rt_rows) * sizeof(C2<R>);
-    int nt = (d.per_row + 63) / 64 * 64;
-    nt = std::max(64, std::min(256, nt));
+    const int nt = d.nt;
     const int j = t;   // every lag is a multiple of QSA_SORT_EVERY
     {
       if (j % QSA_SORT_EVERY == 0) {
@@ -714,7 +719,7 @@ struct Engine {
     Dims d;
     add_dims(d, c->p);
     const qsa_params* ps[1] = {&c->p};
-    finish_dims(d, ps, 1);
+    finish_dims(d, ps, 1, c->tune_nt, c->tune_rt);
     return d;
   }
 
@@ -795,6 +800,21 @@ struct Engine {
     hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, c->stream, c->at<int>(c->L.err), (int64_t)1, 0);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(c->stream));
+    return QSA_OK;
+  }
+
+  // One autotuning trial on the work stream: n > 1 steps in flight (the beam
+  // is put back afterwards) or one sweep; *ms = wall time per step or sweep.
+  static qsa_status trial(qsa_ctx* c, int n, hipEvent_t e0, hipEvent_t e1, float* ms) {
+    HIP_OK(hipEventRecord(e0, c->stream));
+    qsa_status st = (n > 1) ? group(c, n) : sweep(c);
+    if (st != QSA_OK) return st;
+    HIP_OK(hipEventRecord(e1, c->stream));
+    HIP_OK(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIP_OK(hipEventElapsedTime(&t, e0, e1));
+    *ms = t / (float)n;
+    if (n > 1) return restore(c);
     return QSA_OK;
   }
 
@@ -1293,7 +1313,89 @@ qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value) {
     c->pipe_ok = true;
     return QSA_OK;
   }
+  if (option == QSA_OPT_PLASMA_THREADS) {
+    if (value != 0 && value != 64 && value != 128 && value != 256)
+      return fail(c, QSA_E_INVALID, "plasma threads must be 0, 64, 128 or 256");
+    c->tune_nt = (int)value;
+    c->drop_graphs();
+    return QSA_OK;
+  }
+  if (option == QSA_OPT_ROW_THREADS) {
+    const int tpt = c->p.nx / 4;
+    if (value != 0 && !((value == 64 || value == 128 || value == 256) && value >= tpt && value % tpt == 0))
+      return fail(c, QSA_E_INVALID, "row threads must be 0 or 64, 128, 256 (a multiple of nx/4)");
+    c->tune_rt = (int)value;
+    c->drop_graphs();
+    return QSA_OK;
+  }
   return fail(c, QSA_E_INVALID, "unknown option");
+}
+
+qsa_status qsa_autotune(qsa_ctx* c, double* ms_per_step) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
+  if (c->timing_class >= 0) return fail(c, QSA_E_STATE, "kernel timing is active");
+  qsa_status st = enter(c);
+  if (st != QSA_OK) return st;
+  if ((st = check_device(c)) != QSA_OK) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_OK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, QSA_E_DEVICE, "hipEventCreate failed");
+  }
+  const int depth0 = (c->L.nset > 1 && c->pipe_ok) ? c->L.nset : 1;
+  auto run = [&](int n, float* ms) {
+    return dispatch(c, [&] { return Engine<double>::trial(c, n, e0, e1, ms); },
+                    [&] { return Engine<float>::trial(c, n, e0, e1, ms); });
+  };
+  float best = 0.f, t = 0.f;
+  st = run(depth0, &best);   // warm-up: first launches of every kernel
+  if (st == QSA_OK) st = run(depth0, &best);
+  // threads per plasma-row block
+  const int nts[3] = {64, 128, 256};
+  int best_nt = c->tune_nt;
+  for (int k = 0; k < 3 && st == QSA_OK; ++k) {
+    c->tune_nt = nts[k];
+    if ((st = run(depth0, &t)) == QSA_OK && t < best) {
+      best = t;
+      best_nt = nts[k];
+    }
+  }
+  c->tune_nt = best_nt;
+  // threads per row-transform block
+  const int tpt = c->p.nx / 4;
+  int best_rt = c->tune_rt;
+  for (int rt = 64; rt <= 256 && st == QSA_OK; rt *= 2) {
+    if (rt < tpt || rt % tpt) continue;
+    c->tune_rt = rt;
+    if ((st = run(depth0, &t)) == QSA_OK && t < best) {
+      best = t;
+      best_rt = rt;
+    }
+  }
+  c->tune_rt = best_rt;
+  // beam steps in flight (per step)
+  int best_depth = c->pipe_max;
+  if (depth0 > 1) {
+    best_depth = depth0;
+    for (int n = 2; n < depth0 && st == QSA_OK; n *= 2) {
+      if ((st = run(n, &t)) == QSA_OK && t < best) {
+        best = t;
+        best_depth = n;
+      }
+    }
+    c->pipe_max = best_depth;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != QSA_OK) return st;
+  c->drop_graphs();
+  c->swept = false;   // the trials' fields are not a sweep of the current beam
+  c->cur_set = 0;
+  if (ms_per_step) *ms_per_step = best;
+  return leave(c);
 }
 
 qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value) {
@@ -1304,6 +1406,14 @@ qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value) {
   }
   if (option == QSA_OPT_PIPELINE) {
     *value = c->pipe_ok ? c->pipe_max : 1;
+    return QSA_OK;
+  }
+  if (option == QSA_OPT_PLASMA_THREADS || option == QSA_OPT_ROW_THREADS) {
+    typename Engine<double>::Dims d;
+    Engine<double>::add_dims(d, c->p);
+    const qsa_params* ps[1] = {&c->p};
+    Engine<double>::finish_dims(d, ps, 1, c->tune_nt, c->tune_rt);
+    *value = (option == QSA_OPT_PLASMA_THREADS) ? d.nt : d.rt_rows;
     return QSA_OK;
   }
   return QSA_E_INVALID;

@@ -142,6 +142,28 @@ class Sim:
         """Beam steps in flight (1 .. the pipeline parameter)."""
         self._check(self.lib.qsa_set_option(self.ctx, 1, int(depth)))
 
+    def set_shapes(self, plasma_threads: int = 0, row_threads: int = 0):
+        """Launch shapes (0 = default): threads per plasma-row block and per
+        row-transform block."""
+        self._check(self.lib.qsa_set_option(self.ctx, 2, int(plasma_threads)))
+        self._check(self.lib.qsa_set_option(self.ctx, 3, int(row_threads)))
+
+    def shapes(self):
+        out = []
+        for opt in (2, 3):
+            v = C.c_int64(0)
+            self._check(self.lib.qsa_get_option(self.ctx, opt, C.byref(v)))
+            out.append(int(v.value))
+        return tuple(out)
+
+    def autotune(self) -> float:
+        """Time the launch shapes and steps in flight on this machine's data and
+        keep the fastest; returns the best ms per step (per sweep without
+        pipelining)."""
+        ms = C.c_double(0.0)
+        self._check(self.lib.qsa_autotune(self.ctx, C.byref(ms)))
+        return float(ms.value)
+
     @property
     def pipeline(self) -> int:
         """Beam steps in flight in use (1 after a drift fallback)."""

@@ -85,3 +85,10 @@ def test_pipeline_workspace_and_validation():
     assert lib.qsa_workspace_bytes(C.byref(p)) == 0
     v = C.c_int64()
     assert lib.qsa_get_option(None, 1, C.byref(v)) == -1
+
+
+def test_autotune_rejects_null_context():
+    from paper_2607_24214_amd import _lib as L
+    lib = L.lib()
+    ms = C.c_double()
+    assert lib.qsa_autotune(None, C.byref(ms)) == -1
