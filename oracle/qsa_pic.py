@@ -134,20 +134,21 @@ def ifft2r(a: torch.Tensor) -> torch.Tensor:
     return torch.fft.ifft2(a).real
 
 
-def solve_psi(sp: Spectral, S: torch.Tensor, psi0: float):
-    """-lap psi = S for k != 0; the mean of psi is psi0.  Returns psi, d_x psi, d_y psi."""
+def solve_psi(sp: Spectral, S: torch.Tensor, psi0):
+    """-lap psi = S for k != 0; the mean of psi is psi0 (a number or a 0-d
+    tensor).  Returns psi, d_x psi, d_y psi."""
     Sh = fft2(S)
     ph = Sh * sp.inv_ksq
-    ph = torch.where(sp.zero, torch.full_like(ph, psi0 * sp.n), ph)
+    ph = torch.where(sp.zero, (psi0 * sp.n) * torch.ones_like(ph), ph)
     return ifft2r(ph), ifft2r(1j * sp.kdx * ph), ifft2r(1j * sp.kdy * ph)
 
 
-def solve_bz_ez(sp: Spectral, Jxh: torch.Tensor, Jyh: torch.Tensor, ez0: float):
+def solve_bz_ez(sp: Spectral, Jxh: torch.Tensor, Jyh: torch.Tensor, ez0):
     """lap B_z = d_y J_x - d_x J_y and lap E_z = div J_perp for k != 0;
     B_z has zero mean, the mean of E_z is ez0."""
     bzh = -(1j * sp.kdy * Jxh - 1j * sp.kdx * Jyh) * sp.inv_ksq
     ezh = -(1j * sp.kdx * Jxh + 1j * sp.kdy * Jyh) * sp.inv_ksq
-    ezh = torch.where(sp.zero, torch.full_like(ezh, ez0 * sp.n), ezh)
+    ezh = torch.where(sp.zero, (ez0 * sp.n) * torch.ones_like(ezh), ezh)
     return ifft2r(bzh), ifft2r(ezh)
 
 
@@ -283,7 +284,7 @@ def slice_sweep(g: Grid, plasma: Dict, sources: torch.Tensor, n_corr: int = 3,
         Jz = st.deposit(nw * uz / G) + Jzb[j]
         Jxh, Jyh, Jzh = fft2(Jx), fft2(Jy), fft2(Jz)
         # transverse-mean (k = 0) equations, leapfrog in xi
-        e_next = e_half - h * float(Jz.mean())
+        e_next = e_half - h * Jz.mean()
         ez0 = 0.5 * (e_half + e_next)
         psi0_next = psi0 + h * e_next
         Bz, Ez = solve_bz_ez(sp, Jxh, Jyh, ez0)
