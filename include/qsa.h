@@ -109,7 +109,11 @@ typedef struct {
                             one step at a time).  With P > 1 the workspace holds
                             P working sets (sources, fields, plasma state) and a
                             copy of the beam; see qsa_beam_step.             */
-  int32_t reserved_;     /* must be 0                                        */
+  int32_t adjoint_steps; /* 0, or the most beam steps qsa_adjoint_sweep will
+                            differentiate (the workspace then holds the beam
+                            and the 7 field planes for every step, plasma
+                            checkpoints every 16 slices, and the adjoint
+                            arrays; see qsa_adjoint_sweep)                  */
 } qsa_params;
 
 /* Bytes of device workspace a context with these parameters needs; 0 if the
@@ -227,6 +231,24 @@ qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value);
 
 /* Read a context option (see QSA_OPT_*) into *value. */
 qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value);
+
+/* Gradient of the transverse magnetic energy with respect to beam-amplitude
+ * bins (requires adjoint_steps >= n_steps at create).
+ *
+ * Starting from the beam as loaded (or as left by the last step), with every
+ * particle's weight scaled by amps[bin] (bins[s][p] in [0, n_bins): the bin of
+ * particle p of species s, host arrays of beam_n[s] entries; a particle with
+ * a bin outside that range keeps its weight), the call runs n_steps beam
+ * steps and one more sweep, *loss = 1/2 sum (B_x^2 + B_y^2) dx dy dxi over
+ * every node of that last sweep, and grad[b] = d loss / d amps[b] (host
+ * array of n_bins).  The derivative is that of the discrete scheme (sweeps,
+ * deposits, Boris pushes), computed in reverse with the beam and fields of
+ * every step kept and the plasma recomputed between checkpoints every 16
+ * slices.  Its forward passes use their own simple kernels (no pipelining,
+ * the plasma never reordered).  The context's beam, fields and options are
+ * unchanged.  Synchronizing.  n_bins <= 4096. */
+qsa_status qsa_adjoint_sweep(qsa_ctx* c, int32_t n_steps, int32_t n_bins, const double* amps,
+                             const int32_t* const* bins, double* loss, double* grad);
 
 /* Autotuner: times real work on this context's data (direct launches, HIP
  * events) and keeps the fastest threads per plasma-row block (64/128/256),

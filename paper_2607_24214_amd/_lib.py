@@ -26,7 +26,8 @@ STATUS = {0: "QSA_OK", -1: "QSA_E_INVALID", -2: "QSA_E_NOMEM", -3: "QSA_E_DEVICE
 EXPORTS = ("qsa_workspace_bytes", "qsa_create", "qsa_load_plasma", "qsa_load_beam",
            "qsa_read_beam", "qsa_slice_sweep", "qsa_beam_step", "qsa_fields", "qsa_sync",
            "qsa_destroy", "qsa_status_string", "qsa_last_error", "qsa_timing_begin",
-           "qsa_timing_end", "qsa_set_option", "qsa_get_option", "qsa_autotune", "qsa_batch_workspace_bytes",
+           "qsa_timing_end", "qsa_set_option", "qsa_get_option", "qsa_autotune", "qsa_adjoint_sweep",
+           "qsa_batch_workspace_bytes",
            "qsa_batch_create",
            "qsa_batch_sweep", "qsa_batch_step", "qsa_batch_sync", "qsa_batch_destroy")
 
@@ -46,7 +47,7 @@ class QSAParams(C.Structure):
         ("n_plasma", C.c_int64), ("plasma_w", C.c_double),
         ("species", QSASpecies * QSA_MAX_SPECIES),
         ("beam_capacity", C.c_int64 * QSA_MAX_SPECIES),
-        ("pipeline", C.c_int32), ("reserved_", C.c_int32),
+        ("pipeline", C.c_int32), ("adjoint_steps", C.c_int32),
     ]
 
 
@@ -85,6 +86,7 @@ def lib():
     L.qsa_set_option.argtypes = [vp, i32, i64]
     L.qsa_get_option.argtypes = [vp, i32, C.POINTER(i64)]
     L.qsa_autotune.argtypes = [vp, dp]
+    L.qsa_adjoint_sweep.argtypes = [vp, i32, i32, dp, C.POINTER(C.POINTER(i32)), dp, dp]
     L.qsa_batch_workspace_bytes.argtypes = [i32]
     L.qsa_batch_workspace_bytes.restype = C.c_size_t
     L.qsa_batch_create.argtypes = [C.POINTER(vp), i32, vp, C.c_size_t, vp, C.POINTER(vp)]
@@ -99,7 +101,7 @@ def lib():
     for name in ("qsa_create", "qsa_load_plasma", "qsa_load_beam", "qsa_read_beam",
                  "qsa_slice_sweep", "qsa_beam_step", "qsa_fields", "qsa_sync", "qsa_destroy",
                  "qsa_timing_begin", "qsa_timing_end", "qsa_set_option", "qsa_get_option", "qsa_autotune",
-                 "qsa_batch_create",
+                 "qsa_adjoint_sweep", "qsa_batch_create",
                  "qsa_batch_sweep", "qsa_batch_step", "qsa_batch_sync", "qsa_batch_destroy"):
         getattr(L, name).restype = i32
     _lib = L

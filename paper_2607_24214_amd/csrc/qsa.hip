@@ -16,6 +16,7 @@
 
 #include "../../include/qsa.h"
 #include "qsa_kernels.h"
+#include "qsa_adjoint.h"
 
 using namespace qsa;
 
@@ -30,6 +31,78 @@ int ilog2(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
   return l;
+}
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Grid scratch indices (each [ny][nx]).
+enum {
+  AG_S = 0, AG_JX, AG_JY, AG_JZ, AG_JTX, AG_JTY, AG_DX, AG_DY, AG_PSIT, AG_ZERO, AG_JM1X, AG_JM1Y,
+  AG_BAX, AG_BAY, AG_BBX, AG_BBY,
+  AA_PSI, AA_DXPSI, AA_DYPSI, AA_BZ, AA_BKX, AA_BKY, AA_BNX, AA_BNY, AA_JX, AA_JY, AA_JZ, AA_PSIT, AA_S,
+  AA_DBX, AA_DBY,
+  AH0 = 32,            // hist adjoint set 0: fm1[6], psim2, bm2[2], jm1[2]
+  AH1 = AH0 + 11,      // set 1
+  AG_DUMMY = AH1 + 11,
+  AG_COUNT = 64
+};
+enum { AH_FM1 = 0, AH_PSIM2 = 6, AH_BM2 = 7, AH_JM1 = 9 };
+
+struct AdjLayout {
+  int steps = 0, nseg = 0, ck_len = 0;
+  size_t state[QSA_MAX_SPECIES] = {};   // per species: bytes of one beam state in the tape
+  size_t beam[QSA_MAX_SPECIES] = {};    // tape base per species
+  size_t bin[QSA_MAX_SPECIES] = {}, w0[QSA_MAX_SPECIES] = {}, bb[QSA_MAX_SPECIES][7] = {};
+  size_t fields = 0, src = 0, srcb = 0, fb = 0;
+  size_t ck = 0, ck_bytes = 0;
+  size_t segY = 0, segYt = 0, segB = 0, ytmp = 0, Y[2] = {}, Yb[2] = {};
+  size_t grids = 0, work = 0, sc = 0, grad = 0, amps = 0;
+};
+
+
+// Carve the adjoint arrays after the forward workspace.
+void adjoint_layout(const qsa_params& p, size_t& off, AdjLayout& A) {
+  const size_t rs = (p.precision == QSA_FP32) ? 4 : 8;
+  const size_t nperp = (size_t)p.nx * p.ny;
+  const size_t np = (size_t)p.n_plasma;
+  const size_t plane = (size_t)p.nxi * nperp;
+  const int K = std::max(p.n_corr, 0);
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  A.steps = p.adjoint_steps;
+  if (A.steps <= 0) return;
+  A.ck_len = QSA_ADJ_CKPT;
+  A.nseg = (p.nxi + A.ck_len - 1) / A.ck_len;
+  for (int s = 0; s < p.n_species; ++s) {
+    const size_t cap = (size_t)p.beam_capacity[s];
+    A.state[s] = 6 * align_up(cap * rs) + align_up(cap * 8);
+    A.beam[s] = take(A.state[s] * (size_t)(A.steps + 1));
+    A.bin[s] = take(cap * sizeof(int));
+    A.w0[s] = take(cap * rs);
+    for (int k = 0; k < 7; ++k) A.bb[s][k] = take(cap * rs);
+  }
+  A.fields = take((size_t)(A.steps + 1) * N_STORED * plane * rs);
+  A.src = take(4 * plane * rs);
+  A.srcb = take(4 * plane * rs);
+  A.fb = take(N_STORED * plane * rs);
+  A.ck_bytes = align_up(4 * np * rs) + align_up(2 * nperp * rs) + align_up(2 * sizeof(double));
+  A.ck = take((size_t)(A.steps + 1) * A.nseg * A.ck_bytes);
+  A.segY = take((size_t)A.ck_len * 4 * np * rs);
+  A.segYt = take((size_t)A.ck_len * std::max(K, 1) * 4 * np * rs);
+  A.segB = take((size_t)A.ck_len * std::max(K, 1) * 2 * nperp * rs);
+  A.ytmp = take(4 * np * rs);
+  for (int i = 0; i < 2; ++i) {
+    A.Y[i] = take(4 * np * rs);
+    A.Yb[i] = take(4 * np * rs);
+  }
+  A.grids = take((size_t)AG_COUNT * nperp * rs);
+  A.work = take((size_t)SPEC_IN * nperp * 2 * rs);
+  A.sc = take(64 * sizeof(double));
+  A.grad = take(4096 * sizeof(double));
+  A.amps = take(4096 * sizeof(double));
 }
 
 // Byte offsets of one sweep's working set: plasma state, sources, fields and
@@ -57,6 +130,7 @@ struct Layout {
   size_t beam[QSA_MAX_SPECIES][8];  // x, y, ux, uy, uz, w (real), xi (double), id (int64, pipelining)
   size_t snap[QSA_MAX_SPECIES][8];  // sort target and the beam at the start of a pipelined group
   size_t err, emit, lane, pipe;
+  AdjLayout adj;                    // adjoint tapes and arrays (adjoint_steps > 0)
   size_t total;
 };
 
@@ -77,8 +151,7 @@ Layout make_layout(const qsa_params& p) {
   const size_t nperp = (size_t)p.nx * p.ny;
   const size_t nxh = (size_t)p.nx / 2 + 1;
   const size_t spec = (size_t)p.ny * nxh * cs;
-  Layout L;
-  std::memset(&L, 0, sizeof(L));
+  Layout L{};
   Carver c;
   L.twx = c.take(p.nx * cs);
   L.twy = c.take(p.ny * cs);
@@ -138,6 +211,7 @@ Layout make_layout(const qsa_params& p) {
   L.emit = c.take(nperp * sizeof(double));
   L.lane = c.take(L.nset * sizeof(Lane<double>));
   L.pipe = c.take(L.nset * sizeof(PipeBeam<double>));
+  adjoint_layout(p, c.off, L.adj);
   L.total = c.off;
   return L;
 }
@@ -159,7 +233,7 @@ const char* validate(const qsa_params* p) {
   if ((int64_t)p->nxi * p->ny * (p->nx / QSA_BEAM_XCHUNK) > ((int64_t)1 << 30))
     return "nxi * ny * nx / 8 must be <= 2^30";
   if (p->pipeline < 0 || p->pipeline > QSA_MAX_PIPELINE) return "pipeline must be in [0, 8]";
-  if (p->reserved_ != 0) return "reserved_ must be 0";
+  if (p->adjoint_steps < 0 || p->adjoint_steps > 1024) return "adjoint_steps must be in [0, 1024]";
   for (int s = 0; s < p->n_species; ++s) {
     if (p->beam_capacity[s] < 0 || p->beam_capacity[s] > INT32_MAX) return "beam capacity must be in [0, 2^31)";
     if (!(p->species[s].M > 0)) return "species mass must be > 0";
@@ -993,6 +1067,12 @@ struct Engine {
   }
 };
 
+}  // namespace
+
+#include "qsa_adjoint_host.h"
+
+namespace {
+
 // Pending device error -> status (synchronizing).
 qsa_status check_device(qsa_ctx* c) {
   HIP_OK(hipStreamSynchronize(c->stream));
@@ -1396,6 +1476,46 @@ qsa_status qsa_autotune(qsa_ctx* c, double* ms_per_step) {
   c->cur_set = 0;
   if (ms_per_step) *ms_per_step = best;
   return leave(c);
+}
+
+qsa_status qsa_adjoint_sweep(qsa_ctx* c, int32_t n_steps, int32_t n_bins, const double* amps,
+                             const int32_t* const* bins, double* loss, double* grad) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
+  const AdjLayout& A = c->L.adj;
+  if (A.steps <= 0 || n_steps < 0 || n_steps > A.steps)
+    return fail(c, QSA_E_INVALID, "n_steps exceeds the adjoint_steps the context was created with");
+  if (n_bins < 1 || n_bins > 4096 || !amps || !bins || !loss || !grad)
+    return fail(c, QSA_E_INVALID, "bad bins, amplitudes or outputs");
+  for (int s = 0; s < c->p.n_species; ++s)
+    if (c->beam_n[s] > 0 && !bins[s]) return fail(c, QSA_E_INVALID, "null bin array");
+  for (int b = 0; b < n_bins; ++b)
+    if (!std::isfinite(amps[b])) return fail(c, QSA_E_NONFINITE, "non-finite amplitude");
+  qsa_status st = enter(c);
+  if (st != QSA_OK) return st;
+  if ((st = check_device(c)) != QSA_OK) return st;
+  HIP_OK(hipMemcpy(c->ws + A.amps, amps, n_bins * sizeof(double), hipMemcpyHostToDevice));
+  for (int s = 0; s < c->p.n_species; ++s) {
+    const int64_t n = c->beam_n[s];
+    if (n == 0) continue;
+    int* dst = c->at<int>(A.bin[s]);
+    if (c->L.nset > 1) {
+      // the library keeps this beam sorted: bins follow each particle's load index
+      int* tmp = c->at<int>(A.bb[s][0]);
+      HIP_OK(hipMemcpy(tmp, bins[s], n * sizeof(int), hipMemcpyHostToDevice));
+      hipLaunchKernelGGL(k_gather_bins, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                         (const int*)tmp, (const int64_t*)c->at<int64_t>(c->L.beam[s][7]), dst, n);
+      HIP_OK(hipGetLastError());
+    } else {
+      HIP_OK(hipMemcpy(dst, bins[s], n * sizeof(int), hipMemcpyHostToDevice));
+    }
+  }
+  st = dispatch(c, [&] { return Adj<double>(c, A).run(n_steps, n_bins, loss, grad); },
+                [&] { return Adj<float>(c, A).run(n_steps, n_bins, loss, grad); });
+  if (st != QSA_OK) return st;
+  if ((st = leave(c)) != QSA_OK) return st;
+  return check_device(c);
 }
 
 qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value) {

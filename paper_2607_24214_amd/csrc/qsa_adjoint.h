@@ -1,0 +1,955 @@
+// Reverse-mode derivative (adjoint) of the QSA step, for gradients of the
+// transverse magnetic energy of a sweep with respect to the beam's weights.
+//
+// The adjoint differentiates the discrete scheme itself: every deposit,
+// gather, spectral solve, predictor-corrector iteration, plasma push, k = 0
+// leapfrog and beam Boris push of the forward path (see qsa_kernels.h for
+// the scheme), in reverse order.  Its forward passes run the same scheme
+// with simple kernels (one thread per particle, global atomics for deposits,
+// batched full complex transforms) that keep the plasma particles in a fixed
+// order, so that particle identities carry across slices; they store what
+// the reverse pass needs:
+//   * per beam step: the beam state and the 7 stored field planes;
+//   * per sweep: the plasma state and J_perp of the previous slice every
+//     QSA_ADJ_CKPT slices (checkpoints);
+//   * per checkpoint segment, recomputed in the reverse pass: the plasma
+//     state at every slice, its predictor states and the B_perp iterates.
+// Conventions of the transposes used here:
+//   * gather g = sum_n F_n W_n  <->  deposit of g_bar W_n into F_bar;
+//     d g / d x = sum_n F_n dW_n/dx (W piecewise linear);
+//   * a real spectral operator with multiplier M(k) (Hermitian) has the
+//     transpose with multiplier conj(M(k)); a k = 0 value set from a scalar
+//     has the transpose "sum of the adjoint over all nodes";
+//   * index floors and the lost-particle flag are piecewise constant.
+#pragma once
+
+#include "qsa_kernels.h"
+
+namespace qsa {
+
+#define QSA_ADJ_CKPT 16   // plasma checkpoint stride in slices
+
+// ---------------------------------------------------------------------------
+// Batched spectral operators on real [ny][nx] fields:
+//   out_o = Re IFFT( sum_t c_t M_t(k) FFT(in_{i_t}) ),  k = 0 optionally set.
+// Three launches: forward row transforms, column transforms with the
+// multipliers, inverse row transforms.  Full complex transforms (no packing).
+// ---------------------------------------------------------------------------
+enum {
+  SK_ONE = 0,     // 1
+  SK_INVK2,       // 1/|k|^2, 0 at k = 0
+  SK_IKX,         // i kdx
+  SK_IKY,         // i kdy
+  SK_IKX_K2,      // i kdx/|k|^2
+  SK_IKY_K2,      // i kdy/|k|^2
+  SK_DEN,         // 1/(-|k|^2 - kappa^2)
+  SK_IKX_DEN,     // i kdx/(-|k|^2 - kappa^2)
+  SK_IKY_DEN      // i kdy/(-|k|^2 - kappa^2)
+};
+constexpr int SPEC_IN = 5, SPEC_OUT = 5, SPEC_TERMS = 4;
+
+template <typename R>
+struct SpecOp {
+  int ni, no;
+  const R* in[SPEC_IN];
+  R* out[SPEC_OUT];
+  int add[SPEC_OUT];                // 1: out += result, 0: out = result
+  int nterm[SPEC_OUT];
+  int kind[SPEC_OUT][SPEC_TERMS];
+  int src[SPEC_OUT][SPEC_TERMS];
+  double coef[SPEC_OUT][SPEC_TERMS];
+  const double* mean[SPEC_OUT];     // k = 0 value (the output's mean), or null
+  int conj;                         // 1: the transpose (conjugate multipliers)
+  double kappa2;
+  C2<R>* work;                      // [max(ni, no)][ny][nx] complex scratch
+};
+
+// Wavenumber and derivative multiplier of FFT index m on an axis of n cells
+// of size d: m_s in [-n/2, n/2), derivative 0 on the Nyquist index.
+__device__ __forceinline__ void axis_k(int m, int n, double L, double& k, double& kd) {
+  const int ms = (m < (n + 1) / 2) ? m : m - n;
+  k = 2.0 * 3.141592653589793238 * ms / L;
+  kd = (n > 1 && (n & 1) == 0 && m == n / 2) ? 0.0 : k;
+}
+
+__device__ __forceinline__ void spec_mult(int kind, double c, double kx, double kdx, double ky, double kdy,
+                                          double kappa2, bool conj, double& re, double& im) {
+  const double k2 = kx * kx + ky * ky;
+  const double ik2 = (k2 == 0.0) ? 0.0 : 1.0 / k2;
+  const double den = 1.0 / (-k2 - kappa2);
+  re = 0.0;
+  im = 0.0;
+  switch (kind) {
+    case SK_ONE: re = c; break;
+    case SK_INVK2: re = c * ik2; break;
+    case SK_IKX: im = c * kdx; break;
+    case SK_IKY: im = c * kdy; break;
+    case SK_IKX_K2: im = c * kdx * ik2; break;
+    case SK_IKY_K2: im = c * kdy * ik2; break;
+    case SK_DEN: re = c * den; break;
+    case SK_IKX_DEN: im = c * kdx * den; break;
+    case SK_IKY_DEN: im = c * kdy * den; break;
+    default: break;
+  }
+  if (conj) im = -im;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(64) k_spec_rows_fwd(Geo<R> g, SpecOp<R> op, const C2<R>* __restrict__ twx) {
+  const int l = blockIdx.x, f = blockIdx.y;
+  if (l >= g.ny || f >= op.ni) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
+  C2<R>* A = tw + g.nx;
+  C2<R>* B = A + g.nx;
+  const int t = threadIdx.x, tpt = blockDim.x;
+  for (int i = t; i < g.nx; i += tpt) {
+    tw[i] = twx[i];
+    A[i] = C2<R>{op.in[f][(int64_t)l * g.nx + i], R(0)};
+  }
+  __syncthreads();
+  const C2<R>* r = fft_lds<R, false>(A, B, g.nx, g.lgx, t, tpt, tw);
+  C2<R>* w = op.work + (int64_t)f * g.nperp + (int64_t)l * g.nx;
+  for (int i = t; i < g.nx; i += tpt) w[i] = r[i];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(64) k_spec_cols(Geo<R> g, SpecOp<R> op, const C2<R>* __restrict__ twy) {
+  const int kx = blockIdx.x;
+  if (kx >= g.nx) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
+  C2<R>* col = tw + g.ny;                        // [ni][ny] transformed inputs
+  C2<R>* A = col + (int64_t)op.ni * g.ny;        // work pair
+  C2<R>* B = A + g.ny;
+  const int t = threadIdx.x, tpt = blockDim.x;
+  for (int i = t; i < g.ny; i += tpt) tw[i] = twy[i];
+  for (int f = 0; f < op.ni; ++f) {
+    for (int i = t; i < g.ny; i += tpt) A[i] = op.work[(int64_t)f * g.nperp + (int64_t)i * g.nx + kx];
+    __syncthreads();
+    const C2<R>* r = fft_lds<R, false>(A, B, g.ny, g.lgy, t, tpt, tw);
+    for (int i = t; i < g.ny; i += tpt) col[(int64_t)f * g.ny + i] = r[i];
+    __syncthreads();
+  }
+  double kxv, kdx;
+  axis_k(kx, g.nx, (double)g.nx * (double)g.dx, kxv, kdx);
+  const double N = (double)g.nperp;
+  for (int o = 0; o < op.no; ++o) {
+    for (int ky = t; ky < g.ny; ky += tpt) {
+      double kyv, kdy;
+      axis_k(ky, g.ny, (double)g.ny * (double)g.dy, kyv, kdy);
+      double ar = 0.0, ai = 0.0;
+      for (int q = 0; q < op.nterm[o]; ++q) {
+        double mr, mi;
+        spec_mult(op.kind[o][q], op.coef[o][q], kxv, kdx, kyv, kdy, op.kappa2, op.conj != 0, mr, mi);
+        const C2<R> v = col[(int64_t)op.src[o][q] * g.ny + ky];
+        ar += mr * (double)v.x - mi * (double)v.y;
+        ai += mr * (double)v.y + mi * (double)v.x;
+      }
+      if (kx == 0 && ky == 0 && op.mean[o]) {
+        ar = *op.mean[o] * N;
+        ai = 0.0;
+      }
+      A[ky] = C2<R>{(R)ar, (R)ai};
+    }
+    __syncthreads();
+    const C2<R>* r = fft_lds<R, true>(A, B, g.ny, g.lgy, t, tpt, tw);
+    for (int i = t; i < g.ny; i += tpt) op.work[(int64_t)o * g.nperp + (int64_t)i * g.nx + kx] = r[i];
+    __syncthreads();
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(64) k_spec_rows_inv(Geo<R> g, SpecOp<R> op, const C2<R>* __restrict__ twx) {
+  const int l = blockIdx.x, o = blockIdx.y;
+  if (l >= g.ny || o >= op.no) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
+  C2<R>* A = tw + g.nx;
+  C2<R>* B = A + g.nx;
+  const int t = threadIdx.x, tpt = blockDim.x;
+  const C2<R>* w = op.work + (int64_t)o * g.nperp + (int64_t)l * g.nx;
+  for (int i = t; i < g.nx; i += tpt) {
+    tw[i] = twx[i];
+    A[i] = w[i];
+  }
+  __syncthreads();
+  const C2<R>* r = fft_lds<R, true>(A, B, g.nx, g.lgx, t, tpt, tw);
+  const R s = R(1.0 / (double)g.nperp);
+  R* out = op.out[o] + (int64_t)l * g.nx;
+  for (int i = t; i < g.nx; i += tpt) out[i] = op.add[o] ? out[i] + r[i].x * s : r[i].x * s;
+}
+
+// ---------------------------------------------------------------------------
+// Grid helpers
+// ---------------------------------------------------------------------------
+// out[k] = sum_t c_t in_t[k] (+ out[k] when add), for up to 6 terms.
+template <typename R>
+struct Lin {
+  R* out;
+  int add;
+  int nt;
+  double c0;          // constant term
+  const R* in[6];
+  double c[6];
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_lin(Lin<R> a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = (a.add ? (double)a.out[i] : 0.0) + a.c0;
+  for (int t = 0; t < a.nt; ++t) s += a.c[t] * (double)a.in[t][i];
+  a.out[i] = (R)s;
+}
+
+// dst += c * sum(src) (one double accumulator; block sums, then one atomic
+// per block).
+template <typename R>
+__global__ void __launch_bounds__(256) k_sum(const R* __restrict__ src, int64_t n, double c,
+                                             double* __restrict__ dst) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)src[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(dst, c * red[0]);
+}
+
+// dst += c * sum(src^2) (the energy).
+template <typename R>
+__global__ void __launch_bounds__(256) k_sumsq(const R* __restrict__ src, int64_t n, double c,
+                                               double* __restrict__ dst) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = (double)src[i];
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(dst, c * red[0]);
+}
+
+// Transverse-mean leapfrog of one slice, forward: from e = <E_z>_{j-1/2},
+// p = psi0_j and s = sum(J_z): e' = e - h s/N, ez0 = (e + e')/2,
+// p' = p + h e'.  sc = [e, p, s, ez0, e', p'].
+__global__ void k_ode_fwd(double* sc, double h, double N) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double e = sc[0], p = sc[1], s = sc[2];
+  const double en = e - h * s / N;
+  sc[3] = 0.5 * (e + en);
+  sc[4] = en;
+  sc[5] = p + h * en;
+}
+
+// Its transpose.  a = [e_bar', p_bar', ez0_bar] in, out: a[3] = e_bar,
+// a[4] = p_bar (before the psi-mean term), a[5] = the uniform J_z adjoint
+// per node (-h e_next_bar / N).
+__global__ void k_ode_adj(double* a, double h, double N) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double en = a[0] + 0.5 * a[2] + h * a[1];
+  a[3] = en + 0.5 * a[2];
+  a[4] = a[1];
+  a[5] = -h * en / N;
+}
+
+// out[i] += c * (*scalar) for every node.
+template <typename R>
+__global__ void __launch_bounds__(256) k_add_scalar(R* __restrict__ out, int64_t n, const double* s, double c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (R)((double)out[i] + c * (*s));
+}
+
+// ---------------------------------------------------------------------------
+// Plasma: gathers with their transverse gradients, forward right-hand side
+// and its transpose.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Cic {
+  int n00, n10, n01, n11;
+  double fx, fy;
+};
+
+template <typename R>
+__device__ __forceinline__ Cic<R> cic(const Geo<R>& g, R x, R y) {
+  Cic<R> c;
+  int i0, l0;
+  R fx, fy;
+  cell2(g, x, y, i0, l0, fx, fy);
+  const int i1 = (i0 + 1 == g.nx) ? 0 : i0 + 1;
+  const int l1 = (l0 + 1 == g.ny) ? 0 : l0 + 1;
+  c.n00 = l0 * g.nx + i0;
+  c.n10 = l0 * g.nx + i1;
+  c.n01 = l1 * g.nx + i0;
+  c.n11 = l1 * g.nx + i1;
+  c.fx = (double)fx;
+  c.fy = (double)fy;
+  return c;
+}
+
+// value, d/dx, d/dy of the linear interpolant of F
+template <typename R>
+__device__ __forceinline__ void cic_val(const Geo<R>& g, const R* __restrict__ F, const Cic<R>& c, double& v,
+                                        double& dx, double& dy) {
+  const double f00 = F[c.n00], f10 = F[c.n10], f01 = F[c.n01], f11 = F[c.n11];
+  v = f00 * (1 - c.fx) * (1 - c.fy) + f10 * c.fx * (1 - c.fy) + f01 * (1 - c.fx) * c.fy + f11 * c.fx * c.fy;
+  dx = ((f10 - f00) * (1 - c.fy) + (f11 - f01) * c.fy) / (double)g.dx;
+  dy = ((f01 - f00) * (1 - c.fx) + (f11 - f10) * c.fx) / (double)g.dy;
+}
+
+template <typename R>
+__device__ __forceinline__ void cic_add(R* __restrict__ F, const Cic<R>& c, double q) {
+  if (q == 0.0) return;
+  atomic_add(F + c.n00, (R)(q * (1 - c.fx) * (1 - c.fy)));
+  atomic_add(F + c.n10, (R)(q * c.fx * (1 - c.fy)));
+  atomic_add(F + c.n01, (R)(q * (1 - c.fx) * c.fy));
+  atomic_add(F + c.n11, (R)(q * c.fx * c.fy));
+}
+
+// The six fields a plasma particle sees, F = (psi, dxpsi, dypsi, Bx, By, Bz),
+// at slice j (Fa) and the extrapolation (3 Fa - Fm1)/2 (when half is set).
+template <typename R>
+struct Six {
+  const R* a[6];
+  const R* m1[6];
+};
+
+template <typename R>
+__device__ __forceinline__ void six_val(const Geo<R>& g, const Six<R>& F, bool half, const Cic<R>& c,
+                                        double (&v)[6], double (&vx)[6], double (&vy)[6]) {
+  for (int m = 0; m < 6; ++m) {
+    double a, ax, ay;
+    cic_val(g, F.a[m], c, a, ax, ay);
+    if (half) {
+      double b, bx, by;
+      cic_val(g, F.m1[m], c, b, bx, by);
+      a = 0.5 * (3.0 * a - b);
+      ax = 0.5 * (3.0 * ax - bx);
+      ay = 0.5 * (3.0 * ay - by);
+    }
+    v[m] = a;
+    vx[m] = ax;
+    vy[m] = ay;
+  }
+}
+
+// Grid adjoints of the six fields: gbar deposited into Fa_bar (x 1.5 when
+// half) and Fm1_bar (x -0.5 when half).
+template <typename R>
+struct SixBar {
+  R* a[6];
+  R* m1[6];
+};
+
+template <typename R>
+__device__ __forceinline__ void six_add(const SixBar<R>& B, bool half, const Cic<R>& c, const double (&gb)[6]) {
+  for (int m = 0; m < 6; ++m) {
+    if (half) {
+      cic_add(B.a[m], c, 1.5 * gb[m]);
+      cic_add(B.m1[m], c, -0.5 * gb[m]);
+    } else {
+      cic_add(B.a[m], c, gb[m]);
+    }
+  }
+}
+
+// d(x, y, ux, uy)/dxi from the gathered six fields
+__device__ __forceinline__ void rhs_val(const double (&v)[6], double ux, double uy, double (&f)[4]) {
+  const double G = 1.0 + v[0];
+  const double gam = (1.0 + ux * ux + uy * uy + G * G) / (2.0 * G);
+  f[0] = ux / G;
+  f[1] = uy / G;
+  f[2] = gam * v[1] / G - v[4] - uy * v[5] / G;
+  f[3] = gam * v[2] / G + v[3] + ux * v[5] / G;
+}
+
+// Transpose of rhs_val at (v, ux, uy): from f_bar, the adjoints of the six
+// gathered values and of ux, uy.
+__device__ __forceinline__ void rhs_adj(const double (&v)[6], double ux, double uy, const double (&fb)[4],
+                                        double (&gb)[6], double& uxb, double& uyb) {
+  const double G = 1.0 + v[0];
+  const double u2 = ux * ux + uy * uy;
+  const double gam = (1.0 + u2 + G * G) / (2.0 * G);
+  const double A = gam / G;
+  const double A_ux = ux / (G * G), A_uy = uy / (G * G);
+  const double gam_G = 0.5 - (1.0 + u2) / (2.0 * G * G);
+  const double A_G = gam_G / G - gam / (G * G);
+  const double dxp = v[1], dyp = v[2], bz = v[5];
+  uxb = fb[0] / G + fb[2] * A_ux * dxp + fb[3] * (A_ux * dyp + bz / G);
+  uyb = fb[1] / G + fb[2] * (A_uy * dxp - bz / G) + fb[3] * A_uy * dyp;
+  const double Gb = -fb[0] * ux / (G * G) - fb[1] * uy / (G * G) + fb[2] * (A_G * dxp + uy * bz / (G * G)) +
+                    fb[3] * (A_G * dyp - ux * bz / (G * G));
+  gb[0] = Gb;
+  gb[1] = fb[2] * A;
+  gb[2] = fb[3] * A;
+  gb[3] = fb[3];
+  gb[4] = -fb[2];
+  gb[5] = -fb[2] * uy / G + fb[3] * ux / G;
+}
+
+// One RK2 (midpoint) step in double: Y' = Y + h f(Y + h/2 f(Y; Fj); Fh).
+template <typename R>
+__device__ __forceinline__ void rk2_val(const Geo<R>& g, const Six<R>& F, double h, const double (&Y)[4],
+                                        double (&Ys)[4], double (&Yn)[4]) {
+  double v[6], vx[6], vy[6], f[4];
+  six_val(g, F, false, cic(g, (R)Y[0], (R)Y[1]), v, vx, vy);
+  rhs_val(v, Y[2], Y[3], f);
+  for (int c = 0; c < 4; ++c) Ys[c] = Y[c] + 0.5 * h * f[c];
+  six_val(g, F, true, cic(g, (R)Ys[0], (R)Ys[1]), v, vx, vy);
+  rhs_val(v, Ys[2], Ys[3], f);
+  for (int c = 0; c < 4; ++c) Yn[c] = Y[c] + h * f[c];
+}
+
+// Transpose of rk2_val: Yb (adjoint of Y') -> adds to the adjoint of Y and
+// deposits the field adjoints.
+template <typename R>
+__device__ __forceinline__ void rk2_adj(const Geo<R>& g, const Six<R>& F, const SixBar<R>& Fb, double h,
+                                        const double (&Y)[4], const double (&Ynb)[4], double (&Yb)[4]) {
+  double v[6], vx[6], vy[6], f[4], Ys[4];
+  const Cic<R> c0 = cic(g, (R)Y[0], (R)Y[1]);
+  six_val(g, F, false, c0, v, vx, vy);
+  rhs_val(v, Y[2], Y[3], f);
+  for (int c = 0; c < 4; ++c) Ys[c] = Y[c] + 0.5 * h * f[c];
+  // stage 2 at Ys with Fh
+  double v2[6], vx2[6], vy2[6];
+  const Cic<R> c1 = cic(g, (R)Ys[0], (R)Ys[1]);
+  six_val(g, F, true, c1, v2, vx2, vy2);
+  double fb[4], gb[6], uxb, uyb;
+  for (int c = 0; c < 4; ++c) {
+    Yb[c] += Ynb[c];
+    fb[c] = h * Ynb[c];
+  }
+  rhs_adj(v2, Ys[2], Ys[3], fb, gb, uxb, uyb);
+  double Ysb[4] = {0, 0, uxb, uyb};
+  for (int m = 0; m < 6; ++m) {
+    Ysb[0] += gb[m] * vx2[m];
+    Ysb[1] += gb[m] * vy2[m];
+  }
+  six_add(Fb, true, c1, gb);
+  // stage 1 at Y with Fj
+  for (int c = 0; c < 4; ++c) {
+    Yb[c] += Ysb[c];
+    fb[c] = 0.5 * h * Ysb[c];
+  }
+  rhs_adj(v, Y[2], Y[3], fb, gb, uxb, uyb);
+  Yb[2] += uxb;
+  Yb[3] += uyb;
+  for (int m = 0; m < 6; ++m) {
+    Yb[0] += gb[m] * vx[m];
+    Yb[1] += gb[m] * vy[m];
+  }
+  six_add(Fb, false, c0, gb);
+}
+
+template <typename R>
+struct AdjPlasma {
+  Geo<R> g;
+  int np;
+  double nw;           // -w/(dx dy): rho - J_z of one plasma particle per unit area
+  double h;
+  const R* Y[4];       // state at slice j
+  R* Yn[4];            // forward: state out; reverse: adjoint out
+  const R* Yt[4];      // predictor state (stored)
+  const R* Ynb[4];     // adjoint of the state after the push
+  Six<R> F;            // fields of the push
+  SixBar<R> Fb;        // their adjoints
+  const R* psi;        // psi (J stage) or the extrapolated psi (predictor)
+  R* psib;             // its adjoint
+  R* Jx;               // deposits (forward) / their adjoints (reverse)
+  R* Jy;
+  R* Jz;
+  double jscale;       // reverse: scale of the current adjoints (1/(2h) for D)
+  const R* Sb;         // reverse: adjoint of S
+  int* err;
+};
+
+// S += -w W/(dx dy)
+template <typename R>
+__global__ void __launch_bounds__(256) k_af_dep_s(AdjPlasma<R> a, R* __restrict__ S) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.np) return;
+  cic_add(S, cic(a.g, a.Y[0][p], a.Y[1][p]), a.nw);
+}
+
+// J stage: G = 1 + psi(Y); J += -w u/G W/(dx dy)
+template <typename R>
+__global__ void __launch_bounds__(256) k_af_dep_j(AdjPlasma<R> a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.np) return;
+  const Cic<R> c = cic(a.g, a.Y[0][p], a.Y[1][p]);
+  double ps, px, py;
+  cic_val(a.g, a.psi, c, ps, px, py);
+  const double G = 1.0 + ps;
+  if (!(G > QSA_GMIN)) atomicOr(a.err, ERR_BREAKDOWN);
+  const double ux = a.Y[2][p], uy = a.Y[3][p];
+  const double gam = (1.0 + ux * ux + uy * uy + G * G) / (2.0 * G);
+  cic_add(a.Jx, c, a.nw * ux / G);
+  cic_add(a.Jy, c, a.nw * uy / G);
+  cic_add(a.Jz, c, a.nw * (gam - G) / G);
+}
+
+// Predictor: Yt = RK2(Y; F), stored; Jt_perp += -w ut/Gt with Gt = 1 + psit(Yt)
+template <typename R>
+__global__ void __launch_bounds__(256) k_af_pred(AdjPlasma<R> a, R* __restrict__ Yt0, R* __restrict__ Yt1,
+                                                 R* __restrict__ Yt2, R* __restrict__ Yt3) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.np) return;
+  const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
+  double Ys[4], Yt[4];
+  rk2_val(a.g, a.F, a.h, Y, Ys, Yt);
+  Yt0[p] = (R)Yt[0];
+  Yt1[p] = (R)Yt[1];
+  Yt2[p] = (R)Yt[2];
+  Yt3[p] = (R)Yt[3];
+  const Cic<R> c = cic(a.g, (R)Yt[0], (R)Yt[1]);
+  double ps, px, py;
+  cic_val(a.g, a.psi, c, ps, px, py);
+  const double G = 1.0 + ps;
+  if (!(G > QSA_GMIN)) atomicOr(a.err, ERR_BREAKDOWN);
+  cic_add(a.Jx, c, a.nw * Yt[2] / G);
+  cic_add(a.Jy, c, a.nw * Yt[3] / G);
+}
+
+// Final advance: Yn = wrap(RK2(Y; F))
+template <typename R>
+__global__ void __launch_bounds__(256) k_af_final(AdjPlasma<R> a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.np) return;
+  const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
+  double Ys[4], Yn[4];
+  rk2_val(a.g, a.F, a.h, Y, Ys, Yn);
+  a.Yn[0][p] = wrap_pos((R)Yn[0], a.g.lx, a.g.inv_lx);
+  a.Yn[1][p] = wrap_pos((R)Yn[1], a.g.ly, a.g.inv_ly);
+  a.Yn[2][p] = (R)Yn[2];
+  a.Yn[3][p] = (R)Yn[3];
+}
+
+// Reverse of the final advance: Yn (adjoint of Y) = RK2^T(Ynb); fields.
+template <typename R>
+__global__ void __launch_bounds__(256) k_ar_final(AdjPlasma<R> a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.np) return;
+  const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
+  const double Ynb[4] = {a.Ynb[0][p], a.Ynb[1][p], a.Ynb[2][p], a.Ynb[3][p]};
+  double Yb[4] = {0, 0, 0, 0};
+  rk2_adj(a.g, a.F, a.Fb, a.h, Y, Ynb, Yb);
+  for (int c = 0; c < 4; ++c) a.Yn[c][p] = (R)Yb[c];
+}
+
+// Reverse of predictor iteration: the adjoint of Jt_perp (jscale * (Jx, Jy))
+// -> adjoint of Yt and of psit -> RK2^T into the adjoint of Y (added).
+template <typename R>
+__global__ void __launch_bounds__(256) k_ar_pred(AdjPlasma<R> a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.np) return;
+  const Geo<R>& g = a.g;
+  const double Yt[4] = {a.Yt[0][p], a.Yt[1][p], a.Yt[2][p], a.Yt[3][p]};
+  const Cic<R> c = cic(g, (R)Yt[0], (R)Yt[1]);
+  double ps, psx, psy;
+  cic_val(g, a.psi, c, ps, psx, psy);
+  const double G = 1.0 + ps;
+  double jx, jxx, jxy, jy, jyx, jyy;
+  cic_val(g, a.Jx, c, jx, jxx, jxy);
+  cic_val(g, a.Jy, c, jy, jyx, jyy);
+  // nw (hence q) already holds the 1/(dx dy) of the deposit
+  const double s = a.jscale;
+  const double qx = a.nw * Yt[2] / G, qy = a.nw * Yt[3] / G;
+  // q_bar (deposit transpose) and position terms of the deposit
+  const double qxb = s * jx, qyb = s * jy;
+  double Ytb[4];
+  Ytb[0] = s * (qx * jxx + qy * jyx);
+  Ytb[1] = s * (qx * jxy + qy * jyy);
+  Ytb[2] = qxb * a.nw / G;
+  Ytb[3] = qyb * a.nw / G;
+  const double Gb = -(qxb * qx + qyb * qy) / G;
+  Ytb[0] += Gb * psx;
+  Ytb[1] += Gb * psy;
+  cic_add(a.psib, c, Gb);
+  const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
+  double Yb[4] = {a.Yn[0][p], a.Yn[1][p], a.Yn[2][p], a.Yn[3][p]};
+  rk2_adj(g, a.F, a.Fb, a.h, Y, Ytb, Yb);
+  for (int k = 0; k < 4; ++k) a.Yn[k][p] = (R)Yb[k];
+}
+
+// Reverse of the J stage (deposits of -w u/G with G = 1 + psi(Y); when Jx is
+// set) or of the rho - J_z deposit of -w (adjoint Sb; when Sb is set): adds
+// to the adjoint of Y and, for the J stage, of psi.  The two run as separate
+// launches: the adjoint of S needs the psi adjoint the J stage completes.
+template <typename R>
+__global__ void __launch_bounds__(256) k_ar_jstage(AdjPlasma<R> a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.np) return;
+  const Geo<R>& g = a.g;
+  const Cic<R> c = cic(g, a.Y[0][p], a.Y[1][p]);
+  double xb = 0.0, yb = 0.0, uxb = 0.0, uyb = 0.0;   // nw holds the 1/(dx dy) of the deposits
+  if (a.Jx) {
+    const double ux = a.Y[2][p], uy = a.Y[3][p];
+    double ps, psx, psy;
+    cic_val(g, a.psi, c, ps, psx, psy);
+    const double G = 1.0 + ps;
+    const double u2 = ux * ux + uy * uy;
+    double jx, jxx, jxy, jy, jyx, jyy, jz, jzx, jzy;
+    cic_val(g, a.Jx, c, jx, jxx, jxy);
+    cic_val(g, a.Jy, c, jy, jyx, jyy);
+    cic_val(g, a.Jz, c, jz, jzx, jzy);
+    const double qx = a.nw * ux / G, qy = a.nw * uy / G;
+    const double qz = a.nw * ((1.0 + u2 + G * G) / (2.0 * G * G) - 1.0);
+    const double qxb = jx, qyb = jy, qzb = jz;
+    xb = qx * jxx + qy * jyx + qz * jzx;
+    yb = qx * jxy + qy * jyy + qz * jzy;
+    uxb = a.nw * (qxb / G + qzb * ux / (G * G));
+    uyb = a.nw * (qyb / G + qzb * uy / (G * G));
+    const double Gb = a.nw * (-qxb * ux / (G * G) - qyb * uy / (G * G) - qzb * (1.0 + u2) / (G * G * G));
+    xb += Gb * psx;
+    yb += Gb * psy;
+    cic_add(a.psib, c, Gb);
+  }
+  if (a.Sb) {
+    double sv, sx, sy;
+    cic_val(g, a.Sb, c, sv, sx, sy);
+    xb += a.nw * sx;
+    yb += a.nw * sy;
+  }
+  a.Yn[0][p] = (R)((double)a.Yn[0][p] + xb);
+  a.Yn[1][p] = (R)((double)a.Yn[1][p] + yb);
+  a.Yn[2][p] = (R)((double)a.Yn[2][p] + uxb);
+  a.Yn[3][p] = (R)((double)a.Yn[3][p] + uyb);
+}
+
+// ---------------------------------------------------------------------------
+// Beam: 3D linear shape with its gradient, sources and their transpose, the
+// Boris push and its transpose.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Cic3 {
+  Cic<R> c;
+  int j0;        // lower slice (may be -1 or nxi - 1)
+  double fz;
+  bool in;       // any node inside
+};
+
+template <typename R>
+__device__ __forceinline__ Cic3<R> cic3(const Geo<R>& g, R x, R y, double xi, double inv_dxi) {
+  Cic3<R> c;
+  const double gz = xi * inv_dxi;
+  c.in = gz > -1.0 && gz < (double)g.nxi;
+  const double f0 = floor(gz);
+  c.j0 = c.in ? (int)f0 : 0;
+  c.fz = c.in ? gz - f0 : 0.0;
+  c.c = cic(g, x, y);
+  return c;
+}
+
+// value and gradient of the 3D interpolant of a [nxi][ny][nx] field
+template <typename R>
+__device__ __forceinline__ void cic3_val(const Geo<R>& g, const R* __restrict__ F, const Cic3<R>& c,
+                                         double& v, double& vx, double& vy, double& vz) {
+  v = vx = vy = vz = 0.0;
+  if (!c.in) return;
+  double a[2] = {0, 0}, ax[2] = {0, 0}, ay[2] = {0, 0};
+  for (int d = 0; d < 2; ++d) {
+    const int jj = c.j0 + d;
+    if (jj < 0 || jj >= g.nxi) continue;
+    cic_val(g, F + (int64_t)jj * g.nperp, c.c, a[d], ax[d], ay[d]);
+  }
+  v = (1.0 - c.fz) * a[0] + c.fz * a[1];
+  vx = (1.0 - c.fz) * ax[0] + c.fz * ax[1];
+  vy = (1.0 - c.fz) * ay[0] + c.fz * ay[1];
+  vz = (a[1] - a[0]) / (double)g.dxi;
+}
+
+template <typename R>
+__device__ __forceinline__ void cic3_add(const Geo<R>& g, R* __restrict__ F, const Cic3<R>& c, double q) {
+  if (!c.in || q == 0.0) return;
+  for (int d = 0; d < 2; ++d) {
+    const int jj = c.j0 + d;
+    if (jj < 0 || jj >= g.nxi) continue;
+    cic_add(F + (int64_t)jj * g.nperp, c.c, q * (d ? c.fz : 1.0 - c.fz));
+  }
+}
+
+template <typename R>
+struct AdjBeam {
+  Geo<R> g;
+  int64_t n;
+  double zdv;          // Z/(dx dy dxi)
+  double qh;           // (Z/M) dt/2
+  double dt;
+  double inv_dxi;
+  double xi_max;
+  const R* x;          // state at step n (tape)
+  const R* y;
+  const double* xi;
+  const R* ux;
+  const R* uy;
+  const R* uz;
+  const R* w;
+  R* xo;               // forward: state at step n + 1
+  R* yo;
+  double* xio;
+  R* uxo;
+  R* uyo;
+  R* uzo;
+  R* wo;
+  R* src;              // forward: sources [4][nxi][ny][nx]
+  const R* srcb;       // reverse: their adjoint
+  const R* fields;     // [7][nxi][ny][nx] of the step's sweep
+  R* fieldsb;          // their adjoint
+  R* b[7];             // adjoint of x, y, xi, ux, uy, uz, w (in place: step n+1 -> step n)
+};
+
+// 1 - v_z, v_x, v_y, v_z per unit charge and their u-derivatives
+__device__ __forceinline__ void beam_v(double ux, double uy, double uz, double (&v)[4], double (&dv)[4][3]) {
+  const double up2 = ux * ux + uy * uy;
+  const double g2 = 1.0 + up2 + uz * uz;
+  const double gam = sqrt(g2);
+  const double P = 1.0 + up2, Q = gam * (gam + uz);
+  v[0] = P / Q;
+  v[1] = ux / gam;
+  v[2] = uy / gam;
+  v[3] = uz / gam;
+  const double u[3] = {ux, uy, uz};
+  const double g3 = gam * g2;
+  for (int a = 0; a < 3; ++a) {
+    const double dgam = u[a] / gam;
+    const double dQ = (2.0 * gam + uz) * dgam + (a == 2 ? gam : 0.0);
+    const double dP = (a < 2) ? 2.0 * u[a] : 0.0;
+    dv[0][a] = (dP * Q - P * dQ) / (Q * Q);
+    for (int b = 0; b < 3; ++b) dv[1 + b][a] = ((a == b) ? 1.0 / gam : 0.0) - u[b] * u[a] / g3;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_ab_sources(AdjBeam<R> a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n || a.w[p] == R(0)) return;
+  const Cic3<R> c = cic3(a.g, a.x[p], a.y[p], a.xi[p], a.inv_dxi);
+  double v[4], dv[4][3];
+  beam_v(a.ux[p], a.uy[p], a.uz[p], v, dv);
+  const double q = a.zdv * (double)a.w[p];
+  const int64_t plane = (int64_t)a.g.nxi * a.g.nperp;
+  for (int k = 0; k < 4; ++k) cic3_add(a.g, a.src + k * plane, c, q * v[k]);
+}
+
+// Transpose of the sources: adds to the adjoints of position, momentum and
+// weight of step n.
+template <typename R>
+__global__ void __launch_bounds__(256) k_ab_sources_adj(AdjBeam<R> a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n || a.w[p] == R(0)) return;
+  const Cic3<R> c = cic3(a.g, a.x[p], a.y[p], a.xi[p], a.inv_dxi);
+  double v[4], dv[4][3];
+  beam_v(a.ux[p], a.uy[p], a.uz[p], v, dv);
+  const double q = a.zdv * (double)a.w[p];
+  const int64_t plane = (int64_t)a.g.nxi * a.g.nperp;
+  double gb[4], pos[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, wb = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    double s, sx, sy, sz;
+    cic3_val(a.g, a.srcb + k * plane, c, s, sx, sy, sz);
+    gb[k] = s;
+    pos[0] += q * v[k] * sx;
+    pos[1] += q * v[k] * sy;
+    pos[2] += q * v[k] * sz;
+    wb += a.zdv * v[k] * s;
+    for (int d = 0; d < 3; ++d) ub[d] += q * s * dv[k][d];
+  }
+  a.b[0][p] = (R)((double)a.b[0][p] + pos[0]);
+  a.b[1][p] = (R)((double)a.b[1][p] + pos[1]);
+  a.b[2][p] = (R)((double)a.b[2][p] + pos[2]);
+  a.b[3][p] = (R)((double)a.b[3][p] + ub[0]);
+  a.b[4][p] = (R)((double)a.b[4][p] + ub[1]);
+  a.b[5][p] = (R)((double)a.b[5][p] + ub[2]);
+  a.b[6][p] = (R)((double)a.b[6][p] + wb);
+}
+
+__device__ __forceinline__ void cross3(const double (&a)[3], const double (&b)[3], double (&c)[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// The six beam-push fields (d_x psi, d_y psi, E_z, B_x, B_y, B_z) at the
+// particle, with gradients.
+template <typename R>
+__device__ __forceinline__ void boris_fields(const AdjBeam<R>& a, const Cic3<R>& c, double (&f)[6],
+                                             double (&fg)[6][3]) {
+  const int slot[6] = {F_DXPSI, F_DYPSI, F_EZ, F_BX, F_BY, F_BZ};
+  const int64_t plane = (int64_t)a.g.nxi * a.g.nperp;
+  for (int m = 0; m < 6; ++m) cic3_val(a.g, a.fields + slot[m] * plane, c, f[m], fg[m][0], fg[m][1], fg[m][2]);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_ab_push(AdjBeam<R> a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n) return;
+  const Cic3<R> c = cic3(a.g, a.x[p], a.y[p], a.xi[p], a.inv_dxi);
+  double f[6], fg[6][3];
+  boris_fields(a, c, f, fg);
+  const double E[3] = {-f[0] + f[4], -f[1] - f[3], f[2]};
+  const double B[3] = {f[3], f[4], f[5]};
+  double um[3] = {a.ux[p] + a.qh * E[0], a.uy[p] + a.qh * E[1], a.uz[p] + a.qh * E[2]};
+  const double gm = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+  const double t[3] = {a.qh * B[0] / gm, a.qh * B[1] / gm, a.qh * B[2] / gm};
+  const double s = 2.0 / (1.0 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+  const double sv[3] = {s * t[0], s * t[1], s * t[2]};
+  double cx[3], up[3], uq[3];
+  cross3(um, t, cx);
+  for (int d = 0; d < 3; ++d) up[d] = um[d] + cx[d];
+  cross3(up, sv, cx);
+  for (int d = 0; d < 3; ++d) uq[d] = um[d] + cx[d];
+  const double un[3] = {uq[0] + a.qh * E[0], uq[1] + a.qh * E[1], uq[2] + a.qh * E[2]};
+  const double up2 = un[0] * un[0] + un[1] * un[1];
+  const double gam = sqrt(1.0 + up2 + un[2] * un[2]);
+  a.xo[p] = wrap_pos((R)(a.x[p] + a.dt * un[0] / gam), a.g.lx, a.g.inv_lx);
+  a.yo[p] = wrap_pos((R)(a.y[p] + a.dt * un[1] / gam), a.g.ly, a.g.inv_ly);
+  const double xin = a.xi[p] + a.dt * (1.0 + up2) / (gam * (gam + un[2]));
+  a.xio[p] = xin;
+  a.uxo[p] = (R)un[0];
+  a.uyo[p] = (R)un[1];
+  a.uzo[p] = (R)un[2];
+  a.wo[p] = (xin >= a.xi_max) ? R(0) : a.w[p];
+}
+
+// Transpose of the push: b (adjoints at step n + 1) -> adjoints at step n
+// (in place), field adjoints deposited.
+template <typename R>
+__global__ void __launch_bounds__(256) k_ab_push_adj(AdjBeam<R> a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.n) return;
+  const Cic3<R> c = cic3(a.g, a.x[p], a.y[p], a.xi[p], a.inv_dxi);
+  double f[6], fg[6][3];
+  boris_fields(a, c, f, fg);
+  const double qh = a.qh, dt = a.dt;
+  const double E[3] = {-f[0] + f[4], -f[1] - f[3], f[2]};
+  const double B[3] = {f[3], f[4], f[5]};
+  double um[3] = {a.ux[p] + qh * E[0], a.uy[p] + qh * E[1], a.uz[p] + qh * E[2]};
+  const double gm = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+  const double t[3] = {qh * B[0] / gm, qh * B[1] / gm, qh * B[2] / gm};
+  const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+  const double s = 2.0 / (1.0 + tt);
+  const double sv[3] = {s * t[0], s * t[1], s * t[2]};
+  double cx[3], up[3], uq[3];
+  cross3(um, t, cx);
+  for (int d = 0; d < 3; ++d) up[d] = um[d] + cx[d];
+  cross3(up, sv, cx);
+  for (int d = 0; d < 3; ++d) uq[d] = um[d] + cx[d];
+  const double un[3] = {uq[0] + qh * E[0], uq[1] + qh * E[1], uq[2] + qh * E[2]};
+  const double up2 = un[0] * un[0] + un[1] * un[1];
+  const double g2 = 1.0 + up2 + un[2] * un[2];
+  const double gam = sqrt(g2);
+  const double xin = a.xi[p] + dt * (1.0 + up2) / (gam * (gam + un[2]));
+  // adjoints at step n + 1
+  const double xb = a.b[0][p], yb = a.b[1][p], xib = a.b[2][p];
+  double unb[3] = {a.b[3][p], a.b[4][p], a.b[5][p]};
+  const double wb = (xin >= a.xi_max) ? 0.0 : (double)a.b[6][p];
+  // x' = x + dt un_x/gam, y' likewise, xi' = xi + dt P/Q
+  const double g3 = gam * g2;
+  for (int d = 0; d < 3; ++d) {
+    unb[d] += xb * dt * (((d == 0) ? 1.0 / gam : 0.0) - un[0] * un[d] / g3);
+    unb[d] += yb * dt * (((d == 1) ? 1.0 / gam : 0.0) - un[1] * un[d] / g3);
+  }
+  {
+    const double P = 1.0 + up2, Q = gam * (gam + un[2]);
+    for (int d = 0; d < 3; ++d) {
+      const double dgam = un[d] / gam;
+      const double dQ = (2.0 * gam + un[2]) * dgam + (d == 2 ? gam : 0.0);
+      const double dP = (d < 2) ? 2.0 * un[d] : 0.0;
+      unb[d] += xib * dt * (dP * Q - P * dQ) / (Q * Q);
+    }
+  }
+  // un = uq + qh E
+  double Eb[3] = {qh * unb[0], qh * unb[1], qh * unb[2]};
+  double uqb[3] = {unb[0], unb[1], unb[2]};
+  // uq = um + up x sv
+  double umb[3] = {uqb[0], uqb[1], uqb[2]};
+  double upb[3], svb[3];
+  cross3(sv, uqb, upb);     // up_bar += sv x uq_bar
+  cross3(uqb, up, svb);     // sv_bar += uq_bar x up
+  // sv = s t, s = 2/(1 + |t|^2)
+  const double svt = svb[0] * t[0] + svb[1] * t[1] + svb[2] * t[2];
+  double tb[3];
+  for (int d = 0; d < 3; ++d) tb[d] = s * svb[d] - s * s * svt * t[d];
+  // up = um + um x t
+  for (int d = 0; d < 3; ++d) umb[d] += upb[d];
+  double tmp[3];
+  cross3(t, upb, tmp);      // um_bar += t x up_bar
+  for (int d = 0; d < 3; ++d) umb[d] += tmp[d];
+  cross3(upb, um, tmp);     // t_bar += up_bar x um
+  for (int d = 0; d < 3; ++d) tb[d] += tmp[d];
+  // t = qh B/gm
+  double Bb[3];
+  double gmb = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    Bb[d] = qh * tb[d] / gm;
+    gmb -= tb[d] * t[d] / gm;
+  }
+  // gm = sqrt(1 + |um|^2)
+  for (int d = 0; d < 3; ++d) umb[d] += gmb * um[d] / gm;
+  // um = u + qh E
+  for (int d = 0; d < 3; ++d) Eb[d] += qh * umb[d];
+  // field values: (dxpsi, dypsi, Ez, Bx, By, Bz)
+  const double gb[6] = {-Eb[0], -Eb[1], Eb[2], -Eb[1] + Bb[0], Eb[0] + Bb[1], Bb[2]};
+  double pos[3] = {xb, yb, xib};
+  for (int m = 0; m < 6; ++m)
+    for (int d = 0; d < 3; ++d) pos[d] += gb[m] * fg[m][d];
+  const int slot[6] = {F_DXPSI, F_DYPSI, F_EZ, F_BX, F_BY, F_BZ};
+  const int64_t plane = (int64_t)a.g.nxi * a.g.nperp;
+  for (int m = 0; m < 6; ++m) cic3_add(a.g, a.fieldsb + slot[m] * plane, c, gb[m]);
+  a.b[0][p] = (R)pos[0];
+  a.b[1][p] = (R)pos[1];
+  a.b[2][p] = (R)pos[2];
+  a.b[3][p] = (R)umb[0];
+  a.b[4][p] = (R)umb[1];
+  a.b[5][p] = (R)umb[2];
+  a.b[6][p] = (R)wb;
+}
+
+// bins in the library's particle order: out[p] = bin_at_load[id[p]]
+__global__ void __launch_bounds__(256) k_gather_bins(const int* __restrict__ bin_at_load,
+                                                     const int64_t* __restrict__ id, int* __restrict__ out,
+                                                     int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) out[p] = bin_at_load[id[p]];
+}
+
+// weights scaled by their bin amplitude
+template <typename R>
+__global__ void __launch_bounds__(256) k_ab_scale_w(const R* __restrict__ w0, const int* __restrict__ bin,
+                                                    const double* __restrict__ amp, int nb, R* __restrict__ w,
+                                                    int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int b = bin[p];
+  w[p] = (b >= 0 && b < nb) ? (R)((double)w0[p] * amp[b]) : w0[p];
+}
+
+// gradient per bin: sum_p w_bar_p w0_p (LDS per-bin sums, one atomic per
+// bin per block)
+template <typename R>
+__global__ void __launch_bounds__(256) k_ab_bin_grad(const R* __restrict__ wb, const R* __restrict__ w0,
+                                                     const int* __restrict__ bin, int nb, double* __restrict__ grad,
+                                                     int64_t n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc = reinterpret_cast<double*>(smem_raw);
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc[i] = 0.0;
+  __syncthreads();
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const int b = bin[p];
+    if (b >= 0 && b < nb) atomicAdd(acc + b, (double)wb[p] * (double)w0[p]);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x)
+    if (acc[i] != 0.0) atomicAdd(grad + i, acc[i]);
+}
+
+}  // namespace qsa

@@ -32,8 +32,9 @@ def _f64(a):
 def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt: float,
                 species: Sequence, n_plasma: int, plasma_w: float,
                 beam_capacity: Sequence[int], precision: str = "f64", n_corr: int = 3,
-                kappa2: float = 0.75, pipeline: int = 1) -> L.QSAParams:
-    """species: sequence of (Z, M); pipeline: beam steps in flight (1 = off)."""
+                kappa2: float = 0.75, pipeline: int = 1, adjoint_steps: int = 0) -> L.QSAParams:
+    """species: sequence of (Z, M); pipeline: beam steps in flight (1 = off);
+    adjoint_steps: most steps qsa_adjoint_sweep differentiates (0 = none)."""
     p = L.QSAParams()
     p.nx, p.ny, p.nxi = nx, ny, nxi
     p.precision = _PREC[precision]
@@ -42,6 +43,7 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
     p.n_plasma, p.plasma_w = n_plasma, plasma_w
     p.n_species = len(species)
     p.pipeline = int(pipeline)
+    p.adjoint_steps = int(adjoint_steps)
     for i, (Z, M) in enumerate(species):
         p.species[i].Z = int(Z)
         p.species[i].M = float(M)
@@ -51,13 +53,13 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
 
 def params_from_workload(wl, precision: Optional[str] = None,
                          beam_capacity: Optional[Sequence[int]] = None,
-                         pipeline: int = 1) -> L.QSAParams:
+                         pipeline: int = 1, adjoint_steps: int = 0) -> L.QSAParams:
     """Parameters of a workload description (duck-typed: grid, species, loading)."""
     caps = beam_capacity or [wl.n_beam(s) for s in range(len(wl.species))]
     return make_params(wl.nx, wl.ny, wl.nxi, wl.dx, wl.dy, wl.dxi, wl.dt,
                        [(s.Z, s.M) for s in wl.species], wl.n_plasma,
                        wl.dx * wl.dy / wl.plasma_ppc, caps, precision or wl.precision,
-                       wl.n_corr, wl.kappa2, pipeline)
+                       wl.n_corr, wl.kappa2, pipeline, adjoint_steps)
 
 
 class Sim:
@@ -156,6 +158,21 @@ class Sim:
             out.append(int(v.value))
         return tuple(out)
 
+    def adjoint_sweep(self, n_steps: int, amps, bins):
+        """Transverse magnetic energy after n_steps beam steps with the weights
+        scaled by amps[bin] and its gradient with respect to amps.  bins: one
+        int array per species in load order.  Returns (loss, grad ndarray)."""
+        amps = np.ascontiguousarray(np.asarray(amps, dtype=np.float64))
+        arrs = [np.ascontiguousarray(np.asarray(b, dtype=np.int32)) for b in bins]
+        ptrs = (C.POINTER(C.c_int32) * len(arrs))(
+            *[a.ctypes.data_as(C.POINTER(C.c_int32)) for a in arrs])
+        loss = C.c_double(0.0)
+        grad = np.zeros(amps.size, dtype=np.float64)
+        self._check(self.lib.qsa_adjoint_sweep(
+            self.ctx, int(n_steps), int(amps.size), amps.ctypes.data_as(C.POINTER(C.c_double)), ptrs,
+            C.byref(loss), grad.ctypes.data_as(C.POINTER(C.c_double))))
+        return float(loss.value), grad
+
     def autotune(self) -> float:
         """Time the launch shapes and steps in flight on this machine's data and
         keep the fastest; returns the best ms per step (per sweep without
@@ -248,3 +265,20 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class FieldEnergy(torch.autograd.Function):
+    """torch.autograd.Function over the library's adjoint: forward gives the
+    transverse magnetic energy after n_steps beam steps as a function of the
+    beam-amplitude bins, backward the library's reverse-mode gradient."""
+
+    @staticmethod
+    def forward(ctx, amps: torch.Tensor, sim: "Sim", n_steps: int, bins):
+        loss, grad = sim.adjoint_sweep(n_steps, amps.detach().cpu().numpy(), bins)
+        ctx.save_for_backward(torch.as_tensor(grad, dtype=amps.dtype))
+        return torch.tensor(loss, dtype=amps.dtype)
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return g * grad, None, None, None

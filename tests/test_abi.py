@@ -81,8 +81,11 @@ def test_pipeline_workspace_and_validation():
     assert lib.qsa_workspace_bytes(C.byref(_params(pipeline=9))) == 0
     assert lib.qsa_workspace_bytes(C.byref(_params(pipeline=-1))) == 0
     p = _params()
-    p.reserved_ = 1
+    p.adjoint_steps = -1
     assert lib.qsa_workspace_bytes(C.byref(p)) == 0
+    p.adjoint_steps = 2
+    # the beam (7 arrays) and the fields (7 planes) of 3 steps, at least
+    assert lib.qsa_workspace_bytes(C.byref(p)) >= one + 3 * (7 * 128 * 64 * 8 + 65024 * 7 * 8)
     v = C.c_int64()
     assert lib.qsa_get_option(None, 1, C.byref(v)) == -1
 

@@ -1,0 +1,100 @@
+"""The library's adjoint (qsa_adjoint_sweep) against the oracle's gradient
+(reverse-mode differentiation of the float64 scheme, itself pinned by
+central differences) on identical seeded inputs."""
+import numpy as np
+import pytest
+
+import qsa_workloads as W
+from oracle import adjoint as OA
+
+pytestmark = pytest.mark.gpu
+
+AMPS = np.array([1.0, 0.8, 1.2, 1.0])
+
+
+def _case(nb=4, alpha=0.1):
+    return W.small_3d(16, 16, 12).with_(
+        n_bins=nb, dt=5.0, species=(W.Species(Z=-1, alpha=alpha, ppc=2, sigma_par=1e-3),))
+
+
+def _sim(wl, precision="f64", pipeline=1, steps=2, beams=None):
+    import paper_2607_24214_amd as Q
+    beams = beams if beams is not None else W.beam(wl)
+    s = Q.Sim(Q.params_from_workload(wl, precision=precision, pipeline=pipeline, adjoint_steps=max(steps, 1)))
+    s.load_plasma(W.plasma_template(wl))
+    for k, b in enumerate(beams):
+        s.load_beam(k, b)
+    return s, beams
+
+
+def _oracle(wl, beams, steps):
+    return OA.energy_and_gradient(wl, W.plasma_template(wl), beams, steps, AMPS)
+
+
+@pytest.mark.parametrize("steps", [0, 2])
+def test_adjoint_matches_oracle_fp64(steps):
+    wl = _case()
+    sim, beams = _sim(wl, steps=steps)
+    print(f"[adjoint] steps={steps}", flush=True)
+    L, g = sim.adjoint_sweep(steps, AMPS, [b["bin"] for b in beams])
+    Lo, go = _oracle(wl, beams, steps)
+    print(f"[adjoint] loss {L:.12e} vs {Lo:.12e}; grad {g} vs {go}", flush=True)
+    assert L == pytest.approx(Lo, rel=1e-10)
+    assert np.abs(g - go).max() <= 1e-8 * np.abs(go).max()
+
+
+def test_adjoint_across_checkpoint_segments_pair_fp64():
+    """40 slices: three checkpoint segments (the last one partial), recomputed
+    in the reverse pass; an electron-positron beam (two species)."""
+    wl = W.small_3d(16, 8, 40).with_(
+        n_bins=6, dt=5.0, species=(W.Species(Z=-1, alpha=0.05, ppc=2, sigma_par=1e-3),
+                                   W.Species(Z=1, alpha=0.05, ppc=2, sigma_par=1e-3)))
+    amps = np.linspace(0.8, 1.2, 6)
+    sim, beams = _sim(wl, steps=1)
+    L, g = sim.adjoint_sweep(1, amps, [b["bin"] for b in beams])
+    Lo, go = OA.energy_and_gradient(wl, W.plasma_template(wl), beams, 1, amps)
+    print(f"[adjoint] 3 segments, pair: grad rel {np.abs(g - go).max() / np.abs(go).max():.2e}", flush=True)
+    assert L == pytest.approx(Lo, rel=1e-10)
+    assert np.abs(g - go).max() <= 1e-8 * np.abs(go).max()
+
+
+def test_adjoint_with_sorted_beam_and_pipelining_fp64():
+    """A pipelined context keeps its beam sorted internally; bins are given in
+    load order and must follow the particles.  The beam is loaded shuffled."""
+    wl = _case()
+    beams = W.beam(wl)
+    perm = np.random.default_rng(3).permutation(len(beams[0]["x"]))
+    shuffled = [{k: (v[perm] if isinstance(v, np.ndarray) else v) for k, v in beams[0].items()}]
+    sim, _ = _sim(wl, pipeline=4, steps=2, beams=shuffled)
+    before = sim.read_beam(0)
+    L, g = sim.adjoint_sweep(2, AMPS, [shuffled[0]["bin"]])
+    Lo, go = _oracle(wl, beams, 2)
+    assert L == pytest.approx(Lo, rel=1e-10)
+    assert np.abs(g - go).max() <= 1e-8 * np.abs(go).max()
+    after = sim.read_beam(0)
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+
+
+def test_adjoint_fp32():
+    wl = _case()
+    sim, beams = _sim(wl, precision="f32", steps=2)
+    L, g = sim.adjoint_sweep(2, AMPS, [b["bin"] for b in beams])
+    Lo, go = _oracle(wl, beams, 2)
+    print(f"[adjoint] fp32 loss rel {abs(L / Lo - 1):.2e}, grad rel {np.abs(g - go).max() / np.abs(go).max():.2e}",
+          flush=True)
+    assert L == pytest.approx(Lo, rel=1e-3)
+    assert np.abs(g - go).max() <= 1e-2 * np.abs(go).max()
+
+
+def test_autograd_function():
+    import torch
+    import paper_2607_24214_amd as Q
+    wl = _case()
+    sim, beams = _sim(wl, steps=1)
+    a = torch.tensor(AMPS, dtype=torch.float64, requires_grad=True)
+    loss = Q.FieldEnergy.apply(a, sim, 1, [b["bin"] for b in beams])
+    (2.0 * loss).backward()
+    L, g = sim.adjoint_sweep(1, AMPS, [b["bin"] for b in beams])
+    assert float(loss) == pytest.approx(L, rel=1e-12)
+    assert np.allclose(a.grad.numpy(), 2.0 * g, rtol=1e-12, atol=0.0)
