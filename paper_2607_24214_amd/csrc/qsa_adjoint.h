@@ -5,10 +5,10 @@
 // gather, spectral solve, predictor-corrector iteration, plasma push, k = 0
 // leapfrog and beam Boris push of the forward path (see qsa_kernels.h for
 // the scheme), in reverse order.  Its forward passes run the same scheme
-// with simple kernels (one thread per particle, global atomics for deposits,
-// batched full complex transforms) that keep the plasma particles in a fixed
-// order, so that particle identities carry across slices; they store what
-// the reverse pass needs:
+// with kernels of their own (one thread per particle, deposits accumulated
+// per block in an LDS tile, batched full complex transforms) that keep the
+// plasma particles in a fixed order, so that particle identities carry
+// across slices; they store what the reverse pass needs:
 //   * per beam step: the beam state and the 7 stored field planes;
 //   * per sweep: the plasma state and J_perp of the previous slice every
 //     QSA_ADJ_CKPT slices (checkpoints);
@@ -277,6 +277,7 @@ __global__ void __launch_bounds__(256) k_add_scalar(R* __restrict__ out, int64_t
 template <typename R>
 struct Cic {
   int n00, n10, n01, n11;
+  int i0, l0;          // lower cell
   double fx, fy;
 };
 
@@ -292,6 +293,8 @@ __device__ __forceinline__ Cic<R> cic(const Geo<R>& g, R x, R y) {
   c.n10 = l0 * g.nx + i1;
   c.n01 = l1 * g.nx + i0;
   c.n11 = l1 * g.nx + i1;
+  c.i0 = i0;
+  c.l0 = l0;
   c.fx = (double)fx;
   c.fy = (double)fy;
   return c;
@@ -314,6 +317,129 @@ __device__ __forceinline__ void cic_add(R* __restrict__ F, const Cic<R>& c, doub
   atomic_add(F + c.n10, (R)(q * c.fx * (1 - c.fy)));
   atomic_add(F + c.n01, (R)(q * (1 - c.fx) * c.fy));
   atomic_add(F + c.n11, (R)(q * c.fx * c.fy));
+}
+
+// ---------------------------------------------------------------------------
+// Block-local scatter accumulation.  The particles of a block (consecutive
+// in memory, hence close in space while the order of loading by cell holds)
+// reduce the bounding box of the cells they scatter at.  When the box's
+// nodes fit the LDS tile, the linear-shape weights accumulate there with LDS
+// atomics and the block then adds every touched node to the grid with one
+// global atomic per channel; otherwise each particle adds its nodes to the
+// grid directly.  Same-address atomics of neighbouring particles, which
+// serialize at the L2, are thereby merged.  Every thread of the block calls
+// box_reduce, tile_zero and tile_flush (they hold barriers).  NZ = 1 for
+// transverse grids [ny][nx] (cell slice 0), 2 for [nxi][ny][nx] grids.
+// ---------------------------------------------------------------------------
+template <typename R, int NCH>
+struct AdjTile {
+  static constexpr int CAP = 40960 / (NCH * (int)sizeof(R));   // nodes per channel
+};
+
+struct BoxAcc {
+  int lo[3], hi[3];    // cell (j, l, i) range of one thread
+};
+__device__ __forceinline__ void box_init(BoxAcc& b) {
+  for (int d = 0; d < 3; ++d) {
+    b.lo[d] = INT_MAX;
+    b.hi[d] = INT_MIN;
+  }
+}
+__device__ __forceinline__ void box_add(BoxAcc& b, int j, int l, int i) {
+  b.lo[0] = min(b.lo[0], j);
+  b.lo[1] = min(b.lo[1], l);
+  b.lo[2] = min(b.lo[2], i);
+  b.hi[0] = max(b.hi[0], j);
+  b.hi[1] = max(b.hi[1], l);
+  b.hi[2] = max(b.hi[2], i);
+}
+
+struct TileBox {
+  int j0, l0, i0;      // lowest node
+  int nl, ni, nodes;   // node extents (nodes = 0 unless fits)
+  bool fits;
+};
+
+// red: LDS scratch of 6 ints per wavefront of the block
+template <int NZ>
+__device__ __forceinline__ TileBox box_reduce(BoxAcc b, int* red, int cap) {
+  for (int off = 32; off >= 1; off >>= 1)
+    for (int d = 0; d < 3; ++d) {
+      b.lo[d] = min(b.lo[d], __shfl_xor(b.lo[d], off));
+      b.hi[d] = max(b.hi[d], __shfl_xor(b.hi[d], off));
+    }
+  const int wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int d = 0; d < 3; ++d) {
+      red[wave * 6 + d] = b.lo[d];
+      red[wave * 6 + 3 + d] = b.hi[d];
+    }
+  __syncthreads();
+  BoxAcc t;
+  box_init(t);
+  for (int w = 0; w < nw; ++w)
+    for (int d = 0; d < 3; ++d) {
+      t.lo[d] = min(t.lo[d], red[w * 6 + d]);
+      t.hi[d] = max(t.hi[d], red[w * 6 + 3 + d]);
+    }
+  TileBox x;
+  const bool any = t.hi[2] >= t.lo[2];
+  x.j0 = t.lo[0];
+  x.l0 = t.lo[1];
+  x.i0 = t.lo[2];
+  const long long nj = any ? (long long)t.hi[0] - t.lo[0] + NZ : 0;
+  x.nl = any ? t.hi[1] - t.lo[1] + 2 : 0;
+  x.ni = any ? t.hi[2] - t.lo[2] + 2 : 0;
+  const long long nodes = nj * x.nl * x.ni;
+  x.fits = any && nodes <= cap;
+  x.nodes = x.fits ? (int)nodes : 0;
+  return x;
+}
+
+template <typename R>
+__device__ __forceinline__ void tile_zero(R* tile, const TileBox& b, int nch) {
+  for (int t = threadIdx.x; t < nch * b.nodes; t += blockDim.x) tile[t] = R(0);
+  __syncthreads();
+}
+
+// q times the linear shape at c into channel ch (transverse grid glob when
+// the box did not fit)
+template <typename R>
+__device__ __forceinline__ void tile_add(R* tile, const TileBox& b, int ch, const Cic<R>& c, double q, R* glob) {
+  if (q == 0.0) return;
+  if (!b.fits) {
+    cic_add(glob, c, q);
+    return;
+  }
+  R* t = tile + ch * b.nodes + (c.l0 - b.l0) * b.ni + (c.i0 - b.i0);
+  atomicAdd(t, (R)(q * (1 - c.fx) * (1 - c.fy)));
+  atomicAdd(t + 1, (R)(q * c.fx * (1 - c.fy)));
+  atomicAdd(t + b.ni, (R)(q * (1 - c.fx) * c.fy));
+  atomicAdd(t + b.ni + 1, (R)(q * c.fx * c.fy));
+}
+
+// the touched tile nodes into the grids dst[ch] ([nz][ny][nx], nz = 1 for
+// a transverse grid); node slices outside [0, nz) are dropped
+template <typename R, int NCH>
+__device__ __forceinline__ void tile_flush(const Geo<R>& g, const R* tile, const TileBox& b, R* const* dst, int nz) {
+  __syncthreads();
+  const int nli = b.nl * b.ni;
+  for (int t = threadIdx.x; t < b.nodes; t += blockDim.x) {
+    const int jj = t / nli, r = t - jj * nli;
+    const int ll = r / b.ni, ii = r - ll * b.ni;
+    const int j = b.j0 + jj;
+    if (j < 0 || j >= nz) continue;
+    int l = b.l0 + ll;
+    l -= (l >= g.ny) ? g.ny : 0;
+    int i = b.i0 + ii;
+    i -= (i >= g.nx) ? g.nx : 0;
+    const int64_t off = (int64_t)j * g.nperp + (int64_t)l * g.nx + i;
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const R v = tile[ch * b.nodes + t];
+      if (v != R(0)) atomic_add(dst[ch] + off, v);
+    }
+  }
 }
 
 // The six fields a plasma particle sees, F = (psi, dxpsi, dypsi, Bx, By, Bz),
@@ -343,25 +469,13 @@ __device__ __forceinline__ void six_val(const Geo<R>& g, const Six<R>& F, bool h
   }
 }
 
-// Grid adjoints of the six fields: gbar deposited into Fa_bar (x 1.5 when
-// half) and Fm1_bar (x -0.5 when half).
+// Grid adjoints of the six fields: at slice j (a) and j - 1 (m1, the
+// extrapolation (3 Fa - Fm1)/2 reads it).
 template <typename R>
 struct SixBar {
   R* a[6];
   R* m1[6];
 };
-
-template <typename R>
-__device__ __forceinline__ void six_add(const SixBar<R>& B, bool half, const Cic<R>& c, const double (&gb)[6]) {
-  for (int m = 0; m < 6; ++m) {
-    if (half) {
-      cic_add(B.a[m], c, 1.5 * gb[m]);
-      cic_add(B.m1[m], c, -0.5 * gb[m]);
-    } else {
-      cic_add(B.a[m], c, gb[m]);
-    }
-  }
-}
 
 // d(x, y, ux, uy)/dxi from the gathered six fields
 __device__ __forceinline__ void rhs_val(const double (&v)[6], double ux, double uy, double (&f)[4]) {
@@ -410,45 +524,61 @@ __device__ __forceinline__ void rk2_val(const Geo<R>& g, const Six<R>& F, double
   for (int c = 0; c < 4; ++c) Yn[c] = Y[c] + h * f[c];
 }
 
-// Transpose of rk2_val: Yb (adjoint of Y') -> adds to the adjoint of Y and
-// deposits the field adjoints.
+// Transpose of rk2_val: Yb (adjoint of Y') adds to the adjoint of Y; the
+// adjoints of the six values gathered at stage 1 (at Y, fields of slice j)
+// and stage 2 (at Ys, extrapolated fields) with their stencils go to o.
 template <typename R>
-__device__ __forceinline__ void rk2_adj(const Geo<R>& g, const Six<R>& F, const SixBar<R>& Fb, double h,
-                                        const double (&Y)[4], const double (&Ynb)[4], double (&Yb)[4]) {
+struct Rk2Bar {
+  Cic<R> c0, c1;
+  double g0[6], g1[6];
+};
+
+template <typename R>
+__device__ __forceinline__ void rk2_adj(const Geo<R>& g, const Six<R>& F, double h, const double (&Y)[4],
+                                        const double (&Ynb)[4], double (&Yb)[4], Rk2Bar<R>& o) {
   double v[6], vx[6], vy[6], f[4], Ys[4];
-  const Cic<R> c0 = cic(g, (R)Y[0], (R)Y[1]);
-  six_val(g, F, false, c0, v, vx, vy);
+  o.c0 = cic(g, (R)Y[0], (R)Y[1]);
+  six_val(g, F, false, o.c0, v, vx, vy);
   rhs_val(v, Y[2], Y[3], f);
   for (int c = 0; c < 4; ++c) Ys[c] = Y[c] + 0.5 * h * f[c];
   // stage 2 at Ys with Fh
   double v2[6], vx2[6], vy2[6];
-  const Cic<R> c1 = cic(g, (R)Ys[0], (R)Ys[1]);
-  six_val(g, F, true, c1, v2, vx2, vy2);
-  double fb[4], gb[6], uxb, uyb;
+  o.c1 = cic(g, (R)Ys[0], (R)Ys[1]);
+  six_val(g, F, true, o.c1, v2, vx2, vy2);
+  double fb[4], uxb, uyb;
   for (int c = 0; c < 4; ++c) {
     Yb[c] += Ynb[c];
     fb[c] = h * Ynb[c];
   }
-  rhs_adj(v2, Ys[2], Ys[3], fb, gb, uxb, uyb);
+  rhs_adj(v2, Ys[2], Ys[3], fb, o.g1, uxb, uyb);
   double Ysb[4] = {0, 0, uxb, uyb};
   for (int m = 0; m < 6; ++m) {
-    Ysb[0] += gb[m] * vx2[m];
-    Ysb[1] += gb[m] * vy2[m];
+    Ysb[0] += o.g1[m] * vx2[m];
+    Ysb[1] += o.g1[m] * vy2[m];
   }
-  six_add(Fb, true, c1, gb);
   // stage 1 at Y with Fj
   for (int c = 0; c < 4; ++c) {
     Yb[c] += Ysb[c];
     fb[c] = 0.5 * h * Ysb[c];
   }
-  rhs_adj(v, Y[2], Y[3], fb, gb, uxb, uyb);
+  rhs_adj(v, Y[2], Y[3], fb, o.g0, uxb, uyb);
   Yb[2] += uxb;
   Yb[3] += uyb;
   for (int m = 0; m < 6; ++m) {
-    Yb[0] += gb[m] * vx[m];
-    Yb[1] += gb[m] * vy[m];
+    Yb[0] += o.g0[m] * vx[m];
+    Yb[1] += o.g0[m] * vy[m];
   }
-  six_add(Fb, false, c0, gb);
+}
+
+// channels 0..5: fields of slice j (stage 1, and 3/2 of stage 2); 6..11:
+// fields of slice j - 1 (-1/2 of stage 2)
+template <typename R>
+__device__ __forceinline__ void rk2_bar_add(R* tile, const TileBox& b, const Rk2Bar<R>& o, const SixBar<R>& Fb) {
+  for (int m = 0; m < 6; ++m) {
+    tile_add(tile, b, m, o.c0, o.g0[m], Fb.a[m]);
+    tile_add(tile, b, m, o.c1, 1.5 * o.g1[m], Fb.a[m]);
+    tile_add(tile, b, 6 + m, o.c1, -0.5 * o.g1[m], Fb.m1[m]);
+  }
 }
 
 template <typename R>
@@ -473,51 +603,93 @@ struct AdjPlasma {
   int* err;
 };
 
+#define ADJ_TILE(NCH)                                         \
+  constexpr int NCH_ = (NCH);                                 \
+  constexpr int CAP_ = AdjTile<R, NCH_>::CAP;                 \
+  __shared__ R tile[NCH_ * CAP_];                             \
+  __shared__ int red[6 * 16];                                 \
+  BoxAcc bx;                                                  \
+  box_init(bx)
+
 // S += -w W/(dx dy)
 template <typename R>
 __global__ void __launch_bounds__(256) k_af_dep_s(AdjPlasma<R> a, R* __restrict__ S) {
+  ADJ_TILE(1);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.np) return;
-  cic_add(S, cic(a.g, a.Y[0][p], a.Y[1][p]), a.nw);
+  const bool live = p < a.np;
+  Cic<R> c{};
+  if (live) {
+    c = cic(a.g, a.Y[0][p], a.Y[1][p]);
+    box_add(bx, 0, c.l0, c.i0);
+  }
+  const TileBox b = box_reduce<1>(bx, red, CAP_);
+  tile_zero(tile, b, NCH_);
+  if (live) tile_add(tile, b, 0, c, a.nw, S);
+  R* const dst[1] = {S};
+  tile_flush<R, 1>(a.g, tile, b, dst, 1);
 }
 
 // J stage: G = 1 + psi(Y); J += -w u/G W/(dx dy)
 template <typename R>
 __global__ void __launch_bounds__(256) k_af_dep_j(AdjPlasma<R> a) {
+  ADJ_TILE(3);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.np) return;
-  const Cic<R> c = cic(a.g, a.Y[0][p], a.Y[1][p]);
-  double ps, px, py;
-  cic_val(a.g, a.psi, c, ps, px, py);
-  const double G = 1.0 + ps;
-  if (!(G > QSA_GMIN)) atomicOr(a.err, ERR_BREAKDOWN);
-  const double ux = a.Y[2][p], uy = a.Y[3][p];
-  const double gam = (1.0 + ux * ux + uy * uy + G * G) / (2.0 * G);
-  cic_add(a.Jx, c, a.nw * ux / G);
-  cic_add(a.Jy, c, a.nw * uy / G);
-  cic_add(a.Jz, c, a.nw * (gam - G) / G);
+  const bool live = p < a.np;
+  Cic<R> c{};
+  double q[3] = {0, 0, 0};
+  if (live) {
+    c = cic(a.g, a.Y[0][p], a.Y[1][p]);
+    box_add(bx, 0, c.l0, c.i0);
+    double ps, px, py;
+    cic_val(a.g, a.psi, c, ps, px, py);
+    const double G = 1.0 + ps;
+    if (!(G > QSA_GMIN)) atomicOr(a.err, ERR_BREAKDOWN);
+    const double ux = a.Y[2][p], uy = a.Y[3][p];
+    const double gam = (1.0 + ux * ux + uy * uy + G * G) / (2.0 * G);
+    q[0] = a.nw * ux / G;
+    q[1] = a.nw * uy / G;
+    q[2] = a.nw * (gam - G) / G;
+  }
+  const TileBox b = box_reduce<1>(bx, red, CAP_);
+  tile_zero(tile, b, NCH_);
+  R* const dst[3] = {a.Jx, a.Jy, a.Jz};
+  if (live)
+    for (int k = 0; k < 3; ++k) tile_add(tile, b, k, c, q[k], dst[k]);
+  tile_flush<R, 3>(a.g, tile, b, dst, 1);
 }
 
 // Predictor: Yt = RK2(Y; F), stored; Jt_perp += -w ut/Gt with Gt = 1 + psit(Yt)
 template <typename R>
 __global__ void __launch_bounds__(256) k_af_pred(AdjPlasma<R> a, R* __restrict__ Yt0, R* __restrict__ Yt1,
                                                  R* __restrict__ Yt2, R* __restrict__ Yt3) {
+  ADJ_TILE(2);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.np) return;
-  const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
-  double Ys[4], Yt[4];
-  rk2_val(a.g, a.F, a.h, Y, Ys, Yt);
-  Yt0[p] = (R)Yt[0];
-  Yt1[p] = (R)Yt[1];
-  Yt2[p] = (R)Yt[2];
-  Yt3[p] = (R)Yt[3];
-  const Cic<R> c = cic(a.g, (R)Yt[0], (R)Yt[1]);
-  double ps, px, py;
-  cic_val(a.g, a.psi, c, ps, px, py);
-  const double G = 1.0 + ps;
-  if (!(G > QSA_GMIN)) atomicOr(a.err, ERR_BREAKDOWN);
-  cic_add(a.Jx, c, a.nw * Yt[2] / G);
-  cic_add(a.Jy, c, a.nw * Yt[3] / G);
+  const bool live = p < a.np;
+  Cic<R> c{};
+  double q[2] = {0, 0};
+  if (live) {
+    const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
+    double Ys[4], Yt[4];
+    rk2_val(a.g, a.F, a.h, Y, Ys, Yt);
+    Yt0[p] = (R)Yt[0];
+    Yt1[p] = (R)Yt[1];
+    Yt2[p] = (R)Yt[2];
+    Yt3[p] = (R)Yt[3];
+    c = cic(a.g, (R)Yt[0], (R)Yt[1]);
+    box_add(bx, 0, c.l0, c.i0);
+    double ps, px, py;
+    cic_val(a.g, a.psi, c, ps, px, py);
+    const double G = 1.0 + ps;
+    if (!(G > QSA_GMIN)) atomicOr(a.err, ERR_BREAKDOWN);
+    q[0] = a.nw * Yt[2] / G;
+    q[1] = a.nw * Yt[3] / G;
+  }
+  const TileBox b = box_reduce<1>(bx, red, CAP_);
+  tile_zero(tile, b, NCH_);
+  R* const dst[2] = {a.Jx, a.Jy};
+  if (live)
+    for (int k = 0; k < 2; ++k) tile_add(tile, b, k, c, q[k], dst[k]);
+  tile_flush<R, 2>(a.g, tile, b, dst, 1);
 }
 
 // Final advance: Yn = wrap(RK2(Y; F))
@@ -534,51 +706,89 @@ __global__ void __launch_bounds__(256) k_af_final(AdjPlasma<R> a) {
   a.Yn[3][p] = (R)Yn[3];
 }
 
+template <typename R>
+__device__ __forceinline__ void six_bar_dst(const SixBar<R>& Fb, R** dst) {
+  for (int m = 0; m < 6; ++m) {
+    dst[m] = Fb.a[m];
+    dst[6 + m] = Fb.m1[m];
+  }
+}
+
 // Reverse of the final advance: Yn (adjoint of Y) = RK2^T(Ynb); fields.
 template <typename R>
 __global__ void __launch_bounds__(256) k_ar_final(AdjPlasma<R> a) {
+  ADJ_TILE(12);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.np) return;
-  const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
-  const double Ynb[4] = {a.Ynb[0][p], a.Ynb[1][p], a.Ynb[2][p], a.Ynb[3][p]};
-  double Yb[4] = {0, 0, 0, 0};
-  rk2_adj(a.g, a.F, a.Fb, a.h, Y, Ynb, Yb);
-  for (int c = 0; c < 4; ++c) a.Yn[c][p] = (R)Yb[c];
+  const bool live = p < a.np;
+  Rk2Bar<R> o;
+  if (live) {
+    const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
+    const double Ynb[4] = {a.Ynb[0][p], a.Ynb[1][p], a.Ynb[2][p], a.Ynb[3][p]};
+    double Yb[4] = {0, 0, 0, 0};
+    rk2_adj(a.g, a.F, a.h, Y, Ynb, Yb, o);
+    for (int c = 0; c < 4; ++c) a.Yn[c][p] = (R)Yb[c];
+    box_add(bx, 0, o.c0.l0, o.c0.i0);
+    box_add(bx, 0, o.c1.l0, o.c1.i0);
+  }
+  const TileBox b = box_reduce<1>(bx, red, CAP_);
+  tile_zero(tile, b, NCH_);
+  if (live) rk2_bar_add(tile, b, o, a.Fb);
+  R* dst[12];
+  six_bar_dst(a.Fb, dst);
+  tile_flush<R, 12>(a.g, tile, b, dst, 1);
 }
 
 // Reverse of predictor iteration: the adjoint of Jt_perp (jscale * (Jx, Jy))
 // -> adjoint of Yt and of psit -> RK2^T into the adjoint of Y (added).
 template <typename R>
 __global__ void __launch_bounds__(256) k_ar_pred(AdjPlasma<R> a) {
+  ADJ_TILE(13);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.np) return;
+  const bool live = p < a.np;
   const Geo<R>& g = a.g;
-  const double Yt[4] = {a.Yt[0][p], a.Yt[1][p], a.Yt[2][p], a.Yt[3][p]};
-  const Cic<R> c = cic(g, (R)Yt[0], (R)Yt[1]);
-  double ps, psx, psy;
-  cic_val(g, a.psi, c, ps, psx, psy);
-  const double G = 1.0 + ps;
-  double jx, jxx, jxy, jy, jyx, jyy;
-  cic_val(g, a.Jx, c, jx, jxx, jxy);
-  cic_val(g, a.Jy, c, jy, jyx, jyy);
-  // nw (hence q) already holds the 1/(dx dy) of the deposit
-  const double s = a.jscale;
-  const double qx = a.nw * Yt[2] / G, qy = a.nw * Yt[3] / G;
-  // q_bar (deposit transpose) and position terms of the deposit
-  const double qxb = s * jx, qyb = s * jy;
-  double Ytb[4];
-  Ytb[0] = s * (qx * jxx + qy * jyx);
-  Ytb[1] = s * (qx * jxy + qy * jyy);
-  Ytb[2] = qxb * a.nw / G;
-  Ytb[3] = qyb * a.nw / G;
-  const double Gb = -(qxb * qx + qyb * qy) / G;
-  Ytb[0] += Gb * psx;
-  Ytb[1] += Gb * psy;
-  cic_add(a.psib, c, Gb);
-  const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
-  double Yb[4] = {a.Yn[0][p], a.Yn[1][p], a.Yn[2][p], a.Yn[3][p]};
-  rk2_adj(g, a.F, a.Fb, a.h, Y, Ytb, Yb);
-  for (int k = 0; k < 4; ++k) a.Yn[k][p] = (R)Yb[k];
+  Rk2Bar<R> o;
+  Cic<R> c{};
+  double Gb = 0.0;
+  if (live) {
+    const double Yt[4] = {a.Yt[0][p], a.Yt[1][p], a.Yt[2][p], a.Yt[3][p]};
+    c = cic(g, (R)Yt[0], (R)Yt[1]);
+    double ps, psx, psy;
+    cic_val(g, a.psi, c, ps, psx, psy);
+    const double G = 1.0 + ps;
+    double jx, jxx, jxy, jy, jyx, jyy;
+    cic_val(g, a.Jx, c, jx, jxx, jxy);
+    cic_val(g, a.Jy, c, jy, jyx, jyy);
+    // nw (hence q) already holds the 1/(dx dy) of the deposit
+    const double s = a.jscale;
+    const double qx = a.nw * Yt[2] / G, qy = a.nw * Yt[3] / G;
+    // q_bar (deposit transpose) and position terms of the deposit
+    const double qxb = s * jx, qyb = s * jy;
+    double Ytb[4];
+    Ytb[0] = s * (qx * jxx + qy * jyx);
+    Ytb[1] = s * (qx * jxy + qy * jyy);
+    Ytb[2] = qxb * a.nw / G;
+    Ytb[3] = qyb * a.nw / G;
+    Gb = -(qxb * qx + qyb * qy) / G;
+    Ytb[0] += Gb * psx;
+    Ytb[1] += Gb * psy;
+    const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
+    double Yb[4] = {a.Yn[0][p], a.Yn[1][p], a.Yn[2][p], a.Yn[3][p]};
+    rk2_adj(g, a.F, a.h, Y, Ytb, Yb, o);
+    for (int k = 0; k < 4; ++k) a.Yn[k][p] = (R)Yb[k];
+    box_add(bx, 0, c.l0, c.i0);
+    box_add(bx, 0, o.c0.l0, o.c0.i0);
+    box_add(bx, 0, o.c1.l0, o.c1.i0);
+  }
+  const TileBox b = box_reduce<1>(bx, red, CAP_);
+  tile_zero(tile, b, NCH_);
+  if (live) {
+    rk2_bar_add(tile, b, o, a.Fb);
+    tile_add(tile, b, 12, c, Gb, a.psib);
+  }
+  R* dst[13];
+  six_bar_dst(a.Fb, dst);
+  dst[12] = a.psib;
+  tile_flush<R, 13>(g, tile, b, dst, 1);
 }
 
 // Reverse of the J stage (deposits of -w u/G with G = 1 + psi(Y); when Jx is
@@ -587,43 +797,54 @@ __global__ void __launch_bounds__(256) k_ar_pred(AdjPlasma<R> a) {
 // launches: the adjoint of S needs the psi adjoint the J stage completes.
 template <typename R>
 __global__ void __launch_bounds__(256) k_ar_jstage(AdjPlasma<R> a) {
+  ADJ_TILE(1);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.np) return;
+  const bool live = p < a.np;
   const Geo<R>& g = a.g;
-  const Cic<R> c = cic(g, a.Y[0][p], a.Y[1][p]);
-  double xb = 0.0, yb = 0.0, uxb = 0.0, uyb = 0.0;   // nw holds the 1/(dx dy) of the deposits
-  if (a.Jx) {
-    const double ux = a.Y[2][p], uy = a.Y[3][p];
-    double ps, psx, psy;
-    cic_val(g, a.psi, c, ps, psx, psy);
-    const double G = 1.0 + ps;
-    const double u2 = ux * ux + uy * uy;
-    double jx, jxx, jxy, jy, jyx, jyy, jz, jzx, jzy;
-    cic_val(g, a.Jx, c, jx, jxx, jxy);
-    cic_val(g, a.Jy, c, jy, jyx, jyy);
-    cic_val(g, a.Jz, c, jz, jzx, jzy);
-    const double qx = a.nw * ux / G, qy = a.nw * uy / G;
-    const double qz = a.nw * ((1.0 + u2 + G * G) / (2.0 * G * G) - 1.0);
-    const double qxb = jx, qyb = jy, qzb = jz;
-    xb = qx * jxx + qy * jyx + qz * jzx;
-    yb = qx * jxy + qy * jyy + qz * jzy;
-    uxb = a.nw * (qxb / G + qzb * ux / (G * G));
-    uyb = a.nw * (qyb / G + qzb * uy / (G * G));
-    const double Gb = a.nw * (-qxb * ux / (G * G) - qyb * uy / (G * G) - qzb * (1.0 + u2) / (G * G * G));
-    xb += Gb * psx;
-    yb += Gb * psy;
-    cic_add(a.psib, c, Gb);
+  Cic<R> c{};
+  double Gb = 0.0;
+  if (live) {
+    c = cic(g, a.Y[0][p], a.Y[1][p]);
+    double xb = 0.0, yb = 0.0, uxb = 0.0, uyb = 0.0;   // nw holds the 1/(dx dy) of the deposits
+    if (a.Jx) {
+      const double ux = a.Y[2][p], uy = a.Y[3][p];
+      double ps, psx, psy;
+      cic_val(g, a.psi, c, ps, psx, psy);
+      const double G = 1.0 + ps;
+      const double u2 = ux * ux + uy * uy;
+      double jx, jxx, jxy, jy, jyx, jyy, jz, jzx, jzy;
+      cic_val(g, a.Jx, c, jx, jxx, jxy);
+      cic_val(g, a.Jy, c, jy, jyx, jyy);
+      cic_val(g, a.Jz, c, jz, jzx, jzy);
+      const double qx = a.nw * ux / G, qy = a.nw * uy / G;
+      const double qz = a.nw * ((1.0 + u2 + G * G) / (2.0 * G * G) - 1.0);
+      const double qxb = jx, qyb = jy, qzb = jz;
+      xb = qx * jxx + qy * jyx + qz * jzx;
+      yb = qx * jxy + qy * jyy + qz * jzy;
+      uxb = a.nw * (qxb / G + qzb * ux / (G * G));
+      uyb = a.nw * (qyb / G + qzb * uy / (G * G));
+      Gb = a.nw * (-qxb * ux / (G * G) - qyb * uy / (G * G) - qzb * (1.0 + u2) / (G * G * G));
+      xb += Gb * psx;
+      yb += Gb * psy;
+      box_add(bx, 0, c.l0, c.i0);
+    }
+    if (a.Sb) {
+      double sv, sx, sy;
+      cic_val(g, a.Sb, c, sv, sx, sy);
+      xb += a.nw * sx;
+      yb += a.nw * sy;
+    }
+    a.Yn[0][p] = (R)((double)a.Yn[0][p] + xb);
+    a.Yn[1][p] = (R)((double)a.Yn[1][p] + yb);
+    a.Yn[2][p] = (R)((double)a.Yn[2][p] + uxb);
+    a.Yn[3][p] = (R)((double)a.Yn[3][p] + uyb);
   }
-  if (a.Sb) {
-    double sv, sx, sy;
-    cic_val(g, a.Sb, c, sv, sx, sy);
-    xb += a.nw * sx;
-    yb += a.nw * sy;
-  }
-  a.Yn[0][p] = (R)((double)a.Yn[0][p] + xb);
-  a.Yn[1][p] = (R)((double)a.Yn[1][p] + yb);
-  a.Yn[2][p] = (R)((double)a.Yn[2][p] + uxb);
-  a.Yn[3][p] = (R)((double)a.Yn[3][p] + uyb);
+  if (!a.Jx) return;   // uniform over the launch
+  const TileBox b = box_reduce<1>(bx, red, CAP_);
+  tile_zero(tile, b, NCH_);
+  if (live) tile_add(tile, b, 0, c, Gb, a.psib);
+  R* const dst[1] = {a.psib};
+  tile_flush<R, 1>(g, tile, b, dst, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -675,6 +896,26 @@ __device__ __forceinline__ void cic3_add(const Geo<R>& g, R* __restrict__ F, con
     const int jj = c.j0 + d;
     if (jj < 0 || jj >= g.nxi) continue;
     cic_add(F + (int64_t)jj * g.nperp, c.c, q * (d ? c.fz : 1.0 - c.fz));
+  }
+}
+
+// q times the 3D linear shape at c into channel ch of a tile over node
+// slices (grid glob [nxi][ny][nx] when the box did not fit)
+template <typename R>
+__device__ __forceinline__ void tile_add3(const Geo<R>& g, R* tile, const TileBox& b, int ch, const Cic3<R>& c,
+                                          double q, R* glob) {
+  if (!c.in || q == 0.0) return;
+  if (!b.fits) {
+    cic3_add(g, glob, c, q);
+    return;
+  }
+  for (int d = 0; d < 2; ++d) {
+    const double qd = q * (d ? c.fz : 1.0 - c.fz);
+    R* t = tile + ch * b.nodes + ((c.j0 + d - b.j0) * b.nl + (c.c.l0 - b.l0)) * b.ni + (c.c.i0 - b.i0);
+    atomicAdd(t, (R)(qd * (1 - c.c.fx) * (1 - c.c.fy)));
+    atomicAdd(t + 1, (R)(qd * c.c.fx * (1 - c.c.fy)));
+    atomicAdd(t + b.ni, (R)(qd * (1 - c.c.fx) * c.c.fy));
+    atomicAdd(t + b.ni + 1, (R)(qd * c.c.fx * c.c.fy));
   }
 }
 
@@ -731,14 +972,26 @@ __device__ __forceinline__ void beam_v(double ux, double uy, double uz, double (
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_ab_sources(AdjBeam<R> a) {
+  ADJ_TILE(4);
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.n || a.w[p] == R(0)) return;
-  const Cic3<R> c = cic3(a.g, a.x[p], a.y[p], a.xi[p], a.inv_dxi);
-  double v[4], dv[4][3];
-  beam_v(a.ux[p], a.uy[p], a.uz[p], v, dv);
-  const double q = a.zdv * (double)a.w[p];
+  const bool live = p < a.n && a.w[p] != R(0);
+  Cic3<R> c{};
+  double q[4] = {0, 0, 0, 0};
+  if (live) {
+    c = cic3(a.g, a.x[p], a.y[p], a.xi[p], a.inv_dxi);
+    double v[4], dv[4][3];
+    beam_v(a.ux[p], a.uy[p], a.uz[p], v, dv);
+    const double qw = a.zdv * (double)a.w[p];
+    for (int k = 0; k < 4; ++k) q[k] = qw * v[k];
+    if (c.in) box_add(bx, c.j0, c.c.l0, c.c.i0);
+  }
+  const TileBox b = box_reduce<2>(bx, red, CAP_);
+  tile_zero(tile, b, NCH_);
   const int64_t plane = (int64_t)a.g.nxi * a.g.nperp;
-  for (int k = 0; k < 4; ++k) cic3_add(a.g, a.src + k * plane, c, q * v[k]);
+  R* const dst[4] = {a.src, a.src + plane, a.src + 2 * plane, a.src + 3 * plane};
+  if (live)
+    for (int k = 0; k < 4; ++k) tile_add3(a.g, tile, b, k, c, q[k], dst[k]);
+  tile_flush<R, 4>(a.g, tile, b, dst, a.g.nxi);
 }
 
 // Transpose of the sources: adds to the adjoints of position, momentum and
@@ -823,10 +1076,35 @@ __global__ void __launch_bounds__(256) k_ab_push(AdjBeam<R> a) {
 // Transpose of the push: b (adjoints at step n + 1) -> adjoints at step n
 // (in place), field adjoints deposited.
 template <typename R>
+__device__ __forceinline__ void push_adj_one(const AdjBeam<R>& a, int64_t p, const Cic3<R>& c, double (&gb)[6]);
+
+template <typename R>
 __global__ void __launch_bounds__(256) k_ab_push_adj(AdjBeam<R> a) {
+  ADJ_TILE(6);
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.n) return;
-  const Cic3<R> c = cic3(a.g, a.x[p], a.y[p], a.xi[p], a.inv_dxi);
+  const bool live = p < a.n;
+  Cic3<R> c{};
+  double gb[6] = {0, 0, 0, 0, 0, 0};
+  if (live) {
+    c = cic3(a.g, a.x[p], a.y[p], a.xi[p], a.inv_dxi);
+    push_adj_one(a, p, c, gb);
+    if (c.in) box_add(bx, c.j0, c.c.l0, c.c.i0);
+  }
+  const TileBox b = box_reduce<2>(bx, red, CAP_);
+  tile_zero(tile, b, NCH_);
+  const int slot[6] = {F_DXPSI, F_DYPSI, F_EZ, F_BX, F_BY, F_BZ};
+  const int64_t plane = (int64_t)a.g.nxi * a.g.nperp;
+  R* dst[6];
+  for (int m = 0; m < 6; ++m) dst[m] = a.fieldsb + slot[m] * plane;
+  if (live)
+    for (int m = 0; m < 6; ++m) tile_add3(a.g, tile, b, m, c, gb[m], dst[m]);
+  tile_flush<R, 6>(a.g, tile, b, dst, a.g.nxi);
+}
+
+// One particle of the push transpose: its adjoints at step n + 1 -> step n
+// (in place); gb: the adjoints of the six gathered field values.
+template <typename R>
+__device__ __forceinline__ void push_adj_one(const AdjBeam<R>& a, int64_t p, const Cic3<R>& c, double (&gb)[6]) {
   double f[6], fg[6][3];
   boris_fields(a, c, f, fg);
   const double qh = a.qh, dt = a.dt;
@@ -898,13 +1176,15 @@ __global__ void __launch_bounds__(256) k_ab_push_adj(AdjBeam<R> a) {
   // um = u + qh E
   for (int d = 0; d < 3; ++d) Eb[d] += qh * umb[d];
   // field values: (dxpsi, dypsi, Ez, Bx, By, Bz)
-  const double gb[6] = {-Eb[0], -Eb[1], Eb[2], -Eb[1] + Bb[0], Eb[0] + Bb[1], Bb[2]};
+  gb[0] = -Eb[0];
+  gb[1] = -Eb[1];
+  gb[2] = Eb[2];
+  gb[3] = -Eb[1] + Bb[0];
+  gb[4] = Eb[0] + Bb[1];
+  gb[5] = Bb[2];
   double pos[3] = {xb, yb, xib};
   for (int m = 0; m < 6; ++m)
     for (int d = 0; d < 3; ++d) pos[d] += gb[m] * fg[m][d];
-  const int slot[6] = {F_DXPSI, F_DYPSI, F_EZ, F_BX, F_BY, F_BZ};
-  const int64_t plane = (int64_t)a.g.nxi * a.g.nperp;
-  for (int m = 0; m < 6; ++m) cic3_add(a.g, a.fieldsb + slot[m] * plane, c, gb[m]);
   a.b[0][p] = (R)pos[0];
   a.b[1][p] = (R)pos[1];
   a.b[2][p] = (R)pos[2];
