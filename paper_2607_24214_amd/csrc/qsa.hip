@@ -35,28 +35,32 @@ int ilog2(int v) {
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Grid scratch indices (each [ny][nx]).
+// Adjoint grid scratch indices (each [ny][nx]).
 enum {
-  AG_S = 0, AG_JX, AG_JY, AG_JZ, AG_JTX, AG_JTY, AG_DX, AG_DY, AG_PSIT, AG_ZERO, AG_JM1X, AG_JM1Y,
-  AG_BAX, AG_BAY, AG_BBX, AG_BBY,
-  AA_PSI, AA_DXPSI, AA_DYPSI, AA_BZ, AA_BKX, AA_BKY, AA_BNX, AA_BNY, AA_JX, AA_JY, AA_JZ, AA_PSIT, AA_S,
-  AA_DBX, AA_DBY,
-  AH0 = 32,            // hist adjoint set 0: fm1[6], psim2, bm2[2], jm1[2]
-  AH1 = AH0 + 11,      // set 1
-  AG_DUMMY = AH1 + 11,
-  AG_COUNT = 64
+  AG_S = 0,              // forward: rho - J_z of the slice
+  AG_JF0,                // forward J (x, y, z) of slice j: AG_JF0 + 3 (j & 1) + c
+  AG_JT = AG_JF0 + 6,    // predictor J_perp (x, y)
+  AG_PSIT = AG_JT + 2,   // psi extrapolated to j + 1
+  AG_ZERO,               // zeros (fields before slice 0)
+  AG_SINK,               // 7 write-only grids: adjoints of fields before slice 0
+  AA_JZ = AG_SINK + 7,   // reverse: J_z adjoint of the slice
+  AA_PSIT,               // adjoint of the extrapolated psi
+  AA_JB0,                // J_perp adjoint (x, y) of slice j: AA_JB0 + 2 (j & 1) + c
+  AA_DB = AA_JB0 + 4,    // adjoint of the predictor's current difference (x, y)
+  AA_BP0 = AA_DB + 2,    // two pairs of B_perp iterate adjoints (x, y)
+  AA_S = AA_BP0 + 4,     // adjoint of rho - J_z
+  AG_COUNT
 };
-enum { AH_FM1 = 0, AH_PSIM2 = 6, AH_BM2 = 7, AH_JM1 = 9 };
 
 struct AdjLayout {
   int steps = 0, nseg = 0, ck_len = 0;
   size_t state[QSA_MAX_SPECIES] = {};   // per species: bytes of one beam state in the tape
   size_t beam[QSA_MAX_SPECIES] = {};    // tape base per species
   size_t bin[QSA_MAX_SPECIES] = {}, w0[QSA_MAX_SPECIES] = {}, bb[QSA_MAX_SPECIES][7] = {};
-  size_t fields = 0, src = 0, srcb = 0, fb = 0;
+  size_t fields = 0, biter = 0, src = 0, srcb = 0, fb = 0;
   size_t ck = 0, ck_bytes = 0;
-  size_t segY = 0, segYt = 0, segB = 0, ytmp = 0, Y[2] = {}, Yb[2] = {};
-  size_t grids = 0, work = 0, sc = 0, grad = 0, amps = 0;
+  size_t segY = 0, segYt = 0, Y[2] = {}, Yb[2] = {};
+  size_t grids = 0, work = 0, sc = 0, sums = 0, grad = 0, amps = 0;
 };
 
 
@@ -85,15 +89,14 @@ void adjoint_layout(const qsa_params& p, size_t& off, AdjLayout& A) {
     for (int k = 0; k < 7; ++k) A.bb[s][k] = take(cap * rs);
   }
   A.fields = take((size_t)(A.steps + 1) * N_STORED * plane * rs);
+  A.biter = take((size_t)(A.steps + 1) * std::max(K, 1) * 2 * plane * rs);
   A.src = take(4 * plane * rs);
   A.srcb = take(4 * plane * rs);
   A.fb = take(N_STORED * plane * rs);
-  A.ck_bytes = align_up(4 * np * rs) + align_up(2 * nperp * rs) + align_up(2 * sizeof(double));
+  A.ck_bytes = align_up(4 * np * rs);
   A.ck = take((size_t)(A.steps + 1) * A.nseg * A.ck_bytes);
   A.segY = take((size_t)A.ck_len * 4 * np * rs);
   A.segYt = take((size_t)A.ck_len * std::max(K, 1) * 4 * np * rs);
-  A.segB = take((size_t)A.ck_len * std::max(K, 1) * 2 * nperp * rs);
-  A.ytmp = take(4 * np * rs);
   for (int i = 0; i < 2; ++i) {
     A.Y[i] = take(4 * np * rs);
     A.Yb[i] = take(4 * np * rs);
@@ -101,6 +104,7 @@ void adjoint_layout(const qsa_params& p, size_t& off, AdjLayout& A) {
   A.grids = take((size_t)AG_COUNT * nperp * rs);
   A.work = take((size_t)SPEC_IN * nperp * 2 * rs);
   A.sc = take(64 * sizeof(double));
+  A.sums = take(2 * (size_t)p.nxi * sizeof(double));
   A.grad = take(4096 * sizeof(double));
   A.amps = take(4096 * sizeof(double));
 }

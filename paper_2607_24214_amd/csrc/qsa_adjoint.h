@@ -30,10 +30,143 @@ namespace qsa {
 #define QSA_ADJ_CKPT 16   // plasma checkpoint stride in slices
 
 // ---------------------------------------------------------------------------
+// Grid helpers: linear combinations, per-launch side jobs, scalar jobs.
+// ---------------------------------------------------------------------------
+// out[k] = (out[k] when add) + c0 + spc * (*sp) + sum_t c_t in_t[k]
+template <typename R>
+struct Lin {
+  R* out;
+  int add;
+  int nt;
+  double c0;
+  const double* sp;   // optional device scalar
+  double spc;
+  const R* in[3];
+  double c[3];
+};
+
+template <typename R>
+__device__ __forceinline__ void lin_range(const Lin<R>& a, int64_t i0, int64_t n, int64_t step) {
+  const double base = a.c0 + (a.sp ? a.spc * *a.sp : 0.0);
+  for (int64_t i = i0; i < n; i += step) {
+    double s = (a.add ? (double)a.out[i] : 0.0) + base;
+    for (int t = 0; t < a.nt; ++t) s += a.c[t] * (double)a.in[t][i];
+    a.out[i] = (R)s;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_lin(Lin<R> a, int64_t n) {
+  lin_range(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n, (int64_t)gridDim.x * blockDim.x);
+}
+
+// Scalar jobs (thread 0 of a launch), for the transverse-mean leapfrog:
+//  SJ_SET:      *a = b ? *b : v0
+//  SJ_ODE_FWD:  slice slot a = [e, p, s, ez0] (e = <E_z>_{j-1/2}, p = psi0_j,
+//               s = sum J_z): e' = e - h s/N, ez0 = (e + e')/2, and the next
+//               slot b = [e', p + h e'];  v0 = h, v1 = N
+//  SJ_ODE_ADJ:  a = [e_bar', p_bar'] of slice j + 1, b = slot of slice j,
+//               c = sum of the E_z adjoint over the slice (ez0_bar):
+//               b = [e_bar, p_bar (before its psi-mean term), uniform J_z
+//               adjoint per node]
+enum { SJ_NONE = 0, SJ_SET, SJ_ODE_FWD, SJ_ODE_ADJ };
+struct ScalarJob {
+  int kind;
+  double* a;
+  double* b;
+  const double* c;
+  double v0, v1;
+};
+
+__device__ __forceinline__ void run_scalar(const ScalarJob& j) {
+  switch (j.kind) {
+    case SJ_SET: *j.a = j.c ? *j.c : j.v0; break;
+    case SJ_ODE_FWD: {
+      const double e = j.a[0], p = j.a[1], s = j.a[2];
+      const double en = e - j.v0 * s / j.v1;
+      j.a[3] = 0.5 * (e + en);
+      j.b[0] = en;
+      j.b[1] = p + j.v0 * en;
+      break;
+    }
+    case SJ_ODE_ADJ: {
+      const double ez = *j.c;
+      const double en = j.a[0] + 0.5 * ez + j.v0 * j.a[1];
+      j.b[0] = en + 0.5 * ez;
+      j.b[1] = j.a[1];
+      j.b[2] = -j.v0 * en / j.v1;
+      break;
+    }
+    default: break;
+  }
+}
+
+// Work a launch does besides its own: up to SIDE_LIN grid combinations of
+// len nodes and two scalar jobs, none of which may touch what the launch's
+// main work reads or writes (they run concurrently with it).
+constexpr int SIDE_LIN = 6;
+template <typename R>
+struct Side {
+  int nl, ns;
+  int64_t len;
+  Lin<R> op[SIDE_LIN];
+  ScalarJob sj[2];
+};
+
+template <typename R>
+__device__ __forceinline__ void run_side(const Side<R>& s) {
+  const int64_t tid = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+  if (tid == 0)
+    for (int q = 0; q < s.ns; ++q) run_scalar(s.sj[q]);
+  for (int q = 0; q < s.nl; ++q) lin_range(s.op[q], tid, s.len, nth);
+}
+
+// out[j] = sum over the nodes of slice j of src ([nz][nperp]); one block per slice
+template <typename R>
+__global__ void __launch_bounds__(256) k_slice_sums(const R* __restrict__ src, int nperp, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nperp; i += blockDim.x) s += (double)src[(int64_t)j * nperp + i];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    out[j] = t;
+  }
+}
+
+// dst += c * sum(src^2) (the energy).
+template <typename R>
+__global__ void __launch_bounds__(256) k_sumsq(const R* __restrict__ src, int64_t n, double c,
+                                               double* __restrict__ dst) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = (double)src[i];
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(dst, c * red[0]);
+}
+
+// ---------------------------------------------------------------------------
 // Batched spectral operators on real [ny][nx] fields:
-//   out_o = Re IFFT( sum_t c_t M_t(k) FFT(in_{i_t}) ),  k = 0 optionally set.
-// Three launches: forward row transforms, column transforms with the
-// multipliers, inverse row transforms.  Full complex transforms (no packing).
+//   r_o = Re IFFT( sum_t c_t M_t(k) FFT(in_{i_t}) ),  k = 0 optionally set,
+// with each input a combination of up to three grids and each result r_o
+// written to up to three destinations (dst = dst (when added) + c r_o).
+// Three launches: forward row transforms (the half spectrum kx <= nx/2 is
+// kept, the inputs being real), column transforms with the multipliers (one
+// wavefront per input and per output transform, concurrently), inverse row
+// transforms (the other half by Hermitian symmetry).
 // ---------------------------------------------------------------------------
 enum {
   SK_ONE = 0,     // 1
@@ -46,19 +179,24 @@ enum {
   SK_IKX_DEN,     // i kdx/(-|k|^2 - kappa^2)
   SK_IKY_DEN      // i kdy/(-|k|^2 - kappa^2)
 };
-constexpr int SPEC_IN = 5, SPEC_OUT = 5, SPEC_TERMS = 4;
+constexpr int SPEC_IN = 5, SPEC_OUT = 5, SPEC_TERMS = 4, SPEC_COMB = 3;
 
 template <typename R>
 struct SpecOp {
   int ni, no;
-  const R* in[SPEC_IN];
-  R* out[SPEC_OUT];
-  int add[SPEC_OUT];                // 1: out += result, 0: out = result
+  int nin[SPEC_IN];
+  const R* in[SPEC_IN][SPEC_COMB];
+  double inc[SPEC_IN][SPEC_COMB];
+  int nd[SPEC_OUT];
+  R* dst[SPEC_OUT][SPEC_COMB];
+  double dc[SPEC_OUT][SPEC_COMB];
+  int dadd[SPEC_OUT][SPEC_COMB];
   int nterm[SPEC_OUT];
   int kind[SPEC_OUT][SPEC_TERMS];
   int src[SPEC_OUT][SPEC_TERMS];
   double coef[SPEC_OUT][SPEC_TERMS];
-  const double* mean[SPEC_OUT];     // k = 0 value (the output's mean), or null
+  const double* mean[SPEC_OUT];     // k = 0 value (the result's mean), or null
+  double* insum;                    // += sum over the nodes of input 0, or null
   int conj;                         // 1: the transpose (conjugate multipliers)
   double kappa2;
   C2<R>* work;                      // [max(ni, no)][ny][nx] complex scratch
@@ -94,8 +232,11 @@ __device__ __forceinline__ void spec_mult(int kind, double c, double kx, double 
   if (conj) im = -im;
 }
 
+// one block (one wavefront) per (row, input)
 template <typename R>
-__global__ void __launch_bounds__(64) k_spec_rows_fwd(Geo<R> g, SpecOp<R> op, const C2<R>* __restrict__ twx) {
+__global__ void __launch_bounds__(64) k_spec_rows_fwd(Geo<R> g, SpecOp<R> op, const C2<R>* __restrict__ twx,
+                                                      Side<R> side) {
+  run_side(side);
   const int l = blockIdx.x, f = blockIdx.y;
   if (l >= g.ny || f >= op.ni) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -103,64 +244,82 @@ __global__ void __launch_bounds__(64) k_spec_rows_fwd(Geo<R> g, SpecOp<R> op, co
   C2<R>* A = tw + g.nx;
   C2<R>* B = A + g.nx;
   const int t = threadIdx.x, tpt = blockDim.x;
+  double rs = 0.0;
   for (int i = t; i < g.nx; i += tpt) {
     tw[i] = twx[i];
-    A[i] = C2<R>{op.in[f][(int64_t)l * g.nx + i], R(0)};
+    double v = 0.0;
+    for (int q = 0; q < op.nin[f]; ++q) v += op.inc[f][q] * (double)op.in[f][q][(int64_t)l * g.nx + i];
+    rs += v;
+    A[i] = C2<R>{(R)v, R(0)};
+  }
+  if (op.insum && f == 0) {
+    for (int off = 32; off >= 1; off >>= 1) rs += __shfl_xor(rs, off);
+    if (t == 0) atomicAdd(op.insum, rs);
   }
   __syncthreads();
   const C2<R>* r = fft_lds<R, false>(A, B, g.nx, g.lgx, t, tpt, tw);
   C2<R>* w = op.work + (int64_t)f * g.nperp + (int64_t)l * g.nx;
-  for (int i = t; i < g.nx; i += tpt) w[i] = r[i];
+  for (int i = t; i <= g.nx / 2; i += tpt) w[i] = r[i];
 }
 
+// one block per column kx <= nx/2, one wavefront per transform; LDS:
+// twiddles, then two buffers of ny per wavefront
 template <typename R>
-__global__ void __launch_bounds__(64) k_spec_cols(Geo<R> g, SpecOp<R> op, const C2<R>* __restrict__ twy) {
+__global__ void __launch_bounds__(64 * SPEC_IN) k_spec_cols(Geo<R> g, SpecOp<R> op, const C2<R>* __restrict__ twy,
+                                                            Side<R> side) {
+  run_side(side);
   const int kx = blockIdx.x;
-  if (kx >= g.nx) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
-  C2<R>* col = tw + g.ny;                        // [ni][ny] transformed inputs
-  C2<R>* A = col + (int64_t)op.ni * g.ny;        // work pair
+  const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  C2<R>* A = tw + g.ny + (int64_t)(2 * w) * g.ny;
   C2<R>* B = A + g.ny;
-  const int t = threadIdx.x, tpt = blockDim.x;
-  for (int i = t; i < g.ny; i += tpt) tw[i] = twy[i];
-  for (int f = 0; f < op.ni; ++f) {
-    for (int i = t; i < g.ny; i += tpt) A[i] = op.work[(int64_t)f * g.nperp + (int64_t)i * g.nx + kx];
-    __syncthreads();
-    const C2<R>* r = fft_lds<R, false>(A, B, g.ny, g.lgy, t, tpt, tw);
-    for (int i = t; i < g.ny; i += tpt) col[(int64_t)f * g.ny + i] = r[i];
-    __syncthreads();
-  }
+  for (int i = threadIdx.x; i < g.ny; i += blockDim.x) tw[i] = twy[i];
+  for (int i = t; i < g.ny; i += 64)
+    A[i] = (w < op.ni) ? op.work[(int64_t)w * g.nperp + (int64_t)i * g.nx + kx] : C2<R>{R(0), R(0)};
+  __syncthreads();
+  // forward column transforms: every wavefront's result sits in the same
+  // buffer of its pair (same pass count)
+  const C2<R>* r = fft_lds<R, false>(A, B, g.ny, g.lgy, t, 64, tw);
+  const bool inA = (r == A);
+  auto res = [&](int f) -> const C2<R>* { return tw + g.ny + (int64_t)(2 * f + (inA ? 0 : 1)) * g.ny; };
+  C2<R>* S = inA ? B : A;   // free buffer of this wavefront
   double kxv, kdx;
   axis_k(kx, g.nx, (double)g.nx * (double)g.dx, kxv, kdx);
   const double N = (double)g.nperp;
-  for (int o = 0; o < op.no; ++o) {
-    for (int ky = t; ky < g.ny; ky += tpt) {
+  if (w < op.no) {
+    for (int ky = t; ky < g.ny; ky += 64) {
       double kyv, kdy;
       axis_k(ky, g.ny, (double)g.ny * (double)g.dy, kyv, kdy);
       double ar = 0.0, ai = 0.0;
-      for (int q = 0; q < op.nterm[o]; ++q) {
+      for (int q = 0; q < op.nterm[w]; ++q) {
         double mr, mi;
-        spec_mult(op.kind[o][q], op.coef[o][q], kxv, kdx, kyv, kdy, op.kappa2, op.conj != 0, mr, mi);
-        const C2<R> v = col[(int64_t)op.src[o][q] * g.ny + ky];
+        spec_mult(op.kind[w][q], op.coef[w][q], kxv, kdx, kyv, kdy, op.kappa2, op.conj != 0, mr, mi);
+        const C2<R> v = res(op.src[w][q])[ky];
         ar += mr * (double)v.x - mi * (double)v.y;
         ai += mr * (double)v.y + mi * (double)v.x;
       }
-      if (kx == 0 && ky == 0 && op.mean[o]) {
-        ar = *op.mean[o] * N;
+      if (kx == 0 && ky == 0 && op.mean[w]) {
+        ar = *op.mean[w] * N;
         ai = 0.0;
       }
-      A[ky] = C2<R>{(R)ar, (R)ai};
+      S[ky] = C2<R>{(R)ar, (R)ai};
     }
-    __syncthreads();
-    const C2<R>* r = fft_lds<R, true>(A, B, g.ny, g.lgy, t, tpt, tw);
-    for (int i = t; i < g.ny; i += tpt) op.work[(int64_t)o * g.nperp + (int64_t)i * g.nx + kx] = r[i];
-    __syncthreads();
   }
+  __syncthreads();
+  C2<R>* other = const_cast<C2<R>*>(res(w));
+  const C2<R>* q = fft_lds<R, true>(S, other, g.ny, g.lgy, t, 64, tw);
+  (void)nw;
+  if (w < op.no)
+    for (int i = t; i < g.ny; i += 64) op.work[(int64_t)w * g.nperp + (int64_t)i * g.nx + kx] = q[i];
 }
 
+// one block (one wavefront) per (row, output)
 template <typename R>
-__global__ void __launch_bounds__(64) k_spec_rows_inv(Geo<R> g, SpecOp<R> op, const C2<R>* __restrict__ twx) {
+__global__ void __launch_bounds__(64) k_spec_rows_inv(Geo<R> g, SpecOp<R> op, const C2<R>* __restrict__ twx,
+                                                      Side<R> side) {
+  run_side(side);
   const int l = blockIdx.x, o = blockIdx.y;
   if (l >= g.ny || o >= op.no) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -169,105 +328,27 @@ __global__ void __launch_bounds__(64) k_spec_rows_inv(Geo<R> g, SpecOp<R> op, co
   C2<R>* B = A + g.nx;
   const int t = threadIdx.x, tpt = blockDim.x;
   const C2<R>* w = op.work + (int64_t)o * g.nperp + (int64_t)l * g.nx;
+  const int h = g.nx / 2;
   for (int i = t; i < g.nx; i += tpt) {
     tw[i] = twx[i];
-    A[i] = w[i];
+    if (i <= h) {
+      A[i] = w[i];
+    } else {
+      const C2<R> v = w[g.nx - i];
+      A[i] = C2<R>{v.x, -v.y};
+    }
   }
   __syncthreads();
   const C2<R>* r = fft_lds<R, true>(A, B, g.nx, g.lgx, t, tpt, tw);
-  const R s = R(1.0 / (double)g.nperp);
-  R* out = op.out[o] + (int64_t)l * g.nx;
-  for (int i = t; i < g.nx; i += tpt) out[i] = op.add[o] ? out[i] + r[i].x * s : r[i].x * s;
-}
-
-// ---------------------------------------------------------------------------
-// Grid helpers
-// ---------------------------------------------------------------------------
-// out[k] = sum_t c_t in_t[k] (+ out[k] when add), for up to 6 terms.
-template <typename R>
-struct Lin {
-  R* out;
-  int add;
-  int nt;
-  double c0;          // constant term
-  const R* in[6];
-  double c[6];
-};
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_lin(Lin<R> a, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = (a.add ? (double)a.out[i] : 0.0) + a.c0;
-  for (int t = 0; t < a.nt; ++t) s += a.c[t] * (double)a.in[t][i];
-  a.out[i] = (R)s;
-}
-
-// dst += c * sum(src) (one double accumulator; block sums, then one atomic
-// per block).
-template <typename R>
-__global__ void __launch_bounds__(256) k_sum(const R* __restrict__ src, int64_t n, double c,
-                                             double* __restrict__ dst) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    s += (double)src[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+  const double s = 1.0 / (double)g.nperp;
+  for (int d = 0; d < op.nd[o]; ++d) {
+    R* out = op.dst[o][d] + (int64_t)l * g.nx;
+    const double c = op.dc[o][d] * s;
+    if (op.dadd[o][d])
+      for (int i = t; i < g.nx; i += tpt) out[i] = (R)((double)out[i] + c * (double)r[i].x);
+    else
+      for (int i = t; i < g.nx; i += tpt) out[i] = (R)(c * (double)r[i].x);
   }
-  if (threadIdx.x == 0) atomicAdd(dst, c * red[0]);
-}
-
-// dst += c * sum(src^2) (the energy).
-template <typename R>
-__global__ void __launch_bounds__(256) k_sumsq(const R* __restrict__ src, int64_t n, double c,
-                                               double* __restrict__ dst) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = (double)src[i];
-    s += v * v;
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicAdd(dst, c * red[0]);
-}
-
-// Transverse-mean leapfrog of one slice, forward: from e = <E_z>_{j-1/2},
-// p = psi0_j and s = sum(J_z): e' = e - h s/N, ez0 = (e + e')/2,
-// p' = p + h e'.  sc = [e, p, s, ez0, e', p'].
-__global__ void k_ode_fwd(double* sc, double h, double N) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double e = sc[0], p = sc[1], s = sc[2];
-  const double en = e - h * s / N;
-  sc[3] = 0.5 * (e + en);
-  sc[4] = en;
-  sc[5] = p + h * en;
-}
-
-// Its transpose.  a = [e_bar', p_bar', ez0_bar] in, out: a[3] = e_bar,
-// a[4] = p_bar (before the psi-mean term), a[5] = the uniform J_z adjoint
-// per node (-h e_next_bar / N).
-__global__ void k_ode_adj(double* a, double h, double N) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double en = a[0] + 0.5 * a[2] + h * a[1];
-  a[3] = en + 0.5 * a[2];
-  a[4] = a[1];
-  a[5] = -h * en / N;
-}
-
-// out[i] += c * (*scalar) for every node.
-template <typename R>
-__global__ void __launch_bounds__(256) k_add_scalar(R* __restrict__ out, int64_t n, const double* s, double c) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (R)((double)out[i] + c * (*s));
 }
 
 // ---------------------------------------------------------------------------
@@ -600,6 +681,8 @@ struct AdjPlasma {
   R* Jz;
   double jscale;       // reverse: scale of the current adjoints (1/(2h) for D)
   const R* Sb;         // reverse: adjoint of S
+  double* qzsum;       // forward J stage: += sum of the J_z deposits
+  const double* jzs;   // reverse J stage: uniform part of the J_z adjoint
   int* err;
 };
 
@@ -613,7 +696,8 @@ struct AdjPlasma {
 
 // S += -w W/(dx dy)
 template <typename R>
-__global__ void __launch_bounds__(256) k_af_dep_s(AdjPlasma<R> a, R* __restrict__ S) {
+__global__ void __launch_bounds__(256) k_af_dep_s(AdjPlasma<R> a, R* __restrict__ S, Side<R> side) {
+  run_side(side);
   ADJ_TILE(1);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
@@ -631,7 +715,8 @@ __global__ void __launch_bounds__(256) k_af_dep_s(AdjPlasma<R> a, R* __restrict_
 
 // J stage: G = 1 + psi(Y); J += -w u/G W/(dx dy)
 template <typename R>
-__global__ void __launch_bounds__(256) k_af_dep_j(AdjPlasma<R> a) {
+__global__ void __launch_bounds__(256) k_af_dep_j(AdjPlasma<R> a, Side<R> side) {
+  run_side(side);
   ADJ_TILE(3);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
@@ -650,6 +735,11 @@ __global__ void __launch_bounds__(256) k_af_dep_j(AdjPlasma<R> a) {
     q[1] = a.nw * uy / G;
     q[2] = a.nw * (gam - G) / G;
   }
+  {
+    double qz = q[2];
+    for (int off = 32; off >= 1; off >>= 1) qz += __shfl_xor(qz, off);
+    if ((threadIdx.x & 63) == 0 && qz != 0.0) atomicAdd(a.qzsum, qz);
+  }
   const TileBox b = box_reduce<1>(bx, red, CAP_);
   tile_zero(tile, b, NCH_);
   R* const dst[3] = {a.Jx, a.Jy, a.Jz};
@@ -658,10 +748,10 @@ __global__ void __launch_bounds__(256) k_af_dep_j(AdjPlasma<R> a) {
   tile_flush<R, 3>(a.g, tile, b, dst, 1);
 }
 
-// Predictor: Yt = RK2(Y; F), stored; Jt_perp += -w ut/Gt with Gt = 1 + psit(Yt)
+// Predictor: Yt = RK2(Y; F); Jt_perp += -w ut/Gt with Gt = 1 + psit(Yt)
 template <typename R>
-__global__ void __launch_bounds__(256) k_af_pred(AdjPlasma<R> a, R* __restrict__ Yt0, R* __restrict__ Yt1,
-                                                 R* __restrict__ Yt2, R* __restrict__ Yt3) {
+__global__ void __launch_bounds__(256) k_af_pred(AdjPlasma<R> a, Side<R> side) {
+  run_side(side);
   ADJ_TILE(2);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
@@ -671,10 +761,6 @@ __global__ void __launch_bounds__(256) k_af_pred(AdjPlasma<R> a, R* __restrict__
     const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
     double Ys[4], Yt[4];
     rk2_val(a.g, a.F, a.h, Y, Ys, Yt);
-    Yt0[p] = (R)Yt[0];
-    Yt1[p] = (R)Yt[1];
-    Yt2[p] = (R)Yt[2];
-    Yt3[p] = (R)Yt[3];
     c = cic(a.g, (R)Yt[0], (R)Yt[1]);
     box_add(bx, 0, c.l0, c.i0);
     double ps, px, py;
@@ -694,7 +780,8 @@ __global__ void __launch_bounds__(256) k_af_pred(AdjPlasma<R> a, R* __restrict__
 
 // Final advance: Yn = wrap(RK2(Y; F))
 template <typename R>
-__global__ void __launch_bounds__(256) k_af_final(AdjPlasma<R> a) {
+__global__ void __launch_bounds__(256) k_af_final(AdjPlasma<R> a, Side<R> side) {
+  run_side(side);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.np) return;
   const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
@@ -716,7 +803,8 @@ __device__ __forceinline__ void six_bar_dst(const SixBar<R>& Fb, R** dst) {
 
 // Reverse of the final advance: Yn (adjoint of Y) = RK2^T(Ynb); fields.
 template <typename R>
-__global__ void __launch_bounds__(256) k_ar_final(AdjPlasma<R> a) {
+__global__ void __launch_bounds__(256) k_ar_final(AdjPlasma<R> a, Side<R> side) {
+  run_side(side);
   ADJ_TILE(12);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
@@ -741,7 +829,8 @@ __global__ void __launch_bounds__(256) k_ar_final(AdjPlasma<R> a) {
 // Reverse of predictor iteration: the adjoint of Jt_perp (jscale * (Jx, Jy))
 // -> adjoint of Yt and of psit -> RK2^T into the adjoint of Y (added).
 template <typename R>
-__global__ void __launch_bounds__(256) k_ar_pred(AdjPlasma<R> a) {
+__global__ void __launch_bounds__(256) k_ar_pred(AdjPlasma<R> a, Side<R> side) {
+  run_side(side);
   ADJ_TILE(13);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
@@ -796,7 +885,8 @@ __global__ void __launch_bounds__(256) k_ar_pred(AdjPlasma<R> a) {
 // to the adjoint of Y and, for the J stage, of psi.  The two run as separate
 // launches: the adjoint of S needs the psi adjoint the J stage completes.
 template <typename R>
-__global__ void __launch_bounds__(256) k_ar_jstage(AdjPlasma<R> a) {
+__global__ void __launch_bounds__(256) k_ar_jstage(AdjPlasma<R> a, Side<R> side) {
+  run_side(side);
   ADJ_TILE(1);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
@@ -818,7 +908,7 @@ __global__ void __launch_bounds__(256) k_ar_jstage(AdjPlasma<R> a) {
       cic_val(g, a.Jz, c, jz, jzx, jzy);
       const double qx = a.nw * ux / G, qy = a.nw * uy / G;
       const double qz = a.nw * ((1.0 + u2 + G * G) / (2.0 * G * G) - 1.0);
-      const double qxb = jx, qyb = jy, qzb = jz;
+      const double qxb = jx, qyb = jy, qzb = jz + (a.jzs ? *a.jzs : 0.0);
       xb = qx * jxx + qy * jyx + qz * jzx;
       yb = qx * jxy + qy * jyy + qz * jzy;
       uxb = a.nw * (qxb / G + qzb * ux / (G * G));
@@ -845,6 +935,55 @@ __global__ void __launch_bounds__(256) k_ar_jstage(AdjPlasma<R> a) {
   if (live) tile_add(tile, b, 0, c, Gb, a.psib);
   R* const dst[1] = {a.psib};
   tile_flush<R, 1>(g, tile, b, dst, 1);
+}
+
+// Recompute of a checkpoint segment: each thread takes its plasma particle
+// from the checkpointed state through slices j0 .. j0 + len - 1 with the
+// taped fields and B_perp iterates (the predictor states need no deposit),
+// storing the state at every slice and the K predictor states.
+template <typename R>
+struct AdjSeg {
+  Geo<R> g;
+  int np, K, j0, len;
+  double h;
+  const R* Y0[4];       // checkpoint (state at j0)
+  R* segY;              // [len][4][np]
+  R* segYt;             // [len][K][4][np]
+  const R* fields;      // [N_STORED][nxi][ny][nx] of the sweep
+  const R* biter;       // [K][2][nxi][ny][nx]
+  const R* zero;
+};
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_af_segment(AdjSeg<R> a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.np) return;
+  const int64_t nperp = a.g.nperp, plane = (int64_t)a.g.nxi * nperp, np = a.np;
+  double Y[4] = {a.Y0[0][p], a.Y0[1][p], a.Y0[2][p], a.Y0[3][p]};
+  const int fm[6] = {F_PSI, F_DXPSI, F_DYPSI, F_BX, F_BY, F_BZ};
+  for (int i = 0; i < a.len; ++i) {
+    const int j = a.j0 + i;
+    for (int c = 0; c < 4; ++c) a.segY[((int64_t)i * 4 + c) * np + p] = (R)Y[c];
+    Six<R> F;
+    for (int m = 0; m < 6; ++m) {
+      F.a[m] = a.fields + fm[m] * plane + (int64_t)j * nperp;
+      F.m1[m] = (j >= 1) ? F.a[m] - nperp : a.zero;
+    }
+    double Ys[4], Yn[4];
+    for (int k = 0; k < a.K; ++k) {
+      F.a[3] = a.biter + ((int64_t)k * 2 + 0) * plane + (int64_t)j * nperp;
+      F.a[4] = a.biter + ((int64_t)k * 2 + 1) * plane + (int64_t)j * nperp;
+      rk2_val(a.g, F, a.h, Y, Ys, Yn);
+      for (int c = 0; c < 4; ++c) a.segYt[(((int64_t)i * a.K + k) * 4 + c) * np + p] = (R)Yn[c];
+    }
+    F.a[3] = a.fields + F_BX * plane + (int64_t)j * nperp;
+    F.a[4] = a.fields + F_BY * plane + (int64_t)j * nperp;
+    rk2_val(a.g, F, a.h, Y, Ys, Yn);
+    Y[0] = wrap_pos((R)Yn[0], a.g.lx, a.g.inv_lx);
+    Y[1] = wrap_pos((R)Yn[1], a.g.ly, a.g.inv_ly);
+    Y[2] = (R)Yn[2];
+    Y[3] = (R)Yn[3];
+  }
 }
 
 // ---------------------------------------------------------------------------
