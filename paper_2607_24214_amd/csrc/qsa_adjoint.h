@@ -60,30 +60,41 @@ __global__ void __launch_bounds__(256) k_lin(Lin<R> a, int64_t n) {
   lin_range(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n, (int64_t)gridDim.x * blockDim.x);
 }
 
-// Scalar jobs (thread 0 of a launch), for the transverse-mean leapfrog:
-//  SJ_SET:      *a = b ? *b : v0
+// Scalar jobs (the first wavefront of a launch), for the transverse-mean
+// leapfrog; part[0..npart) are per-block partial sums written by an earlier
+// launch, added by the wavefront:
 //  SJ_ODE_FWD:  slice slot a = [e, p, s, ez0] (e = <E_z>_{j-1/2}, p = psi0_j,
-//               s = sum J_z): e' = e - h s/N, ez0 = (e + e')/2, and the next
-//               slot b = [e', p + h e'];  v0 = h, v1 = N
-//  SJ_ODE_ADJ:  a = [e_bar', p_bar'] of slice j + 1, b = slot of slice j,
+//               s = sum J_z = *c + sum part): e' = e - h s/N,
+//               ez0 = (e + e')/2, and the next slot b = [e', p + h e'];
+//               v0 = h, v1 = N
+//  SJ_ODE_ADJ:  a = [e_bar', p_bar'] of slice j + 1 (p_bar' still without
+//               the sum part of its psi adjoint), b = slot of slice j,
 //               c = sum of the E_z adjoint over the slice (ez0_bar):
-//               b = [e_bar, p_bar (before its psi-mean term), uniform J_z
-//               adjoint per node]
-enum { SJ_NONE = 0, SJ_SET, SJ_ODE_FWD, SJ_ODE_ADJ };
+//               b = [e_bar, p_bar (before its own psi-mean part), uniform
+//               J_z adjoint per node]
+enum { SJ_NONE = 0, SJ_ODE_FWD, SJ_ODE_ADJ };
 struct ScalarJob {
   int kind;
+  int npart;
   double* a;
   double* b;
   const double* c;
+  const double* part;
   double v0, v1;
 };
 
+// every lane of wavefront 0 of block 0 calls this
 __device__ __forceinline__ void run_scalar(const ScalarJob& j) {
+  const int lane = threadIdx.x & 63;
+  double ps = 0.0;
+  for (int i = lane; i < j.npart; i += 64) ps += j.part[i];
+  for (int off = 32; off >= 1; off >>= 1) ps += __shfl_xor(ps, off);
+  if (lane != 0) return;
   switch (j.kind) {
-    case SJ_SET: *j.a = j.c ? *j.c : j.v0; break;
     case SJ_ODE_FWD: {
-      const double e = j.a[0], p = j.a[1], s = j.a[2];
+      const double e = j.a[0], p = j.a[1], s = *j.c + ps;
       const double en = e - j.v0 * s / j.v1;
+      j.a[2] = s;
       j.a[3] = 0.5 * (e + en);
       j.b[0] = en;
       j.b[1] = p + j.v0 * en;
@@ -91,9 +102,10 @@ __device__ __forceinline__ void run_scalar(const ScalarJob& j) {
     }
     case SJ_ODE_ADJ: {
       const double ez = *j.c;
-      const double en = j.a[0] + 0.5 * ez + j.v0 * j.a[1];
+      const double pb = j.a[1] + ps;
+      const double en = j.a[0] + 0.5 * ez + j.v0 * pb;
       j.b[0] = en + 0.5 * ez;
-      j.b[1] = j.a[1];
+      j.b[1] = pb;
       j.b[2] = -j.v0 * en / j.v1;
       break;
     }
@@ -117,7 +129,7 @@ template <typename R>
 __device__ __forceinline__ void run_side(const Side<R>& s) {
   const int64_t tid = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t nth = (int64_t)gridDim.x * gridDim.y * blockDim.x;
-  if (tid == 0)
+  if (tid < 64)
     for (int q = 0; q < s.ns; ++q) run_scalar(s.sj[q]);
   for (int q = 0; q < s.nl; ++q) lin_range(s.op[q], tid, s.len, nth);
 }
@@ -196,7 +208,7 @@ struct SpecOp {
   int src[SPEC_OUT][SPEC_TERMS];
   double coef[SPEC_OUT][SPEC_TERMS];
   const double* mean[SPEC_OUT];     // k = 0 value (the result's mean), or null
-  double* insum;                    // += sum over the nodes of input 0, or null
+  double* insum;                    // [ny] per-row sums of input 0, or null
   int conj;                         // 1: the transpose (conjugate multipliers)
   double kappa2;
   C2<R>* work;                      // [max(ni, no)][ny][nx] complex scratch
@@ -254,7 +266,7 @@ __global__ void __launch_bounds__(64) k_spec_rows_fwd(Geo<R> g, SpecOp<R> op, co
   }
   if (op.insum && f == 0) {
     for (int off = 32; off >= 1; off >>= 1) rs += __shfl_xor(rs, off);
-    if (t == 0) atomicAdd(op.insum, rs);
+    if (t == 0) op.insum[l] = rs;
   }
   __syncthreads();
   const C2<R>* r = fft_lds<R, false>(A, B, g.nx, g.lgx, t, tpt, tw);
@@ -401,7 +413,9 @@ __device__ __forceinline__ void cic_add(R* __restrict__ F, const Cic<R>& c, doub
 }
 
 // ---------------------------------------------------------------------------
-// Block-local scatter accumulation.  The particles of a block (consecutive
+// Block-local scatter accumulation.  Tile kernels number their particle
+// chunks with xcd_block, so that neighbouring chunks (which flush to shared
+// nodes) run on one XCD.  The particles of a block (consecutive
 // in memory, hence close in space while the order of loading by cell holds)
 // reduce the bounding box of the cells they scatter at.  When the box's
 // nodes fit the LDS tile, the linear-shape weights accumulate there with LDS
@@ -412,11 +426,6 @@ __device__ __forceinline__ void cic_add(R* __restrict__ F, const Cic<R>& c, doub
 // box_reduce, tile_zero and tile_flush (they hold barriers).  NZ = 1 for
 // transverse grids [ny][nx] (cell slice 0), 2 for [nxi][ny][nx] grids.
 // ---------------------------------------------------------------------------
-template <typename R, int NCH>
-struct AdjTile {
-  static constexpr int CAP = 40960 / (NCH * (int)sizeof(R));   // nodes per channel
-};
-
 struct BoxAcc {
   int lo[3], hi[3];    // cell (j, l, i) range of one thread
 };
@@ -483,20 +492,106 @@ __device__ __forceinline__ void tile_zero(R* tile, const TileBox& b, int nch) {
   __syncthreads();
 }
 
+// Lane-group merge.  Particles that share a cell sit on neighbouring lanes
+// (4 plasma particles per cell in loading order, 8 beam particles per cell
+// after sorting).  When an aligned group of G lanes (G = 4 or 8) scatters
+// at one cell, the group sums its node weights with DPP lane moves and only
+// its first lane adds them to the tile: a quarter (an eighth) of the LDS
+// atomics, and none from several lanes to one address.  Every lane of the
+// wavefront calls merge_of and the tile adds (converged code); a lane with
+// nothing to add passes act = false, and its group adds lane by lane.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_r(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_r(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<CTRL>((int)(b & 0xffffffffll));
+  const int hi = dpp_i<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7 - i within 8 lanes
+
+template <int G>
+__device__ __forceinline__ void group_minmax(int& mn, int& mx) {
+  mn = min(mn, dpp_i<DPP_XOR1>(mn));
+  mx = max(mx, dpp_i<DPP_XOR1>(mx));
+  mn = min(mn, dpp_i<DPP_XOR2>(mn));
+  mx = max(mx, dpp_i<DPP_XOR2>(mx));
+  if (G == 8) {
+    mn = min(mn, dpp_i<DPP_HALF_MIRROR>(mn));
+    mx = max(mx, dpp_i<DPP_HALF_MIRROR>(mx));
+  }
+}
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  v += dpp_r<DPP_XOR1>(v);
+  v += dpp_r<DPP_XOR2>(v);
+  if (G == 8) v += dpp_r<DPP_HALF_MIRROR>(v);
+  return v;
+}
+
+struct Merge {
+  bool uni;    // the lane's group shares one cell
+  bool lead;   // first lane of its group
+  bool act;    // the lane adds something at this position
+};
+
+// keys: the cell (two non-negative parts) when act
+template <int G>
+__device__ __forceinline__ Merge merge_of(bool act, int key0, int key1 = 0) {
+  const int lane = threadIdx.x & 63;
+  int a0 = act ? key0 : -1 - lane, b0 = a0;
+  int a1 = act ? key1 : 0, b1 = a1;
+  group_minmax<G>(a0, b0);
+  group_minmax<G>(a1, b1);
+  Merge m;
+  m.uni = (a0 == b0) && (a1 == b1);
+  m.lead = (lane & (G - 1)) == 0;
+  m.act = act;
+  return m;
+}
+
+template <int G, typename R>
+__device__ __forceinline__ Merge merge_at(bool act, const Cic<R>& c, int nx) {
+  return merge_of<G>(act, c.l0 * nx + c.i0);
+}
+
 // q times the linear shape at c into channel ch (transverse grid glob when
 // the box did not fit)
-template <typename R>
-__device__ __forceinline__ void tile_add(R* tile, const TileBox& b, int ch, const Cic<R>& c, double q, R* glob) {
-  if (q == 0.0) return;
-  if (!b.fits) {
-    cic_add(glob, c, q);
+template <int G, typename R>
+__device__ __forceinline__ void tile_add(R* tile, const TileBox& b, int ch, const Cic<R>& c, double q, R* glob,
+                                         const Merge& m) {
+  if (!b.fits) {   // uniform over the block
+    if (m.act && q != 0.0) cic_add(glob, c, q);
+    return;
+  }
+  R w[4] = {R(0), R(0), R(0), R(0)};
+  if (m.act) {
+    w[0] = (R)(q * (1 - c.fx) * (1 - c.fy));
+    w[1] = (R)(q * c.fx * (1 - c.fy));
+    w[2] = (R)(q * (1 - c.fx) * c.fy);
+    w[3] = (R)(q * c.fx * c.fy);
+  }
+  if (m.uni) {
+#pragma unroll
+    for (int n = 0; n < 4; ++n) w[n] = group_sum<G>(w[n]);
+    if (!m.lead) return;
+  } else if (!m.act || q == 0.0) {
     return;
   }
   R* t = tile + ch * b.nodes + (c.l0 - b.l0) * b.ni + (c.i0 - b.i0);
-  atomicAdd(t, (R)(q * (1 - c.fx) * (1 - c.fy)));
-  atomicAdd(t + 1, (R)(q * c.fx * (1 - c.fy)));
-  atomicAdd(t + b.ni, (R)(q * (1 - c.fx) * c.fy));
-  atomicAdd(t + b.ni + 1, (R)(q * c.fx * c.fy));
+  atomicAdd(t, w[0]);
+  atomicAdd(t + 1, w[1]);
+  atomicAdd(t + b.ni, w[2]);
+  atomicAdd(t + b.ni + 1, w[3]);
 }
 
 // the touched tile nodes into the grids dst[ch] ([nz][ny][nx], nz = 1 for
@@ -654,11 +749,12 @@ __device__ __forceinline__ void rk2_adj(const Geo<R>& g, const Six<R>& F, double
 // channels 0..5: fields of slice j (stage 1, and 3/2 of stage 2); 6..11:
 // fields of slice j - 1 (-1/2 of stage 2)
 template <typename R>
-__device__ __forceinline__ void rk2_bar_add(R* tile, const TileBox& b, const Rk2Bar<R>& o, const SixBar<R>& Fb) {
+__device__ __forceinline__ void rk2_bar_add(R* tile, const TileBox& b, const Rk2Bar<R>& o, const SixBar<R>& Fb,
+                                            const Merge& m0, const Merge& m1) {
   for (int m = 0; m < 6; ++m) {
-    tile_add(tile, b, m, o.c0, o.g0[m], Fb.a[m]);
-    tile_add(tile, b, m, o.c1, 1.5 * o.g1[m], Fb.a[m]);
-    tile_add(tile, b, 6 + m, o.c1, -0.5 * o.g1[m], Fb.m1[m]);
+    tile_add<4>(tile, b, m, o.c0, o.g0[m], Fb.a[m], m0);
+    tile_add<4>(tile, b, m, o.c1, 1.5 * o.g1[m], Fb.a[m], m1);
+    tile_add<4>(tile, b, 6 + m, o.c1, -0.5 * o.g1[m], Fb.m1[m], m1);
   }
 }
 
@@ -681,25 +777,30 @@ struct AdjPlasma {
   R* Jz;
   double jscale;       // reverse: scale of the current adjoints (1/(2h) for D)
   const R* Sb;         // reverse: adjoint of S
-  double* qzsum;       // forward J stage: += sum of the J_z deposits
+  double* qzsum;       // forward J stage: per-block sums of the J_z deposits
   const double* jzs;   // reverse J stage: uniform part of the J_z adjoint
+  int tile_bytes;      // dynamic LDS of the launch (scatter tile)
   int* err;
 };
 
-#define ADJ_TILE(NCH)                                         \
-  constexpr int NCH_ = (NCH);                                 \
-  constexpr int CAP_ = AdjTile<R, NCH_>::CAP;                 \
-  __shared__ R tile[NCH_ * CAP_];                             \
-  __shared__ int red[6 * 16];                                 \
-  BoxAcc bx;                                                  \
+// LDS of a tile kernel (dynamic, tile_bytes of the launch): 512 bytes of
+// scratch (box reduction: 6 ints per wavefront from byte 0; per-wavefront
+// doubles from byte 384), then NCH channels of CAP_ nodes.
+#define ADJ_TILE(NCH, BYTES)                                              \
+  constexpr int NCH_ = (NCH);                                             \
+  extern __shared__ __align__(16) unsigned char smem_raw[];               \
+  int* red = reinterpret_cast<int*>(smem_raw);                            \
+  R* tile = reinterpret_cast<R*>(smem_raw + 512);                         \
+  const int CAP_ = ((int)(BYTES) - 512) / (NCH_ * (int)sizeof(R));        \
+  BoxAcc bx;                                                              \
   box_init(bx)
 
 // S += -w W/(dx dy)
 template <typename R>
 __global__ void __launch_bounds__(256) k_af_dep_s(AdjPlasma<R> a, R* __restrict__ S, Side<R> side) {
   run_side(side);
-  ADJ_TILE(1);
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  ADJ_TILE(1, a.tile_bytes);
+  const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
   Cic<R> c{};
   if (live) {
@@ -708,7 +809,8 @@ __global__ void __launch_bounds__(256) k_af_dep_s(AdjPlasma<R> a, R* __restrict_
   }
   const TileBox b = box_reduce<1>(bx, red, CAP_);
   tile_zero(tile, b, NCH_);
-  if (live) tile_add(tile, b, 0, c, a.nw, S);
+  const Merge m = merge_at<4>(live, c, a.g.nx);
+  tile_add<4>(tile, b, 0, c, a.nw, S, m);
   R* const dst[1] = {S};
   tile_flush<R, 1>(a.g, tile, b, dst, 1);
 }
@@ -717,8 +819,9 @@ __global__ void __launch_bounds__(256) k_af_dep_s(AdjPlasma<R> a, R* __restrict_
 template <typename R>
 __global__ void __launch_bounds__(256) k_af_dep_j(AdjPlasma<R> a, Side<R> side) {
   run_side(side);
-  ADJ_TILE(3);
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  ADJ_TILE(3, a.tile_bytes);
+  double* wsum = reinterpret_cast<double*>(smem_raw + 384);   // per-wavefront J_z sums
+  const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
   Cic<R> c{};
   double q[3] = {0, 0, 0};
@@ -738,13 +841,18 @@ __global__ void __launch_bounds__(256) k_af_dep_j(AdjPlasma<R> a, Side<R> side) 
   {
     double qz = q[2];
     for (int off = 32; off >= 1; off >>= 1) qz += __shfl_xor(qz, off);
-    if ((threadIdx.x & 63) == 0 && qz != 0.0) atomicAdd(a.qzsum, qz);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = qz;
   }
-  const TileBox b = box_reduce<1>(bx, red, CAP_);
+  const TileBox b = box_reduce<1>(bx, red, CAP_);   // its barrier publishes wsum
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += wsum[w];
+    a.qzsum[blockIdx.x] = t;
+  }
   tile_zero(tile, b, NCH_);
   R* const dst[3] = {a.Jx, a.Jy, a.Jz};
-  if (live)
-    for (int k = 0; k < 3; ++k) tile_add(tile, b, k, c, q[k], dst[k]);
+  const Merge m = merge_at<4>(live, c, a.g.nx);
+  for (int k = 0; k < 3; ++k) tile_add<4>(tile, b, k, c, q[k], dst[k], m);
   tile_flush<R, 3>(a.g, tile, b, dst, 1);
 }
 
@@ -752,8 +860,8 @@ __global__ void __launch_bounds__(256) k_af_dep_j(AdjPlasma<R> a, Side<R> side) 
 template <typename R>
 __global__ void __launch_bounds__(256) k_af_pred(AdjPlasma<R> a, Side<R> side) {
   run_side(side);
-  ADJ_TILE(2);
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  ADJ_TILE(2, a.tile_bytes);
+  const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
   Cic<R> c{};
   double q[2] = {0, 0};
@@ -773,8 +881,8 @@ __global__ void __launch_bounds__(256) k_af_pred(AdjPlasma<R> a, Side<R> side) {
   const TileBox b = box_reduce<1>(bx, red, CAP_);
   tile_zero(tile, b, NCH_);
   R* const dst[2] = {a.Jx, a.Jy};
-  if (live)
-    for (int k = 0; k < 2; ++k) tile_add(tile, b, k, c, q[k], dst[k]);
+  const Merge m = merge_at<4>(live, c, a.g.nx);
+  for (int k = 0; k < 2; ++k) tile_add<4>(tile, b, k, c, q[k], dst[k], m);
   tile_flush<R, 2>(a.g, tile, b, dst, 1);
 }
 
@@ -805,10 +913,10 @@ __device__ __forceinline__ void six_bar_dst(const SixBar<R>& Fb, R** dst) {
 template <typename R>
 __global__ void __launch_bounds__(256) k_ar_final(AdjPlasma<R> a, Side<R> side) {
   run_side(side);
-  ADJ_TILE(12);
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  ADJ_TILE(12, a.tile_bytes);
+  const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
-  Rk2Bar<R> o;
+  Rk2Bar<R> o{};
   if (live) {
     const double Y[4] = {a.Y[0][p], a.Y[1][p], a.Y[2][p], a.Y[3][p]};
     const double Ynb[4] = {a.Ynb[0][p], a.Ynb[1][p], a.Ynb[2][p], a.Ynb[3][p]};
@@ -820,7 +928,7 @@ __global__ void __launch_bounds__(256) k_ar_final(AdjPlasma<R> a, Side<R> side) 
   }
   const TileBox b = box_reduce<1>(bx, red, CAP_);
   tile_zero(tile, b, NCH_);
-  if (live) rk2_bar_add(tile, b, o, a.Fb);
+  rk2_bar_add(tile, b, o, a.Fb, merge_at<4>(live, o.c0, a.g.nx), merge_at<4>(live, o.c1, a.g.nx));
   R* dst[12];
   six_bar_dst(a.Fb, dst);
   tile_flush<R, 12>(a.g, tile, b, dst, 1);
@@ -831,11 +939,11 @@ __global__ void __launch_bounds__(256) k_ar_final(AdjPlasma<R> a, Side<R> side) 
 template <typename R>
 __global__ void __launch_bounds__(256) k_ar_pred(AdjPlasma<R> a, Side<R> side) {
   run_side(side);
-  ADJ_TILE(13);
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  ADJ_TILE(13, a.tile_bytes);
+  const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
   const Geo<R>& g = a.g;
-  Rk2Bar<R> o;
+  Rk2Bar<R> o{};
   Cic<R> c{};
   double Gb = 0.0;
   if (live) {
@@ -870,10 +978,8 @@ __global__ void __launch_bounds__(256) k_ar_pred(AdjPlasma<R> a, Side<R> side) {
   }
   const TileBox b = box_reduce<1>(bx, red, CAP_);
   tile_zero(tile, b, NCH_);
-  if (live) {
-    rk2_bar_add(tile, b, o, a.Fb);
-    tile_add(tile, b, 12, c, Gb, a.psib);
-  }
+  rk2_bar_add(tile, b, o, a.Fb, merge_at<4>(live, o.c0, g.nx), merge_at<4>(live, o.c1, g.nx));
+  tile_add<4>(tile, b, 12, c, Gb, a.psib, merge_at<4>(live, c, g.nx));
   R* dst[13];
   six_bar_dst(a.Fb, dst);
   dst[12] = a.psib;
@@ -887,8 +993,8 @@ __global__ void __launch_bounds__(256) k_ar_pred(AdjPlasma<R> a, Side<R> side) {
 template <typename R>
 __global__ void __launch_bounds__(256) k_ar_jstage(AdjPlasma<R> a, Side<R> side) {
   run_side(side);
-  ADJ_TILE(1);
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  ADJ_TILE(1, a.tile_bytes);
+  const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
   const Geo<R>& g = a.g;
   Cic<R> c{};
@@ -932,7 +1038,7 @@ __global__ void __launch_bounds__(256) k_ar_jstage(AdjPlasma<R> a, Side<R> side)
   if (!a.Jx) return;   // uniform over the launch
   const TileBox b = box_reduce<1>(bx, red, CAP_);
   tile_zero(tile, b, NCH_);
-  if (live) tile_add(tile, b, 0, c, Gb, a.psib);
+  tile_add<4>(tile, b, 0, c, Gb, a.psib, merge_at<4>(live, c, g.nx));
   R* const dst[1] = {a.psib};
   tile_flush<R, 1>(g, tile, b, dst, 1);
 }
@@ -1039,22 +1145,43 @@ __device__ __forceinline__ void cic3_add(const Geo<R>& g, R* __restrict__ F, con
 }
 
 // q times the 3D linear shape at c into channel ch of a tile over node
-// slices (grid glob [nxi][ny][nx] when the box did not fit)
-template <typename R>
+// slices (grid glob [nxi][ny][nx] when the box did not fit); m from
+// merge_at3 (lanes whose particle has no node in the grid pass act = false)
+template <int G, typename R>
+__device__ __forceinline__ Merge merge_at3(bool act, const Cic3<R>& c, int nx) {
+  return merge_of<G>(act && c.in, c.c.l0 * nx + c.c.i0, c.j0 + 1);
+}
+
+template <int G, typename R>
 __device__ __forceinline__ void tile_add3(const Geo<R>& g, R* tile, const TileBox& b, int ch, const Cic3<R>& c,
-                                          double q, R* glob) {
-  if (!c.in || q == 0.0) return;
-  if (!b.fits) {
-    cic3_add(g, glob, c, q);
+                                          double q, R* glob, const Merge& m) {
+  if (!b.fits) {   // uniform over the block
+    if (m.act && q != 0.0) cic3_add(g, glob, c, q);
+    return;
+  }
+  R w[2][4];
+  for (int d = 0; d < 2; ++d) {
+    const double qd = m.act ? q * (d ? c.fz : 1.0 - c.fz) : 0.0;
+    w[d][0] = (R)(qd * (1 - c.c.fx) * (1 - c.c.fy));
+    w[d][1] = (R)(qd * c.c.fx * (1 - c.c.fy));
+    w[d][2] = (R)(qd * (1 - c.c.fx) * c.c.fy);
+    w[d][3] = (R)(qd * c.c.fx * c.c.fy);
+  }
+  if (m.uni) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) w[d][n] = group_sum<G>(w[d][n]);
+    if (!m.lead) return;
+  } else if (!m.act || q == 0.0) {
     return;
   }
   for (int d = 0; d < 2; ++d) {
-    const double qd = q * (d ? c.fz : 1.0 - c.fz);
     R* t = tile + ch * b.nodes + ((c.j0 + d - b.j0) * b.nl + (c.c.l0 - b.l0)) * b.ni + (c.c.i0 - b.i0);
-    atomicAdd(t, (R)(qd * (1 - c.c.fx) * (1 - c.c.fy)));
-    atomicAdd(t + 1, (R)(qd * c.c.fx * (1 - c.c.fy)));
-    atomicAdd(t + b.ni, (R)(qd * (1 - c.c.fx) * c.c.fy));
-    atomicAdd(t + b.ni + 1, (R)(qd * c.c.fx * c.c.fy));
+    atomicAdd(t, w[d][0]);
+    atomicAdd(t + 1, w[d][1]);
+    atomicAdd(t + b.ni, w[d][2]);
+    atomicAdd(t + b.ni + 1, w[d][3]);
   }
 }
 
@@ -1086,6 +1213,7 @@ struct AdjBeam {
   const R* fields;     // [7][nxi][ny][nx] of the step's sweep
   R* fieldsb;          // their adjoint
   R* b[7];             // adjoint of x, y, xi, ux, uy, uz, w (in place: step n+1 -> step n)
+  int tile_bytes;      // dynamic LDS of the launch (scatter tile)
 };
 
 // 1 - v_z, v_x, v_y, v_z per unit charge and their u-derivatives
@@ -1111,8 +1239,8 @@ __device__ __forceinline__ void beam_v(double ux, double uy, double uz, double (
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_ab_sources(AdjBeam<R> a) {
-  ADJ_TILE(4);
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  ADJ_TILE(4, a.tile_bytes);
+  const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.n && a.w[p] != R(0);
   Cic3<R> c{};
   double q[4] = {0, 0, 0, 0};
@@ -1128,8 +1256,8 @@ __global__ void __launch_bounds__(256) k_ab_sources(AdjBeam<R> a) {
   tile_zero(tile, b, NCH_);
   const int64_t plane = (int64_t)a.g.nxi * a.g.nperp;
   R* const dst[4] = {a.src, a.src + plane, a.src + 2 * plane, a.src + 3 * plane};
-  if (live)
-    for (int k = 0; k < 4; ++k) tile_add3(a.g, tile, b, k, c, q[k], dst[k]);
+  const Merge m = merge_at3<8>(live, c, a.g.nx);
+  for (int k = 0; k < 4; ++k) tile_add3<8>(a.g, tile, b, k, c, q[k], dst[k], m);
   tile_flush<R, 4>(a.g, tile, b, dst, a.g.nxi);
 }
 
@@ -1219,8 +1347,8 @@ __device__ __forceinline__ void push_adj_one(const AdjBeam<R>& a, int64_t p, con
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_ab_push_adj(AdjBeam<R> a) {
-  ADJ_TILE(6);
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  ADJ_TILE(6, a.tile_bytes);
+  const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.n;
   Cic3<R> c{};
   double gb[6] = {0, 0, 0, 0, 0, 0};
@@ -1235,8 +1363,8 @@ __global__ void __launch_bounds__(256) k_ab_push_adj(AdjBeam<R> a) {
   const int64_t plane = (int64_t)a.g.nxi * a.g.nperp;
   R* dst[6];
   for (int m = 0; m < 6; ++m) dst[m] = a.fieldsb + slot[m] * plane;
-  if (live)
-    for (int m = 0; m < 6; ++m) tile_add3(a.g, tile, b, m, c, gb[m], dst[m]);
+  const Merge mg = merge_at3<8>(live, c, a.g.nx);
+  for (int m = 0; m < 6; ++m) tile_add3<8>(a.g, tile, b, m, c, gb[m], dst[m], mg);
   tile_flush<R, 6>(a.g, tile, b, dst, a.g.nxi);
 }
 

@@ -31,6 +31,8 @@ struct Adj {
   double h;
   Side<R> none;
   bool overflow = false;
+  int tile_small = 40960;    // LDS of a scatter tile (few channels)
+  int tile_big = 40960;      // of the plasma transposes (12-13 channels), raised in run()
 
   Adj(qsa_ctx* ctx, const AdjLayout& lay) : c(ctx), p(ctx->p), A(lay) {
     g = Engine<R>::geo(p);
@@ -49,6 +51,8 @@ struct Adj {
   double* scr(int par) const { return sc() + 16 + 8 * par; }   // reverse
   double* jzsum() const { return c->at<double>(A.sums); }      // per slice: sum of the beam's J_z
   double* ezsum() const { return c->at<double>(A.sums) + p.nxi; }   // per slice: sum of the E_z adjoint
+  double* jzpart() const { return c->at<double>(A.part); }              // per plasma block: sum of J_z deposits
+  double* psipart() const { return c->at<double>(A.part) + blocks(np); }   // per row: sum of the psi adjoint
   R* fields(int t) const { return c->at<R>(A.fields) + (int64_t)t * N_STORED * plane; }
   R* field(int t, int f, int j) const { return fields(t) + (int64_t)f * plane + (int64_t)j * nperp; }
   R* fbar(int f, int j) const { return c->at<R>(A.fb) + (int64_t)f * plane + (int64_t)j * nperp; }
@@ -106,7 +110,8 @@ struct Adj {
       }
       return *this;
     }
-    SideB& scalar(int kind, double* x, double* y, const double* z, double v0 = 0.0, double v1 = 0.0) {
+    SideB& scalar(int kind, double* x, double* y, const double* z, const double* part, int npart, double v0,
+                  double v1) {
       if (s.ns >= 2) {
         owner->overflow = true;
         return *this;
@@ -116,6 +121,8 @@ struct Adj {
       j.a = x;
       j.b = y;
       j.c = z;
+      j.part = part;
+      j.npart = npart;
       j.v0 = v0;
       j.v1 = v1;
       return *this;
@@ -199,10 +206,11 @@ struct Adj {
     return QSA_OK;
   }
 
+  // lds: the launch's dynamic LDS (a.tile_bytes for the scatter kernels)
   template <typename Kern>
-  qsa_status plasma(Kern kern, const AdjPlasma<R>& a, const Side<R>& s) {
+  qsa_status plasma(Kern kern, const AdjPlasma<R>& a, const Side<R>& s, int lds) {
     if (overflow) return fail(c, QSA_E_INVALID, "adjoint: operator description overflow");
-    hipLaunchKernelGGL(kern, dim3(blocks(np)), dim3(256), 0, st(), a, s);
+    hipLaunchKernelGGL(kern, dim3(blocks(np)), dim3(256), (size_t)lds, st(), a, s);
     HIP_OK(hipGetLastError());
     return QSA_OK;
   }
@@ -214,6 +222,7 @@ struct Adj {
     a.np = (int)np;
     a.nw = -p.plasma_w / (p.dx * p.dy);
     a.h = h;
+    a.tile_bytes = tile_small;
     a.err = c->at<int>(c->L.err);
     return a;
   }
@@ -249,9 +258,9 @@ struct Adj {
     {
       SideB sd(this);
       sd.lin(J[0], 0, {{src(1, j), 1.0}}).lin(J[1], 0, {{src(2, j), 1.0}}).lin(J[2], 0, {{src(3, j), 1.0}});
-      sd.scalar(SJ_SET, si + 2, nullptr, jzsum() + j);
       if (overflow) return fail(c, QSA_E_INVALID, "adjoint: operator description overflow");
-      hipLaunchKernelGGL(k_af_dep_s<R>, dim3(blocks(np)), dim3(256), 0, st(), a, grid(AG_S), sd.s);
+      hipLaunchKernelGGL(k_af_dep_s<R>, dim3(blocks(np)), dim3(256), (size_t)a.tile_bytes, st(), a, grid(AG_S),
+                         sd.s);
     }
     {
       SpecB b(this, 0);
@@ -279,7 +288,7 @@ struct Adj {
       a.Jx = J[0];
       a.Jy = J[1];
       a.Jz = J[2];
-      a.qzsum = si + 2;
+      a.qzsum = jzpart();
       SideB sd(this);
       if (K > 0) {
         const R* pm1 = (j >= 1) ? field(t, F_PSI, j - 1) : zero;
@@ -288,7 +297,7 @@ struct Adj {
         sd.lin(grid(AG_JT), 0, {{last ? zero : src(1, j + 1), 1.0}});
         sd.lin(grid(AG_JT + 1), 0, {{last ? zero : src(2, j + 1), 1.0}});
       }
-      if ((st0 = plasma(k_af_dep_j<R>, a, sd.s)) != QSA_OK) return st0;
+      if ((st0 = plasma(k_af_dep_j<R>, a, sd.s, a.tile_bytes)) != QSA_OK) return st0;
       a.qzsum = nullptr;
     }
     {
@@ -303,7 +312,7 @@ struct Adj {
       b.dest(o1, field(t, F_EZ, j), 1.0, 0);
       b.op.mean[o1] = si + 3;
       SideB sr(this);
-      sr.scalar(SJ_ODE_FWD, si, so, nullptr, h, (double)nperp);
+      sr.scalar(SJ_ODE_FWD, si, so, jzsum() + j, jzpart(), blocks(np), h, (double)nperp);
       if ((st0 = spec(b, sr.s, none, none)) != QSA_OK) return st0;
     }
     // B_perp predictor-corrector
@@ -315,7 +324,7 @@ struct Adj {
       b.Jx = grid(AG_JT);
       b.Jy = grid(AG_JT + 1);
       b.Jz = nullptr;
-      if ((st0 = plasma(k_af_pred<R>, b, none)) != QSA_OK) return st0;
+      if ((st0 = plasma(k_af_pred<R>, b, none, b.tile_bytes)) != QSA_OK) return st0;
       SpecB s(this, 0);
       const int fz = s.input({{J[2], 1.0}});
       const int fx = s.input({{grid(AG_JT), i2h}, {jm1x, -i2h}});
@@ -345,7 +354,7 @@ struct Adj {
       for (int k = 0; k < 4; ++k) b.Yn[k] = Yout[k];
       SideB sd(this);
       if (!last) sd.lin(grid(AG_S), 0, {{src(0, j + 1), 1.0}});
-      if ((st0 = plasma(k_af_final<R>, b, sd.s)) != QSA_OK) return st0;
+      if ((st0 = plasma(k_af_final<R>, b, sd.s, 0)) != QSA_OK) return st0;
     }
     return QSA_OK;
   }
@@ -411,8 +420,9 @@ struct Adj {
         sd.lin(grid(AG_PSIT), 0, {{field(t, F_PSI, j), 3.0}, {pm1, -3.0}, {pm2, 1.0}});
       }
       if (j >= 1) sd.lin(JBm1[0], 0, {}).lin(JBm1[1], 0, {});
-      sd.scalar(SJ_ODE_ADJ, ai, ao, ezsum() + j, h, (double)nperp);
-      if ((st0 = plasma(k_ar_final<R>, b, sd.s)) != QSA_OK) return st0;
+      sd.scalar(SJ_ODE_ADJ, ai, ao, ezsum() + j, psipart(), (j + 1 < p.nxi) ? (int)g.ny : 0, h, (double)nperp);
+      b.tile_bytes = tile_big;
+      if ((st0 = plasma(k_ar_final<R>, b, sd.s, b.tile_bytes)) != QSA_OK) return st0;
     }
     // predictor-corrector, iterations in reverse
     R* bcur[2] = {fbar(F_BX, j), fbar(F_BY, j)};
@@ -455,7 +465,8 @@ struct Adj {
       b.Jx = grid(AA_DB);
       b.Jy = grid(AA_DB + 1);
       b.jscale = i2h;
-      if ((st0 = plasma(k_ar_pred<R>, b, none)) != QSA_OK) return st0;
+      b.tile_bytes = tile_big;
+      if ((st0 = plasma(k_ar_pred<R>, b, none, b.tile_bytes)) != QSA_OK) return st0;
       bcur[0] = bnew[0];
       bcur[1] = bnew[1];
     }
@@ -495,7 +506,7 @@ struct Adj {
       SideB sd(this);
       sd.lin(srcb(1, j), 1, {{JB[0], 1.0}}).lin(srcb(2, j), 1, {{JB[1], 1.0}});
       sd.lin(srcb(3, j), 1, {{grid(AA_JZ), 1.0}}, ao + 2, 1.0);
-      if ((st0 = plasma(k_ar_jstage<R>, b, sd.s)) != QSA_OK) return st0;
+      if ((st0 = plasma(k_ar_jstage<R>, b, sd.s, b.tile_bytes)) != QSA_OK) return st0;
     }
     // psi stage: adjoint of S (and of the beam's rho - J_z), of psi0
     {
@@ -509,14 +520,14 @@ struct Adj {
       s.term(o, SK_IKY_K2, f2, 1.0);
       s.dest(o, grid(AA_S), 1.0, 0);
       s.dest(o, srcb(0, j), 1.0, 1);
-      s.op.insum = ao + 1;
+      s.op.insum = psipart();
       if ((st0 = spec(s, none, none, none)) != QSA_OK) return st0;
     }
     {
       AdjPlasma<R> b = a;
       b.Sb = grid(AA_S);
       for (int q = 0; q < 4; ++q) b.Yn[q] = yout[q];
-      if ((st0 = plasma(k_ar_jstage<R>, b, none)) != QSA_OK) return st0;
+      if ((st0 = plasma(k_ar_jstage<R>, b, none, b.tile_bytes)) != QSA_OK) return st0;
     }
     return QSA_OK;
   }
@@ -594,6 +605,7 @@ struct Adj {
     b.fields = fields(t);
     b.fieldsb = c->at<R>(A.fb);
     for (int k = 0; k < 7; ++k) b.b[k] = c->at<R>(A.bb[s][k]);
+    b.tile_bytes = tile_small;
     return b;
   }
 
@@ -603,7 +615,8 @@ struct Adj {
     if (st0 != QSA_OK) return st0;
     for (int s = 0; s < p.n_species; ++s) {
       if (c->beam_n[s] == 0) continue;
-      hipLaunchKernelGGL(k_ab_sources<R>, dim3(blocks(c->beam_n[s])), dim3(256), 0, st(), beam_args(t, s));
+      hipLaunchKernelGGL(k_ab_sources<R>, dim3(blocks(c->beam_n[s])), dim3(256), (size_t)tile_small, st(),
+                         beam_args(t, s));
     }
     hipLaunchKernelGGL(k_slice_sums<R>, dim3(p.nxi), dim3(256), 0, st(), (const R*)src(3, 0), (int)nperp, jzsum());
     HIP_OK(hipGetLastError());
@@ -618,6 +631,19 @@ struct Adj {
       if (cols_lds > 65536)
         HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spec_cols<R>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)cols_lds));
+      // the plasma transposes scatter 12-13 channels: one block per CU
+      // holds the launch anyway (256 particles per block), so their tile
+      // takes most of the CU's LDS
+      int dev = 0, optin = 0;
+      HIP_OK(hipGetDevice(&dev));
+      if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
+      tile_big = std::max(tile_small, std::min(133120, optin));
+      if (tile_big > 65536) {
+        HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ar_final<R>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, tile_big));
+        HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_ar_pred<R>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, tile_big));
+      }
     }
     if ((st0 = lin(grid(AG_ZERO), 0, {}, nperp)) != QSA_OK) return st0;
     // step 0: the current beam with scaled weights
@@ -670,7 +696,7 @@ struct Adj {
         if ((st0 = lin(c->at<R>(A.fb), 0, {}, N_STORED * plane)) != QSA_OK) return st0;
         for (int s = 0; s < p.n_species; ++s) {
           if (c->beam_n[s] == 0) continue;
-          hipLaunchKernelGGL(k_ab_push_adj<R>, dim3(blocks(c->beam_n[s])), dim3(256), 0, st(),
+          hipLaunchKernelGGL(k_ab_push_adj<R>, dim3(blocks(c->beam_n[s])), dim3(256), (size_t)tile_small, st(),
                              beam_args(t - 1, s));
         }
       }
