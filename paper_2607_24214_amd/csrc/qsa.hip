@@ -60,7 +60,7 @@ struct AdjLayout {
   size_t fields = 0, biter = 0, src = 0, srcb = 0, fb = 0;
   size_t ck = 0, ck_bytes = 0;
   size_t segY = 0, segYt = 0, Y[2] = {}, Yb[2] = {};
-  size_t grids = 0, work = 0, sc = 0, sums = 0, part = 0, grad = 0, amps = 0;
+  size_t grids = 0, work = 0, ktab = 0, sc = 0, sums = 0, part = 0, grad = 0, amps = 0;
 };
 
 
@@ -103,6 +103,7 @@ void adjoint_layout(const qsa_params& p, size_t& off, AdjLayout& A) {
   }
   A.grids = take((size_t)AG_COUNT * nperp * rs);
   A.work = take((size_t)SPEC_IN * nperp * 2 * rs);
+  A.ktab = take((size_t)(p.nx / 2 + 1) * p.ny * 4 * sizeof(double));
   A.sc = take(64 * sizeof(double));
   A.sums = take(2 * (size_t)p.nxi * sizeof(double));
   A.part = take(((np + 255) / 256 + (size_t)p.ny) * sizeof(double));   // per-block / per-row partial sums

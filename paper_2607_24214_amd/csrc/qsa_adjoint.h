@@ -210,7 +210,7 @@ struct SpecOp {
   const double* mean[SPEC_OUT];     // k = 0 value (the result's mean), or null
   double* insum;                    // [ny] per-row sums of input 0, or null
   int conj;                         // 1: the transpose (conjugate multipliers)
-  double kappa2;
+  const double* ktab;               // multiplier tables (k_spec_table)
   C2<R>* work;                      // [max(ni, no)][ny][nx] complex scratch
 };
 
@@ -222,11 +222,28 @@ __device__ __forceinline__ void axis_k(int m, int n, double L, double& k, double
   kd = (n > 1 && (n & 1) == 0 && m == n / 2) ? 0.0 : k;
 }
 
-__device__ __forceinline__ void spec_mult(int kind, double c, double kx, double kdx, double ky, double kdy,
-                                          double kappa2, bool conj, double& re, double& im) {
-  const double k2 = kx * kx + ky * ky;
-  const double ik2 = (k2 == 0.0) ? 0.0 : 1.0 / k2;
-  const double den = 1.0 / (-k2 - kappa2);
+// Multiplier tables of the half spectrum, [kx <= nx/2][ky][4] =
+// (1/|k|^2 (0 at k = 0), 1/(-|k|^2 - kappa^2), kdx, kdy); one block per kx.
+template <typename R>
+__global__ void __launch_bounds__(256) k_spec_table(Geo<R> g, double kappa2, double* __restrict__ tab) {
+  const int kx = blockIdx.x;
+  double kxv, kdx;
+  axis_k(kx, g.nx, (double)g.nx * (double)g.dx, kxv, kdx);
+  for (int ky = threadIdx.x; ky < g.ny; ky += blockDim.x) {
+    double kyv, kdy;
+    axis_k(ky, g.ny, (double)g.ny * (double)g.dy, kyv, kdy);
+    const double k2 = kxv * kxv + kyv * kyv;
+    double* t = tab + ((int64_t)kx * g.ny + ky) * 4;
+    t[0] = (k2 == 0.0) ? 0.0 : 1.0 / k2;
+    t[1] = 1.0 / (-k2 - kappa2);
+    t[2] = kdx;
+    t[3] = kdy;
+  }
+}
+
+__device__ __forceinline__ void spec_mult(int kind, double c, const double (&t)[4], bool conj, double& re,
+                                          double& im) {
+  const double ik2 = t[0], den = t[1], kdx = t[2], kdy = t[3];
   re = 0.0;
   im = 0.0;
   switch (kind) {
@@ -297,17 +314,15 @@ __global__ void __launch_bounds__(64 * SPEC_IN) k_spec_cols(Geo<R> g, SpecOp<R> 
   const bool inA = (r == A);
   auto res = [&](int f) -> const C2<R>* { return tw + g.ny + (int64_t)(2 * f + (inA ? 0 : 1)) * g.ny; };
   C2<R>* S = inA ? B : A;   // free buffer of this wavefront
-  double kxv, kdx;
-  axis_k(kx, g.nx, (double)g.nx * (double)g.dx, kxv, kdx);
   const double N = (double)g.nperp;
   if (w < op.no) {
     for (int ky = t; ky < g.ny; ky += 64) {
-      double kyv, kdy;
-      axis_k(ky, g.ny, (double)g.ny * (double)g.dy, kyv, kdy);
+      const double* tp = op.ktab + ((int64_t)kx * g.ny + ky) * 4;
+      const double tk[4] = {tp[0], tp[1], tp[2], tp[3]};
       double ar = 0.0, ai = 0.0;
       for (int q = 0; q < op.nterm[w]; ++q) {
         double mr, mi;
-        spec_mult(op.kind[w][q], op.coef[w][q], kxv, kdx, kyv, kdy, op.kappa2, op.conj != 0, mr, mi);
+        spec_mult(op.kind[w][q], op.coef[w][q], tk, op.conj != 0, mr, mi);
         const C2<R> v = res(op.src[w][q])[ky];
         ar += mr * (double)v.x - mi * (double)v.y;
         ai += mr * (double)v.y + mi * (double)v.x;

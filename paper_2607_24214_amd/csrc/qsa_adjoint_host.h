@@ -181,7 +181,7 @@ struct Adj {
   qsa_status spec(SpecB& b, const Side<R>& s_rows, const Side<R>& s_cols, const Side<R>& s_inv) {
     if (overflow) return fail(c, QSA_E_INVALID, "adjoint: operator description overflow");
     SpecOp<R>& op = b.op;
-    op.kappa2 = p.kappa2;
+    op.ktab = c->at<double>(A.ktab);
     op.work = c->at<C2<R>>(A.work);
     const int W = std::max(op.ni, op.no);
     const size_t rows_lds = 3 * (size_t)g.nx * sizeof(C2<R>);
@@ -646,6 +646,7 @@ struct Adj {
       }
     }
     if ((st0 = lin(grid(AG_ZERO), 0, {}, nperp)) != QSA_OK) return st0;
+    hipLaunchKernelGGL(k_spec_table<R>, dim3(g.nx / 2 + 1), dim3(256), 0, st(), g, p.kappa2, c->at<double>(A.ktab));
     // step 0: the current beam with scaled weights
     for (int s = 0; s < p.n_species; ++s) {
       const int64_t n = c->beam_n[s];
