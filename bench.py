@@ -12,8 +12,9 @@ k - 1 in the same launches); the results equal those of one step at a time.
 
 Prints one JSON line (rank 0) with the measured rate, a roofline entry for
 the dominant kernel (timed with HIP events on the library's stream inside
-the timed region) and the float64 oracle timed on a bounded sample of the
-same workload on the host cores.
+the timed region), the float64 oracle timed on a bounded sample of the
+same workload on the host cores, and the adjoint/forward time of the
+gradient workload (128 x 128 x 256, float32, 20 beam steps, 64 bins).
 """
 from __future__ import annotations
 
@@ -115,6 +116,63 @@ def cpu_baseline(wl, n_slices: int):
     }
 
 
+def adjoint_ratio(steps_in_flight: int):
+    """adjoint/forward time on the adjoint workload (128 x 128 x 256, float32,
+    20 beam steps, 64 xi bins, plasma checkpoints every 16 slices): the time
+    of one qsa_adjoint_sweep (its checkpointed forward pass, the reverse
+    pass and the bin gradient) over that of the forward alone (20 beam
+    steps and the sweep of the last, steps in flight as in the main run).
+    Each is timed on its second call (the first captures graphs and loads
+    code)."""
+    import numpy as np
+    import torch
+    import qsa_workloads as W
+    import paper_2607_24214_amd as Q
+    wl = W.adjoint128()
+    steps = wl.steps
+    plasma = W.plasma_template(wl)
+    beams = W.beam(wl)
+    bins = [b["bin"] for b in beams]
+    amps = np.ones(wl.n_bins)
+    sim = Q.Sim(Q.params_from_workload(wl, precision="f32", pipeline=steps_in_flight, adjoint_steps=steps))
+    sim.load_plasma(plasma)
+    fwd = []
+    for _ in range(2):
+        for k, b in enumerate(beams):
+            sim.load_beam(k, b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.beam_step(steps)
+        sim.slice_sweep()
+        torch.cuda.synchronize()
+        fwd.append(time.perf_counter() - t0)
+    for k, b in enumerate(beams):
+        sim.load_beam(k, b)
+    adj = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss, grad = sim.adjoint_sweep(steps, amps, bins)
+        torch.cuda.synchronize()
+        adj.append(time.perf_counter() - t0)
+    if not (math.isfinite(loss) and np.all(np.isfinite(grad))):
+        raise RuntimeError("adjoint produced non-finite values")
+    out = {
+        "metric": "adjoint/forward time",
+        "value": adj[-1] / fwd[-1],
+        "higher_is_better": False,
+        "adjoint_ms": 1e3 * adj[-1],
+        "forward_ms": 1e3 * fwd[-1],
+        "dtype": "f32",
+        "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nxi": wl.nxi, "beam_steps": steps,
+                   "bins": wl.n_bins, "checkpoint_every_slices": wl.ckpt_every, "n_corr": wl.n_corr,
+                   "forward_steps_in_flight": sim.pipeline},
+    }
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +193,10 @@ def main():
                     help="only run a plain device copy of 2 GiB three times (scale for HBM counters)")
     ap.add_argument("--breakdown", action="store_true",
                     help="also time every kernel class over one extra group of steps each")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward time of the 128x128x256 adjoint workload")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only measure the adjoint/forward time (its own JSON line)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -156,6 +218,11 @@ def main():
     import qsa_workloads as W
     import paper_2607_24214_amd as Q
 
+    if args.adjoint_only:
+        adj = adjoint_ratio(args.pipeline)
+        print(json.dumps(dict(adj, n_gpus=1, data="synthetic (seeded PCG64 plasma lattice + flat-top beam)")),
+              flush=True)
+        return
     wl = W.CONFIGS[args.workload]().with_(precision=args.precision)
     rsize = 8 if args.precision == "f64" else 4
     log(f"workload {wl.name}: {wl.nx}x{wl.ny}x{wl.nxi}, plasma {wl.n_plasma}/slice, "
@@ -257,6 +324,14 @@ def main():
         "alg_bytes_per_launch": per_launch,
         "slices_per_launch": lane_slices / max(dom_n, 1),
     }
+    adjoint = None
+    if not args.no_adjoint:
+        del sim
+        torch.cuda.empty_cache()
+        log("adjoint workload ...")
+        adjoint = adjoint_ratio(depth)
+        log(f"adjoint {adjoint['adjoint_ms']:.0f} ms / forward {adjoint['forward_ms']:.0f} ms "
+            f"= {adjoint['value']:.2f}")
     cpu = None
     if not args.no_cpu_baseline:
         log(f"oracle baseline on {args.cpu_slices} slices ...")
@@ -284,6 +359,7 @@ def main():
         "sweep_only": {"ms": 1e3 * t_sweep, "updates_per_s": wl.n_plasma * wl.nxi / t_sweep},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "adjoint": adjoint,
     }
     if breakdown:
         out["kernel_breakdown_ms_per_step"] = {k: round(v["ms_per_step"], 3) for k, v in breakdown.items()}
