@@ -68,9 +68,9 @@ def alg_bytes(kclass: str, wl, rsize: int) -> float:
     npl = wl.n_plasma
     ng = wl.nx * wl.ny
     R = rsize
-    if kclass == "push_pred":     # read x,y,ux,uy; read F^j, F^{j-1} (6+6), psi^{j-2}; write 2 deposits
+    if kclass == "push_pred":     # read x,y,ux,uy; read F^j and F^{j+1/2} (6+6), psi extrapolated; write 2 deposits
         return 4 * R * npl + (13 + 2) * R * ng
-    if kclass == "push_final":    # read and write x,y,ux,uy; read F^j, F^{j-1}
+    if kclass == "push_final":    # read and write x,y,ux,uy; read F^j and F^{j+1/2}
         return 8 * R * npl + 12 * R * ng
     if kclass == "dep_S":
         return 2 * R * npl + R * ng

@@ -117,7 +117,7 @@ void adjoint_layout(const qsa_params& p, size_t& off, AdjLayout& A) {
 struct SetLayout {
   size_t pl[4], pl2[4];
   size_t cell_of, count, bsum, prow, ppart;
-  size_t src, fields, dep, rowspec, colout, jring, jz, bring, ode;
+  size_t src, fields, half, dep, rowspec, colout, jring, jz, bring, ode;
   size_t ring;   // slab ring of the deposits this set receives from the lane before it
   size_t hist;   // new-row count matrix of this set's slab pushes, and row starts
   size_t base;
@@ -178,6 +178,7 @@ Layout make_layout(const qsa_params& p) {
     S.ppart = c.take((size_t)p.ny * 4 * 3 * p.nx * rs);
     S.src = c.take(4 * (size_t)p.nxi * nperp * rs);
     S.fields = c.take((size_t)N_STORED * p.nxi * nperp * rs);
+    S.half = c.take((size_t)N_HALF * nperp * rs);
     S.dep = c.take(3 * nperp * rs);
     S.rowspec = c.take(4 * spec);
     S.colout = c.take(4 * spec);
@@ -619,6 +620,7 @@ struct Engine {
     a.h = (R)p.dxi;
     a.kappa2 = (R)p.kappa2;
     a.fields = c->at<R>(S.fields);
+    a.half = c->at<R>(S.half);
     a.src = c->at<R>(S.src);
     for (int i = 0; i < 4; ++i) {
       a.tmpl[i] = c->at<R>(L.tmpl[i]);
@@ -850,10 +852,10 @@ struct Engine {
       if ((st = tick(c, c->stream, lanes, d, t)) != QSA_OK) return st;
       if (t < QSA_PUSH_LAG) continue;
       QSA_LAUNCH(c, QSA_K_BEAM_PUSH, k_pipe_push<R>, dim3(g.ny, 1, n), dim3(256), 0, c->stream, pipes, t, n);
-      hipLaunchKernelGGL(k_pipe_scan<R>, dim3(1, 1, n - 1), dim3(512), 0, c->stream, pipes, t, n);
+      hipLaunchKernelGGL(k_pipe_scan<R>, dim3(g.ny, 1, n - 1), dim3(256), 0, c->stream, pipes, t, n);
       hipLaunchKernelGGL(k_pipe_place<R>, dim3(g.ny, 1, n - 1), dim3(256), 0, c->stream, pipes, t, n);
-      QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_pipe_deposit<R>, dim3(g.ny, 1, n - 1), dim3(256), tile, c->stream, pipes,
-                 t, n);
+      QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_pipe_deposit<R>, dim3(g.ny, 1, n - 1), dim3(256),
+                 tile + (g.ny + 1 + 16) * sizeof(int), c->stream, pipes, t, n);
       hipLaunchKernelGGL(k_pipe_reduce<R>, dim3(nperp_blocks, 1, n - 1), dim3(256), 0, c->stream, pipes, t, n);
     }
     HIP_OK(hipGetLastError());
@@ -1023,6 +1025,12 @@ struct Engine {
     HIP_OK(hipDeviceGetAttribute(&plain, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const int limit = std::max(optin, plain);
     static_assert(2 * 2 * 4 * 512 * 8 <= 65536, "beam tile");
+    // pipelined beam deposit: its tile, then row starts and scan scratch
+    const int pipe = 2 * 2 * 4 * c->p.nx * (int)sizeof(R) + (c->p.ny + 1 + 16) * (int)sizeof(int);
+    if (pipe > limit) return fail(c, QSA_E_INVALID, "nx too large for the device's LDS");
+    if (pipe > 65536)
+      HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pipe_deposit<R>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, pipe));
     // column transforms: (2G + 1) columns of ny complex values per block
     const int colj = (2 * ColShape<COL_J>::G + 1) * c->p.ny * (int)sizeof(C2<R>);
     if (colj > limit) return fail(c, QSA_E_INVALID, "ny too large for the device's LDS");

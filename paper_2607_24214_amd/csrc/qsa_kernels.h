@@ -21,6 +21,11 @@ namespace qsa {
 enum { COL_PSI = 0, COL_J = 1, COL_B = 2 };
 // stored field slots
 enum { F_PSI = 0, F_DXPSI = 1, F_DYPSI = 2, F_EZ = 3, F_BX = 4, F_BY = 5, F_BZ = 6, N_STORED = 7 };
+// grids of the current slice the plasma pushes gather: the six pushed
+// fields at j + 1/2, (3 F^j - F^{j-1})/2 (H_PSI .. H_BZ, in the order of
+// PlasmaArgs::F0), and psi extrapolated to j + 1, 3 psi^j - 3 psi^{j-1} +
+// psi^{j-2} (H_PSIT); written by the inverse row transforms with the fields
+enum { H_PSI = 0, H_DXPSI, H_DYPSI, H_BX, H_BY, H_BZ, H_PSIT, N_HALF };
 enum { ERR_BREAKDOWN = 1, ERR_DRIFT = 2 };
 
 #define QSA_GMIN 1.0e-3
@@ -46,6 +51,7 @@ struct Lane {
   R h;                  // dxi
   R kappa2;             // Helmholtz shift of the B_perp iteration
   R* fields;            // [7][nxi][ny][nx]
+  R* half;              // [N_HALF][ny][nx] of the slice being swept
   const R* src;         // beam sources [4][nxi][ny][nx]
   const R* tmpl[4];     // plasma template x, y, ux, uy
   const C2<R>* twx;     // transform tables
@@ -310,6 +316,19 @@ __device__ __forceinline__ int stage_slot(int stage, int f) {
   return f == 0 ? F_BX : F_BY;
 }
 
+// slot in Lane::half of a stored field (-1: E_z, not pushed with)
+__device__ __forceinline__ int half_slot(int so) {
+  switch (so) {
+    case F_PSI: return H_PSI;
+    case F_DXPSI: return H_DXPSI;
+    case F_DYPSI: return H_DYPSI;
+    case F_BX: return H_BX;
+    case F_BY: return H_BY;
+    case F_BZ: return H_BZ;
+    default: return -1;
+  }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_row_c2r(const Lane<R>* __restrict__ lanes, int tick, int stage) {
   const Lane<R>& L = lanes[blockIdx.z];
@@ -362,6 +381,26 @@ __global__ void __launch_bounds__(256) k_row_c2r(const Lane<R>* __restrict__ lan
       const C2<R> z = res[i];
       out[r0 * g.nx + i] = z.x;
       if (v1) out[r1 * g.nx + i] = z.y;
+    }
+    // the pushed fields at j + 1/2 (and psi extrapolated to j + 1)
+    const int so = stage_slot(stage, f);
+    const int hs = half_slot(so);
+    if (hs >= 0) {
+      R* hp = L.half + (size_t)hs * g.nperp;
+      const R* m1 = (j >= 1) ? outp - g.nperp : nullptr;
+      const R* m2 = (j >= 2) ? outp - 2 * g.nperp : nullptr;
+      R* pt = L.half + (size_t)H_PSIT * g.nperp;
+      for (int i = t; i < g.nx; i += tpt) {
+        const C2<R> z = res[i];
+        for (int k = 0; k < 2; ++k) {
+          if (k == 1 && !v1) break;
+          const int o = (k ? r1 : r0) * g.nx + i;
+          const R v = k ? z.y : z.x;
+          const R a = m1 ? m1[o] : R(0);
+          hp[o] = R(1.5) * v - R(0.5) * a;
+          if (so == F_PSI) pt[o] = R(3) * v - R(3) * a + (m2 ? m2[o] : R(0));
+        }
+      }
     }
   }
 }
@@ -550,8 +589,8 @@ struct PlasmaArgs {
   R* dep1;
   R* dep2;
   const R* F0[6];     // psi, d_x psi, d_y psi, B_x, B_y, B_z at slice j
-  const R* F1[6];     // the same at j-1 (all null when j = 0)
-  const R* psi_m2;    // psi at j-2 (null when j < 2)
+  const R* H[6];      // the six at j + 1/2: (3 F^j - F^{j-1})/2
+  const R* psit;      // psi extrapolated to j + 1
   int* err;
   R h;
   const int* prow;    // [ny + 1] first particle of each cell row (state sorted by cell)
@@ -574,11 +613,9 @@ __device__ __forceinline__ PlasmaArgs<R> plasma_args(const Lane<R>& L, int j) {
   a.dep1 = L.dep + g.nperp;
   a.dep2 = L.dep + 2 * g.nperp;
   const int fs[6] = {F_PSI, F_DXPSI, F_DYPSI, F_BX, F_BY, F_BZ};
-  for (int q = 0; q < 6; ++q) {
-    a.F0[q] = L.fields + fs[q] * plane + (int64_t)j * g.nperp;
-    a.F1[q] = (j >= 1) ? L.fields + fs[q] * plane + (int64_t)(j - 1) * g.nperp : nullptr;
-  }
-  a.psi_m2 = (j >= 2) ? L.fields + F_PSI * plane + (int64_t)(j - 2) * g.nperp : nullptr;
+  for (int q = 0; q < 6; ++q) a.F0[q] = L.fields + fs[q] * plane + (int64_t)j * g.nperp;
+  for (int q = 0; q < 6; ++q) a.H[q] = L.half + (size_t)q * g.nperp;
+  a.psit = L.half + (size_t)H_PSIT * g.nperp;
   a.err = L.err;
   a.h = L.h;
   a.prow = L.prow;
@@ -610,7 +647,8 @@ __device__ __forceinline__ void plasma_rhs(const R f[6], R ux, R uy, R d[4], int
   d[3] = gam * f[2] * iG + f[3] + ux * f[5] * iG;
 }
 
-// RK2 (midpoint) push from slice j with F^j and F^{j+1/2} = (3F^j - F^{j-1})/2.
+// RK2 (midpoint) push from slice j with F^j and F^{j+1/2} = (3F^j - F^{j-1})/2
+// (the latter gathered from its grids).
 template <typename R>
 __device__ __forceinline__ void rk2_push(const Geo<R>& g, const PlasmaArgs<R>& a, R x, R y, R ux,
                                          R uy, R& xn, R& yn, R& uxn, R& uyn) {
@@ -628,13 +666,8 @@ __device__ __forceinline__ void rk2_push(const Geo<R>& g, const PlasmaArgs<R>& a
   const R uys = uy + R(0.5) * hh * d1[3];
   {
     const Stencil<R> s = stencil2(g, xs, ys);
-    if (a.F1[0]) {
 #pragma unroll
-      for (int q = 0; q < 6; ++q) f[q] = R(0.5) * (R(3) * gather(a.F0[q], s) - gather(a.F1[q], s));
-    } else {
-#pragma unroll
-      for (int q = 0; q < 6; ++q) f[q] = R(0.5) * (R(3) * gather(a.F0[q], s));
-    }
+    for (int q = 0; q < 6; ++q) f[q] = gather(a.H[q], s);
     plasma_rhs(f, uxs, uys, d2, a.err);
   }
   xn = x + hh * d2[0];
@@ -746,10 +779,7 @@ __global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__
       R uxn, uyn;
       rk2_push(g, a, a.x[p], a.y[p], a.ux[p], a.uy[p], px, py, uxn, uyn);
       const Stencil<R> s = stencil2(g, px, py);
-      R pt = R(3) * gather(a.F0[0], s);
-      if (a.F1[0]) pt -= R(3) * gather(a.F1[0], s);
-      if (a.psi_m2) pt += gather(a.psi_m2, s);
-      const R G = R(1) + pt;
+      const R G = R(1) + gather(a.psit, s);
       if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
       const R qg = a.q / G;
       v[0] = qg * uxn;
@@ -1109,6 +1139,24 @@ __device__ __forceinline__ void tile_add(R* __restrict__ tile, int nx, int j0, i
   }
 }
 
+// Add the accumulated nodes of cell column i (node slices j0, j0+1 x node
+// rows l, l+1 x columns i, i+1 x 4 sources) to a tile as tile_add lays out.
+template <typename R>
+__device__ __forceinline__ void tile_add_cell(R* __restrict__ tile, int nx, int i, const R (&acc)[2][2][2][4]) {
+  const int i1 = (i + 1 == nx) ? 0 : i + 1;
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      R* tt = tile + ((d * 2 + e) * 4) * nx;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        atomicAdd(tt + c * nx + i, acc[d][e][0][c]);
+        atomicAdd(tt + c * nx + i1, acc[d][e][1][c]);
+      }
+    }
+}
+
 // Beam deposit owned by cell rows b = (j, l): the block takes exactly the
 // particles of its row (through the permutation), adds them to an LDS tile
 // of node slices (j, j+1) x node rows (l, l+1) with LDS atomics and writes
@@ -1348,7 +1396,7 @@ struct PipeBeam {
   double xi_max;
   const R* fields;          // this lane's fields (the push)
   int* hist;                // [4 species][ny source rows][ny new rows]: counts, then slots
-  int* base;                // [4 species][ny + 1]: start of each new row in the slab
+  int* base;                // [4 species][ny + 1]: particles of each new row in the slab
   R* ring_next;             // next lane's slab ring [2][ny][2][2][4][nx]
   R* src_next;              // next lane's sources [4][nxi][ny][nx]
   int* err;
@@ -1479,39 +1527,50 @@ __global__ void __launch_bounds__(256) k_pipe_push(const PipeBeam<R>* __restrict
   if (bad) atomicOr(B.err, ERR_DRIFT);
 }
 
-// One block per lane: hist[l][L] <- first slot of source row l's particles
-// within new row L; base[L] <- start of new row L in the slab.
+// Exclusive prefix sums of n <= 2 blockDim.x values val(i), i < n, into
+// out[0..n] in LDS (out[n] = their total); ws: LDS scratch of blockDim.x/64
+// ints.  Every thread of the block calls this; it ends with a barrier.
+template <typename F>
+__device__ __forceinline__ void block_exclusive_scan(F val, int n, int* out, int* ws) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int a = (2 * t < n) ? val(2 * t) : 0;
+  const int b = (2 * t + 1 < n) ? val(2 * t + 1) : 0;
+  const int s = a + b;
+  int inc = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(inc, o);
+    if (lane >= o) inc += u;
+  }
+  if (lane == 63) ws[w] = inc;
+  __syncthreads();
+  int wb = 0;
+  for (int k = 0; k < w; ++k) wb += ws[k];
+  const int ex = wb + inc - s;
+  if (2 * t < n) out[2 * t] = ex;
+  if (2 * t + 1 < n) out[2 * t + 1] = ex + a;
+  if (t == (int)blockDim.x - 1) out[n] = wb + inc;
+  __syncthreads();
+}
+
+// Block L of a lane: the column of new row L in hist (its particles from
+// each source row l) becomes its exclusive prefix over l, i.e. the first
+// slot of source row l's particles within new row L; base[L] <- the row's
+// count (k_pipe_place and k_pipe_deposit form the row starts from these).
 template <typename R>
-__global__ void __launch_bounds__(512) k_pipe_scan(const PipeBeam<R>* __restrict__ tab, int tick, int nlanes) {
-  const int lane = blockIdx.z;
+__global__ void __launch_bounds__(256) k_pipe_scan(const PipeBeam<R>* __restrict__ tab, int tick, int nlanes) {
+  const int lane = blockIdx.z, L = blockIdx.x;
   if (lane + 1 >= nlanes) return;
   const PipeBeam<R>& B = tab[lane];
   const Geo<R>& g = B.g;
   const int jp = tick - B.lag - QSA_PUSH_LAG;
-  if (jp < 0 || jp > g.nxi - 2) return;
-  __shared__ int red[512];
-  const int L = threadIdx.x;
+  if (jp < 0 || jp > g.nxi - 2 || L >= g.ny) return;
+  __shared__ int col[513];
+  __shared__ int ws[16];
   for (int s = 0; s < B.ns; ++s) {
     int* h = B.hist + (int64_t)s * g.ny * g.ny;
-    int acc = 0;
-    if (L < g.ny) {
-      for (int l = 0; l < g.ny; ++l) {
-        const int c = h[(int64_t)l * g.ny + L];
-        h[(int64_t)l * g.ny + L] = acc;
-        acc += c;
-      }
-    }
-    red[L] = acc;
-    __syncthreads();
-    for (int o = 1; o < 512; o <<= 1) {
-      const int add = (L >= o) ? red[L - o] : 0;
-      __syncthreads();
-      red[L] += add;
-      __syncthreads();
-    }
-    int* base = B.base + s * (g.ny + 1);
-    if (L < g.ny) base[L] = red[L] - acc;
-    if (L == g.ny - 1) base[g.ny] = red[L];
+    block_exclusive_scan([&](int l) { return h[(int64_t)l * g.ny + L]; }, g.ny, col, ws);
+    for (int l = threadIdx.x; l < g.ny; l += blockDim.x) h[(int64_t)l * g.ny + L] = col[l];
+    if (threadIdx.x == 0) B.base[s * (g.ny + 1) + L] = col[g.ny];
     __syncthreads();
   }
 }
@@ -1527,10 +1586,13 @@ __global__ void __launch_bounds__(256) k_pipe_place(const PipeBeam<R>* __restric
   const int jp = tick - B.lag - QSA_PUSH_LAG;
   if (jp < 0 || jp > g.nxi - 2 || l >= g.ny) return;
   const int64_t row = (int64_t)jp * g.ny + l;
+  __shared__ int base[513];
+  __shared__ int ws[16];
   for (int s = 0; s < B.ns; ++s) {
     const int64_t s0 = B.rowoff[s][(int64_t)jp * g.ny];
     const int* h = B.hist + ((int64_t)s * g.ny + l) * g.ny;
-    const int* base = B.base + s * (g.ny + 1);
+    const int* cnt = B.base + s * (g.ny + 1);
+    block_exclusive_scan([&](int L) { return cnt[L]; }, g.ny, base, ws);
     const int64_t p1 = B.rowoff[s][row + 1];
     for (int64_t p = B.rowoff[s][row] + threadIdx.x; p < p1; p += blockDim.x) {
       const int t = B.tag[s][p];
@@ -1538,6 +1600,7 @@ __global__ void __launch_bounds__(256) k_pipe_place(const PipeBeam<R>* __restric
       const int L = t & 511;
       B.perm[s][s0 + base[L] + h[L] + (t >> 9)] = (int)p;
     }
+    __syncthreads();
   }
 }
 
@@ -1551,23 +1614,60 @@ __global__ void __launch_bounds__(256) k_pipe_deposit(const PipeBeam<R>* __restr
   const Geo<R>& g = B.g;
   const int jp = tick - B.lag - QSA_PUSH_LAG;
   if (jp < 0 || jp > g.nxi - 2 || L >= g.ny) return;
+  // LDS: the tile, then the row starts (ny + 1) and scan scratch (16)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
   const int tn = 2 * 2 * 4 * g.nx;
+  int* base = reinterpret_cast<int*>(tile + tn);
+  int* ws = base + g.ny + 1;
   for (int i = threadIdx.x; i < tn; i += blockDim.x) tile[i] = R(0);
   __syncthreads();
   for (int s = 0; s < B.ns; ++s) {
-    const int* base = B.base + s * (g.ny + 1);
+    const int* cnt = B.base + s * (g.ny + 1);
+    block_exclusive_scan([&](int l) { return cnt[l]; }, g.ny, base, ws);
     const int64_t s0 = B.rowoff[s][(int64_t)jp * g.ny];
-    const int64_t q1 = s0 + base[L + 1];
-    for (int64_t q = s0 + base[L] + threadIdx.x; q < q1; q += blockDim.x) {
+    const int64_t q0 = s0 + base[L], q1 = s0 + base[L + 1];
+    __syncthreads();
+    // each thread a contiguous run of the row's particles; the row keeps them
+    // in cell order, so consecutive particles of one cell (all are in slab
+    // jp and row L: only the column changes) add up in registers and the sum
+    // goes to the tile when the column changes
+    const int64_t run = (q1 - q0 + blockDim.x - 1) / blockDim.x;
+    const int64_t a0 = q0 + (int64_t)threadIdx.x * run;
+    const int64_t a1 = (a0 + run < q1) ? a0 + run : q1;
+    R acc[2][2][2][4];
+    int ci = -1;
+    for (int64_t q = a0; q < a1; ++q) {
       const int p = B.perm[s][q];
       int jc, i, lc;
       R fz, fy, fx, v[4];
       beam_sources_of(g, B.x[s][p], B.y[s][p], B.xi[s][p], B.ux[s][p], B.uy[s][p], B.uz[s][p],
                       B.zq[s] * B.w[s][p], B.inv_dxi, jc, i, lc, fz, fy, fx, v);
-      tile_add(tile, g.nx, jp, jc, i, fz, fy, fx, v);
+      if (i != ci) {
+        if (ci >= 0) tile_add_cell(tile, g.nx, ci, acc);
+        ci = i;
+#pragma unroll
+        for (int d = 0; d < 2; ++d)
+#pragma unroll
+          for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+              for (int c = 0; c < 4; ++c) acc[d][e][x][c] = R(0);
+      }
+      const R wz[2] = {R(1) - fz, fz}, wy[2] = {R(1) - fy, fy}, wx[2] = {R(1) - fx, fx};
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const R wc = wz[d] * wy[e];
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[d][e][x][c] += v[c] * wc * wx[x];
+        }
     }
+    if (ci >= 0) tile_add_cell(tile, g.nx, ci, acc);
   }
   __syncthreads();
   R* out = B.ring_next + ((int64_t)(jp & 1) * g.ny + L) * tn;
