@@ -1139,22 +1139,110 @@ __device__ __forceinline__ void tile_add(R* __restrict__ tile, int nx, int j0, i
   }
 }
 
-// Add the accumulated nodes of cell column i (node slices j0, j0+1 x node
-// rows l, l+1 x columns i, i+1 x 4 sources) to a tile as tile_add lays out.
+// Add the accumulated nodes of one cell (node slices t0, t0+1 of the tile,
+// t0 = the cell's slice minus the tile's first; node rows l, l+1; columns
+// i, i+1; 4 sources) to a tile as tile_add lays it out.
 template <typename R>
-__device__ __forceinline__ void tile_add_cell(R* __restrict__ tile, int nx, int i, const R (&acc)[2][2][2][4]) {
+__device__ __forceinline__ void tile_add_cell(R* __restrict__ tile, int nx, int t0, int i,
+                                              const R (&acc)[2][2][2][4]) {
   const int i1 = (i + 1 == nx) ? 0 : i + 1;
 #pragma unroll
-  for (int d = 0; d < 2; ++d)
+  for (int d = 0; d < 2; ++d) {
+    if (t0 + d < 0) continue;   // node slice -1 of a particle in front of the grid
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      R* tt = tile + ((d * 2 + e) * 4) * nx;
+      R* tt = tile + (((t0 + d) * 2 + e) * 4) * nx;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         atomicAdd(tt + c * nx + i, acc[d][e][0][c]);
         atomicAdd(tt + c * nx + i1, acc[d][e][1][c]);
       }
     }
+  }
+}
+
+// Deposit of a cell row's n particles into the row's tile, staged through
+// LDS in chunks of QSA_DEP_STAGE = QSA_DEP_RUN x 256: each thread computes
+// QSA_DEP_RUN particles' cell, offsets and sources from coalesced loads
+// (src(k, ...) for the row's k-th particle; t0 = the cell's slice minus the
+// tile's first, -1 or 0) and stores them transposed, so that thread t then
+// reads QSA_DEP_RUN consecutive particles of the chunk without bank
+// conflicts.  A row keeps its particles in cell order: equal-cell runs add
+// up in registers before the LDS atomics (fewer of them, on neighbouring
+// cells instead of eight lanes on one).
+// LDS: sval [7][QSA_DEP_STAGE] (fz, fy, fx, 4 sources), skey [QSA_DEP_STAGE].
+// Every thread of the 256-thread block calls this (it holds barriers).
+#define QSA_DEP_RUN 2
+#define QSA_DEP_STAGE (256 * QSA_DEP_RUN)
+template <typename R, typename Src>
+__device__ __forceinline__ void deposit_staged(R* __restrict__ tile, int nx, int64_t n, Src src, R* sval,
+                                               int* skey) {
+  constexpr int T = 256, C = QSA_DEP_STAGE, RUN = QSA_DEP_RUN;
+  const int t = threadIdx.x;
+  for (int64_t c0 = 0; c0 < n; c0 += C) {
+#pragma unroll
+    for (int k = 0; k < RUN; ++k) {
+      const int pc = k * T + t;
+      const int slot = (pc % RUN) * T + pc / RUN;
+      int key = -1;
+      if (c0 + pc < n) {
+        int t0, i;
+        R fz, fy, fx, v[4];
+        src(c0 + pc, t0, i, fz, fy, fx, v);
+        key = ((t0 + 1) << 16) | i;
+        sval[0 * C + slot] = fz;
+        sval[1 * C + slot] = fy;
+        sval[2 * C + slot] = fx;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sval[(3 + c) * C + slot] = v[c];
+      }
+      skey[slot] = key;
+    }
+    __syncthreads();
+    R acc[2][2][2][4];
+    int ck = -1;
+#pragma unroll
+    for (int r = 0; r < RUN; ++r) {
+      const int slot = r * T + t;
+      const int key = skey[slot];
+      if (key < 0) continue;
+      if (key != ck) {
+        if (ck >= 0) tile_add_cell(tile, nx, (ck >> 16) - 1, ck & 0xffff, acc);
+        ck = key;
+#pragma unroll
+        for (int d = 0; d < 2; ++d)
+#pragma unroll
+          for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+              for (int c = 0; c < 4; ++c) acc[d][e][x][c] = R(0);
+      }
+      const R fz = sval[0 * C + slot], fy = sval[1 * C + slot], fx = sval[2 * C + slot];
+      const R wz[2] = {R(1) - fz, fz}, wy[2] = {R(1) - fy, fy}, wx[2] = {R(1) - fx, fx};
+      R v[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = sval[(3 + c) * C + slot];
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const R wc = wz[d] * wy[e];
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[d][e][x][c] += v[c] * wc * wx[x];
+        }
+    }
+    if (ck >= 0) tile_add_cell(tile, nx, (ck >> 16) - 1, ck & 0xffff, acc);
+    __syncthreads();
+  }
+}
+
+// LDS bytes of a staged beam deposit beyond its tile
+template <typename R>
+__host__ __device__ constexpr int dep_stage_bytes() {
+  return QSA_DEP_STAGE * (7 * (int)sizeof(R) + (int)sizeof(int));
 }
 
 // Beam deposit owned by cell rows b = (j, l): the block takes exactly the
@@ -1163,24 +1251,26 @@ __device__ __forceinline__ void tile_add_cell(R* __restrict__ tile, int nx, int 
 // the tile out as the row's partial node rows.
 template <typename R>
 __global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a) {
+  // LDS: the tile, then the deposit stage
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
   const int b = blockIdx.x;
   const int jb = b / g.ny;
   const int tn = 2 * 2 * 4 * g.nx;
+  R* sval = tile + tn;
+  int* skey = reinterpret_cast<int*>(sval + 7 * QSA_DEP_STAGE);
   for (int t = threadIdx.x; t < tn; t += blockDim.x) tile[t] = R(0);
   __syncthreads();
   for (int s = 0; s < a.ns; ++s) {
     const int nxc = nx_chunks(g);
-    const int64_t q1 = a.doff[s][(int64_t)(b + 1) * nxc];
-    for (int64_t q = a.doff[s][(int64_t)b * nxc] + threadIdx.x; q < q1; q += blockDim.x) {
-      const int p = a.perm[s][q];
-      int jc, i, l;
-      R fz, fy, fx, v[4];
+    const int64_t q0 = a.doff[s][(int64_t)b * nxc], q1 = a.doff[s][(int64_t)(b + 1) * nxc];
+    deposit_staged(tile, g.nx, q1 - q0, [&](int64_t k, int& t0, int& i, R& fz, R& fy, R& fx, R (&v)[4]) {
+      const int p = a.perm[s][q0 + k];
+      int jc, l;
       beam_sources_of(g, a.x[s][p], a.y[s][p], a.xi[s][p], a.ux[s][p], a.uy[s][p], a.uz[s][p],
                       a.zq[s] * a.w[s][p], a.inv_dxi, jc, i, l, fz, fy, fx, v);
-      tile_add(tile, g.nx, jb, jc, i, fz, fy, fx, v);
-    }
+      t0 = jc - jb;
+    }, sval, skey);
   }
   __syncthreads();
   R* out = a.bpart + (int64_t)b * tn;
@@ -1282,12 +1372,21 @@ __global__ void __launch_bounds__(256) k_beam_reduce(Geo<R> g, const R* __restri
 // + B_y, -d_y psi - B_x, E_z), B = (B_x, B_y, B_z), 3D linear shape, zero
 // outside the xi grid.  Positions use the new momentum; dxi/dtau = 1 - v_z.
 // A particle reaching xi >= (nxi - 1) dxi leaves the box (weight 0).
+// State of a beam particle after its push (as stored), with gamma and
+// u_perp^2 at the new momentum.
 template <typename R>
-__device__ __forceinline__ void boris_one(const Geo<R>& g, const R* __restrict__ fields, R qh, R dt,
-                                          double inv_dxi, double xi_max, R* __restrict__ px,
-                                          R* __restrict__ py, double* __restrict__ pxi, R* __restrict__ pux,
-                                          R* __restrict__ puy, R* __restrict__ puz, R* __restrict__ pw,
-                                          int64_t p) {
+struct BeamNew {
+  R x, y, ux, uy, uz, gam, up2;
+  double xi;
+  bool lost;
+};
+
+template <typename R>
+__device__ __forceinline__ BeamNew<R> boris_one(const Geo<R>& g, const R* __restrict__ fields, R qh, R dt,
+                                                double inv_dxi, double xi_max, R* __restrict__ px,
+                                                R* __restrict__ py, double* __restrict__ pxi, R* __restrict__ pux,
+                                                R* __restrict__ puy, R* __restrict__ puz, R* __restrict__ pw,
+                                                int64_t p) {
   const R x = px[p], y = py[p];
   const double xi = pxi[p];
   R ux = pux[p], uy = puy[p], uz = puz[p];
@@ -1332,14 +1431,24 @@ __device__ __forceinline__ void boris_one(const Geo<R>& g, const R* __restrict__
   uz = uqz + qh * ez;
   const R up2 = ux * ux + uy * uy;
   const R gam = sqrt(R(1) + up2 + uz * uz);
-  px[p] = wrap_pos(x + dt * ux / gam, g.lx, g.inv_lx);
-  py[p] = wrap_pos(y + dt * uy / gam, g.ly, g.inv_ly);
-  const double xin = xi + (double)(dt * (R(1) + up2) / (gam * (gam + uz)));
-  pxi[p] = xin;
+  BeamNew<R> o;
+  o.x = wrap_pos(x + dt * ux / gam, g.lx, g.inv_lx);
+  o.y = wrap_pos(y + dt * uy / gam, g.ly, g.inv_ly);
+  o.xi = xi + (double)(dt * (R(1) + up2) / (gam * (gam + uz)));
+  o.ux = ux;
+  o.uy = uy;
+  o.uz = uz;
+  o.gam = gam;
+  o.up2 = up2;
+  o.lost = o.xi >= xi_max;
+  px[p] = o.x;
+  py[p] = o.y;
+  pxi[p] = o.xi;
   pux[p] = ux;
   puy[p] = uy;
   puz[p] = uz;
-  if (xin >= xi_max) pw[p] = R(0);
+  if (o.lost) pw[p] = R(0);
+  return o;
 }
 
 template <typename R>
@@ -1464,20 +1573,29 @@ __device__ __forceinline__ bool pipe_push_one(const PipeBeam<R>& B, int s, int64
     if (gz > -1.0 && gz < (double)g.nxi && gz >= (double)(jp + 3)) bad = true;
     if (feeds && B.w[s][p] != R(0) && gz < (double)(jp - 3)) bad = true;
   }
-  boris_one(g, B.fields, B.qmh[s], B.dt, B.inv_dxi, B.xi_max, B.x[s], B.y[s], B.xi[s], B.ux[s], B.uy[s], B.uz[s],
-            B.w[s], p);
+  const R w0 = B.w[s][p];
+  const BeamNew<R> n = boris_one(g, B.fields, B.qmh[s], B.dt, B.inv_dxi, B.xi_max, B.x[s], B.y[s], B.xi[s],
+                                 B.ux[s], B.uy[s], B.uz[s], B.w[s], p);
   if (!feeds) return bad;
-  const R w = B.w[s][p];
-  const double gn = B.xi[s][p] * B.inv_dxi;
+  const R w = n.lost ? R(0) : w0;
+  const double gn = n.xi * B.inv_dxi;
   const bool deposits = w != R(0) && gn > -1.0 && gn < (double)g.nxi;
   if (!slab) return bad || deposits;   // not deposited for the next lane: must carry nothing
   if (deposits) {
-    int jc, i, l;
-    R fz, fy, fx, v[4];
-    beam_sources_of(g, B.x[s][p], B.y[s][p], B.xi[s][p], B.ux[s][p], B.uy[s][p], B.uz[s][p], B.zq[s] * w,
-                    B.inv_dxi, jc, i, l, fz, fy, fx, v);
-    if (jc == jp) row = l;
-    else dense_add(g, B.src_next, jc, i, l, fz, fy, fx, v);
+    // its cell from the new state in registers; the sources only for a
+    // particle that left slab jp (deposited here, with atomics)
+    const int jc = (int)floor(gn);
+    int i, l;
+    R fx, fy;
+    cell2(g, n.x, n.y, i, l, fx, fy);
+    if (jc == jp) {
+      row = l;
+    } else {
+      const R qw = B.zq[s] * w;
+      const R v[4] = {qw * ((R(1) + n.up2) / (n.gam * (n.gam + n.uz))), qw * n.ux / n.gam, qw * n.uy / n.gam,
+                      qw * n.uz / n.gam};
+      dense_add(g, B.src_next, jc, i, l, (R)(gn - floor(gn)), fy, fx, v);
+    }
   }
   return bad;
 }
@@ -1614,11 +1732,13 @@ __global__ void __launch_bounds__(256) k_pipe_deposit(const PipeBeam<R>* __restr
   const Geo<R>& g = B.g;
   const int jp = tick - B.lag - QSA_PUSH_LAG;
   if (jp < 0 || jp > g.nxi - 2 || L >= g.ny) return;
-  // LDS: the tile, then the row starts (ny + 1) and scan scratch (16)
+  // LDS: the tile, the deposit stage, the row starts (ny + 1), scan scratch (16)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
   const int tn = 2 * 2 * 4 * g.nx;
-  int* base = reinterpret_cast<int*>(tile + tn);
+  R* sval = tile + tn;
+  int* skey = reinterpret_cast<int*>(sval + 7 * QSA_DEP_STAGE);
+  int* base = skey + QSA_DEP_STAGE;
   int* ws = base + g.ny + 1;
   for (int i = threadIdx.x; i < tn; i += blockDim.x) tile[i] = R(0);
   __syncthreads();
@@ -1628,46 +1748,13 @@ __global__ void __launch_bounds__(256) k_pipe_deposit(const PipeBeam<R>* __restr
     const int64_t s0 = B.rowoff[s][(int64_t)jp * g.ny];
     const int64_t q0 = s0 + base[L], q1 = s0 + base[L + 1];
     __syncthreads();
-    // each thread a contiguous run of the row's particles; the row keeps them
-    // in cell order, so consecutive particles of one cell (all are in slab
-    // jp and row L: only the column changes) add up in registers and the sum
-    // goes to the tile when the column changes
-    const int64_t run = (q1 - q0 + blockDim.x - 1) / blockDim.x;
-    const int64_t a0 = q0 + (int64_t)threadIdx.x * run;
-    const int64_t a1 = (a0 + run < q1) ? a0 + run : q1;
-    R acc[2][2][2][4];
-    int ci = -1;
-    for (int64_t q = a0; q < a1; ++q) {
-      const int p = B.perm[s][q];
-      int jc, i, lc;
-      R fz, fy, fx, v[4];
+    deposit_staged(tile, g.nx, q1 - q0, [&](int64_t k, int& t0, int& i, R& fz, R& fy, R& fx, R (&v)[4]) {
+      const int p = B.perm[s][q0 + k];
+      int jc, lc;
       beam_sources_of(g, B.x[s][p], B.y[s][p], B.xi[s][p], B.ux[s][p], B.uy[s][p], B.uz[s][p],
                       B.zq[s] * B.w[s][p], B.inv_dxi, jc, i, lc, fz, fy, fx, v);
-      if (i != ci) {
-        if (ci >= 0) tile_add_cell(tile, g.nx, ci, acc);
-        ci = i;
-#pragma unroll
-        for (int d = 0; d < 2; ++d)
-#pragma unroll
-          for (int e = 0; e < 2; ++e)
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-              for (int c = 0; c < 4; ++c) acc[d][e][x][c] = R(0);
-      }
-      const R wz[2] = {R(1) - fz, fz}, wy[2] = {R(1) - fy, fy}, wx[2] = {R(1) - fx, fx};
-#pragma unroll
-      for (int d = 0; d < 2; ++d)
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const R wc = wz[d] * wy[e];
-#pragma unroll
-          for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[d][e][x][c] += v[c] * wc * wx[x];
-        }
-    }
-    if (ci >= 0) tile_add_cell(tile, g.nx, ci, acc);
+      t0 = jc - jp;
+    }, sval, skey);
   }
   __syncthreads();
   R* out = B.ring_next + ((int64_t)(jp & 1) * g.ny + L) * tn;
