@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--pre-steps", type=int, default=0,
                     help="untimed beam steps after the warmup (time a more evolved beam)")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--col-threads", type=int, default=0,
+                    help="threads per column transform (16, 32, 64; 0 = the library's default)")
     ap.add_argument("--workload", default="cube256")
     ap.add_argument("--cpu-slices", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -239,12 +241,14 @@ def main():
     del beams
     if args.no_graphs:
         sim.set_graphs(False)
+    if args.col_threads:
+        sim.set_shapes(0, 0, args.col_threads)
     tuned = None
     if args.autotune:
         t = time.perf_counter()
         best = sim.autotune()
-        nt, rt = sim.shapes()
-        tuned = {"plasma_threads": nt, "row_threads": rt, "steps_in_flight": sim.pipeline,
+        nt, rt, ct = sim.shapes()
+        tuned = {"plasma_threads": nt, "row_threads": rt, "column_threads": ct, "steps_in_flight": sim.pipeline,
                  "best_trial_ms_per_step": best}
         log(f"autotune {time.perf_counter() - t:.1f} s: {tuned}")
     log(f"loaded; workspace {sim.ws_bytes / 2**30:.2f} GiB")

@@ -264,6 +264,8 @@ struct qsa_ctx {
   int pipe_max = 1;      // beam steps in flight when pipelining (<= L.nset)
   int tune_nt = 0;       // threads per plasma-row block (0: from the particles per row)
   int tune_rt = 0;       // threads per row-transform block (0: max(64, nx/4))
+  int tune_ct = 0;       // threads per column transform (0: QSA_COL_TPT)
+  int col_lds_max = 0;   // LDS the column passes may take (opted in)
   int cur_set = 0;       // working set holding the last sweep's sources and fields
   int64_t beam_n[QSA_MAX_SPECIES] = {0, 0, 0, 0};
   bool plasma_loaded = false;
@@ -691,6 +693,7 @@ struct Engine {
     int n = 0, nx = 0, ny = 0, nxi = 0, nxh = 0, np = 0, per_row = 0, n_corr = 0;
     int nt = 64;                      // plasma-row block size
     int rows_r2c = 0, rt_rows = 64;   // row-pass grid and block size
+    int ctpt = 0;                     // threads per column transform (0: default)
     int cols[3] = {0, 0, 0};          // column-pass grid per mode
     size_t smem_col[3] = {0, 0, 0};
     int64_t clear = 0;
@@ -707,7 +710,8 @@ struct Engine {
     const int64_t spec = (int64_t)p.ny * (p.nx / 2 + 1);
     d.clear = std::max<int64_t>(d.clear, std::max<int64_t>(6 * spec, 3 * (int64_t)p.nx * p.ny));
   }
-  static void finish_dims(Dims& d, const qsa_params* const* ps, int n, int nt = 0, int rt = 0) {
+  static void finish_dims(Dims& d, const qsa_params* const* ps, int n, int nt = 0, int rt = 0, int ct = 0) {
+    d.ctpt = (ct == 16 || ct == 32 || ct == 64) ? ct : 0;
     d.rt_rows = std::max(64, d.nx / 4);
     if (rt >= d.nx / 4 && rt % (d.nx / 4) == 0 && rt <= 256) d.rt_rows = rt;
     d.nt = std::max(64, std::min(256, (d.per_row + 63) / 64 * 64));
@@ -722,7 +726,7 @@ struct Engine {
       const qsa_params& p = *ps[i];
       const int ppw = d.rt_rows / (p.nx / 4);
       d.rows_r2c = std::max(d.rows_r2c, ((p.ny + 1) / 2 + ppw - 1) / ppw);
-      const int tpt = col_tpt(p.ny);
+      const int tpt = col_tpt(p.ny, d.ctpt);
       const int cpw = 64 / tpt;
       for (int m = 0; m < 3; ++m) {
         d.cols[m] = std::max(d.cols[m], (p.nx / 2 + 1 + cpw - 1) / cpw);
@@ -757,7 +761,7 @@ struct Engine {
                          4 * 1 * (size_t)d.nx * sizeof(R), st, lanes, j);
       QSA_LAUNCH(tc, QSA_K_ROW_R2C, k_row_r2c<R>, rgrid_psi, rblock, smem_rows, st, lanes, j, (int)ST_PSI);
       QSA_LAUNCH(tc, QSA_K_COL, (k_col<R, COL_PSI>), dim3(d.cols[0], 1, n), dim3(64 * ColShape<COL_PSI>::G),
-                         d.smem_col[0], st, lanes, j);
+                         d.smem_col[0], st, lanes, j, d.ctpt);
       QSA_LAUNCH(tc, QSA_K_ROW_C2R, k_row_c2r<R>, dim3(d.rows_r2c, 3, n), rblock, smem_rows, st, lanes, j,
                  (int)ST_PSI);
       // ---- J stage
@@ -765,7 +769,7 @@ struct Engine {
                          4 * 3 * (size_t)d.nx * sizeof(R), st, lanes, j);
       QSA_LAUNCH(tc, QSA_K_ROW_R2C, k_row_r2c<R>, rgrid_j, rblock, smem_rows, st, lanes, j, (int)ST_J);
       QSA_LAUNCH(tc, QSA_K_COL, (k_col<R, COL_J>), dim3(d.cols[1], 1, n), dim3(64 * ColShape<COL_J>::G),
-                         d.smem_col[1], st, lanes, j);
+                         d.smem_col[1], st, lanes, j, d.ctpt);
       QSA_LAUNCH(tc, QSA_K_ROW_C2R, k_row_c2r<R>, dim3(d.rows_r2c, 4, n), rblock, smem_rows, st, lanes, j, (int)ST_J);
       // ---- B_perp predictor-corrector
       for (int k = 0; k < d.n_corr; ++k) {
@@ -773,7 +777,7 @@ struct Engine {
                            4 * 2 * (size_t)d.nx * sizeof(R), st, lanes, j);
         QSA_LAUNCH(tc, QSA_K_ROW_R2C, k_row_r2c<R>, rgrid_b, rblock, smem_rows, st, lanes, j, (int)ST_B);
         QSA_LAUNCH(tc, QSA_K_COL, (k_col<R, COL_B>), dim3(d.cols[2], 1, n), dim3(64 * ColShape<COL_B>::G),
-                           d.smem_col[2], st, lanes, j);
+                           d.smem_col[2], st, lanes, j, d.ctpt);
         QSA_LAUNCH(tc, QSA_K_ROW_C2R, k_row_c2r<R>, rgrid_b, rblock, smem_rows, st, lanes, j, (int)ST_B);
       }
       // ---- advance the plasma to slice j+1
@@ -801,7 +805,7 @@ struct Engine {
     Dims d;
     add_dims(d, c->p);
     const qsa_params* ps[1] = {&c->p};
-    finish_dims(d, ps, 1, c->tune_nt, c->tune_rt);
+    finish_dims(d, ps, 1, c->tune_nt, c->tune_rt, c->tune_ct);
     return d;
   }
 
@@ -1018,6 +1022,12 @@ struct Engine {
   // Launch limits on LDS: beam tiles (2 node slices x 2 node rows x 4
   // sources x nx) stay within 64 KiB for nx <= 512; the column transforms of
   // tall grids opt in to more.
+  // LDS of the widest column pass (COL_J) with ct threads per transform
+  static int col_lds(int ny, int ct) {
+    const int cpw = 64 / col_tpt(ny, ct);
+    return (cpw * 2 * ColShape<COL_J>::G + 1) * ny * (int)sizeof(C2<R>);
+  }
+
   static qsa_status set_lds_limits(qsa_ctx* c) {
     int dev = 0, optin = 0, plain = 0;
     HIP_OK(hipGetDevice(&dev));
@@ -1036,9 +1046,13 @@ struct Engine {
     if (pipe > 65536)
       HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pipe_deposit<R>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, pipe));
-    // column transforms: (2G + 1) columns of ny complex values per block
-    const int colj = (2 * ColShape<COL_J>::G + 1) * c->p.ny * (int)sizeof(C2<R>);
+    // column transforms: (2 G cpw + 1) columns of ny complex values per
+    // block, cpw = 64 / threads per transform; the largest that fits
+    int colj = col_lds(c->p.ny, 64);
     if (colj > limit) return fail(c, QSA_E_INVALID, "ny too large for the device's LDS");
+    for (int ct = 32; ct >= 16; ct /= 2)
+      if (col_lds(c->p.ny, ct) <= limit) colj = std::max(colj, col_lds(c->p.ny, ct));
+    c->col_lds_max = colj;
     if (colj > 65536) {
       HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_col<R, COL_PSI>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, colj));
@@ -1427,6 +1441,17 @@ qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value) {
     c->drop_graphs();
     return QSA_OK;
   }
+  if (option == QSA_OPT_COL_THREADS) {
+    if (value != 0 && value != 16 && value != 32 && value != 64)
+      return fail(c, QSA_E_INVALID, "column threads must be 0, 16, 32 or 64");
+    const int need = (c->p.precision == QSA_FP32) ? Engine<float>::col_lds(c->p.ny, (int)value)
+                                                   : Engine<double>::col_lds(c->p.ny, (int)value);
+    if (need > c->col_lds_max)
+      return fail(c, QSA_E_INVALID, "column threads: the column pass would not fit the device's LDS");
+    c->tune_ct = (int)value;
+    c->drop_graphs();
+    return QSA_OK;
+  }
   return fail(c, QSA_E_INVALID, "unknown option");
 }
 
@@ -1475,6 +1500,19 @@ qsa_status qsa_autotune(qsa_ctx* c, double* ms_per_step) {
     }
   }
   c->tune_rt = best_rt;
+  // threads per column transform
+  int best_ct = c->tune_ct;
+  for (int ct = 64; ct >= 16 && st == QSA_OK; ct /= 2) {
+    const int need = (c->p.precision == QSA_FP32) ? Engine<float>::col_lds(c->p.ny, ct)
+                                                   : Engine<double>::col_lds(c->p.ny, ct);
+    if (need > c->col_lds_max) continue;
+    c->tune_ct = ct;
+    if ((st = run(depth0, &t)) == QSA_OK && t < best) {
+      best = t;
+      best_ct = ct;
+    }
+  }
+  c->tune_ct = best_ct;
   // beam steps in flight (per step)
   int best_depth = c->pipe_max;
   if (depth0 > 1) {
@@ -1547,12 +1585,14 @@ qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value) {
     *value = c->pipe_ok ? c->pipe_max : 1;
     return QSA_OK;
   }
-  if (option == QSA_OPT_PLASMA_THREADS || option == QSA_OPT_ROW_THREADS) {
+  if (option == QSA_OPT_PLASMA_THREADS || option == QSA_OPT_ROW_THREADS || option == QSA_OPT_COL_THREADS) {
     typename Engine<double>::Dims d;
     Engine<double>::add_dims(d, c->p);
     const qsa_params* ps[1] = {&c->p};
-    Engine<double>::finish_dims(d, ps, 1, c->tune_nt, c->tune_rt);
-    *value = (option == QSA_OPT_PLASMA_THREADS) ? d.nt : d.rt_rows;
+    Engine<double>::finish_dims(d, ps, 1, c->tune_nt, c->tune_rt, c->tune_ct);
+    *value = (option == QSA_OPT_PLASMA_THREADS) ? d.nt
+             : (option == QSA_OPT_ROW_THREADS)  ? d.rt_rows
+                                                : col_tpt(c->p.ny, d.ctpt);
     return QSA_OK;
   }
   return QSA_E_INVALID;

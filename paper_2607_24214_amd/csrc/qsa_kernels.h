@@ -432,10 +432,15 @@ struct ColShape {
   static constexpr int G = NIN > NOUT ? NIN : NOUT;   // thread groups per column
 };
 
-// Threads per column transform for ny rows (loops cover the rest).
-__host__ __device__ __forceinline__ int col_tpt(int ny) {
+// Threads per column transform for ny rows (loops cover the rest): want
+// (16, 32 or 64; 0 = QSA_COL_TPT) capped at ny/4.  A wavefront takes
+// 64 / threads adjacent columns, so fewer threads per transform read and
+// write longer runs of each spectral row.
+#define QSA_COL_TPT 32
+__host__ __device__ __forceinline__ int col_tpt(int ny, int want = 0) {
+  const int w = want > 0 ? want : QSA_COL_TPT;
   const int t = ny >> 2;
-  return t < 1 ? 1 : (t > 64 ? 64 : t);
+  return t < 1 ? 1 : (t > w ? w : t);
 }
 
 // Forward transform along y of each input column, the spectral solve of the
@@ -471,7 +476,7 @@ __device__ __forceinline__ ColArgs<R> col_args(const Lane<R>& L, int j) {
 }
 
 template <typename R, int MODE>
-__global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, int tick) {
+__global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, int tick, int ctpt) {
   using S = ColShape<MODE>;
   constexpr int G = S::G;
   const Lane<R>& L = lanes[blockIdx.z];
@@ -483,7 +488,7 @@ __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* sm = reinterpret_cast<C2<R>*>(smem_raw);
   const int ny = g.ny;
-  const int tpt = col_tpt(ny);
+  const int tpt = col_tpt(ny, ctpt);
   const int per_col = G * tpt;
   const int cpw = blockDim.x / per_col;
   if (blockIdx.x * cpw >= g.nxh) return;

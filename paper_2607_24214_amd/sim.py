@@ -144,15 +144,18 @@ class Sim:
         """Beam steps in flight (1 .. the pipeline parameter)."""
         self._check(self.lib.qsa_set_option(self.ctx, 1, int(depth)))
 
-    def set_shapes(self, plasma_threads: int = 0, row_threads: int = 0):
-        """Launch shapes (0 = default): threads per plasma-row block and per
-        row-transform block."""
+    def set_shapes(self, plasma_threads: int = 0, row_threads: int = 0, col_threads: int = 0):
+        """Launch shapes (0 = default): threads per plasma-row block, per
+        row-transform block and per column transform."""
         self._check(self.lib.qsa_set_option(self.ctx, 2, int(plasma_threads)))
         self._check(self.lib.qsa_set_option(self.ctx, 3, int(row_threads)))
+        self._check(self.lib.qsa_set_option(self.ctx, 4, int(col_threads)))
 
     def shapes(self):
+        """(threads per plasma-row block, per row-transform block, per column
+        transform) in use."""
         out = []
-        for opt in (2, 3):
+        for opt in (2, 3, 4):
             v = C.c_int64(0)
             self._check(self.lib.qsa_get_option(self.ctx, opt, C.byref(v)))
             out.append(int(v.value))

@@ -1,6 +1,7 @@
 """Launch shapes and the autotuner: every plasma-row and row-transform block
-width gives the same sweep (up to the order of additions), and autotuning
-leaves the beam untouched and later steps unchanged."""
+width and column-transform thread count gives the same sweep (up to the
+order of additions), and autotuning leaves the beam untouched and later
+steps unchanged."""
 import numpy as np
 import pytest
 
@@ -24,7 +25,7 @@ def test_launch_shapes_agree_fp64(nt, rt):
     wl = W.small_3d(64, 32, 16)
     ref, sim = _sim(wl), _sim(wl)
     sim.set_shapes(nt, rt)
-    assert sim.shapes() == (nt, rt)
+    assert sim.shapes()[:2] == (nt, rt)
     ref.slice_sweep()
     sim.slice_sweep()
     err, where = slice_errors({k: sim.fields(k) for k in OUT_FIELDS}, {k: ref.fields(k) for k in OUT_FIELDS})
@@ -32,12 +33,27 @@ def test_launch_shapes_agree_fp64(nt, rt):
     assert err <= 1e-12, (err, where)
 
 
+@pytest.mark.parametrize("ct", [16, 32, 64])
+def test_column_threads_agree_fp64(ct):
+    """ny = 256: 16, 32 or 64 threads per column transform (4, 2 or 1
+    columns per wavefront)."""
+    wl = W.small_3d(32, 256, 6)
+    ref, sim = _sim(wl), _sim(wl)
+    sim.set_shapes(0, 0, ct)
+    assert sim.shapes()[2] == ct
+    ref.slice_sweep()
+    sim.slice_sweep()
+    err, where = slice_errors({k: sim.fields(k) for k in OUT_FIELDS}, {k: ref.fields(k) for k in OUT_FIELDS})
+    print(f"[shapes] column threads {ct}: {err:.3e} at {where}", flush=True)
+    assert err <= 1e-12, (err, where)
+
+
 def test_invalid_shapes_rejected():
     import paper_2607_24214_amd as Q
     sim = _sim(W.small_3d(32, 16, 8))
-    for nt, rt in ((96, 0), (0, 32), (512, 0)):
+    for nt, rt, ct in ((96, 0, 0), (0, 32, 0), (512, 0, 0), (0, 0, 8), (0, 0, 128)):
         with pytest.raises(Q.QSAError):
-            sim.set_shapes(nt, rt)
+            sim.set_shapes(nt, rt, ct)
 
 
 def test_autotune_keeps_the_beam_and_the_physics_fp64():
@@ -52,8 +68,8 @@ def test_autotune_keeps_the_beam_and_the_physics_fp64():
     after = sim.read_beam(0)
     for k in before:
         assert np.array_equal(before[k], after[k]), k
-    nt, rt = sim.shapes()
-    assert nt in (64, 128, 256) and rt in (64, 128, 256)
+    nt, rt, ct = sim.shapes()
+    assert nt in (64, 128, 256) and rt in (64, 128, 256) and ct in (8, 16, 32, 64)
     assert sim.pipeline in (2, 4)
     with pytest.raises(Q.QSAError):
         sim.fields("psi")
