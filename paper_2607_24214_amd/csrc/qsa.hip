@@ -1053,6 +1053,7 @@ struct Engine {
     for (int ct = 32; ct >= 16; ct /= 2)
       if (col_lds(c->p.ny, ct) <= limit) colj = std::max(colj, col_lds(c->p.ny, ct));
     c->col_lds_max = colj;
+    if (c->tune_ct == 0 && col_lds(c->p.ny, QSA_COL_TPT) > colj) c->tune_ct = 64;   // the default does not fit
     if (colj > 65536) {
       HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_col<R, COL_PSI>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, colj));
