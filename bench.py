@@ -173,6 +173,50 @@ def adjoint_ratio(steps_in_flight: int):
     return out
 
 
+def scan_rate(n_inst: int, steps: int, warmup: int):
+    """Batched parameter scan (float32): the first n_inst instances of the
+    64-instance scan (the scan shards by instance: 32 are one GPU's share of
+    two) advanced together, one launch per phase and slice for all of them;
+    a step is every instance's beam deposit, sweep and beam push."""
+    import torch
+    import qsa_workloads as W
+    import paper_2607_24214_amd as Q
+    wls = W.scan_instances()[:n_inst]
+    t = time.perf_counter()
+    sims = []
+    for wl in wls:
+        sim = Q.Sim(Q.params_from_workload(wl, precision="f32", pipeline=1))
+        sim.load_plasma(W.plasma_template(wl))
+        for k, b in enumerate(W.beam(wl)):
+            sim.load_beam(k, b)
+        sims.append(sim)
+    log(f"scan: {n_inst} instances loaded in {time.perf_counter() - t:.1f} s")
+    batch = Q.Batch(sims)
+    batch.step(warmup)
+    batch.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    batch.sync()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    updates = sum(wl.n_plasma * wl.nxi for wl in wls) * steps
+    out = {
+        "metric": "plasma particle-slice updates/s (push+deposit+solve), batched scan",
+        "value": updates / T,
+        "unit": "plasma particle-slice updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * T / steps,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic (seeded PCG64 plasma lattice + flat-top beam)",
+        "config": {"workload": f"scan of {n_inst} of 64 instances", "instances": n_inst,
+                   "plasma_updates_per_step": updates // steps,
+                   "beam_particles": sum(wl.n_beam_total for wl in wls),
+                   "grids": sorted({(wl.nx, wl.ny) for wl in wls}),
+                   "nxi": sorted({wl.nxi for wl in wls})},
+    }
+    batch.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +243,8 @@ def main():
                     help="skip the adjoint/forward time of the 128x128x256 adjoint workload")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only measure the adjoint/forward time (its own JSON line)")
+    ap.add_argument("--scan", type=int, default=0,
+                    help="only measure batched steps of the first N scan instances (its own JSON line)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -220,6 +266,9 @@ def main():
     import qsa_workloads as W
     import paper_2607_24214_amd as Q
 
+    if args.scan:
+        print(json.dumps(scan_rate(args.scan, args.steps, args.warmup)), flush=True)
+        return
     if args.adjoint_only:
         adj = adjoint_ratio(args.pipeline)
         print(json.dumps(dict(adj, n_gpus=1, data="synthetic (seeded PCG64 plasma lattice + flat-top beam)")),
