@@ -578,7 +578,7 @@ struct Engine {
     const BeamDepArgs<R> a = beam_dep_args(c);
     const int nrows = p.nxi * p.ny;
     QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_beam_rows<R>, dim3(nrows), dim3(256),
-               2 * 2 * 4 * g.nx * sizeof(R) + dep_stage_bytes<R>(), c->stream, g, a);
+               2 * 2 * 4 * g.nx * sizeof(R), c->stream, g, a);
     const int64_t plane = (int64_t)p.nxi * g.nperp;
     hipLaunchKernelGGL(k_beam_reduce<R>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, c->stream, g,
                        (const R*)a.bpart, c->at<R>(c->L.set[0].src));
@@ -859,7 +859,7 @@ struct Engine {
       hipLaunchKernelGGL(k_pipe_scan<R>, dim3(g.ny, 1, n - 1), dim3(256), 0, c->stream, pipes, t, n);
       hipLaunchKernelGGL(k_pipe_place<R>, dim3(g.ny, 1, n - 1), dim3(256), 0, c->stream, pipes, t, n);
       QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_pipe_deposit<R>, dim3(g.ny, 1, n - 1), dim3(256),
-                 tile + dep_stage_bytes<R>() + (g.ny + 1 + 16) * sizeof(int), c->stream, pipes, t, n);
+                 tile + (g.ny + 1 + 16) * sizeof(int), c->stream, pipes, t, n);
       hipLaunchKernelGGL(k_pipe_reduce<R>, dim3(nperp_blocks, 1, n - 1), dim3(256), 0, c->stream, pipes, t, n);
     }
     HIP_OK(hipGetLastError());
@@ -1035,9 +1035,9 @@ struct Engine {
     HIP_OK(hipDeviceGetAttribute(&plain, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const int limit = std::max(optin, plain);
     static_assert(2 * 2 * 4 * 512 * 8 <= 65536, "beam tile");
-    // beam deposits: the tile and the deposit stage; the pipelined one also
-    // row starts and scan scratch
-    const int rows = 2 * 2 * 4 * c->p.nx * (int)sizeof(R) + dep_stage_bytes<R>();
+    // beam deposits: the tile; the pipelined one also row starts and scan
+    // scratch
+    const int rows = 2 * 2 * 4 * c->p.nx * (int)sizeof(R);
     const int pipe = rows + (c->p.ny + 1 + 16) * (int)sizeof(int);
     if (pipe > limit) return fail(c, QSA_E_INVALID, "nx too large for the device's LDS");
     if (rows > 65536)

@@ -1166,54 +1166,32 @@ __device__ __forceinline__ void tile_add_cell(R* __restrict__ tile, int nx, int 
   }
 }
 
-// Deposit of a cell row's n particles into the row's tile, staged through
-// LDS in chunks of QSA_DEP_STAGE = QSA_DEP_RUN x 256: each thread computes
-// QSA_DEP_RUN particles' cell, offsets and sources from coalesced loads
-// (src(k, ...) for the row's k-th particle; t0 = the cell's slice minus the
-// tile's first, -1 or 0) and stores them transposed, so that thread t then
-// reads QSA_DEP_RUN consecutive particles of the chunk without bank
-// conflicts.  A row keeps its particles in cell order: equal-cell runs add
-// up in registers before the LDS atomics (fewer of them, on neighbouring
-// cells instead of eight lanes on one).
-// LDS: sval [7][QSA_DEP_STAGE] (fz, fy, fx, 4 sources), skey [QSA_DEP_STAGE].
-// Every thread of the 256-thread block calls this (it holds barriers).
-#define QSA_DEP_RUN 2
-#define QSA_DEP_STAGE (256 * QSA_DEP_RUN)
+// Deposit of a cell row's n particles into the row's tile (src(k, ...) gives
+// the row's k-th particle's cell, offsets and sources; t0 = the cell's slice
+// minus the tile's first, -1 or 0): thread t takes particles 2t and 2t + 1 of
+// each chunk of 2 x blockDim straight from memory (a wavefront still covers
+// 128 consecutive particles, so the loads stay within a few cache lines) and
+// sums them in registers when they share a cell (a row keeps its particles
+// in cell order) before the LDS atomics.
 template <typename R, typename Src>
-__device__ __forceinline__ void deposit_staged(R* __restrict__ tile, int nx, int64_t n, Src src, R* sval,
-                                               int* skey) {
-  constexpr int T = 256, C = QSA_DEP_STAGE, RUN = QSA_DEP_RUN;
+__device__ __forceinline__ void deposit_pairs(R* __restrict__ tile, int nx, int64_t n, Src src) {
   const int t = threadIdx.x;
-  for (int64_t c0 = 0; c0 < n; c0 += C) {
+  for (int64_t c0 = 2 * (int64_t)t; c0 < n; c0 += 2 * (int64_t)blockDim.x) {
+    int t0[2], i[2];
+    R fz[2], fy[2], fx[2], v[2][4];
+    const int m = (c0 + 1 < n) ? 2 : 1;
 #pragma unroll
-    for (int k = 0; k < RUN; ++k) {
-      const int pc = k * T + t;
-      const int slot = (pc % RUN) * T + pc / RUN;
-      int key = -1;
-      if (c0 + pc < n) {
-        int t0, i;
-        R fz, fy, fx, v[4];
-        src(c0 + pc, t0, i, fz, fy, fx, v);
-        key = ((t0 + 1) << 16) | i;
-        sval[0 * C + slot] = fz;
-        sval[1 * C + slot] = fy;
-        sval[2 * C + slot] = fx;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) sval[(3 + c) * C + slot] = v[c];
-      }
-      skey[slot] = key;
-    }
-    __syncthreads();
+    for (int k = 0; k < 2; ++k)
+      if (k < m) src(c0 + k, t0[k], i[k], fz[k], fy[k], fx[k], v[k]);
     R acc[2][2][2][4];
-    int ck = -1;
+    int ck = -1, ct0 = 0;
 #pragma unroll
-    for (int r = 0; r < RUN; ++r) {
-      const int slot = r * T + t;
-      const int key = skey[slot];
-      if (key < 0) continue;
-      if (key != ck) {
-        if (ck >= 0) tile_add_cell(tile, nx, (ck >> 16) - 1, ck & 0xffff, acc);
-        ck = key;
+    for (int k = 0; k < 2; ++k) {
+      if (k >= m) break;
+      if (i[k] != ck || t0[k] != ct0) {
+        if (ck >= 0) tile_add_cell(tile, nx, ct0, ck, acc);
+        ck = i[k];
+        ct0 = t0[k];
 #pragma unroll
         for (int d = 0; d < 2; ++d)
 #pragma unroll
@@ -1223,11 +1201,7 @@ __device__ __forceinline__ void deposit_staged(R* __restrict__ tile, int nx, int
 #pragma unroll
               for (int c = 0; c < 4; ++c) acc[d][e][x][c] = R(0);
       }
-      const R fz = sval[0 * C + slot], fy = sval[1 * C + slot], fx = sval[2 * C + slot];
-      const R wz[2] = {R(1) - fz, fz}, wy[2] = {R(1) - fy, fy}, wx[2] = {R(1) - fx, fx};
-      R v[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] = sval[(3 + c) * C + slot];
+      const R wz[2] = {R(1) - fz[k], fz[k]}, wy[2] = {R(1) - fy[k], fy[k]}, wx[2] = {R(1) - fx[k], fx[k]};
 #pragma unroll
       for (int d = 0; d < 2; ++d)
 #pragma unroll
@@ -1236,18 +1210,11 @@ __device__ __forceinline__ void deposit_staged(R* __restrict__ tile, int nx, int
 #pragma unroll
           for (int x = 0; x < 2; ++x)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[d][e][x][c] += v[c] * wc * wx[x];
+            for (int c = 0; c < 4; ++c) acc[d][e][x][c] += v[k][c] * wc * wx[x];
         }
     }
-    if (ck >= 0) tile_add_cell(tile, nx, (ck >> 16) - 1, ck & 0xffff, acc);
-    __syncthreads();
+    if (ck >= 0) tile_add_cell(tile, nx, ct0, ck, acc);
   }
-}
-
-// LDS bytes of a staged beam deposit beyond its tile
-template <typename R>
-__host__ __device__ constexpr int dep_stage_bytes() {
-  return QSA_DEP_STAGE * (7 * (int)sizeof(R) + (int)sizeof(int));
 }
 
 // Beam deposit owned by cell rows b = (j, l): the block takes exactly the
@@ -1256,26 +1223,23 @@ __host__ __device__ constexpr int dep_stage_bytes() {
 // the tile out as the row's partial node rows.
 template <typename R>
 __global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a) {
-  // LDS: the tile, then the deposit stage
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
   const int b = blockIdx.x;
   const int jb = b / g.ny;
   const int tn = 2 * 2 * 4 * g.nx;
-  R* sval = tile + tn;
-  int* skey = reinterpret_cast<int*>(sval + 7 * QSA_DEP_STAGE);
   for (int t = threadIdx.x; t < tn; t += blockDim.x) tile[t] = R(0);
   __syncthreads();
   for (int s = 0; s < a.ns; ++s) {
     const int nxc = nx_chunks(g);
     const int64_t q0 = a.doff[s][(int64_t)b * nxc], q1 = a.doff[s][(int64_t)(b + 1) * nxc];
-    deposit_staged(tile, g.nx, q1 - q0, [&](int64_t k, int& t0, int& i, R& fz, R& fy, R& fx, R (&v)[4]) {
+    deposit_pairs(tile, g.nx, q1 - q0, [&](int64_t k, int& t0, int& i, R& fz, R& fy, R& fx, R (&v)[4]) {
       const int p = a.perm[s][q0 + k];
       int jc, l;
       beam_sources_of(g, a.x[s][p], a.y[s][p], a.xi[s][p], a.ux[s][p], a.uy[s][p], a.uz[s][p],
                       a.zq[s] * a.w[s][p], a.inv_dxi, jc, i, l, fz, fy, fx, v);
       t0 = jc - jb;
-    }, sval, skey);
+    });
   }
   __syncthreads();
   R* out = a.bpart + (int64_t)b * tn;
@@ -1737,13 +1701,11 @@ __global__ void __launch_bounds__(256) k_pipe_deposit(const PipeBeam<R>* __restr
   const Geo<R>& g = B.g;
   const int jp = tick - B.lag - QSA_PUSH_LAG;
   if (jp < 0 || jp > g.nxi - 2 || L >= g.ny) return;
-  // LDS: the tile, the deposit stage, the row starts (ny + 1), scan scratch (16)
+  // LDS: the tile, the row starts (ny + 1), scan scratch (16)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* tile = reinterpret_cast<R*>(smem_raw);
   const int tn = 2 * 2 * 4 * g.nx;
-  R* sval = tile + tn;
-  int* skey = reinterpret_cast<int*>(sval + 7 * QSA_DEP_STAGE);
-  int* base = skey + QSA_DEP_STAGE;
+  int* base = reinterpret_cast<int*>(tile + tn);
   int* ws = base + g.ny + 1;
   for (int i = threadIdx.x; i < tn; i += blockDim.x) tile[i] = R(0);
   __syncthreads();
@@ -1753,13 +1715,13 @@ __global__ void __launch_bounds__(256) k_pipe_deposit(const PipeBeam<R>* __restr
     const int64_t s0 = B.rowoff[s][(int64_t)jp * g.ny];
     const int64_t q0 = s0 + base[L], q1 = s0 + base[L + 1];
     __syncthreads();
-    deposit_staged(tile, g.nx, q1 - q0, [&](int64_t k, int& t0, int& i, R& fz, R& fy, R& fx, R (&v)[4]) {
+    deposit_pairs(tile, g.nx, q1 - q0, [&](int64_t k, int& t0, int& i, R& fz, R& fy, R& fx, R (&v)[4]) {
       const int p = B.perm[s][q0 + k];
       int jc, lc;
       beam_sources_of(g, B.x[s][p], B.y[s][p], B.xi[s][p], B.ux[s][p], B.uy[s][p], B.uz[s][p],
                       B.zq[s] * B.w[s][p], B.inv_dxi, jc, i, lc, fz, fy, fx, v);
       t0 = jc - jp;
-    }, sval, skey);
+    });
   }
   __syncthreads();
   R* out = B.ring_next + ((int64_t)(jp & 1) * g.ny + L) * tn;
