@@ -260,12 +260,27 @@ __device__ __forceinline__ R row_value(const Geo<R>& g, const RowIn<R>& a, int r
 
 // Real rows -> half spectra along x.  Rows 2p and 2p+1 are packed as the
 // real and imaginary parts of one complex transform and separated after it.
+// Block indices of a launch of gridDim.x x gridDim.y blocks per lane and
+// gridDim.z lanes, remapped so that each XCD (workgroups go round-robin to
+// the 8 XCDs in linear order) takes a contiguous range of the (lane, y, x)
+// order: the same lanes as the particle kernels' remapping, so each lane's
+// grids are written and read by one XCD and stay in its L2.
+__device__ __forceinline__ void lane_block3(int& lane, int& by, int& bx) {
+  const int nbx = gridDim.x, nby = gridDim.y;
+  const int lg = xcd_block(blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z), nbx * nby * gridDim.z);
+  bx = lg % nbx;
+  const int r = lg / nbx;
+  by = r % nby;
+  lane = r / nby;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_row_r2c(const Lane<R>* __restrict__ lanes, int tick, int stage) {
-  const Lane<R>& L = lanes[blockIdx.z];
+  int lane, f, bx;
+  lane_block3(lane, f, bx);
+  const Lane<R>& L = lanes[lane];
   const int j = tick - L.lag;
   const Geo<R> g = L.g;
-  const int f = blockIdx.y;
   if (j < 0 || j >= g.nxi || f >= stage_fields_in<R>(stage)) return;
   const RowIn<R> a = row_in(L, j, stage, f);
   const C2<R>* __restrict__ twx = L.twx;
@@ -273,10 +288,10 @@ __global__ void __launch_bounds__(256) k_row_r2c(const Lane<R>* __restrict__ lan
   C2<R>* sm = reinterpret_cast<C2<R>*>(smem_raw);
   const int tpt = g.nx >> 2;
   const int ppw = blockDim.x / tpt;
-  if (blockIdx.x * ppw >= ((g.ny + 1) >> 1)) return;
+  if (bx * ppw >= ((g.ny + 1) >> 1)) return;
   const int slot = threadIdx.x / tpt, t = threadIdx.x - slot * tpt;
   const int npairs = (g.ny + 1) >> 1;
-  const int pair = blockIdx.x * ppw + slot;
+  const int pair = bx * ppw + slot;
   const bool v0 = pair < npairs;
   const int r0 = 2 * pair, r1 = 2 * pair + 1;
   const bool v1 = v0 && r1 < g.ny;
@@ -331,10 +346,11 @@ __device__ __forceinline__ int half_slot(int so) {
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_row_c2r(const Lane<R>* __restrict__ lanes, int tick, int stage) {
-  const Lane<R>& L = lanes[blockIdx.z];
+  int lane, f, bx;
+  lane_block3(lane, f, bx);
+  const Lane<R>& L = lanes[lane];
   const int j = tick - L.lag;
   const Geo<R> g = L.g;
-  const int f = blockIdx.y;
   if (j < 0 || j >= g.nxi || f >= stage_fields_out(stage)) return;
   const C2<R>* __restrict__ in = L.colout + (size_t)f * g.ny * g.nxh;
   R* __restrict__ outp = L.fields + (int64_t)stage_slot(stage, f) * g.nxi * g.nperp + (int64_t)j * g.nperp;
@@ -343,10 +359,10 @@ __global__ void __launch_bounds__(256) k_row_c2r(const Lane<R>* __restrict__ lan
   C2<R>* sm = reinterpret_cast<C2<R>*>(smem_raw);
   const int tpt = g.nx >> 2;
   const int ppw = blockDim.x / tpt;
-  if (blockIdx.x * ppw >= ((g.ny + 1) >> 1)) return;
+  if (bx * ppw >= ((g.ny + 1) >> 1)) return;
   const int slot = threadIdx.x / tpt, t = threadIdx.x - slot * tpt;
   const int npairs = (g.ny + 1) >> 1;
-  const int pair = blockIdx.x * ppw + slot;
+  const int pair = bx * ppw + slot;
   const bool v0 = pair < npairs;
   const int r0 = 2 * pair, r1 = 2 * pair + 1;
   const bool v1 = v0 && r1 < g.ny;
@@ -479,7 +495,9 @@ template <typename R, int MODE>
 __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, int tick, int ctpt) {
   using S = ColShape<MODE>;
   constexpr int G = S::G;
-  const Lane<R>& L = lanes[blockIdx.z];
+  int lane, by, bx;
+  lane_block3(lane, by, bx);
+  const Lane<R>& L = lanes[lane];
   const int j = tick - L.lag;
   const Geo<R> g = L.g;
   if (j < 0 || j >= g.nxi) return;
@@ -491,11 +509,11 @@ __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, 
   const int tpt = col_tpt(ny, ctpt);
   const int per_col = G * tpt;
   const int cpw = blockDim.x / per_col;
-  if (blockIdx.x * cpw >= g.nxh) return;
+  if (bx * cpw >= g.nxh) return;
   const int c = threadIdx.x / per_col;
   const int r = threadIdx.x - c * per_col;
   const int grp = r / tpt, t = r - grp * tpt;
-  const int kx = blockIdx.x * cpw + c;
+  const int kx = bx * cpw + c;
   const bool valid = kx < g.nxh;
   C2<R>* tw = sm;                          // twiddles, staged once per block
   for (int i = threadIdx.x; i < ny; i += blockDim.x) tw[i] = twy[i];
