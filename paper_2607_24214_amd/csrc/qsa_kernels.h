@@ -1184,40 +1184,106 @@ __device__ __forceinline__ void tile_add_cell(R* __restrict__ tile, int nx, int 
   }
 }
 
+// Value of lane i - N of the wavefront within its row of 16 lanes (DPP
+// row_shr); only read where lane i - N lies in lane i's row.
+template <int N>
+__device__ __forceinline__ int lane_back(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x110 + N, 0xF, 0xF, false);
+}
+template <int N>
+__device__ __forceinline__ float lane_back(float v) {
+  return __int_as_float(lane_back<N>(__float_as_int(v)));
+}
+template <int N>
+__device__ __forceinline__ double lane_back(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_back<N>((int)(b & 0xffffffffll));
+  const int hi = lane_back<N>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Segmented sums over consecutive lanes with equal keys: runs of equal keys
+// are cut at every row of 16 lanes and into segments of at most 4 lanes;
+// the last lane of each segment ends up with the segment's sum of acc and
+// is the one that returns true (when act).  Every lane of the wavefront calls
+// this together; an inactive lane passes a key no other lane has.
+template <typename R>
+__device__ __forceinline__ bool wave_segment_sum(int key, bool act, R (&acc)[2][2][2][4]) {
+  const int lane = threadIdx.x & 63;
+  const int kprev = lane_back<1>(key);
+  const bool head = ((lane & 15) == 0) || kprev != key;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = (lane == 63) ? heads : (heads & ((2ull << lane) - 1ull));
+  const int rs = 63 - __clzll((long long)upto);          // first lane of the run
+  const int ss = rs + ((lane - rs) & ~3);                 // first lane of the segment
+  const bool a1 = lane - 1 >= ss, a2 = lane - 2 >= ss;
+#pragma unroll
+  for (int d = 0; d < 2; ++d)
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          R v = acc[d][e][x][c];
+          const R v1 = lane_back<1>(v);
+          if (a1) v += v1;
+          const R v2 = lane_back<2>(v);
+          if (a2) v += v2;
+          acc[d][e][x][c] = v;
+        }
+  const bool next_head = (lane == 63) || ((heads >> (lane + 1)) & 1ull);
+  return act && (next_head || ((lane + 1 - rs) & 3) == 0);
+}
+
 // Deposit of a cell row's n particles into the row's tile (src(k, ...) gives
 // the row's k-th particle's cell, offsets and sources; t0 = the cell's slice
 // minus the tile's first, -1 or 0): thread t takes particles 2t and 2t + 1 of
 // each chunk of 2 x blockDim straight from memory (a wavefront still covers
 // 128 consecutive particles, so the loads stay within a few cache lines) and
-// sums them in registers when they share a cell (a row keeps its particles
-// in cell order) before the LDS atomics.
+// sums them in registers when they share a cell; the lanes then sum runs of
+// equal cells across the wavefront (a row keeps its particles in cell order,
+// so a cell's particles sit on neighbouring lanes) before the LDS atomics,
+// which same-address conflicts would otherwise serialize.
 template <typename R, typename Src>
 __device__ __forceinline__ void deposit_pairs(R* __restrict__ tile, int nx, int64_t n, Src src) {
   const int t = threadIdx.x;
-  for (int64_t c0 = 2 * (int64_t)t; c0 < n; c0 += 2 * (int64_t)blockDim.x) {
+  for (int64_t base = 0; base < n; base += 2 * (int64_t)blockDim.x) {
+    // a uniform trip count: every lane reaches the cross-lane sums
+    const int64_t c0 = base + 2 * (int64_t)t;
+    const int m = (c0 + 1 < n) ? 2 : (c0 < n ? 1 : 0);
     int t0[2], i[2];
     R fz[2], fy[2], fx[2], v[2][4];
-    const int m = (c0 + 1 < n) ? 2 : 1;
 #pragma unroll
     for (int k = 0; k < 2; ++k)
       if (k < m) src(c0 + k, t0[k], i[k], fz[k], fy[k], fx[k], v[k]);
     R acc[2][2][2][4];
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[d][e][x][c] = R(0);
     int ck = -1, ct0 = 0;
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (k >= m) break;
       if (i[k] != ck || t0[k] != ct0) {
-        if (ck >= 0) tile_add_cell(tile, nx, ct0, ck, acc);
+        if (ck >= 0) {
+          tile_add_cell(tile, nx, ct0, ck, acc);
+#pragma unroll
+          for (int d = 0; d < 2; ++d)
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+#pragma unroll
+              for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[d][e][x][c] = R(0);
+        }
         ck = i[k];
         ct0 = t0[k];
-#pragma unroll
-        for (int d = 0; d < 2; ++d)
-#pragma unroll
-          for (int e = 0; e < 2; ++e)
-#pragma unroll
-            for (int x = 0; x < 2; ++x)
-#pragma unroll
-              for (int c = 0; c < 4; ++c) acc[d][e][x][c] = R(0);
       }
       const R wz[2] = {R(1) - fz[k], fz[k]}, wy[2] = {R(1) - fy[k], fy[k]}, wx[2] = {R(1) - fx[k], fx[k]};
 #pragma unroll
@@ -1231,7 +1297,9 @@ __device__ __forceinline__ void deposit_pairs(R* __restrict__ tile, int nx, int6
             for (int c = 0; c < 4; ++c) acc[d][e][x][c] += v[k][c] * wc * wx[x];
         }
     }
-    if (ck >= 0) tile_add_cell(tile, nx, ct0, ck, acc);
+    // the lane's last cell, summed with its neighbours' equal cells
+    const int key = (ck >= 0) ? (((ct0 + 1) << 16) | ck) : -1 - (t & 63);
+    if (wave_segment_sum(key, ck >= 0, acc)) tile_add_cell(tile, nx, ct0, ck, acc);
   }
 }
 
