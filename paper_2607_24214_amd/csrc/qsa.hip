@@ -119,6 +119,7 @@ struct SetLayout {
   size_t cell_of, count, bsum, prow, ppart;
   size_t src, fields, half, dep, rowspec, colout, jring, jz, bring, ode;
   size_t ring;   // slab ring of the deposits this set receives from the lane before it
+  size_t fpack;  // packed fields of the beam push (pipelining)
   size_t hist;   // new-row count matrix of this set's slab pushes, and row starts
   size_t base;
 };
@@ -150,6 +151,9 @@ struct Carver {
 };
 
 int pipeline_depth(const qsa_params& p) { return std::max(1, (int)p.pipeline); }
+
+// bytes of one node's packed beam-push fields (element size rs)
+size_t pack_stride_bytes(size_t rs) { return rs == 8 ? 6 * 8 : 8 * 4; }
 
 Layout make_layout(const qsa_params& p) {
   const size_t rs = (p.precision == QSA_FP32) ? 4 : 8;
@@ -189,6 +193,7 @@ Layout make_layout(const qsa_params& p) {
     // two slabs x ny cell rows x (2 node slices x 2 node rows x 4 sources x nx)
     S.ring = (k > 0) ? c.take(2 * (size_t)p.ny * 2 * 2 * 4 * p.nx * rs) : 0;
     S.hist = (L.nset > 1) ? c.take((size_t)QSA_MAX_SPECIES * p.ny * p.ny * sizeof(int)) : 0;
+    S.fpack = (L.nset > 1) ? c.take((size_t)QSA_PACK_RING * nperp * pack_stride_bytes(rs)) : 0;
     S.base = (L.nset > 1) ? c.take((size_t)QSA_MAX_SPECIES * (p.ny + 1) * sizeof(int)) : 0;
   }
   const size_t nrows = (size_t)p.nxi * p.ny;
@@ -648,6 +653,7 @@ struct Engine {
     a.jz = c->at<C2<R>>(S.jz);
     a.bring = c->at<C2<R>>(S.bring);
     a.ode = c->at<double>(S.ode);
+    a.fpack = S.fpack ? c->at<R>(S.fpack) : nullptr;
     return a;
   }
 
@@ -678,6 +684,7 @@ struct Engine {
     a.inv_dxi = 1.0 / p.dxi;
     a.xi_max = (double)(p.nxi - 1) * p.dxi;
     a.fields = c->at<R>(L.set[k].fields);
+    a.fpack = L.set[k].fpack ? c->at<R>(L.set[k].fpack) : nullptr;
     a.hist = L.set[k].hist ? c->at<int>(L.set[k].hist) : nullptr;
     a.base = L.set[k].base ? c->at<int>(L.set[k].base) : nullptr;
     if (k + 1 < L.nset) {

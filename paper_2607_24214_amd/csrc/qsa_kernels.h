@@ -74,7 +74,19 @@ struct Lane {
   C2<R>* jz;            // J_z spectrum [ny][nxh]
   C2<R>* bring;         // B_perp spectra, ring of 3 slices [3][2][ny][nxh]
   double* ode;          // [<E_z> at j-1/2, <psi> at j]
+  R* fpack;             // the beam push's fields, packed per node (or null):
+                        // [QSA_PACK_RING][ny][nx][pack_stride<R>()]
 };
+
+// Fields of the beam push packed per node for aligned vector gathers:
+// (d_x psi, d_y psi, E_z, B_x, B_y, B_z) in 48 bytes (float64) or in 32
+// bytes with two unused (float32), in a ring of QSA_PACK_RING slices (slot
+// j % QSA_PACK_RING).  A pipelined push reads slices up to four back.
+#define QSA_PACK_RING 8
+template <typename R>
+__host__ __device__ constexpr int pack_stride() {
+  return sizeof(R) == 8 ? 6 : 8;
+}
 
 // plasma buffer set that holds the state at slice j
 __device__ __forceinline__ int plasma_set(int j) { return (j / QSA_SORT_EVERY) & 1; }
@@ -862,6 +874,23 @@ __global__ void __launch_bounds__(256) k_push_final(const Lane<R>* __restrict__ 
   const Geo<R> g = L.g;
   if (j < 0 || j >= g.nxi) return;
   const int p = b * blockDim.x + threadIdx.x;
+  if (L.fpack) {
+    // slice j is final: pack the beam push's fields
+    const int64_t plane = (int64_t)g.nxi * g.nperp;
+    const R* f = L.fields + (int64_t)j * g.nperp;
+    R* dst = L.fpack + (int64_t)(j % QSA_PACK_RING) * g.nperp * pack_stride<R>();
+    const int slot[6] = {F_DXPSI, F_DYPSI, F_EZ, F_BX, F_BY, F_BZ};
+    for (int o = p; o < g.nperp; o += gridDim.x * blockDim.x) {
+      R v[pack_stride<R>()];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) v[q] = f[slot[q] * plane + o];
+#pragma unroll
+      for (int q = 6; q < pack_stride<R>(); ++q) v[q] = R(0);
+      R* r = dst + (int64_t)o * pack_stride<R>();
+#pragma unroll
+      for (int q = 0; q < pack_stride<R>(); ++q) r[q] = v[q];
+    }
+  }
   if (p >= L.np) return;
   const PlasmaArgs<R> a = plasma_args(L, j);
   R xn, yn, uxn, uyn;
@@ -1436,33 +1465,79 @@ struct BeamNew {
   bool lost;
 };
 
+// The six fields (d_x psi, d_y psi, E_z, B_x, B_y, B_z) at a beam particle:
+// 3D linear shape, zero outside the xi grid; from the stored fields
+// [7][nxi][ny][nx], or (packed set) from the packed ring of a pipelined lane.
 template <typename R>
-__device__ __forceinline__ BeamNew<R> boris_one(const Geo<R>& g, const R* __restrict__ fields, R qh, R dt,
-                                                double inv_dxi, double xi_max, R* __restrict__ px,
-                                                R* __restrict__ py, double* __restrict__ pxi, R* __restrict__ pux,
-                                                R* __restrict__ puy, R* __restrict__ puz, R* __restrict__ pw,
-                                                int64_t p) {
-  const R x = px[p], y = py[p];
-  const double xi = pxi[p];
-  R ux = pux[p], uy = puy[p], uz = puz[p];
-  R fd[6] = {0, 0, 0, 0, 0, 0};   // d_x psi, d_y psi, E_z, B_x, B_y, B_z
-  const double gz = xi * inv_dxi;
-  if (gz > -1.0 && gz < (double)g.nxi) {
-    const double fz0 = floor(gz);
-    const int j0 = (int)fz0;
-    const R fz = (R)(gz - fz0);
-    const Stencil<R> s = stencil2(g, x, y);
-    const int64_t plane = (int64_t)g.nxi * g.nperp;
-    const int slot[6] = {F_DXPSI, F_DYPSI, F_EZ, F_BX, F_BY, F_BZ};
+__device__ __forceinline__ void packed_node(const R* __restrict__ rec, R (&v)[6]) {
+  if constexpr (sizeof(R) == 8) {
+    typedef double D2 __attribute__((ext_vector_type(2)));
+    const D2* q = reinterpret_cast<const D2*>(rec);
+    const D2 a = q[0], b = q[1], c = q[2];
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
+    v[4] = c.x;
+    v[5] = c.y;
+  } else {
+    typedef float F4 __attribute__((ext_vector_type(4)));
+    const F4* q = reinterpret_cast<const F4*>(rec);
+    const F4 a = q[0], b = q[1];
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+    v[4] = b.x;
+    v[5] = b.y;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void beam_fields(const Geo<R>& g, const R* __restrict__ fields, const R* __restrict__ fpack,
+                                            double inv_dxi, R x, R y, double xi, R (&fd)[6]) {
 #pragma unroll
-    for (int dj = 0; dj < 2; ++dj) {
-      const int jj = j0 + dj;
-      if (jj < 0 || jj >= g.nxi) continue;
-      const R wz = dj ? fz : R(1) - fz;
+  for (int q = 0; q < 6; ++q) fd[q] = R(0);
+  const double gz = xi * inv_dxi;
+  if (!(gz > -1.0 && gz < (double)g.nxi)) return;
+  const double fz0 = floor(gz);
+  const int j0 = (int)fz0;
+  const R fz = (R)(gz - fz0);
+  const Stencil<R> s = stencil2(g, x, y);
+  const int64_t plane = (int64_t)g.nxi * g.nperp;
+  const int slot[6] = {F_DXPSI, F_DYPSI, F_EZ, F_BX, F_BY, F_BZ};
+#pragma unroll
+  for (int dj = 0; dj < 2; ++dj) {
+    const int jj = j0 + dj;
+    if (jj < 0 || jj >= g.nxi) continue;
+    const R wz = dj ? fz : R(1) - fz;
+    if (fpack) {
+      const R* rec = fpack + (int64_t)(jj % QSA_PACK_RING) * g.nperp * pack_stride<R>();
+      R a[6], b[6], c[6], d[6];
+      packed_node(rec + (int64_t)s.n00 * pack_stride<R>(), a);
+      packed_node(rec + (int64_t)s.n10 * pack_stride<R>(), b);
+      packed_node(rec + (int64_t)s.n01 * pack_stride<R>(), c);
+      packed_node(rec + (int64_t)s.n11 * pack_stride<R>(), d);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) fd[q] += wz * (a[q] * s.w00 + b[q] * s.w10 + c[q] * s.w01 + d[q] * s.w11);
+    } else {
 #pragma unroll
       for (int q = 0; q < 6; ++q) fd[q] += wz * gather(fields + slot[q] * plane + (int64_t)jj * g.nperp, s);
     }
   }
+}
+
+template <typename R>
+__device__ __forceinline__ BeamNew<R> boris_one(const Geo<R>& g, const R* __restrict__ fields,
+                                                const R* __restrict__ fpack, R qh, R dt, double inv_dxi,
+                                                double xi_max, R* __restrict__ px, R* __restrict__ py,
+                                                double* __restrict__ pxi, R* __restrict__ pux, R* __restrict__ puy,
+                                                R* __restrict__ puz, R* __restrict__ pw, int64_t p) {
+  const R x = px[p], y = py[p];
+  const double xi = pxi[p];
+  R ux = pux[p], uy = puy[p], uz = puz[p];
+  R fd[6];   // d_x psi, d_y psi, E_z, B_x, B_y, B_z
+  beam_fields(g, fields, fpack, inv_dxi, x, y, xi, fd);
   const R ex = -fd[0] + fd[4];
   const R ey = -fd[1] - fd[3];
   const R ez = fd[2];
@@ -1510,7 +1585,7 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_beam_push(Geo<R> g, BeamArgs<R> a) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.n) return;
-  boris_one(g, a.fields, a.qmh, a.dt, a.inv_dxi, a.xi_max, a.x, a.y, a.xi, a.ux, a.uy, a.uz, a.w, p);
+  boris_one<R>(g, a.fields, nullptr, a.qmh, a.dt, a.inv_dxi, a.xi_max, a.x, a.y, a.xi, a.ux, a.uy, a.uz, a.w, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -1559,6 +1634,7 @@ struct PipeBeam {
   double inv_dxi;
   double xi_max;
   const R* fields;          // this lane's fields (the push)
+  const R* fpack;           // this lane's packed ring of them (or null)
   int* hist;                // [4 species][ny source rows][ny new rows]: counts, then slots
   int* base;                // [4 species][ny + 1]: particles of each new row in the slab
   R* ring_next;             // next lane's slab ring [2][ny][2][2][4][nx]
@@ -1629,7 +1705,7 @@ __device__ __forceinline__ bool pipe_push_one(const PipeBeam<R>& B, int s, int64
     if (feeds && B.w[s][p] != R(0) && gz < (double)(jp - 3)) bad = true;
   }
   const R w0 = B.w[s][p];
-  const BeamNew<R> n = boris_one(g, B.fields, B.qmh[s], B.dt, B.inv_dxi, B.xi_max, B.x[s], B.y[s], B.xi[s],
+  const BeamNew<R> n = boris_one(g, B.fields, B.fpack, B.qmh[s], B.dt, B.inv_dxi, B.xi_max, B.x[s], B.y[s], B.xi[s],
                                  B.ux[s], B.uy[s], B.uz[s], B.w[s], p);
   if (!feeds) return bad;
   const R w = n.lost ? R(0) : w0;
