@@ -583,7 +583,7 @@ struct Engine {
     const BeamDepArgs<R> a = beam_dep_args(c);
     const int nrows = p.nxi * p.ny;
     QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_beam_rows<R>, dim3(nrows), dim3(256),
-               2 * 2 * 4 * g.nx * sizeof(R), c->stream, g, a);
+               2 * 2 * 4 * g.nx * sizeof(double), c->stream, g, a);
     const int64_t plane = (int64_t)p.nxi * g.nperp;
     hipLaunchKernelGGL(k_beam_reduce<R>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, c->stream, g,
                        (const R*)a.bpart, c->at<R>(c->L.set[0].src));
@@ -765,7 +765,7 @@ struct Engine {
       const dim3 rblock(d.rt_rows);
       // ---- psi stage
       QSA_LAUNCH(tc, QSA_K_DEP_S, (k_plasma_rows<R, PL_DEP_S>), dim3(d.ny, 1, n), dim3(nt),
-                         4 * 1 * (size_t)d.nx * sizeof(R), st, lanes, j);
+                         4 * 1 * (size_t)d.nx * sizeof(double), st, lanes, j);
       QSA_LAUNCH(tc, QSA_K_ROW_R2C, k_row_r2c<R>, rgrid_psi, rblock, smem_rows, st, lanes, j, (int)ST_PSI);
       QSA_LAUNCH(tc, QSA_K_COL, (k_col<R, COL_PSI>), dim3(d.cols[0], 1, n), dim3(64 * ColShape<COL_PSI>::G),
                          d.smem_col[0], st, lanes, j, d.ctpt);
@@ -773,7 +773,7 @@ struct Engine {
                  (int)ST_PSI);
       // ---- J stage
       QSA_LAUNCH(tc, QSA_K_DEP_J, (k_plasma_rows<R, PL_DEP_J>), dim3(d.ny, 1, n), dim3(nt),
-                         4 * 3 * (size_t)d.nx * sizeof(R), st, lanes, j);
+                         4 * 3 * (size_t)d.nx * sizeof(double), st, lanes, j);
       QSA_LAUNCH(tc, QSA_K_ROW_R2C, k_row_r2c<R>, rgrid_j, rblock, smem_rows, st, lanes, j, (int)ST_J);
       QSA_LAUNCH(tc, QSA_K_COL, (k_col<R, COL_J>), dim3(d.cols[1], 1, n), dim3(64 * ColShape<COL_J>::G),
                          d.smem_col[1], st, lanes, j, d.ctpt);
@@ -781,7 +781,7 @@ struct Engine {
       // ---- B_perp predictor-corrector
       for (int k = 0; k < d.n_corr; ++k) {
         QSA_LAUNCH(tc, QSA_K_PUSH_PRED, (k_plasma_rows<R, PL_PRED>), dim3(d.ny, 1, n), dim3(nt),
-                           4 * 2 * (size_t)d.nx * sizeof(R), st, lanes, j);
+                           4 * 2 * (size_t)d.nx * sizeof(double), st, lanes, j);
         QSA_LAUNCH(tc, QSA_K_ROW_R2C, k_row_r2c<R>, rgrid_b, rblock, smem_rows, st, lanes, j, (int)ST_B);
         QSA_LAUNCH(tc, QSA_K_COL, (k_col<R, COL_B>), dim3(d.cols[2], 1, n), dim3(64 * ColShape<COL_B>::G),
                            d.smem_col[2], st, lanes, j, d.ctpt);
@@ -855,7 +855,7 @@ struct Engine {
     d.n = n;
     const Lane<R>* lanes = c->at<Lane<R>>(L.lane);
     const PipeBeam<R>* pipes = c->at<PipeBeam<R>>(L.pipe);
-    const size_t tile = (size_t)2 * 2 * 4 * g.nx * sizeof(R);
+    const size_t tile = (size_t)2 * 2 * 4 * g.nx * sizeof(double);
     const int nperp_blocks = (g.nperp + 255) / 256;
     const int T = p.nxi + 2 + (n - 1) * QSA_PIPE_LAG;
     for (int t = 0; t < T; ++t) {
@@ -1044,7 +1044,7 @@ struct Engine {
     static_assert(2 * 2 * 4 * 512 * 8 <= 65536, "beam tile");
     // beam deposits: the tile; the pipelined one also row starts and scan
     // scratch
-    const int rows = 2 * 2 * 4 * c->p.nx * (int)sizeof(R);
+    const int rows = 2 * 2 * 4 * c->p.nx * (int)sizeof(double);
     const int pipe = rows + (c->p.ny + 1 + 16) * (int)sizeof(int);
     if (pipe > limit) return fail(c, QSA_E_INVALID, "nx too large for the device's LDS");
     if (rows > 65536)

@@ -722,7 +722,7 @@ struct PlasmaNC {
 // (i0, l0) to the tile of block row r (node rows r-1 .. r+2), or, when the
 // cell is more than one row away, to the stray grids with atomics.
 template <typename R, int NC>
-__device__ __forceinline__ void row_tile_add(const Geo<R>& g, R* tile, int r, int i0, int l0,
+__device__ __forceinline__ void row_tile_add(const Geo<R>& g, double* tile, int r, int i0, int l0,
                                              const R (&acc)[4][NC], R* const* stray) {
   int d = l0 - r;
   if (g.ny == 1) {
@@ -736,12 +736,12 @@ __device__ __forceinline__ void row_tile_add(const Geo<R>& g, R* tile, int r, in
     const int k0 = d + 1;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      R* t0 = tile + (k0 * NC + c) * g.nx;
-      R* t1 = tile + ((k0 + 1) * NC + c) * g.nx;
-      atomicAdd(t0 + i0, acc[0][c]);
-      atomicAdd(t0 + i1, acc[1][c]);
-      atomicAdd(t1 + i0, acc[2][c]);
-      atomicAdd(t1 + i1, acc[3][c]);
+      double* t0 = tile + (k0 * NC + c) * g.nx;
+      double* t1 = tile + ((k0 + 1) * NC + c) * g.nx;
+      atomicAdd(t0 + i0, (double)acc[0][c]);
+      atomicAdd(t0 + i1, (double)acc[1][c]);
+      atomicAdd(t1 + i0, (double)acc[2][c]);
+      atomicAdd(t1 + i1, (double)acc[3][c]);
     }
   } else {
     const int l1 = (l0 + 1 == g.ny) ? 0 : l0 + 1;
@@ -773,11 +773,13 @@ __global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__
   const Geo<R> g = L.g;
   if (j < 0 || j >= g.nxi || r >= g.ny) return;
   const PlasmaArgs<R> a = plasma_args(L, j);
+  // the LDS tile accumulates in float64 for either precision (LDS float32
+  // atomic adds are about three times slower per instruction here)
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* tile = reinterpret_cast<R*>(smem_raw);
+  double* tile = reinterpret_cast<double*>(smem_raw);
   const int nt = blockDim.x, tid = threadIdx.x;
   const int tn = 4 * NC * g.nx;
-  for (int t = tid; t < tn; t += nt) tile[t] = R(0);
+  for (int t = tid; t < tn; t += nt) tile[t] = 0.0;
   __syncthreads();
   const int p0 = a.prow[r], p1 = a.prow[r + 1];
   const int run = (p1 - p0 + nt - 1) / nt;
@@ -842,7 +844,7 @@ __global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__
   if (ci >= 0) row_tile_add<R, NC>(g, tile, r, ci, cl, acc, stray);
   __syncthreads();
   R* out = a.ppart + (size_t)r * tn;
-  for (int t = tid; t < tn; t += nt) out[t] = tile[t];
+  for (int t = tid; t < tn; t += nt) out[t] = (R)tile[t];
 }
 
 // First particle of each cell row from the scanned cell counts (cell c
@@ -1167,35 +1169,11 @@ __device__ __forceinline__ void beam_sources_of(const Geo<R>& g, R x, R y, doubl
   v[3] = qw * uz / gam;
 }
 
-// Add one particle to a tile of node slices (j0, j0+1) x node rows (l, l+1)
-// x 4 sources x nx held in LDS (the particle's cell row is (j0 or j0-1, l)).
-template <typename R>
-__device__ __forceinline__ void tile_add(R* __restrict__ tile, int nx, int j0, int jc, int i, R fz, R fy, R fx,
-                                         const R (&v)[4]) {
-  const int i1 = (i + 1 == nx) ? 0 : i + 1;
-  const R wz[2] = {R(1) - fz, fz}, wy[2] = {R(1) - fy, fy}, wx[2] = {R(1) - fx, fx};
-#pragma unroll
-  for (int dj = 0; dj < 2; ++dj) {
-    const int t = jc + dj - j0;
-    if (t < 0) continue;   // node slice -1 of a particle in front of the grid
-#pragma unroll
-    for (int dl = 0; dl < 2; ++dl) {
-      const R wc = wz[dj] * wy[dl];
-      R* tt = tile + ((t * 2 + dl) * 4) * nx;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        atomicAdd(tt + c * nx + i, v[c] * wc * wx[0]);
-        atomicAdd(tt + c * nx + i1, v[c] * wc * wx[1]);
-      }
-    }
-  }
-}
-
 // Add the accumulated nodes of one cell (node slices t0, t0+1 of the tile,
 // t0 = the cell's slice minus the tile's first; node rows l, l+1; columns
 // i, i+1; 4 sources) to a tile as tile_add lays it out.
 template <typename R>
-__device__ __forceinline__ void tile_add_cell(R* __restrict__ tile, int nx, int t0, int i,
+__device__ __forceinline__ void tile_add_cell(double* __restrict__ tile, int nx, int t0, int i,
                                               const R (&acc)[2][2][2][4]) {
   const int i1 = (i + 1 == nx) ? 0 : i + 1;
 #pragma unroll
@@ -1203,11 +1181,11 @@ __device__ __forceinline__ void tile_add_cell(R* __restrict__ tile, int nx, int 
     if (t0 + d < 0) continue;   // node slice -1 of a particle in front of the grid
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      R* tt = tile + (((t0 + d) * 2 + e) * 4) * nx;
+      double* tt = tile + (((t0 + d) * 2 + e) * 4) * nx;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        atomicAdd(tt + c * nx + i, acc[d][e][0][c]);
-        atomicAdd(tt + c * nx + i1, acc[d][e][1][c]);
+        atomicAdd(tt + c * nx + i, (double)acc[d][e][0][c]);
+        atomicAdd(tt + c * nx + i1, (double)acc[d][e][1][c]);
       }
     }
   }
@@ -1275,7 +1253,7 @@ __device__ __forceinline__ bool wave_segment_sum(int key, bool act, R (&acc)[2][
 // so a cell's particles sit on neighbouring lanes) before the LDS atomics,
 // which same-address conflicts would otherwise serialize.
 template <typename R, typename Src>
-__device__ __forceinline__ void deposit_pairs(R* __restrict__ tile, int nx, int64_t n, Src src) {
+__device__ __forceinline__ void deposit_pairs(double* __restrict__ tile, int nx, int64_t n, Src src) {
   const int t = threadIdx.x;
   for (int64_t base = 0; base < n; base += 2 * (int64_t)blockDim.x) {
     // a uniform trip count: every lane reaches the cross-lane sums
@@ -1339,16 +1317,16 @@ __device__ __forceinline__ void deposit_pairs(R* __restrict__ tile, int nx, int6
 template <typename R>
 __global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* tile = reinterpret_cast<R*>(smem_raw);
+  double* tile = reinterpret_cast<double*>(smem_raw);   // float64 for either precision
   const int b = blockIdx.x;
   const int jb = b / g.ny;
   const int tn = 2 * 2 * 4 * g.nx;
-  for (int t = threadIdx.x; t < tn; t += blockDim.x) tile[t] = R(0);
+  for (int t = threadIdx.x; t < tn; t += blockDim.x) tile[t] = 0.0;
   __syncthreads();
   for (int s = 0; s < a.ns; ++s) {
     const int nxc = nx_chunks(g);
     const int64_t q0 = a.doff[s][(int64_t)b * nxc], q1 = a.doff[s][(int64_t)(b + 1) * nxc];
-    deposit_pairs(tile, g.nx, q1 - q0, [&](int64_t k, int& t0, int& i, R& fz, R& fy, R& fx, R (&v)[4]) {
+    deposit_pairs<R>(tile, g.nx, q1 - q0, [&](int64_t k, int& t0, int& i, R& fz, R& fy, R& fx, R (&v)[4]) {
       const int p = a.perm[s][q0 + k];
       int jc, l;
       beam_sources_of(g, a.x[s][p], a.y[s][p], a.xi[s][p], a.ux[s][p], a.uy[s][p], a.uz[s][p],
@@ -1358,7 +1336,7 @@ __global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a) {
   }
   __syncthreads();
   R* out = a.bpart + (int64_t)b * tn;
-  for (int t = threadIdx.x; t < tn; t += blockDim.x) out[t] = tile[t];
+  for (int t = threadIdx.x; t < tn; t += blockDim.x) out[t] = (R)tile[t];
 }
 
 // Beam particles reordered by cell row (a stable-in-runs counting sort):
@@ -1865,11 +1843,11 @@ __global__ void __launch_bounds__(256) k_pipe_deposit(const PipeBeam<R>* __restr
   if (jp < 0 || jp > g.nxi - 2 || L >= g.ny) return;
   // LDS: the tile, the row starts (ny + 1), scan scratch (16)
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* tile = reinterpret_cast<R*>(smem_raw);
+  double* tile = reinterpret_cast<double*>(smem_raw);   // float64 for either precision
   const int tn = 2 * 2 * 4 * g.nx;
   int* base = reinterpret_cast<int*>(tile + tn);
   int* ws = base + g.ny + 1;
-  for (int i = threadIdx.x; i < tn; i += blockDim.x) tile[i] = R(0);
+  for (int i = threadIdx.x; i < tn; i += blockDim.x) tile[i] = 0.0;
   __syncthreads();
   for (int s = 0; s < B.ns; ++s) {
     const int* cnt = B.base + s * (g.ny + 1);
@@ -1877,7 +1855,7 @@ __global__ void __launch_bounds__(256) k_pipe_deposit(const PipeBeam<R>* __restr
     const int64_t s0 = B.rowoff[s][(int64_t)jp * g.ny];
     const int64_t q0 = s0 + base[L], q1 = s0 + base[L + 1];
     __syncthreads();
-    deposit_pairs(tile, g.nx, q1 - q0, [&](int64_t k, int& t0, int& i, R& fz, R& fy, R& fx, R (&v)[4]) {
+    deposit_pairs<R>(tile, g.nx, q1 - q0, [&](int64_t k, int& t0, int& i, R& fz, R& fy, R& fx, R (&v)[4]) {
       const int p = B.perm[s][q0 + k];
       int jc, lc;
       beam_sources_of(g, B.x[s][p], B.y[s][p], B.xi[s][p], B.ux[s][p], B.uy[s][p], B.uz[s][p],
@@ -1887,7 +1865,7 @@ __global__ void __launch_bounds__(256) k_pipe_deposit(const PipeBeam<R>* __restr
   }
   __syncthreads();
   R* out = B.ring_next + ((int64_t)(jp & 1) * g.ny + L) * tn;
-  for (int i = threadIdx.x; i < tn; i += blockDim.x) out[i] = tile[i];
+  for (int i = threadIdx.x; i < tn; i += blockDim.x) out[i] = (R)tile[i];
 }
 
 // Node slice s of the next lane gets corner dj of slabs s - dj and corner k
