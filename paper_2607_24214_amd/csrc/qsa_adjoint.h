@@ -501,9 +501,9 @@ __device__ __forceinline__ TileBox box_reduce(BoxAcc b, int* red, int cap) {
   return x;
 }
 
-template <typename R>
-__device__ __forceinline__ void tile_zero(R* tile, const TileBox& b, int nch) {
-  for (int t = threadIdx.x; t < nch * b.nodes; t += blockDim.x) tile[t] = R(0);
+template <typename T>
+__device__ __forceinline__ void tile_zero(T* tile, const TileBox& b, int nch) {
+  for (int t = threadIdx.x; t < nch * b.nodes; t += blockDim.x) tile[t] = T(0);
   __syncthreads();
 }
 
@@ -581,19 +581,19 @@ __device__ __forceinline__ Merge merge_at(bool act, const Cic<R>& c, int nx) {
 
 // q times the linear shape at c into channel ch (transverse grid glob when
 // the box did not fit)
-template <int G, typename R>
-__device__ __forceinline__ void tile_add(R* tile, const TileBox& b, int ch, const Cic<R>& c, double q, R* glob,
+template <int G, typename R, typename T>
+__device__ __forceinline__ void tile_add(T* tile, const TileBox& b, int ch, const Cic<R>& c, double q, R* glob,
                                          const Merge& m) {
   if (!b.fits) {   // uniform over the block
     if (m.act && q != 0.0) cic_add(glob, c, q);
     return;
   }
-  R w[4] = {R(0), R(0), R(0), R(0)};
+  T w[4] = {T(0), T(0), T(0), T(0)};
   if (m.act) {
-    w[0] = (R)(q * (1 - c.fx) * (1 - c.fy));
-    w[1] = (R)(q * c.fx * (1 - c.fy));
-    w[2] = (R)(q * (1 - c.fx) * c.fy);
-    w[3] = (R)(q * c.fx * c.fy);
+    w[0] = (T)(q * (1 - c.fx) * (1 - c.fy));
+    w[1] = (T)(q * c.fx * (1 - c.fy));
+    w[2] = (T)(q * (1 - c.fx) * c.fy);
+    w[3] = (T)(q * c.fx * c.fy);
   }
   if (m.uni) {
 #pragma unroll
@@ -602,7 +602,7 @@ __device__ __forceinline__ void tile_add(R* tile, const TileBox& b, int ch, cons
   } else if (!m.act || q == 0.0) {
     return;
   }
-  R* t = tile + ch * b.nodes + (c.l0 - b.l0) * b.ni + (c.i0 - b.i0);
+  T* t = tile + ch * b.nodes + (c.l0 - b.l0) * b.ni + (c.i0 - b.i0);
   atomicAdd(t, w[0]);
   atomicAdd(t + 1, w[1]);
   atomicAdd(t + b.ni, w[2]);
@@ -611,8 +611,8 @@ __device__ __forceinline__ void tile_add(R* tile, const TileBox& b, int ch, cons
 
 // the touched tile nodes into the grids dst[ch] ([nz][ny][nx], nz = 1 for
 // a transverse grid); node slices outside [0, nz) are dropped
-template <typename R, int NCH>
-__device__ __forceinline__ void tile_flush(const Geo<R>& g, const R* tile, const TileBox& b, R* const* dst, int nz) {
+template <typename R, int NCH, typename T>
+__device__ __forceinline__ void tile_flush(const Geo<R>& g, const T* tile, const TileBox& b, R* const* dst, int nz) {
   __syncthreads();
   const int nli = b.nl * b.ni;
   for (int t = threadIdx.x; t < b.nodes; t += blockDim.x) {
@@ -627,8 +627,8 @@ __device__ __forceinline__ void tile_flush(const Geo<R>& g, const R* tile, const
     const int64_t off = (int64_t)j * g.nperp + (int64_t)l * g.nx + i;
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
-      const R v = tile[ch * b.nodes + t];
-      if (v != R(0)) atomic_add(dst[ch] + off, v);
+      const T v = tile[ch * b.nodes + t];
+      if (v != T(0)) atomic_add(dst[ch] + off, (R)v);
     }
   }
 }
@@ -764,7 +764,7 @@ __device__ __forceinline__ void rk2_adj(const Geo<R>& g, const Six<R>& F, double
 // channels 0..5: fields of slice j (stage 1, and 3/2 of stage 2); 6..11:
 // fields of slice j - 1 (-1/2 of stage 2)
 template <typename R>
-__device__ __forceinline__ void rk2_bar_add(R* tile, const TileBox& b, const Rk2Bar<R>& o, const SixBar<R>& Fb,
+__device__ __forceinline__ void rk2_bar_add(double* tile, const TileBox& b, const Rk2Bar<R>& o, const SixBar<R>& Fb,
                                             const Merge& m0, const Merge& m1) {
   for (int m = 0; m < 6; ++m) {
     tile_add<4>(tile, b, m, o.c0, o.g0[m], Fb.a[m], m0);
@@ -800,13 +800,17 @@ struct AdjPlasma {
 
 // LDS of a tile kernel (dynamic, tile_bytes of the launch): 512 bytes of
 // scratch (box reduction: 6 ints per wavefront from byte 0; per-wavefront
-// doubles from byte 384), then NCH channels of CAP_ nodes.
-#define ADJ_TILE(NCH, BYTES)                                              \
+// doubles from byte 384), then NCH channels of CAP_ nodes of type T.  The
+// plasma transposes accumulate in float64 for either precision (LDS float32
+// atomic adds are slower per instruction on this part); the beam kernels'
+// 3D tiles measured faster in the working precision.
+#define ADJ_TILE(NCH, BYTES, T)                                           \
   constexpr int NCH_ = (NCH);                                             \
+  using T_ = T;                                                           \
   extern __shared__ __align__(16) unsigned char smem_raw[];               \
   int* red = reinterpret_cast<int*>(smem_raw);                            \
-  R* tile = reinterpret_cast<R*>(smem_raw + 512);                         \
-  const int CAP_ = ((int)(BYTES) - 512) / (NCH_ * (int)sizeof(R));        \
+  T_* tile = reinterpret_cast<T_*>(smem_raw + 512);                       \
+  const int CAP_ = ((int)(BYTES) - 512) / (NCH_ * (int)sizeof(T_));       \
   BoxAcc bx;                                                              \
   box_init(bx)
 
@@ -814,7 +818,7 @@ struct AdjPlasma {
 template <typename R>
 __global__ void __launch_bounds__(256) k_af_dep_s(AdjPlasma<R> a, R* __restrict__ S, Side<R> side) {
   run_side(side);
-  ADJ_TILE(1, a.tile_bytes);
+  ADJ_TILE(1, a.tile_bytes, double);
   const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
   Cic<R> c{};
@@ -834,7 +838,7 @@ __global__ void __launch_bounds__(256) k_af_dep_s(AdjPlasma<R> a, R* __restrict_
 template <typename R>
 __global__ void __launch_bounds__(256) k_af_dep_j(AdjPlasma<R> a, Side<R> side) {
   run_side(side);
-  ADJ_TILE(3, a.tile_bytes);
+  ADJ_TILE(3, a.tile_bytes, double);
   double* wsum = reinterpret_cast<double*>(smem_raw + 384);   // per-wavefront J_z sums
   const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
@@ -875,7 +879,7 @@ __global__ void __launch_bounds__(256) k_af_dep_j(AdjPlasma<R> a, Side<R> side) 
 template <typename R>
 __global__ void __launch_bounds__(256) k_af_pred(AdjPlasma<R> a, Side<R> side) {
   run_side(side);
-  ADJ_TILE(2, a.tile_bytes);
+  ADJ_TILE(2, a.tile_bytes, double);
   const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
   Cic<R> c{};
@@ -928,7 +932,7 @@ __device__ __forceinline__ void six_bar_dst(const SixBar<R>& Fb, R** dst) {
 template <typename R>
 __global__ void __launch_bounds__(256) k_ar_final(AdjPlasma<R> a, Side<R> side) {
   run_side(side);
-  ADJ_TILE(12, a.tile_bytes);
+  ADJ_TILE(12, a.tile_bytes, double);
   const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
   Rk2Bar<R> o{};
@@ -954,7 +958,7 @@ __global__ void __launch_bounds__(256) k_ar_final(AdjPlasma<R> a, Side<R> side) 
 template <typename R>
 __global__ void __launch_bounds__(256) k_ar_pred(AdjPlasma<R> a, Side<R> side) {
   run_side(side);
-  ADJ_TILE(13, a.tile_bytes);
+  ADJ_TILE(13, a.tile_bytes, double);
   const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
   const Geo<R>& g = a.g;
@@ -1008,7 +1012,7 @@ __global__ void __launch_bounds__(256) k_ar_pred(AdjPlasma<R> a, Side<R> side) {
 template <typename R>
 __global__ void __launch_bounds__(256) k_ar_jstage(AdjPlasma<R> a, Side<R> side) {
   run_side(side);
-  ADJ_TILE(1, a.tile_bytes);
+  ADJ_TILE(1, a.tile_bytes, double);
   const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.np;
   const Geo<R>& g = a.g;
@@ -1167,20 +1171,20 @@ __device__ __forceinline__ Merge merge_at3(bool act, const Cic3<R>& c, int nx) {
   return merge_of<G>(act && c.in, c.c.l0 * nx + c.c.i0, c.j0 + 1);
 }
 
-template <int G, typename R>
-__device__ __forceinline__ void tile_add3(const Geo<R>& g, R* tile, const TileBox& b, int ch, const Cic3<R>& c,
+template <int G, typename R, typename T>
+__device__ __forceinline__ void tile_add3(const Geo<R>& g, T* tile, const TileBox& b, int ch, const Cic3<R>& c,
                                           double q, R* glob, const Merge& m) {
   if (!b.fits) {   // uniform over the block
     if (m.act && q != 0.0) cic3_add(g, glob, c, q);
     return;
   }
-  R w[2][4];
+  T w[2][4];
   for (int d = 0; d < 2; ++d) {
     const double qd = m.act ? q * (d ? c.fz : 1.0 - c.fz) : 0.0;
-    w[d][0] = (R)(qd * (1 - c.c.fx) * (1 - c.c.fy));
-    w[d][1] = (R)(qd * c.c.fx * (1 - c.c.fy));
-    w[d][2] = (R)(qd * (1 - c.c.fx) * c.c.fy);
-    w[d][3] = (R)(qd * c.c.fx * c.c.fy);
+    w[d][0] = (T)(qd * (1 - c.c.fx) * (1 - c.c.fy));
+    w[d][1] = (T)(qd * c.c.fx * (1 - c.c.fy));
+    w[d][2] = (T)(qd * (1 - c.c.fx) * c.c.fy);
+    w[d][3] = (T)(qd * c.c.fx * c.c.fy);
   }
   if (m.uni) {
 #pragma unroll
@@ -1192,7 +1196,7 @@ __device__ __forceinline__ void tile_add3(const Geo<R>& g, R* tile, const TileBo
     return;
   }
   for (int d = 0; d < 2; ++d) {
-    R* t = tile + ch * b.nodes + ((c.j0 + d - b.j0) * b.nl + (c.c.l0 - b.l0)) * b.ni + (c.c.i0 - b.i0);
+    T* t = tile + ch * b.nodes + ((c.j0 + d - b.j0) * b.nl + (c.c.l0 - b.l0)) * b.ni + (c.c.i0 - b.i0);
     atomicAdd(t, w[d][0]);
     atomicAdd(t + 1, w[d][1]);
     atomicAdd(t + b.ni, w[d][2]);
@@ -1254,7 +1258,7 @@ __device__ __forceinline__ void beam_v(double ux, double uy, double uz, double (
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_ab_sources(AdjBeam<R> a) {
-  ADJ_TILE(4, a.tile_bytes);
+  ADJ_TILE(4, a.tile_bytes, R);
   const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.n && a.w[p] != R(0);
   Cic3<R> c{};
@@ -1362,7 +1366,7 @@ __device__ __forceinline__ void push_adj_one(const AdjBeam<R>& a, int64_t p, con
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_ab_push_adj(AdjBeam<R> a) {
-  ADJ_TILE(6, a.tile_bytes);
+  ADJ_TILE(6, a.tile_bytes, R);
   const int64_t p = (int64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const bool live = p < a.n;
   Cic3<R> c{};
