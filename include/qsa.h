@@ -82,7 +82,7 @@ enum {
 };
 
 #define QSA_MAX_SPECIES 4
-#define QSA_MAX_PIPELINE 8
+#define QSA_MAX_PIPELINE 16
 
 typedef struct {
   int32_t Z;        /* charge number: -1 electron, +1 positron              */
@@ -105,7 +105,7 @@ typedef struct {
   double plasma_w;       /* their common weight: area per particle (> 0)     */
   qsa_species species[QSA_MAX_SPECIES];
   int64_t beam_capacity[QSA_MAX_SPECIES]; /* max particles per species (>= 0) */
-  int32_t pipeline;      /* beam steps in flight in qsa_beam_step, 0..8 (0 and 1:
+  int32_t pipeline;      /* beam steps in flight in qsa_beam_step, 0..16 (0 and 1:
                             one step at a time).  With P > 1 the workspace holds
                             P working sets (sources, fields, plasma state) and a
                             copy of the beam; see qsa_beam_step.             */

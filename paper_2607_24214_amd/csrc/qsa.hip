@@ -244,7 +244,7 @@ const char* validate(const qsa_params* p) {
   if (p->n_species < 1 || p->n_species > QSA_MAX_SPECIES) return "n_species must be in [1, 4]";
   if ((int64_t)p->nxi * p->ny * (p->nx / QSA_BEAM_XCHUNK) > ((int64_t)1 << 30))
     return "nxi * ny * nx / 8 must be <= 2^30";
-  if (p->pipeline < 0 || p->pipeline > QSA_MAX_PIPELINE) return "pipeline must be in [0, 8]";
+  if (p->pipeline < 0 || p->pipeline > QSA_MAX_PIPELINE) return "pipeline must be in [0, 16]";
   if (p->adjoint_steps < 0 || p->adjoint_steps > 1024) return "adjoint_steps must be in [0, 1024]";
   for (int s = 0; s < p->n_species; ++s) {
     if (p->beam_capacity[s] < 0 || p->beam_capacity[s] > INT32_MAX) return "beam capacity must be in [0, 2^31)";

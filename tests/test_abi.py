@@ -78,7 +78,8 @@ def test_pipeline_workspace_and_validation():
     four = lib.qsa_workspace_bytes(C.byref(_params(pipeline=4)))
     # three more sets of fields (7) and sources (4), and the beam copy
     assert four >= one + 3 * (7 + 4) * 128 * 64 * 8 + 65024 * 7 * 8
-    assert lib.qsa_workspace_bytes(C.byref(_params(pipeline=9))) == 0
+    assert lib.qsa_workspace_bytes(C.byref(_params(pipeline=16))) > four
+    assert lib.qsa_workspace_bytes(C.byref(_params(pipeline=17))) == 0
     assert lib.qsa_workspace_bytes(C.byref(_params(pipeline=-1))) == 0
     p = _params()
     p.adjoint_steps = -1

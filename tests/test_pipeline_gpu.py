@@ -69,6 +69,18 @@ def test_pipeline_deeper_than_box_fp64():
     _compare("8 in flight, nxi 12", pip, seq, 1e-10, 1e-11)
 
 
+def test_pipeline_sixteen_deep_fp64():
+    """The deepest pipeline: sixteen steps in flight (lags up to 120 slices,
+    beyond a 24-slice box), as one group and then as a group of 5."""
+    wl = W.small_3d(16, 16, 24).with_(dt=10.0)
+    seq, pip = _sim(wl, 1), _sim(wl, 16)
+    for n in (16, 5):
+        seq.beam_step(n)
+        pip.beam_step(n)
+        _compare(f"16 in flight, +{n} steps", pip, seq, 1e-10, 1e-11)
+    assert pip.pipeline == 16
+
+
 def test_pipelined_slab_fp64():
     wl = W.slab_electron()
     seq, pip = _sim(wl, 1), _sim(wl, 4)
