@@ -39,13 +39,13 @@ struct Geo {
   R lx, ly, inv_lx, inv_ly;
 };
 
-// Wrap an integer cell index into [0, n); any input (also from a non-finite
-// coordinate) lands inside the grid, so no access can leave the array.
-__device__ __forceinline__ int wrap_index(int v, int n) {
-  v %= n;
-  v += (v < 0) ? n : 0;
-  return ((unsigned)v < (unsigned)n) ? v : 0;
-}
+// Wrap an integer cell index into [0, n) for n a power of two (the library
+// accepts no other grid sizes): the two's-complement mask is the periodic
+// wrap for negative indices too, and any input (also from a non-finite
+// coordinate) lands inside the grid, so no access can leave the array.  (An
+// integer remainder by a runtime n costs a long division sequence, several
+// of them per particle.)
+__device__ __forceinline__ int wrap_index(int v, int n) { return v & (n - 1); }
 
 // Four nodes and weights of the linear shape at (x, y).
 template <typename R>
