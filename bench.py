@@ -217,6 +217,40 @@ def scan_rate(n_inst: int, steps: int, warmup: int):
     return out
 
 
+def diagnostics_rate(sim, wl, rsize):
+    """Device diagnostics of the last sweep (windows of 2 c/omega_p): the
+    field-moment reduction reads six stored field planes once, the beam
+    moments each beam particle's xi, u and w once; wall time per call
+    (launches and the call's own synchronization included), against
+    copying the same six fields of every slice to the host."""
+    import torch
+    ws = max(1, int(round(2.0 / wl.dxi)))
+    sim.field_moments(ws, on_device=True)
+    sim.beam_moments(0, ws, on_device=True)
+    reps = 5
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        sim.field_moments(ws, on_device=True)
+    tf = (time.perf_counter() - t) / reps
+    t = time.perf_counter()
+    for _ in range(reps):
+        sim.beam_moments(0, ws, on_device=True)
+    tb = (time.perf_counter() - t) / reps
+    t = time.perf_counter()
+    for name in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        sim.fields(name)
+    th = time.perf_counter() - t
+    bf = 6 * wl.nxi * wl.nx * wl.ny * rsize
+    bb = wl.n_beam_total * (8 + 4 * rsize)
+    return {"window_slices": ws,
+            "field_moments_ms": 1e3 * tf, "field_moments_GB_s": bf / tf / 1e9,
+            "field_moments_frac_hbm": bf / tf / 1e9 / HBM_PEAK_GBS,
+            "beam_moments_ms": 1e3 * tb, "beam_moments_GB_s": bb / tb / 1e9,
+            "host_copy_of_the_six_fields_ms": 1e3 * th,
+            "timing": "wall clock per synchronizing call, 5 calls each, after one untimed call"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +273,8 @@ def main():
                     help="only run a plain device copy of 2 GiB three times (scale for HBM counters)")
     ap.add_argument("--breakdown", action="store_true",
                     help="also time every kernel class over one extra group of steps each")
+    ap.add_argument("--no-diagnostics", action="store_true",
+                    help="skip the device diagnostics measurement")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the adjoint/forward time of the 128x128x256 adjoint workload")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -349,6 +385,13 @@ def main():
     torch.cuda.synchronize()
     t_sweep = time.perf_counter() - t
 
+    diag = None
+    if not args.no_diagnostics:
+        diag = diagnostics_rate(sim, wl, rsize)
+        log(f"diagnostics: field moments {diag['field_moments_ms']:.3f} ms "
+            f"({diag['field_moments_GB_s']:.0f} GB/s), beam moments {diag['beam_moments_ms']:.3f} ms, "
+            f"host copy of the fields {diag['host_copy_of_the_six_fields_ms']:.0f} ms")
+
     # per-class times over further groups of steps (after the timed region,
     # which they would otherwise move to a later, more evolved beam)
     breakdown = {}
@@ -413,6 +456,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "adjoint": adjoint,
+        "diagnostics": diag,
     }
     if breakdown:
         out["kernel_breakdown_ms_per_step"] = {k: round(v["ms_per_step"], 3) for k, v in breakdown.items()}

@@ -181,6 +181,28 @@ qsa_status qsa_beam_step(qsa_ctx* c, int32_t n_steps);
 qsa_status qsa_fields(qsa_ctx* c, int32_t field, int32_t xi0, int32_t xi1,
                       double* dst, size_t count, int32_t dst_on_device);
 
+/* Diagnostics of the last sweep, reduced on the device (no copy of the 3D
+ * fields): the transverse field amplitudes and field energies the paper
+ * follows at positions along the beam (Fig. 2; Fig. 3(d,e) and the
+ * saturation estimates, which take eps_F = <F^2>/(4 n_b gamma_b) in these
+ * units).  Slices are grouped in windows of `window` consecutive slices
+ * (the last one may be shorter).  dst[w*6 + f] = the mean over window w's
+ * slices of the transverse mean of F^2, F = (E_x, E_y, E_z, B_x, B_y, B_z)
+ * in that order (E_x = -d_x psi + B_y, E_y = -d_y psi - B_x); count >=
+ * 6 ceil(nxi/window) doubles, host or device memory (dst_on_device).
+ * Accumulated in float64.  Synchronizing; QSA_E_STATE before any sweep. */
+qsa_status qsa_field_moments(qsa_ctx* c, int32_t window, double* dst, size_t count, int32_t dst_on_device);
+
+/* Beam momentum moments of species s (the spreads of the paper's Fig.
+ * 3(f)): dst[w*7 + k] = the sum over the particles with w_p != 0 and slice
+ * floor(xi/dxi) in window w (slices [0, nxi) only) of k = (w_p, w_p u_x,
+ * w_p u_y, w_p u_z, w_p u_x^2, w_p u_y^2, w_p u_z^2); the weighted RMS
+ * spread is sqrt(sum w u^2/sum w - (sum w u/sum w)^2).  count >=
+ * 7 ceil(nxi/window) doubles, host or device memory.  Accumulated in float64
+ * (atomic sums: the order of additions varies).  Synchronizing. */
+qsa_status qsa_beam_moments(qsa_ctx* c, int32_t species, int32_t window, double* dst, size_t count,
+                            int32_t dst_on_device);
+
 /* Wait for the stream and report any pending device error. */
 qsa_status qsa_sync(qsa_ctx* c);
 

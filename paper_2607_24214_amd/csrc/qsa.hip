@@ -137,6 +137,7 @@ struct Layout {
   size_t beam[QSA_MAX_SPECIES][8];  // x, y, ux, uy, uz, w (real), xi (double), id (int64, pipelining)
   size_t snap[QSA_MAX_SPECIES][8];  // sort target and the beam at the start of a pipelined group
   size_t err, emit, lane, pipe;
+  size_t diag;                      // diagnostics: 7 doubles per slice
   AdjLayout adj;                    // adjoint tapes and arrays (adjoint_steps > 0)
   size_t total;
 };
@@ -221,6 +222,7 @@ Layout make_layout(const qsa_params& p) {
   }
   L.err = c.take(sizeof(int));
   L.emit = c.take(nperp * sizeof(double));
+  L.diag = c.take(7 * (size_t)p.nxi * sizeof(double));
   L.lane = c.take(L.nset * sizeof(Lane<double>));
   L.pipe = c.take(L.nset * sizeof(PipeBeam<double>));
   adjoint_layout(p, c.off, L.adj);
@@ -1026,6 +1028,45 @@ struct Engine {
     return QSA_OK;
   }
 
+  // Diagnostics: per-window field mean squares of the last sweep, beam
+  // moments of species s (k_field_moments, k_beam_moments).
+  static qsa_status moments_out(qsa_ctx* c, double* out, double* dst, int64_t n, int on_device) {
+    if (!on_device)
+      HIP_OK(hipMemcpyAsync(dst, out, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return QSA_OK;
+  }
+
+  static qsa_status field_moments(qsa_ctx* c, int ws, double* dst, int on_device) {
+    const qsa_params& p = c->p;
+    const Geo<R> g = geo(p);
+    const int64_t n = 6 * (int64_t)((p.nxi + ws - 1) / ws);
+    double* out = on_device ? dst : c->at<double>(c->L.diag);
+    hipLaunchKernelGGL(k_fill<double>, dim3(fill_blocks(n)), dim3(256), 0, c->stream, out, n, 0.0);
+    hipLaunchKernelGGL(k_field_moments<R>, dim3(p.nxi), dim3(256), 0, c->stream, g,
+                       (const R*)c->at<R>(c->L.set[c->cur_set].fields), ws, out);
+    HIP_OK(hipGetLastError());
+    return moments_out(c, out, dst, n, on_device);
+  }
+
+  static qsa_status beam_moments(qsa_ctx* c, int s, int ws, double* dst, int on_device) {
+    const qsa_params& p = c->p;
+    const int64_t n = 7 * (int64_t)((p.nxi + ws - 1) / ws);
+    double* out = on_device ? dst : c->at<double>(c->L.diag);
+    hipLaunchKernelGGL(k_fill<double>, dim3(fill_blocks(n)), dim3(256), 0, c->stream, out, n, 0.0);
+    const int64_t np = c->beam_n[s];
+    if (np > 0) {
+      const Layout& L = c->L;
+      hipLaunchKernelGGL(k_beam_moments<R>, dim3((unsigned)((np + QSA_DIAG_CHUNK - 1) / QSA_DIAG_CHUNK)),
+                         dim3(256), 0, c->stream, (const double*)c->at<double>(L.beam[s][6]),
+                         (const R*)c->at<R>(L.beam[s][2]), (const R*)c->at<R>(L.beam[s][3]),
+                         (const R*)c->at<R>(L.beam[s][4]), (const R*)c->at<R>(L.beam[s][5]), np, 1.0 / p.dxi,
+                         p.nxi, ws, out);
+      HIP_OK(hipGetLastError());
+    }
+    return moments_out(c, out, dst, n, on_device);
+  }
+
   // Launch limits on LDS: beam tiles (2 node slices x 2 node rows x 4
   // sources x nx) stay within 64 KiB for nx <= 512; the column transforms of
   // tall grids opt in to more.
@@ -1619,6 +1660,39 @@ qsa_status qsa_fields(qsa_ctx* c, int32_t field, int32_t xi0, int32_t xi1, doubl
   if (st != QSA_OK) return st;
   st = dispatch(c, [&] { return Engine<double>::fields(c, field, xi0, xi1, dst, dst_on_device); },
                            [&] { return Engine<float>::fields(c, field, xi0, xi1, dst, dst_on_device); });
+  if (st != QSA_OK) return st;
+  if ((st = leave(c)) != QSA_OK) return st;
+  return check_device(c);
+}
+
+qsa_status qsa_field_moments(qsa_ctx* c, int32_t window, double* dst, size_t count, int32_t dst_on_device) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (!c->swept) return fail(c, QSA_E_STATE, "no sweep has run");
+  if (window < 1) return fail(c, QSA_E_INVALID, "window must be at least one slice");
+  const size_t need = 6 * (size_t)((c->p.nxi + window - 1) / window);
+  if (!dst || count < need) return fail(c, QSA_E_INVALID, "destination too small");
+  qsa_status st = enter(c);
+  if (st != QSA_OK) return st;
+  st = dispatch(c, [&] { return Engine<double>::field_moments(c, window, dst, dst_on_device); },
+                [&] { return Engine<float>::field_moments(c, window, dst, dst_on_device); });
+  if (st != QSA_OK) return st;
+  if ((st = leave(c)) != QSA_OK) return st;
+  return check_device(c);
+}
+
+qsa_status qsa_beam_moments(qsa_ctx* c, int32_t species, int32_t window, double* dst, size_t count,
+                            int32_t dst_on_device) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (species < 0 || species >= c->p.n_species) return fail(c, QSA_E_INVALID, "unknown species");
+  if (window < 1) return fail(c, QSA_E_INVALID, "window must be at least one slice");
+  const size_t need = 7 * (size_t)((c->p.nxi + window - 1) / window);
+  if (!dst || count < need) return fail(c, QSA_E_INVALID, "destination too small");
+  qsa_status st = enter(c);
+  if (st != QSA_OK) return st;
+  st = dispatch(c, [&] { return Engine<double>::beam_moments(c, species, window, dst, dst_on_device); },
+                [&] { return Engine<float>::beam_moments(c, species, window, dst, dst_on_device); });
   if (st != QSA_OK) return st;
   if ((st = leave(c)) != QSA_OK) return st;
   return check_device(c);

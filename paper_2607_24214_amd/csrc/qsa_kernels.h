@@ -1047,6 +1047,114 @@ struct BeamArgs {
   double xi_max;      // (nxi - 1) dxi: particles at or beyond it leave the box
 };
 
+// ------------------------------------------------------------- diagnostics
+// Field moments of a sweep: block j reduces slice j of the stored fields to
+// the transverse means of E_x^2, E_y^2, E_z^2, B_x^2, B_y^2, B_z^2 (E_x =
+// -d_x psi + B_y, E_y = -d_y psi - B_x) in float64 and adds mean/cnt to the
+// six sums of its window of ws slices (cnt = the window's slice count);
+// out[(j/ws)*6 + f] must start at zero.
+template <typename R>
+__global__ void __launch_bounds__(256) k_field_moments(Geo<R> g, const R* __restrict__ fields, int ws,
+                                                       double* __restrict__ out) {
+  const int j = blockIdx.x;
+  if (j >= g.nxi) return;
+  const int64_t plane = (int64_t)g.nxi * g.nperp;
+  const R* f = fields + (int64_t)j * g.nperp;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (int o = threadIdx.x; o < g.nperp; o += blockDim.x) {
+    const double dx = f[F_DXPSI * plane + o], dy = f[F_DYPSI * plane + o], ez = f[F_EZ * plane + o];
+    const double bx = f[F_BX * plane + o], by = f[F_BY * plane + o], bz = f[F_BZ * plane + o];
+    const double ex = -dx + by, ey = -dy - bx;
+    s[0] += ex * ex;
+    s[1] += ey * ey;
+    s[2] += ez * ez;
+    s[3] += bx * bx;
+    s[4] += by * by;
+    s[5] += bz * bz;
+  }
+  __shared__ double red[4][6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+    for (int off = 32; off >= 1; off >>= 1) s[q] += __shfl_xor(s[q], off);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) red[threadIdx.x >> 6][q] = s[q];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w][threadIdx.x];
+    const int win = j / ws;
+    const int cnt = min(ws, g.nxi - win * ws);
+    atomicAdd(out + (int64_t)win * 6 + threadIdx.x, t / ((double)g.nperp * cnt));
+  }
+}
+
+// Beam moments of one species: for the particles with w != 0 and slice j =
+// floor(xi/dxi) in [0, nxi), the sums of (w, w u_x, w u_y, w u_z, w u_x^2,
+// w u_y^2, w u_z^2) over each window of ws slices, into out[(j/ws)*7 + k]
+// (zeroed before).  Block b takes particles [b CH, (b+1) CH); a thread sums
+// in registers while its window stays the same (beam particles come sorted
+// by slice) and folds the sums into an LDS window of QSA_DIAG_WIN windows
+// from the block's first particle on, or straight into out outside it.
+#define QSA_DIAG_WIN 32
+#define QSA_DIAG_CHUNK 4096
+template <typename R>
+__global__ void __launch_bounds__(256) k_beam_moments(const double* __restrict__ xi, const R* __restrict__ ux,
+                                                      const R* __restrict__ uy, const R* __restrict__ uz,
+                                                      const R* __restrict__ w, int64_t n, double inv_dxi, int nxi,
+                                                      int ws, double* __restrict__ out) {
+  __shared__ double bins[QSA_DIAG_WIN][7];
+  __shared__ int wb_s;
+  const int64_t c0 = (int64_t)blockIdx.x * QSA_DIAG_CHUNK;
+  for (int t = threadIdx.x; t < QSA_DIAG_WIN * 7; t += blockDim.x) (&bins[0][0])[t] = 0.0;
+  if (threadIdx.x == 0) {
+    const double gz = (c0 < n) ? floor(xi[c0] * inv_dxi) : 0.0;
+    wb_s = (gz >= 0.0 && gz < (double)nxi) ? (int)gz / ws : 0;
+  }
+  __syncthreads();
+  const int wb = wb_s, nwin = (nxi + ws - 1) / ws;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  int cur = -1;
+  auto flush = [&]() {
+    if (cur < 0) return;
+    const int k = cur - wb;
+    if (k >= 0 && k < QSA_DIAG_WIN) {
+#pragma unroll
+      for (int q = 0; q < 7; ++q) atomicAdd(&bins[k][q], acc[q]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 7; ++q) atomicAdd(out + (int64_t)cur * 7 + q, acc[q]);
+    }
+  };
+  const int64_t c1 = min(n, c0 + (int64_t)QSA_DIAG_CHUNK);
+  for (int64_t p = c0 + threadIdx.x; p < c1; p += blockDim.x) {
+    const double wp = (double)w[p];
+    const double gz = floor(xi[p] * inv_dxi);
+    if (wp == 0.0 || !(gz >= 0.0 && gz < (double)nxi)) continue;
+    const int win = (int)gz / ws;
+    if (win != cur) {
+      flush();
+      cur = win;
+#pragma unroll
+      for (int q = 0; q < 7; ++q) acc[q] = 0.0;
+    }
+    const double u[3] = {(double)ux[p], (double)uy[p], (double)uz[p]};
+    acc[0] += wp;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      acc[1 + a] += wp * u[a];
+      acc[4 + a] += wp * u[a] * u[a];
+    }
+  }
+  flush();
+  __syncthreads();
+  for (int t = threadIdx.x; t < QSA_DIAG_WIN * 7; t += blockDim.x) {
+    const int k = t / 7, q = t - k * 7;
+    const double v = bins[k][q];
+    if (v != 0.0 && wb + k < nwin) atomicAdd(out + (int64_t)(wb + k) * 7 + q, v);
+  }
+}
+
 // ------------------------------------------------------- beam source deposit
 // Run-aggregated counter increments: every active lane of a wavefront takes
 // the next slot of counter cnt[key]; consecutive lanes with equal keys (the

@@ -220,6 +220,37 @@ class Sim:
                                             C.c_void_p(out.ctypes.data), n, 0))
         return out
 
+    FIELD_MOMENTS = ("Ex", "Ey", "Ez", "Bx", "By", "Bz")
+    BEAM_MOMENTS = ("w", "wux", "wuy", "wuz", "wux2", "wuy2", "wuz2")
+
+    def field_moments(self, window: int = 1, on_device: bool = False):
+        """[n_windows, 6] float64: per window of `window` slices, the mean of
+        the transverse means of E_x^2, E_y^2, E_z^2, B_x^2, B_y^2, B_z^2 of
+        the last sweep (qsa_field_moments)."""
+        nw = -(-self.params.nxi // window) if window >= 1 else 1   # the library rejects window < 1
+        if on_device:
+            out = torch.empty((nw, 6), dtype=torch.float64, device=self.device)
+            self._check(self.lib.qsa_field_moments(self.ctx, window, C.c_void_p(out.data_ptr()), out.numel(), 1))
+        else:
+            out = np.empty((nw, 6))
+            self._check(self.lib.qsa_field_moments(self.ctx, window, C.c_void_p(out.ctypes.data), out.size, 0))
+        return out
+
+    def beam_moments(self, species: int = 0, window: int = 1, on_device: bool = False):
+        """[n_windows, 7] float64: per window of `window` slices, the sums of
+        (w, w u_x, w u_y, w u_z, w u_x^2, w u_y^2, w u_z^2) over the beam
+        particles of species s in it (qsa_beam_moments)."""
+        nw = -(-self.params.nxi // window) if window >= 1 else 1
+        if on_device:
+            out = torch.empty((nw, 7), dtype=torch.float64, device=self.device)
+            self._check(self.lib.qsa_beam_moments(self.ctx, species, window, C.c_void_p(out.data_ptr()),
+                                                  out.numel(), 1))
+        else:
+            out = np.empty((nw, 7))
+            self._check(self.lib.qsa_beam_moments(self.ctx, species, window, C.c_void_p(out.ctypes.data),
+                                                  out.size, 0))
+        return out
+
 
 class Batch:
     """Several Sims advanced together: their slice loops run as lanes of the
