@@ -251,6 +251,39 @@ def diagnostics_rate(sim, wl, rsize):
             "timing": "wall clock per synchronizing call, 5 calls each, after one untimed call"}
 
 
+def linear_model_scan():
+    """A growth-rate scan for the linear model (Eq. 5): 64 instances (Gamma
+    spread over a factor 4 around Gamma0 = 0.05 omega_p, random seeds), xi in
+    [0, 40] at 0.02 (2001 points), RK4 with Gamma0 dtau = 0.01 up to
+    Gamma0 tau = 8 (800 steps), outputs at every Gamma0 tau = 0.5."""
+    import numpy as np
+    rng = np.random.default_rng(11)
+    n_inst, g0 = 64, 0.05
+    gam = g0 * np.exp(rng.uniform(np.log(0.5), np.log(2.0), n_inst))
+    xi = np.arange(2001) * 0.02
+    seeds = rng.uniform(-1.0, 1.0, (n_inst, xi.size))
+    return gam, xi, seeds, 0.01 / g0, np.arange(0, 17) * 0.5 / g0
+
+
+def linear_model_rate():
+    """The batched solver on linear_model_scan(): wall time of the
+    synchronized launch."""
+    import torch
+    import paper_2607_24214_amd as Q
+    gam, xi, seeds, dtau, taus = linear_model_scan()
+    n_inst = gam.size
+    Q.linear_model(gam, seeds, 0.02, taus[:2], dtau)      # first launch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Q.linear_model(gam, seeds, 0.02, taus, dtau)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t
+    steps = int(round(taus[-1] / dtau))
+    work = n_inst * xi.size * steps
+    return {"instances": n_inst, "xi_points": int(xi.size), "rk4_steps": steps, "ms": 1e3 * tg,
+            "point_steps_per_s": work / tg}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +306,8 @@ def main():
                     help="only run a plain device copy of 2 GiB three times (scale for HBM counters)")
     ap.add_argument("--breakdown", action="store_true",
                     help="also time every kernel class over one extra group of steps each")
+    ap.add_argument("--no-linear-model", action="store_true",
+                    help="skip the linear-model solver measurement")
     ap.add_argument("--no-diagnostics", action="store_true",
                     help="skip the device diagnostics measurement")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -420,6 +455,11 @@ def main():
         "alg_bytes_per_launch": per_launch,
         "slices_per_launch": lane_slices / max(dom_n, 1),
     }
+    linear = None
+    if not args.no_linear_model:
+        linear = linear_model_rate()
+        log(f"linear model: {linear['instances']} instances x {linear['xi_points']} points x "
+            f"{linear['rk4_steps']} RK4 steps in {linear['ms']:.1f} ms")
     adjoint = None
     if not args.no_adjoint:
         del sim
@@ -433,6 +473,15 @@ def main():
         log(f"oracle baseline on {args.cpu_slices} slices ...")
         cpu = cpu_baseline(wl, args.cpu_slices)
         log(f"oracle: {cpu['value']:.3e} updates/s on {cpu['cores']} threads")
+        if linear is not None:
+            # the oracle's solver of the linear model on one instance of the scan
+            from oracle import linear_theory as LT
+            gam, xi, seeds, dtau, taus = linear_model_scan()
+            t = time.perf_counter()
+            LT.solve_eq5(float(gam[0]), xi, seeds[0], taus, dtau)
+            to = time.perf_counter() - t
+            cpu["linear_model"] = {"one_instance_ms": 1e3 * to,
+                                   "point_steps_per_s": xi.size * int(round(taus[-1] / dtau)) / to}
 
     out = {
         "metric": "plasma particle-slice updates/s (push+deposit+solve)",
@@ -457,6 +506,7 @@ def main():
         "cpu_baseline": cpu,
         "adjoint": adjoint,
         "diagnostics": diag,
+        "linear_model": linear,
     }
     if breakdown:
         out["kernel_breakdown_ms_per_step"] = {k: round(v["ms_per_step"], 3) for k, v in breakdown.items()}

@@ -203,6 +203,26 @@ qsa_status qsa_field_moments(qsa_ctx* c, int32_t window, double* dst, size_t cou
 qsa_status qsa_beam_moments(qsa_ctx* c, int32_t species, int32_t window, double* dst, size_t count,
                             int32_t dst_on_device);
 
+/* Batched solver of the single-mode linear model, Eq. (5) of the paper,
+ * [(d_xi^2 + 1) d_tau^2 - Gamma^2] dPsi = 0, the tool the paper compares its
+ * simulations with (its Fig. 1(e)) and from which growth rates along the
+ * beam are read.  It is solved as n = (d_xi^2 + 1) dPsi with the causal
+ * inverse dPsi(xi) = int_0^xi sin(xi - xi') n(xi') dxi' (trapezoid rule on
+ * xi_j = j dxi, j < nxi) and d_tau^2 n = Gamma^2 dPsi by classical RK4 in
+ * tau with step dtau, from n(xi, 0) = n0 and d_tau n(xi, 0) = 0, for n_inst
+ * independent instances (one Gamma and one seed each) at once.
+ *   gamma [n_inst], n0 [n_inst][nxi]: device memory (float64);
+ *   taus [n_tau]: host memory, output times (each reached in
+ *     round((tau_m - tau_{m-1})/dtau) steps, ties to even; non-decreasing);
+ *   n_out, psi_out [n_inst][n_tau][nxi]: device memory, n and dPsi at them.
+ * Limits: nxi <= 4096, n_tau <= 256.  Enqueued on hip_stream (a hipStream_t,
+ * null for the default stream) without synchronizing; QSA_E_INVALID for
+ * arguments out of range (nothing launched), QSA_E_DEVICE if the launch
+ * fails.  Needs no context. */
+qsa_status qsa_linear_model(int32_t n_inst, int32_t nxi, double dxi, double dtau, const double* gamma,
+                            const double* n0, int32_t n_tau, const double* taus, double* n_out, double* psi_out,
+                            void* hip_stream);
+
 /* Wait for the stream and report any pending device error. */
 qsa_status qsa_sync(qsa_ctx* c);
 

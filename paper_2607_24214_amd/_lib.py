@@ -27,7 +27,7 @@ EXPORTS = ("qsa_workspace_bytes", "qsa_create", "qsa_load_plasma", "qsa_load_bea
            "qsa_read_beam", "qsa_slice_sweep", "qsa_beam_step", "qsa_fields", "qsa_sync",
            "qsa_destroy", "qsa_status_string", "qsa_last_error", "qsa_timing_begin",
            "qsa_timing_end", "qsa_set_option", "qsa_get_option", "qsa_autotune", "qsa_adjoint_sweep",
-           "qsa_field_moments", "qsa_beam_moments",
+           "qsa_field_moments", "qsa_beam_moments", "qsa_linear_model",
            "qsa_batch_workspace_bytes",
            "qsa_batch_create",
            "qsa_batch_sweep", "qsa_batch_step", "qsa_batch_sync", "qsa_batch_destroy")
@@ -82,6 +82,7 @@ def lib():
     L.qsa_fields.argtypes = [vp, i32, i32, i32, vp, C.c_size_t, i32]
     L.qsa_field_moments.argtypes = [vp, i32, vp, C.c_size_t, i32]
     L.qsa_beam_moments.argtypes = [vp, i32, i32, vp, C.c_size_t, i32]
+    L.qsa_linear_model.argtypes = [i32, i32, C.c_double, C.c_double, vp, vp, i32, dp, vp, vp, vp]
     L.qsa_sync.argtypes = [vp]
     L.qsa_destroy.argtypes = [vp]
     L.qsa_timing_begin.argtypes = [vp, i32]

@@ -16,6 +16,7 @@
 
 #include "../../include/qsa.h"
 #include "qsa_kernels.h"
+#include "qsa_linear.h"
 #include "qsa_adjoint.h"
 
 using namespace qsa;
@@ -1696,6 +1697,32 @@ qsa_status qsa_beam_moments(qsa_ctx* c, int32_t species, int32_t window, double*
   if (st != QSA_OK) return st;
   if ((st = leave(c)) != QSA_OK) return st;
   return check_device(c);
+}
+
+qsa_status qsa_linear_model(int32_t n_inst, int32_t nxi, double dxi, double dtau, const double* gamma,
+                            const double* n0, int32_t n_tau, const double* taus, double* n_out, double* psi_out,
+                            void* hip_stream) {
+  if (n_inst < 1 || nxi < 1 || nxi > QSA_LIN_THREADS * QSA_LIN_SEG) return QSA_E_INVALID;
+  if (!(dxi > 0.0) || !std::isfinite(dxi) || !(dtau > 0.0) || !std::isfinite(dtau)) return QSA_E_INVALID;
+  if (n_tau < 1 || n_tau > QSA_LIN_MAX_OUT) return QSA_E_INVALID;
+  if (!gamma || !n0 || !taus || !n_out || !psi_out) return QSA_E_INVALID;
+  LinOut out{};
+  out.n = n_tau;
+  double t = 0.0;
+  int64_t acc = 0;
+  for (int m = 0; m < n_tau; ++m) {
+    if (!std::isfinite(taus[m])) return QSA_E_INVALID;
+    // steps to the next output time, rounded to the nearest (ties to even)
+    const double k = std::nearbyint((taus[m] - t) / dtau);
+    if (k < 0.0 || k > 1e9) return QSA_E_INVALID;
+    acc += (int64_t)k;
+    t += k * dtau;
+    out.steps[m] = acc;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(k_linear_model, dim3(n_inst), dim3(QSA_LIN_THREADS), 0, st, nxi, dxi, dtau, gamma, n0, out,
+                     n_out, psi_out);
+  return hipGetLastError() == hipSuccess ? QSA_OK : QSA_E_DEVICE;
 }
 
 qsa_status qsa_sync(qsa_ctx* c) {

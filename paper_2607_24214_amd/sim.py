@@ -301,6 +301,34 @@ class Batch:
             pass
 
 
+def linear_model(gamma, n0, dxi: float, taus, dtau: float, device=None):
+    """Batched solve of the single-mode linear model, Eq. (5)
+    (qsa_linear_model): gamma [n_inst] growth rates, n0 [n_inst, nxi] (or
+    [nxi], shared) seeds on xi_j = j dxi; returns device tensors n and dPsi
+    [n_inst, len(taus), nxi] at the output times taus (multiples of dtau
+    from 0)."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    g = torch.as_tensor(np.asarray(gamma, dtype=np.float64).reshape(-1)).to(dev)
+    s0 = torch.as_tensor(np.asarray(n0, dtype=np.float64)).to(dev)
+    if s0.dim() == 1:
+        s0 = s0.expand(g.numel(), -1)
+    s0 = s0.contiguous()
+    n_inst, nxi = s0.shape
+    if g.numel() != n_inst:
+        raise ValueError("one gamma per seed row")
+    t = np.ascontiguousarray(np.asarray(taus, dtype=np.float64).reshape(-1))
+    n_out = torch.empty((n_inst, t.size, nxi), dtype=torch.float64, device=dev)
+    p_out = torch.empty_like(n_out)
+    lib = L.lib()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    st = lib.qsa_linear_model(n_inst, nxi, float(dxi), float(dtau), C.c_void_p(g.data_ptr()),
+                              C.c_void_p(s0.data_ptr()), t.size, t.ctypes.data_as(C.POINTER(C.c_double)),
+                              C.c_void_p(n_out.data_ptr()), C.c_void_p(p_out.data_ptr()), C.c_void_p(stream))
+    if st != L.QSA_OK:
+        raise L.QSAError(st, "qsa_linear_model: arguments out of range or launch failed")
+    return n_out, p_out
+
+
 class FieldEnergy(torch.autograd.Function):
     """torch.autograd.Function over the library's adjoint: forward gives the
     transverse magnetic energy after n_steps beam steps as a function of the

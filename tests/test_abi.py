@@ -96,3 +96,20 @@ def test_autotune_rejects_null_context():
     lib = L.lib()
     ms = C.c_double()
     assert lib.qsa_autotune(None, C.byref(ms)) == -1
+
+
+def test_linear_model_rejects_bad_arguments_without_a_launch():
+    """qsa_linear_model checks its arguments on the host before any launch."""
+    from paper_2607_24214_amd import _lib as L
+    lib = L.lib()
+    taus = (C.c_double * 2)(0.0, 1.0)
+    null = C.c_void_p(0)
+    dummy = C.c_void_p(16)
+    assert lib.qsa_linear_model(0, 10, 0.1, 0.1, dummy, dummy, 2, taus, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(1, 4097, 0.1, 0.1, dummy, dummy, 2, taus, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(1, 10, 0.0, 0.1, dummy, dummy, 2, taus, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(1, 10, 0.1, -1.0, dummy, dummy, 2, taus, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(1, 10, 0.1, 0.1, null, dummy, 2, taus, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(1, 10, 0.1, 0.1, dummy, dummy, 257, taus, dummy, dummy, null) == -1
+    back = (C.c_double * 2)(1.0, 0.5)
+    assert lib.qsa_linear_model(1, 10, 0.1, 0.1, dummy, dummy, 2, back, dummy, dummy, null) == -1
