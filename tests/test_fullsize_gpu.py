@@ -1,0 +1,121 @@
+"""Parity at the full size of the benchmark workload (3D 256 x 256 x 512,
+268 M beam particles) in the launch configuration the benchmark times
+(8 beam steps in flight, graphs, default launch shapes).
+
+The oracle cannot sweep 512 slices of this box in seconds, but a slice
+depends only on the slices before it and on the beam sources up to the next
+one, so the oracle computes the first slices exactly: it sweeps K slices
+with the beam of the full workload's first K cells (the generator draws
+each slice from its own seed) and slices 0 .. K-2 must match (float32:
+to the oracle computing on the same inputs rounded to float32).  Beyond
+them, properties that hold at any size: the pipelined steps equal the same
+steps taken one at a time (up to the order of additions), at sampled slices
+through the whole box."""
+import gc
+
+import numpy as np
+import pytest
+
+import qsa_workloads as W
+from tests.helpers import OUT_FIELDS, slice_errors
+
+pytestmark = pytest.mark.gpu
+
+K = 8
+
+
+def _free():
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def _full_sim(wl, precision, pipeline, beams):
+    import paper_2607_24214_amd as Q
+    caps = [len(b["x"]) for b in beams]
+    sim = Q.Sim(Q.params_from_workload(wl, precision=precision, beam_capacity=caps, pipeline=pipeline))
+    sim.load_plasma(W.plasma_template(wl))
+    for s, b in enumerate(beams):
+        sim.load_beam(s, b)
+    return sim
+
+
+def _as_f32(d):
+    """The same inputs as the float32 library stores them (each value
+    rounded to float32), for the oracle to compute on in float64."""
+    return {k: (v.astype(np.float32).astype(np.float64) if isinstance(v, np.ndarray) and v.dtype == np.float64
+                else v) for k, v in d.items()}
+
+
+def _oracle_first_slices(wl, f32_inputs=False):
+    from oracle import qsa_pic as O
+    sub = wl.with_(nxi=K)
+    g = O.Grid.of(sub)
+    pl = W.plasma_template(sub)
+    bs = W.beam(wl, 0, K)
+    if f32_inputs:
+        pl = _as_f32(pl)
+        bs = [_as_f32(b) for b in bs]
+    plasma = O.to_torch(pl)
+    beams = [O.to_torch(b) for b in bs]
+    src = O.beam_sources(g, beams, [s.Z for s in sub.species])
+    fields = O.slice_sweep(g, plasma, src, sub.n_corr, sub.kappa2)
+    return {k: v.numpy() for k, v in O.output_fields(fields).items()}
+
+
+# float32: the 1e-4 bound of the smaller parity workloads is not met on the
+# first slices of this box: 1.2e-4 on float32-rounded inputs (slice 1, E_y,
+# where the fields behind the beam front are weakest).  Plasma positions in
+# absolute coordinates of a 12.8 c/omega_p box resolve about 1e-6, while a
+# slice's displacement is about 5e-4, so each push keeps about three digits
+# of it: rounding only the pushed positions of the float64 oracle to float32
+# gives 0.9e-4 at the same place.  The bound below guards that level.
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 2e-4)])
+def test_first_slices_match_oracle(precision, tol):
+    wl = W.cube256()
+    beams = W.beam(wl)
+    sim = _full_sim(wl, precision, 8, beams)
+    del beams
+    sim.slice_sweep()
+    got = {k: sim.fields(k, 0, K - 1) for k in OUT_FIELDS}
+    del sim
+    _free()
+    ref = _oracle_first_slices(wl, f32_inputs=(precision == "f32"))
+    ref = {k: v[:K - 1] for k, v in ref.items()}
+    err, where = slice_errors(got, ref)
+    print(f"[full] {wl.name} {precision}: first {K - 1} slices vs oracle {err:.3e} at {where}", flush=True)
+    assert err <= tol, (err, where)
+    if precision == "f32":
+        # the same against the oracle on the float64 inputs: the rounding of
+        # the inputs to float32 (positions in a 12.8 c/omega_p box to about
+        # 1e-6, 2e-5 of a cell) is then part of the difference
+        raw = {k: v[:K - 1] for k, v in _oracle_first_slices(wl).items()}
+        e2, w2 = slice_errors(got, raw)
+        print(f"[full] {wl.name} f32 vs oracle on float64 inputs: {e2:.3e} at {w2}", flush=True)
+        assert e2 <= 1e-3, (e2, w2)
+
+
+def test_pipelined_steps_equal_sequential_full_size_fp64():
+    wl = W.cube256()
+    beams = W.beam(wl)
+    pip = _full_sim(wl, "f64", 8, beams)
+    seq = _full_sim(wl, "f64", 1, beams)
+    del beams
+    pip.beam_step(8)
+    seq.beam_step(8)
+    assert pip.pipeline == 8
+    pip.slice_sweep()
+    seq.slice_sweep()
+    for j in (0, 37, 255, 400, 510):
+        a = {k: pip.fields(k, j, j + 1) for k in OUT_FIELDS}
+        b = {k: seq.fields(k, j, j + 1) for k in OUT_FIELDS}
+        err, where = slice_errors(a, b)
+        print(f"[full] pipelined vs sequential after 8 steps, slice {j}: {err:.3e} at {where}", flush=True)
+        assert err <= 1e-10, (j, err, where)
+    bp, bs = pip.read_beam(0), seq.read_beam(0)
+    for k in ("x", "y", "xi", "ux", "uy", "uz", "w"):
+        d = float(np.abs(bp[k] - bs[k]).max())
+        scale = max(1.0, float(np.abs(bs[k]).max()))
+        assert d <= 1e-11 * scale, (k, d)
+    del pip, seq
+    _free()
