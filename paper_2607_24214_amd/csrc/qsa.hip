@@ -171,12 +171,13 @@ Layout make_layout(const qsa_params& p) {
   L.kdx = c.take(nxh * rs);
   L.ky2 = c.take(p.ny * rs);
   L.kdy = c.take(p.ny * rs);
-  for (int i = 0; i < 4; ++i) L.tmpl[i] = c.take(p.n_plasma * rs);
+  // plasma x, y in float64 for either precision; u_x, u_y in R
+  for (int i = 0; i < 4; ++i) L.tmpl[i] = c.take(p.n_plasma * (i < 2 ? 8 : rs));
   L.nset = pipeline_depth(p);
   for (int k = 0; k < L.nset; ++k) {
     SetLayout& S = L.set[k];
-    for (int i = 0; i < 4; ++i) S.pl[i] = c.take(p.n_plasma * rs);
-    for (int i = 0; i < 4; ++i) S.pl2[i] = c.take(p.n_plasma * rs);
+    for (int i = 0; i < 4; ++i) S.pl[i] = c.take(p.n_plasma * (i < 2 ? 8 : rs));
+    for (int i = 0; i < 4; ++i) S.pl2[i] = c.take(p.n_plasma * (i < 2 ? 8 : rs));
     S.cell_of = c.take(p.n_plasma * sizeof(int));
     S.count = c.take(nperp * sizeof(int));
     S.bsum = c.take(256 * sizeof(int));
@@ -401,6 +402,12 @@ struct Engine {
     g.ly = (R)(p.ny * p.dy);
     g.inv_lx = (R)(1.0 / (p.nx * p.dx));
     g.inv_ly = (R)(1.0 / (p.ny * p.dy));
+    g.inv_dxd = 1.0 / p.dx;
+    g.inv_dyd = 1.0 / p.dy;
+    g.lxd = p.nx * p.dx;
+    g.lyd = p.ny * p.dy;
+    g.inv_lxd = 1.0 / (p.nx * p.dx);
+    g.inv_lyd = 1.0 / (p.ny * p.dy);
     return g;
   }
 
@@ -632,10 +639,13 @@ struct Engine {
     a.fields = c->at<R>(S.fields);
     a.half = c->at<R>(S.half);
     a.src = c->at<R>(S.src);
-    for (int i = 0; i < 4; ++i) {
-      a.tmpl[i] = c->at<R>(L.tmpl[i]);
-      a.pl[0][i] = c->at<R>(S.pl[i]);
-      a.pl[1][i] = c->at<R>(S.pl2[i]);
+    for (int i = 0; i < 2; ++i) {
+      a.tpos[i] = c->at<double>(L.tmpl[i]);
+      a.tmom[i] = c->at<R>(L.tmpl[2 + i]);
+      a.pos[0][i] = c->at<double>(S.pl[i]);
+      a.pos[1][i] = c->at<double>(S.pl2[i]);
+      a.mom[0][i] = c->at<R>(S.pl[2 + i]);
+      a.mom[1][i] = c->at<R>(S.pl2[2 + i]);
     }
     a.twx = c->at<C2<R>>(L.twx);
     a.twy = c->at<C2<R>>(L.twy);
@@ -1360,8 +1370,8 @@ qsa_status qsa_load_plasma(qsa_ctx* c, const double* x, const double* y, const d
   if (st0 != QSA_OK) return st0;
   for (int i = 0; i < 4; ++i) {
     qsa_status st = dispatch(
-        c, [&] { return Engine<double>::upload(c, arr[i], c->ws + c->L.tmpl[i], n, on_device, false); },
-        [&] { return Engine<float>::upload(c, arr[i], c->ws + c->L.tmpl[i], n, on_device, false); });
+        c, [&] { return Engine<double>::upload(c, arr[i], c->ws + c->L.tmpl[i], n, on_device, i < 2); },
+        [&] { return Engine<float>::upload(c, arr[i], c->ws + c->L.tmpl[i], n, on_device, i < 2); });
     if (st != QSA_OK) return st;
   }
   c->plasma_loaded = true;

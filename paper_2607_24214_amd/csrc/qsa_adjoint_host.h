@@ -366,7 +366,13 @@ struct Adj {
     for (int k = 0; k < 4; ++k) {
       Ya[k] = yarr(A.Y[0], 0, k);
       Yb2[k] = yarr(A.Y[1], 0, k);
-      HIP_OK(hipMemcpyAsync(Ya[k], c->ws + c->L.tmpl[k], np * sizeof(R), hipMemcpyDeviceToDevice, st()));
+      if (k >= 2 || sizeof(R) == 8) {
+        HIP_OK(hipMemcpyAsync(Ya[k], c->ws + c->L.tmpl[k], np * sizeof(R), hipMemcpyDeviceToDevice, st()));
+      } else {
+        // the template keeps positions in float64
+        hipLaunchKernelGGL(k_from_f64<R>, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st(),
+                           (const double*)(c->ws + c->L.tmpl[k]), Ya[k], (int64_t)np);
+      }
     }
     hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(64), 0, st(), sc(), (int64_t)16, 0.0);
     if ((st0 = lin(grid(AG_S), 0, {{src(0, 0), 1.0}}, nperp)) != QSA_OK) return st0;

@@ -37,6 +37,10 @@ struct Geo {
   R dx, dy, dxi;
   R inv_dx, inv_dy;
   R lx, ly, inv_lx, inv_ly;
+  // the same in float64, for the plasma positions (float64 in either
+  // precision: a float32 position in a box of a few c/omega_p resolves only
+  // about 1e-6, coarser than a slice's displacement allows)
+  double inv_dxd, inv_dyd, lxd, lyd, inv_lxd, inv_lyd;
 };
 
 // Wrap an integer cell index into [0, n) for n a power of two (the library
@@ -54,18 +58,20 @@ struct Stencil {
   R w00, w10, w01, w11;
 };
 
-template <typename R>
-__device__ __forceinline__ Stencil<R> stencil2(const Geo<R>& g, R x, R y) {
-  R gx = x * g.inv_dx;
-  R gy = y * g.inv_dy;
-  R fx0 = floor(gx);
-  R fy0 = floor(gy);
-  R fx = gx - fx0;
-  R fy = gy - fy0;
+// (x, y) of type P: the working precision R (beam particles) or float64
+// (plasma particles); the cell offsets are taken in P, the weights in R.
+template <typename R, typename P>
+__device__ __forceinline__ Stencil<R> stencil2(const Geo<R>& g, P x, P y) {
+  P gx = x * (P)g.inv_dxd;
+  P gy = y * (P)g.inv_dyd;
+  P fx0 = floor(gx);
+  P fy0 = floor(gy);
+  R fx = (R)(gx - fx0);
+  R fy = (R)(gy - fy0);
   // coordinates are bounded (a few box lengths at most) for finite input;
   // the clamp keeps the float->int conversion defined for any input
-  R cx = fmin(fmax(fx0, R(-1.0e9)), R(1.0e9));
-  R cy = fmin(fmax(fy0, R(-1.0e9)), R(1.0e9));
+  P cx = fmin(fmax(fx0, P(-1.0e9)), P(1.0e9));
+  P cy = fmin(fmax(fy0, P(-1.0e9)), P(1.0e9));
   int i0 = wrap_index((int)cx, g.nx);
   int l0 = wrap_index((int)cy, g.ny);
   int i1 = (i0 + 1 == g.nx) ? 0 : i0 + 1;
@@ -84,16 +90,16 @@ __device__ __forceinline__ Stencil<R> stencil2(const Geo<R>& g, R x, R y) {
 }
 
 // Cell (i0, l0), wrapped into the grid, and the fractional offsets of (x, y).
-template <typename R>
-__device__ __forceinline__ void cell2(const Geo<R>& g, R x, R y, int& i0, int& l0, R& fx, R& fy) {
-  R gx = x * g.inv_dx;
-  R gy = y * g.inv_dy;
-  R fx0 = floor(gx);
-  R fy0 = floor(gy);
-  fx = gx - fx0;
-  fy = gy - fy0;
-  R cx = fmin(fmax(fx0, R(-1.0e9)), R(1.0e9));
-  R cy = fmin(fmax(fy0, R(-1.0e9)), R(1.0e9));
+template <typename R, typename P>
+__device__ __forceinline__ void cell2(const Geo<R>& g, P x, P y, int& i0, int& l0, R& fx, R& fy) {
+  P gx = x * (P)g.inv_dxd;
+  P gy = y * (P)g.inv_dyd;
+  P fx0 = floor(gx);
+  P fy0 = floor(gy);
+  fx = (R)(gx - fx0);
+  fy = (R)(gy - fy0);
+  P cx = fmin(fmax(fx0, P(-1.0e9)), P(1.0e9));
+  P cy = fmin(fmax(fy0, P(-1.0e9)), P(1.0e9));
   i0 = wrap_index((int)cx, g.nx);
   l0 = wrap_index((int)cy, g.ny);
 }

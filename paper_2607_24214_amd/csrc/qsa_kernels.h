@@ -53,7 +53,8 @@ struct Lane {
   R* fields;            // [7][nxi][ny][nx]
   R* half;              // [N_HALF][ny][nx] of the slice being swept
   const R* src;         // beam sources [4][nxi][ny][nx]
-  const R* tmpl[4];     // plasma template x, y, ux, uy
+  const double* tpos[2];  // plasma template x, y (float64 in either precision)
+  const R* tmom[2];       // and u_x, u_y
   const C2<R>* twx;     // transform tables
   const C2<R>* twy;
   const R* kx2;
@@ -61,7 +62,8 @@ struct Lane {
   const R* ky2;
   const R* kdy;
   int* err;             // sticky device error flags
-  R* pl[2][4];          // plasma state, two buffer sets (sorts ping-pong)
+  double* pos[2][2];    // plasma x, y (float64), two buffer sets (sorts ping-pong)
+  R* mom[2][2];         // plasma u_x, u_y, the same two sets
   int* cell_of;         // sort scratch
   int* count;
   int* bsum;
@@ -614,8 +616,8 @@ __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, 
 // ---------------------------------------------------------- plasma particles
 template <typename R>
 struct PlasmaArgs {
-  R* x;
-  R* y;
+  double* x;          // positions in float64 for either precision
+  double* y;
   R* ux;
   R* uy;
   int np;
@@ -637,11 +639,11 @@ __device__ __forceinline__ PlasmaArgs<R> plasma_args(const Lane<R>& L, int j) {
   const Geo<R>& g = L.g;
   const int64_t plane = (int64_t)g.nxi * g.nperp;
   PlasmaArgs<R> a;
-  R* const* P = L.pl[plasma_set(j)];
-  a.x = P[0];
-  a.y = P[1];
-  a.ux = P[2];
-  a.uy = P[3];
+  const int set = plasma_set(j);
+  a.x = L.pos[set][0];
+  a.y = L.pos[set][1];
+  a.ux = L.mom[set][0];
+  a.uy = L.mom[set][1];
   a.np = L.np;
   a.q = L.q;
   a.dep0 = L.dep;
@@ -685,8 +687,8 @@ __device__ __forceinline__ void plasma_rhs(const R f[6], R ux, R uy, R d[4], int
 // RK2 (midpoint) push from slice j with F^j and F^{j+1/2} = (3F^j - F^{j-1})/2
 // (the latter gathered from its grids).
 template <typename R>
-__device__ __forceinline__ void rk2_push(const Geo<R>& g, const PlasmaArgs<R>& a, R x, R y, R ux,
-                                         R uy, R& xn, R& yn, R& uxn, R& uyn) {
+__device__ __forceinline__ void rk2_push(const Geo<R>& g, const PlasmaArgs<R>& a, double x, double y, R ux,
+                                         R uy, double& xn, double& yn, R& uxn, R& uyn) {
   const R hh = a.h;
   R f[6], d1[4], d2[4];
   {
@@ -695,8 +697,9 @@ __device__ __forceinline__ void rk2_push(const Geo<R>& g, const PlasmaArgs<R>& a
     for (int q = 0; q < 6; ++q) f[q] = gather(a.F0[q], s);
     plasma_rhs(f, ux, uy, d1, a.err);
   }
-  const R xs = x + R(0.5) * hh * d1[0];
-  const R ys = y + R(0.5) * hh * d1[1];
+  // positions advance in float64 by increments formed in R
+  const double xs = x + (double)(R(0.5) * hh * d1[0]);
+  const double ys = y + (double)(R(0.5) * hh * d1[1]);
   const R uxs = ux + R(0.5) * hh * d1[2];
   const R uys = uy + R(0.5) * hh * d1[3];
   {
@@ -705,8 +708,8 @@ __device__ __forceinline__ void rk2_push(const Geo<R>& g, const PlasmaArgs<R>& a
     for (int q = 0; q < 6; ++q) f[q] = gather(a.H[q], s);
     plasma_rhs(f, uxs, uys, d2, a.err);
   }
-  xn = x + hh * d2[0];
-  yn = y + hh * d2[1];
+  xn = x + (double)(hh * d2[0]);
+  yn = y + (double)(hh * d2[1]);
   uxn = ux + hh * d2[2];
   uyn = uy + hh * d2[3];
 }
@@ -794,7 +797,7 @@ __global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__
   R acc[4][NC];
   int ci = -1, cl = -1;
   for (int p = q0; p < q1; ++p) {
-    R px, py;
+    double px, py;
     R v[NC];
     if constexpr (MODE == PL_DEP_S) {
       px = a.x[p];
@@ -895,10 +898,11 @@ __global__ void __launch_bounds__(256) k_push_final(const Lane<R>* __restrict__ 
   }
   if (p >= L.np) return;
   const PlasmaArgs<R> a = plasma_args(L, j);
-  R xn, yn, uxn, uyn;
+  double xn, yn;
+  R uxn, uyn;
   rk2_push(g, a, a.x[p], a.y[p], a.ux[p], a.uy[p], xn, yn, uxn, uyn);
-  a.x[p] = wrap_pos(xn, g.lx, g.inv_lx);
-  a.y[p] = wrap_pos(yn, g.ly, g.inv_ly);
+  a.x[p] = wrap_pos(xn, g.lxd, g.inv_lxd);
+  a.y[p] = wrap_pos(yn, g.lyd, g.inv_lyd);
   a.ux[p] = uxn;
   a.uy[p] = uyn;
 }
@@ -908,10 +912,30 @@ __global__ void __launch_bounds__(256) k_push_final(const Lane<R>* __restrict__ 
 // Sort at slice j (a multiple of QSA_SORT_EVERY): source buffers (the
 // template at j = 0) and destination buffers.
 template <typename R>
-__device__ __forceinline__ void sort_buffers(const Lane<R>& L, int j, const R* const*& A, R* const*& B) {
+struct PlasmaSrc {
+  const double* x;
+  const double* y;
+  const R* ux;
+  const R* uy;
+};
+template <typename R>
+struct PlasmaDst {
+  double* x;
+  double* y;
+  R* ux;
+  R* uy;
+};
+template <typename R>
+__device__ __forceinline__ void sort_buffers(const Lane<R>& L, int j, PlasmaSrc<R>& A, PlasmaDst<R>& B) {
   const int m = j / QSA_SORT_EVERY;
-  A = (m == 0) ? L.tmpl : (const R* const*)L.pl[(m - 1) & 1];
-  B = L.pl[m & 1];
+  if (m == 0) {
+    A = PlasmaSrc<R>{L.tpos[0], L.tpos[1], L.tmom[0], L.tmom[1]};
+  } else {
+    const int a = (m - 1) & 1;
+    A = PlasmaSrc<R>{L.pos[a][0], L.pos[a][1], L.mom[a][0], L.mom[a][1]};
+  }
+  const int b = m & 1;
+  B = PlasmaDst<R>{L.pos[b][0], L.pos[b][1], L.mom[b][0], L.mom[b][1]};
 }
 
 template <typename R>
@@ -923,11 +947,11 @@ __global__ void __launch_bounds__(256) k_sort_count(const Lane<R>* __restrict__ 
   if (j % QSA_SORT_EVERY != 0) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= L.np) return;
-  const R* const* A;
-  R* const* B;
+  PlasmaSrc<R> A;
+  PlasmaDst<R> B;
   sort_buffers(L, j, A, B);
-  const R* __restrict__ x = A[0];
-  const R* __restrict__ y = A[1];
+  const double* __restrict__ x = A.x;
+  const double* __restrict__ y = A.y;
   int* __restrict__ cell_of = L.cell_of;
   int* __restrict__ count = L.count;
   int i0, l0;
@@ -1006,20 +1030,20 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const Lane<R>* __restrict_
   if (j % QSA_SORT_EVERY != 0) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= L.np) return;
-  const R* const* A;
-  R* const* B;
+  PlasmaSrc<R> A;
+  PlasmaDst<R> B;
   sort_buffers(L, j, A, B);
   const int* __restrict__ cell_of = L.cell_of;
   int* __restrict__ cursor = L.count;
   const int* __restrict__ bsum = L.bsum;
-  const R* __restrict__ x = A[0];
-  const R* __restrict__ y = A[1];
-  const R* __restrict__ ux = A[2];
-  const R* __restrict__ uy = A[3];
-  R* __restrict__ x2 = B[0];
-  R* __restrict__ y2 = B[1];
-  R* __restrict__ ux2 = B[2];
-  R* __restrict__ uy2 = B[3];
+  const double* __restrict__ x = A.x;
+  const double* __restrict__ y = A.y;
+  const R* __restrict__ ux = A.ux;
+  const R* __restrict__ uy = A.uy;
+  double* __restrict__ x2 = B.x;
+  double* __restrict__ y2 = B.y;
+  R* __restrict__ ux2 = B.ux;
+  R* __restrict__ uy2 = B.uy;
   const int c = cell_of[p];
   const int d = atomicAdd(&cursor[c], 1) + bsum[c >> 10];
   x2[d] = x[p];

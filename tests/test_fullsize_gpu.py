@@ -6,8 +6,7 @@ The oracle cannot sweep 512 slices of this box in seconds, but a slice
 depends only on the slices before it and on the beam sources up to the next
 one, so the oracle computes the first slices exactly: it sweeps K slices
 with the beam of the full workload's first K cells (the generator draws
-each slice from its own seed) and slices 0 .. K-2 must match (float32:
-to the oracle computing on the same inputs rounded to float32).  Beyond
+each slice from its own seed) and slices 0 .. K-2 must match.  Beyond
 them, properties that hold at any size: the pipelined steps equal the same
 steps taken one at a time (up to the order of additions), at sampled slices
 through the whole box."""
@@ -40,38 +39,23 @@ def _full_sim(wl, precision, pipeline, beams):
     return sim
 
 
-def _as_f32(d):
-    """The same inputs as the float32 library stores them (each value
-    rounded to float32), for the oracle to compute on in float64."""
-    return {k: (v.astype(np.float32).astype(np.float64) if isinstance(v, np.ndarray) and v.dtype == np.float64
-                else v) for k, v in d.items()}
-
-
-def _oracle_first_slices(wl, f32_inputs=False):
+def _oracle_first_slices(wl):
     from oracle import qsa_pic as O
     sub = wl.with_(nxi=K)
     g = O.Grid.of(sub)
-    pl = W.plasma_template(sub)
-    bs = W.beam(wl, 0, K)
-    if f32_inputs:
-        pl = _as_f32(pl)
-        bs = [_as_f32(b) for b in bs]
-    plasma = O.to_torch(pl)
-    beams = [O.to_torch(b) for b in bs]
+    plasma = O.to_torch(W.plasma_template(sub))
+    beams = [O.to_torch(b) for b in W.beam(wl, 0, K)]
     src = O.beam_sources(g, beams, [s.Z for s in sub.species])
     fields = O.slice_sweep(g, plasma, src, sub.n_corr, sub.kappa2)
     return {k: v.numpy() for k, v in O.output_fields(fields).items()}
 
 
-# float32: the 1e-4 bound of the smaller parity workloads is not met on the
-# first slices of this box: 1.2e-4 on float32-rounded inputs (slice 1, E_y,
-# where the fields behind the beam front are weakest).  Plasma positions in
-# absolute coordinates of a 12.8 c/omega_p box resolve about 1e-6, while a
-# slice's displacement is about 5e-4, so each push keeps about three digits
-# of it: rounding only the pushed positions of the float64 oracle to float32
-# gives 0.9e-4 at the same place.  The bound below guards that level.
-@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 2e-4)])
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
 def test_first_slices_match_oracle(precision, tol):
+    """float32 keeps the plasma positions in float64 (in absolute coordinates
+    of this 12.8 c/omega_p box float32 would resolve about 1e-6, while a
+    slice's displacement is about 5e-4: that alone costs 0.9e-4 here, on the
+    slice behind the beam front where the fields are weakest)."""
     wl = W.cube256()
     beams = W.beam(wl)
     sim = _full_sim(wl, precision, 8, beams)
@@ -80,19 +64,10 @@ def test_first_slices_match_oracle(precision, tol):
     got = {k: sim.fields(k, 0, K - 1) for k in OUT_FIELDS}
     del sim
     _free()
-    ref = _oracle_first_slices(wl, f32_inputs=(precision == "f32"))
-    ref = {k: v[:K - 1] for k, v in ref.items()}
+    ref = {k: v[:K - 1] for k, v in _oracle_first_slices(wl).items()}
     err, where = slice_errors(got, ref)
     print(f"[full] {wl.name} {precision}: first {K - 1} slices vs oracle {err:.3e} at {where}", flush=True)
     assert err <= tol, (err, where)
-    if precision == "f32":
-        # the same against the oracle on the float64 inputs: the rounding of
-        # the inputs to float32 (positions in a 12.8 c/omega_p box to about
-        # 1e-6, 2e-5 of a cell) is then part of the difference
-        raw = {k: v[:K - 1] for k, v in _oracle_first_slices(wl).items()}
-        e2, w2 = slice_errors(got, raw)
-        print(f"[full] {wl.name} f32 vs oracle on float64 inputs: {e2:.3e} at {w2}", flush=True)
-        assert e2 <= 1e-3, (e2, w2)
 
 
 def test_pipelined_steps_equal_sequential_full_size_fp64():
