@@ -210,8 +210,12 @@ qsa_status qsa_beam_moments(qsa_ctx* c, int32_t species, int32_t window, double*
  * inverse dPsi(xi) = int_0^xi sin(xi - xi') n(xi') dxi' (trapezoid rule on
  * xi_j = j dxi, j < nxi) and d_tau^2 n = Gamma^2 dPsi by classical RK4 in
  * tau with step dtau, from n(xi, 0) = n0 and d_tau n(xi, 0) = 0, for n_inst
- * independent instances (one Gamma and one seed each) at once.
- *   gamma [n_inst], n0 [n_inst][nxi]: device memory (float64);
+ * independent instances (one Gamma and one seed each) at once.  A
+ * longitudinal beam profile enters through Gamma(xi), the paper's
+ * generalization of Eq. (5): d_tau^2 n = Gamma(xi)^2 dPsi point by point.
+ *   gamma: device memory (float64), [n_inst] (gamma_per_point = 0) or the
+ *     profiles [n_inst][nxi] (gamma_per_point = 1);
+ *   n0 [n_inst][nxi]: device memory (float64);
  *   taus [n_tau]: host memory, output times (each reached in
  *     round((tau_m - tau_{m-1})/dtau) steps, ties to even; non-decreasing);
  *   n_out, psi_out [n_inst][n_tau][nxi]: device memory, n and dPsi at them.
@@ -220,7 +224,7 @@ qsa_status qsa_beam_moments(qsa_ctx* c, int32_t species, int32_t window, double*
  * arguments out of range (nothing launched), QSA_E_DEVICE if the launch
  * fails.  Needs no context. */
 qsa_status qsa_linear_model(int32_t n_inst, int32_t nxi, double dxi, double dtau, const double* gamma,
-                            const double* n0, int32_t n_tau, const double* taus, double* n_out, double* psi_out,
+                            int32_t gamma_per_point, const double* n0, int32_t n_tau, const double* taus, double* n_out, double* psi_out,
                             void* hip_stream);
 
 /* Wait for the stream and report any pending device error. */

@@ -57,10 +57,13 @@ RAY_SLOPE = 2.0 / math.sqrt(27.0)                     # xi_t = RAY_SLOPE * Gamma
 RAY_RATE = 4.0 / 3.0 * math.sqrt(2.0 / 3.0)           # growth rate along the ray / Gamma
 
 
-def solve_eq5(gamma: float, xi: np.ndarray, n0: np.ndarray, taus: np.ndarray,
+def solve_eq5(gamma, xi: np.ndarray, n0: np.ndarray, taus: np.ndarray,
               dtau: float) -> Tuple[np.ndarray, np.ndarray]:
     """Solve Eq. (5) for a seed n(xi, 0) = n0, d_tau n(xi, 0) = 0.
 
+    gamma: a number, or Gamma(xi) on the grid (an arbitrary longitudinal
+    beam profile, for which the paper generalizes Eq. (5) through Gamma(xi):
+    d_tau^2 n = Gamma(xi)^2 Psi point by point).
     xi: uniform grid starting at 0.  Returns (n, Psi) sampled at the requested
     taus, arrays [len(taus), len(xi)].  The xi integral uses the trapezoid
     rule; tau uses classical RK4 with step dtau (taus must be multiples).
@@ -70,7 +73,7 @@ def solve_eq5(gamma: float, xi: np.ndarray, n0: np.ndarray, taus: np.ndarray,
     A = np.sin(xi[:, None] - xi[None, :]) * d
     A = np.tril(A)
     A[:, 0] *= 0.5          # trapezoid end weight (the diagonal term is sin 0 = 0)
-    g2 = gamma * gamma
+    g2 = np.asarray(gamma, dtype=np.float64) ** 2
 
     def rhs(state):
         n, v = state

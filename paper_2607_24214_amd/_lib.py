@@ -82,7 +82,7 @@ def lib():
     L.qsa_fields.argtypes = [vp, i32, i32, i32, vp, C.c_size_t, i32]
     L.qsa_field_moments.argtypes = [vp, i32, vp, C.c_size_t, i32]
     L.qsa_beam_moments.argtypes = [vp, i32, i32, vp, C.c_size_t, i32]
-    L.qsa_linear_model.argtypes = [i32, i32, C.c_double, C.c_double, vp, vp, i32, dp, vp, vp, vp]
+    L.qsa_linear_model.argtypes = [i32, i32, C.c_double, C.c_double, vp, i32, vp, i32, dp, vp, vp, vp]
     L.qsa_sync.argtypes = [vp]
     L.qsa_destroy.argtypes = [vp]
     L.qsa_timing_begin.argtypes = [vp, i32]

@@ -1710,11 +1710,12 @@ qsa_status qsa_beam_moments(qsa_ctx* c, int32_t species, int32_t window, double*
 }
 
 qsa_status qsa_linear_model(int32_t n_inst, int32_t nxi, double dxi, double dtau, const double* gamma,
-                            const double* n0, int32_t n_tau, const double* taus, double* n_out, double* psi_out,
+                            int32_t gamma_per_point, const double* n0, int32_t n_tau, const double* taus, double* n_out, double* psi_out,
                             void* hip_stream) {
   if (n_inst < 1 || nxi < 1 || nxi > QSA_LIN_THREADS * QSA_LIN_SEG) return QSA_E_INVALID;
   if (!(dxi > 0.0) || !std::isfinite(dxi) || !(dtau > 0.0) || !std::isfinite(dtau)) return QSA_E_INVALID;
   if (n_tau < 1 || n_tau > QSA_LIN_MAX_OUT) return QSA_E_INVALID;
+  if (gamma_per_point != 0 && gamma_per_point != 1) return QSA_E_INVALID;
   if (!gamma || !n0 || !taus || !n_out || !psi_out) return QSA_E_INVALID;
   LinOut out{};
   out.n = n_tau;
@@ -1730,7 +1731,8 @@ qsa_status qsa_linear_model(int32_t n_inst, int32_t nxi, double dxi, double dtau
     out.steps[m] = acc;
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  hipLaunchKernelGGL(k_linear_model, dim3(n_inst), dim3(QSA_LIN_THREADS), 0, st, nxi, dxi, dtau, gamma, n0, out,
+  hipLaunchKernelGGL(k_linear_model, dim3(n_inst), dim3(QSA_LIN_THREADS), 0, st, nxi, dxi, dtau, gamma, (int)gamma_per_point,
+                     n0, out,
                      n_out, psi_out);
   return hipGetLastError() == hipSuccess ? QSA_OK : QSA_E_DEVICE;
 }

@@ -77,17 +77,18 @@ __device__ __forceinline__ void lin_volterra(const double (&n)[QSA_LIN_SEG], con
   }
 }
 
-// One block per instance b: Gamma_b, seed n0[b][nxi]; outputs
-// n_out[b][m][nxi] and psi_out[b][m][nxi] after out.steps[m] RK4 steps.
+// One block per instance b: Gamma_b (per_point = 0) or the longitudinal
+// profile Gamma_b(xi_i) = gamma[b][i] (per_point = 1), seed n0[b][nxi];
+// outputs n_out[b][m][nxi] and psi_out[b][m][nxi] after out.steps[m] RK4
+// steps.
 __global__ void __launch_bounds__(QSA_LIN_THREADS) k_linear_model(int nxi, double dxi, double dtau,
-                                                                  const double* __restrict__ gamma,
+                                                                  const double* __restrict__ gamma, int per_point,
                                                                   const double* __restrict__ n0, LinOut out,
                                                                   double* __restrict__ n_out,
                                                                   double* __restrict__ psi_out) {
   __shared__ double ws[32];
   const int b = blockIdx.x, t = threadIdx.x;
-  const double g2 = gamma[b] * gamma[b];
-  double cs[QSA_LIN_SEG], sn[QSA_LIN_SEG], cw[QSA_LIN_SEG], n[QSA_LIN_SEG], v[QSA_LIN_SEG];
+  double cs[QSA_LIN_SEG], sn[QSA_LIN_SEG], cw[QSA_LIN_SEG], n[QSA_LIN_SEG], v[QSA_LIN_SEG], g2[QSA_LIN_SEG];
 #pragma unroll
   for (int k = 0; k < QSA_LIN_SEG; ++k) {
     const int i = t * QSA_LIN_SEG + k;
@@ -98,6 +99,8 @@ __global__ void __launch_bounds__(QSA_LIN_THREADS) k_linear_model(int nxi, doubl
     cw[k] = in ? (i == 0 ? 0.5 : 1.0) : 0.0;   // points past the grid carry nothing
     n[k] = in ? n0[(int64_t)b * nxi + i] : 0.0;
     v[k] = 0.0;
+    const double gk = per_point ? (in ? gamma[(int64_t)b * nxi + i] : 0.0) : gamma[b];
+    g2[k] = gk * gk;
   }
   auto emit = [&](int m) {
     double q[QSA_LIN_SEG];
@@ -121,19 +124,19 @@ __global__ void __launch_bounds__(QSA_LIN_THREADS) k_linear_model(int nxi, doubl
 #pragma unroll
       for (int k = 0; k < QSA_LIN_SEG; ++k) {
         an[k] = v[k];
-        av[k] = g2 * q[k];
+        av[k] = g2[k] * q[k];
         sn_[k] = n[k] + 0.5 * dtau * v[k];
       }
       double vs[QSA_LIN_SEG];
 #pragma unroll
-      for (int k = 0; k < QSA_LIN_SEG; ++k) vs[k] = v[k] + 0.5 * dtau * (g2 * q[k]);
+      for (int k = 0; k < QSA_LIN_SEG; ++k) vs[k] = v[k] + 0.5 * dtau * (g2[k] * q[k]);
       // stage 2
       lin_volterra(sn_, cs, sn, cw, dxi, ws, q);
       double k2n[QSA_LIN_SEG], k2v[QSA_LIN_SEG];
 #pragma unroll
       for (int k = 0; k < QSA_LIN_SEG; ++k) {
         k2n[k] = vs[k];
-        k2v[k] = g2 * q[k];
+        k2v[k] = g2[k] * q[k];
         an[k] += 2.0 * k2n[k];
         av[k] += 2.0 * k2v[k];
         sn_[k] = n[k] + 0.5 * dtau * k2n[k];
@@ -143,7 +146,7 @@ __global__ void __launch_bounds__(QSA_LIN_THREADS) k_linear_model(int nxi, doubl
       lin_volterra(sn_, cs, sn, cw, dxi, ws, q);
 #pragma unroll
       for (int k = 0; k < QSA_LIN_SEG; ++k) {
-        const double k3n = vs[k], k3v = g2 * q[k];
+        const double k3n = vs[k], k3v = g2[k] * q[k];
         an[k] += 2.0 * k3n;
         av[k] += 2.0 * k3v;
         sn_[k] = n[k] + dtau * k3n;
@@ -154,7 +157,7 @@ __global__ void __launch_bounds__(QSA_LIN_THREADS) k_linear_model(int nxi, doubl
 #pragma unroll
       for (int k = 0; k < QSA_LIN_SEG; ++k) {
         an[k] += vs[k];
-        av[k] += g2 * q[k];
+        av[k] += g2[k] * q[k];
         n[k] += dtau / 6.0 * an[k];
         v[k] += dtau / 6.0 * av[k];
       }

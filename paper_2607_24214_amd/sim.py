@@ -303,25 +303,30 @@ class Batch:
 
 def linear_model(gamma, n0, dxi: float, taus, dtau: float, device=None):
     """Batched solve of the single-mode linear model, Eq. (5)
-    (qsa_linear_model): gamma [n_inst] growth rates, n0 [n_inst, nxi] (or
-    [nxi], shared) seeds on xi_j = j dxi; returns device tensors n and dPsi
+    (qsa_linear_model): gamma [n_inst] growth rates, or [n_inst, nxi]
+    longitudinal profiles Gamma(xi_j); n0 [n_inst, nxi] (or [nxi], shared)
+    seeds on xi_j = j dxi; returns device tensors n and dPsi
     [n_inst, len(taus), nxi] at the output times taus (multiples of dtau
     from 0)."""
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-    g = torch.as_tensor(np.asarray(gamma, dtype=np.float64).reshape(-1)).to(dev)
+    ga = np.asarray(gamma, dtype=np.float64)
+    per_point = 1 if ga.ndim == 2 else 0
+    if ga.ndim > 2:
+        raise ValueError("gamma is [n_inst] or [n_inst, nxi]")
+    g = torch.as_tensor(np.ascontiguousarray(ga if per_point else ga.reshape(-1))).to(dev)
     s0 = torch.as_tensor(np.asarray(n0, dtype=np.float64)).to(dev)
     if s0.dim() == 1:
-        s0 = s0.expand(g.numel(), -1)
+        s0 = s0.expand(g.shape[0], -1)
     s0 = s0.contiguous()
     n_inst, nxi = s0.shape
-    if g.numel() != n_inst:
-        raise ValueError("one gamma per seed row")
+    if g.shape[0] != n_inst or (per_point and g.shape[1] != nxi):
+        raise ValueError("one gamma (or one profile of nxi points) per seed row")
     t = np.ascontiguousarray(np.asarray(taus, dtype=np.float64).reshape(-1))
     n_out = torch.empty((n_inst, t.size, nxi), dtype=torch.float64, device=dev)
     p_out = torch.empty_like(n_out)
     lib = L.lib()
     stream = torch.cuda.current_stream(dev).cuda_stream
-    st = lib.qsa_linear_model(n_inst, nxi, float(dxi), float(dtau), C.c_void_p(g.data_ptr()),
+    st = lib.qsa_linear_model(n_inst, nxi, float(dxi), float(dtau), C.c_void_p(g.data_ptr()), per_point,
                               C.c_void_p(s0.data_ptr()), t.size, t.ctypes.data_as(C.POINTER(C.c_double)),
                               C.c_void_p(n_out.data_ptr()), C.c_void_p(p_out.data_ptr()), C.c_void_p(stream))
     if st != L.QSA_OK:

@@ -105,11 +105,12 @@ def test_linear_model_rejects_bad_arguments_without_a_launch():
     taus = (C.c_double * 2)(0.0, 1.0)
     null = C.c_void_p(0)
     dummy = C.c_void_p(16)
-    assert lib.qsa_linear_model(0, 10, 0.1, 0.1, dummy, dummy, 2, taus, dummy, dummy, null) == -1
-    assert lib.qsa_linear_model(1, 4097, 0.1, 0.1, dummy, dummy, 2, taus, dummy, dummy, null) == -1
-    assert lib.qsa_linear_model(1, 10, 0.0, 0.1, dummy, dummy, 2, taus, dummy, dummy, null) == -1
-    assert lib.qsa_linear_model(1, 10, 0.1, -1.0, dummy, dummy, 2, taus, dummy, dummy, null) == -1
-    assert lib.qsa_linear_model(1, 10, 0.1, 0.1, null, dummy, 2, taus, dummy, dummy, null) == -1
-    assert lib.qsa_linear_model(1, 10, 0.1, 0.1, dummy, dummy, 257, taus, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(0, 10, 0.1, 0.1, dummy, 0, dummy, 2, taus, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(1, 4097, 0.1, 0.1, dummy, 0, dummy, 2, taus, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(1, 10, 0.0, 0.1, dummy, 0, dummy, 2, taus, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(1, 10, 0.1, -1.0, dummy, 0, dummy, 2, taus, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(1, 10, 0.1, 0.1, null, 0, dummy, 2, taus, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(1, 10, 0.1, 0.1, dummy, 0, dummy, 257, taus, dummy, dummy, null) == -1
     back = (C.c_double * 2)(1.0, 0.5)
-    assert lib.qsa_linear_model(1, 10, 0.1, 0.1, dummy, dummy, 2, back, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(1, 10, 0.1, 0.1, dummy, 0, dummy, 2, back, dummy, dummy, null) == -1
+    assert lib.qsa_linear_model(1, 10, 0.1, 0.1, dummy, 2, dummy, 2, taus, dummy, dummy, null) == -1

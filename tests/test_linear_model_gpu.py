@@ -77,3 +77,40 @@ def test_invalid_arguments():
         Q.linear_model([1.0], np.ones(10), 0.01, [1.0, 0.5], 0.1)     # time going back
     with pytest.raises(Q.QSAError, match="INVALID"):
         Q.linear_model([1.0], np.ones(10), 0.01, np.arange(257), 1.0)  # too many outputs
+
+
+def test_longitudinal_profiles_match_oracle():
+    """Gamma(xi) per point: a Gaussian bunch, a step (nothing grows ahead of
+    it) and a linear ramp, 600 points (several wavefronts and a ragged last
+    one), against the oracle's solver with the same profiles; a constant
+    profile gives exactly the scalar-Gamma result."""
+    import paper_2607_24214_amd as Q
+    d = 0.01
+    xi = np.arange(600) * d
+    prof = np.vstack([1.5 * np.exp(-0.5 * ((xi - 3.0) / 1.2) ** 2),
+                      np.where(xi >= 2.0, 1.0, 0.0),
+                      0.2 + 0.3 * xi])
+    rng = np.random.default_rng(11)
+    seeds = np.vstack([np.ones_like(xi), rng.uniform(-1, 1, xi.size), np.cos(xi)])
+    taus = np.array([0.0, 0.4, 1.0, 2.0])
+    n_g, p_g = Q.linear_model(prof, seeds, d, taus, 0.02)
+    n_g, p_g = n_g.cpu().numpy(), p_g.cpu().numpy()
+    for b in range(3):
+        n_o, p_o = LT.solve_eq5(prof[b], xi, seeds[b], taus, 0.02)
+        en, ep = _rel(n_g[b], n_o), _rel(p_g[b], p_o)
+        print(f"[linear] profile {b}: n {en:.2e} psi {ep:.2e}", flush=True)
+        assert en <= 1e-10 and ep <= 1e-10, (b, en, ep)
+    ahead = xi < 2.0
+    assert np.array_equal(n_g[1][:, ahead], np.tile(seeds[1][ahead], (4, 1)))
+    n_c, p_c = Q.linear_model(np.full((1, xi.size), 0.8), seeds[2], d, taus, 0.02)
+    n_s, p_s = Q.linear_model([0.8], seeds[2], d, taus, 0.02)
+    assert np.array_equal(n_c.cpu().numpy(), n_s.cpu().numpy())
+    assert np.array_equal(p_c.cpu().numpy(), p_s.cpu().numpy())
+
+
+def test_profile_shape_checked():
+    import paper_2607_24214_amd as Q
+    with pytest.raises(ValueError):
+        Q.linear_model(np.ones((1, 9)), np.ones(10), 0.01, [1.0], 0.1)
+    with pytest.raises(ValueError):
+        Q.linear_model(np.ones((2, 10)), np.ones((3, 10)), 0.01, [1.0], 0.1)

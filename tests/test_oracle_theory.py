@@ -95,3 +95,31 @@ def test_eq5_ray_rate_tends_to_saddle_value():
     n2, p2 = L.solve_eq5(0.5, xi, np.ones_like(xi), taus * 2, 0.04)
     r2 = L.ray_rate(0.5, xi, p2, taus * 2, 20.0, 30.0)
     assert r2 == pytest.approx(0.5 * r, rel=1e-3)
+
+
+def test_eq5_solver_with_a_longitudinal_profile():
+    """Gamma(xi) a step (0 ahead of xi0 = 1.5, 1 behind): nothing grows
+    where Gamma = 0, and behind the step the short-time series holds,
+    n = 1 + (tau^2/2) P[1] + (tau^4/24) P[g P[1]] with g the step and
+    P[f](xi) = int_0^xi sin(xi - s) f(s) ds evaluated by adaptive quadrature."""
+    from scipy.integrate import quad
+    xi = np.arange(0, 4.0, 0.005)
+    g = np.where(xi >= 1.5, 1.0, 0.0)
+    t = 0.1
+    n, _ = L.solve_eq5(g, xi, np.ones_like(xi), np.array([t, 2 * t]), 0.005)
+    ahead = xi < 1.5
+    assert np.array_equal(n[:, ahead], np.ones((2, ahead.sum())))
+    # the constant profile is the scalar solver
+    nc, pc = L.solve_eq5(np.full_like(xi, 0.7), xi, np.ones_like(xi), np.array([t]), 0.005)
+    ns, ps = L.solve_eq5(0.7, xi, np.ones_like(xi), np.array([t]), 0.005)
+    assert np.array_equal(nc, ns) and np.array_equal(pc, ps)
+
+    def p_gp1(x):
+        if x <= 1.5:
+            return 0.0
+        return quad(lambda s: np.sin(x - s) * (1 - np.cos(s)), 1.5, x, epsabs=1e-13, epsrel=1e-12)[0]
+
+    for x in (2.0, 2.7, 3.5):
+        i = int(round(x / 0.005))
+        expect = 1.0 + 0.5 * t * t * (1 - np.cos(xi[i])) + t ** 4 / 24.0 * p_gp1(xi[i])
+        assert abs(n[0, i] - expect) < 1e-6, (x, n[0, i], expect)
