@@ -26,7 +26,9 @@ class Species:
     alpha: n_b/n_p; ppc: macro-particles per 3D cell (per (x, xi) cell in a slab);
     sigma_par / sigma_perp: Gaussian momentum spread relative to gamma_b*beta_b;
     mod_eps, mod_m: optional weight modulation (1 + mod_eps*cos(2 pi mod_m x / Lx))
-    used to seed a single transverse mode.
+    used to seed a single transverse mode;
+    w_spread: random macro-particle weights, each weight times
+    (1 + w_spread (2U - 1)) with U uniform in [0, 1) (mean unchanged).
     """
     Z: int = -1
     M: float = 1.0
@@ -36,6 +38,7 @@ class Species:
     sigma_perp: float = 0.0
     mod_eps: float = 0.0
     mod_m: int = 0
+    w_spread: float = 0.0
 
 
 @dataclass(frozen=True)

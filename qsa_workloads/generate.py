@@ -63,7 +63,8 @@ def beam_species(wl: Workload, s: int, j0: int = 0, j1: Optional[int] = None,
     split).  Order: slice j, row l, column i, then particle.  Momenta
     u_z = gamma_b beta_b (1 + sigma_par N), u_perp = gamma_b beta_b sigma_perp N.
     Weight alpha dx dy dxi / ppc, times (1 + eps cos(2 pi m x / Lx)) when a
-    mode is seeded.  Also returns the cell-independent 'bin' index (-1 if no
+    mode is seeded, and times (1 + w_spread (2U - 1)) for random weights
+    (U from a stream of its own per species and slice).  Also returns the cell-independent 'bin' index (-1 if no
     bins) that the adjoint workload uses.
     """
     sp = wl.species[s]
@@ -113,6 +114,9 @@ def beam_species(wl: Workload, s: int, j0: int = 0, j1: Optional[int] = None,
             out["w"][sl] = w0 * (1.0 + sp.mod_eps * np.cos(2.0 * math.pi * sp.mod_m * x / lx))
         else:
             out["w"][sl] = w0
+        if sp.w_spread > 0.0:
+            gw = _rng(wl.seed, 100 + s, j)
+            out["w"][sl] *= 1.0 + sp.w_spread * (2.0 * gw.random(n_slice) - 1.0)
     if wl.n_bins > 0:
         extent = wl.beam_slices * wl.dxi
         b = np.floor(out["xi"] / (extent / wl.n_bins)).astype(np.int32)

@@ -44,6 +44,14 @@ def test_3d_rectangular_pair_fp64():
     _case(wl, 1, "f64", 1e-10)
 
 
+def test_random_beam_weights_fp64():
+    """Random macro-particle weights (each weight times 1 + 0.9 (2U - 1)), the
+    paper's noise-control loading, through a beam step."""
+    wl = W.small_3d(32, 16, 20).with_(
+        species=(W.Species(Z=-1, alpha=0.05, ppc=4, sigma_perp=1e-3, w_spread=0.9),))
+    _case(wl, 1, "f64", 1e-10)
+
+
 def test_3d_fp32():
     _case(W.small_3d(32, 32, 24), 1, "f32", 1e-4)
 
