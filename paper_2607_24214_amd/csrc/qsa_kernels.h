@@ -218,15 +218,15 @@ __device__ __forceinline__ R beam_partial(const R* __restrict__ bp, int ny, int 
 
 // ------------------------------------------------------------ row transforms
 // Row-pass inputs of field f of a stage at slice j: the plasma partial rows
-// and out-of-row grid of the stage's deposit, the beam source (of slice j+1
-// for the predicted J_perp) and the ion background.
+// (for rho - J_z with the ion background folded in) and out-of-row grid of
+// the stage's deposit, and the beam source (of slice j+1 for the predicted
+// J_perp).
 template <typename R>
 struct RowIn {
   R* dep;             // out-of-row deposits of this field: read, then cleared
   const R* pp;        // plasma partial rows, component offset applied
   int pnc;            // components per plasma partial row block
   const R* add;       // beam source slice or null
-  R addc;             // ion background
   C2<R>* out;         // half spectra [ny][nxh]
 };
 
@@ -244,7 +244,6 @@ __device__ __forceinline__ RowIn<R> row_in(const Lane<R>& L, int j, int stage, i
   a.dep = L.dep + f * g.nperp;
   a.pp = L.ppart + (size_t)f * g.nx;
   a.out = L.rowspec + (size_t)f * g.ny * g.nxh;
-  a.addc = (stage == ST_PSI) ? R(1) : R(0);
   if (stage == ST_PSI) a.add = L.src + (int64_t)j * g.nperp;
   else if (stage == ST_J) a.add = L.src + (1 + f) * plane + (int64_t)j * g.nperp;
   else a.add = (j + 1 < g.nxi) ? L.src + (1 + f) * plane + (int64_t)(j + 1) * g.nperp : nullptr;
@@ -254,7 +253,7 @@ __device__ __forceinline__ RowIn<R> row_in(const Lane<R>& L, int j, int stage, i
 template <typename R>
 __device__ __forceinline__ R row_value(const Geo<R>& g, const RowIn<R>& a, int r, int i) {
   const int o = r * g.nx + i;
-  R v = a.addc + a.dep[o];
+  R v = a.dep[o];
   a.dep[o] = R(0);
   // partial rows: block rr covers node rows rr-1 .. rr+2 (k = 0..3)
 #pragma unroll
@@ -782,7 +781,15 @@ __global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__
   double* tile = reinterpret_cast<double*>(smem_raw);
   const int nt = blockDim.x, tid = threadIdx.x;
   const int tn = 4 * NC * g.nx;
-  for (int t = tid; t < tn; t += nt) tile[t] = 0.0;
+  // rho - J_z: the block's tile starts from half the ion density on node
+  // rows r and r + 1 (k = 1, 2), so that every node row gets the ions'
+  // +1 once, from blocks r and r - 1, and the stored partial rows hold the
+  // small difference of ions and plasma instead of the plasma density
+  // (float32 partial rows then round that difference, not O(1) values)
+  for (int t = tid; t < tn; t += nt) {
+    const int k = t / g.nx;
+    tile[t] = (MODE == PL_DEP_S && (k == 1 || k == 2)) ? 0.5 : 0.0;
+  }
   __syncthreads();
   const int p0 = a.prow[r], p1 = a.prow[r + 1];
   const int run = (p1 - p0 + nt - 1) / nt;
@@ -1637,15 +1644,40 @@ __device__ __forceinline__ void beam_fields(const Geo<R>& g, const R* __restrict
   }
 }
 
+// A beam particle's state before the push (loaded ahead of its use).
 template <typename R>
-__device__ __forceinline__ BeamNew<R> boris_one(const Geo<R>& g, const R* __restrict__ fields,
-                                                const R* __restrict__ fpack, R qh, R dt, double inv_dxi,
-                                                double xi_max, R* __restrict__ px, R* __restrict__ py,
-                                                double* __restrict__ pxi, R* __restrict__ pux, R* __restrict__ puy,
-                                                R* __restrict__ puz, R* __restrict__ pw, int64_t p) {
-  const R x = px[p], y = py[p];
-  const double xi = pxi[p];
-  R ux = pux[p], uy = puy[p], uz = puz[p];
+struct BeamOld {
+  R x, y, ux, uy, uz, w;
+  double xi;
+};
+
+template <typename R>
+__device__ __forceinline__ BeamOld<R> beam_old(const R* __restrict__ px, const R* __restrict__ py,
+                                               const double* __restrict__ pxi, const R* __restrict__ pux,
+                                               const R* __restrict__ puy, const R* __restrict__ puz,
+                                               const R* __restrict__ pw, int64_t p) {
+  BeamOld<R> o;
+  o.x = px[p];
+  o.y = py[p];
+  o.xi = pxi[p];
+  o.ux = pux[p];
+  o.uy = puy[p];
+  o.uz = puz[p];
+  o.w = pw[p];
+  return o;
+}
+
+// Boris push of particle p from its loaded state b; stores the new state.
+template <typename R>
+__device__ __forceinline__ BeamNew<R> boris_state(const Geo<R>& g, const R* __restrict__ fields,
+                                                  const R* __restrict__ fpack, R qh, R dt, double inv_dxi,
+                                                  double xi_max, const BeamOld<R>& b, R* __restrict__ px,
+                                                  R* __restrict__ py, double* __restrict__ pxi,
+                                                  R* __restrict__ pux, R* __restrict__ puy, R* __restrict__ puz,
+                                                  R* __restrict__ pw, int64_t p) {
+  const R x = b.x, y = b.y;
+  const double xi = b.xi;
+  R ux = b.ux, uy = b.uy, uz = b.uz;
   R fd[6];   // d_x psi, d_y psi, E_z, B_x, B_y, B_z
   beam_fields(g, fields, fpack, inv_dxi, x, y, xi, fd);
   const R ex = -fd[0] + fd[4];
@@ -1689,6 +1721,16 @@ __device__ __forceinline__ BeamNew<R> boris_one(const Geo<R>& g, const R* __rest
   puz[p] = uz;
   if (o.lost) pw[p] = R(0);
   return o;
+}
+
+template <typename R>
+__device__ __forceinline__ BeamNew<R> boris_one(const Geo<R>& g, const R* __restrict__ fields,
+                                                const R* __restrict__ fpack, R qh, R dt, double inv_dxi,
+                                                double xi_max, R* __restrict__ px, R* __restrict__ py,
+                                                double* __restrict__ pxi, R* __restrict__ pux, R* __restrict__ puy,
+                                                R* __restrict__ puz, R* __restrict__ pw, int64_t p) {
+  const BeamOld<R> b = beam_old<R>(px, py, pxi, pux, puy, puz, pw, p);
+  return boris_state(g, fields, fpack, qh, dt, inv_dxi, xi_max, b, px, py, pxi, pux, puy, puz, pw, p);
 }
 
 template <typename R>
@@ -1799,24 +1841,30 @@ __device__ __forceinline__ int wave_class_rank(int* cnt, int c, bool act) {
   return rank;
 }
 
-// Push particle p of species s; with feeds, also its new cell row (-1: none,
-// or deposited here).  Returns whether the schedule is broken.
 template <typename R>
-__device__ __forceinline__ bool pipe_push_one(const PipeBeam<R>& B, int s, int64_t p, int jp, bool slab, bool feeds,
-                                              int& row) {
+__device__ __forceinline__ BeamOld<R> pipe_old(const PipeBeam<R>& B, int s, int64_t p) {
+  return beam_old<R>(B.x[s], B.y[s], B.xi[s], B.ux[s], B.uy[s], B.uz[s], B.w[s], p);
+}
+
+// Push particle p of species s from its loaded state b; with feeds, also
+// its new cell row (-1: none, or deposited here).  Returns whether the
+// schedule is broken.
+template <typename R>
+__device__ __forceinline__ bool pipe_push_one(const PipeBeam<R>& B, int s, int64_t p, const BeamOld<R>& b, int jp,
+                                              bool slab, bool feeds, int& row) {
   const Geo<R>& g = B.g;
   bool bad = false;
   row = -1;
-  const double gz = B.xi[s][p] * B.inv_dxi;
+  const double gz = b.xi * B.inv_dxi;
   if (slab) {
     // fields are final up to slice jp + 3; a deposit must reach the next
     // lane before it sweeps slice jp - 3
     if (gz > -1.0 && gz < (double)g.nxi && gz >= (double)(jp + 3)) bad = true;
-    if (feeds && B.w[s][p] != R(0) && gz < (double)(jp - 3)) bad = true;
+    if (feeds && b.w != R(0) && gz < (double)(jp - 3)) bad = true;
   }
-  const R w0 = B.w[s][p];
-  const BeamNew<R> n = boris_one(g, B.fields, B.fpack, B.qmh[s], B.dt, B.inv_dxi, B.xi_max, B.x[s], B.y[s], B.xi[s],
-                                 B.ux[s], B.uy[s], B.uz[s], B.w[s], p);
+  const R w0 = b.w;
+  const BeamNew<R> n = boris_state(g, B.fields, B.fpack, B.qmh[s], B.dt, B.inv_dxi, B.xi_max, b, B.x[s], B.y[s],
+                                   B.xi[s], B.ux[s], B.uy[s], B.uz[s], B.w[s], p);
   if (!feeds) return bad;
   const R w = n.lost ? R(0) : w0;
   const double gn = n.xi * B.inv_dxi;
@@ -1857,11 +1905,16 @@ __global__ void __launch_bounds__(256) k_pipe_push(const PipeBeam<R>* __restrict
     for (int i = threadIdx.x; i < g.ny; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
     const int64_t p0 = B.rowoff[s][row], p1 = B.rowoff[s][row + 1];
+    // each thread loads its next particle before pushing the current one
+    BeamOld<R> cur{}, nxt{};
+    if (p0 + threadIdx.x < p1) cur = pipe_old(B, s, p0 + threadIdx.x);
     for (int64_t b0 = p0; b0 < p1; b0 += blockDim.x) {
       const int64_t p = b0 + threadIdx.x;
       const bool act = p < p1;
+      if (p + blockDim.x < p1) nxt = pipe_old(B, s, p + blockDim.x);
       int L = -1;
-      if (act) bad |= pipe_push_one(B, s, p, jp, true, feeds, L);
+      if (act) bad |= pipe_push_one(B, s, p, cur, jp, true, feeds, L);
+      cur = nxt;
       if (!feeds) continue;
       const int r = wave_class_rank(cnt, L, act && L >= 0);
       if (act) B.tag[s][p] = (L >= 0) ? ((r << 9) | L) : -1;
@@ -1878,7 +1931,7 @@ __global__ void __launch_bounds__(256) k_pipe_push(const PipeBeam<R>* __restrict
       for (int64_t p = B.rowoff[s][(int64_t)(jp + 1) * g.ny] + (int64_t)l * blockDim.x + threadIdx.x; p < t1;
            p += (int64_t)g.ny * blockDim.x) {
         int L;
-        bad |= pipe_push_one(B, s, p, jp, false, feeds, L);
+        bad |= pipe_push_one(B, s, p, pipe_old(B, s, p), jp, false, feeds, L);
       }
     }
     __syncthreads();

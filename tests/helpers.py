@@ -60,3 +60,16 @@ def slice_errors(got: dict, ref: dict, j0: int = 0, j1=None):
             if e > worst:
                 worst, where = e, (f, j)
     return worst, where
+
+
+def psi_floor(wl, precision):
+    """Rounding floor of the L2 norm of psi on one slice.  A CIC weight is
+    known to eps_w: float64 weights come from absolute positions, so
+    eps_w = eps_64 n_x (positions up to n_x cells, resolved to eps_64 of
+    their value); float32 weights are rounded to eps_32.  Independent
+    errors of that size in the deposited source, carried through the
+    inverse Laplacian, give ||d psi||_2 ~ eps_w (L/2 pi)^2 (sum over
+    m != 0 of |m|^-4)^(1/2), the sum about 6."""
+    L = max(wl.nx * wl.dx, wl.ny * wl.dy)
+    eps_w = np.finfo(np.float64).eps * max(wl.nx, wl.ny) if precision == "f64" else np.finfo(np.float32).eps
+    return eps_w * (L / (2.0 * np.pi)) ** 2 * np.sqrt(6.0)

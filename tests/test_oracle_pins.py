@@ -413,3 +413,33 @@ def test_beam_leaving_box_is_dropped():
     assert float(b["w"]) == 0.0
     b = O.boris_push(g, _beam1(xi=1.0, uz=2.0), -1, 1.0, fields, 1.0)
     assert float(b["w"]) == 1.0
+
+
+def test_psi_rounding_floor_on_the_dilute_pair_box():
+    """On the 512^2 pair box psi is set by rounding: a one-ulp change of the
+    plasma template positions alone moves the oracle's psi on the first
+    slice by 40% of the float64 relative bound (1e-10 of the slice's field
+    scale), and the estimated floor the GPU parity test holds psi to is of
+    that size (within a factor 30), not a loose bound."""
+    from tests.helpers import psi_floor
+    wl = W.pair512()
+    sub = wl.with_(nxi=2)
+    g = O.Grid.of(sub)
+    pt = W.plasma_template(sub)
+    beams = [O.to_torch(b) for b in W.beam(wl, 0, 2)]
+    src = O.beam_sources(g, beams, [s.Z for s in sub.species])
+
+    def psi_and_scale(plasma):
+        f = O.output_fields(O.slice_sweep(g, O.to_torch(plasma), src, sub.n_corr, sub.kappa2))
+        return f["psi"][0].numpy(), max(float(np.linalg.norm(v[0].numpy())) for v in f.values())
+
+    a, scale = psi_and_scale(pt)
+    rng = np.random.default_rng(2)
+    pu = dict(pt)
+    for k in ("x", "y"):
+        pu[k] = np.nextafter(pt[k], pt[k] + rng.choice([-1.0, 1.0], size=pt[k].size))
+    b, _ = psi_and_scale(pu)
+    d = float(np.linalg.norm(b - a))
+    floor = psi_floor(wl, "f64")
+    assert 0.2e-10 * scale < d, (d, scale)
+    assert floor / 30 < d <= floor, (d, floor)
