@@ -200,3 +200,59 @@ def test_pair512_pipelined_steps_equal_sequential_fp32():
             du = float(np.abs(bu[sp][k] - bs[sp][k]).max())
             scale = max(1.0, float(np.abs(bs[sp][k]).max()))
             assert d <= max(1e-5 * scale, 10 * du), (sp, k, d, du)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_scan_instances_batched_equal_alone(precision, tol):
+    """Five instances of the 64-instance parameter scan at their real sizes
+    (64 x 64 x 128 up to 256 x 64 x 128 and 64 x 64 x 1024; alpha from
+    5e-4 to 0.09, gamma_b from 16 to 3237, each with its own dt) advanced
+    together as one batch for 2 steps: every member equals the same box run
+    alone at every slice, to the working-precision bound or, where the
+    plasma has amplified rounding beyond it, to ten times what a one-ulp
+    change of the plasma positions does in that box."""
+    import paper_2607_24214_amd as Q
+    pick = ("scan23", "scan26", "scan30", "scan15", "scan08")
+    wls = [w for w in W.scan_instances(64) if w.name in pick]
+    assert len(wls) == len(pick)
+
+    def make(wl, plasma, beam):
+        s = Q.Sim(Q.params_from_workload(wl, precision=precision, beam_capacity=[len(beam["x"])]))
+        s.load_plasma(plasma)
+        s.load_beam(0, beam)
+        return s
+
+    def outs(s):
+        return {k: s.fields(k) for k in OUT_FIELDS}
+
+    members, alone, ulp = [], [], []
+    rng = np.random.default_rng(3)
+    for wl in wls:
+        plasma, beam = W.plasma_template(wl), W.beam(wl)[0]
+        pu = dict(plasma)
+        pu["x"] = np.nextafter(plasma["x"], plasma["x"] + rng.choice([-1.0, 1.0], size=plasma["x"].size))
+        members.append(make(wl, plasma, beam))
+        for lst, pl in ((alone, plasma), (ulp, pu)):
+            s = make(wl, pl, beam)
+            s.beam_step(2)
+            s.slice_sweep()
+            lst.append(outs(s))
+            del s
+    batch = Q.Batch(members)
+    batch.step(2)
+    batch.sweep()
+    batch.sync()
+    for wl, sb, ra, ru in zip(wls, members, alone, ulp):
+        got = outs(sb)
+        for j in range(wl.nxi):
+            one = lambda d: {k: v[j:j + 1] for k, v in d.items()}
+            e, where = slice_errors(one(got), one(ra))
+            eu, _ = slice_errors(one(ru), one(ra))
+            assert e <= max(tol, 10 * eu), (wl.name, j, e, eu, where)
+        e, where = slice_errors(got, ra)
+        eu, whereu = slice_errors(ru, ra)
+        print(f"[scan] {wl.name} {wl.nx}x{wl.ny}x{wl.nxi} {precision}: batched vs alone {e:.3e} at {where}; "
+              f"one-ulp plasma change {eu:.3e} at {whereu}", flush=True)
+    batch.close()
+    del members
+    _free()
