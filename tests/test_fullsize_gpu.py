@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import qsa_workloads as W
-from tests.helpers import OUT_FIELDS, psi_floor, slice_errors
+from tests.helpers import OUT_FIELDS, psi_floor, run_gpu, run_oracle, slice_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -256,3 +256,30 @@ def test_scan_instances_batched_equal_alone(precision, tol):
     batch.close()
     del members
     _free()
+
+
+def test_slab_workload_all_steps_fp64():
+    """The whole 1D slab workload (64 cells x 128 slices, e- beam alpha 0.1,
+    gamma_b 100, seeded noise) for all of its 50 beam steps against the
+    oracle.  The beam is unstable, so rounding grows with the instability:
+    the bound is 1e-10 of the slice's field scale or ten times what a
+    one-ulp change of the plasma positions does on the GPU after the same
+    steps, whichever is larger."""
+    wl = W.slab_electron()
+    _, ref = run_oracle(wl, steps=wl.steps)
+    _, got = run_gpu(wl, steps=wl.steps, precision="f64")
+    pt = W.plasma_template(wl)
+    rng = np.random.default_rng(4)
+    pu = dict(pt)
+    pu["x"] = np.nextafter(pt["x"], pt["x"] + rng.choice([-1.0, 1.0], size=pt["x"].size))
+    _, gu = run_gpu(wl, steps=wl.steps, precision="f64", plasma=pu)
+    worst = (0.0, None)
+    for j in range(wl.nxi):
+        one = lambda d: {k: v[j:j + 1] for k, v in d.items()}
+        e, _ = slice_errors(one(got), one(ref))
+        eu, _ = slice_errors(one(gu), one(got))
+        assert e <= max(1e-10, 10 * eu), (j, e, eu)
+        worst = max(worst, (e, j), key=lambda t: t[0])
+    eu_all, _ = slice_errors(gu, got)
+    print(f"[full] {wl.name}: {wl.steps} steps vs oracle {worst[0]:.3e} at slice {worst[1]}; "
+          f"one-ulp plasma change {eu_all:.3e}", flush=True)
