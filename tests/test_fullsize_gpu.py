@@ -30,11 +30,11 @@ def _free():
     torch.cuda.empty_cache()
 
 
-def _full_sim(wl, precision, pipeline, beams):
+def _full_sim(wl, precision, pipeline, beams, plasma=None):
     import paper_2607_24214_amd as Q
     caps = [len(b["x"]) for b in beams]
     sim = Q.Sim(Q.params_from_workload(wl, precision=precision, beam_capacity=caps, pipeline=pipeline))
-    sim.load_plasma(W.plasma_template(wl))
+    sim.load_plasma(plasma if plasma is not None else W.plasma_template(wl))
     for s, b in enumerate(beams):
         sim.load_beam(s, b)
     return sim
@@ -283,3 +283,46 @@ def test_slab_workload_all_steps_fp64():
     eu_all, _ = slice_errors(gu, got)
     print(f"[full] {wl.name}: {wl.steps} steps vs oracle {worst[0]:.3e} at slice {worst[1]}; "
           f"one-ulp plasma change {eu_all:.3e}", flush=True)
+
+
+def test_benchmark_workload_all_steps_pipelined_vs_sequential_fp64():
+    """All 200 beam steps of the benchmark workload (the beam filaments on
+    the way), 8 in flight against one at a time, at sampled slices and in
+    the beam's momentum moments per 16-slice window: the difference is held
+    to 1e-10 or to ten times what a one-ulp change of the plasma positions
+    does over the same 200 steps, whichever is larger (the instability
+    amplifies rounding: the one-ulp change reaches about 1e-7 of the field
+    scale at the last slices)."""
+    wl = W.cube256()
+    beams = W.beam(wl)
+    pt = W.plasma_template(wl)
+    rng = np.random.default_rng(5)
+    pu = dict(pt)
+    pu["x"] = np.nextafter(pt["x"], pt["x"] + rng.choice([-1.0, 1.0], size=pt["x"].size))
+    slices = (0, 37, 255, 400, 510)
+
+    def run(pipeline, plasma):
+        sim = _full_sim(wl, "f64", pipeline, beams, plasma)
+        sim.beam_step(wl.steps)
+        depth = sim.pipeline
+        sim.slice_sweep()
+        f = {j: {k: sim.fields(k, j, j + 1) for k in OUT_FIELDS} for j in slices}
+        m = sim.beam_moments(0, 16)
+        del sim
+        _free()
+        return f, m, depth
+
+    fp, mp, depth = run(8, pt)
+    fs, ms, _ = run(1, pt)
+    fu, mu, _ = run(1, pu)
+    assert depth == 8   # no group fell back to one step at a time
+    for j in slices:
+        e, where = slice_errors(fp[j], fs[j])
+        eu, _ = slice_errors(fu[j], fs[j])
+        print(f"[full] {wl.name} after {wl.steps} steps, slice {j}: pipelined vs sequential {e:.3e} at {where}; "
+              f"one-ulp plasma change {eu:.3e}", flush=True)
+        assert e <= max(1e-10, 10 * eu), (j, e, eu)
+    scale = float(np.abs(ms).max())
+    dm, dmu = float(np.abs(mp - ms).max()) / scale, float(np.abs(mu - ms).max()) / scale
+    print(f"[full] beam moments: pipelined vs sequential {dm:.3e}; one-ulp plasma change {dmu:.3e}", flush=True)
+    assert dm <= max(1e-10, 10 * dmu), (dm, dmu)
