@@ -321,7 +321,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the slice sweep runs on a single MI355X; "
-              "multi-GPU runs are not part of this build (--gpus must be 1)", file=sys.stderr)
+              "running on several GPUs is not implemented (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
