@@ -301,7 +301,6 @@ __global__ void __launch_bounds__(64 * SPEC_IN) k_spec_cols(Geo<R> g, SpecOp<R> 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
   const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
-  const int nw = blockDim.x >> 6;
   C2<R>* A = tw + g.ny + (int64_t)(2 * w) * g.ny;
   C2<R>* B = A + g.ny;
   for (int i = threadIdx.x; i < g.ny; i += blockDim.x) tw[i] = twy[i];
@@ -337,7 +336,6 @@ __global__ void __launch_bounds__(64 * SPEC_IN) k_spec_cols(Geo<R> g, SpecOp<R> 
   __syncthreads();
   C2<R>* other = const_cast<C2<R>*>(res(w));
   const C2<R>* q = fft_lds<R, true>(S, other, g.ny, g.lgy, t, 64, tw);
-  (void)nw;
   if (w < op.no)
     for (int i = t; i < g.ny; i += 64) op.work[(int64_t)w * g.nperp + (int64_t)i * g.nx + kx] = q[i];
 }

@@ -31,7 +31,7 @@ struct LinOut {
 // Exclusive block-wide prefix sums of (a, b) over the threads in order;
 // ws: LDS scratch of 2 x 16 doubles.  Every thread calls it.
 __device__ __forceinline__ void lin_block_scan(double& a, double& b, double* ws) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   double ia = a, ib = b;
   for (int o = 1; o < 64; o <<= 1) {
     const double ua = __shfl_up(ia, o), ub = __shfl_up(ib, o);
@@ -50,7 +50,6 @@ __device__ __forceinline__ void lin_block_scan(double& a, double& b, double* ws)
     oa += ws[k];
     ob += ws[16 + k];
   }
-  (void)nw;
   a = oa + ia - a;
   b = ob + ib - b;
   __syncthreads();
