@@ -1,4 +1,7 @@
-"""Growth-rate gate (current filamentation): the pair-beam slab with a single
+"""Growth-rate gates: current filamentation along the transition ray, and
+the oblique two-stream region behind it (second half of this file).
+
+Filamentation: the pair-beam slab with a single
 seeded transverse mode (lattice-loaded e- and e+ beams, weights modulated
 +-1e-3 at mode m = 5), |B_y(k_m)| sampled along the ray xi = (2/sqrt 27)
 Gamma tau, growth rate fitted over Gamma tau in [4, 7.75].
