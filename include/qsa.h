@@ -268,11 +268,13 @@ enum {
                             256, or 0 for the default (from the particles per
                             row); get: the value in use                     */
   QSA_OPT_ROW_THREADS = 3, /* threads per row-transform block: 64, 128, 256
-                            (a multiple of nx/4), or 0 for max(64, nx/4);
+                            (a multiple of nx/4), or 0 for
+                            min(256, max(64, nx/2));
                             get: the value in use                           */
   QSA_OPT_COL_THREADS = 4 /* threads per column transform: 16, 32 or 64 (a
                             wavefront takes 64 / value adjacent columns), or
-                            0 for the default; get: the value in use        */
+                            0 for 64; at most ny/4 are used; get: the value
+                            in use                                          */
 };
 
 /* Set a context option (see QSA_OPT_*). */

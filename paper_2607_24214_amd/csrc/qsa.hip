@@ -732,7 +732,7 @@ struct Engine {
   }
   static void finish_dims(Dims& d, const qsa_params* const* ps, int n, int nt = 0, int rt = 0, int ct = 0) {
     d.ctpt = (ct == 16 || ct == 32 || ct == 64) ? ct : 0;
-    d.rt_rows = std::max(64, d.nx / 4);
+    d.rt_rows = std::min(256, std::max(64, d.nx / 2));   // two row pairs per block from nx = 256
     if (rt >= d.nx / 4 && rt % (d.nx / 4) == 0 && rt <= 256) d.rt_rows = rt;
     d.nt = std::max(64, std::min(256, (d.per_row + 63) / 64 * 64));
     if (nt == 64 || nt == 128 || nt == 256) d.nt = nt;
@@ -1112,7 +1112,6 @@ struct Engine {
     for (int ct = 32; ct >= 16; ct /= 2)
       if (col_lds(c->p.ny, ct) <= limit) colj = std::max(colj, col_lds(c->p.ny, ct));
     c->col_lds_max = colj;
-    if (c->tune_ct == 0 && col_lds(c->p.ny, QSA_COL_TPT) > colj) c->tune_ct = 64;   // the default does not fit
     if (colj > 65536) {
       HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_col<R, COL_PSI>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, colj));

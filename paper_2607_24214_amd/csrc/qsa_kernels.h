@@ -465,7 +465,7 @@ struct ColShape {
 // (16, 32 or 64; 0 = QSA_COL_TPT) capped at ny/4.  A wavefront takes
 // 64 / threads adjacent columns, so fewer threads per transform read and
 // write longer runs of each spectral row.
-#define QSA_COL_TPT 32
+#define QSA_COL_TPT 64
 __host__ __device__ __forceinline__ int col_tpt(int ny, int want = 0) {
   const int w = want > 0 ? want : QSA_COL_TPT;
   const int t = ny >> 2;
