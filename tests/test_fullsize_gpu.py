@@ -326,3 +326,38 @@ def test_benchmark_workload_all_steps_pipelined_vs_sequential_fp64():
     dm, dmu = float(np.abs(mp - ms).max()) / scale, float(np.abs(mu - ms).max()) / scale
     print(f"[full] beam moments: pipelined vs sequential {dm:.3e}; one-ulp plasma change {dmu:.3e}", flush=True)
     assert dm <= max(1e-10, 10 * dmu), (dm, dmu)
+
+
+def test_diagnostics_at_full_size_fp64():
+    """Device diagnostics on the benchmark workload after a pipelined step:
+    field moments for every window (windows of 8 and 40 slices: 64 and 13
+    windows, more than the kernel's 32 LDS window bins in the first case)
+    against the oracle's definitions on the host copy of the fields, and
+    beam moments on sampled windows (the particles of those windows only,
+    summed by the oracle's definition)."""
+    from oracle import diagnostics as D
+    wl = W.cube256()
+    beams = W.beam(wl)
+    sim = _full_sim(wl, "f64", 8, beams)
+    del beams
+    sim.beam_step(1)
+    sim.slice_sweep()
+    per = D.field_slice_means({k: sim.fields(k) for k in D.FIELDS})
+    beam = sim.read_beam(0)
+    for window in (8, 40):
+        got = sim.field_moments(window)
+        ref = D.windows(per, 1.0, float(window)) / D.window_counts(per.shape[0], 1.0, float(window))[:, None]
+        err = float(np.abs(got - ref).max() / np.abs(ref).max())
+        assert err <= 1e-12, (window, err)
+        gb = sim.beam_moments(0, window)
+        j = np.floor(beam["xi"] / wl.dxi)
+        for w in (0, 5, gb.shape[0] - 1):
+            sel = (j >= w * window) & (j < (w + 1) * window)
+            sub = {k: v[sel] for k, v in beam.items()}
+            ref_w = D.beam_slice_sums(sub, wl.dxi, wl.nxi).sum(axis=0)
+            e = float(np.abs(gb[w] - ref_w).max() / np.abs(ref_w).max())
+            print(f"[full] diagnostics window {window} (#{w}): beam moments {e:.2e}; field moments {err:.2e}",
+                  flush=True)
+            assert e <= 1e-12, (window, w, e)
+    del sim
+    _free()
