@@ -114,3 +114,25 @@ def test_profile_shape_checked():
         Q.linear_model(np.ones((1, 9)), np.ones(10), 0.01, [1.0], 0.1)
     with pytest.raises(ValueError):
         Q.linear_model(np.ones((2, 10)), np.ones((3, 10)), 0.01, [1.0], 0.1)
+
+
+def test_benchmark_scan_sampled_against_oracle():
+    """The benchmark's growth-rate scan (64 instances, 2001 points of xi,
+    800 RK4 steps, 17 output times) in one launch; four instances (the
+    smallest and largest Gamma and two others) against the oracle's solver
+    at every output time."""
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    import paper_2607_24214_amd as Q
+    gam, xi, seeds, dtau, taus = bench.linear_model_scan()
+    n_g, p_g = Q.linear_model(gam, seeds, float(xi[1] - xi[0]), taus, dtau)
+    n_g, p_g = n_g.cpu().numpy(), p_g.cpu().numpy()
+    for b in sorted({int(np.argmin(gam)), int(np.argmax(gam)), 7, 40}):
+        n_o, p_o = LT.solve_eq5(gam[b], xi, seeds[b], taus, dtau)
+        for m in range(taus.size):
+            en, ep = _rel(n_g[b, m], n_o[m]), _rel(p_g[b, m], p_o[m])
+            assert en <= 1e-10 and ep <= 1e-10, (b, m, en, ep)
+        print(f"[linear] scan instance {b} (Gamma {gam[b]:.4f}): n {en:.2e}, psi {ep:.2e} at the last time",
+              flush=True)
