@@ -127,7 +127,8 @@ size_t qsa_workspace_bytes(const qsa_params* p);
 qsa_status qsa_create(const qsa_params* p, void* dev_ws, size_t ws_bytes,
                       void* hip_stream, qsa_ctx** out);
 
-/* Load the plasma template: the n = p->n_plasma macro-particles that enter
+/* Load the plasma template (the cold or warm plasma electrons of the
+ * problem statement, "Quasistatic model" section): the n = p->n_plasma macro-particles that enter
  * every slice sweep at xi = 0 (positions x, y in [0, L), momenta u_x, u_y;
  * u_z follows from gamma - u_z = 1).  Arrays are float64, host memory when
  * on_device = 0 (the call then synchronizes), device memory otherwise.
@@ -136,7 +137,9 @@ qsa_status qsa_load_plasma(qsa_ctx* c, const double* x, const double* y,
                            const double* ux, const double* uy, int64_t n,
                            int32_t on_device);
 
-/* Load n (<= capacity) particles of beam species s: position (x, y, xi),
+/* Load n (<= capacity) particles of beam species s (the beam species of
+ * the problem statement; flat-top loading as in the "PIC simulations"
+ * section): position (x, y, xi),
  * momentum (u_x, u_y, u_z) and weight w (number of physical particles per
  * unit n_p, i.e. alpha dV/ppc for a uniform beam).  A particle with w = 0 is
  * inert.  Float64 arrays, host (synchronizing) or device memory.  Any order;
@@ -154,12 +157,16 @@ qsa_status qsa_read_beam(qsa_ctx* c, int32_t s, double* x, double* y,
                          double* xi, double* ux, double* uy, double* uz,
                          double* w, int64_t cap, int64_t* n, int32_t on_device);
 
-/* One quasistatic sweep at the current tau: beam sources from the beam
- * particles, then the plasma response slice by slice from xi = 0 to the
- * tail.  Fields of every slice are kept until the next sweep. */
+/* One quasistatic sweep at the current tau (the field and plasma equations
+ * at fixed tau of the "Quasistatic model" section, whose linearization is
+ * Eqs. (1)-(2)): beam sources from the beam particles, then the plasma
+ * response slice by slice from xi = 0 to the tail.  Fields of every slice
+ * are kept until the next sweep. */
 qsa_status qsa_slice_sweep(qsa_ctx* c);
 
-/* n_steps x (qsa_slice_sweep; Boris push of every beam species by dt).
+/* n_steps x (qsa_slice_sweep; Boris push of every beam species by dt): the
+ * slow evolution of the beam in tau in the quasistatic fields ("Quasistatic
+ * model" section; linearized, Eq. (3)).
  *
  * With pipeline = P > 1 the steps run in groups of up to P steps in flight:
  * step n0 + k sweeps QSA_PIPE_LAG = 8 slices behind step n0 + k - 1 in the
@@ -175,7 +182,9 @@ qsa_status qsa_slice_sweep(qsa_ctx* c);
  * calls synchronize once per group (to read that flag). */
 qsa_status qsa_beam_step(qsa_ctx* c, int32_t n_steps);
 
-/* Copy slices [xi0, xi1) of one field of the last sweep as float64 into dst
+/* Fields of the last sweep (psi is minus the paper's Psi of Eq. (2); the
+ * transverse force on a v = c particle is -grad psi, the paper's F_perp).
+ * Copy slices [xi0, xi1) of one field of the last sweep as float64 into dst
  * (count >= (xi1 - xi0) * nx * ny values), host or device memory.
  * Synchronizing; reports a pending device error. */
 qsa_status qsa_fields(qsa_ctx* c, int32_t field, int32_t xi0, int32_t xi1,
@@ -284,7 +293,10 @@ qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value);
 qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value);
 
 /* Gradient of the transverse magnetic energy with respect to beam-amplitude
- * bins (requires adjoint_steps >= n_steps at create).
+ * bins (requires adjoint_steps >= n_steps at create).  The paper has no
+ * adjoint: this differentiates the discrete form of its quasistatic model
+ * (the operations of qsa_slice_sweep and qsa_beam_step); the field energy is
+ * the quantity behind its saturation estimates (discussion of Fig. 3).
  *
  * Starting from the beam as loaded (or as left by the last step), with every
  * particle's weight scaled by amps[bin] (bins[s][p] in [0, n_bins): the bin of
@@ -301,9 +313,10 @@ qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value);
 qsa_status qsa_adjoint_sweep(qsa_ctx* c, int32_t n_steps, int32_t n_bins, const double* amps,
                              const int32_t* const* bins, double* loss, double* grad);
 
-/* Autotuner: times real work on this context's data (direct launches, HIP
- * events) and keeps the fastest threads per plasma-row block (64/128/256),
- * threads per row-transform block (64/128/256, multiples of nx/4) and, with
+/* Autotuner (launch shapes only, nothing the paper defines): times real work
+ * on this context's data (direct launches, HIP events) and keeps the fastest
+ * threads per plasma-row block (64/128/256), threads per row-transform block
+ * (64/128/256, multiples of nx/4), threads per column transform and, with
  * pipeline > 1, beam steps in flight (2, 4, ... up to pipeline).  A trial is
  * a group of steps in flight, after which the beam is restored, or (pipeline
  * <= 1) one sweep.  The beam and the device flags are as before the call;
@@ -315,7 +328,9 @@ qsa_status qsa_autotune(qsa_ctx* c, double* ms_per_step);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent boxes (a growth-rate parameter scan: different
- * nx, ny, nxi, alpha, gamma_b, dt per box) advanced together.  The slice
+ * nx, ny, nxi, alpha, gamma_b, dt per box, as in the paper's comparison of
+ * growth rates across beam parameters in its results section) advanced
+ * together.  The slice
  * loops of all member contexts run as lanes of the same kernel launches (one
  * launch per phase per slice for the whole batch; a box with fewer slices
  * drops out), and the whole batched sweep or step is captured once into a
