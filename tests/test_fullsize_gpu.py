@@ -71,6 +71,33 @@ def test_first_slices_match_oracle(precision, tol):
     assert err <= tol, (err, where)
 
 
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_first_slices_after_two_pipelined_steps_match_oracle(precision, tol):
+    """Two beam steps in flight on the full box, then a sweep, against the
+    oracle's two steps on the first 12 slices with the beam of the first 12
+    cells.  Beam particles only drift to larger xi, a push reads the fields
+    of its cell's two node slices and a slice's fields need the sources up
+    to the next node slice, so each step narrows the exact region by two
+    slices: slices 0 .. 12 - 2 - 2 x 2 = 0 .. 6 are those of the full box."""
+    wl = W.cube256()
+    k = 12
+    beams = W.beam(wl)
+    sim = _full_sim(wl, precision, 8, beams)
+    del beams
+    sim.beam_step(2)
+    sim.slice_sweep()
+    n_ok = k - 2 - 2 * 2 + 1
+    got = {f: sim.fields(f, 0, n_ok) for f in OUT_FIELDS}
+    del sim
+    _free()
+    _, ref = run_oracle(wl.with_(nxi=k), steps=2, beams=W.beam(wl, 0, k))
+    ref = {f: v[:n_ok] for f, v in ref.items()}
+    err, where = slice_errors(got, ref)
+    print(f"[full] {wl.name} {precision}: 2 pipelined steps, first {n_ok} slices vs oracle {err:.3e} at {where}",
+          flush=True)
+    assert err <= tol, (err, where)
+
+
 def test_pipelined_steps_equal_sequential_full_size_fp64():
     wl = W.cube256()
     beams = W.beam(wl)
