@@ -29,8 +29,10 @@
  *     calls documented as synchronizing.  The library runs its kernels on
  *     a stream of its own, ordered after the work enqueued on the caller's
  *     stream before the call, and the caller's stream is ordered after the
- *     call's work; the sweep and the beam step are captured once into HIP
- *     graphs and replayed (QSA_OPT_GRAPHS).
+ *     call's work; the sweep and the single beam step are captured once
+ *     into HIP graphs and replayed (QSA_OPT_GRAPHS); a group of steps in
+ *     flight is enqueued directly on two streams of the library's (the beam
+ *     work of each slice tick alongside the next ticks of the slice loop).
  *   - A context is used from one host thread at a time.
  *
  * Errors
@@ -267,7 +269,8 @@ qsa_status qsa_timing_end(qsa_ctx* c, double* total_ms, int64_t* launches);
 /* Options for qsa_set_option / qsa_get_option. */
 enum {
   QSA_OPT_GRAPHS = 0,    /* 1 (default): replay a captured HIP graph of the sweep
-                            and of the beam step; 0: enqueue every launch   */
+                            and of the single beam step; 0: enqueue every
+                            launch (groups of steps in flight always are)  */
   QSA_OPT_PIPELINE = 1,  /* beam steps in flight in qsa_beam_step: set 1..P
                             (values above the parameter's pipeline = P are
                             clamped to P; setting also re-enables pipelining
