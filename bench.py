@@ -390,7 +390,7 @@ def main():
     depth = sim.pipeline
     sim.beam_step(depth)
     sim.sync()
-    # timed region: exactly K steps (graph replays) between synchronizations
+    # timed region: exactly K steps (groups of steps in flight) between synchronizations
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.beam_step(args.steps)

@@ -1,6 +1,6 @@
 """Parity at the full size of the benchmark workload (3D 256 x 256 x 512,
 268 M beam particles) in the launch configuration the benchmark times
-(8 beam steps in flight, graphs, default launch shapes), and on the box of
+(8 beam steps in flight on two streams, default launch shapes), and on the box of
 the dilute pair-beam workload (3D 512 x 512 x 2048, two species).
 
 The oracle cannot sweep 512 slices of this box in seconds, but a slice
