@@ -341,7 +341,6 @@ struct qsa_ctx {
     }
     if (bstream) (void)hipStreamDestroy(bstream);
     if (stream) (void)hipStreamDestroy(stream);
-    (void)hipDeviceSynchronize();
   }
 };
 
@@ -356,6 +355,8 @@ struct qsa_batch {
   hipGraphExec_t gx_step = nullptr, gx_sweep = nullptr;
   bool use_graphs = true;
   ~qsa_batch() {
+    // finish the batch's work before its graphs and stream go
+    if (stream) (void)hipStreamSynchronize(stream);
     if (gx_step) (void)hipGraphExecDestroy(gx_step);
     if (gx_sweep) (void)hipGraphExecDestroy(gx_sweep);
     if (ev_in) (void)hipEventDestroy(ev_in);
@@ -812,7 +813,13 @@ struct Engine {
         QSA_LAUNCH(tc, QSA_K_ROW_C2R, k_row_c2r<R>, rgrid_b, rblock, smem_rows, st, lanes, j, (int)ST_B);
       }
       // ---- advance the plasma to slice j+1
-      if (before_final && hipStreamWaitEvent(st, before_final, 0) != hipSuccess) return QSA_E_DEVICE;
+      if (before_final) {
+        const hipError_t e = hipStreamWaitEvent(st, before_final, 0);
+        if (e != hipSuccess) {
+          tc->sticky = QSA_E_DEVICE;
+          return fail(tc, QSA_E_DEVICE, std::string("hipStreamWaitEvent: ") + hipGetErrorString(e));
+        }
+      }
       QSA_LAUNCH(tc, QSA_K_PUSH_FINAL, k_push_final<R>, dim3(pb, 1, n), dim3(256), 0, st, lanes, j);
     }
     return QSA_OK;
@@ -867,6 +874,21 @@ struct Engine {
   // QSA_PIPE_LAG slices behind lane k - 1, pushes each beam slab as soon as
   // its fields are final there and deposits it as lane k + 1's sources.
   static qsa_status group(qsa_ctx* c, int n) {
+    int last = -1;
+    const qsa_status st = group_body(c, n, last);
+    if (st != QSA_OK && last >= 0) {
+      // an early exit: order the work stream after the beam work already
+      // enqueued, so that no later call overlaps it
+      if (hipStreamWaitEvent(c->stream, c->gdone[last % QSA_GEV], 0) != hipSuccess)
+        (void)hipStreamSynchronize(c->bstream);
+    }
+    if (st != QSA_OK && c->sticky == QSA_OK) c->sticky = st;
+    return st;
+  }
+
+  // The body of group(); `last` receives the last tick whose beam work was
+  // enqueued on the beam stream (-1: none).
+  static qsa_status group_body(qsa_ctx* c, int n, int& last) {
     const qsa_params& p = c->p;
     const Layout& L = c->L;
     const Geo<R> g = geo(p);
@@ -885,14 +907,13 @@ struct Engine {
     const int T = p.nxi + 2 + (n - 1) * QSA_PIPE_LAG;
     // The beam work of tick t (push, row sort, deposit of the slabs behind
     // every lane) runs on a stream of its own, after the slice loop's tick t
-    // and alongside its next ticks.  It reads packed field slots down to
-    // slice t - lag - 6, which the final advance of tick t + 2 overwrites,
-    // and writes sources of the next lane first read at tick t + 4: so the
-    // final advance of tick t + 2 waits for it.
-    int last = -1;
+    // and alongside its next ticks; the final advance of tick
+    // t + QSA_RING_WAIT waits for it (the constraints are in qsa_kernels.h).
+    static_assert(QSA_RING_WAIT < QSA_GEV, "event ring too short");
     for (int t = 0; t < T; ++t) {
       if (t % QSA_PIPE_LAG == 0 && t < n * QSA_PIPE_LAG) clear_lanes(c->stream, lanes, d, t);
-      hipEvent_t wait = (t - 2 >= QSA_PUSH_LAG) ? c->gdone[(t - 2) % QSA_GEV] : nullptr;
+      const int tw = t - QSA_RING_WAIT;
+      hipEvent_t wait = (tw >= QSA_PUSH_LAG) ? c->gdone[tw % QSA_GEV] : nullptr;
       if ((st = tick(c, c->stream, lanes, d, t, wait)) != QSA_OK) return st;
       if (t < QSA_PUSH_LAG) continue;
       hipStream_t bs = c->bstream;

@@ -32,9 +32,13 @@ enum { ERR_BREAKDOWN = 1, ERR_DRIFT = 2 };
 #define QSA_SORT_EVERY 8   // the plasma is counting-sorted by cell every this many slices
 #define QSA_PIPE_LAG 8     // slices between successive beam steps in flight
 #define QSA_PUSH_LAG 3     // a lane pushes beam slab j once it has finished slice j + 3
-// A deposit may land up to 3 slices behind its slab and must still precede
-// the next lane's use of that slice (one slice ahead of its sweep).
-static_assert(QSA_PIPE_LAG % QSA_SORT_EVERY == 0 && QSA_PIPE_LAG > QSA_PUSH_LAG + 4, "pipeline lag");
+// A pushed particle of slab j must sit in cells [j - QSA_DRIFT_BACK,
+// j + QSA_PUSH_LAG): its fields are final up to node slice j + QSA_PUSH_LAG,
+// and its deposit (node slices down to j - QSA_DRIFT_BACK) must precede the
+// next lane's first use of them.  Particles only drift to larger xi, so a
+// particle of slab j never sits behind cell j; the guard flags anything else.
+#define QSA_DRIFT_BACK 1
+static_assert(QSA_PIPE_LAG % QSA_SORT_EVERY == 0 && QSA_PIPE_LAG > QSA_PUSH_LAG + QSA_DRIFT_BACK + 2, "pipeline lag");
 
 // One box's slice loop: geometry, constants and every array the per-slice
 // kernels touch.  The per-slice kernels take an array of lanes and a tick t;
@@ -83,8 +87,20 @@ struct Lane {
 // Fields of the beam push packed per node for aligned vector gathers:
 // (d_x psi, d_y psi, E_z, B_x, B_y, B_z) in 48 bytes (float64) or in 32
 // bytes with two unused (float32), in a ring of QSA_PACK_RING slices (slot
-// j % QSA_PACK_RING).  A pipelined push reads slices up to four back.
+// j % QSA_PACK_RING).  The push of a lane's tick t reads node slices
+// t - lag - QSA_PUSH_LAG - QSA_DRIFT_BACK .. t - lag (up to four back).
 #define QSA_PACK_RING 8
+// The beam work of tick t runs beside the slice loop's next ticks; the final
+// advance of tick t + QSA_RING_WAIT (which packs a slice into the ring) waits
+// for it.  That final advance must come before the ring slot of the lowest
+// slice the push reads is overwritten, and before the next lane first reads
+// the lowest source slice the deposit writes (at tick
+// t + QSA_PIPE_LAG - QSA_PUSH_LAG - QSA_DRIFT_BACK - 1, for the predictor's
+// J_perp one slice ahead).
+#define QSA_RING_WAIT 2
+static_assert(QSA_RING_WAIT >= 1, "the beam work of tick t starts after tick t");
+static_assert(QSA_RING_WAIT <= QSA_PACK_RING - QSA_PUSH_LAG - QSA_DRIFT_BACK, "packed ring overwritten too early");
+static_assert(QSA_RING_WAIT <= QSA_PIPE_LAG - QSA_PUSH_LAG - QSA_DRIFT_BACK - 2, "sources read too early");
 template <typename R>
 __host__ __device__ constexpr int pack_stride() {
   return sizeof(R) == 8 ? 6 : 8;
@@ -1762,8 +1778,8 @@ __global__ void __launch_bounds__(256) k_beam_push(Geo<R> g, BeamArgs<R> a) {
 // drift in xi is slow) deposits with atomics straight from the push.
 //
 // The schedule holds while every particle of slab jp sits in
-// [jp - 3, jp + 3) cells when pushed; a violation sets ERR_DRIFT and the host
-// repeats the group from a copy of the beam.
+// [jp - QSA_DRIFT_BACK, jp + QSA_PUSH_LAG) cells when pushed; a violation
+// sets ERR_DRIFT and the host repeats the group from a copy of the beam.
 // ---------------------------------------------------------------------------
 template <typename R>
 struct PipeBeam {
@@ -1857,10 +1873,10 @@ __device__ __forceinline__ bool pipe_push_one(const PipeBeam<R>& B, int s, int64
   row = -1;
   const double gz = b.xi * B.inv_dxi;
   if (slab) {
-    // fields are final up to slice jp + 3; a deposit must reach the next
-    // lane before it sweeps slice jp - 3
-    if (gz > -1.0 && gz < (double)g.nxi && gz >= (double)(jp + 3)) bad = true;
-    if (feeds && b.w != R(0) && gz < (double)(jp - 3)) bad = true;
+    // fields are final up to node slice jp + QSA_PUSH_LAG; a deposit must
+    // reach the next lane before it first reads node slice jp - QSA_DRIFT_BACK
+    if (gz > -1.0 && gz < (double)g.nxi && gz >= (double)(jp + QSA_PUSH_LAG)) bad = true;
+    if (feeds && b.w != R(0) && gz < (double)(jp - QSA_DRIFT_BACK)) bad = true;
   }
   const R w0 = b.w;
   const BeamNew<R> n = boris_state(g, B.fields, B.fpack, B.qmh[s], B.dt, B.inv_dxi, B.xi_max, b, B.x[s], B.y[s],

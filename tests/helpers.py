@@ -42,17 +42,19 @@ def run_gpu(wl, steps: int = 0, precision=None, beams=None, plasma=None):
     return sim, out
 
 
-def slice_errors(got: dict, ref: dict, j0: int = 0, j1=None):
+def slice_errors(got: dict, ref: dict, j0: int = 0, j1=None, floor: float = 0.0):
     """Per slice and field: ||got - ref||_2 / max_f ||ref_f||_2 over the slice
     (the scale is the largest field of that slice, so that fields that are
-    identically zero in a geometry are judged on an absolute scale).
+    identically zero in a geometry are judged on an absolute scale; it is
+    raised to `floor` where a slice's fields are weaker, so that a slice
+    whose fields sit at rounding level is judged on the box's scale).
     Returns (max error, worst (field, slice))."""
     names = list(ref.keys())
     nxi = ref[names[0]].shape[0]
     j1 = nxi if j1 is None else j1
     worst, where = 0.0, None
     for j in range(j0, j1):
-        scale = max(float(np.linalg.norm(ref[f][j])) for f in names)
+        scale = max(max(float(np.linalg.norm(ref[f][j])) for f in names), floor)
         if scale == 0.0:
             scale = 1.0
         for f in names:
@@ -73,3 +75,15 @@ def psi_floor(wl, precision):
     L = max(wl.nx * wl.dx, wl.ny * wl.dy)
     eps_w = np.finfo(np.float64).eps * max(wl.nx, wl.ny) if precision == "f64" else np.finfo(np.float32).eps
     return eps_w * (L / (2.0 * np.pi)) ** 2 * np.sqrt(6.0)
+
+
+def scale_floor(*refs, frac: float = 1e-3):
+    """frac times the largest per-slice field scale (max_f ||F_f||_2 over a
+    slice) found in the given field dicts: the smallest scale a slice is
+    judged on when the one-ulp rule compares two runs."""
+    s = 0.0
+    for ref in refs:
+        names = list(ref.keys())
+        for j in range(ref[names[0]].shape[0]):
+            s = max(s, max(float(np.linalg.norm(ref[f][j])) for f in names))
+    return frac * s

@@ -81,10 +81,13 @@ def test_adjoint_fp32():
     sim, beams = _sim(wl, precision="f32", steps=2)
     L, g = sim.adjoint_sweep(2, AMPS, [b["bin"] for b in beams])
     Lo, go = _oracle(wl, beams, 2)
-    print(f"[adjoint] fp32 loss rel {abs(L / Lo - 1):.2e}, grad rel {np.abs(g - go).max() / np.abs(go).max():.2e}",
-          flush=True)
-    assert L == pytest.approx(Lo, rel=1e-3)
-    assert np.abs(g - go).max() <= 1e-2 * np.abs(go).max()
+    rel_l2 = float(np.linalg.norm(g - go) / np.linalg.norm(go))
+    print(f"[adjoint] fp32 loss rel {abs(L / Lo - 1):.2e}, grad rel {np.abs(g - go).max() / np.abs(go).max():.2e}, "
+          f"rel L2 {rel_l2:.2e}", flush=True)
+    # measured: gradient 1.6e-7 of its largest bin; bounds about 60x that
+    assert L == pytest.approx(Lo, rel=1e-5)
+    assert np.abs(g - go).max() <= 1e-5 * np.abs(go).max()
+    assert rel_l2 <= 1e-5
 
 
 def test_autograd_function():
@@ -156,8 +159,11 @@ def test_adjoint_full_size_fd_and_fp32():
         sim.load_beam(k, b)
     L32, g32 = sim.adjoint_sweep(steps, amps, bins)
     err = np.abs(g32 - g64).max() / np.abs(g64).max()
-    print(f"[adjoint] float32: loss rel {abs(L32 / L64 - 1):.2e}, gradient {err:.2e} of max", flush=True)
+    rel_l2 = float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))
+    print(f"[adjoint] float32: loss rel {abs(L32 / L64 - 1):.2e}, gradient {err:.2e} of max, "
+          f"rel L2 {rel_l2:.2e}", flush=True)
     assert L32 == pytest.approx(L64, rel=1e-4)
     assert err <= 5e-4
+    assert rel_l2 <= 1e-3      # the float32 gradient bar: relative L2 against float64
     del sim
     torch.cuda.empty_cache()

@@ -333,6 +333,14 @@ def test_linear_response_matches_closed_form():
     assert np.abs(mod - mod_ref).max() < 2e-2 * np.abs(mod_ref).max()
     assert np.abs(psi.mean(1) - psi_ref.mean(1)).max() < 2e-3 * alpha
     assert np.abs(by - by_ref[None, :]).max() < 1e-2 * np.abs(by_ref).max()
+    # E_z = d_xi psi of the same closed form (its k != 0 part comes from
+    # div J_perp, its mean from the transverse-mean leapfrog)
+    ez_ref = alpha * beta * np.sin(xis[j])[:, None] * (1 + eps * np.cos(k * x) / (k * k + 1))[None, :]
+    ez = f[O.EZ, j, 0, :].numpy()
+    emod = ez - ez.mean(axis=1, keepdims=True)
+    emod_ref = ez_ref - ez_ref.mean(axis=1, keepdims=True)
+    assert np.abs(emod - emod_ref).max() < 3e-2 * np.abs(emod_ref).max()
+    assert np.abs(ez.mean(1) - ez_ref.mean(1)).max() < 2e-3 * alpha
 
 
 # ------------------------------------------------ P7 predictor-corrector
