@@ -1,24 +1,31 @@
 #!/usr/bin/env python
 """Throughput of the QSA particle-in-cell hot path on one MI355X.
 
-A step is one beam step of the 3D workload 256 x 256 x 512 (dx = dy = dxi =
-0.05 c/omega_p, warm plasma u_th = 0.01, 2x2 plasma lattice, electron beam
-alpha = 1e-2, gamma_b = 1e3, 8 particles per cell): the beam source deposit,
-the full quasistatic sweep over 512 slices (K = 3 predictor-corrector
-iterations) and the Boris push of all 2.68e8 beam particles.  The metric is
-plasma particle-slice updates per second over whole steps.  Beam steps run
---pipeline at a time in flight (lane k of a group sweeps 8 slices behind lane
-k - 1 in the same launches); the results equal those of one step at a time.
+The headline workload is the dilute pair beam 512 x 512 x 2048 (dx = dy =
+dxi = 0.1 c/omega_p, warm plasma u_th = 1e-3, 2x2 plasma lattice, electron
+and positron beams alpha = 1e-4 each, gamma_b = 1e4, 4 particles per cell
+per species, u_perp ~ N(0, 1), float32): the largest workload one GPU holds.
+A step is one beam step: the beam source deposit of its 4.29e9 particles,
+the quasistatic sweep over 2048 slices (K = 3 predictor-corrector
+iterations) and the Boris push.  The metric is plasma particle-slice
+updates per second over whole steps.  Its workspace (217 GiB) leaves no
+room for beam steps in flight, so steps run one at a time.
 
-Prints one JSON line (rank 0) with the measured rate, a roofline entry for
-the dominant kernel (timed with HIP events on the library's stream inside
-the timed region), the float64 oracle timed on a bounded sample of the
-same workload on the host cores, and the adjoint/forward time of the
-gradient workload (128 x 128 x 256, float32, 20 beam steps, 64 bins).
+The 3D workload 256 x 256 x 512 (float64 and float32, 8 beam steps in
+flight: lane k of a group sweeps 8 slices behind lane k - 1 in the same
+launches) is timed too, as extra entries.
+
+Prints one JSON line with the measured rate, a roofline entry for the
+dominant kernel (timed with HIP events on the library's stream) and the
+whole path's fraction of the HBM roofline, the float64 oracle timed on a
+bounded sample of the same workload on the host cores (and on one core),
+and the adjoint/forward time of the gradient workload (128 x 128 x 256,
+float32, 20 beam steps, 64 bins).
 """
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -30,7 +37,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_push_pred_cube256_f64.json")
+TRAFFIC_FILES = (os.path.join(ROOT, "profiles", "traffic_push_pred_pair512_f32.json"),
+                 os.path.join(ROOT, "profiles", "traffic_push_pred_cube256_f64.json"))
 KERNEL_SOURCES = ("paper_2607_24214_amd/csrc/qsa_kernels.h", "paper_2607_24214_amd/csrc/qsa_device.h")
 
 
@@ -46,15 +54,16 @@ def measured_traffic(workload: str, precision: str, pipeline: int):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE record, if it was taken on the same
     kernel sources and configuration; else None."""
-    try:
-        with open(TRAFFIC_FILE) as fh:
-            rec = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if (rec.get("source_sha256") != kernel_source_hash() or rec.get("workload") != workload
-            or rec.get("precision") != precision or rec.get("steps_in_flight") != pipeline):
-        return None
-    return rec.get("hbm_bytes_per_launch")
+    for f in TRAFFIC_FILES:
+        try:
+            with open(f) as fh:
+                rec = json.load(fh)
+        except (OSError, ValueError):
+            continue
+        if (rec.get("source_sha256") == kernel_source_hash() and rec.get("workload") == workload
+                and rec.get("precision") == precision and rec.get("steps_in_flight") == pipeline):
+            return rec.get("hbm_bytes_per_launch")
+    return None
 
 
 def log(msg):
@@ -91,29 +100,60 @@ def timed_step(sim, kclass: str, n: int):
     return sim.timing_end()
 
 
-def cpu_baseline(wl, n_slices: int):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(wl, n_slices: int):
     """The float64 oracle on the first n_slices slices of one sweep of the
-    same workload (full transverse grid, beam restricted to those slices)."""
-    import torch
+    workload (full transverse grid, beam restricted to those slices);
+    -> (seconds, updates)."""
     import qsa_workloads as W
     from oracle import qsa_pic as O
     sub = wl.with_(nxi=n_slices)
     g = O.Grid.of(sub)
     plasma = O.to_torch(W.plasma_template(sub))
-    beams = [O.to_torch(b) for b in W.beam(sub)]
+    beams = [O.to_torch(b) for b in W.beam(wl, 0, n_slices)]
     t0 = time.perf_counter()
     src = O.beam_sources(g, beams, [s.Z for s in sub.species])
     O.slice_sweep(g, plasma, src, sub.n_corr, sub.kappa2)
-    dt = time.perf_counter() - t0
-    return {
-        "value": sub.n_plasma * n_slices / dt,
+    return time.perf_counter() - t0, sub.n_plasma * n_slices
+
+
+def cpu_baseline(wl, n_slices: int, n_slices_one_core: int):
+    """The oracle timed on the host: on all the threads torch uses, and on
+    one thread (the paper quotes its QS-PIC run on a single core)."""
+    import torch
+    dt, upd = _oracle_sample(wl, n_slices)
+    threads = torch.get_num_threads()
+    out = {
+        "value": upd / dt,
         "unit": "plasma particle-slice updates/s",
-        "cores": torch.get_num_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": (f"first {n_slices} of {wl.nxi} slices of one sweep of {wl.name} "
-                   f"({wl.nx}x{wl.ny} grid, {sub.n_plasma} plasma particles/slice, beam "
+                   f"({wl.nx}x{wl.ny} grid, {wl.n_plasma} plasma particles/slice, beam "
                    f"cells in those slices only), float64, beam sources included; {dt:.1f} s"),
+        "cpu_model": cpu_model(),
+        "nproc": os.cpu_count(),
+        "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
     }
+    if n_slices_one_core > 0:
+        torch.set_num_threads(1)
+        try:
+            d1, u1 = _oracle_sample(wl, n_slices_one_core)
+        finally:
+            torch.set_num_threads(threads)
+        out["one_core"] = {"value": u1 / d1, "cores": 1,
+                           "sample": f"first {n_slices_one_core} slices, the same way; {d1:.1f} s"}
+    return out
 
 
 def adjoint_ratio(steps_in_flight: int):
@@ -237,10 +277,11 @@ def diagnostics_rate(sim, wl, rsize):
     for _ in range(reps):
         sim.beam_moments(0, ws, on_device=True)
     tb = (time.perf_counter() - t) / reps
+    nc = min(wl.nxi, 128)
     t = time.perf_counter()
     for name in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
-        sim.fields(name)
-    th = time.perf_counter() - t
+        sim.fields(name, 0, nc)
+    th = (time.perf_counter() - t) * wl.nxi / nc
     bf = 6 * wl.nxi * wl.nx * wl.ny * rsize
     bb = wl.n_beam_total * (8 + 4 * rsize)
     return {"window_slices": ws,
@@ -248,7 +289,8 @@ def diagnostics_rate(sim, wl, rsize):
             "field_moments_frac_hbm": bf / tf / 1e9 / HBM_PEAK_GBS,
             "beam_moments_ms": 1e3 * tb, "beam_moments_GB_s": bb / tb / 1e9,
             "host_copy_of_the_six_fields_ms": 1e3 * th,
-            "timing": "wall clock per synchronizing call, 5 calls each, after one untimed call"}
+            "timing": ("wall clock per synchronizing call, 5 calls each, after one untimed call; the host "
+                       f"copy of the six fields timed on {nc} slices and scaled to {wl.nxi}")}
 
 
 def linear_model_scan():
@@ -284,24 +326,194 @@ def linear_model_rate():
             "point_steps_per_s": work / tg}
 
 
+def b_alg(wl, rsize: int) -> float:
+    """Algorithmic HBM bytes per plasma particle-slice update of the whole
+    sweep: the particle state (x, y, u_x, u_y) read and written and its
+    weight read once, plus the slice's grid I/O (4 beam source values read,
+    6 field values written per cell) shared by the particles of a cell."""
+    ppc = wl.plasma_ppc
+    grid = (4 + 6) if wl.ny > 1 else (2 + 4)
+    state = (5 + 4) if wl.ny > 1 else (3 + 2)
+    return state * rsize + grid * rsize / ppc
+
+
+def load_beam_in_ranges(sim, wl, slices_per_range: int = 8):
+    """Generate the beam range by range of slices on host threads (numpy
+    releases the GIL while it draws and fills arrays) and hand each range to
+    the library through a device staging buffer (qsa_load_beam_range), so
+    the host never holds the whole beam.  Returns seconds."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    import qsa_workloads as W
+    nthr = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 8))
+    t0 = time.perf_counter()
+    keys = ("x", "y", "xi", "ux", "uy", "uz", "w")
+    for s in range(len(wl.species)):
+        ranges = [(j, min(j + slices_per_range, wl.beam_slices)) for j in range(0, wl.beam_slices, slices_per_range)]
+        first = 0
+        with ThreadPoolExecutor(nthr) as ex:
+            futs = {}
+            nxt = 0
+            for i in range(len(ranges)):
+                while nxt < len(ranges) and nxt < i + 2 * nthr:
+                    futs[nxt] = ex.submit(W.beam_species, wl, s, *ranges[nxt])
+                    nxt += 1
+                b = futs.pop(i).result()
+                dev = {k: torch.from_numpy(b[k]).to("cuda") for k in keys}
+                sim.load_beam_range(s, first, dev)
+                first += int(b["x"].size)
+                del b, dev
+    sim.sync()
+    return time.perf_counter() - t0
+
+
+def run_workload(wl, precision: str, pipeline: int, steps: int, warmup: int, args, with_extras: bool):
+    """Load a workload, warm up, time exactly `steps` beam steps; then the
+    dominant kernel's launches with HIP events, the sweep alone and the
+    diagnostics.  Returns the measurement dict."""
+    import torch
+    import qsa_workloads as W
+    import paper_2607_24214_amd as Q
+    rsize = 8 if precision == "f64" else 4
+    log(f"workload {wl.name}: {wl.nx}x{wl.ny}x{wl.nxi}, plasma {wl.n_plasma}/slice, "
+        f"beam {wl.n_beam_total}, precision {precision}, steps in flight {pipeline}")
+    sim = Q.Sim(Q.params_from_workload(wl, precision=precision, pipeline=pipeline))
+    log(f"workspace {sim.ws_bytes / 2**30:.2f} GiB")
+    t = time.perf_counter()
+    sim.load_plasma(W.plasma_template(wl))
+    if wl.n_beam_total > 1 << 28:
+        tl = load_beam_in_ranges(sim, wl)
+    else:
+        for s, b in enumerate(W.beam(wl)):
+            sim.load_beam(s, b)
+        sim.sync()
+        tl = time.perf_counter() - t
+    log(f"inputs generated and loaded in {tl:.1f} s")
+    if args.no_graphs:
+        sim.set_graphs(False)
+    if args.col_threads:
+        sim.set_shapes(0, 0, args.col_threads)
+    tuned = None
+    if args.autotune:
+        t = time.perf_counter()
+        best = sim.autotune()
+        nt, rt, ct = sim.shapes()
+        tuned = {"plasma_threads": nt, "row_threads": rt, "column_threads": ct, "steps_in_flight": sim.pipeline,
+                 "best_trial_ms_per_step": best}
+        log(f"autotune {time.perf_counter() - t:.1f} s: {tuned}")
+    # warmup (the first step captures the step graph, outside the timed region)
+    t = time.perf_counter()
+    sim.beam_step(max(warmup, 1))
+    sim.sync()
+    log(f"warmup {max(warmup, 1)} steps: {time.perf_counter() - t:.2f} s")
+    if args.pre_steps:
+        t = time.perf_counter()
+        sim.beam_step(args.pre_steps)
+        sim.sync()
+        log(f"{args.pre_steps} further untimed steps: {time.perf_counter() - t:.2f} s")
+    depth = sim.pipeline
+    # timed region: exactly `steps` beam steps between synchronizations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.beam_step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if sim.pipeline != depth:
+        raise RuntimeError(f"pipelining fell back to depth {sim.pipeline}")
+    T = t1 - t0
+    ms_step = 1e3 * T / steps
+    updates = wl.n_plasma * wl.nxi * steps
+    value = updates / T
+    log(f"timed {steps} steps: {T:.3f} s, {ms_step:.2f} ms/step, {value:.3e} updates/s")
+    # the dominant kernel's launch duration: HIP events around each of its
+    # launches over further steps, enqueued launch by launch
+    dominant = "push_pred"
+    n_ev = depth * max(1, min(steps, 16) // depth) if depth > 1 else min(steps, 4)
+    dom_ms, dom_n = timed_step(sim, dominant, n_ev)
+    timing_note = ("HIP events recorded at the start and end of every launch of the kernel "
+                   "(hipExtLaunchKernelGGL on the library's work stream), over "
+                   f"{n_ev} steps enqueued launch by launch right after the timed region")
+    # the sweep alone (the beam push excluded)
+    sim.slice_sweep()
+    sim.sync()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sim.slice_sweep()
+    torch.cuda.synchronize()
+    t_sweep = time.perf_counter() - t
+    diag = None
+    if with_extras and not args.no_diagnostics:
+        diag = diagnostics_rate(sim, wl, rsize)
+        log(f"diagnostics: field moments {diag['field_moments_ms']:.3f} ms "
+            f"({diag['field_moments_GB_s']:.0f} GB/s), beam moments {diag['beam_moments_ms']:.3f} ms")
+    breakdown = {}
+    if args.breakdown and with_extras:
+        for kc in ("push_pred", "push_final", "dep_S", "dep_J", "row_r2c", "col", "row_c2r",
+                   "beam_deposit", "beam_push"):
+            ms, n = timed_step(sim, kc, depth)
+            breakdown[kc] = {"ms_per_step": ms / depth, "launches": n, "us_per_launch": 1e3 * ms / max(n, 1)}
+            log(f"  {kc:13s} {ms / depth:9.2f} ms/step  {n:6d} launches  {1e3 * ms / max(n, 1):8.2f} us/launch")
+    del sim
+    gc.collect()
+    torch.cuda.empty_cache()
+    avg_s = dom_ms / 1e3 / max(dom_n, 1)
+    # one launch advances every step in flight by a slice: algorithmic bytes
+    # per launch = per-slice bytes x lane-slices the launches covered / launches
+    lane_slices = n_ev * wl.nxi * wl.n_corr
+    per_launch = alg_bytes(dominant, wl, rsize) * lane_slices / max(dom_n, 1)
+    achieved = per_launch / avg_s / 1e9
+    ba = b_alg(wl, rsize)
+    path_gbs = value * ba / 1e9
+    roofline = {
+        "kernel": (f"k_plasma_rows<{'double' if rsize == 8 else 'float'}, 2> (predictor: plasma RK2 push "
+                   "+ predicted J_perp deposit)"),
+        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": measured_traffic(wl.name, precision, depth) if not tuned else None,
+        "avg_launch_us": avg_s * 1e6, "launches_timed": dom_n,
+        "timing": timing_note,
+        "alg_bytes_per_launch": per_launch,
+        "slices_per_launch": lane_slices / max(dom_n, 1),
+        "path_alg_bytes_per_update": ba,
+        "path_achieved_GB_s": path_gbs,
+        "path_frac": path_gbs / HBM_PEAK_GBS,
+    }
+    out = {"value": value, "ms_per_step": ms_step, "steps": steps, "warmup": warmup, "dtype": precision,
+           "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nxi": wl.nxi,
+                      "dx": wl.dx, "plasma_per_slice": wl.n_plasma, "beam_particles": wl.n_beam_total,
+                      "species": [{"Z": sp.Z, "alpha": sp.alpha, "ppc": sp.ppc} for sp in wl.species],
+                      "gamma_b": wl.gamma_b, "n_corr": wl.n_corr, "steps_in_flight": depth, "autotuned": tuned,
+                      "step": f"beam source deposit + {wl.nxi}-slice sweep + Boris beam push"},
+           "sweep_only": {"ms": 1e3 * t_sweep, "updates_per_s": wl.n_plasma * wl.nxi / t_sweep},
+           "roofline": roofline, "diagnostics": diag}
+    if breakdown:
+        out["kernel_breakdown_ms_per_step"] = {k: round(v["ms_per_step"], 3) for k, v in breakdown.items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=16)
-    ap.add_argument("--warmup", type=int, default=8)
-    ap.add_argument("--pipeline", type=int, default=8, help="beam steps in flight (1 = one at a time)")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="pair512", choices=sorted(["pair512", "cube256", "slab", "adjoint128"]))
+    ap.add_argument("--precision", default=None, choices=["f64", "f32"],
+                    help="default: the workload's (float32 for pair512, float64 for cube256)")
+    ap.add_argument("--pipeline", type=int, default=None,
+                    help="beam steps in flight (1 = one at a time; default 1 for pair512, 8 otherwise)")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time its launch shapes and steps in flight first")
     ap.add_argument("--pre-steps", type=int, default=0,
                     help="untimed beam steps after the warmup (time a more evolved beam)")
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--col-threads", type=int, default=0,
                     help="threads per column transform (16, 32, 64; 0 = the library's default)")
-    ap.add_argument("--workload", default="cube256")
-    ap.add_argument("--cpu-slices", type=int, default=96)
+    ap.add_argument("--cpu-slices", type=int, default=None,
+                    help="slices of the oracle sample (default: about 15 s of oracle work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the extra entries (the 256^3-class workload in float64 and float32)")
     ap.add_argument("--no-graphs", action="store_true",
-                    help="enqueue every launch instead of replaying HIP graphs (for counter runs)")
+                    help="enqueue every launch instead of replaying HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 2 GiB three times (scale for HBM counters)")
     ap.add_argument("--breakdown", action="store_true",
@@ -335,126 +547,28 @@ def main():
         print(json.dumps({"copy_bytes_read_per_launch": a.numel() * 8, "launches": 3}), flush=True)
         return
     import qsa_workloads as W
-    import paper_2607_24214_amd as Q
 
     if args.scan:
         print(json.dumps(scan_rate(args.scan, args.steps, args.warmup)), flush=True)
         return
     if args.adjoint_only:
-        adj = adjoint_ratio(args.pipeline)
+        adj = adjoint_ratio(args.pipeline or 8)
         print(json.dumps(dict(adj, n_gpus=1, data="synthetic (seeded PCG64 plasma lattice + flat-top beam)")),
               flush=True)
         return
-    wl = W.CONFIGS[args.workload]().with_(precision=args.precision)
-    rsize = 8 if args.precision == "f64" else 4
-    log(f"workload {wl.name}: {wl.nx}x{wl.ny}x{wl.nxi}, plasma {wl.n_plasma}/slice, "
-        f"beam {wl.n_beam_total}, precision {args.precision}")
+    wl = W.CONFIGS[args.workload]()
+    precision = args.precision or wl.precision
+    wl = wl.with_(precision=precision)
+    pipeline = args.pipeline if args.pipeline is not None else (1 if args.workload == "pair512" else 8)
+    head = run_workload(wl, precision, pipeline, args.steps, args.warmup, args, with_extras=True)
 
-    t = time.perf_counter()
-    plasma = W.plasma_template(wl)
-    beams = W.beam(wl)
-    log(f"inputs generated in {time.perf_counter() - t:.1f} s")
-    sim = Q.Sim(Q.params_from_workload(wl, precision=args.precision, pipeline=args.pipeline))
-    sim.load_plasma(plasma)
-    for s, b in enumerate(beams):
-        sim.load_beam(s, b)
-    del beams
-    if args.no_graphs:
-        sim.set_graphs(False)
-    if args.col_threads:
-        sim.set_shapes(0, 0, args.col_threads)
-    tuned = None
-    if args.autotune:
-        t = time.perf_counter()
-        best = sim.autotune()
-        nt, rt, ct = sim.shapes()
-        tuned = {"plasma_threads": nt, "row_threads": rt, "column_threads": ct, "steps_in_flight": sim.pipeline,
-                 "best_trial_ms_per_step": best}
-        log(f"autotune {time.perf_counter() - t:.1f} s: {tuned}")
-    log(f"loaded; workspace {sim.ws_bytes / 2**30:.2f} GiB")
-
-    # warmup
-    t = time.perf_counter()
-    sim.beam_step(args.warmup)
-    sim.sync()
-    log(f"warmup {args.warmup} steps: {time.perf_counter() - t:.2f} s")
-    if args.pre_steps:
-        t = time.perf_counter()
-        sim.beam_step(args.pre_steps)
-        sim.sync()
-        log(f"{args.pre_steps} further untimed steps: {time.perf_counter() - t:.2f} s")
-
-    dominant = "push_pred"
-    # the step graphs (a whole group when pipelined) are captured here,
-    # outside the timed region
-    depth = sim.pipeline
-    sim.beam_step(depth)
-    sim.sync()
-    # timed region: exactly K steps (groups of steps in flight) between synchronizations
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.beam_step(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if sim.pipeline != depth:
-        raise RuntimeError(f"pipelining fell back to depth {sim.pipeline}")
-    # the dominant kernel's launch duration: HIP events around each of its
-    # launches over the same number of steps, enqueued launch by launch
-    dom_ms, dom_n = timed_step(sim, dominant, args.steps)
-    timing_note = ("HIP events recorded at the start and end of every launch of the kernel "
-                   "(hipExtLaunchKernelGGL on the library's work stream), over "
-                   f"{args.steps} steps enqueued launch by launch right after the timed region")
-    T = t1 - t0
-    ms_step = 1e3 * T / args.steps
-    updates = wl.n_plasma * wl.nxi * args.steps
-    value = updates / T
-    log(f"timed {args.steps} steps: {T:.3f} s, {ms_step:.2f} ms/step, {value:.3e} updates/s")
-
-    # sweep alone (the beam push excluded), for the record: graph captured
-    # by the first call, the second is timed
-    sim.slice_sweep()
-    sim.sync()
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    sim.slice_sweep()
-    torch.cuda.synchronize()
-    t_sweep = time.perf_counter() - t
-
-    diag = None
-    if not args.no_diagnostics:
-        diag = diagnostics_rate(sim, wl, rsize)
-        log(f"diagnostics: field moments {diag['field_moments_ms']:.3f} ms "
-            f"({diag['field_moments_GB_s']:.0f} GB/s), beam moments {diag['beam_moments_ms']:.3f} ms, "
-            f"host copy of the fields {diag['host_copy_of_the_six_fields_ms']:.0f} ms")
-
-    # per-class times over further groups of steps (after the timed region,
-    # which they would otherwise move to a later, more evolved beam)
-    breakdown = {}
-    if args.breakdown:
-        for kc in ("push_pred", "push_final", "dep_S", "dep_J", "row_r2c", "col", "row_c2r",
-                   "beam_deposit", "beam_push"):
-            nst = depth
-            ms, n = timed_step(sim, kc, nst)
-            breakdown[kc] = {"ms_per_step": ms / nst, "launches": n, "us_per_launch": 1e3 * ms / max(n, 1)}
-            log(f"  {kc:13s} {ms / nst:9.2f} ms/step  {n:6d} launches  {1e3 * ms / max(n, 1):8.2f} us/launch")
-
-    avg_s = dom_ms / 1e3 / max(dom_n, 1)
-    # one launch advances every step in flight by a slice: algorithmic bytes
-    # per launch = per-slice bytes x lane-slices the launches covered / launches
-    lane_slices = args.steps * wl.nxi * wl.n_corr
-    per_launch = alg_bytes(dominant, wl, rsize) * lane_slices / max(dom_n, 1)
-    achieved = per_launch / avg_s / 1e9
-    roofline = {
-        "kernel": (f"k_plasma_rows<{'double' if rsize == 8 else 'float'}, 2> (predictor: plasma RK2 push "
-                   "+ predicted J_perp deposit)"),
-        "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": achieved / HBM_PEAK_GBS,
-        "traffic": measured_traffic(wl.name, args.precision, depth) if not tuned else None,
-        "avg_launch_us": avg_s * 1e6, "launches_timed": dom_n,
-        "timing": timing_note,
-        "alg_bytes_per_launch": per_launch,
-        "slices_per_launch": lane_slices / max(dom_n, 1),
-    }
+    extra = {}
+    if not args.no_extra and args.workload != "cube256":
+        cube = W.cube256()
+        for prec in ("f64", "f32"):
+            e = run_workload(cube.with_(precision=prec), prec, 8, 16, 4, args, with_extras=False)
+            extra[f"{cube.name}_{prec}"] = {k: e[k] for k in ("value", "ms_per_step", "steps", "warmup", "dtype",
+                                                              "config", "sweep_only", "roofline")}
     linear = None
     if not args.no_linear_model:
         linear = linear_model_rate()
@@ -462,17 +576,24 @@ def main():
             f"{linear['rk4_steps']} RK4 steps in {linear['ms']:.1f} ms")
     adjoint = None
     if not args.no_adjoint:
-        del sim
-        torch.cuda.empty_cache()
         log("adjoint workload ...")
-        adjoint = adjoint_ratio(depth)
+        adjoint = adjoint_ratio(8)
         log(f"adjoint {adjoint['adjoint_ms']:.0f} ms / forward {adjoint['forward_ms']:.0f} ms "
             f"= {adjoint['value']:.2f}")
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"oracle baseline on {args.cpu_slices} slices ...")
-        cpu = cpu_baseline(wl, args.cpu_slices)
-        log(f"oracle: {cpu['value']:.3e} updates/s on {cpu['cores']} threads")
+        # about 15 s of float64 oracle work on the box's threads and about as
+        # much on one (measured on 8 cores: 1.5 us per plasma particle-slice
+        # and 0.42 us per beam particle)
+        import torch
+        nthr = torch.get_num_threads()
+        est8 = 1.5e-6 * wl.n_plasma + 0.42e-6 * wl.n_beam_total / max(wl.beam_slices, 1)
+        n_sl = args.cpu_slices or max(2, min(wl.nxi, int(15.0 / (est8 * 8.0 / nthr))))
+        n_one = max(1, min(wl.nxi, int(15.0 / (est8 * 6.0))))
+        log(f"oracle baseline on {n_sl} slices (and {n_one} on one core) ...")
+        cpu = cpu_baseline(wl, n_sl, n_one)
+        log(f"oracle: {cpu['value']:.3e} updates/s on {cpu['cores']} threads, "
+            f"{cpu['one_core']['value']:.3e} on one ({cpu['cpu_model']}, nproc {cpu['nproc']})")
         if linear is not None:
             # the oracle's solver of the linear model on one instance of the scan
             from oracle import linear_theory as LT
@@ -485,31 +606,28 @@ def main():
 
     out = {
         "metric": "plasma particle-slice updates/s (push+deposit+solve)",
-        "value": value,
+        "value": head["value"],
         "unit": "plasma particle-slice updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": precision,
         "data": "synthetic (seeded PCG64 plasma lattice + flat-top beam)",
-        "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nxi": wl.nxi,
-                   "dx": wl.dx, "plasma_per_slice": wl.n_plasma, "beam_particles": wl.n_beam_total,
-                   "alpha": wl.species[0].alpha, "gamma_b": wl.gamma_b, "n_corr": wl.n_corr,
-                   "steps_in_flight": depth, "autotuned": tuned,
-                   "step": "beam source deposit + 512-slice sweep + Boris beam push"},
-        "sweep_only": {"ms": 1e3 * t_sweep, "updates_per_s": wl.n_plasma * wl.nxi / t_sweep},
-        "roofline": roofline,
+        "config": head["config"],
+        "sweep_only": head["sweep_only"],
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
+        "extra_configs": extra or None,
         "adjoint": adjoint,
-        "diagnostics": diag,
+        "diagnostics": head["diagnostics"],
         "linear_model": linear,
     }
-    if breakdown:
-        out["kernel_breakdown_ms_per_step"] = {k: round(v["ms_per_step"], 3) for k, v in breakdown.items()}
+    if "kernel_breakdown_ms_per_step" in head:
+        out["kernel_breakdown_ms_per_step"] = head["kernel_breakdown_ms_per_step"]
     print(json.dumps(out), flush=True)
 
 

@@ -114,8 +114,11 @@ typedef struct {
   int32_t adjoint_steps; /* 0, or the most beam steps qsa_adjoint_sweep will
                             differentiate (the workspace then holds the beam
                             and the 7 field planes for every step, plasma
-                            checkpoints every 16 slices, and the adjoint
-                            arrays; see qsa_adjoint_sweep)                  */
+                            checkpoints every ckpt_every slices, and the
+                            adjoint arrays; see qsa_adjoint_sweep)          */
+  int32_t ckpt_every;    /* adjoint plasma checkpoint stride in xi slices,
+                            1..nxi (0: 16).  Memory of the checkpoints falls
+                            and of the recomputed segment grows with it.    */
 } qsa_params;
 
 /* Bytes of device workspace a context with these parameters needs; 0 if the
@@ -152,6 +155,20 @@ qsa_status qsa_load_beam(qsa_ctx* c, int32_t s, const double* x,
                          const double* y, const double* xi, const double* ux,
                          const double* uy, const double* uz, const double* w,
                          int64_t n, int32_t on_device);
+
+/* Load a beam of species s in parts, for beams too large to stage at once
+ * (the 512 x 512 x 2048 pair beam holds 2.1e9 particles per species):
+ * particles [first, first + n) of the species, in the layout of
+ * qsa_load_beam.  first = 0 starts a new beam of n particles; first equal
+ * to the species' current count appends n; first + n <= capacity.  The
+ * species then holds first + n particles, in load order.  With pipeline > 1
+ * the sort by cell row is left to the next group of steps in flight (every
+ * group starts with it).  Host arrays synchronize; QSA_E_INVALID for any
+ * other first, QSA_E_NONFINITE for a non-finite host value. */
+qsa_status qsa_load_beam_range(qsa_ctx* c, int32_t s, int64_t first, const double* x,
+                               const double* y, const double* xi, const double* ux,
+                               const double* uy, const double* uz, const double* w,
+                               int64_t n, int32_t on_device);
 
 /* Copy the current particles of species s out as float64 (7 arrays of at
  * least *n entries; cap = their length).  Synchronizing when on_device = 0. */
@@ -280,8 +297,7 @@ enum {
                             256, or 0 for the default (from the particles per
                             row); get: the value in use                     */
   QSA_OPT_ROW_THREADS = 3, /* threads per row-transform block: 64, 128, 256
-                            (a multiple of nx/4), or 0 for
-                            min(256, max(64, nx/2));
+                            (a multiple of nx/8), or 0 for 64;
                             get: the value in use                           */
   QSA_OPT_COL_THREADS = 4 /* threads per column transform: 16, 32 or 64 (a
                             wavefront takes 64 / value adjacent columns), or
@@ -319,7 +335,7 @@ qsa_status qsa_adjoint_sweep(qsa_ctx* c, int32_t n_steps, int32_t n_bins, const 
 /* Autotuner (launch shapes only, nothing the paper defines): times real work
  * on this context's data (direct launches, HIP events) and keeps the fastest
  * threads per plasma-row block (64/128/256), threads per row-transform block
- * (64/128/256, multiples of nx/4), threads per column transform and, with
+ * (64/128/256, multiples of nx/8), threads per column transform and, with
  * pipeline > 1, beam steps in flight (2, 4, ... up to pipeline).  A trial is
  * a group of steps in flight, after which the beam is restored, or (pipeline
  * <= 1) one sweep.  The beam and the device flags are as before the call;

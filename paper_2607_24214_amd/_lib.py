@@ -23,7 +23,7 @@ FIELD_IDS = {"psi": 0, "Ex": 1, "Ey": 2, "Ez": 3, "Bx": 4, "By": 5, "Bz": 6,
 STATUS = {0: "QSA_OK", -1: "QSA_E_INVALID", -2: "QSA_E_NOMEM", -3: "QSA_E_DEVICE",
           -4: "QSA_E_BREAKDOWN", -5: "QSA_E_NONFINITE", -6: "QSA_E_STATE"}
 
-EXPORTS = ("qsa_workspace_bytes", "qsa_create", "qsa_load_plasma", "qsa_load_beam",
+EXPORTS = ("qsa_workspace_bytes", "qsa_create", "qsa_load_plasma", "qsa_load_beam", "qsa_load_beam_range",
            "qsa_read_beam", "qsa_slice_sweep", "qsa_beam_step", "qsa_fields", "qsa_sync",
            "qsa_destroy", "qsa_status_string", "qsa_last_error", "qsa_timing_begin",
            "qsa_timing_end", "qsa_set_option", "qsa_get_option", "qsa_autotune", "qsa_adjoint_sweep",
@@ -48,7 +48,7 @@ class QSAParams(C.Structure):
         ("n_plasma", C.c_int64), ("plasma_w", C.c_double),
         ("species", QSASpecies * QSA_MAX_SPECIES),
         ("beam_capacity", C.c_int64 * QSA_MAX_SPECIES),
-        ("pipeline", C.c_int32), ("adjoint_steps", C.c_int32),
+        ("pipeline", C.c_int32), ("adjoint_steps", C.c_int32), ("ckpt_every", C.c_int32),
     ]
 
 
@@ -76,6 +76,7 @@ def lib():
     L.qsa_create.argtypes = [C.POINTER(QSAParams), vp, C.c_size_t, vp, C.POINTER(vp)]
     L.qsa_load_plasma.argtypes = [vp, vp, vp, vp, vp, i64, i32]
     L.qsa_load_beam.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, i64, i32]
+    L.qsa_load_beam_range.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, i64, i32]
     L.qsa_read_beam.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, i64, C.POINTER(i64), i32]
     L.qsa_slice_sweep.argtypes = [vp]
     L.qsa_beam_step.argtypes = [vp, i32]
@@ -102,7 +103,7 @@ def lib():
     L.qsa_status_string.restype = C.c_char_p
     L.qsa_last_error.argtypes = [vp]
     L.qsa_last_error.restype = C.c_char_p
-    for name in ("qsa_create", "qsa_load_plasma", "qsa_load_beam", "qsa_read_beam",
+    for name in ("qsa_create", "qsa_load_plasma", "qsa_load_beam", "qsa_load_beam_range", "qsa_read_beam",
                  "qsa_slice_sweep", "qsa_beam_step", "qsa_fields", "qsa_sync", "qsa_destroy",
                  "qsa_timing_begin", "qsa_timing_end", "qsa_set_option", "qsa_get_option", "qsa_autotune",
                  "qsa_adjoint_sweep", "qsa_batch_create",

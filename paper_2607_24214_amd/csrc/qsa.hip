@@ -79,7 +79,7 @@ void adjoint_layout(const qsa_params& p, size_t& off, AdjLayout& A) {
   };
   A.steps = p.adjoint_steps;
   if (A.steps <= 0) return;
-  A.ck_len = QSA_ADJ_CKPT;
+  A.ck_len = (p.ckpt_every > 0) ? p.ckpt_every : QSA_ADJ_CKPT;
   A.nseg = (p.nxi + A.ck_len - 1) / A.ck_len;
   for (int s = 0; s < p.n_species; ++s) {
     const size_t cap = (size_t)p.beam_capacity[s];
@@ -123,6 +123,7 @@ struct SetLayout {
   size_t fpack;  // packed fields of the beam push (pipelining)
   size_t hist;   // new-row count matrix of this set's slab pushes, and row starts
   size_t base;
+  size_t cpos[2], cval[6];  // RK2 cache of the slice's plasma particles
 };
 
 // Byte offsets of every device array inside the workspace.
@@ -198,6 +199,8 @@ Layout make_layout(const qsa_params& p) {
     S.hist = (L.nset > 1) ? c.take((size_t)QSA_MAX_SPECIES * p.ny * p.ny * sizeof(int)) : 0;
     S.fpack = (L.nset > 1) ? c.take((size_t)QSA_PACK_RING * nperp * pack_stride_bytes(rs)) : 0;
     S.base = (L.nset > 1) ? c.take((size_t)QSA_MAX_SPECIES * (p.ny + 1) * sizeof(int)) : 0;
+    for (int i = 0; i < 2; ++i) S.cpos[i] = c.take(p.n_plasma * sizeof(double));
+    for (int i = 0; i < 6; ++i) S.cval[i] = c.take(p.n_plasma * rs);
   }
   const size_t nrows = (size_t)p.nxi * p.ny;
   const size_t nkeys = nrows * (p.nx / QSA_BEAM_XCHUNK) + 1;   // sort keys, the last for inert particles
@@ -250,6 +253,7 @@ const char* validate(const qsa_params* p) {
     return "nxi * ny * nx / 8 must be <= 2^30";
   if (p->pipeline < 0 || p->pipeline > QSA_MAX_PIPELINE) return "pipeline must be in [0, 16]";
   if (p->adjoint_steps < 0 || p->adjoint_steps > 1024) return "adjoint_steps must be in [0, 1024]";
+  if (p->ckpt_every < 0 || p->ckpt_every > p->nxi) return "ckpt_every must be in [0, nxi]";
   for (int s = 0; s < p->n_species; ++s) {
     if (p->beam_capacity[s] < 0 || p->beam_capacity[s] > INT32_MAX) return "beam capacity must be in [0, 2^31)";
     if (!(p->species[s].M > 0)) return "species mass must be > 0";
@@ -677,6 +681,8 @@ struct Engine {
     a.bring = c->at<C2<R>>(S.bring);
     a.ode = c->at<double>(S.ode);
     a.fpack = S.fpack ? c->at<R>(S.fpack) : nullptr;
+    for (int i = 0; i < 2; ++i) a.cpos[i] = c->at<double>(S.cpos[i]);
+    for (int i = 0; i < 6; ++i) a.cval[i] = c->at<R>(S.cval[i]);
     return a;
   }
 
@@ -742,8 +748,9 @@ struct Engine {
   }
   static void finish_dims(Dims& d, const qsa_params* const* ps, int n, int nt = 0, int rt = 0, int ct = 0) {
     d.ctpt = (ct == 16 || ct == 32 || ct == 64) ? ct : 0;
-    d.rt_rows = std::min(256, std::max(64, d.nx / 2));   // two row pairs per block from nx = 256
-    if (rt >= d.nx / 4 && rt % (d.nx / 4) == 0 && rt <= 256) d.rt_rows = rt;
+    // one wavefront per block (one row pair at nx = 512, two at 256)
+    d.rt_rows = std::max(64, row_tpt(d.nx));
+    if (rt >= row_tpt(d.nx) && rt % row_tpt(d.nx) == 0 && rt <= 256) d.rt_rows = rt;
     d.nt = std::max(64, std::min(256, (d.per_row + 63) / 64 * 64));
     if (nt == 64 || nt == 128 || nt == 256) d.nt = nt;
     d.rows_r2c = 0;
@@ -754,7 +761,7 @@ struct Engine {
     const int G[3] = {ColShape<COL_PSI>::G, ColShape<COL_J>::G, ColShape<COL_B>::G};
     for (int i = 0; i < n; ++i) {
       const qsa_params& p = *ps[i];
-      const int ppw = d.rt_rows / (p.nx / 4);
+      const int ppw = d.rt_rows / row_tpt(p.nx);
       d.rows_r2c = std::max(d.rows_r2c, ((p.ny + 1) / 2 + ppw - 1) / ppw);
       const int tpt = col_tpt(p.ny, d.ctpt);
       const int cpw = 64 / tpt;
@@ -773,7 +780,8 @@ struct Engine {
                          hipEvent_t before_final = nullptr) {
     const int n = d.n;
     const int pb = (d.np + 255) / 256;
-    const size_t smem_rows = ((size_t)d.nx + 8 * (size_t)d.rt_rows) * sizeof(C2<R>);
+    // twiddles and two rows of nx per row pair, rt_rows / row_tpt(nx) pairs
+    const size_t smem_rows = ((size_t)d.nx + 2 * (size_t)d.nx * (d.rt_rows / row_tpt(d.nx))) * sizeof(C2<R>);
     const int nt = d.nt;
     const int j = t;   // every lag is a multiple of QSA_SORT_EVERY
     {
@@ -790,7 +798,7 @@ struct Engine {
       const dim3 rblock(d.rt_rows);
       // ---- psi stage
       QSA_LAUNCH(tc, QSA_K_DEP_S, (k_plasma_rows<R, PL_DEP_S>), dim3(d.ny, 1, n), dim3(nt),
-                         4 * 1 * (size_t)d.nx * sizeof(double), st, lanes, j);
+                         4 * 1 * (size_t)d.nx * sizeof(double), st, lanes, j, 0);
       QSA_LAUNCH(tc, QSA_K_ROW_R2C, k_row_r2c<R>, rgrid_psi, rblock, smem_rows, st, lanes, j, (int)ST_PSI);
       QSA_LAUNCH(tc, QSA_K_COL, (k_col<R, COL_PSI>), dim3(d.cols[0], 1, n), dim3(64 * ColShape<COL_PSI>::G),
                          d.smem_col[0], st, lanes, j, d.ctpt);
@@ -798,7 +806,7 @@ struct Engine {
                  (int)ST_PSI);
       // ---- J stage
       QSA_LAUNCH(tc, QSA_K_DEP_J, (k_plasma_rows<R, PL_DEP_J>), dim3(d.ny, 1, n), dim3(nt),
-                         4 * 3 * (size_t)d.nx * sizeof(double), st, lanes, j);
+                         4 * 3 * (size_t)d.nx * sizeof(double), st, lanes, j, 0);
       QSA_LAUNCH(tc, QSA_K_ROW_R2C, k_row_r2c<R>, rgrid_j, rblock, smem_rows, st, lanes, j, (int)ST_J);
       QSA_LAUNCH(tc, QSA_K_COL, (k_col<R, COL_J>), dim3(d.cols[1], 1, n), dim3(64 * ColShape<COL_J>::G),
                          d.smem_col[1], st, lanes, j, d.ctpt);
@@ -806,7 +814,7 @@ struct Engine {
       // ---- B_perp predictor-corrector
       for (int k = 0; k < d.n_corr; ++k) {
         QSA_LAUNCH(tc, QSA_K_PUSH_PRED, (k_plasma_rows<R, PL_PRED>), dim3(d.ny, 1, n), dim3(nt),
-                           4 * 2 * (size_t)d.nx * sizeof(double), st, lanes, j);
+                           4 * 2 * (size_t)d.nx * sizeof(double), st, lanes, j, k);
         QSA_LAUNCH(tc, QSA_K_ROW_R2C, k_row_r2c<R>, rgrid_b, rblock, smem_rows, st, lanes, j, (int)ST_B);
         QSA_LAUNCH(tc, QSA_K_COL, (k_col<R, COL_B>), dim3(d.cols[2], 1, n), dim3(64 * ColShape<COL_B>::G),
                            d.smem_col[2], st, lanes, j, d.ctpt);
@@ -820,7 +828,8 @@ struct Engine {
           return fail(tc, QSA_E_DEVICE, std::string("hipStreamWaitEvent: ") + hipGetErrorString(e));
         }
       }
-      QSA_LAUNCH(tc, QSA_K_PUSH_FINAL, k_push_final<R>, dim3(pb, 1, n), dim3(256), 0, st, lanes, j);
+      QSA_LAUNCH(tc, QSA_K_PUSH_FINAL, k_push_final<R>, dim3(pb, 1, n), dim3(256), 0, st, lanes, j,
+                 d.n_corr > 0 ? 1 : 0);
     }
     return QSA_OK;
   }
@@ -1322,38 +1331,48 @@ qsa_status step_group(qsa_ctx* c, int n, bool graphs, bool* done) {
   return QSA_OK;
 }
 
-// Batched sweep (and push): every context's beam deposit on the batch's
-// stream, then one slice loop over all lanes.
+// Batched sweep (and push) of the member contexts ctxs[0 .. n): every
+// context's beam deposit on stream st, then one slice loop over all lanes,
+// whose descriptors are in `lanes` (device memory, one per member, in order).
+// No allocation.
 template <typename R>
-qsa_status batch_run(qsa_batch* b, bool push) {
-  qsa_ctx* c0 = b->ctxs[0];
+qsa_status batch_run(qsa_ctx* const* ctxs, int n, hipStream_t st, const void* lanes, bool push) {
+  qsa_ctx* c0 = ctxs[0];
   typename Engine<R>::Dims d;
-  std::vector<const qsa_params*> ps;
-  for (qsa_ctx* c : b->ctxs) {
-    Engine<R>::add_dims(d, c->p);
-    ps.push_back(&c->p);
+  const qsa_params* ps[1024];
+  if (n > 1024) return fail(c0, QSA_E_INVALID, "a batch holds at most 1024 contexts");
+  for (int i = 0; i < n; ++i) {
+    Engine<R>::add_dims(d, ctxs[i]->p);
+    ps[i] = &ctxs[i]->p;
   }
-  Engine<R>::finish_dims(d, ps.data(), (int)ps.size());
-  for (qsa_ctx* c : b->ctxs) {
+  Engine<R>::finish_dims(d, ps, n);
+  for (int i = 0; i < n; ++i) {
+    qsa_ctx* c = ctxs[i];
     hipStream_t own = c->stream;
-    c->stream = b->stream;
-    const qsa_status st = Engine<R>::beam_deposit_all(c, Engine<R>::geo(c->p));
+    c->stream = st;
+    const qsa_status s = Engine<R>::beam_deposit_all(c, Engine<R>::geo(c->p));
     c->stream = own;
-    if (st != QSA_OK) return st;
+    if (s != QSA_OK) return s;
   }
-  qsa_status st = Engine<R>::slices(c0, b->stream, reinterpret_cast<const Lane<R>*>(b->ws), d);
-  if (st != QSA_OK) return st;
-  for (qsa_ctx* c : b->ctxs) {
+  qsa_status s = Engine<R>::slices(c0, st, reinterpret_cast<const Lane<R>*>(lanes), d);
+  if (s != QSA_OK) return s;
+  for (int i = 0; i < n; ++i) {
+    qsa_ctx* c = ctxs[i];
     c->swept = true;
     c->cur_set = 0;
     if (!push) continue;
     hipStream_t own = c->stream;
-    c->stream = b->stream;
-    st = Engine<R>::push(c);
+    c->stream = st;
+    s = Engine<R>::push(c);
     c->stream = own;
-    if (st != QSA_OK) return st;
+    if (s != QSA_OK) return s;
   }
   return QSA_OK;
+}
+
+template <typename R>
+qsa_status batch_run(qsa_batch* b, bool push) {
+  return batch_run<R>(b->ctxs.data(), (int)b->ctxs.size(), b->stream, b->ws, push);
 }
 
 }  // namespace
@@ -1461,6 +1480,44 @@ qsa_status qsa_load_beam(qsa_ctx* c, int32_t s, const double* x, const double* y
   return leave(c);
 }
 
+qsa_status qsa_load_beam_range(qsa_ctx* c, int32_t s, int64_t first, const double* x, const double* y,
+                               const double* xi, const double* ux, const double* uy, const double* uz,
+                               const double* w, int64_t n, int32_t on_device) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (s < 0 || s >= c->p.n_species) return fail(c, QSA_E_INVALID, "species index out of range");
+  if (first != 0 && first != c->beam_n[s])
+    return fail(c, QSA_E_INVALID, "first must be 0 or the species' current particle count");
+  if (n < 0 || first + n > c->p.beam_capacity[s]) return fail(c, QSA_E_INVALID, "beam count exceeds capacity");
+  const double* arr[7] = {x, y, ux, uy, uz, w, xi};
+  for (int i = 0; i < 7; ++i)
+    if (n > 0 && !arr[i]) return fail(c, QSA_E_INVALID, "null beam array");
+  if (!on_device)
+    for (int i = 0; i < 7; ++i)
+      if (!all_finite(arr[i], n)) return fail(c, QSA_E_NONFINITE, "non-finite beam value");
+  qsa_status st0 = enter(c);
+  if (st0 != QSA_OK) return st0;
+  const size_t rs = (c->p.precision == QSA_FP32) ? 4 : 8;
+  for (int i = 0; i < 7; ++i) {
+    const bool f64 = (i == 6);
+    char* dst = c->ws + c->L.beam[s][i] + (size_t)first * (f64 ? 8 : rs);
+    qsa_status st = dispatch(c, [&] { return Engine<double>::upload(c, arr[i], dst, n, on_device, f64); },
+                             [&] { return Engine<float>::upload(c, arr[i], dst, n, on_device, f64); });
+    if (st != QSA_OK) return st;
+  }
+  c->beam_n[s] = first + n;
+  c->pipe_ok = true;
+  c->drop_graphs();
+  if (c->L.nset > 1 && n > 0) {
+    // load indices of the new particles; the sort by cell row waits for the
+    // next group of steps in flight, which starts with it
+    hipLaunchKernelGGL(k_iota64_from, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                       c->at<int64_t>(c->L.beam[s][7]) + first, first, n);
+    HIP_OK(hipGetLastError());
+  }
+  return leave(c);
+}
+
 qsa_status qsa_read_beam(qsa_ctx* c, int32_t s, double* x, double* y, double* xi, double* ux,
                          double* uy, double* uz, double* w, int64_t cap, int64_t* n,
                          int32_t on_device) {
@@ -1545,9 +1602,9 @@ qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value) {
     return QSA_OK;
   }
   if (option == QSA_OPT_ROW_THREADS) {
-    const int tpt = c->p.nx / 4;
+    const int tpt = row_tpt(c->p.nx);
     if (value != 0 && !((value == 64 || value == 128 || value == 256) && value >= tpt && value % tpt == 0))
-      return fail(c, QSA_E_INVALID, "row threads must be 0 or 64, 128, 256 (a multiple of nx/4)");
+      return fail(c, QSA_E_INVALID, "row threads must be 0 or 64, 128, 256 (a multiple of nx/8)");
     c->tune_rt = (int)value;
     c->drop_graphs();
     return QSA_OK;
@@ -1600,7 +1657,7 @@ qsa_status qsa_autotune(qsa_ctx* c, double* ms_per_step) {
   }
   c->tune_nt = best_nt;
   // threads per row-transform block
-  const int tpt = c->p.nx / 4;
+  const int tpt = row_tpt(c->p.nx);
   int best_rt = c->tune_rt;
   for (int rt = 64; rt <= 256 && st == QSA_OK; rt *= 2) {
     if (rt < tpt || rt % tpt) continue;

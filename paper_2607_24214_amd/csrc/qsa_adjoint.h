@@ -27,7 +27,7 @@
 
 namespace qsa {
 
-#define QSA_ADJ_CKPT 16   // plasma checkpoint stride in slices
+#define QSA_ADJ_CKPT 16   // default plasma checkpoint stride in slices (qsa_params.ckpt_every = 0)
 
 // ---------------------------------------------------------------------------
 // Grid helpers: linear combinations, per-launch side jobs, scalar jobs.

@@ -216,8 +216,8 @@ __device__ __forceinline__ R wrap_pos(R x, R L, R invL) {
 
 // ---------------------------------------------------------------------------
 // Stockham autosort FFT in LDS.  A transform of length n (power of two) is
-// worked by tpt threads (thread t in [0, tpt)); passes are radix 4 with one
-// final radix-2 pass when log2 n is odd.  tw[m] = exp(-2 pi i m/n); INV uses
+// worked by tpt threads (thread t in [0, tpt)); passes are radix 8 with one
+// final radix-4 or radix-2 pass when log2 n is not a multiple of 3.  tw[m] = exp(-2 pi i m/n); INV uses
 // the conjugate twiddles and is unnormalized.  Every pass ends with a
 // workgroup barrier, so all threads of the workgroup must call with the same
 // n (threads without a transform still take part).
@@ -271,22 +271,96 @@ __device__ __forceinline__ void fft_pass2(const C2<R>* in, C2<R>* out, int n, in
   }
 }
 
-// Returns the buffer (a or b) that holds the result.
+// Multiply by the 8th roots of unity W^q, W = exp(-+ 2 pi i/8) (INV: +).
+template <typename R, bool INV>
+__device__ __forceinline__ C2<R> mul_w8(C2<R> o, int q) {
+  const R c = R(0.70710678118654752440084436210484903928);
+  switch (q) {
+    case 1: return INV ? C2<R>{c * (o.x - o.y), c * (o.x + o.y)} : C2<R>{c * (o.x + o.y), c * (o.y - o.x)};
+    case 2: return INV ? C2<R>{-o.y, o.x} : C2<R>{o.y, -o.x};
+    case 3: return INV ? C2<R>{-c * (o.x + o.y), c * (o.x - o.y)} : C2<R>{c * (o.y - o.x), -c * (o.x + o.y)};
+    default: return o;
+  }
+}
+
+// In-register 4-point DFT of (x0, x1, x2, x3) (unnormalized; INV: +i).
+template <typename R, bool INV>
+__device__ __forceinline__ void dft4(C2<R>& x0, C2<R>& x1, C2<R>& x2, C2<R>& x3) {
+  const C2<R> t0 = cadd(x0, x2), t1 = csub(x0, x2), t2 = cadd(x1, x3), d = csub(x1, x3);
+  const C2<R> t3 = INV ? C2<R>{-d.y, d.x} : C2<R>{d.y, -d.x};
+  x0 = cadd(t0, t2);
+  x1 = cadd(t1, t3);
+  x2 = csub(t0, t2);
+  x3 = csub(t1, t3);
+}
+
+// In-register 8-point DFT: the 4-point DFTs of the even and odd samples,
+// combined with the twiddles W^q.
+template <typename R, bool INV>
+__device__ __forceinline__ void dft8(C2<R> (&a)[8]) {
+  C2<R> e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  C2<R> o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+  dft4<R, INV>(e0, e1, e2, e3);
+  dft4<R, INV>(o0, o1, o2, o3);
+  const C2<R> e[4] = {e0, e1, e2, e3};
+  const C2<R> o[4] = {o0, mul_w8<R, INV>(o1, 1), mul_w8<R, INV>(o2, 2), mul_w8<R, INV>(o3, 3)};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    a[q] = cadd(e[q], o[q]);
+    a[q + 4] = csub(e[q], o[q]);
+  }
+}
+
+// Radix-8 Stockham pass: n/8 butterflies, thread t of tpt takes butterflies
+// t, t + tpt, ...; ns = the product of the earlier passes' radices.
+template <typename R, bool INV>
+__device__ __forceinline__ void fft_pass8(const C2<R>* in, C2<R>* out, int n, int ns, int t, int tpt,
+                                          const C2<R>* __restrict__ tw) {
+  const int q = n >> 3;
+  const int stride = n / (8 * ns);
+  for (int jj = t; jj < q; jj += tpt) {
+    const int k = jj & (ns - 1);
+    C2<R> a[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) a[m] = in[jj + m * q];
+    if (ns > 1) {
+#pragma unroll
+      for (int m = 1; m < 8; ++m) {
+        C2<R> w = tw[m * k * stride];
+        if (INV) w = cconj(w);
+        a[m] = cmul(a[m], w);
+      }
+    }
+    dft8<R, INV>(a);
+    const int o = 8 * (jj - k) + k;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) out[o + m * ns] = a[m];
+  }
+}
+
+// Returns the buffer (a or b) that holds the result.  Radix-8 passes while
+// at least three factors of two remain, then one radix-4 or radix-2 pass.
 template <typename R, bool INV>
 __device__ __forceinline__ C2<R>* fft_lds(C2<R>* a, C2<R>* b, int n, int lg, int t, int tpt,
                                           const C2<R>* __restrict__ tw) {
   int ns = 1;
   int s = lg;
-  while (s >= 2) {
+  while (s >= 3) {
+    fft_pass8<R, INV>(a, b, n, ns, t, tpt, tw);
+    __syncthreads();
+    C2<R>* tmp = a;
+    a = b;
+    b = tmp;
+    ns <<= 3;
+    s -= 3;
+  }
+  if (s == 2) {
     fft_pass4<R, INV>(a, b, n, ns, t, tpt, tw);
     __syncthreads();
     C2<R>* tmp = a;
     a = b;
     b = tmp;
-    ns <<= 2;
-    s -= 2;
-  }
-  if (s == 1) {
+  } else if (s == 1) {
     fft_pass2<R, INV>(a, b, n, ns, t, tpt, tw);
     __syncthreads();
     C2<R>* tmp = a;
@@ -296,9 +370,13 @@ __device__ __forceinline__ C2<R>* fft_lds(C2<R>* a, C2<R>* b, int n, int lg, int
   return a;
 }
 
+// Threads per row transform of length n (two real rows packed as one
+// complex row): one radix-8 butterfly each per pass.
+__host__ __device__ __forceinline__ int row_tpt(int n) { return n >= 8 ? n >> 3 : 1; }
+
 // Number of passes fft_lds takes for log2 n = lg (its result sits in the
 // input buffer when this is even).
-__host__ __device__ __forceinline__ int fft_passes(int lg) { return (lg >> 1) + (lg & 1); }
+__host__ __device__ __forceinline__ int fft_passes(int lg) { return lg / 3 + (lg % 3 != 0); }
 
 // In-place variant: the result ends in `a` (one extra LDS copy when the pass
 // count is odd).

@@ -76,12 +76,19 @@ struct Lane {
   R* dep;               // out-of-row plasma deposits [3][nperp]
   C2<R>* rowspec;       // row-pass half spectra [4][ny][nxh]
   C2<R>* colout;        // column-pass outputs [4][ny][nxh]
-  C2<R>* jring;         // J_perp spectra, ring of 2 slices [2][2][ny][nxh]
-  C2<R>* jz;            // J_z spectrum [ny][nxh]
-  C2<R>* bring;         // B_perp spectra, ring of 3 slices [3][2][ny][nxh]
+  C2<R>* jring;         // J_perp spectra, ring of 2 slices [2][2][nxh][ny]
+                        // (this and jz, bring: column-major, [kx][ky], as only the
+                        // column pass touches them)
+  C2<R>* jz;            // J_z spectrum [nxh][ny]
+  C2<R>* bring;         // B_perp spectra, ring of 3 slices [3][2][nxh][ny]
   double* ode;          // [<E_z> at j-1/2, <psi> at j]
   R* fpack;             // the beam push's fields, packed per node (or null):
                         // [QSA_PACK_RING][ny][nx][pack_stride<R>()]
+  double* cpos[2];      // per plasma particle: the RK2 midpoint x, y of the slice
+  R* cval[6];           // and the parts of its RK2 step that B_perp does not
+                        // enter (see rk2_full), written by the first predictor
+                        // pass of a slice, read by the later ones and the final
+                        // advance
 };
 
 // Fields of the beam push packed per node for aligned vector gathers:
@@ -315,7 +322,7 @@ __global__ void __launch_bounds__(256) k_row_r2c(const Lane<R>* __restrict__ lan
   const C2<R>* __restrict__ twx = L.twx;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* sm = reinterpret_cast<C2<R>*>(smem_raw);
-  const int tpt = g.nx >> 2;
+  const int tpt = row_tpt(g.nx);
   const int ppw = blockDim.x / tpt;
   if (bx * ppw >= ((g.ny + 1) >> 1)) return;
   const int slot = threadIdx.x / tpt, t = threadIdx.x - slot * tpt;
@@ -386,7 +393,7 @@ __global__ void __launch_bounds__(256) k_row_c2r(const Lane<R>* __restrict__ lan
   const C2<R>* __restrict__ twx = L.twx;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* sm = reinterpret_cast<C2<R>*>(smem_raw);
-  const int tpt = g.nx >> 2;
+  const int tpt = row_tpt(g.nx);
   const int ppw = blockDim.x / tpt;
   if (bx * ppw >= ((g.ny + 1) >> 1)) return;
   const int slot = threadIdx.x / tpt, t = threadIdx.x - slot * tpt;
@@ -559,7 +566,7 @@ __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, 
 #pragma unroll
     for (int q = 0; q < S::NOUT; ++q) o[q] = C2<R>{0, 0};
     if (valid) {
-      const int e = y * g.nxh + kx;
+      const int e = kx * ny + y;   // the spectral ring state is column-major
       const R kdx = a.kdx[kx], kdy = a.kdy[y];
       const R ksq = a.kx2[kx] + a.ky2[y];
       const bool k0 = (kx == 0 && y == 0);
@@ -647,6 +654,8 @@ struct PlasmaArgs {
   R h;
   const int* prow;    // [ny + 1] first particle of each cell row (state sorted by cell)
   R* ppart;           // partial node rows [ny][4][NC][nx]
+  double* cpos[2];    // RK2 cache of the slice (see rk2_full)
+  R* cval[6];
 };
 
 template <typename R>
@@ -672,6 +681,8 @@ __device__ __forceinline__ PlasmaArgs<R> plasma_args(const Lane<R>& L, int j) {
   a.h = L.h;
   a.prow = L.prow;
   a.ppart = L.ppart;
+  for (int q = 0; q < 2; ++q) a.cpos[q] = L.cpos[q];
+  for (int q = 0; q < 6; ++q) a.cval[q] = L.cval[q];
   return a;
 }
 
@@ -686,47 +697,132 @@ __device__ __forceinline__ void lane_block(int& lane, int& b) {
   b = lg - lane * per;
 }
 
-// d/dxi of (x, y, u_x, u_y) from the six gathered fields
+// RK2 (midpoint) push from slice j with F^j and F^{j+1/2} = (3F^j - F^{j-1})/2
+// (the latter gathered from its grids), F = (psi, d_x psi, d_y psi, B_x, B_y,
+// B_z).  With G = 1 + psi and gamma = (1 + |u_perp|^2 + G^2)/(2G) at the
+// stage position,
+//   dx_perp/dxi = u_perp/G,
+//   du_x/dxi = a_x - B_y,  a_x = gamma d_x psi/G - u_y B_z/G,
+//   du_y/dxi = a_y + B_x,  a_y = gamma d_y psi/G + u_x B_z/G.
+// B_perp enters only through the last terms, and the midpoint position only
+// through u_perp/G: so the stage-1 a_x, a_y, the midpoint (x_s, y_s) and
+// G, d_x psi, d_y psi, B_z at the midpoint are the same in every predictor
+// pass of a slice and in its final advance.  rk2_full gathers all twelve
+// values (and stores those eight when `store`); rk2_cached reloads them and
+// gathers only B_x, B_y at both stages.
+
+// The step from the cached parts and the four B_perp values.
 template <typename R>
-__device__ __forceinline__ void plasma_rhs(const R f[6], R ux, R uy, R d[4], int* err) {
-  const R G = R(1) + f[0];
-  if (!(G > R(QSA_GMIN))) atomicOr(err, ERR_BREAKDOWN);
-  const R iG = R(1) / G;
-  const R gam = (R(1) + ux * ux + uy * uy + G * G) * R(0.5) * iG;
-  d[0] = ux * iG;
-  d[1] = uy * iG;
-  d[2] = gam * f[1] * iG - f[4] - uy * f[5] * iG;
-  d[3] = gam * f[2] * iG + f[3] + ux * f[5] * iG;
+__device__ __forceinline__ void rk2_finish(R hh, double x, double y, R ux, R uy, R ax, R ay, R bx1, R by1,
+                                           R gs, R pxs, R pys, R bzs, R bxh, R byh, double& xn, double& yn,
+                                           R& uxn, R& uyn) {
+  const R uxs = ux + R(0.5) * hh * (ax - by1);
+  const R uys = uy + R(0.5) * hh * (ay + bx1);
+  const R iGs = R(1) / gs;
+  const R gams = (R(1) + uxs * uxs + uys * uys + gs * gs) * R(0.5) * iGs;
+  // positions advance in float64 by increments formed in R
+  xn = x + (double)(hh * (uxs * iGs));
+  yn = y + (double)(hh * (uys * iGs));
+  uxn = ux + hh * ((gams * pxs * iGs - uys * bzs * iGs) - byh);
+  uyn = uy + hh * ((gams * pys * iGs + uxs * bzs * iGs) + bxh);
 }
 
-// RK2 (midpoint) push from slice j with F^j and F^{j+1/2} = (3F^j - F^{j-1})/2
-// (the latter gathered from its grids).
 template <typename R>
-__device__ __forceinline__ void rk2_push(const Geo<R>& g, const PlasmaArgs<R>& a, double x, double y, R ux,
-                                         R uy, double& xn, double& yn, R& uxn, R& uyn) {
+__device__ __forceinline__ void rk2_full(const Geo<R>& g, const PlasmaArgs<R>& a, int p, bool store, double x,
+                                         double y, R ux, R uy, double& xn, double& yn, R& uxn, R& uyn) {
   const R hh = a.h;
-  R f[6], d1[4], d2[4];
+  R ax, ay, bx1, by1;
+  double xs, ys;
   {
     const Stencil<R> s = stencil2(g, x, y);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) f[q] = gather(a.F0[q], s);
-    plasma_rhs(f, ux, uy, d1, a.err);
+    const R G = R(1) + gather(a.F0[0], s);
+    if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
+    const R iG = R(1) / G;
+    const R gam = (R(1) + ux * ux + uy * uy + G * G) * R(0.5) * iG;
+    const R bz = gather(a.F0[5], s);
+    ax = gam * gather(a.F0[1], s) * iG - uy * bz * iG;
+    ay = gam * gather(a.F0[2], s) * iG + ux * bz * iG;
+    bx1 = gather(a.F0[3], s);
+    by1 = gather(a.F0[4], s);
+    xs = x + (double)(R(0.5) * hh * (ux * iG));
+    ys = y + (double)(R(0.5) * hh * (uy * iG));
   }
-  // positions advance in float64 by increments formed in R
-  const double xs = x + (double)(R(0.5) * hh * d1[0]);
-  const double ys = y + (double)(R(0.5) * hh * d1[1]);
-  const R uxs = ux + R(0.5) * hh * d1[2];
-  const R uys = uy + R(0.5) * hh * d1[3];
-  {
-    const Stencil<R> s = stencil2(g, xs, ys);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) f[q] = gather(a.H[q], s);
-    plasma_rhs(f, uxs, uys, d2, a.err);
+  const Stencil<R> s = stencil2(g, xs, ys);
+  const R gs = R(1) + gather(a.H[0], s);
+  if (!(gs > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
+  const R pxs = gather(a.H[1], s), pys = gather(a.H[2], s), bzs = gather(a.H[5], s);
+  const R bxh = gather(a.H[3], s), byh = gather(a.H[4], s);
+  if (store) {
+    a.cpos[0][p] = xs;
+    a.cpos[1][p] = ys;
+    a.cval[0][p] = ax;
+    a.cval[1][p] = ay;
+    a.cval[2][p] = gs;
+    a.cval[3][p] = pxs;
+    a.cval[4][p] = pys;
+    a.cval[5][p] = bzs;
   }
-  xn = x + (double)(hh * d2[0]);
-  yn = y + (double)(hh * d2[1]);
-  uxn = ux + hh * d2[2];
-  uyn = uy + hh * d2[3];
+  rk2_finish(hh, x, y, ux, uy, ax, ay, bx1, by1, gs, pxs, pys, bzs, bxh, byh, xn, yn, uxn, uyn);
+}
+
+template <typename R>
+__device__ __forceinline__ void rk2_cached(const Geo<R>& g, const PlasmaArgs<R>& a, int p, double x, double y,
+                                           R ux, R uy, double& xn, double& yn, R& uxn, R& uyn) {
+  const double xs = a.cpos[0][p], ys = a.cpos[1][p];
+  const R ax = a.cval[0][p], ay = a.cval[1][p], gs = a.cval[2][p];
+  const R pxs = a.cval[3][p], pys = a.cval[4][p], bzs = a.cval[5][p];
+  const Stencil<R> s1 = stencil2(g, x, y);
+  const R bx1 = gather(a.F0[3], s1), by1 = gather(a.F0[4], s1);
+  const Stencil<R> s2 = stencil2(g, xs, ys);
+  const R bxh = gather(a.H[3], s2), byh = gather(a.H[4], s2);
+  rk2_finish(a.h, x, y, ux, uy, ax, ay, bx1, by1, gs, pxs, pys, bzs, bxh, byh, xn, yn, uxn, uyn);
+}
+
+// Value of lane i - N of the wavefront within its row of 16 lanes (DPP
+// row_shr); only read where lane i - N lies in lane i's row.
+template <int N>
+__device__ __forceinline__ int lane_back(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x110 + N, 0xF, 0xF, false);
+}
+template <int N>
+__device__ __forceinline__ float lane_back(float v) {
+  return __int_as_float(lane_back<N>(__float_as_int(v)));
+}
+template <int N>
+__device__ __forceinline__ double lane_back(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_back<N>((int)(b & 0xffffffffll));
+  const int hi = lane_back<N>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Segmented sums over consecutive lanes with equal keys: runs of equal keys
+// are cut at every row of 16 lanes and into segments of at most 4 lanes;
+// the last lane of each segment ends up with the segment's sum of the NV
+// values acc and is the one that returns true (when act).  Every lane of the
+// wavefront calls this together; an inactive lane passes a key no other
+// lane has.
+template <typename R, int NV>
+__device__ __forceinline__ bool wave_segment_sum(int key, bool act, R* acc) {
+  const int lane = threadIdx.x & 63;
+  const int kprev = lane_back<1>(key);
+  const bool head = ((lane & 15) == 0) || kprev != key;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = (lane == 63) ? heads : (heads & ((2ull << lane) - 1ull));
+  const int rs = 63 - __clzll((long long)upto);          // first lane of the run
+  const int ss = rs + ((lane - rs) & ~3);                 // first lane of the segment
+  const bool a1 = lane - 1 >= ss, a2 = lane - 2 >= ss;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    R v = acc[q];
+    const R v1 = lane_back<1>(v);
+    if (a1) v += v1;
+    const R v2 = lane_back<2>(v);
+    if (a2) v += v2;
+    acc[q] = v;
+  }
+  const bool next_head = (lane == 63) || ((heads >> (lane + 1)) & 1ull);
+  return act && (next_head || ((lane + 1 - rs) & 3) == 0);
 }
 
 enum { PL_DEP_S = 0, PL_DEP_J = 1, PL_PRED = 2 };
@@ -773,16 +869,54 @@ __device__ __forceinline__ void row_tile_add(const Geo<R>& g, double* tile, int 
   }
 }
 
-// Plasma deposits owned by cell rows: block r takes the particles of cell
-// row r (state sorted by cell), each thread a contiguous run of them, and
-// adds them to its LDS tile of node rows r-1 .. r+2 with LDS atomics; the
-// tile is written out as partial rows.
+// One plasma particle p of the row kernels: its deposit position and the
+// NC values it deposits there.
 //   PL_DEP_S: rho - J_z at slice j (positions only)
 //   PL_DEP_J: J_x, J_y, J_z at slice j (gathers psi^j for 1 + psi)
 //   PL_PRED : predictor push to j+1 and J~_perp at j+1 with 1 + psi~^{j+1},
-//             psi~^{j+1} = 3 psi^j - 3 psi^{j-1} + psi^{j-2}
+//             psi~^{j+1} = 3 psi^j - 3 psi^{j-1} + psi^{j-2}; predictor pass
+//             `pass` of the slice (the first gathers every field and caches
+//             the parts of the step B_perp does not enter)
 template <typename R, int MODE>
-__global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__ lanes, int tick) {
+__device__ __forceinline__ void plasma_particle(const Geo<R>& g, const PlasmaArgs<R>& a, int p, int pass,
+                                                double& px, double& py, R (&v)[PlasmaNC<MODE>::NC]) {
+  constexpr int NC = PlasmaNC<MODE>::NC;
+  if constexpr (MODE == PL_DEP_S) {
+    px = a.x[p];
+    py = a.y[p];
+    v[0] = a.q;
+  } else if constexpr (MODE == PL_DEP_J) {
+    px = a.x[p];
+    py = a.y[p];
+    const R ux = a.ux[p], uy = a.uy[p];
+    const Stencil<R> s = stencil2(g, px, py);
+    const R G = R(1) + gather(a.F0[0], s);
+    if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
+    const R gam = (R(1) + ux * ux + uy * uy + G * G) / (R(2) * G);
+    const R qg = a.q / G;
+    v[0] = qg * ux;
+    v[1] = qg * uy;
+    v[(NC > 2) ? 2 : 0] = qg * (gam - G);
+  } else {
+    R uxn, uyn;
+    if (pass == 0)
+      rk2_full(g, a, p, true, a.x[p], a.y[p], a.ux[p], a.uy[p], px, py, uxn, uyn);
+    else
+      rk2_cached(g, a, p, a.x[p], a.y[p], a.ux[p], a.uy[p], px, py, uxn, uyn);
+    const Stencil<R> s = stencil2(g, px, py);
+    const R G = R(1) + gather(a.psit, s);
+    if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
+    const R qg = a.q / G;
+    v[0] = qg * uxn;
+    v[(NC > 1) ? 1 : 0] = qg * uyn;
+  }
+}
+
+// Plasma deposits owned by cell rows: block r takes the particles of cell
+// row r (state sorted by cell) and adds them to its LDS tile of node rows
+// r-1 .. r+2 with LDS atomics; the tile is written out as partial rows.
+template <typename R, int MODE>
+__global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__ lanes, int tick, int pass) {
   constexpr int NC = PlasmaNC<MODE>::NC;
   int lane, r;
   lane_block(lane, r);
@@ -808,66 +942,76 @@ __global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__
   }
   __syncthreads();
   const int p0 = a.prow[r], p1 = a.prow[r + 1];
-  const int run = (p1 - p0 + nt - 1) / nt;
-  const int q0 = p0 + tid * run;
-  const int q1 = min(q0 + run, p1);
   R* stray[NC];
   stray[0] = a.dep0;
   if constexpr (NC > 1) stray[1] = a.dep1;
   if constexpr (NC > 2) stray[2] = a.dep2;
-  // consecutive particles of one cell (the state is sorted by cell) add up
-  // in registers; the sum goes to the tile when the cell changes
-  R acc[4][NC];
-  int ci = -1, cl = -1;
-  for (int p = q0; p < q1; ++p) {
-    double px, py;
-    R v[NC];
-    if constexpr (MODE == PL_DEP_S) {
-      px = a.x[p];
-      py = a.y[p];
-      v[0] = a.q;
-    } else if constexpr (MODE == PL_DEP_J) {
-      px = a.x[p];
-      py = a.y[p];
-      const R ux = a.ux[p], uy = a.uy[p];
-      const Stencil<R> s = stencil2(g, px, py);
-      const R G = R(1) + gather(a.F0[0], s);
-      if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
-      const R gam = (R(1) + ux * ux + uy * uy + G * G) / (R(2) * G);
-      const R qg = a.q / G;
-      v[0] = qg * ux;
-      v[1] = qg * uy;
-      v[(NC > 2) ? 2 : 0] = qg * (gam - G);
-    } else {
-      R uxn, uyn;
-      rk2_push(g, a, a.x[p], a.y[p], a.ux[p], a.uy[p], px, py, uxn, uyn);
-      const Stencil<R> s = stencil2(g, px, py);
-      const R G = R(1) + gather(a.psit, s);
-      if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
-      const R qg = a.q / G;
-      v[0] = qg * uxn;
-      v[(NC > 1) ? 1 : 0] = qg * uyn;
-    }
-    int i0, l0;
-    R fx, fy;
-    cell2(g, px, py, i0, l0, fx, fy);
-    if (i0 != ci || l0 != cl) {
-      if (ci >= 0) row_tile_add<R, NC>(g, tile, r, ci, cl, acc, stray);
-      ci = i0;
-      cl = l0;
+  if constexpr (MODE == PL_PRED) {
+    // consecutive lanes take consecutive particles (coalesced loads of the
+    // state and of the slice's RK2 cache); the row keeps its particles in
+    // cell order, so the particles of a cell sit on neighbouring lanes: they
+    // are summed across lanes (segmented sums) before the tile's LDS
+    // atomics.  The trip count is uniform over the block, so every lane
+    // reaches the sums.
+    for (int base = p0; base < p1; base += nt) {
+      const int p = base + tid;
+      const bool act = p < p1;
+      R acc[4][NC];
 #pragma unroll
       for (int n = 0; n < 4; ++n)
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[n][c] = R(0);
+      int i0 = 0, l0 = 0;
+      if (act) {
+        double px, py;
+        R v[NC];
+        plasma_particle<R, MODE>(g, a, p, pass, px, py, v);
+        R fx, fy;
+        cell2(g, px, py, i0, l0, fx, fy);
+        const R ax = R(1) - fx, ay = R(1) - fy;
+        const R w[4] = {ax * ay, fx * ay, ax * fy, fx * fy};
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[n][c] = v[c] * w[n];
+      }
+      const int key = act ? (l0 * g.nx + i0) : -1 - (tid & 63);
+      if (wave_segment_sum<R, 4 * NC>(key, act, &acc[0][0])) row_tile_add<R, NC>(g, tile, r, i0, l0, acc, stray);
     }
-    const R ax = R(1) - fx, ay = R(1) - fy;
-    const R w[4] = {ax * ay, fx * ay, ax * fy, fx * fy};
+  } else {
+    // the deposits: each thread a contiguous run of the row's particles;
+    // consecutive particles of one cell (the state is sorted by cell) add
+    // up in registers and the sum goes to the tile when the cell changes
+    const int run = (p1 - p0 + nt - 1) / nt;
+    const int q0 = p0 + tid * run;
+    const int q1 = min(q0 + run, p1);
+    R acc[4][NC];
+    int ci = -1, cl = -1;
+    for (int p = q0; p < q1; ++p) {
+      double px, py;
+      R v[NC];
+      plasma_particle<R, MODE>(g, a, p, pass, px, py, v);
+      int i0, l0;
+      R fx, fy;
+      cell2(g, px, py, i0, l0, fx, fy);
+      if (i0 != ci || l0 != cl) {
+        if (ci >= 0) row_tile_add<R, NC>(g, tile, r, ci, cl, acc, stray);
+        ci = i0;
+        cl = l0;
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
+        for (int n = 0; n < 4; ++n)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc[n][c] += v[c] * w[n];
+          for (int c = 0; c < NC; ++c) acc[n][c] = R(0);
+      }
+      const R ax = R(1) - fx, ay = R(1) - fy;
+      const R w[4] = {ax * ay, fx * ay, ax * fy, fx * fy};
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[n][c] += v[c] * w[n];
+    }
+    if (ci >= 0) row_tile_add<R, NC>(g, tile, r, ci, cl, acc, stray);
   }
-  if (ci >= 0) row_tile_add<R, NC>(g, tile, r, ci, cl, acc, stray);
   __syncthreads();
   R* out = a.ppart + (size_t)r * tn;
   for (int t = tid; t < tn; t += nt) out[t] = (R)tile[t];
@@ -894,7 +1038,7 @@ __global__ void k_row_offsets(const Lane<R>* __restrict__ lanes, int tick) {
 
 // Final advance: Y^{j+1} with the converged fields, positions wrapped.
 template <typename R>
-__global__ void __launch_bounds__(256) k_push_final(const Lane<R>* __restrict__ lanes, int tick) {
+__global__ void __launch_bounds__(256) k_push_final(const Lane<R>* __restrict__ lanes, int tick, int cached) {
   int lane, b;
   lane_block(lane, b);
   const Lane<R>& L = lanes[lane];
@@ -923,7 +1067,11 @@ __global__ void __launch_bounds__(256) k_push_final(const Lane<R>* __restrict__ 
   const PlasmaArgs<R> a = plasma_args(L, j);
   double xn, yn;
   R uxn, uyn;
-  rk2_push(g, a, a.x[p], a.y[p], a.ux[p], a.uy[p], xn, yn, uxn, uyn);
+  // with predictor passes the slice's RK2 cache holds the B_perp-free parts
+  if (cached)
+    rk2_cached(g, a, p, a.x[p], a.y[p], a.ux[p], a.uy[p], xn, yn, uxn, uyn);
+  else
+    rk2_full(g, a, p, false, a.x[p], a.y[p], a.ux[p], a.uy[p], xn, yn, uxn, uyn);
   a.x[p] = wrap_pos(xn, g.lxd, g.inv_lxd);
   a.y[p] = wrap_pos(yn, g.lyd, g.inv_lyd);
   a.ux[p] = uxn;
@@ -1346,58 +1494,6 @@ __device__ __forceinline__ void tile_add_cell(double* __restrict__ tile, int nx,
   }
 }
 
-// Value of lane i - N of the wavefront within its row of 16 lanes (DPP
-// row_shr); only read where lane i - N lies in lane i's row.
-template <int N>
-__device__ __forceinline__ int lane_back(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x110 + N, 0xF, 0xF, false);
-}
-template <int N>
-__device__ __forceinline__ float lane_back(float v) {
-  return __int_as_float(lane_back<N>(__float_as_int(v)));
-}
-template <int N>
-__device__ __forceinline__ double lane_back(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = lane_back<N>((int)(b & 0xffffffffll));
-  const int hi = lane_back<N>((int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Segmented sums over consecutive lanes with equal keys: runs of equal keys
-// are cut at every row of 16 lanes and into segments of at most 4 lanes;
-// the last lane of each segment ends up with the segment's sum of acc and
-// is the one that returns true (when act).  Every lane of the wavefront calls
-// this together; an inactive lane passes a key no other lane has.
-template <typename R>
-__device__ __forceinline__ bool wave_segment_sum(int key, bool act, R (&acc)[2][2][2][4]) {
-  const int lane = threadIdx.x & 63;
-  const int kprev = lane_back<1>(key);
-  const bool head = ((lane & 15) == 0) || kprev != key;
-  const unsigned long long heads = __ballot(head);
-  const unsigned long long upto = (lane == 63) ? heads : (heads & ((2ull << lane) - 1ull));
-  const int rs = 63 - __clzll((long long)upto);          // first lane of the run
-  const int ss = rs + ((lane - rs) & ~3);                 // first lane of the segment
-  const bool a1 = lane - 1 >= ss, a2 = lane - 2 >= ss;
-#pragma unroll
-  for (int d = 0; d < 2; ++d)
-#pragma unroll
-    for (int e = 0; e < 2; ++e)
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          R v = acc[d][e][x][c];
-          const R v1 = lane_back<1>(v);
-          if (a1) v += v1;
-          const R v2 = lane_back<2>(v);
-          if (a2) v += v2;
-          acc[d][e][x][c] = v;
-        }
-  const bool next_head = (lane == 63) || ((heads >> (lane + 1)) & 1ull);
-  return act && (next_head || ((lane + 1 - rs) & 3) == 0);
-}
-
 // Deposit of a cell row's n particles into the row's tile (src(k, ...) gives
 // the row's k-th particle's cell, offsets and sources; t0 = the cell's slice
 // minus the tile's first, -1 or 0): thread t takes particles 2t and 2t + 1 of
@@ -1461,7 +1557,7 @@ __device__ __forceinline__ void deposit_pairs(double* __restrict__ tile, int nx,
     }
     // the lane's last cell, summed with its neighbours' equal cells
     const int key = (ck >= 0) ? (((ct0 + 1) << 16) | ck) : -1 - (t & 63);
-    if (wave_segment_sum(key, ck >= 0, acc)) tile_add_cell(tile, nx, ct0, ck, acc);
+    if (wave_segment_sum<R, 32>(key, ck >= 0, &acc[0][0][0][0])) tile_add_cell(tile, nx, ct0, ck, acc);
   }
 }
 
@@ -1526,6 +1622,12 @@ __global__ void __launch_bounds__(256) k_beam_sort(BeamMove<R> m) {
 __global__ void __launch_bounds__(256) k_iota64(int64_t* __restrict__ v, int64_t n) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < n) v[p] = p;
+}
+
+// v[i] = first + i, i < n
+__global__ void __launch_bounds__(256) k_iota64_from(int64_t* __restrict__ v, int64_t first, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = first + i;
 }
 
 // Back to load order as float64: dst[id[p]] = src[p].

@@ -32,9 +32,11 @@ def _f64(a):
 def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt: float,
                 species: Sequence, n_plasma: int, plasma_w: float,
                 beam_capacity: Sequence[int], precision: str = "f64", n_corr: int = 3,
-                kappa2: float = 0.75, pipeline: int = 1, adjoint_steps: int = 0) -> L.QSAParams:
+                kappa2: float = 0.75, pipeline: int = 1, adjoint_steps: int = 0,
+                ckpt_every: int = 0) -> L.QSAParams:
     """species: sequence of (Z, M); pipeline: beam steps in flight (1 = off);
-    adjoint_steps: most steps qsa_adjoint_sweep differentiates (0 = none)."""
+    adjoint_steps: most steps qsa_adjoint_sweep differentiates (0 = none);
+    ckpt_every: the adjoint's plasma checkpoint stride in slices (0 = 16)."""
     p = L.QSAParams()
     p.nx, p.ny, p.nxi = nx, ny, nxi
     p.precision = _PREC[precision]
@@ -44,6 +46,7 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
     p.n_species = len(species)
     p.pipeline = int(pipeline)
     p.adjoint_steps = int(adjoint_steps)
+    p.ckpt_every = int(ckpt_every)
     for i, (Z, M) in enumerate(species):
         p.species[i].Z = int(Z)
         p.species[i].M = float(M)
@@ -53,13 +56,15 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
 
 def params_from_workload(wl, precision: Optional[str] = None,
                          beam_capacity: Optional[Sequence[int]] = None,
-                         pipeline: int = 1, adjoint_steps: int = 0) -> L.QSAParams:
+                         pipeline: int = 1, adjoint_steps: int = 0,
+                         ckpt_every: Optional[int] = None) -> L.QSAParams:
     """Parameters of a workload description (duck-typed: grid, species, loading)."""
     caps = beam_capacity or [wl.n_beam(s) for s in range(len(wl.species))]
+    ck = getattr(wl, "ckpt_every", 0) if ckpt_every is None else ckpt_every
     return make_params(wl.nx, wl.ny, wl.nxi, wl.dx, wl.dy, wl.dxi, wl.dt,
                        [(s.Z, s.M) for s in wl.species], wl.n_plasma,
                        wl.dx * wl.dy / wl.plasma_ppc, caps, precision or wl.precision,
-                       wl.n_corr, wl.kappa2, pipeline, adjoint_steps)
+                       wl.n_corr, wl.kappa2, pipeline, adjoint_steps, min(int(ck), wl.nxi))
 
 
 class Sim:
@@ -117,6 +122,15 @@ class Sim:
         on_dev = arrs[0][1]
         self._check(self.lib.qsa_load_beam(self.ctx, s, *[C.c_void_p(_ptr(a)) for a, _ in arrs],
                                            n, on_dev))
+
+    def load_beam_range(self, s: int, first: int, beam: Dict):
+        """Particles [first, first + n) of species s (first = 0 starts a new
+        beam, first = the current count appends)."""
+        arrs = [_f64(beam[k]) for k in ("x", "y", "xi", "ux", "uy", "uz", "w")]
+        n = arrs[0][0].shape[0]
+        on_dev = arrs[0][1]
+        self._check(self.lib.qsa_load_beam_range(self.ctx, s, int(first),
+                                                 *[C.c_void_p(_ptr(a)) for a, _ in arrs], n, on_dev))
 
     def read_beam(self, s: int) -> Dict[str, np.ndarray]:
         cap = int(self.params.beam_capacity[s])

@@ -114,3 +114,15 @@ def test_linear_model_rejects_bad_arguments_without_a_launch():
     back = (C.c_double * 2)(1.0, 0.5)
     assert lib.qsa_linear_model(1, 10, 0.1, 0.1, dummy, 0, dummy, 2, back, dummy, dummy, null) == -1
     assert lib.qsa_linear_model(1, 10, 0.1, 0.1, dummy, 2, dummy, 2, taus, dummy, dummy, null) == -1
+
+
+def test_checkpoint_stride_validated():
+    from paper_2607_24214_amd import _lib as L
+    lib = L.lib()
+    ok = _params(adjoint_steps=2, ckpt_every=8)
+    assert lib.qsa_workspace_bytes(C.byref(ok)) > 0
+    small = lib.qsa_workspace_bytes(C.byref(_params(adjoint_steps=2, ckpt_every=64)))
+    big = lib.qsa_workspace_bytes(C.byref(_params(adjoint_steps=2, ckpt_every=4)))
+    assert big != small       # checkpoint and segment storage follow the stride
+    assert lib.qsa_workspace_bytes(C.byref(_params(adjoint_steps=2, ckpt_every=-1))) == 0
+    assert lib.qsa_workspace_bytes(C.byref(_params(adjoint_steps=2, ckpt_every=129))) == 0

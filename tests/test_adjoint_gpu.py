@@ -58,6 +58,27 @@ def test_adjoint_across_checkpoint_segments_pair_fp64():
     assert np.abs(g - go).max() <= 1e-8 * np.abs(go).max()
 
 
+@pytest.mark.parametrize("ckpt", [1, 7, 40])
+def test_adjoint_checkpoint_stride_is_a_parameter(ckpt):
+    """The plasma checkpoint stride (qsa_params.ckpt_every) only trades
+    memory for recomputation: every slice (1), segments of 7 with a partial
+    last one, and one segment over all 40 slices give the oracle's gradient."""
+    import paper_2607_24214_amd as Q
+    wl = W.small_3d(16, 8, 40).with_(
+        n_bins=6, dt=5.0, ckpt_every=ckpt, species=(W.Species(Z=-1, alpha=0.05, ppc=2, sigma_par=1e-3),))
+    amps = np.linspace(0.8, 1.2, 6)
+    beams = W.beam(wl)
+    sim = Q.Sim(Q.params_from_workload(wl, precision="f64", adjoint_steps=1))
+    assert sim.params.ckpt_every == ckpt
+    sim.load_plasma(W.plasma_template(wl))
+    sim.load_beam(0, beams[0])
+    L, g = sim.adjoint_sweep(1, amps, [beams[0]["bin"]])
+    Lo, go = OA.energy_and_gradient(wl, W.plasma_template(wl), beams, 1, amps)
+    print(f"[adjoint] ckpt_every={ckpt}: grad rel {np.abs(g - go).max() / np.abs(go).max():.2e}", flush=True)
+    assert L == pytest.approx(Lo, rel=1e-10)
+    assert np.abs(g - go).max() <= 1e-8 * np.abs(go).max()
+
+
 def test_adjoint_with_sorted_beam_and_pipelining_fp64():
     """A pipelined context keeps its beam sorted internally; bins are given in
     load order and must follow the particles.  The beam is loaded shuffled."""
