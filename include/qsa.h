@@ -379,6 +379,31 @@ qsa_status qsa_batch_step(qsa_batch* b, int32_t n_steps);
 /* Wait for the batch's work and report any member's pending device error. */
 qsa_status qsa_batch_sync(qsa_batch* b);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one sweep
+ * of every member context (their beam deposits, then their slice loops as
+ * lanes of the same launches), the same work as qsa_batch_sweep, without a
+ * batch object or its workspace.  The lane table (one descriptor per
+ * member) lives in a static device array of the library, QSA_STATIC_MAX_CTX
+ * descriptors (about 50 KB) per device, held until the process ends; the
+ * members' fields, beams and scratch stay in their own workspaces.
+ *   ctxs[n_ctx]: distinct contexts with plasma loaded, one precision and
+ *     n_corr; 1 <= n_ctx <= QSA_STATIC_MAX_CTX (else QSA_E_INVALID with a
+ *     message in qsa_last_error(ctxs[0])).
+ *   hip_stream: the stream every launch is enqueued on (a hipStream_t, null
+ *     for the default stream); nothing synchronizes.  Pass the stream the
+ *     members were created with: each context call orders that stream after
+ *     its own work, so this call then follows the members' earlier calls
+ *     and their later calls follow it.
+ * No device memory is allocated or freed, and no stream, event or graph is
+ * created.  Every call on one device rewrites that device's table, so calls
+ * that overlap on one device (enqueued on different streams) race; calls in
+ * one stream order do not.  Read results with qsa_fields on each member.
+ * Errors: QSA_E_INVALID / QSA_E_STATE for bad arguments (nothing enqueued),
+ * a member's sticky status, QSA_E_DEVICE if a launch fails. */
+#define QSA_STATIC_MAX_CTX 64
+qsa_status qsa_batch_sweep_static(qsa_ctx* const* ctxs, int32_t n_ctx, void* hip_stream);
+
 /* Free the batch (member contexts and workspaces are not touched). */
 qsa_status qsa_batch_destroy(qsa_batch* b);
 

@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqsa.so")
 
 QSA_MAX_SPECIES = 4
+QSA_STATIC_MAX_CTX = 64
 QSA_FP64, QSA_FP32 = 0, 1
 QSA_OK = 0
 
@@ -30,7 +31,8 @@ EXPORTS = ("qsa_workspace_bytes", "qsa_create", "qsa_load_plasma", "qsa_load_bea
            "qsa_field_moments", "qsa_beam_moments", "qsa_linear_model",
            "qsa_batch_workspace_bytes",
            "qsa_batch_create",
-           "qsa_batch_sweep", "qsa_batch_step", "qsa_batch_sync", "qsa_batch_destroy")
+           "qsa_batch_sweep", "qsa_batch_step", "qsa_batch_sync", "qsa_batch_destroy",
+           "qsa_batch_sweep_static")
 
 KERNEL_CLASSES = {"push_pred": 0, "push_final": 1, "dep_S": 2, "dep_J": 3, "row_r2c": 4,
                   "col": 5, "row_c2r": 6, "beam_deposit": 7, "beam_push": 8}
@@ -99,6 +101,7 @@ def lib():
     L.qsa_batch_step.argtypes = [vp, i32]
     L.qsa_batch_sync.argtypes = [vp]
     L.qsa_batch_destroy.argtypes = [vp]
+    L.qsa_batch_sweep_static.argtypes = [C.POINTER(vp), i32, vp]
     L.qsa_status_string.argtypes = [i32]
     L.qsa_status_string.restype = C.c_char_p
     L.qsa_last_error.argtypes = [vp]
@@ -107,7 +110,8 @@ def lib():
                  "qsa_slice_sweep", "qsa_beam_step", "qsa_fields", "qsa_sync", "qsa_destroy",
                  "qsa_timing_begin", "qsa_timing_end", "qsa_set_option", "qsa_get_option", "qsa_autotune",
                  "qsa_adjoint_sweep", "qsa_batch_create",
-                 "qsa_batch_sweep", "qsa_batch_step", "qsa_batch_sync", "qsa_batch_destroy"):
+                 "qsa_batch_sweep", "qsa_batch_step", "qsa_batch_sync", "qsa_batch_destroy",
+                 "qsa_batch_sweep_static"):
         getattr(L, name).restype = i32
     _lib = L
     return L

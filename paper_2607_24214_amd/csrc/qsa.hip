@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1339,7 +1340,7 @@ template <typename R>
 qsa_status batch_run(qsa_ctx* const* ctxs, int n, hipStream_t st, const void* lanes, bool push) {
   qsa_ctx* c0 = ctxs[0];
   typename Engine<R>::Dims d;
-  const qsa_params* ps[1024];
+  const qsa_params* ps[QSA_STATIC_MAX_CTX > 1024 ? QSA_STATIC_MAX_CTX : 1024];
   if (n > 1024) return fail(c0, QSA_E_INVALID, "a batch holds at most 1024 contexts");
   for (int i = 0; i < n; ++i) {
     Engine<R>::add_dims(d, ctxs[i]->p);
@@ -1373,6 +1374,60 @@ qsa_status batch_run(qsa_ctx* const* ctxs, int n, hipStream_t st, const void* la
 template <typename R>
 qsa_status batch_run(qsa_batch* b, bool push) {
   return batch_run<R>(b->ctxs.data(), (int)b->ctxs.size(), b->stream, b->ws, push);
+}
+
+// ---- the sweep of a batch with its lane table in static device memory ----
+// The batch calls keep their lane table (one descriptor per member) in the
+// workspace the caller passes to qsa_batch_create.  qsa_batch_sweep_static
+// keeps it instead in `scratch`, a file-scope device array of
+// QSA_STATIC_MAX_CTX descriptors that every call on a device shares.  Its
+// device address is looked up once per device (hipGetSymbolAddress, with
+// that device current) and kept in g_scratch: host code passes only that
+// address to kernels, never the array's name.
+constexpr size_t kLaneBytes = sizeof(Lane<double>) > sizeof(Lane<float>) ? sizeof(Lane<double>) : sizeof(Lane<float>);
+static __device__ __align__(256) unsigned char scratch[QSA_STATIC_MAX_CTX * kLaneBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call for that device); null with a message on failure.
+void* scratch_on_current_device(std::string& why) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    why = "no current HIP device (or more than 64 devices)";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch[dev] = ptr;
+  }
+  return g_scratch[dev];
+}
+
+// Copy one lane descriptor (passed by value) into the lane table.
+template <typename R>
+__global__ void k_put_lane(Lane<R>* __restrict__ dst, Lane<R> lane) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = lane;
+}
+
+template <typename R>
+qsa_status static_sweep(qsa_ctx* const* ctxs, int n, hipStream_t st, void* table) {
+  qsa_ctx* c = ctxs[0];   // error reporting (HIP_OK)
+  Lane<R>* lanes = reinterpret_cast<Lane<R>*>(table);
+  for (int i = 0; i < n; ++i)
+    hipLaunchKernelGGL(k_put_lane<R>, dim3(1), dim3(64), 0, st, lanes + i, Engine<R>::make_lane(ctxs[i]));
+  HIP_OK(hipGetLastError());
+  return batch_run<R>(ctxs, n, st, table, false);
 }
 
 }  // namespace
@@ -2000,6 +2055,36 @@ qsa_status qsa_batch_sync(qsa_batch* b) {
     if (st != QSA_OK) return st;
   }
   return QSA_OK;
+}
+
+qsa_status qsa_batch_sweep_static(qsa_ctx* const* ctxs, int32_t n_ctx, void* hip_stream) {
+  if (!ctxs || n_ctx < 1) return QSA_E_INVALID;
+  qsa_ctx* c = ctxs[0];
+  for (int i = 0; i < n_ctx; ++i)
+    if (!ctxs[i]) return QSA_E_INVALID;
+  if (n_ctx > QSA_STATIC_MAX_CTX)
+    return fail(c, QSA_E_INVALID,
+                "qsa_batch_sweep_static: " + std::to_string(n_ctx) + " contexts, more than the " +
+                    std::to_string(QSA_STATIC_MAX_CTX) + " its static lane table holds");
+  for (int i = 0; i < n_ctx; ++i) {
+    qsa_ctx* m = ctxs[i];
+    if (m->sticky != QSA_OK) return m->sticky;
+    if (m->p.precision != c->p.precision || m->p.n_corr != c->p.n_corr)
+      return fail(c, QSA_E_INVALID, "qsa_batch_sweep_static: members differ in precision or n_corr");
+    if (!m->plasma_loaded) return fail(c, QSA_E_STATE, "qsa_batch_sweep_static: a member has no plasma loaded");
+    if (m->timing_class >= 0) return fail(c, QSA_E_STATE, "qsa_batch_sweep_static: kernel timing is active");
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == m) return fail(c, QSA_E_INVALID, "qsa_batch_sweep_static: a context appears twice");
+  }
+  std::string why;
+  void* table = scratch_on_current_device(why);
+  if (!table) {
+    c->sticky = QSA_E_DEVICE;
+    return fail(c, QSA_E_DEVICE, "qsa_batch_sweep_static: " + why);
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  return c->p.precision == QSA_FP32 ? static_sweep<float>(ctxs, n_ctx, st, table)
+                                    : static_sweep<double>(ctxs, n_ctx, st, table);
 }
 
 qsa_status qsa_batch_destroy(qsa_batch* b) {

@@ -315,6 +315,21 @@ class Batch:
             pass
 
 
+def batch_sweep_static(sims: Sequence[Sim], stream: Optional[torch.cuda.Stream] = None):
+    """One sweep of every Sim as lanes of the same launches, with the lane
+    table in the library's static device memory (qsa_batch_sweep_static: no
+    batch object, no workspace, nothing allocated).  `stream` defaults to
+    the first Sim's stream."""
+    if not sims:
+        raise ValueError("empty batch")
+    lib = L.lib()
+    st = stream if stream is not None else sims[0].stream
+    arr = (C.c_void_p * len(sims))(*[s.ctx.value for s in sims])
+    status = lib.qsa_batch_sweep_static(arr, len(sims), C.c_void_p(st.cuda_stream))
+    if status != L.QSA_OK:
+        raise L.QSAError(status, lib.qsa_last_error(sims[0].ctx).decode())
+
+
 def linear_model(gamma, n0, dxi: float, taus, dtau: float, device=None):
     """Batched solve of the single-mode linear model, Eq. (5)
     (qsa_linear_model): gamma [n_inst] growth rates, or [n_inst, nxi]

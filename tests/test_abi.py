@@ -116,6 +116,15 @@ def test_linear_model_rejects_bad_arguments_without_a_launch():
     assert lib.qsa_linear_model(1, 10, 0.1, 0.1, dummy, 2, dummy, 2, taus, dummy, dummy, null) == -1
 
 
+def test_static_batch_sweep_rejects_null_and_empty():
+    from paper_2607_24214_amd import _lib as L
+    lib = L.lib()
+    assert lib.qsa_batch_sweep_static(None, 1, None) == -1
+    arr = (C.c_void_p * 1)(None)
+    assert lib.qsa_batch_sweep_static(arr, 0, None) == -1
+    assert lib.qsa_batch_sweep_static(arr, 1, None) == -1
+
+
 def test_checkpoint_stride_validated():
     from paper_2607_24214_amd import _lib as L
     lib = L.lib()
