@@ -225,7 +225,8 @@ def scan_rate(n_inst: int, steps: int, warmup: int):
     t = time.perf_counter()
     sims = []
     for wl in wls:
-        sim = Q.Sim(Q.params_from_workload(wl, precision="f32", pipeline=1))
+        # all 64 instances fit one GPU without the packed push fields
+        sim = Q.Sim(Q.params_from_workload(wl, precision="f32", pipeline=1, field_pack=False))
         sim.load_plasma(W.plasma_template(wl))
         for k, b in enumerate(W.beam(wl)):
             sim.load_beam(k, b)

@@ -119,6 +119,13 @@ typedef struct {
   int32_t ckpt_every;    /* adjoint plasma checkpoint stride in xi slices,
                             1..nxi (0: 16).  Memory of the checkpoints falls
                             and of the recomputed segment grows with it.    */
+  int32_t no_field_pack; /* 0: without steps in flight the workspace keeps
+                            the beam push's six fields packed per node for
+                            every slice (32 bytes per cell in float32, 48
+                            in float64; the push then gathers 16-byte
+                            records); 1: it does not (the push gathers from
+                            the stored planes), for boxes that need the
+                            memory                                          */
 } qsa_params;
 
 /* Bytes of device workspace a context with these parameters needs; 0 if the
@@ -287,7 +294,8 @@ qsa_status qsa_timing_end(qsa_ctx* c, double* total_ms, int64_t* launches);
 enum {
   QSA_OPT_GRAPHS = 0,    /* 1 (default): replay a captured HIP graph of the sweep
                             and of the single beam step; 0: enqueue every
-                            launch (groups of steps in flight always are)  */
+                            launch (groups of steps in flight, and single
+                            steps with QSA_OPT_BEAM_BESIDE, always are)     */
   QSA_OPT_PIPELINE = 1,  /* beam steps in flight in qsa_beam_step: set 1..P
                             (values above the parameter's pipeline = P are
                             clamped to P; setting also re-enables pipelining
@@ -297,12 +305,21 @@ enum {
                             256, or 0 for the default (from the particles per
                             row); get: the value in use                     */
   QSA_OPT_ROW_THREADS = 3, /* threads per row-transform block: 64, 128, 256
-                            (a multiple of nx/8), or 0 for 64;
+                            (a multiple of nx/4), or 0 for
+                            min(256, max(64, nx/2));
                             get: the value in use                           */
-  QSA_OPT_COL_THREADS = 4 /* threads per column transform: 16, 32 or 64 (a
+  QSA_OPT_COL_THREADS = 4, /* threads per column transform: 16, 32 or 64 (a
                             wavefront takes 64 / value adjacent columns), or
                             0 for 64; at most ny/4 are used; get: the value
                             in use                                          */
+  QSA_OPT_BEAM_BESIDE = 5 /* contexts without steps in flight (pipeline = 1):
+                            1 runs a beam step's source deposit and
+                            push on a second stream beside the slice loop, a
+                            few slabs at a time (the deposit ahead of the
+                            slice that needs it, the push once the fields it
+                            gathers are final); 0 (default): deposit, sweep,
+                            push one after the other.  The results agree up to the
+                            order of the deposit's additions.              */
 };
 
 /* Set a context option (see QSA_OPT_*). */
@@ -335,7 +352,7 @@ qsa_status qsa_adjoint_sweep(qsa_ctx* c, int32_t n_steps, int32_t n_bins, const 
 /* Autotuner (launch shapes only, nothing the paper defines): times real work
  * on this context's data (direct launches, HIP events) and keeps the fastest
  * threads per plasma-row block (64/128/256), threads per row-transform block
- * (64/128/256, multiples of nx/8), threads per column transform and, with
+ * (64/128/256, multiples of nx/4), threads per column transform and, with
  * pipeline > 1, beam steps in flight (2, 4, ... up to pipeline).  A trial is
  * a group of steps in flight, after which the beam is restored, or (pipeline
  * <= 1) one sweep.  The beam and the device flags are as before the call;

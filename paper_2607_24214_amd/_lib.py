@@ -51,6 +51,7 @@ class QSAParams(C.Structure):
         ("species", QSASpecies * QSA_MAX_SPECIES),
         ("beam_capacity", C.c_int64 * QSA_MAX_SPECIES),
         ("pipeline", C.c_int32), ("adjoint_steps", C.c_int32), ("ckpt_every", C.c_int32),
+        ("no_field_pack", C.c_int32),
     ]
 
 

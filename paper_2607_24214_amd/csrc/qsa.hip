@@ -121,7 +121,8 @@ struct SetLayout {
   size_t cell_of, count, bsum, prow, ppart;
   size_t src, fields, half, dep, rowspec, colout, jring, jz, bring, ode;
   size_t ring;   // slab ring of the deposits this set receives from the lane before it
-  size_t fpack;  // packed fields of the beam push (pipelining)
+  size_t fpack;  // packed fields of the beam push
+  int pack_ring;  // slices fpack holds
   size_t hist;   // new-row count matrix of this set's slab pushes, and row starts
   size_t base;
   size_t cpos[2], cval[6];  // RK2 cache of the slice's plasma particles
@@ -136,7 +137,7 @@ struct Layout {
   size_t rowoff[QSA_MAX_SPECIES];   // slab partition of the sorted beam (pipelining)
   size_t doff[QSA_MAX_SPECIES];     // sort-key offsets into perm of the current deposit
   size_t key[QSA_MAX_SPECIES], perm[QSA_MAX_SPECIES];
-  size_t cursor, scan64, bpart;
+  size_t cursor, scan64;
   size_t beam[QSA_MAX_SPECIES][8];  // x, y, ux, uy, uz, w (real), xi (double), id (int64, pipelining)
   size_t snap[QSA_MAX_SPECIES][8];  // sort target and the beam at the start of a pipelined group
   size_t err, emit, lane, pipe;
@@ -198,7 +199,10 @@ Layout make_layout(const qsa_params& p) {
     // two slabs x ny cell rows x (2 node slices x 2 node rows x 4 sources x nx)
     S.ring = (k > 0) ? c.take(2 * (size_t)p.ny * 2 * 2 * 4 * p.nx * rs) : 0;
     S.hist = (L.nset > 1) ? c.take((size_t)QSA_MAX_SPECIES * p.ny * p.ny * sizeof(int)) : 0;
-    S.fpack = (L.nset > 1) ? c.take((size_t)QSA_PACK_RING * nperp * pack_stride_bytes(rs)) : 0;
+    // packed push fields: a ring of slices with steps in flight, every slice
+    // without (the beam push then reads them after the sweep)
+    S.pack_ring = (L.nset > 1) ? QSA_PACK_RING : (p.no_field_pack ? 0 : p.nxi);
+    S.fpack = S.pack_ring ? c.take((size_t)S.pack_ring * nperp * pack_stride_bytes(rs)) : 0;
     S.base = (L.nset > 1) ? c.take((size_t)QSA_MAX_SPECIES * (p.ny + 1) * sizeof(int)) : 0;
     for (int i = 0; i < 2; ++i) S.cpos[i] = c.take(p.n_plasma * sizeof(double));
     for (int i = 0; i < 6; ++i) S.cval[i] = c.take(p.n_plasma * rs);
@@ -209,12 +213,11 @@ Layout make_layout(const qsa_params& p) {
     const size_t cap = (s < p.n_species) ? (size_t)p.beam_capacity[s] : 0;
     L.rowoff[s] = c.take((nrows + 2) * sizeof(int64_t));
     L.doff[s] = c.take((nkeys + 2) * sizeof(int64_t));
-    L.key[s] = c.take(cap * sizeof(int));
+    L.key[s] = (L.nset > 1) ? c.take(cap * sizeof(int)) : 0;   // kept only for steps in flight
     L.perm[s] = c.take(cap * sizeof(int));
   }
   L.cursor = c.take((nkeys + 2) * sizeof(int64_t));
   L.scan64 = c.take(((nkeys + 2) / 1024 + 64) * 2 * sizeof(int64_t));
-  L.bpart = c.take(nrows * 2 * 2 * 4 * (size_t)p.nx * rs);
   for (int s = 0; s < QSA_MAX_SPECIES; ++s) {
     const size_t cap = (s < p.n_species) ? (size_t)p.beam_capacity[s] : 0;
     for (int k = 0; k < 6; ++k) L.beam[s][k] = c.take(cap * rs);
@@ -255,6 +258,7 @@ const char* validate(const qsa_params* p) {
   if (p->pipeline < 0 || p->pipeline > QSA_MAX_PIPELINE) return "pipeline must be in [0, 16]";
   if (p->adjoint_steps < 0 || p->adjoint_steps > 1024) return "adjoint_steps must be in [0, 1024]";
   if (p->ckpt_every < 0 || p->ckpt_every > p->nxi) return "ckpt_every must be in [0, nxi]";
+  if (p->no_field_pack != 0 && p->no_field_pack != 1) return "no_field_pack must be 0 or 1";
   for (int s = 0; s < p->n_species; ++s) {
     if (p->beam_capacity[s] < 0 || p->beam_capacity[s] > INT32_MAX) return "beam capacity must be in [0, 2^31)";
     if (!(p->species[s].M > 0)) return "species mass must be > 0";
@@ -265,6 +269,9 @@ const char* validate(const qsa_params* p) {
 }  // namespace
 
 #define QSA_GEV 4   // events per ring between the slice loop and the beam stream
+#define QSA_BEAM_CHUNK 8    // slabs per beam deposit and push beside the slice loop
+#define QSA_BEAM_AHEAD 2    // chunks deposited ahead of the slice loop
+#define QSA_PUSH_BLOCKS 2048   // grid of a key-range push
 
 struct qsa_ctx {
   qsa_params p;
@@ -277,6 +284,7 @@ struct qsa_ctx {
   hipEvent_t gfork[QSA_GEV] = {}, gdone[QSA_GEV] = {};   // slice loop -> beam work -> slice loop
   hipGraphExec_t gx_step = nullptr, gx_sweep = nullptr;   // captured beam step / sweep
   bool use_graphs = true;
+  bool beam_beside = false;   // one step at a time: the beam work beside the slice loop
   bool pipe_ok = true;   // off after a drift violation, until the next beam load
   int pipe_max = 1;      // beam steps in flight when pipelining (<= L.nset)
   int tune_nt = 0;       // threads per plasma-row block (0: from the particles per row)
@@ -494,12 +502,11 @@ struct Engine {
       a.uz[s] = c->at<R>(c->L.beam[s][4]);
       a.w[s] = c->at<R>(c->L.beam[s][5]);
       a.xi[s] = c->at<double>(c->L.beam[s][6]);
-      a.key[s] = c->at<int>(c->L.key[s]);
+      a.key[s] = c->L.key[s] ? c->at<int>(c->L.key[s]) : nullptr;
       a.perm[s] = c->at<int>(c->L.perm[s]);
       a.doff[s] = c->at<int64_t>(c->L.doff[s]);
       a.zq[s] = (R)(p.species[s].Z / (p.dx * p.dy * p.dxi));
     }
-    a.bpart = c->at<R>(c->L.bpart);
     a.inv_dxi = 1.0 / p.dxi;
     return a;
   }
@@ -593,27 +600,42 @@ struct Engine {
     return QSA_OK;
   }
 
-  // Beam sources: particles grouped by cell row, each row deposited by one
-  // block into its partial node rows, then reduced to dense sources.
-  static qsa_status beam_deposit_all(qsa_ctx* c, const Geo<R>& g) {
+  // Beam sources: particles grouped by cell row (keys, their offsets and a
+  // permutation), each row deposited by one block into the dense sources
+  // (four launches by the parity of the row, see k_beam_rows).
+  static qsa_status beam_perm_all(qsa_ctx* c, const Geo<R>& g) {
     const qsa_params& p = c->p;
     for (int s = 0; s < p.n_species; ++s) {
       qsa_status st = keys(c, s);
       if (st != QSA_OK) return st;
       const int64_t n = c->beam_n[s];
       if (n > 0)
-        hipLaunchKernelGGL(k_beam_perm<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL(k_beam_perm<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
                            beam_dep_args(c), s, n, c->at<int64_t>(c->L.cursor));
     }
-    const BeamDepArgs<R> a = beam_dep_args(c);
-    const int nrows = p.nxi * p.ny;
-    QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_beam_rows<R>, dim3(nrows), dim3(256),
-               2 * 2 * 4 * g.nx * sizeof(double), c->stream, g, a);
-    const int64_t plane = (int64_t)p.nxi * g.nperp;
-    hipLaunchKernelGGL(k_beam_reduce<R>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, c->stream, g,
-                       (const R*)a.bpart, c->at<R>(c->L.set[0].src));
     HIP_OK(hipGetLastError());
     return QSA_OK;
+  }
+
+  // Deposit the slabs [jlo, jhi) into src (on stream st).
+  static qsa_status deposit_slabs(qsa_ctx* c, const Geo<R>& g, hipStream_t st, R* src, int jlo, int jhi) {
+    const BeamDepArgs<R> a = beam_dep_args(c);
+    for (int colour = 0; colour < 4; ++colour) {
+      const int nb = beam_colour_rows(jlo, jhi, c->p.ny, colour);
+      if (nb > 0)
+        QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_beam_rows<R>, dim3(nb), dim3(256), 2 * 2 * 4 * g.nx * sizeof(double),
+                   st, g, a, src, colour, jlo, jhi);
+    }
+    HIP_OK(hipGetLastError());
+    return QSA_OK;
+  }
+
+  static qsa_status beam_deposit_all(qsa_ctx* c, const Geo<R>& g) {
+    qsa_status st = beam_perm_all(c, g);
+    if (st != QSA_OK) return st;
+    R* src = c->at<R>(c->L.set[0].src);
+    if ((st = fill(c, src, 4 * (int64_t)c->p.nxi * g.nperp, R(0))) != QSA_OK) return st;
+    return deposit_slabs(c, g, c->stream, src, 0, c->p.nxi);
   }
 
   static BeamArgs<R> beam_args(qsa_ctx* c, const Geo<R>& g, int s) {
@@ -628,6 +650,11 @@ struct Engine {
     a.xi = c->at<double>(c->L.beam[s][6]);
     a.n = c->beam_n[s];
     a.fields = c->at<R>(c->L.set[0].fields);
+    // every slice's packed fields (contexts without steps in flight), else
+    // gathers from the stored planes
+    const SetLayout& S0 = c->L.set[0];
+    a.fpack = (S0.fpack && S0.pack_ring >= p.nxi) ? c->at<R>(S0.fpack) : nullptr;
+    a.ring = S0.pack_ring;
     a.zq = (R)(p.species[s].Z / (p.dx * p.dy * p.dxi));
     a.qmh = (R)((double)p.species[s].Z / p.species[s].M * 0.5 * p.dt);
     a.dt = (R)p.dt;
@@ -682,6 +709,7 @@ struct Engine {
     a.bring = c->at<C2<R>>(S.bring);
     a.ode = c->at<double>(S.ode);
     a.fpack = S.fpack ? c->at<R>(S.fpack) : nullptr;
+    a.pack_ring = S.pack_ring;
     for (int i = 0; i < 2; ++i) a.cpos[i] = c->at<double>(S.cpos[i]);
     for (int i = 0; i < 6; ++i) a.cval[i] = c->at<R>(S.cval[i]);
     return a;
@@ -705,7 +733,7 @@ struct Engine {
       a.w[s] = c->at<R>(L.beam[s][5]);
       a.xi[s] = c->at<double>(L.beam[s][6]);
       a.rowoff[s] = c->at<int64_t>(L.rowoff[s]);
-      a.tag[s] = c->at<int>(L.key[s]);
+      a.tag[s] = L.key[s] ? c->at<int>(L.key[s]) : nullptr;
       a.perm[s] = c->at<int>(L.perm[s]);
       a.qmh[s] = (R)((double)p.species[s].Z / p.species[s].M * 0.5 * p.dt);
       a.zq[s] = (R)(p.species[s].Z / (p.dx * p.dy * p.dxi));
@@ -733,6 +761,7 @@ struct Engine {
     int ctpt = 0;                     // threads per column transform (0: default)
     int cols[3] = {0, 0, 0};          // column-pass grid per mode
     size_t smem_col[3] = {0, 0, 0};
+    size_t smem_rows = 0;             // row-pass LDS
     int64_t clear = 0;
   };
   static void add_dims(Dims& d, const qsa_params& p) {
@@ -749,12 +778,12 @@ struct Engine {
   }
   static void finish_dims(Dims& d, const qsa_params* const* ps, int n, int nt = 0, int rt = 0, int ct = 0) {
     d.ctpt = (ct == 16 || ct == 32 || ct == 64) ? ct : 0;
-    // one wavefront per block (one row pair at nx = 512, two at 256)
-    d.rt_rows = std::max(64, row_tpt(d.nx));
+    d.rt_rows = std::min(256, std::max(64, d.nx / 2));   // two row pairs per block from nx = 256
     if (rt >= row_tpt(d.nx) && rt % row_tpt(d.nx) == 0 && rt <= 256) d.rt_rows = rt;
     d.nt = std::max(64, std::min(256, (d.per_row + 63) / 64 * 64));
     if (nt == 64 || nt == 128 || nt == 256) d.nt = nt;
     d.rows_r2c = 0;
+    d.smem_rows = 0;
     for (int m = 0; m < 3; ++m) {
       d.cols[m] = 0;
       d.smem_col[m] = 0;
@@ -764,11 +793,14 @@ struct Engine {
       const qsa_params& p = *ps[i];
       const int ppw = d.rt_rows / row_tpt(p.nx);
       d.rows_r2c = std::max(d.rows_r2c, ((p.ny + 1) / 2 + ppw - 1) / ppw);
+      // twiddles and two FFT buffers per row pair, ppw pairs per block
+      d.smem_rows = std::max(d.smem_rows, ((size_t)p.nx + 2 * (size_t)fft_cap(p.nx) * ppw) * sizeof(C2<R>));
       const int tpt = col_tpt(p.ny, d.ctpt);
       const int cpw = 64 / tpt;
       for (int m = 0; m < 3; ++m) {
         d.cols[m] = std::max(d.cols[m], (p.nx / 2 + 1 + cpw - 1) / cpw);
-        d.smem_col[m] = std::max(d.smem_col[m], ((size_t)cpw * 2 * G[m] + 1) * p.ny * sizeof(C2<R>));
+        d.smem_col[m] = std::max(d.smem_col[m],
+                                 ((size_t)p.ny + (size_t)cpw * 2 * G[m] * fft_cap(p.ny)) * sizeof(C2<R>));
       }
     }
   }
@@ -781,8 +813,7 @@ struct Engine {
                          hipEvent_t before_final = nullptr) {
     const int n = d.n;
     const int pb = (d.np + 255) / 256;
-    // twiddles and two rows of nx per row pair, rt_rows / row_tpt(nx) pairs
-    const size_t smem_rows = ((size_t)d.nx + 2 * (size_t)d.nx * (d.rt_rows / row_tpt(d.nx))) * sizeof(C2<R>);
+    const size_t smem_rows = d.smem_rows;
     const int nt = d.nt;
     const int j = t;   // every lag is a multiple of QSA_SORT_EVERY
     {
@@ -863,6 +894,100 @@ struct Engine {
     qsa_status st = beam_deposit_all(c, g);
     if (st != QSA_OK) return st;
     if ((st = slices(c, c->stream, c->at<Lane<R>>(c->L.lane), dims_of(c))) != QSA_OK) return st;
+    HIP_OK(hipGetLastError());
+    c->swept = true;
+    return QSA_OK;
+  }
+
+  // Push the particles of every species whose deposit keys lie in [k0, k1)
+  // (on stream st).
+  static qsa_status push_keys(qsa_ctx* c, const Geo<R>& g, hipStream_t st, int64_t k0, int64_t k1) {
+    const BeamDepArgs<R> da = beam_dep_args(c);
+    for (int s = 0; s < c->p.n_species; ++s) {
+      if (c->beam_n[s] == 0) continue;
+      const BeamArgs<R> a = beam_args(c, g, s);
+      const int blocks = (int)std::min<int64_t>(QSA_PUSH_BLOCKS, (a.n + 255) / 256);
+      QSA_LAUNCH(c, QSA_K_BEAM_PUSH, k_beam_push_keys<R>, dim3(blocks), dim3(256), 0, st, g, a,
+                 (const int*)da.perm[s], da.doff[s], k0, k1);
+    }
+    HIP_OK(hipGetLastError());
+    return QSA_OK;
+  }
+
+  // One beam step with the beam work beside the slice loop (one step in
+  // flight).  The keys and permutation of the step's start order the beam
+  // by slab; a second stream deposits the sources QSA_BEAM_CHUNK slabs at a
+  // time, QSA_BEAM_AHEAD chunks ahead of the slice loop (tick j waits for
+  // the chunk holding slab j, whose deposit completes node slice j), and
+  // pushes each chunk once the slice loop has finished the slice after its
+  // last slab (a slab-j particle gathers slices j and j + 1; the fields of
+  // every slice are stored, so no later tick overwrites what it reads).  The
+  // particles of a chunk are those its keys held at the step's start, so no
+  // drift can take one out of the slices its push waits for.  Equal to
+  // sweep() + push() up to the order of the deposit's additions.
+  static qsa_status step_beside(qsa_ctx* c) {
+    const qsa_status st = step_beside_body(c);
+    if (st != QSA_OK) {
+      // an early exit: no later call may overlap the beam work enqueued
+      (void)hipStreamSynchronize(c->bstream);
+      if (c->sticky == QSA_OK) c->sticky = st;
+    }
+    return st;
+  }
+
+  static qsa_status step_beside_body(qsa_ctx* c) {
+    const qsa_params& p = c->p;
+    const Geo<R> g = geo(p);
+    static_assert(QSA_BEAM_AHEAD >= 2, "a chunk's deposit waits for the push of the chunk AHEAD before it");
+    static_assert(QSA_BEAM_AHEAD + 1 < QSA_GEV, "event ring too short");
+    qsa_status st = beam_perm_all(c, g);
+    if (st != QSA_OK) return st;
+    R* src = c->at<R>(c->L.set[0].src);
+    if ((st = fill(c, src, 4 * (int64_t)p.nxi * g.nperp, R(0))) != QSA_OK) return st;
+    const Lane<R>* lanes = c->at<Lane<R>>(c->L.lane);
+    const Dims d = dims_of(c);
+    const int C = QSA_BEAM_CHUNK, nch = (p.nxi + C - 1) / C;
+    const int64_t keys_per_slab = (int64_t)p.ny * (p.nx / QSA_BEAM_XCHUNK);
+    const int64_t key_end = (int64_t)p.nxi * keys_per_slab + 1;   // past the left-the-box key
+    hipStream_t bs = c->bstream;
+    auto chunk_end = [&](int ch) { return std::min(p.nxi, (ch + 1) * C); };
+    auto deposit = [&](int ch) -> qsa_status {
+      qsa_status s = deposit_slabs(c, g, bs, src, ch * C, chunk_end(ch));
+      if (s != QSA_OK) return s;
+      HIP_OK(hipEventRecord(c->gdone[ch % QSA_GEV], bs));
+      return QSA_OK;
+    };
+    auto fork = [&](int slot) -> qsa_status {
+      HIP_OK(hipEventRecord(c->gfork[slot % QSA_GEV], c->stream));
+      HIP_OK(hipStreamWaitEvent(bs, c->gfork[slot % QSA_GEV], 0));
+      return QSA_OK;
+    };
+    if ((st = fork(0)) != QSA_OK) return st;
+    for (int ch = 0; ch < std::min(QSA_BEAM_AHEAD, nch); ++ch)
+      if ((st = deposit(ch)) != QSA_OK) return st;
+    clear_lanes(c->stream, lanes, d, 0);
+    int pushed = 0;   // chunks pushed so far
+    for (int t = 0; t < p.nxi; ++t) {
+      if (t % C == 0) HIP_OK(hipStreamWaitEvent(c->stream, c->gdone[(t / C) % QSA_GEV], 0));
+      if ((st = tick(c, c->stream, lanes, d, t)) != QSA_OK) return st;
+      if (t + 1 < p.nxi && t == chunk_end(pushed)) {
+        // slices <= t are final: chunk `pushed` goes, then the deposit of
+        // the chunk QSA_BEAM_AHEAD after it
+        if ((st = fork(pushed)) != QSA_OK) return st;
+        if ((st = push_keys(c, g, bs, (int64_t)pushed * C * keys_per_slab,
+                            (int64_t)chunk_end(pushed) * keys_per_slab)) != QSA_OK)
+          return st;
+        if (pushed + QSA_BEAM_AHEAD < nch && (st = deposit(pushed + QSA_BEAM_AHEAD)) != QSA_OK) return st;
+        ++pushed;
+      }
+    }
+    // the chunks left, and the particles outside the box, after the last
+    // slice (every chunk's deposit was enqueued before the tick that waits
+    // for it: chunk k after the push of chunk k - QSA_BEAM_AHEAD)
+    if ((st = fork(pushed)) != QSA_OK) return st;
+    if ((st = push_keys(c, g, bs, (int64_t)pushed * C * keys_per_slab, key_end)) != QSA_OK) return st;
+    HIP_OK(hipEventRecord(c->gdone[0], bs));
+    HIP_OK(hipStreamWaitEvent(c->stream, c->gdone[0], 0));   // join
     HIP_OK(hipGetLastError());
     c->swept = true;
     return QSA_OK;
@@ -1141,7 +1266,7 @@ struct Engine {
   // LDS of the widest column pass (COL_J) with ct threads per transform
   static int col_lds(int ny, int ct) {
     const int cpw = 64 / col_tpt(ny, ct);
-    return (cpw * 2 * ColShape<COL_J>::G + 1) * ny * (int)sizeof(C2<R>);
+    return (ny + cpw * 2 * ColShape<COL_J>::G * fft_cap(ny)) * (int)sizeof(C2<R>);
   }
 
   static qsa_status set_lds_limits(qsa_ctx* c) {
@@ -1162,8 +1287,8 @@ struct Engine {
     if (pipe > 65536)
       HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pipe_deposit<R>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, pipe));
-    // column transforms: (2 G cpw + 1) columns of ny complex values per
-    // block, cpw = 64 / threads per transform; the largest that fits
+    // column transforms: twiddles and 2 G cpw FFT buffers per block, cpw =
+    // 64 / threads per transform; the largest that fits
     int colj = col_lds(c->p.ny, 64);
     if (colj > limit) return fail(c, QSA_E_INVALID, "ny too large for the device's LDS");
     for (int ct = 32; ct >= 16; ct /= 2)
@@ -1286,13 +1411,24 @@ qsa_status run_step(qsa_ctx* c) {
   if (st != QSA_OK) return st;
   return dispatch(c, [&] { return Engine<double>::push(c); }, [&] { return Engine<float>::push(c); });
 }
+qsa_status run_step_beside(qsa_ctx* c) {
+  return dispatch(c, [&] { return Engine<double>::step_beside(c); },
+                  [&] { return Engine<float>::step_beside(c); });
+}
 qsa_status run_group(qsa_ctx* c, int n) {
   return dispatch(c, [&] { return Engine<double>::group(c, n); }, [&] { return Engine<float>::group(c, n); });
 }
 
-// One beam step at a time (graph replay unless timing or graphs are off).
+// One beam step at a time: the beam work beside the slice loop on two
+// streams (enqueued directly), else graph replay unless timing or graphs
+// are off.
 qsa_status step_one(qsa_ctx* c, bool graphs) {
   qsa_status st = QSA_OK;
+  if (c->beam_beside && c->L.nset == 1) {
+    if ((st = run_step_beside(c)) != QSA_OK) return st;
+    c->cur_set = 0;
+    return QSA_OK;
+  }
   if (graphs && (st = capture(c, &c->gx_step, [&] { return run_step(c); })) != QSA_OK) return st;
   if (graphs && c->gx_step) {
     HIP_OK(hipGraphLaunch(c->gx_step, c->stream));
@@ -1659,9 +1795,14 @@ qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value) {
   if (option == QSA_OPT_ROW_THREADS) {
     const int tpt = row_tpt(c->p.nx);
     if (value != 0 && !((value == 64 || value == 128 || value == 256) && value >= tpt && value % tpt == 0))
-      return fail(c, QSA_E_INVALID, "row threads must be 0 or 64, 128, 256 (a multiple of nx/8)");
+      return fail(c, QSA_E_INVALID, "row threads must be 0 or 64, 128, 256 (a multiple of nx/4)");
     c->tune_rt = (int)value;
     c->drop_graphs();
+    return QSA_OK;
+  }
+  if (option == QSA_OPT_BEAM_BESIDE) {
+    if (value != 0 && value != 1) return fail(c, QSA_E_INVALID, "beam beside: 0 or 1");
+    c->beam_beside = value != 0;
     return QSA_OK;
   }
   if (option == QSA_OPT_COL_THREADS) {
@@ -1806,6 +1947,10 @@ qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value) {
   }
   if (option == QSA_OPT_PIPELINE) {
     *value = c->pipe_ok ? c->pipe_max : 1;
+    return QSA_OK;
+  }
+  if (option == QSA_OPT_BEAM_BESIDE) {
+    *value = c->beam_beside ? 1 : 0;
     return QSA_OK;
   }
   if (option == QSA_OPT_PLASMA_THREADS || option == QSA_OPT_ROW_THREADS || option == QSA_OPT_COL_THREADS) {

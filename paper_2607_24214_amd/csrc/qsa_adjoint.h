@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(64) k_spec_rows_fwd(Geo<R> g, SpecOp<R> op, co
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
   C2<R>* A = tw + g.nx;
-  C2<R>* B = A + g.nx;
+  C2<R>* B = A + fft_cap(g.nx);
   const int t = threadIdx.x, tpt = blockDim.x;
   double rs = 0.0;
   for (int i = t; i < g.nx; i += tpt) {
@@ -301,8 +301,9 @@ __global__ void __launch_bounds__(64 * SPEC_IN) k_spec_cols(Geo<R> g, SpecOp<R> 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
   const int w = threadIdx.x >> 6, t = threadIdx.x & 63;
-  C2<R>* A = tw + g.ny + (int64_t)(2 * w) * g.ny;
-  C2<R>* B = A + g.ny;
+  const int cs = fft_cap(g.ny);
+  C2<R>* A = tw + g.ny + (int64_t)(2 * w) * cs;
+  C2<R>* B = A + cs;
   for (int i = threadIdx.x; i < g.ny; i += blockDim.x) tw[i] = twy[i];
   for (int i = t; i < g.ny; i += 64)
     A[i] = (w < op.ni) ? op.work[(int64_t)w * g.nperp + (int64_t)i * g.nx + kx] : C2<R>{R(0), R(0)};
@@ -311,7 +312,7 @@ __global__ void __launch_bounds__(64 * SPEC_IN) k_spec_cols(Geo<R> g, SpecOp<R> 
   // buffer of its pair (same pass count)
   const C2<R>* r = fft_lds<R, false>(A, B, g.ny, g.lgy, t, 64, tw);
   const bool inA = (r == A);
-  auto res = [&](int f) -> const C2<R>* { return tw + g.ny + (int64_t)(2 * f + (inA ? 0 : 1)) * g.ny; };
+  auto res = [&](int f) -> const C2<R>* { return tw + g.ny + (int64_t)(2 * f + (inA ? 0 : 1)) * cs; };
   C2<R>* S = inA ? B : A;   // free buffer of this wavefront
   const double N = (double)g.nperp;
   if (w < op.no) {
@@ -350,7 +351,7 @@ __global__ void __launch_bounds__(64) k_spec_rows_inv(Geo<R> g, SpecOp<R> op, co
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
   C2<R>* A = tw + g.nx;
-  C2<R>* B = A + g.nx;
+  C2<R>* B = A + fft_cap(g.nx);
   const int t = threadIdx.x, tpt = blockDim.x;
   const C2<R>* w = op.work + (int64_t)o * g.nperp + (int64_t)l * g.nx;
   const int h = g.nx / 2;

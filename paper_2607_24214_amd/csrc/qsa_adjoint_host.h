@@ -184,8 +184,8 @@ struct Adj {
     op.ktab = c->at<double>(A.ktab);
     op.work = c->at<C2<R>>(A.work);
     const int W = std::max(op.ni, op.no);
-    const size_t rows_lds = 3 * (size_t)g.nx * sizeof(C2<R>);
-    const size_t cols_lds = (size_t)g.ny * (1 + 2 * W) * sizeof(C2<R>);
+    const size_t rows_lds = ((size_t)g.nx + 2 * (size_t)fft_cap(g.nx)) * sizeof(C2<R>);
+    const size_t cols_lds = ((size_t)g.ny + 2 * (size_t)W * fft_cap(g.ny)) * sizeof(C2<R>);
     hipLaunchKernelGGL(k_spec_rows_fwd<R>, dim3(g.ny, op.ni), dim3(64), rows_lds, st(), g, op,
                        (const C2<R>*)c->at<C2<R>>(c->L.twx), s_rows);
     hipLaunchKernelGGL(k_spec_cols<R>, dim3(g.nx / 2 + 1), dim3(64 * W), cols_lds, st(), g, op,
@@ -632,8 +632,8 @@ struct Adj {
   qsa_status run(int nsteps, int nb, double* loss, double* grad) {
     qsa_status st0;
     {
-      // column transforms: twiddles and two buffers of ny per wavefront
-      const size_t cols_lds = (size_t)g.ny * (1 + 2 * SPEC_IN) * sizeof(C2<R>);
+      // column transforms: twiddles and two FFT buffers per wavefront
+      const size_t cols_lds = ((size_t)g.ny + 2 * (size_t)SPEC_IN * fft_cap(g.ny)) * sizeof(C2<R>);
       if (cols_lds > 65536)
         HIP_OK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spec_cols<R>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)cols_lds));

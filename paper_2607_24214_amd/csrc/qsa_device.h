@@ -221,15 +221,36 @@ __device__ __forceinline__ R wrap_pos(R x, R L, R invL) {
 // the conjugate twiddles and is unnormalized.  Every pass ends with a
 // workgroup barrier, so all threads of the workgroup must call with the same
 // n (threads without a transform still take part).
+//
+// The input and the result are in natural order; the passes in between
+// write a padded layout, one spare entry after every 8.  An early pass
+// stores its 8 outputs at a stride of 8 (ns = 1) or in runs of 8 that are
+// 64 entries apart (ns = 8): unpadded, a wavefront's stores then fall in a
+// quarter of the LDS banks (16-way conflicts for 8-byte entries, 32-way for
+// 16-byte ones); with a spare entry per 8 they spread over all banks.
 // ---------------------------------------------------------------------------
-template <typename R, bool INV>
+
+// Number of passes fft_lds takes for log2 n = lg (its result sits in the
+// input buffer when this is even).
+__host__ __device__ __forceinline__ int fft_passes(int lg) { return lg / 3 + (lg % 3 != 0); }
+
+// Entries an FFT work buffer of length n must hold (both of the two
+// buffers a transform alternates between).
+__host__ __device__ __forceinline__ int fft_cap(int n) { return n + (n >> 3); }
+
+// Position of entry i in the padded (P) or natural layout.
+template <bool P>
+__device__ __forceinline__ int fpad(int i) { return P ? i + (i >> 3) : i; }
+
+template <typename R, bool INV, bool PI>
 __device__ __forceinline__ void fft_pass4(const C2<R>* in, C2<R>* out, int n, int ns, int t,
                                           int tpt, const C2<R>* __restrict__ tw) {
   const int q = n >> 2;
   const int stride = n / (4 * ns);
   for (int jj = t; jj < q; jj += tpt) {
     const int k = jj & (ns - 1);
-    C2<R> a0 = in[jj], a1 = in[jj + q], a2 = in[jj + 2 * q], a3 = in[jj + 3 * q];
+    C2<R> a0 = in[fpad<PI>(jj)], a1 = in[fpad<PI>(jj + q)], a2 = in[fpad<PI>(jj + 2 * q)],
+          a3 = in[fpad<PI>(jj + 3 * q)];
     if (ns > 1) {
       C2<R> w1 = tw[k * stride], w2 = tw[2 * k * stride], w3 = tw[3 * k * stride];
       if (INV) {
@@ -252,14 +273,14 @@ __device__ __forceinline__ void fft_pass4(const C2<R>* in, C2<R>* out, int n, in
   }
 }
 
-template <typename R, bool INV>
+template <typename R, bool INV, bool PI>
 __device__ __forceinline__ void fft_pass2(const C2<R>* in, C2<R>* out, int n, int ns, int t,
                                           int tpt, const C2<R>* __restrict__ tw) {
   const int h = n >> 1;
   const int stride = n / (2 * ns);
   for (int jj = t; jj < h; jj += tpt) {
     const int k = jj & (ns - 1);
-    C2<R> a = in[jj], b = in[jj + h];
+    C2<R> a = in[fpad<PI>(jj)], b = in[fpad<PI>(jj + h)];
     if (ns > 1) {
       C2<R> w = tw[k * stride];
       if (INV) w = cconj(w);
@@ -312,8 +333,9 @@ __device__ __forceinline__ void dft8(C2<R> (&a)[8]) {
 }
 
 // Radix-8 Stockham pass: n/8 butterflies, thread t of tpt takes butterflies
-// t, t + tpt, ...; ns = the product of the earlier passes' radices.
-template <typename R, bool INV>
+// t, t + tpt, ...; ns = the product of the earlier passes' radices.  PI, PO:
+// the input, output is in the padded layout.
+template <typename R, bool INV, bool PI, bool PO>
 __device__ __forceinline__ void fft_pass8(const C2<R>* in, C2<R>* out, int n, int ns, int t, int tpt,
                                           const C2<R>* __restrict__ tw) {
   const int q = n >> 3;
@@ -322,7 +344,7 @@ __device__ __forceinline__ void fft_pass8(const C2<R>* in, C2<R>* out, int n, in
     const int k = jj & (ns - 1);
     C2<R> a[8];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) a[m] = in[jj + m * q];
+    for (int m = 0; m < 8; ++m) a[m] = in[fpad<PI>(jj + m * q)];
     if (ns > 1) {
 #pragma unroll
       for (int m = 1; m < 8; ++m) {
@@ -334,19 +356,31 @@ __device__ __forceinline__ void fft_pass8(const C2<R>* in, C2<R>* out, int n, in
     dft8<R, INV>(a);
     const int o = 8 * (jj - k) + k;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) out[o + m * ns] = a[m];
+    for (int m = 0; m < 8; ++m) out[fpad<PO>(o + m * ns)] = a[m];
   }
 }
 
-// Returns the buffer (a or b) that holds the result.  Radix-8 passes while
+// Returns the buffer (a or b) that holds the result, in natural order; each
+// of a and b holds fft_cap(n) entries.  Radix-8 passes while
 // at least three factors of two remain, then one radix-4 or radix-2 pass.
 template <typename R, bool INV>
 __device__ __forceinline__ C2<R>* fft_lds(C2<R>* a, C2<R>* b, int n, int lg, int t, int tpt,
                                           const C2<R>* __restrict__ tw) {
+  const int np = fft_passes(lg);
   int ns = 1;
   int s = lg;
+  int p = 0;
   while (s >= 3) {
-    fft_pass8<R, INV>(a, b, n, ns, t, tpt, tw);
+    const bool pi = p > 0, po = p + 1 < np;
+    if (pi && po)
+      fft_pass8<R, INV, true, true>(a, b, n, ns, t, tpt, tw);
+    else if (pi)
+      fft_pass8<R, INV, true, false>(a, b, n, ns, t, tpt, tw);
+    else if (po)
+      fft_pass8<R, INV, false, true>(a, b, n, ns, t, tpt, tw);
+    else
+      fft_pass8<R, INV, false, false>(a, b, n, ns, t, tpt, tw);
+    ++p;
     __syncthreads();
     C2<R>* tmp = a;
     a = b;
@@ -355,13 +389,19 @@ __device__ __forceinline__ C2<R>* fft_lds(C2<R>* a, C2<R>* b, int n, int lg, int
     s -= 3;
   }
   if (s == 2) {
-    fft_pass4<R, INV>(a, b, n, ns, t, tpt, tw);
+    if (p > 0)
+      fft_pass4<R, INV, true>(a, b, n, ns, t, tpt, tw);
+    else
+      fft_pass4<R, INV, false>(a, b, n, ns, t, tpt, tw);
     __syncthreads();
     C2<R>* tmp = a;
     a = b;
     b = tmp;
   } else if (s == 1) {
-    fft_pass2<R, INV>(a, b, n, ns, t, tpt, tw);
+    if (p > 0)
+      fft_pass2<R, INV, true>(a, b, n, ns, t, tpt, tw);
+    else
+      fft_pass2<R, INV, false>(a, b, n, ns, t, tpt, tw);
     __syncthreads();
     C2<R>* tmp = a;
     a = b;
@@ -371,12 +411,11 @@ __device__ __forceinline__ C2<R>* fft_lds(C2<R>* a, C2<R>* b, int n, int lg, int
 }
 
 // Threads per row transform of length n (two real rows packed as one
-// complex row): one radix-8 butterfly each per pass.
-__host__ __device__ __forceinline__ int row_tpt(int n) { return n >= 8 ? n >> 3 : 1; }
+// complex row): n/4, so that the loads of the rows' inputs (a sum of partial
+// rows and sources per value) have threads enough to be in flight together;
+// the radix-8 passes use half of them.
+__host__ __device__ __forceinline__ int row_tpt(int n) { return n >= 4 ? n >> 2 : 1; }
 
-// Number of passes fft_lds takes for log2 n = lg (its result sits in the
-// input buffer when this is even).
-__host__ __device__ __forceinline__ int fft_passes(int lg) { return lg / 3 + (lg % 3 != 0); }
 
 // In-place variant: the result ends in `a` (one extra LDS copy when the pass
 // count is odd).

@@ -83,7 +83,9 @@ struct Lane {
   C2<R>* bring;         // B_perp spectra, ring of 3 slices [3][2][nxh][ny]
   double* ode;          // [<E_z> at j-1/2, <psi> at j]
   R* fpack;             // the beam push's fields, packed per node (or null):
-                        // [QSA_PACK_RING][ny][nx][pack_stride<R>()]
+                        // [pack_ring][ny][nx][pack_stride<R>()], slice j in slot
+                        // j % pack_ring
+  int pack_ring;        // QSA_PACK_RING (steps in flight) or nxi (every slice)
   double* cpos[2];      // per plasma particle: the RK2 midpoint x, y of the slice
   R* cval[6];           // and the parts of its RK2 step that B_perp does not
                         // enter (see rk2_full), written by the first predictor
@@ -219,26 +221,6 @@ __device__ __forceinline__ R plasma_partial(const R* __restrict__ pp, int nc, in
   return s;
 }
 
-// Beam partial rows: block (j, l) holds node rows (j + dj, l + k), dj, k in
-// {0, 1}, for the 4 sources: bpart[((((j*ny + l)*2 + dj)*2 + k)*4 + q)*nx + i].
-// Node (J, L) collects corner (dj, k) of cell rows (J - dj, L - k).
-template <typename R>
-__device__ __forceinline__ R beam_partial(const R* __restrict__ bp, int ny, int nx, int q, int J, int L, int i) {
-  R s = R(0);
-#pragma unroll
-  for (int dj = 0; dj < 2; ++dj) {
-    const int jj = J - dj;
-    if (jj < 0) continue;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      int ll = L - k;
-      ll = (ny == 1) ? 0 : ((ll < 0) ? ll + ny : ll);
-      s += bp[(((((int64_t)jj * ny + ll) * 2 + dj) * 2 + k) * 4 + q) * nx + i];
-    }
-  }
-  return s;
-}
-
 // ------------------------------------------------------------ row transforms
 // Row-pass inputs of field f of a stage at slice j: the plasma partial rows
 // (for rho - J_z with the ion background folded in) and out-of-row grid of
@@ -333,8 +315,8 @@ __global__ void __launch_bounds__(256) k_row_r2c(const Lane<R>* __restrict__ lan
   const bool v1 = v0 && r1 < g.ny;
   C2<R>* tw = sm;                       // twiddles, staged once per block
   for (int i = threadIdx.x; i < g.nx; i += blockDim.x) tw[i] = twx[i];
-  C2<R>* A = sm + g.nx + (size_t)slot * 2 * g.nx;
-  C2<R>* B = A + g.nx;
+  C2<R>* A = sm + g.nx + (size_t)slot * 2 * fft_cap(g.nx);
+  C2<R>* B = A + fft_cap(g.nx);
   for (int i = t; i < g.nx; i += tpt) {
     const R va = v0 ? row_value(g, a, r0, i) : R(0);
     const R vb = v1 ? row_value(g, a, r1, i) : R(0);
@@ -404,8 +386,8 @@ __global__ void __launch_bounds__(256) k_row_c2r(const Lane<R>* __restrict__ lan
   const bool v1 = v0 && r1 < g.ny;
   C2<R>* tw = sm;                       // twiddles, staged once per block
   for (int i = threadIdx.x; i < g.nx; i += blockDim.x) tw[i] = twx[i];
-  C2<R>* A = sm + g.nx + (size_t)slot * 2 * g.nx;
-  C2<R>* B = A + g.nx;
+  C2<R>* A = sm + g.nx + (size_t)slot * 2 * fft_cap(g.nx);
+  C2<R>* B = A + fft_cap(g.nx);
   const int half = g.nx >> 1;
   for (int i = t; i < g.nx; i += tpt) {
     C2<R> av{0, 0}, bv{0, 0};
@@ -553,13 +535,14 @@ __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, 
   const bool valid = kx < g.nxh;
   C2<R>* tw = sm;                          // twiddles, staged once per block
   for (int i = threadIdx.x; i < ny; i += blockDim.x) tw[i] = twy[i];
-  C2<R>* D = sm + ny + (size_t)c * 2 * G * ny;   // G data columns
-  C2<R>* Sx = D + G * ny;                   // G scratch columns
-  C2<R>* mine = D + grp * ny;
+  const int cs = fft_cap(ny);               // column stride in LDS
+  C2<R>* D = sm + ny + (size_t)c * 2 * G * cs;   // G data columns
+  C2<R>* Sx = D + G * cs;                   // G scratch columns
+  C2<R>* mine = D + grp * cs;
   for (int y = t; y < ny; y += tpt)
     mine[y] = (valid && grp < S::NIN) ? L.rowspec[(size_t)grp * g.ny * g.nxh + y * g.nxh + kx] : C2<R>{0, 0};
   __syncthreads();
-  fft_lds_inplace<R, false>(mine, Sx + grp * ny, ny, g.lgy, t, tpt, tw);
+  fft_lds_inplace<R, false>(mine, Sx + grp * cs, ny, g.lgy, t, tpt, tw);
 
   for (int y = r; y < ny; y += per_col) {
     C2<R> o[S::NOUT];
@@ -579,7 +562,7 @@ __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, 
         o[1] = cscale(cmul_ik(ph, kdx), a.inv_n);
         o[2] = cscale(cmul_ik(ph, kdy), a.inv_n);
       } else if (MODE == COL_J) {
-        const C2<R> jx = D[y], jy = D[ny + y], jzv = D[2 * ny + y];
+        const C2<R> jx = D[y], jy = D[cs + y], jzv = D[2 * cs + y];
         a.jr_w[0][e] = jx;
         a.jr_w[1][e] = jy;
         a.jz[e] = jzv;
@@ -610,7 +593,7 @@ __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, 
         // D = d_xi J_perp ~ (J~_perp^{j+1} - J_perp^{j-1})/(2h)
         const R i2h = R(0.5) / a.h;
         const C2<R> dx = cscale(csub(D[y], a.jr_r[0][e]), i2h);
-        const C2<R> dy = cscale(csub(D[ny + y], a.jr_r[1][e]), i2h);
+        const C2<R> dy = cscale(csub(D[cs + y], a.jr_r[1][e]), i2h);
         const C2<R> jzv = a.jz[e];
         const C2<R> bxo = a.b_cur[0][e], byo = a.b_cur[1][e];
         const R iden = R(1) / (-ksq - a.kappa2);
@@ -627,10 +610,10 @@ __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, 
     // every thread of the column has read its inputs at row y before any
     // output at row y is written: rows are owned by exactly one thread here
 #pragma unroll
-    for (int q = 0; q < S::NOUT; ++q) D[q * ny + y] = o[q];
+    for (int q = 0; q < S::NOUT; ++q) D[q * cs + y] = o[q];
   }
   __syncthreads();
-  fft_lds_inplace<R, true>(mine, Sx + grp * ny, ny, g.lgy, t, tpt, tw);
+  fft_lds_inplace<R, true>(mine, Sx + grp * cs, ny, g.lgy, t, tpt, tw);
   if (valid && grp < S::NOUT)
     for (int y = t; y < ny; y += tpt) L.colout[(size_t)grp * g.ny * g.nxh + y * g.nxh + kx] = mine[y];
 }
@@ -1050,7 +1033,7 @@ __global__ void __launch_bounds__(256) k_push_final(const Lane<R>* __restrict__ 
     // slice j is final: pack the beam push's fields
     const int64_t plane = (int64_t)g.nxi * g.nperp;
     const R* f = L.fields + (int64_t)j * g.nperp;
-    R* dst = L.fpack + (int64_t)(j % QSA_PACK_RING) * g.nperp * pack_stride<R>();
+    R* dst = L.fpack + (int64_t)(j % L.pack_ring) * g.nperp * pack_stride<R>();
     const int slot[6] = {F_DXPSI, F_DYPSI, F_EZ, F_BX, F_BY, F_BZ};
     for (int o = p; o < g.nperp; o += gridDim.x * blockDim.x) {
       R v[pack_stride<R>()];
@@ -1235,6 +1218,8 @@ struct BeamArgs {
   R* w;
   int64_t n;
   const R* fields;    // [7][nxi][nperp]
+  const R* fpack;     // the same fields packed per node for every slice (or null)
+  int ring;           // slots of fpack (>= nxi when set)
   R zq;               // Z/(dx dy dxi)
   R qmh;              // (Z/M) dt/2
   R dt;
@@ -1419,12 +1404,11 @@ struct BeamDepArgs {
   const R* uy[4];
   const R* uz[4];
   const R* w[4];
-  int* key[4];                // per particle: cell-row key
+  int* key[4];                // per particle: cell-row key (null: recomputed where needed)
   int* perm[4];               // particles of each cell row, row after row
   const int64_t* doff[4];     // chunk offsets [nxi*ny*nxc + 2]: row b's particles are
                               // perm[doff[b*nxc] .. doff[(b+1)*nxc])
   R zq[4];                    // Z/(dx dy dxi)
-  R* bpart;                   // partial node rows [nxi*ny][2][2][4][nx]
   double inv_dxi;
 };
 
@@ -1437,18 +1421,21 @@ __global__ void __launch_bounds__(256) k_beam_keys(Geo<R> g, BeamDepArgs<R> a, i
   int key = 0;
   if (act) {
     key = beam_key(g, a.x[s][p], a.y[s][p], a.xi[s][p], a.w[s][p], a.inv_dxi);
-    a.key[s][p] = key;
+    if (a.key[s]) a.key[s][p] = key;
   }
   (void)wave_run_add(cnt, key, act);
 }
 
 // Particle indices grouped by key: cur holds the exclusive offsets on entry.
 template <typename R>
-__global__ void __launch_bounds__(256) k_beam_perm(BeamDepArgs<R> a, int s, int64_t n,
+__global__ void __launch_bounds__(256) k_beam_perm(Geo<R> g, BeamDepArgs<R> a, int s, int64_t n,
                                                    int64_t* __restrict__ cur) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = p < n;
-  const int key = act ? a.key[s][p] : 0;
+  // the key kept by k_beam_keys, or the same key again (contexts without
+  // steps in flight keep no key array)
+  const int key = act ? (a.key[s] ? a.key[s][p] : beam_key(g, a.x[s][p], a.y[s][p], a.xi[s][p], a.w[s][p], a.inv_dxi))
+                      : 0;
   const int64_t slot = wave_run_add(cur, key, act);
   if (act) a.perm[s][slot] = (int)p;
 }
@@ -1562,15 +1549,36 @@ __device__ __forceinline__ void deposit_pairs(double* __restrict__ tile, int nx,
 }
 
 // Beam deposit owned by cell rows b = (j, l): the block takes exactly the
-// particles of its row (through the permutation), adds them to an LDS tile
-// of node slices (j, j+1) x node rows (l, l+1) with LDS atomics and writes
-// the tile out as the row's partial node rows.
+// particles of its row (through the permutation) and adds them to an LDS
+// tile of node slices (j, j+1) x node rows (l, l+1) with LDS atomics.  The
+// rows go in four launches by the parity of (j, l) (colour = 2 (j & 1) +
+// (l & 1); in a slab only the parity of j): the blocks of one launch cover
+// disjoint nodes, so each adds its tile to the dense sources [4][nxi][ny][nx]
+// in place, with plain loads and stores (the sources are zeroed before the
+// first launch).  A launch may cover the slabs [jlo, jhi) only; launches of
+// neighbouring slab ranges share a node slice and must not overlap in time.
+__host__ __device__ __forceinline__ int beam_colour_first(int jlo, int colour) {
+  return jlo + ((jlo ^ (colour >> 1)) & 1);   // first slab of the colour's parity
+}
+__host__ __device__ __forceinline__ int beam_colour_rows(int jlo, int jhi, int ny, int colour) {
+  const int cl = colour & 1;
+  const int nyc = (ny == 1) ? (cl ? 0 : 1) : (ny >> 1);
+  const int j0 = beam_colour_first(jlo, colour);
+  return (j0 < jhi) ? ((jhi - j0 + 1) >> 1) * nyc : 0;
+}
+
 template <typename R>
-__global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a) {
+__global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a, R* __restrict__ src, int colour,
+                                                   int jlo, int jhi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* tile = reinterpret_cast<double*>(smem_raw);   // float64 for either precision
-  const int b = blockIdx.x;
-  const int jb = b / g.ny;
+  const int cl = colour & 1;
+  const int nyc = (g.ny == 1) ? 1 : (g.ny >> 1);
+  const int jj = blockIdx.x / nyc, ll = blockIdx.x - jj * nyc;
+  const int jb = beam_colour_first(jlo, colour) + 2 * jj;
+  const int lb = (g.ny == 1) ? 0 : 2 * ll + cl;
+  if (jb >= jhi || jb >= g.nxi) return;
+  const int b = jb * g.ny + lb;
   const int tn = 2 * 2 * 4 * g.nx;
   for (int t = threadIdx.x; t < tn; t += blockDim.x) tile[t] = 0.0;
   __syncthreads();
@@ -1586,8 +1594,24 @@ __global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a) {
     });
   }
   __syncthreads();
-  R* out = a.bpart + (int64_t)b * tn;
-  for (int t = threadIdx.x; t < tn; t += blockDim.x) out[t] = (R)tile[t];
+  // tile layout (tile_add_cell): [node slice d][node row e][source c][x]
+  const int64_t plane = (int64_t)g.nxi * g.nperp;
+  for (int t = threadIdx.x; t < 2 * 4 * g.nx; t += blockDim.x) {
+    const int i = t % g.nx, rest = t / g.nx, c = rest & 3, d = rest >> 2;
+    const int J = jb + d;
+    if (J >= g.nxi) continue;
+    const double v0 = tile[((d * 2 + 0) * 4 + c) * g.nx + i];
+    const double v1 = tile[((d * 2 + 1) * 4 + c) * g.nx + i];
+    R* base = src + c * plane + (int64_t)J * g.nperp + i;
+    if (g.ny == 1) {
+      // both node rows of a slab cell are row 0
+      base[0] += (R)(v0 + v1);
+    } else {
+      const int L1 = (lb + 1 == g.ny) ? 0 : lb + 1;
+      base[(int64_t)lb * g.nx] += (R)v0;
+      base[(int64_t)L1 * g.nx] += (R)v1;
+    }
+  }
 }
 
 // Beam particles reordered by cell row (a stable-in-runs counting sort):
@@ -1672,19 +1696,6 @@ __global__ void __launch_bounds__(256) k_scan64_add(int64_t* __restrict__ v, int
   if (i < n) v[i] += bsum[i >> 10];
 }
 
-// Dense beam sources [4][nxi][ny][nx] from the partial rows: one pass before
-// the sweep, so the row transforms read one value per node.
-template <typename R>
-__global__ void __launch_bounds__(256) k_beam_reduce(Geo<R> g, const R* __restrict__ bpart, R* __restrict__ src) {
-  const int64_t plane = (int64_t)g.nxi * g.nperp;
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= plane) return;
-  const int J = (int)(o / g.nperp);
-  const int r = (int)(o - (int64_t)J * g.nperp);
-  const int L = r / g.nx, i = r - L * g.nx;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) src[q * plane + o] = beam_partial(bpart, g.ny, g.nx, q, J, L, i);
-}
 
 
 // Boris push of one beam particle by dt in the stored fields, E = (-d_x psi
@@ -1729,7 +1740,7 @@ __device__ __forceinline__ void packed_node(const R* __restrict__ rec, R (&v)[6]
 }
 
 template <typename R>
-__device__ __forceinline__ void beam_fields(const Geo<R>& g, const R* __restrict__ fields, const R* __restrict__ fpack,
+__device__ __forceinline__ void beam_fields(const Geo<R>& g, const R* __restrict__ fields, const R* __restrict__ fpack, int ring,
                                             double inv_dxi, R x, R y, double xi, R (&fd)[6]) {
 #pragma unroll
   for (int q = 0; q < 6; ++q) fd[q] = R(0);
@@ -1747,7 +1758,7 @@ __device__ __forceinline__ void beam_fields(const Geo<R>& g, const R* __restrict
     if (jj < 0 || jj >= g.nxi) continue;
     const R wz = dj ? fz : R(1) - fz;
     if (fpack) {
-      const R* rec = fpack + (int64_t)(jj % QSA_PACK_RING) * g.nperp * pack_stride<R>();
+      const R* rec = fpack + (int64_t)(jj % ring) * g.nperp * pack_stride<R>();
       R a[6], b[6], c[6], d[6];
       packed_node(rec + (int64_t)s.n00 * pack_stride<R>(), a);
       packed_node(rec + (int64_t)s.n10 * pack_stride<R>(), b);
@@ -1788,7 +1799,7 @@ __device__ __forceinline__ BeamOld<R> beam_old(const R* __restrict__ px, const R
 // Boris push of particle p from its loaded state b; stores the new state.
 template <typename R>
 __device__ __forceinline__ BeamNew<R> boris_state(const Geo<R>& g, const R* __restrict__ fields,
-                                                  const R* __restrict__ fpack, R qh, R dt, double inv_dxi,
+                                                  const R* __restrict__ fpack, int ring, R qh, R dt, double inv_dxi,
                                                   double xi_max, const BeamOld<R>& b, R* __restrict__ px,
                                                   R* __restrict__ py, double* __restrict__ pxi,
                                                   R* __restrict__ pux, R* __restrict__ puy, R* __restrict__ puz,
@@ -1797,7 +1808,7 @@ __device__ __forceinline__ BeamNew<R> boris_state(const Geo<R>& g, const R* __re
   const double xi = b.xi;
   R ux = b.ux, uy = b.uy, uz = b.uz;
   R fd[6];   // d_x psi, d_y psi, E_z, B_x, B_y, B_z
-  beam_fields(g, fields, fpack, inv_dxi, x, y, xi, fd);
+  beam_fields(g, fields, fpack, ring, inv_dxi, x, y, xi, fd);
   const R ex = -fd[0] + fd[4];
   const R ey = -fd[1] - fd[3];
   const R ez = fd[2];
@@ -1843,19 +1854,34 @@ __device__ __forceinline__ BeamNew<R> boris_state(const Geo<R>& g, const R* __re
 
 template <typename R>
 __device__ __forceinline__ BeamNew<R> boris_one(const Geo<R>& g, const R* __restrict__ fields,
-                                                const R* __restrict__ fpack, R qh, R dt, double inv_dxi,
+                                                const R* __restrict__ fpack, int ring, R qh, R dt, double inv_dxi,
                                                 double xi_max, R* __restrict__ px, R* __restrict__ py,
                                                 double* __restrict__ pxi, R* __restrict__ pux, R* __restrict__ puy,
                                                 R* __restrict__ puz, R* __restrict__ pw, int64_t p) {
   const BeamOld<R> b = beam_old<R>(px, py, pxi, pux, puy, puz, pw, p);
-  return boris_state(g, fields, fpack, qh, dt, inv_dxi, xi_max, b, px, py, pxi, pux, puy, puz, pw, p);
+  return boris_state(g, fields, fpack, ring, qh, dt, inv_dxi, xi_max, b, px, py, pxi, pux, puy, puz, pw, p);
 }
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_beam_push(Geo<R> g, BeamArgs<R> a) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.n) return;
-  boris_one<R>(g, a.fields, nullptr, a.qmh, a.dt, a.inv_dxi, a.xi_max, a.x, a.y, a.xi, a.ux, a.uy, a.uz, a.w, p);
+  boris_one<R>(g, a.fields, a.fpack, a.ring, a.qmh, a.dt, a.inv_dxi, a.xi_max, a.x, a.y, a.xi, a.ux, a.uy, a.uz,
+               a.w, p);
+}
+
+// The same push for the particles whose deposit keys lie in [k0, k1):
+// perm[off[k0] .. off[k1]) (the permutation and chunk offsets of the beam
+// deposit, so a slab range of keys is the particles of those slabs at the
+// step's start); grid-stride, as the count is only known on the device.
+template <typename R>
+__global__ void __launch_bounds__(256) k_beam_push_keys(Geo<R> g, BeamArgs<R> a, const int* __restrict__ perm,
+                                                        const int64_t* __restrict__ off, int64_t k0, int64_t k1) {
+  const int64_t q1 = off[k1];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = off[k0] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < q1; q += stride)
+    boris_one<R>(g, a.fields, a.fpack, a.ring, a.qmh, a.dt, a.inv_dxi, a.xi_max, a.x, a.y, a.xi, a.ux, a.uy,
+                 a.uz, a.w, (int64_t)perm[q]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1981,7 +2007,8 @@ __device__ __forceinline__ bool pipe_push_one(const PipeBeam<R>& B, int s, int64
     if (feeds && b.w != R(0) && gz < (double)(jp - QSA_DRIFT_BACK)) bad = true;
   }
   const R w0 = b.w;
-  const BeamNew<R> n = boris_state(g, B.fields, B.fpack, B.qmh[s], B.dt, B.inv_dxi, B.xi_max, b, B.x[s], B.y[s],
+  const BeamNew<R> n = boris_state(g, B.fields, B.fpack, QSA_PACK_RING, B.qmh[s], B.dt, B.inv_dxi, B.xi_max, b,
+                                   B.x[s], B.y[s],
                                    B.xi[s], B.ux[s], B.uy[s], B.uz[s], B.w[s], p);
   if (!feeds) return bad;
   const R w = n.lost ? R(0) : w0;

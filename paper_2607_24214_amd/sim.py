@@ -33,10 +33,12 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
                 species: Sequence, n_plasma: int, plasma_w: float,
                 beam_capacity: Sequence[int], precision: str = "f64", n_corr: int = 3,
                 kappa2: float = 0.75, pipeline: int = 1, adjoint_steps: int = 0,
-                ckpt_every: int = 0) -> L.QSAParams:
+                ckpt_every: int = 0, field_pack: bool = True) -> L.QSAParams:
     """species: sequence of (Z, M); pipeline: beam steps in flight (1 = off);
     adjoint_steps: most steps qsa_adjoint_sweep differentiates (0 = none);
-    ckpt_every: the adjoint's plasma checkpoint stride in slices (0 = 16)."""
+    ckpt_every: the adjoint's plasma checkpoint stride in slices (0 = 16);
+    field_pack: keep the push's fields packed for every slice (without steps
+    in flight; False saves 32-48 bytes per cell)."""
     p = L.QSAParams()
     p.nx, p.ny, p.nxi = nx, ny, nxi
     p.precision = _PREC[precision]
@@ -47,6 +49,7 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
     p.pipeline = int(pipeline)
     p.adjoint_steps = int(adjoint_steps)
     p.ckpt_every = int(ckpt_every)
+    p.no_field_pack = 0 if field_pack else 1
     for i, (Z, M) in enumerate(species):
         p.species[i].Z = int(Z)
         p.species[i].M = float(M)
@@ -57,14 +60,14 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
 def params_from_workload(wl, precision: Optional[str] = None,
                          beam_capacity: Optional[Sequence[int]] = None,
                          pipeline: int = 1, adjoint_steps: int = 0,
-                         ckpt_every: Optional[int] = None) -> L.QSAParams:
+                         ckpt_every: Optional[int] = None, field_pack: bool = True) -> L.QSAParams:
     """Parameters of a workload description (duck-typed: grid, species, loading)."""
     caps = beam_capacity or [wl.n_beam(s) for s in range(len(wl.species))]
     ck = getattr(wl, "ckpt_every", 0) if ckpt_every is None else ckpt_every
     return make_params(wl.nx, wl.ny, wl.nxi, wl.dx, wl.dy, wl.dxi, wl.dt,
                        [(s.Z, s.M) for s in wl.species], wl.n_plasma,
                        wl.dx * wl.dy / wl.plasma_ppc, caps, precision or wl.precision,
-                       wl.n_corr, wl.kappa2, pipeline, adjoint_steps, min(int(ck), wl.nxi))
+                       wl.n_corr, wl.kappa2, pipeline, adjoint_steps, min(int(ck), wl.nxi), field_pack)
 
 
 class Sim:
@@ -157,6 +160,11 @@ class Sim:
     def set_pipeline(self, depth: int):
         """Beam steps in flight (1 .. the pipeline parameter)."""
         self._check(self.lib.qsa_set_option(self.ctx, 1, int(depth)))
+
+    def set_beam_beside(self, enable: bool):
+        """One step at a time: run the beam deposit and push beside the slice
+        loop on a second stream (default) or after it."""
+        self._check(self.lib.qsa_set_option(self.ctx, 5, int(bool(enable))))
 
     def set_shapes(self, plasma_threads: int = 0, row_threads: int = 0, col_threads: int = 0):
         """Launch shapes (0 = default): threads per plasma-row block, per
