@@ -221,16 +221,34 @@ def scan_rate(n_inst: int, steps: int, warmup: int):
     import torch
     import qsa_workloads as W
     import paper_2607_24214_amd as Q
+    from concurrent.futures import ThreadPoolExecutor
     wls = W.scan_instances()[:n_inst]
     t = time.perf_counter()
-    sims = []
-    for wl in wls:
+    sims = [None] * len(wls)
+
+    def make(i):
         # all 64 instances fit one GPU without the packed push fields
-        sim = Q.Sim(Q.params_from_workload(wl, precision="f32", pipeline=1, field_pack=False))
-        sim.load_plasma(W.plasma_template(wl))
-        for k, b in enumerate(W.beam(wl)):
-            sim.load_beam(k, b)
-        sims.append(sim)
+        return Q.Sim(Q.params_from_workload(wls[i], precision="f32", pipeline=1, field_pack=False))
+
+    big = [i for i, wl in enumerate(wls) if wl.n_beam_total > 1 << 26]
+    small = [i for i in range(len(wls)) if i not in big]
+    for i in big:   # generated range by range on host threads
+        sims[i] = make(i)
+        sims[i].load_plasma(W.plasma_template(wls[i]))
+        load_beam_in_ranges(sims[i], wls[i])
+    nthr = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 8))
+    with ThreadPoolExecutor(nthr) as ex:
+        # instances generated on host threads a group at a time (bounded host memory)
+        for g0 in range(0, len(small), nthr):
+            grp = small[g0:g0 + nthr]
+            data = list(ex.map(lambda i: (W.plasma_template(wls[i]), W.beam(wls[i])), grp))
+            for i, (pl, beams) in zip(grp, data):
+                sims[i] = make(i)
+                sims[i].load_plasma(pl)
+                for k, b in enumerate(beams):
+                    sims[i].load_beam(k, b)
+            del data
+    torch.cuda.synchronize()
     log(f"scan: {n_inst} instances loaded in {time.perf_counter() - t:.1f} s")
     batch = Q.Batch(sims)
     batch.step(warmup)
@@ -327,6 +345,30 @@ def linear_model_rate():
             "point_steps_per_s": work / tg}
 
 
+def dirichlet_rate(n_grid: int = 256, n: int = 511):
+    """The conducting-wall solver on n_grid grids of n x n interior nodes in
+    float32 (a batch of slices of a 512-class box): wall time of the
+    synchronized three-launch solve, averaged over 5 after one untimed.
+    Algorithmic bytes: the source read and the solution written once (8
+    bytes per node); the three passes move each node's value through HBM
+    three times (24 bytes)."""
+    import torch
+    import paper_2607_24214_amd as Q
+    f = torch.randn((n_grid, n, n), dtype=torch.float32, device="cuda")
+    u = torch.empty_like(f)
+    Q.dirichlet_solve(f, 0.1, 0.1, 0.0, out=u)
+    torch.cuda.synchronize()
+    reps = 5
+    t = time.perf_counter()
+    for _ in range(reps):
+        Q.dirichlet_solve(f, 0.1, 0.1, 0.0, out=u)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t) / reps
+    nodes = n_grid * n * n
+    return {"grids": n_grid, "nx": n, "ny": n, "dtype": "f32", "ms": ms, "grids_per_s": n_grid / (ms * 1e-3),
+            "alg_GB_s": 8.0 * nodes / (ms * 1e-3) / 1e9, "moved_GB_s": 24.0 * nodes / (ms * 1e-3) / 1e9}
+
+
 def b_alg(wl, rsize: int) -> float:
     """Algorithmic HBM bytes per plasma particle-slice update of the whole
     sweep: the particle state (x, y, u_x, u_y) read and written and its
@@ -392,8 +434,12 @@ def run_workload(wl, precision: str, pipeline: int, steps: int, warmup: int, arg
     log(f"inputs generated and loaded in {tl:.1f} s")
     if args.no_graphs:
         sim.set_graphs(False)
-    if args.col_threads:
-        sim.set_shapes(0, 0, args.col_threads)
+    if args.no_beside:
+        sim.set_beam_beside(False)
+    if args.beside_blocks is not None:
+        sim.set_beside_blocks(args.beside_blocks)
+    if args.col_threads or args.plasma_threads:
+        sim.set_shapes(args.plasma_threads, 0, args.col_threads)
     tuned = None
     if args.autotune:
         t = time.perf_counter()
@@ -506,6 +552,8 @@ def main():
                     help="let the library time its launch shapes and steps in flight first")
     ap.add_argument("--pre-steps", type=int, default=0,
                     help="untimed beam steps after the warmup (time a more evolved beam)")
+    ap.add_argument("--plasma-threads", type=int, default=0,
+                    help="threads per plasma cell-row block (0 = the library's default)")
     ap.add_argument("--col-threads", type=int, default=0,
                     help="threads per column transform (16, 32, 64; 0 = the library's default)")
     ap.add_argument("--cpu-slices", type=int, default=None,
@@ -513,12 +561,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the extra entries (the 256^3-class workload in float64 and float32)")
+    ap.add_argument("--beside-blocks", type=int, default=None,
+                    help="workgroups per launch of the beam work beside the slice loop (0 = the work's)")
+    ap.add_argument("--no-beside", action="store_true",
+                    help="one step at a time: deposit, sweep and push one after the other instead of the "
+                         "beam work beside the slice loop")
     ap.add_argument("--no-graphs", action="store_true",
                     help="enqueue every launch instead of replaying HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 2 GiB three times (scale for HBM counters)")
     ap.add_argument("--breakdown", action="store_true",
                     help="also time every kernel class over one extra group of steps each")
+    ap.add_argument("--no-scan", action="store_true",
+                    help="skip the 64-instance batched scan among the extra configurations")
+    ap.add_argument("--no-dirichlet", action="store_true",
+                    help="skip the conducting-wall (sine-transform) solver measurement")
     ap.add_argument("--no-linear-model", action="store_true",
                     help="skip the linear-model solver measurement")
     ap.add_argument("--no-diagnostics", action="store_true",
@@ -570,11 +627,21 @@ def main():
             e = run_workload(cube.with_(precision=prec), prec, 8, 16, 4, args, with_extras=False)
             extra[f"{cube.name}_{prec}"] = {k: e[k] for k in ("value", "ms_per_step", "steps", "warmup", "dtype",
                                                               "config", "sweep_only", "roofline")}
+        if not args.no_scan:
+            # the 64-instance batched scan (float32), all instances on this GPU
+            sc = scan_rate(64, 3, 1)
+            log(f"scan64: {sc['ms_per_step']:.1f} ms per batched step, {sc['value']:.3e} updates/s")
+            extra["scan64_f32"] = {k: sc[k] for k in ("value", "ms_per_step", "steps", "warmup", "dtype", "config")}
     linear = None
     if not args.no_linear_model:
         linear = linear_model_rate()
         log(f"linear model: {linear['instances']} instances x {linear['xi_points']} points x "
             f"{linear['rk4_steps']} RK4 steps in {linear['ms']:.1f} ms")
+    dirichlet = None
+    if not args.no_dirichlet:
+        dirichlet = dirichlet_rate()
+        log(f"dirichlet solve: {dirichlet['grids']} grids of {dirichlet['ny']}x{dirichlet['nx']} in "
+            f"{dirichlet['ms']:.2f} ms ({dirichlet['alg_GB_s']:.0f} GB/s algorithmic)")
     adjoint = None
     if not args.no_adjoint:
         log("adjoint workload ...")
@@ -626,6 +693,7 @@ def main():
         "adjoint": adjoint,
         "diagnostics": head["diagnostics"],
         "linear_model": linear,
+        "dirichlet_solve": dirichlet,
     }
     if "kernel_breakdown_ms_per_step" in head:
         out["kernel_breakdown_ms_per_step"] = head["kernel_breakdown_ms_per_step"]

@@ -126,6 +126,13 @@ typedef struct {
                             records); 1: it does not (the push gathers from
                             the stored planes), for boxes that need the
                             memory                                          */
+  int32_t plasma_weights; /* 0: every plasma macro-particle has weight
+                            plasma_w; 1: the workspace keeps a weight per
+                            particle (random macro-particle weights, the
+                            noise control of the "Extending the QSA to
+                            extreme blazar jet regimes" section), loaded
+                            with qsa_load_plasma_weights (until then all
+                            plasma_w).  qsa_adjoint_sweep requires 0.      */
 } qsa_params;
 
 /* Bytes of device workspace a context with these parameters needs; 0 if the
@@ -148,6 +155,16 @@ qsa_status qsa_create(const qsa_params* p, void* dev_ws, size_t ws_bytes,
 qsa_status qsa_load_plasma(qsa_ctx* c, const double* x, const double* y,
                            const double* ux, const double* uy, int64_t n,
                            int32_t on_device);
+
+/* Per-particle weights of the loaded plasma template (contexts created
+ * with plasma_weights = 1; after qsa_load_plasma, which resets them to
+ * plasma_w): w[i] is the weight of template particle i in the units of
+ * plasma_w (area per particle times the local density, so that a uniform
+ * plasma has w[i] = plasma_w); each particle deposits -w[i]/(dx dy) times
+ * its shape.  n must equal n_plasma.  Float64, host (synchronizing; every
+ * value finite and >= 0, else QSA_E_NONFINITE) or device memory.
+ * QSA_E_STATE without plasma_weights or before a template is loaded. */
+qsa_status qsa_load_plasma_weights(qsa_ctx* c, const double* w, int64_t n, int32_t on_device);
 
 /* Load n (<= capacity) particles of beam species s (the beam species of
  * the problem statement; flat-top loading as in the "PIC simulations"
@@ -262,6 +279,28 @@ qsa_status qsa_linear_model(int32_t n_inst, int32_t nxi, double dxi, double dtau
                             int32_t gamma_per_point, const double* n0, int32_t n_tau, const double* taus, double* n_out, double* psi_out,
                             void* hip_stream);
 
+/* Conducting-wall (Dirichlet) transverse solves by sine transforms, the
+ * sine-transform form of the field equations' transverse solves (the
+ * pseudo-potential's Poisson equation, Eq. (2) in its linear form, and the
+ * Helmholtz-shifted B_perp iteration) for a box whose walls hold the
+ * potential at zero.  For n_grid independent grids f[g][ny][nx] of values
+ * at the interior nodes x_i = i dx (i = 1..nx, walls at 0 and (nx+1) dx) and
+ * y_l = l dy (l = 1..ny), solve (-lap_perp + kappa2) u = f with u = 0 on the
+ * walls, in the wall modes sin(m pi x/L_x) sin(n pi y/L_y) (m <= nx,
+ * n <= ny; L = (N+1) d) with their exact eigenvalues (m pi/L_x)^2 +
+ * (n pi/L_y)^2 + kappa2; ny = 1 is a slab with x walls only.
+ *   precision: QSA_FP64 (f, u double) or QSA_FP32 (float);
+ *   nx + 1 and (unless ny = 1) ny + 1 powers of two in [2, 512];
+ *   dx, dy > 0; kappa2 >= 0 (0: Poisson);
+ *   f, u: device memory [n_grid][ny][nx], row-major (x fastest); u may be f
+ *     (in place) but must not overlap it otherwise.
+ * Enqueued on hip_stream (a hipStream_t, null for the default stream)
+ * without synchronizing: three launches (one for a slab).  QSA_E_INVALID for
+ * arguments out of range (nothing launched), QSA_E_DEVICE if a launch
+ * fails.  Needs no context. */
+qsa_status qsa_dirichlet_solve(int32_t precision, int32_t n_grid, int32_t nx, int32_t ny, double dx, double dy,
+                               double kappa2, const void* f, void* u, void* hip_stream);
+
 /* Wait for the stream and report any pending device error. */
 qsa_status qsa_sync(qsa_ctx* c);
 
@@ -302,8 +341,10 @@ enum {
                             after a drift fallback); get: the depth in use,
                             1 when pipelining is off                        */
   QSA_OPT_PLASMA_THREADS = 2, /* threads per plasma cell-row block: 64, 128,
-                            256, or 0 for the default (from the particles per
-                            row); get: the value in use                     */
+                            256, 512 (float32 only), or 0 for the default
+                            (from the particles per row, at most 512 in
+                            float32 and 256 in float64); get: the value in
+                            use                                             */
   QSA_OPT_ROW_THREADS = 3, /* threads per row-transform block: 64, 128, 256
                             (a multiple of nx/4), or 0 for
                             min(256, max(64, nx/2));
@@ -312,7 +353,7 @@ enum {
                             wavefront takes 64 / value adjacent columns), or
                             0 for 64; at most ny/4 are used; get: the value
                             in use                                          */
-  QSA_OPT_BEAM_BESIDE = 5 /* contexts without steps in flight (pipeline = 1):
+  QSA_OPT_BEAM_BESIDE = 5, /* contexts without steps in flight (pipeline = 1):
                             1 runs a beam step's source deposit and
                             push on a second stream beside the slice loop, a
                             few slabs at a time (the deposit ahead of the
@@ -320,6 +361,11 @@ enum {
                             gathers are final); 0 (default): deposit, sweep,
                             push one after the other.  The results agree up to the
                             order of the deposit's additions.              */
+  QSA_OPT_BESIDE_BLOCKS = 6 /* workgroups per launch of the beam work beside
+                            the slice loop: 0 (default) as many as the work
+                            has; n > 0 caps every such launch at n (each
+                            workgroup then loops over its share), leaving
+                            the rest of the chip to the slice loop       */
 };
 
 /* Set a context option (see QSA_OPT_*). */

@@ -5,8 +5,8 @@ thin Python binding.  Importing the binding does not need a GPU; creating a
 Sim does, and fails loudly if the library has not been built.
 """
 from ._lib import FIELD_IDS, QSAError, QSAParams, lib  # noqa: F401
-from .sim import (Batch, FieldEnergy, Sim, batch_sweep_static, linear_model, make_params,  # noqa: F401
-                  params_from_workload)
+from .sim import (Batch, FieldEnergy, Sim, batch_sweep_static, dirichlet_solve, linear_model,  # noqa: F401
+                  make_params, params_from_workload)
 
-__all__ = ["Sim", "Batch", "FieldEnergy", "batch_sweep_static", "linear_model", "make_params", "params_from_workload", "QSAError", "QSAParams", "lib",
-           "FIELD_IDS"]
+__all__ = ["Sim", "Batch", "FieldEnergy", "batch_sweep_static", "dirichlet_solve", "linear_model", "make_params",
+           "params_from_workload", "QSAError", "QSAParams", "lib", "FIELD_IDS"]

@@ -18,6 +18,7 @@
 #include "../../include/qsa.h"
 #include "qsa_kernels.h"
 #include "qsa_linear.h"
+#include "qsa_dirichlet.h"
 #include "qsa_adjoint.h"
 
 using namespace qsa;
@@ -118,6 +119,7 @@ void adjoint_layout(const qsa_params& p, size_t& off, AdjLayout& A) {
 // steps in flight, lane k of a group works in set k.
 struct SetLayout {
   size_t pl[4], pl2[4];
+  size_t qw[2];   // plasma relative weights of the two buffer sets (plasma_weights)
   size_t cell_of, count, bsum, prow, ppart;
   size_t src, fields, half, dep, rowspec, colout, jring, jz, bring, ode;
   size_t ring;   // slab ring of the deposits this set receives from the lane before it
@@ -132,6 +134,7 @@ struct SetLayout {
 struct Layout {
   size_t twx, twy, kx2, kdx, ky2, kdy;
   size_t tmpl[4];
+  size_t tmpl_qw;                   // template relative weights (plasma_weights)
   int nset;                         // working sets (beam steps in flight)
   SetLayout set[QSA_MAX_PIPELINE];
   size_t rowoff[QSA_MAX_SPECIES];   // slab partition of the sorted beam (pipelining)
@@ -176,11 +179,13 @@ Layout make_layout(const qsa_params& p) {
   L.kdy = c.take(p.ny * rs);
   // plasma x, y in float64 for either precision; u_x, u_y in R
   for (int i = 0; i < 4; ++i) L.tmpl[i] = c.take(p.n_plasma * (i < 2 ? 8 : rs));
+  L.tmpl_qw = p.plasma_weights ? c.take(p.n_plasma * rs) : 0;
   L.nset = pipeline_depth(p);
   for (int k = 0; k < L.nset; ++k) {
     SetLayout& S = L.set[k];
     for (int i = 0; i < 4; ++i) S.pl[i] = c.take(p.n_plasma * (i < 2 ? 8 : rs));
     for (int i = 0; i < 4; ++i) S.pl2[i] = c.take(p.n_plasma * (i < 2 ? 8 : rs));
+    for (int i = 0; i < 2; ++i) S.qw[i] = p.plasma_weights ? c.take(p.n_plasma * rs) : 0;
     S.cell_of = c.take(p.n_plasma * sizeof(int));
     S.count = c.take(nperp * sizeof(int));
     S.bsum = c.take(256 * sizeof(int));
@@ -259,6 +264,7 @@ const char* validate(const qsa_params* p) {
   if (p->adjoint_steps < 0 || p->adjoint_steps > 1024) return "adjoint_steps must be in [0, 1024]";
   if (p->ckpt_every < 0 || p->ckpt_every > p->nxi) return "ckpt_every must be in [0, nxi]";
   if (p->no_field_pack != 0 && p->no_field_pack != 1) return "no_field_pack must be 0 or 1";
+  if (p->plasma_weights != 0 && p->plasma_weights != 1) return "plasma_weights must be 0 or 1";
   for (int s = 0; s < p->n_species; ++s) {
     if (p->beam_capacity[s] < 0 || p->beam_capacity[s] > INT32_MAX) return "beam capacity must be in [0, 2^31)";
     if (!(p->species[s].M > 0)) return "species mass must be > 0";
@@ -280,6 +286,7 @@ struct qsa_ctx {
   hipStream_t user = nullptr;     // the caller's stream
   hipStream_t stream = nullptr;   // the library's work stream (ordered after `user` per call)
   hipStream_t bstream = nullptr;  // beam work of steps in flight, overlapping the slice loop
+  int beside_blocks = 0;          // workgroups per beam launch beside the slice loop (0: the work's)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipEvent_t gfork[QSA_GEV] = {}, gdone[QSA_GEV] = {};   // slice loop -> beam work -> slice loop
   hipGraphExec_t gx_step = nullptr, gx_sweep = nullptr;   // captured beam step / sweep
@@ -356,6 +363,7 @@ struct qsa_ctx {
     if (stream) (void)hipStreamDestroy(stream);
   }
 };
+
 
 // A batch: the slice loops of several contexts run as lanes of the same
 // launches; beam deposits and pushes run per context on the batch's stream.
@@ -617,13 +625,16 @@ struct Engine {
     return QSA_OK;
   }
 
-  // Deposit the slabs [jlo, jhi) into src (on stream st).
-  static qsa_status deposit_slabs(qsa_ctx* c, const Geo<R>& g, hipStream_t st, R* src, int jlo, int jhi) {
+  // Deposit the slabs [jlo, jhi) into src (on stream st), with at most
+  // max_blocks workgroups per launch (0: one per cell row).
+  static qsa_status deposit_slabs(qsa_ctx* c, const Geo<R>& g, hipStream_t st, R* src, int jlo, int jhi,
+                                  int max_blocks = 0) {
     const BeamDepArgs<R> a = beam_dep_args(c);
     for (int colour = 0; colour < 4; ++colour) {
       const int nb = beam_colour_rows(jlo, jhi, c->p.ny, colour);
+      const int grid = (max_blocks > 0) ? std::min(nb, max_blocks) : nb;
       if (nb > 0)
-        QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_beam_rows<R>, dim3(nb), dim3(256), 2 * 2 * 4 * g.nx * sizeof(double),
+        QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_beam_rows<R>, dim3(grid), dim3(256), 2 * 2 * 4 * g.nx * sizeof(double),
                    st, g, a, src, colour, jlo, jhi);
     }
     HIP_OK(hipGetLastError());
@@ -688,7 +699,9 @@ struct Engine {
       a.pos[1][i] = c->at<double>(S.pl2[i]);
       a.mom[0][i] = c->at<R>(S.pl[2 + i]);
       a.mom[1][i] = c->at<R>(S.pl2[2 + i]);
+      a.qw[i] = p.plasma_weights ? c->at<R>(S.qw[i]) : nullptr;
     }
+    a.tqw = p.plasma_weights ? c->at<R>(L.tmpl_qw) : nullptr;
     a.twx = c->at<C2<R>>(L.twx);
     a.twy = c->at<C2<R>>(L.twy);
     a.kx2 = c->at<R>(L.kx2);
@@ -780,8 +793,8 @@ struct Engine {
     d.ctpt = (ct == 16 || ct == 32 || ct == 64) ? ct : 0;
     d.rt_rows = std::min(256, std::max(64, d.nx / 2));   // two row pairs per block from nx = 256
     if (rt >= row_tpt(d.nx) && rt % row_tpt(d.nx) == 0 && rt <= 256) d.rt_rows = rt;
-    d.nt = std::max(64, std::min(256, (d.per_row + 63) / 64 * 64));
-    if (nt == 64 || nt == 128 || nt == 256) d.nt = nt;
+    d.nt = std::max(64, std::min(PlasmaBlock<R>::MAX, (d.per_row + 63) / 64 * 64));
+    if (nt == 64 || nt == 128 || nt == 256 || (nt == 512 && PlasmaBlock<R>::MAX >= 512)) d.nt = nt;
     d.rows_r2c = 0;
     d.smem_rows = 0;
     for (int m = 0; m < 3; ++m) {
@@ -906,7 +919,8 @@ struct Engine {
     for (int s = 0; s < c->p.n_species; ++s) {
       if (c->beam_n[s] == 0) continue;
       const BeamArgs<R> a = beam_args(c, g, s);
-      const int blocks = (int)std::min<int64_t>(QSA_PUSH_BLOCKS, (a.n + 255) / 256);
+      const int grid = (c->beside_blocks > 0) ? c->beside_blocks : QSA_PUSH_BLOCKS;
+      const int blocks = (int)std::min<int64_t>(grid, (a.n + 255) / 256);
       QSA_LAUNCH(c, QSA_K_BEAM_PUSH, k_beam_push_keys<R>, dim3(blocks), dim3(256), 0, st, g, a,
                  (const int*)da.perm[s], da.doff[s], k0, k1);
     }
@@ -926,16 +940,17 @@ struct Engine {
   // drift can take one out of the slices its push waits for.  Equal to
   // sweep() + push() up to the order of the deposit's additions.
   static qsa_status step_beside(qsa_ctx* c) {
-    const qsa_status st = step_beside_body(c);
+    hipStream_t bs = c->bstream;
+    const qsa_status st = step_beside_body(c, bs);
     if (st != QSA_OK) {
       // an early exit: no later call may overlap the beam work enqueued
-      (void)hipStreamSynchronize(c->bstream);
+      (void)hipStreamSynchronize(bs);
       if (c->sticky == QSA_OK) c->sticky = st;
     }
     return st;
   }
 
-  static qsa_status step_beside_body(qsa_ctx* c) {
+  static qsa_status step_beside_body(qsa_ctx* c, hipStream_t bs) {
     const qsa_params& p = c->p;
     const Geo<R> g = geo(p);
     static_assert(QSA_BEAM_AHEAD >= 2, "a chunk's deposit waits for the push of the chunk AHEAD before it");
@@ -949,10 +964,9 @@ struct Engine {
     const int C = QSA_BEAM_CHUNK, nch = (p.nxi + C - 1) / C;
     const int64_t keys_per_slab = (int64_t)p.ny * (p.nx / QSA_BEAM_XCHUNK);
     const int64_t key_end = (int64_t)p.nxi * keys_per_slab + 1;   // past the left-the-box key
-    hipStream_t bs = c->bstream;
     auto chunk_end = [&](int ch) { return std::min(p.nxi, (ch + 1) * C); };
     auto deposit = [&](int ch) -> qsa_status {
-      qsa_status s = deposit_slabs(c, g, bs, src, ch * C, chunk_end(ch));
+      qsa_status s = deposit_slabs(c, g, bs, src, ch * C, chunk_end(ch), c->beside_blocks);
       if (s != QSA_OK) return s;
       HIP_OK(hipEventRecord(c->gdone[ch % QSA_GEV], bs));
       return QSA_OK;
@@ -1130,6 +1144,27 @@ struct Engine {
       for (int64_t i = 0; i < m; ++i) tmp[i] = (R)src[o + i];
       HIP_OK(hipMemcpyAsync(reinterpret_cast<R*>(dst) + o, tmp.data(), m * sizeof(R),
                             hipMemcpyHostToDevice, c->stream));
+      HIP_OK(hipStreamSynchronize(c->stream));
+    }
+    return QSA_OK;
+  }
+
+  // float64 values times `scale` -> working precision at workspace offset off
+  static qsa_status upload_scaled(qsa_ctx* c, const double* src, size_t off, int64_t n, int on_device,
+                                  double scale) {
+    if (n == 0) return QSA_OK;
+    R* dst = c->at<R>(off);
+    if (on_device) {
+      hipLaunchKernelGGL(k_scaled_from_f64<R>, dim3(fill_blocks(n)), dim3(256), 0, c->stream, src, dst, scale, n);
+      HIP_OK(hipGetLastError());
+      return QSA_OK;
+    }
+    const int64_t chunk = 1 << 22;
+    std::vector<R> tmp((size_t)std::min<int64_t>(n, chunk));
+    for (int64_t o = 0; o < n; o += chunk) {
+      const int64_t m = std::min<int64_t>(chunk, n - o);
+      for (int64_t i = 0; i < m; ++i) tmp[i] = (R)(src[o + i] * scale);
+      HIP_OK(hipMemcpyAsync(dst + o, tmp.data(), m * sizeof(R), hipMemcpyHostToDevice, c->stream));
       HIP_OK(hipStreamSynchronize(c->stream));
     }
     return QSA_OK;
@@ -1635,7 +1670,34 @@ qsa_status qsa_load_plasma(qsa_ctx* c, const double* x, const double* y, const d
         [&] { return Engine<float>::upload(c, arr[i], c->ws + c->L.tmpl[i], n, on_device, i < 2); });
     if (st != QSA_OK) return st;
   }
+  if (c->p.plasma_weights) {
+    // uniform until qsa_load_plasma_weights
+    qsa_status st = dispatch(
+        c, [&] { return Engine<double>::fill(c, c->at<double>(c->L.tmpl_qw), n, 1.0); },
+        [&] { return Engine<float>::fill(c, c->at<float>(c->L.tmpl_qw), n, 1.0f); });
+    if (st != QSA_OK) return st;
+  }
   c->plasma_loaded = true;
+  c->drop_graphs();
+  return leave(c);
+}
+
+qsa_status qsa_load_plasma_weights(qsa_ctx* c, const double* w, int64_t n, int32_t on_device) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (!c->p.plasma_weights) return fail(c, QSA_E_STATE, "the context keeps no plasma weights (plasma_weights = 0)");
+  if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
+  if (n != c->p.n_plasma) return fail(c, QSA_E_INVALID, "weight count differs from n_plasma");
+  if (!w) return fail(c, QSA_E_INVALID, "null weight array");
+  if (!on_device)
+    for (int64_t i = 0; i < n; ++i)
+      if (!std::isfinite(w[i]) || w[i] < 0) return fail(c, QSA_E_NONFINITE, "plasma weights must be finite and >= 0");
+  qsa_status st0 = enter(c);
+  if (st0 != QSA_OK) return st0;
+  const double scale = 1.0 / c->p.plasma_w;
+  qsa_status st = dispatch(c, [&] { return Engine<double>::upload_scaled(c, w, c->L.tmpl_qw, n, on_device, scale); },
+                           [&] { return Engine<float>::upload_scaled(c, w, c->L.tmpl_qw, n, on_device, scale); });
+  if (st != QSA_OK) return st;
   c->drop_graphs();
   return leave(c);
 }
@@ -1786,8 +1848,9 @@ qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value) {
     return QSA_OK;
   }
   if (option == QSA_OPT_PLASMA_THREADS) {
-    if (value != 0 && value != 64 && value != 128 && value != 256)
-      return fail(c, QSA_E_INVALID, "plasma threads must be 0, 64, 128 or 256");
+    const bool f32 = c->p.precision == QSA_FP32;
+    if (value != 0 && value != 64 && value != 128 && value != 256 && !(f32 && value == 512))
+      return fail(c, QSA_E_INVALID, "plasma threads must be 0, 64, 128, 256 (or 512 in float32)");
     c->tune_nt = (int)value;
     c->drop_graphs();
     return QSA_OK;
@@ -1803,6 +1866,11 @@ qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value) {
   if (option == QSA_OPT_BEAM_BESIDE) {
     if (value != 0 && value != 1) return fail(c, QSA_E_INVALID, "beam beside: 0 or 1");
     c->beam_beside = value != 0;
+    return QSA_OK;
+  }
+  if (option == QSA_OPT_BESIDE_BLOCKS) {
+    if (value < 0 || value > 65536) return fail(c, QSA_E_INVALID, "beside blocks: 0 .. 65536");
+    c->beside_blocks = (int)value;
     return QSA_OK;
   }
   if (option == QSA_OPT_COL_THREADS) {
@@ -1842,9 +1910,10 @@ qsa_status qsa_autotune(qsa_ctx* c, double* ms_per_step) {
   st = run(depth0, &best);   // warm-up: first launches of every kernel
   if (st == QSA_OK) st = run(depth0, &best);
   // threads per plasma-row block
-  const int nts[3] = {64, 128, 256};
+  const int nts[4] = {64, 128, 256, 512};
+  const int n_nt = (c->p.precision == QSA_FP32) ? 4 : 3;
   int best_nt = c->tune_nt;
-  for (int k = 0; k < 3 && st == QSA_OK; ++k) {
+  for (int k = 0; k < n_nt && st == QSA_OK; ++k) {
     c->tune_nt = nts[k];
     if ((st = run(depth0, &t)) == QSA_OK && t < best) {
       best = t;
@@ -1904,6 +1973,8 @@ qsa_status qsa_adjoint_sweep(qsa_ctx* c, int32_t n_steps, int32_t n_bins, const 
   if (!c) return QSA_E_INVALID;
   if (c->sticky != QSA_OK) return c->sticky;
   if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
+  if (c->p.plasma_weights)
+    return fail(c, QSA_E_INVALID, "the adjoint sweep takes a plasma of one weight (plasma_weights = 0)");
   const AdjLayout& A = c->L.adj;
   if (A.steps <= 0 || n_steps < 0 || n_steps > A.steps)
     return fail(c, QSA_E_INVALID, "n_steps exceeds the adjoint_steps the context was created with");
@@ -1953,14 +2024,25 @@ qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value) {
     *value = c->beam_beside ? 1 : 0;
     return QSA_OK;
   }
+  if (option == QSA_OPT_BESIDE_BLOCKS) {
+    *value = c->beside_blocks;
+    return QSA_OK;
+  }
   if (option == QSA_OPT_PLASMA_THREADS || option == QSA_OPT_ROW_THREADS || option == QSA_OPT_COL_THREADS) {
-    typename Engine<double>::Dims d;
-    Engine<double>::add_dims(d, c->p);
     const qsa_params* ps[1] = {&c->p};
-    Engine<double>::finish_dims(d, ps, 1, c->tune_nt, c->tune_rt, c->tune_ct);
-    *value = (option == QSA_OPT_PLASMA_THREADS) ? d.nt
-             : (option == QSA_OPT_ROW_THREADS)  ? d.rt_rows
-                                                : col_tpt(c->p.ny, d.ctpt);
+    int nt = 0, rt = 0, ctpt = 0;
+    if (c->p.precision == QSA_FP32) {
+      typename Engine<float>::Dims d;
+      Engine<float>::add_dims(d, c->p);
+      Engine<float>::finish_dims(d, ps, 1, c->tune_nt, c->tune_rt, c->tune_ct);
+      nt = d.nt, rt = d.rt_rows, ctpt = d.ctpt;
+    } else {
+      typename Engine<double>::Dims d;
+      Engine<double>::add_dims(d, c->p);
+      Engine<double>::finish_dims(d, ps, 1, c->tune_nt, c->tune_rt, c->tune_ct);
+      nt = d.nt, rt = d.rt_rows, ctpt = d.ctpt;
+    }
+    *value = (option == QSA_OPT_PLASMA_THREADS) ? nt : (option == QSA_OPT_ROW_THREADS) ? rt : col_tpt(c->p.ny, ctpt);
     return QSA_OK;
   }
   return QSA_E_INVALID;
@@ -2043,6 +2125,54 @@ qsa_status qsa_linear_model(int32_t n_inst, int32_t nxi, double dxi, double dtau
                      n0, out,
                      n_out, psi_out);
   return hipGetLastError() == hipSuccess ? QSA_OK : QSA_E_DEVICE;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename R>
+qsa_status dirichlet_launch(int n_grid, int nx, int ny, double dx, double dy, double kappa2, const void* f,
+                            void* u, hipStream_t st) {
+  const int Mx = 2 * (nx + 1);
+  const int lgx = ilog2(Mx);
+  const double inv_lx = 1.0 / ((nx + 1) * dx);
+  const int64_t nrows = (int64_t)n_grid * ny;
+  const int64_t bx = ((nrows + 1) / 2 + 256 / dst_tpt(Mx) - 1) / (256 / dst_tpt(Mx));
+  if (ny == 1) {
+    hipLaunchKernelGGL(k_dst_rows<R>, dim3((unsigned)bx), dim3(256), dst_lds<R>(Mx), st, nrows, nx, lgx,
+                       (const R*)f, (R*)u, 2.0 / (nx + 1), 1, inv_lx, kappa2);
+    return hipGetLastError() == hipSuccess ? QSA_OK : QSA_E_DEVICE;
+  }
+  const int My = 2 * (ny + 1);
+  const int64_t tr = (int64_t)n_grid * ((nx + 1) / 2);
+  const int64_t by = (tr + 256 / dst_tpt(My) - 1) / (256 / dst_tpt(My));
+  hipLaunchKernelGGL(k_dst_rows<R>, dim3((unsigned)bx), dim3(256), dst_lds<R>(Mx), st, nrows, nx, lgx,
+                     (const R*)f, (R*)u, 1.0, 0, inv_lx, kappa2);
+  hipLaunchKernelGGL(k_dst_cols<R>, dim3((unsigned)by), dim3(256), dst_lds<R>(My), st, n_grid, nx, ny, ilog2(My),
+                     (R*)u, inv_lx, 1.0 / ((ny + 1) * dy), kappa2, 2.0 / (ny + 1));
+  hipLaunchKernelGGL(k_dst_rows<R>, dim3((unsigned)bx), dim3(256), dst_lds<R>(Mx), st, nrows, nx, lgx,
+                     (const R*)u, (R*)u, 2.0 / (nx + 1), 0, inv_lx, kappa2);
+  return hipGetLastError() == hipSuccess ? QSA_OK : QSA_E_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+qsa_status qsa_dirichlet_solve(int32_t precision, int32_t n_grid, int32_t nx, int32_t ny, double dx, double dy,
+                               double kappa2, const void* f, void* u, void* hip_stream) {
+  if (precision != QSA_FP64 && precision != QSA_FP32) return QSA_E_INVALID;
+  if (n_grid < 0 || !pow2(nx + 1) || nx + 1 < 2 || nx + 1 > kMaxN) return QSA_E_INVALID;
+  if (!(ny == 1 || (pow2(ny + 1) && ny + 1 >= 2 && ny + 1 <= kMaxN))) return QSA_E_INVALID;
+  if (!(dx > 0.0) || !std::isfinite(dx) || !(dy > 0.0) || !std::isfinite(dy)) return QSA_E_INVALID;
+  if (!(kappa2 >= 0.0) || !std::isfinite(kappa2)) return QSA_E_INVALID;
+  if ((int64_t)n_grid * ny * nx > ((int64_t)1 << 34)) return QSA_E_INVALID;
+  if (n_grid == 0) return QSA_OK;
+  if (!f || !u) return QSA_E_INVALID;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  return precision == QSA_FP64 ? dirichlet_launch<double>(n_grid, nx, ny, dx, dy, kappa2, f, u, st)
+                               : dirichlet_launch<float>(n_grid, nx, ny, dx, dy, kappa2, f, u, st);
 }
 
 qsa_status qsa_sync(qsa_ctx* c) {

@@ -59,6 +59,7 @@ struct Lane {
   const R* src;         // beam sources [4][nxi][ny][nx]
   const double* tpos[2];  // plasma template x, y (float64 in either precision)
   const R* tmom[2];       // and u_x, u_y
+  const R* tqw;           // and its weights relative to plasma_w (null: all 1)
   const C2<R>* twx;     // transform tables
   const C2<R>* twy;
   const R* kx2;
@@ -68,6 +69,7 @@ struct Lane {
   int* err;             // sticky device error flags
   double* pos[2][2];    // plasma x, y (float64), two buffer sets (sorts ping-pong)
   R* mom[2][2];         // plasma u_x, u_y, the same two sets
+  R* qw[2];             // plasma relative weights, the same two sets (or null)
   int* cell_of;         // sort scratch
   int* count;
   int* bsum;
@@ -133,6 +135,13 @@ __global__ void k_from_f64(const double* __restrict__ src, R* __restrict__ dst, 
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t s = (int64_t)gridDim.x * blockDim.x;
   for (; i < n; i += s) dst[i] = (R)src[i];
+}
+
+template <typename R>
+__global__ void k_scaled_from_f64(const double* __restrict__ src, R* __restrict__ dst, double scale, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t s = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += s) dst[i] = (R)(src[i] * scale);
 }
 
 template <typename R>
@@ -627,6 +636,7 @@ struct PlasmaArgs {
   R* uy;
   int np;
   R q;                // -w/(dx dy): rho - J_z per particle per unit area
+  const R* qw;        // per particle: its weight relative to w (null: all 1)
   R* dep0;
   R* dep1;
   R* dep2;
@@ -653,6 +663,7 @@ __device__ __forceinline__ PlasmaArgs<R> plasma_args(const Lane<R>& L, int j) {
   a.uy = L.mom[set][1];
   a.np = L.np;
   a.q = L.q;
+  a.qw = L.qw[set];
   a.dep0 = L.dep;
   a.dep1 = L.dep + g.nperp;
   a.dep2 = L.dep + 2 * g.nperp;
@@ -860,14 +871,23 @@ __device__ __forceinline__ void row_tile_add(const Geo<R>& g, double* tile, int 
 //             psi~^{j+1} = 3 psi^j - 3 psi^{j-1} + psi^{j-2}; predictor pass
 //             `pass` of the slice (the first gathers every field and caches
 //             the parts of the step B_perp does not enter)
+// Threads per plasma cell-row block at most: the float32 kernels fit 512
+// (two wavefronts per SIMD from one block per CU, within 128 VGPRs); the
+// float64 predictor needs more registers than 512 threads allow.
+template <typename R>
+struct PlasmaBlock {
+  static constexpr int MAX = sizeof(R) == 4 ? 512 : 256;
+};
+
 template <typename R, int MODE>
 __device__ __forceinline__ void plasma_particle(const Geo<R>& g, const PlasmaArgs<R>& a, int p, int pass,
                                                 double& px, double& py, R (&v)[PlasmaNC<MODE>::NC]) {
   constexpr int NC = PlasmaNC<MODE>::NC;
+  const R q = a.qw ? a.q * a.qw[p] : a.q;
   if constexpr (MODE == PL_DEP_S) {
     px = a.x[p];
     py = a.y[p];
-    v[0] = a.q;
+    v[0] = q;
   } else if constexpr (MODE == PL_DEP_J) {
     px = a.x[p];
     py = a.y[p];
@@ -876,7 +896,7 @@ __device__ __forceinline__ void plasma_particle(const Geo<R>& g, const PlasmaArg
     const R G = R(1) + gather(a.F0[0], s);
     if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
     const R gam = (R(1) + ux * ux + uy * uy + G * G) / (R(2) * G);
-    const R qg = a.q / G;
+    const R qg = q / G;
     v[0] = qg * ux;
     v[1] = qg * uy;
     v[(NC > 2) ? 2 : 0] = qg * (gam - G);
@@ -889,7 +909,7 @@ __device__ __forceinline__ void plasma_particle(const Geo<R>& g, const PlasmaArg
     const Stencil<R> s = stencil2(g, px, py);
     const R G = R(1) + gather(a.psit, s);
     if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
-    const R qg = a.q / G;
+    const R qg = q / G;
     v[0] = qg * uxn;
     v[(NC > 1) ? 1 : 0] = qg * uyn;
   }
@@ -899,7 +919,8 @@ __device__ __forceinline__ void plasma_particle(const Geo<R>& g, const PlasmaArg
 // row r (state sorted by cell) and adds them to its LDS tile of node rows
 // r-1 .. r+2 with LDS atomics; the tile is written out as partial rows.
 template <typename R, int MODE>
-__global__ void __launch_bounds__(256) k_plasma_rows(const Lane<R>* __restrict__ lanes, int tick, int pass) {
+__global__ void __launch_bounds__(PlasmaBlock<R>::MAX) k_plasma_rows(const Lane<R>* __restrict__ lanes, int tick,
+                                                                     int pass) {
   constexpr int NC = PlasmaNC<MODE>::NC;
   int lane, r;
   lane_block(lane, r);
@@ -1071,6 +1092,7 @@ struct PlasmaSrc {
   const double* y;
   const R* ux;
   const R* uy;
+  const R* qw;   // relative weights (null: none kept)
 };
 template <typename R>
 struct PlasmaDst {
@@ -1078,18 +1100,19 @@ struct PlasmaDst {
   double* y;
   R* ux;
   R* uy;
+  R* qw;
 };
 template <typename R>
 __device__ __forceinline__ void sort_buffers(const Lane<R>& L, int j, PlasmaSrc<R>& A, PlasmaDst<R>& B) {
   const int m = j / QSA_SORT_EVERY;
   if (m == 0) {
-    A = PlasmaSrc<R>{L.tpos[0], L.tpos[1], L.tmom[0], L.tmom[1]};
+    A = PlasmaSrc<R>{L.tpos[0], L.tpos[1], L.tmom[0], L.tmom[1], L.tqw};
   } else {
     const int a = (m - 1) & 1;
-    A = PlasmaSrc<R>{L.pos[a][0], L.pos[a][1], L.mom[a][0], L.mom[a][1]};
+    A = PlasmaSrc<R>{L.pos[a][0], L.pos[a][1], L.mom[a][0], L.mom[a][1], L.qw[a]};
   }
   const int b = m & 1;
-  B = PlasmaDst<R>{L.pos[b][0], L.pos[b][1], L.mom[b][0], L.mom[b][1]};
+  B = PlasmaDst<R>{L.pos[b][0], L.pos[b][1], L.mom[b][0], L.mom[b][1], L.qw[b]};
 }
 
 template <typename R>
@@ -1204,6 +1227,7 @@ __global__ void __launch_bounds__(256) k_sort_scatter(const Lane<R>* __restrict_
   y2[d] = y[p];
   ux2[d] = ux[p];
   uy2[d] = uy[p];
+  if (B.qw) B.qw[d] = A.qw[p];
 }
 
 // -------------------------------------------------------------------- beam
@@ -1567,6 +1591,13 @@ __host__ __device__ __forceinline__ int beam_colour_rows(int jlo, int jhi, int n
   return (j0 < jhi) ? ((jhi - j0 + 1) >> 1) * nyc : 0;
 }
 
+// One cell row (jb, lb) of a colour pass: tile, particles, store.
+template <typename R>
+__device__ __forceinline__ void beam_row(const Geo<R>& g, const BeamDepArgs<R>& a, R* __restrict__ src,
+                                         double* tile, int jb, int lb);
+
+// Block k of a launch of gridDim.x blocks takes the colour's rows k,
+// k + gridDim.x, ... (one row per block when the grid covers them all).
 template <typename R>
 __global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a, R* __restrict__ src, int colour,
                                                    int jlo, int jhi) {
@@ -1574,10 +1605,20 @@ __global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a, R
   double* tile = reinterpret_cast<double*>(smem_raw);   // float64 for either precision
   const int cl = colour & 1;
   const int nyc = (g.ny == 1) ? 1 : (g.ny >> 1);
-  const int jj = blockIdx.x / nyc, ll = blockIdx.x - jj * nyc;
-  const int jb = beam_colour_first(jlo, colour) + 2 * jj;
-  const int lb = (g.ny == 1) ? 0 : 2 * ll + cl;
-  if (jb >= jhi || jb >= g.nxi) return;
+  const int nb = beam_colour_rows(jlo, jhi, g.ny, colour);
+  for (int k = blockIdx.x; k < nb; k += gridDim.x) {
+    const int jj = k / nyc, ll = k - jj * nyc;
+    const int jb = beam_colour_first(jlo, colour) + 2 * jj;
+    const int lb = (g.ny == 1) ? 0 : 2 * ll + cl;
+    if (jb >= jhi || jb >= g.nxi) continue;   // uniform over the block
+    beam_row<R>(g, a, src, tile, jb, lb);
+    __syncthreads();   // the tile is reused by the next row
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void beam_row(const Geo<R>& g, const BeamDepArgs<R>& a, R* __restrict__ src,
+                                         double* tile, int jb, int lb) {
   const int b = jb * g.ny + lb;
   const int tn = 2 * 2 * 4 * g.nx;
   for (int t = threadIdx.x; t < tn; t += blockDim.x) tile[t] = 0.0;

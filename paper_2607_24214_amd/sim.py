@@ -33,12 +33,15 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
                 species: Sequence, n_plasma: int, plasma_w: float,
                 beam_capacity: Sequence[int], precision: str = "f64", n_corr: int = 3,
                 kappa2: float = 0.75, pipeline: int = 1, adjoint_steps: int = 0,
-                ckpt_every: int = 0, field_pack: bool = True) -> L.QSAParams:
+                ckpt_every: int = 0, field_pack: bool = True,
+                plasma_weights: bool = False) -> L.QSAParams:
     """species: sequence of (Z, M); pipeline: beam steps in flight (1 = off);
     adjoint_steps: most steps qsa_adjoint_sweep differentiates (0 = none);
     ckpt_every: the adjoint's plasma checkpoint stride in slices (0 = 16);
     field_pack: keep the push's fields packed for every slice (without steps
-    in flight; False saves 32-48 bytes per cell)."""
+    in flight; False saves 32-48 bytes per cell); plasma_weights: keep a
+    weight per plasma macro-particle (Sim.load_plasma loads them when the
+    template's "w" is an array)."""
     p = L.QSAParams()
     p.nx, p.ny, p.nxi = nx, ny, nxi
     p.precision = _PREC[precision]
@@ -50,6 +53,7 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
     p.adjoint_steps = int(adjoint_steps)
     p.ckpt_every = int(ckpt_every)
     p.no_field_pack = 0 if field_pack else 1
+    p.plasma_weights = 1 if plasma_weights else 0
     for i, (Z, M) in enumerate(species):
         p.species[i].Z = int(Z)
         p.species[i].M = float(M)
@@ -67,7 +71,8 @@ def params_from_workload(wl, precision: Optional[str] = None,
     return make_params(wl.nx, wl.ny, wl.nxi, wl.dx, wl.dy, wl.dxi, wl.dt,
                        [(s.Z, s.M) for s in wl.species], wl.n_plasma,
                        wl.dx * wl.dy / wl.plasma_ppc, caps, precision or wl.precision,
-                       wl.n_corr, wl.kappa2, pipeline, adjoint_steps, min(int(ck), wl.nxi), field_pack)
+                       wl.n_corr, wl.kappa2, pipeline, adjoint_steps, min(int(ck), wl.nxi), field_pack,
+                       getattr(wl, "plasma_w_spread", 0.0) > 0.0)
 
 
 class Sim:
@@ -113,11 +118,20 @@ class Sim:
 
     # ------------------------------------------------------------------
     def load_plasma(self, plasma: Dict):
+        """The plasma template; a "w" array (one weight per particle, in the
+        units of plasma_w) needs a context made with plasma_weights."""
         arrs = [_f64(plasma[k]) for k in ("x", "y", "ux", "uy")]
         n = arrs[0][0].shape[0]
         on_dev = arrs[0][1]
+        w = plasma.get("w")
+        per_particle = w is not None and (w.dim() > 0 if torch.is_tensor(w) else np.ndim(w) > 0)
+        if per_particle and not self.params.plasma_weights:
+            raise ValueError("per-particle plasma weights need a context made with plasma_weights")
         self._check(self.lib.qsa_load_plasma(self.ctx, *[C.c_void_p(_ptr(a)) for a, _ in arrs],
                                              n, on_dev))
+        if per_particle:
+            wa, wdev = _f64(w)
+            self._check(self.lib.qsa_load_plasma_weights(self.ctx, C.c_void_p(_ptr(wa)), wa.shape[0], wdev))
 
     def load_beam(self, s: int, beam: Dict):
         arrs = [_f64(beam[k]) for k in ("x", "y", "xi", "ux", "uy", "uz", "w")]
@@ -165,6 +179,11 @@ class Sim:
         """One step at a time: run the beam deposit and push beside the slice
         loop on a second stream (default) or after it."""
         self._check(self.lib.qsa_set_option(self.ctx, 5, int(bool(enable))))
+
+    def set_beside_blocks(self, n: int):
+        """Workgroups per launch of the beam work beside the slice loop (0 =
+        as many as the work has)."""
+        self._check(self.lib.qsa_set_option(self.ctx, 6, int(n)))
 
     def set_shapes(self, plasma_threads: int = 0, row_threads: int = 0, col_threads: int = 0):
         """Launch shapes (0 = default): threads per plasma-row block, per
@@ -369,6 +388,29 @@ def linear_model(gamma, n0, dxi: float, taus, dtau: float, device=None):
     if st != L.QSA_OK:
         raise L.QSAError(st, "qsa_linear_model: arguments out of range or launch failed")
     return n_out, p_out
+
+
+def dirichlet_solve(f: torch.Tensor, dx: float, dy: float, kappa2: float = 0.0,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Conducting-wall solve (qsa_dirichlet_solve) of (-lap_perp + kappa2) u = f
+    on the interior nodes: f a device tensor [..., ny, nx] (float64 or
+    float32; nx + 1 and ny + 1, unless ny = 1, powers of two); returns u of
+    the same shape and dtype (out may be f)."""
+    if not f.is_cuda or f.dtype not in (torch.float64, torch.float32) or f.dim() < 2:
+        raise ValueError("f: a float64 or float32 device tensor [..., ny, nx]")
+    f = f.contiguous()
+    ny, nx = int(f.shape[-2]), int(f.shape[-1])
+    n_grid = int(f.numel() // max(nx * ny, 1))
+    u = torch.empty_like(f) if out is None else out
+    if u.shape != f.shape or u.dtype != f.dtype or not u.is_contiguous():
+        raise ValueError("out: a contiguous tensor of f's shape and dtype")
+    prec = 0 if f.dtype == torch.float64 else 1
+    stream = torch.cuda.current_stream(f.device).cuda_stream
+    st = L.lib().qsa_dirichlet_solve(prec, n_grid, nx, ny, float(dx), float(dy), float(kappa2),
+                                     C.c_void_p(f.data_ptr()), C.c_void_p(u.data_ptr()), C.c_void_p(stream))
+    if st != L.QSA_OK:
+        raise L.QSAError(st, "qsa_dirichlet_solve: arguments out of range or launch failed")
+    return u
 
 
 class FieldEnergy(torch.autograd.Function):

@@ -5,8 +5,8 @@ contains none of the method's arithmetic.
 """
 from .configs import (Species, Workload, slab_electron, slab_pair, cube256,
                       pair512, adjoint128, scan_instances, small_3d, CONFIGS)
-from .generate import plasma_template, beam_species, beam
+from .generate import plasma_template, beam_species, beam, longitudinal_profile
 
 __all__ = ["Species", "Workload", "slab_electron", "slab_pair", "cube256",
            "pair512", "adjoint128", "scan_instances", "small_3d", "CONFIGS",
-           "plasma_template", "beam_species", "beam"]
+           "plasma_template", "beam_species", "beam", "longitudinal_profile"]

@@ -28,7 +28,11 @@ class Species:
     mod_eps, mod_m: optional weight modulation (1 + mod_eps*cos(2 pi mod_m x / Lx))
     used to seed a single transverse mode;
     w_spread: random macro-particle weights, each weight times
-    (1 + w_spread (2U - 1)) with U uniform in [0, 1) (mean unchanged).
+    (1 + w_spread (2U - 1)) with U uniform in [0, 1) (mean unchanged);
+    ramp_head, ramp_tail: a longitudinal density profile instead of the flat
+    top: the density rises linearly from 0 at the head (xi = 0) to its
+    plateau over ramp_head, and falls linearly to 0 over the last ramp_tail
+    of the beam (lengths in c/omega_p; 0 = a sharp edge).
     """
     Z: int = -1
     M: float = 1.0
@@ -39,6 +43,8 @@ class Species:
     mod_eps: float = 0.0
     mod_m: int = 0
     w_spread: float = 0.0
+    ramp_head: float = 0.0
+    ramp_tail: float = 0.0
 
 
 @dataclass(frozen=True)
@@ -55,6 +61,7 @@ class Workload:
     plasma_mx: int = 2       # plasma lattice per cell along x
     plasma_my: int = 2       # ... along y (1 in a slab)
     plasma_uth: float = 0.0  # thermal spread of u_x, u_y (0 = cold)
+    plasma_w_spread: float = 0.0  # random plasma weights: w0 (1 + spread (2U - 1)), 0 = all w0
     dt: float = 5.0          # beam time step
     steps: int = 1
     seed: int = 0

@@ -29,8 +29,10 @@ def plasma_template(wl: Workload) -> Dict[str, np.ndarray]:
 
     A plasma_mx x plasma_my lattice per transverse cell at
     x = (i + (a + 1/2)/mx) dx, y = (l + (b + 1/2)/my) dy, ordered by cell
-    (row l, column i) then lattice site; all weights dx*dy/ppc (unit density).
-    Cold (u = 0) or u_x, u_y ~ N(0, u_th^2).
+    (row l, column i) then lattice site; all weights dx*dy/ppc (unit density),
+    or, with plasma_w_spread > 0, an array of random macro-particle weights
+    dx*dy/ppc (1 + spread (2U - 1)), U uniform on [0, 1) from a stream of its
+    own.  Cold (u = 0) or u_x, u_y ~ N(0, u_th^2).
     """
     mx, my = wl.plasma_mx, wl.plasma_my
     ii = np.arange(wl.nx)
@@ -50,6 +52,10 @@ def plasma_template(wl: Workload) -> Dict[str, np.ndarray]:
         ux = np.zeros(n)
         uy = np.zeros(n)
     w = wl.dx * wl.dy / (mx * my)
+    if wl.plasma_w_spread > 0.0:
+        gw = _rng(wl.seed, 0, 1)
+        return {"x": x, "y": y, "ux": ux, "uy": uy,
+                "w": w * (1.0 + wl.plasma_w_spread * (2.0 * gw.random(n) - 1.0))}
     return {"x": x, "y": y, "ux": ux, "uy": uy, "w": float(w)}
 
 
@@ -117,11 +123,28 @@ def beam_species(wl: Workload, s: int, j0: int = 0, j1: Optional[int] = None,
         if sp.w_spread > 0.0:
             gw = _rng(wl.seed, 100 + s, j)
             out["w"][sl] *= 1.0 + sp.w_spread * (2.0 * gw.random(n_slice) - 1.0)
+        if sp.ramp_head > 0.0 or sp.ramp_tail > 0.0:
+            out["w"][sl] *= longitudinal_profile(wl, s, out["xi"][sl])
     if wl.n_bins > 0:
         extent = wl.beam_slices * wl.dxi
         b = np.floor(out["xi"] / (extent / wl.n_bins)).astype(np.int32)
         out["bin"] = np.clip(b, 0, wl.n_bins - 1)
     return out
+
+
+def longitudinal_profile(wl: Workload, s: int, xi) -> np.ndarray:
+    """Beam density of species s at xi relative to its plateau: linear from
+    0 at xi = 0 to 1 at ramp_head, 1 on the plateau, linear from 1 to 0 over
+    the last ramp_tail before the beam's end (beam_slices * dxi)."""
+    sp = wl.species[s]
+    xi = np.asarray(xi, dtype=np.float64)
+    end = wl.beam_slices * wl.dxi
+    f = np.ones_like(xi)
+    if sp.ramp_head > 0.0:
+        f = np.minimum(f, xi / sp.ramp_head)
+    if sp.ramp_tail > 0.0:
+        f = np.minimum(f, (end - xi) / sp.ramp_tail)
+    return np.clip(f, 0.0, 1.0)
 
 
 def _lattice_offsets(ppc: int, three_d: bool) -> np.ndarray:

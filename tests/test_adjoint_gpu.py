@@ -43,6 +43,15 @@ def test_adjoint_matches_oracle_fp64(steps):
     assert np.abs(g - go).max() <= 1e-8 * np.abs(go).max()
 
 
+def test_adjoint_refuses_per_particle_plasma_weights():
+    import paper_2607_24214_amd as Q
+    wl = _case().with_(plasma_w_spread=0.5)
+    sim, beams = _sim(wl, steps=1)
+    with pytest.raises(Q.QSAError) as e:
+        sim.adjoint_sweep(1, AMPS, [b["bin"] for b in beams])
+    assert e.value.status == -1
+
+
 def test_adjoint_across_checkpoint_segments_pair_fp64():
     """40 slices: three checkpoint segments (the last one partial), recomputed
     in the reverse pass; an electron-positron beam (two species)."""

@@ -451,3 +451,89 @@ def test_psi_rounding_floor_on_the_dilute_pair_box():
     floor = psi_floor(wl, "f64")
     assert 0.2e-10 * scale < d, (d, scale)
     assert floor / 30 < d <= floor, (d, floor)
+
+
+def test_oracle_raises_on_quasistatic_breakdown():
+    """A dense positron beam (alpha = 5, gamma_b = 2) in the slab pulls
+    1 + psi below the threshold within the first slices: the oracle must
+    raise; the same box with alpha = 2 stays above it (its minimum of psi is
+    about -0.78)."""
+    from oracle import qsa_pic as O
+    base = W.slab_electron().with_(nx=16, nxi=32, gamma_b=2.0, steps=1)
+    dense = base.with_(species=(W.Species(Z=+1, M=1.0, alpha=5.0, ppc=2),))
+    s = O.Sim(dense, W.plasma_template(dense), W.beam(dense))
+    with pytest.raises(O.QSABreakdown):
+        s.sweep()
+    mild = base.with_(species=(W.Species(Z=+1, M=1.0, alpha=2.0, ppc=2),))
+    s = O.Sim(mild, W.plasma_template(mild), W.beam(mild))
+    s.sweep()
+    psi = O.output_fields(s.fields)["psi"]
+    assert 1.0 + float(psi.min()) > O.BREAKDOWN_G
+
+
+def _plasma_only_sweep(wl, plasma):
+    """The oracle's sweep of a plasma template with an empty beam."""
+    empty = [{k: np.zeros(0) for k in ("x", "y", "xi", "ux", "uy", "uz", "w")} for _ in wl.species]
+    s = O.Sim(wl, plasma, empty)
+    s.sweep()
+    return s.fields
+
+
+def test_plasma_weight_modulation_gives_the_closed_form_psi():
+    """Per-particle plasma weights w0 (1 + eps cos(k x_p)) on the slab's
+    lattice, at rest, no beam: at slice 0 the node density is
+    1 + eps T cos(k x_i), with T = (1/mx) sum over the lattice offsets d of a
+    node of W(d) cos(k d) (W the linear shape), so -lap psi = -eps T cos(k x)
+    gives psi = -eps T cos(k x)/k^2 exactly (the solve is spectral); E_z = 0
+    there.  A weight that is dropped, inverted or applied twice fails."""
+    wl = W.slab_electron().with_(nx=64, nxi=4)
+    pl = W.plasma_template(wl)
+    m, eps = 3, 0.1
+    L = wl.nx * wl.dx
+    k = 2.0 * math.pi * m / L
+    w = pl["w"] * (1.0 + eps * np.cos(k * pl["x"]))
+    F = _plasma_only_sweep(wl, {**pl, "w": w})
+    mx = wl.plasma_mx
+    offs = [((a + 0.5) / mx) for a in range(mx)] + [((a + 0.5) / mx - 1.0) for a in range(mx)]
+    T = sum((1.0 - abs(d)) * math.cos(k * d * wl.dx) for d in offs) / mx
+    xi = np.arange(wl.nx) * wl.dx
+    want = -eps * T * np.cos(k * xi) / k ** 2
+    psi0 = O.output_fields(F)["psi"][0, 0].numpy()
+    assert np.abs(psi0 - want).max() <= 1e-12 * np.abs(want).max()
+    # uniform weights give psi = 0 at slice 0
+    F1 = _plasma_only_sweep(wl, pl)
+    assert float(O.output_fields(F1)["psi"][0].abs().max()) < 1e-14
+
+
+def test_plasma_weights_split_and_zero_particles():
+    """Weights enter every deposit and nothing else: a template of random
+    weights equals the same template with every particle split into two
+    coincident halves (fields to 1e-12 over the whole sweep), particles of
+    weight 0 change nothing, and an array of equal weights equals the scalar
+    weight."""
+    wl = W.small_3d(8, 8, 10).with_(plasma_uth=0.05, plasma_w_spread=0.6)
+    pl = W.plasma_template(wl)
+    beams = W.beam(wl)
+    assert np.ndim(pl["w"]) == 1 and float(np.std(pl["w"])) > 0.0
+    ref = O.Sim(wl, pl, beams)
+    ref.sweep()
+    split = {k: np.concatenate([pl[k], pl[k]]) for k in ("x", "y", "ux", "uy")}
+    split["w"] = np.concatenate([pl["w"], pl["w"]]) * 0.5
+    s2 = O.Sim(wl, split, beams)
+    s2.sweep()
+    scale = float(ref.fields.abs().max())
+    assert float((s2.fields - ref.fields).abs().max()) <= 1e-12 * scale
+    rng = np.random.default_rng(5)
+    extra = {"x": rng.uniform(0, wl.nx * wl.dx, 50), "y": rng.uniform(0, wl.ny * wl.dy, 50),
+             "ux": rng.normal(0, 0.1, 50), "uy": rng.normal(0, 0.1, 50)}
+    withz = {k: np.concatenate([pl[k], extra[k]]) for k in ("x", "y", "ux", "uy")}
+    withz["w"] = np.concatenate([pl["w"], np.zeros(50)])
+    s3 = O.Sim(wl, withz, beams)
+    s3.sweep()
+    assert float((s3.fields - ref.fields).abs().max()) <= 1e-12 * scale
+    uni = W.plasma_template(wl.with_(plasma_w_spread=0.0))
+    a = O.Sim(wl, uni, beams)
+    a.sweep()
+    b = O.Sim(wl, {**uni, "w": np.full(uni["x"].size, uni["w"])}, beams)
+    b.sweep()
+    assert float((a.fields - b.fields).abs().max()) == 0.0

@@ -52,6 +52,46 @@ def test_random_beam_weights_fp64():
     _case(wl, 1, "f64", 1e-10)
 
 
+def test_ramped_beam_fp64():
+    """A longitudinal profile instead of the flat top (linear head and tail
+    ramps, with random weights on top), through two beam steps."""
+    wl = W.small_3d(32, 16, 30).with_(
+        dt=20.0, species=(W.Species(Z=-1, alpha=0.05, ppc=4, sigma_perp=1e-3, w_spread=0.3,
+                                    ramp_head=0.9, ramp_tail=0.6),))
+    _case(wl, 2, "f64", 1e-10)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_random_plasma_weights(prec, tol):
+    """Random plasma macro-particle weights (each w0 (1 + 0.6 (2U - 1))),
+    a warm plasma, through two beam steps: the weights follow the particles
+    through the sorts."""
+    wl = W.small_3d(32, 16, 20).with_(plasma_uth=0.01, plasma_w_spread=0.6, dt=20.0)
+    _case(wl, 2, prec, tol)
+
+
+def test_plasma_weights_need_the_parameter():
+    import paper_2607_24214_amd as Q
+    wl = W.small_3d(16, 16, 8).with_(plasma_w_spread=0.5)
+    pl = W.plasma_template(wl)
+    p = Q.params_from_workload(wl)
+    assert p.plasma_weights == 1
+    p0 = Q.params_from_workload(wl.with_(plasma_w_spread=0.0))
+    s = Q.Sim(p0)
+    with pytest.raises(ValueError):
+        s.load_plasma(pl)
+    s.load_plasma(W.plasma_template(wl.with_(plasma_w_spread=0.0)))
+    import ctypes as C
+    w = np.ascontiguousarray(pl["w"])
+    assert s.lib.qsa_load_plasma_weights(s.ctx, C.c_void_p(w.ctypes.data), w.size, 0) == -6   # QSA_E_STATE
+    t = Q.Sim(p)
+    t.load_plasma(pl)
+    bad = w.copy()
+    bad[3] = -1.0
+    assert t.lib.qsa_load_plasma_weights(t.ctx, C.c_void_p(bad.ctypes.data), bad.size, 0) == -5   # NONFINITE
+    assert t.lib.qsa_load_plasma_weights(t.ctx, C.c_void_p(w.ctypes.data), w.size - 1, 0) == -1   # count
+
+
 def test_3d_fp32():
     _case(W.small_3d(32, 32, 24), 1, "f32", 1e-4)
 

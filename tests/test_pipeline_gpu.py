@@ -112,6 +112,15 @@ def test_pipelined_warm_beam_fp64():
     _compare("warm beam", pip, seq, 1e-10, 1e-11)
 
 
+def test_pipelined_random_plasma_weights_fp64():
+    wl = W.small_3d(32, 16, 24).with_(dt=20.0, plasma_uth=0.01, plasma_w_spread=0.6)
+    seq, pip = _sim(wl, 1), _sim(wl, 3)
+    seq.beam_step(3)
+    pip.beam_step(3)
+    assert pip.pipeline == 3
+    _compare("plasma weights", pip, seq, 1e-10, 1e-11)
+
+
 def test_pipelined_fp32():
     wl = W.small_3d(32, 32, 24).with_(dt=20.0)
     seq, pip = _sim(wl, 1, "f32"), _sim(wl, 4, "f32")
