@@ -438,8 +438,8 @@ def run_workload(wl, precision: str, pipeline: int, steps: int, warmup: int, arg
         sim.set_beam_beside(False)
     if args.beside_blocks is not None:
         sim.set_beside_blocks(args.beside_blocks)
-    if args.col_threads or args.plasma_threads:
-        sim.set_shapes(args.plasma_threads, 0, args.col_threads)
+    if args.col_threads or args.plasma_threads or args.row_threads:
+        sim.set_shapes(args.plasma_threads, args.row_threads, args.col_threads)
     tuned = None
     if args.autotune:
         t = time.perf_counter()
@@ -552,6 +552,8 @@ def main():
                     help="let the library time its launch shapes and steps in flight first")
     ap.add_argument("--pre-steps", type=int, default=0,
                     help="untimed beam steps after the warmup (time a more evolved beam)")
+    ap.add_argument("--row-threads", type=int, default=0,
+                    help="threads per row-transform block (0 = the library's default)")
     ap.add_argument("--plasma-threads", type=int, default=0,
                     help="threads per plasma cell-row block (0 = the library's default)")
     ap.add_argument("--col-threads", type=int, default=0,

@@ -10,8 +10,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libqsa.so")
 SOURCES = [os.path.join(HERE, "csrc", "qsa.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("qsa_device.h", "qsa_kernels.h")] + \
-    [os.path.join(ROOT, "include", "qsa.h")]
 
 
 def hipcc() -> str:

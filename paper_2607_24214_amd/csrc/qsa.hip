@@ -139,11 +139,13 @@ struct Layout {
   SetLayout set[QSA_MAX_PIPELINE];
   size_t rowoff[QSA_MAX_SPECIES];   // slab partition of the sorted beam (pipelining)
   size_t doff[QSA_MAX_SPECIES];     // sort-key offsets into perm of the current deposit
+  size_t cnt_next[QSA_MAX_SPECIES]; // key counts of the beam's current positions (see keys())
   size_t key[QSA_MAX_SPECIES], perm[QSA_MAX_SPECIES];
   size_t cursor, scan64;
   size_t beam[QSA_MAX_SPECIES][8];  // x, y, ux, uy, uz, w (real), xi (double), id (int64, pipelining)
   size_t snap[QSA_MAX_SPECIES][8];  // sort target and the beam at the start of a pipelined group
   size_t err, emit, lane, pipe;
+  size_t kvalid;                    // int: cnt_next holds the key counts of the beam as it stands
   size_t diag;                      // diagnostics: 7 doubles per slice
   AdjLayout adj;                    // adjoint tapes and arrays (adjoint_steps > 0)
   size_t total;
@@ -216,8 +218,11 @@ Layout make_layout(const qsa_params& p) {
   const size_t nkeys = nrows * (p.nx / QSA_BEAM_XCHUNK) + 1;   // sort keys, the last for inert particles
   for (int s = 0; s < QSA_MAX_SPECIES; ++s) {
     const size_t cap = (s < p.n_species) ? (size_t)p.beam_capacity[s] : 0;
+    const bool used = s < p.n_species;
     L.rowoff[s] = c.take((nrows + 2) * sizeof(int64_t));
-    L.doff[s] = c.take((nkeys + 2) * sizeof(int64_t));
+    L.doff[s] = used ? c.take((nkeys + 2) * sizeof(int64_t)) : 0;
+    // key counts of the next deposit, made by the pushes beside the slice loop
+    L.cnt_next[s] = (used && L.nset == 1) ? c.take((nkeys + 2) * sizeof(int64_t)) : 0;
     L.key[s] = (L.nset > 1) ? c.take(cap * sizeof(int)) : 0;   // kept only for steps in flight
     L.perm[s] = c.take(cap * sizeof(int));
   }
@@ -235,6 +240,7 @@ Layout make_layout(const qsa_params& p) {
     }
   }
   L.err = c.take(sizeof(int));
+  L.kvalid = c.take(sizeof(int));
   L.emit = c.take(nperp * sizeof(double));
   L.diag = c.take(7 * (size_t)p.nxi * sizeof(double));
   L.lane = c.take(L.nset * sizeof(Lane<double>));
@@ -278,6 +284,18 @@ const char* validate(const qsa_params* p) {
 #define QSA_BEAM_CHUNK 8    // slabs per beam deposit and push beside the slice loop
 #define QSA_BEAM_AHEAD 2    // chunks deposited ahead of the slice loop
 #define QSA_PUSH_BLOCKS 2048   // grid of a key-range push
+// Host-side bound on the work enqueued ahead of the device: a slice loop
+// enqueues about QSA_TICK_LAUNCHES launches per tick, and the host waits
+// (spinning on an event) before it runs more than 2 QSA_THROTTLE_TICKS
+// ticks ahead.  A full hardware queue otherwise parks the enqueuing thread
+// in a blocking wait that was measured to resume only at whole seconds
+// (a 512x512x2048 step: exactly 1.000 s however fast the kernels got).
+// Graph replays cannot be throttled, so slice loops longer than
+// QSA_GRAPH_MAX_LAUNCHES launches are enqueued directly.
+#define QSA_THROTTLE_TICKS 16
+#define QSA_TEV 4
+#define QSA_TICK_LAUNCHES 26
+#define QSA_GRAPH_MAX_LAUNCHES 4096
 
 struct qsa_ctx {
   qsa_params p;
@@ -289,6 +307,7 @@ struct qsa_ctx {
   int beside_blocks = 0;          // workgroups per beam launch beside the slice loop (0: the work's)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipEvent_t gfork[QSA_GEV] = {}, gdone[QSA_GEV] = {};   // slice loop -> beam work -> slice loop
+  hipEvent_t tev[QSA_TEV] = {};   // enqueue throttle (see QSA_THROTTLE_TICKS)
   hipGraphExec_t gx_step = nullptr, gx_sweep = nullptr;   // captured beam step / sweep
   bool use_graphs = true;
   bool beam_beside = false;   // one step at a time: the beam work beside the slice loop
@@ -359,11 +378,30 @@ struct qsa_ctx {
       if (gfork[i]) (void)hipEventDestroy(gfork[i]);
       if (gdone[i]) (void)hipEventDestroy(gdone[i]);
     }
+    for (int i = 0; i < QSA_TEV; ++i)
+      if (tev[i]) (void)hipEventDestroy(tev[i]);
     if (bstream) (void)hipStreamDestroy(bstream);
     if (stream) (void)hipStreamDestroy(stream);
   }
 };
 
+
+// Slice loops short enough to be replayed from a graph (see
+// QSA_GRAPH_MAX_LAUNCHES).
+static bool graph_fits(int nxi) { return (int64_t)nxi * QSA_TICK_LAUNCHES <= QSA_GRAPH_MAX_LAUNCHES; }
+
+// The key counts the pushes made (cnt_next) no longer describe the beam
+// (something else moved or reloaded it), or they do again: a flag on the
+// device, written in stream order (also from captured graphs).
+static void invalidate_counts(qsa_ctx* c) {
+  hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int*>(c->ws + c->L.kvalid), 0);
+}
+static void counts_made(qsa_ctx* c) {
+  bool all = c->p.n_species > 0;
+  for (int s = 0; s < c->p.n_species; ++s) all = all && c->L.cnt_next[s] != 0;
+  hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int*>(c->ws + c->L.kvalid),
+                     all ? 1 : 0);
+}
 
 // A batch: the slice loops of several contexts run as lanes of the same
 // launches; beam deposits and pushes run per context on the batch's stream.
@@ -541,12 +579,24 @@ struct Engine {
     const Geo<R> g = geo(p);
     const int64_t nkeys = (int64_t)p.nxi * p.ny * (p.nx / QSA_BEAM_XCHUNK) + 1;
     int64_t* off = c->at<int64_t>(c->L.doff[s]);
-    hipLaunchKernelGGL(k_fill<int64_t>, dim3(fill_blocks(nkeys + 1)), dim3(256), 0, c->stream, off, nkeys + 1,
-                       (int64_t)0);
     const int64_t n = c->beam_n[s];
-    if (n > 0)
-      hipLaunchKernelGGL(k_beam_keys<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
-                         beam_dep_args(c), s, n, off);
+    if (c->L.cnt_next[s]) {
+      // the counts the last pushes made when they are valid (nothing has
+      // moved the beam since; a flag on the device, so that a captured graph
+      // decides at each replay), else counted here
+      const int* valid = c->at<int>(c->L.kvalid);
+      hipLaunchKernelGGL(k_counts_or_zero, dim3(fill_blocks(nkeys + 1)), dim3(256), 0, c->stream, valid,
+                         (const int64_t*)c->at<int64_t>(c->L.cnt_next[s]), off, nkeys + 1);
+      if (n > 0)
+        hipLaunchKernelGGL(k_beam_keys<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
+                           beam_dep_args(c), s, n, off, valid);
+    } else {
+      hipLaunchKernelGGL(k_fill<int64_t>, dim3(fill_blocks(nkeys + 1)), dim3(256), 0, c->stream, off, nkeys + 1,
+                         (int64_t)0);
+      if (n > 0)
+        hipLaunchKernelGGL(k_beam_keys<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
+                           beam_dep_args(c), s, n, off, (const int*)nullptr);
+    }
     HIP_OK(hipGetLastError());
     qsa_status st = scan64(c, off, nkeys + 1, c->at<int64_t>(c->L.scan64));
     if (st != QSA_OK) return st;
@@ -621,6 +671,13 @@ struct Engine {
         hipLaunchKernelGGL(k_beam_perm<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
                            beam_dep_args(c), s, n, c->at<int64_t>(c->L.cursor));
     }
+    // consumed: the next push counts afresh
+    const int64_t nkeys = (int64_t)p.nxi * p.ny * (p.nx / QSA_BEAM_XCHUNK) + 1;
+    for (int s = 0; s < p.n_species; ++s)
+      if (c->L.cnt_next[s])
+        hipLaunchKernelGGL(k_fill<int64_t>, dim3(fill_blocks(nkeys + 1)), dim3(256), 0, c->stream,
+                           c->at<int64_t>(c->L.cnt_next[s]), nkeys + 1, (int64_t)0);
+    invalidate_counts(c);
     HIP_OK(hipGetLastError());
     return QSA_OK;
   }
@@ -884,13 +941,35 @@ struct Engine {
     hipLaunchKernelGGL((k_lane_clear<R, 0>), dim3(blocks, 1, d.n), dim3(256), 0, st, lanes, t);
   }
 
+  // Before the launches of tick t on stream st: every QSA_THROTTLE_TICKS
+  // ticks, wait (spinning) until the device has reached the mark of two
+  // periods back, then set a new mark.  Nothing while st is being captured.
+  static qsa_status throttle(qsa_ctx* c, hipStream_t st, int t) {
+    if (t % QSA_THROTTLE_TICKS != 0) return QSA_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_OK(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return QSA_OK;
+    const int k = t / QSA_THROTTLE_TICKS;
+    if (k >= 2) {
+      hipError_t e;
+      while ((e = hipEventQuery(c->tev[(k - 2) % QSA_TEV])) == hipErrorNotReady) {
+      }
+      HIP_OK(e);
+    }
+    HIP_OK(hipEventRecord(c->tev[k % QSA_TEV], st));
+    return QSA_OK;
+  }
+
   // The slice loop of every lane (all with lag 0).
   static qsa_status slices(qsa_ctx* tc, hipStream_t st, const Lane<R>* lanes, const Dims& d) {
+    qsa_ctx* c = tc;   // error reporting (HIP_OK)
     clear_lanes(st, lanes, d, 0);
     for (int t = 0; t < d.nxi; ++t) {
-      const qsa_status s = tick(tc, st, lanes, d, t);
+      qsa_status s = throttle(tc, st, t);
+      if (s == QSA_OK) s = tick(tc, st, lanes, d, t);
       if (s != QSA_OK) return s;
     }
+    HIP_OK(hipGetLastError());
     return QSA_OK;
   }
 
@@ -921,8 +1000,9 @@ struct Engine {
       const BeamArgs<R> a = beam_args(c, g, s);
       const int grid = (c->beside_blocks > 0) ? c->beside_blocks : QSA_PUSH_BLOCKS;
       const int blocks = (int)std::min<int64_t>(grid, (a.n + 255) / 256);
+      int64_t* cnt = c->L.cnt_next[s] ? c->at<int64_t>(c->L.cnt_next[s]) : nullptr;
       QSA_LAUNCH(c, QSA_K_BEAM_PUSH, k_beam_push_keys<R>, dim3(blocks), dim3(256), 0, st, g, a,
-                 (const int*)da.perm[s], da.doff[s], k0, k1);
+                 (const int*)da.perm[s], da.doff[s], k0, k1, cnt);
     }
     HIP_OK(hipGetLastError());
     return QSA_OK;
@@ -982,6 +1062,7 @@ struct Engine {
     clear_lanes(c->stream, lanes, d, 0);
     int pushed = 0;   // chunks pushed so far
     for (int t = 0; t < p.nxi; ++t) {
+      if ((st = throttle(c, c->stream, t)) != QSA_OK) return st;
       if (t % C == 0) HIP_OK(hipStreamWaitEvent(c->stream, c->gdone[(t / C) % QSA_GEV], 0));
       if ((st = tick(c, c->stream, lanes, d, t)) != QSA_OK) return st;
       if (t + 1 < p.nxi && t == chunk_end(pushed)) {
@@ -1002,19 +1083,24 @@ struct Engine {
     if ((st = push_keys(c, g, bs, (int64_t)pushed * C * keys_per_slab, key_end)) != QSA_OK) return st;
     HIP_OK(hipEventRecord(c->gdone[0], bs));
     HIP_OK(hipStreamWaitEvent(c->stream, c->gdone[0], 0));   // join
+    counts_made(c);
     HIP_OK(hipGetLastError());
     c->swept = true;
     return QSA_OK;
   }
 
+  // Every particle pushed; the pushes count the next deposit's keys where
+  // the context keeps the counts (cnt_next was zeroed by this step's deposit).
   static qsa_status push(qsa_ctx* c) {
     const Geo<R> g = geo(c->p);
     for (int s = 0; s < c->p.n_species; ++s) {
       if (c->beam_n[s] == 0) continue;
       BeamArgs<R> a = beam_args(c, g, s);
       const int64_t blocks = (a.n + 255) / 256;
-      QSA_LAUNCH(c, QSA_K_BEAM_PUSH, k_beam_push<R>, dim3((unsigned)blocks), dim3(256), 0, c->stream, g, a);
+      int64_t* cnt = c->L.cnt_next[s] ? c->at<int64_t>(c->L.cnt_next[s]) : nullptr;
+      QSA_LAUNCH(c, QSA_K_BEAM_PUSH, k_beam_push<R>, dim3((unsigned)blocks), dim3(256), 0, c->stream, g, a, cnt);
     }
+    counts_made(c);
     HIP_OK(hipGetLastError());
     return QSA_OK;
   }
@@ -1023,6 +1109,7 @@ struct Engine {
   // QSA_PIPE_LAG slices behind lane k - 1, pushes each beam slab as soon as
   // its fields are final there and deposits it as lane k + 1's sources.
   static qsa_status group(qsa_ctx* c, int n) {
+    invalidate_counts(c);
     int last = -1;
     const qsa_status st = group_body(c, n, last);
     if (st != QSA_OK && last >= 0) {
@@ -1060,6 +1147,7 @@ struct Engine {
     // t + QSA_RING_WAIT waits for it (the constraints are in qsa_kernels.h).
     static_assert(QSA_RING_WAIT < QSA_GEV, "event ring too short");
     for (int t = 0; t < T; ++t) {
+      if ((st = throttle(c, c->stream, t)) != QSA_OK) return st;
       if (t % QSA_PIPE_LAG == 0 && t < n * QSA_PIPE_LAG) clear_lanes(c->stream, lanes, d, t);
       const int tw = t - QSA_RING_WAIT;
       hipEvent_t wait = (tw >= QSA_PUSH_LAG) ? c->gdone[tw % QSA_GEV] : nullptr;
@@ -1097,6 +1185,7 @@ struct Engine {
 
   // Put back the beam of the group's start, with clear device flags.
   static qsa_status restore(qsa_ctx* c) {
+    invalidate_counts(c);
     qsa_status st = copy_beam(c, c->L.beam, c->L.snap);
     if (st != QSA_OK) return st;
     hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, c->stream, c->at<int>(c->L.err), (int64_t)1, 0);
@@ -1352,6 +1441,7 @@ struct Engine {
     HIP_OK(hipMemcpyAsync(c->ws + c->L.ky2, ky2.data(), ky2.size(), hipMemcpyHostToDevice, c->stream));
     HIP_OK(hipMemcpyAsync(c->ws + c->L.kdy, kdy.data(), kdy.size(), hipMemcpyHostToDevice, c->stream));
     hipLaunchKernelGGL(k_fill<int>, dim3(1), dim3(64), 0, c->stream, c->at<int>(c->L.err), (int64_t)1, 0);
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, c->stream, c->at<int>(c->L.kvalid), 0);
     {
       std::vector<Lane<R>> lanes;
       std::vector<PipeBeam<R>> pipes;
@@ -1631,6 +1721,8 @@ qsa_status qsa_create(const qsa_params* p, void* dev_ws, size_t ws_bytes, void* 
   for (int i = 0; i < QSA_GEV && made; ++i)
     made = hipEventCreateWithFlags(&c->gfork[i], hipEventDisableTiming) == hipSuccess &&
            hipEventCreateWithFlags(&c->gdone[i], hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < QSA_TEV && made; ++i)
+    made = hipEventCreateWithFlags(&c->tev[i], hipEventDisableTiming) == hipSuccess;
   if (!made) {
     delete c;
     return QSA_E_DEVICE;
@@ -1709,6 +1801,7 @@ qsa_status qsa_load_beam(qsa_ctx* c, int32_t s, const double* x, const double* y
   if (c->sticky != QSA_OK) return c->sticky;
   if (s < 0 || s >= c->p.n_species) return fail(c, QSA_E_INVALID, "species index out of range");
   if (n < 0 || n > c->p.beam_capacity[s]) return fail(c, QSA_E_INVALID, "beam count exceeds capacity");
+  invalidate_counts(c);
   const double* arr[7] = {x, y, ux, uy, uz, w, xi};
   for (int i = 0; i < 7; ++i)
     if (n > 0 && !arr[i]) return fail(c, QSA_E_INVALID, "null beam array");
@@ -1739,6 +1832,7 @@ qsa_status qsa_load_beam_range(qsa_ctx* c, int32_t s, int64_t first, const doubl
   if (!c) return QSA_E_INVALID;
   if (c->sticky != QSA_OK) return c->sticky;
   if (s < 0 || s >= c->p.n_species) return fail(c, QSA_E_INVALID, "species index out of range");
+  invalidate_counts(c);
   if (first != 0 && first != c->beam_n[s])
     return fail(c, QSA_E_INVALID, "first must be 0 or the species' current particle count");
   if (n < 0 || first + n > c->p.beam_capacity[s]) return fail(c, QSA_E_INVALID, "beam count exceeds capacity");
@@ -1800,7 +1894,7 @@ qsa_status qsa_slice_sweep(qsa_ctx* c) {
   if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
   qsa_status st = enter(c);
   if (st != QSA_OK) return st;
-  const bool graphs = c->use_graphs && c->timing_class < 0;
+  const bool graphs = c->use_graphs && c->timing_class < 0 && graph_fits(c->p.nxi);
   if (graphs && (st = capture(c, &c->gx_sweep, [&] { return run_sweep(c); })) != QSA_OK) return st;
   if (graphs && c->gx_sweep) {
     HIP_OK(hipGraphLaunch(c->gx_sweep, c->stream));
@@ -1820,7 +1914,7 @@ qsa_status qsa_beam_step(qsa_ctx* c, int32_t n_steps) {
   if (n_steps == 0) return QSA_OK;
   qsa_status st = enter(c);
   if (st != QSA_OK) return st;
-  const bool graphs = c->use_graphs && c->timing_class < 0;
+  const bool graphs = c->use_graphs && c->timing_class < 0 && graph_fits(c->p.nxi);
   for (int i = 0; i < n_steps;) {
     const int n = c->pipe_ok ? std::min(c->pipe_max, n_steps - i) : 1;
     if (n == 1) {
@@ -1892,6 +1986,7 @@ qsa_status qsa_autotune(qsa_ctx* c, double* ms_per_step) {
   if (c->sticky != QSA_OK) return c->sticky;
   if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
   if (c->timing_class >= 0) return fail(c, QSA_E_STATE, "kernel timing is active");
+  invalidate_counts(c);
   qsa_status st = enter(c);
   if (st != QSA_OK) return st;
   if ((st = check_device(c)) != QSA_OK) return st;
@@ -1973,6 +2068,7 @@ qsa_status qsa_adjoint_sweep(qsa_ctx* c, int32_t n_steps, int32_t n_bins, const 
   if (!c) return QSA_E_INVALID;
   if (c->sticky != QSA_OK) return c->sticky;
   if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
+  invalidate_counts(c);
   if (c->p.plasma_weights)
     return fail(c, QSA_E_INVALID, "the adjoint sweep takes a plasma of one weight (plasma_weights = 0)");
   const AdjLayout& A = c->L.adj;
@@ -2005,6 +2101,7 @@ qsa_status qsa_adjoint_sweep(qsa_ctx* c, int32_t n_steps, int32_t n_bins, const 
   }
   st = dispatch(c, [&] { return Adj<double>(c, A).run(n_steps, n_bins, loss, grad); },
                 [&] { return Adj<float>(c, A).run(n_steps, n_bins, loss, grad); });
+  invalidate_counts(c);   // whatever the adjoint's own steps left in the counts
   if (st != QSA_OK) return st;
   if ((st = leave(c)) != QSA_OK) return st;
   return check_device(c);
@@ -2271,7 +2368,9 @@ static qsa_status batch_call(qsa_batch* b, int32_t n_steps, bool push) {
   HIP_OK(hipStreamWaitEvent(b->stream, b->ev_in, 0));
   hipGraphExec_t* gx = push ? &b->gx_step : &b->gx_sweep;
   auto body = [&] { return b->precision == QSA_FP32 ? batch_run<float>(b, push) : batch_run<double>(b, push); };
-  const bool graphs = b->use_graphs && c->timing_class < 0;
+  int nxi_max = 0;
+  for (qsa_ctx* m : b->ctxs) nxi_max = std::max(nxi_max, m->p.nxi);
+  const bool graphs = b->use_graphs && c->timing_class < 0 && graph_fits(nxi_max);
   if (graphs && !*gx) {
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
       const qsa_status st = body();

@@ -45,6 +45,8 @@ struct Adj {
   }
 
   hipStream_t st() const { return c->stream; }
+  int thr_n = 0;   // slices enqueued, for the enqueue throttle
+  qsa_status throttle() { return Engine<R>::throttle(c, st(), thr_n++); }
   R* grid(int k) const { return c->at<R>(A.grids) + (int64_t)k * nperp; }
   double* sc() const { return c->at<double>(A.sc); }
   double* scf(int par) const { return sc() + 8 * par; }        // forward leapfrog slot of a slice parity
@@ -377,6 +379,7 @@ struct Adj {
     hipLaunchKernelGGL(k_fill<double>, dim3(1), dim3(64), 0, st(), sc(), (int64_t)16, 0.0);
     if ((st0 = lin(grid(AG_S), 0, {{src(0, 0), 1.0}}, nperp)) != QSA_OK) return st0;
     for (int j = 0; j < p.nxi; ++j) {
+      if ((st0 = throttle()) != QSA_OK) return st0;
       if (j % A.ck_len == 0)
         for (int k = 0; k < 4; ++k)
           HIP_OK(hipMemcpyAsync(ck(t, j / A.ck_len, k), Ya[k], np * sizeof(R), hipMemcpyDeviceToDevice, st()));
@@ -572,6 +575,7 @@ struct Adj {
       hipLaunchKernelGGL(k_af_segment<R>, dim3(blocks(np)), dim3(256), 0, st(), sg);
       HIP_OK(hipGetLastError());
       for (int j = j1 - 1; j >= j0; --j) {
+        if ((st0 = throttle()) != QSA_OK) return st0;
         if ((st0 = rev_slice(t, j, j - j0, yb[cur], yb[1 - cur])) != QSA_OK) return st0;
         cur = 1 - cur;
       }

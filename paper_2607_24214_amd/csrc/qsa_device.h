@@ -416,17 +416,4 @@ __device__ __forceinline__ C2<R>* fft_lds(C2<R>* a, C2<R>* b, int n, int lg, int
 // the radix-8 passes use half of them.
 __host__ __device__ __forceinline__ int row_tpt(int n) { return n >= 4 ? n >> 2 : 1; }
 
-
-// In-place variant: the result ends in `a` (one extra LDS copy when the pass
-// count is odd).
-template <typename R, bool INV>
-__device__ __forceinline__ void fft_lds_inplace(C2<R>* a, C2<R>* scratch, int n, int lg, int t,
-                                                int tpt, const C2<R>* __restrict__ tw) {
-  C2<R>* r = fft_lds<R, INV>(a, scratch, n, lg, t, tpt, tw);
-  if (r != a) {
-    for (int i = t; i < n; i += tpt) a[i] = r[i];
-    __syncthreads();
-  }
-}
-
 }  // namespace qsa

@@ -551,7 +551,9 @@ __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, 
   for (int y = t; y < ny; y += tpt)
     mine[y] = (valid && grp < S::NIN) ? L.rowspec[(size_t)grp * g.ny * g.nxh + y * g.nxh + kx] : C2<R>{0, 0};
   __syncthreads();
-  fft_lds_inplace<R, false>(mine, Sx + grp * cs, ny, g.lgy, t, tpt, tw);
+  // every group's transform ends in the same one of its two buffers (same
+  // pass count): the multipliers work there, with no copy back
+  C2<R>* const Rb = (fft_lds<R, false>(mine, Sx + grp * cs, ny, g.lgy, t, tpt, tw) == mine) ? D : Sx;
 
   for (int y = r; y < ny; y += per_col) {
     C2<R> o[S::NOUT];
@@ -565,13 +567,13 @@ __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, 
       const R iks = k0 ? R(0) : R(1) / ksq;
       if (MODE == COL_PSI) {
         // -lap psi = rho - J_z; the k = 0 value is the transverse-mean wake
-        C2<R> ph = cscale(D[y], iks);
+        C2<R> ph = cscale(Rb[y], iks);
         if (k0) ph = C2<R>{(R)a.ode[1] * a.n_perp, R(0)};
         o[0] = cscale(ph, a.inv_n);
         o[1] = cscale(cmul_ik(ph, kdx), a.inv_n);
         o[2] = cscale(cmul_ik(ph, kdy), a.inv_n);
       } else if (MODE == COL_J) {
-        const C2<R> jx = D[y], jy = D[cs + y], jzv = D[2 * cs + y];
+        const C2<R> jx = Rb[y], jy = Rb[cs + y], jzv = Rb[2 * cs + y];
         a.jr_w[0][e] = jx;
         a.jr_w[1][e] = jy;
         a.jz[e] = jzv;
@@ -601,8 +603,8 @@ __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, 
       } else {
         // D = d_xi J_perp ~ (J~_perp^{j+1} - J_perp^{j-1})/(2h)
         const R i2h = R(0.5) / a.h;
-        const C2<R> dx = cscale(csub(D[y], a.jr_r[0][e]), i2h);
-        const C2<R> dy = cscale(csub(D[cs + y], a.jr_r[1][e]), i2h);
+        const C2<R> dx = cscale(csub(Rb[y], a.jr_r[0][e]), i2h);
+        const C2<R> dy = cscale(csub(Rb[cs + y], a.jr_r[1][e]), i2h);
         const C2<R> jzv = a.jz[e];
         const C2<R> bxo = a.b_cur[0][e], byo = a.b_cur[1][e];
         const R iden = R(1) / (-ksq - a.kappa2);
@@ -619,12 +621,12 @@ __global__ void __launch_bounds__(256) k_col(const Lane<R>* __restrict__ lanes, 
     // every thread of the column has read its inputs at row y before any
     // output at row y is written: rows are owned by exactly one thread here
 #pragma unroll
-    for (int q = 0; q < S::NOUT; ++q) D[q * cs + y] = o[q];
+    for (int q = 0; q < S::NOUT; ++q) Rb[q * cs + y] = o[q];
   }
   __syncthreads();
-  fft_lds_inplace<R, true>(mine, Sx + grp * cs, ny, g.lgy, t, tpt, tw);
+  const C2<R>* res = fft_lds<R, true>(Rb + grp * cs, ((Rb == D) ? Sx : D) + grp * cs, ny, g.lgy, t, tpt, tw);
   if (valid && grp < S::NOUT)
-    for (int y = t; y < ny; y += tpt) L.colout[(size_t)grp * g.ny * g.nxh + y * g.nxh + kx] = mine[y];
+    for (int y = t; y < ny; y += tpt) L.colout[(size_t)grp * g.ny * g.nxh + y * g.nxh + kx] = res[y];
 }
 
 // ---------------------------------------------------------- plasma particles
@@ -1062,9 +1064,20 @@ __global__ void __launch_bounds__(256) k_push_final(const Lane<R>* __restrict__ 
       for (int q = 0; q < 6; ++q) v[q] = f[slot[q] * plane + o];
 #pragma unroll
       for (int q = 6; q < pack_stride<R>(); ++q) v[q] = R(0);
+      // the record in 16-byte stores (records are 16-byte aligned)
       R* r = dst + (int64_t)o * pack_stride<R>();
-#pragma unroll
-      for (int q = 0; q < pack_stride<R>(); ++q) r[q] = v[q];
+      if constexpr (sizeof(R) == 8) {
+        typedef double D2 __attribute__((ext_vector_type(2)));
+        D2* q = reinterpret_cast<D2*>(r);
+        q[0] = D2{v[0], v[1]};
+        q[1] = D2{v[2], v[3]};
+        q[2] = D2{v[4], v[5]};
+      } else {
+        typedef float F4 __attribute__((ext_vector_type(4)));
+        F4* q = reinterpret_cast<F4*>(r);
+        q[0] = F4{v[0], v[1], v[2], v[3]};
+        q[1] = F4{v[4], v[5], v[6], v[7]};
+      }
     }
   }
   if (p >= L.np) return;
@@ -1436,10 +1449,12 @@ struct BeamDepArgs {
   double inv_dxi;
 };
 
-// Keys of species s and their counts per row (cnt zeroed by the caller).
+// Keys of species s and their counts per row (cnt zeroed by the caller);
+// nothing when *skip is set (the counts are already there).
 template <typename R>
 __global__ void __launch_bounds__(256) k_beam_keys(Geo<R> g, BeamDepArgs<R> a, int s, int64_t n,
-                                                   int64_t* __restrict__ cnt) {
+                                                   int64_t* __restrict__ cnt, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = p < n;
   int key = 0;
@@ -1903,26 +1918,63 @@ __device__ __forceinline__ BeamNew<R> boris_one(const Geo<R>& g, const R* __rest
   return boris_state(g, fields, fpack, ring, qh, dt, inv_dxi, xi_max, b, px, py, pxi, pux, puy, puz, pw, p);
 }
 
+// Counts of deposit keys: dst = *valid ? src : 0 (the counts a push made, or
+// a fresh start for k_beam_keys).
+__global__ void __launch_bounds__(256) k_counts_or_zero(const int* __restrict__ valid,
+                                                        const int64_t* __restrict__ src,
+                                                        int64_t* __restrict__ dst, int64_t n) {
+  const bool ok = *valid != 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = ok ? src[i] : 0;
+}
+
+__global__ void k_set_flag(int* __restrict__ f, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *f = v;
+}
+
+// Every particle of a species pushed once; with cnt (not null) its new
+// deposit key is counted there (see k_beam_push_keys).
 template <typename R>
-__global__ void __launch_bounds__(256) k_beam_push(Geo<R> g, BeamArgs<R> a) {
+__global__ void __launch_bounds__(256) k_beam_push(Geo<R> g, BeamArgs<R> a, int64_t* __restrict__ cnt) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.n) return;
-  boris_one<R>(g, a.fields, a.fpack, a.ring, a.qmh, a.dt, a.inv_dxi, a.xi_max, a.x, a.y, a.xi, a.ux, a.uy, a.uz,
-               a.w, p);
+  const bool act = p < a.n;
+  int key = 0;
+  if (act) {
+    const BeamOld<R> b = beam_old<R>(a.x, a.y, a.xi, a.ux, a.uy, a.uz, a.w, p);
+    const BeamNew<R> n = boris_state(g, a.fields, a.fpack, a.ring, a.qmh, a.dt, a.inv_dxi, a.xi_max, b, a.x, a.y,
+                                     a.xi, a.ux, a.uy, a.uz, a.w, p);
+    key = beam_key(g, n.x, n.y, n.xi, n.lost ? R(0) : b.w, a.inv_dxi);
+  }
+  if (cnt) (void)wave_run_add(cnt, key, act);
 }
 
 // The same push for the particles whose deposit keys lie in [k0, k1):
 // perm[off[k0] .. off[k1]) (the permutation and chunk offsets of the beam
 // deposit, so a slab range of keys is the particles of those slabs at the
 // step's start); grid-stride, as the count is only known on the device.
+// With cnt (not null) every pushed particle's new deposit key is counted
+// there (cnt[key] += 1), so that the next deposit needs no pass of its own
+// to count them.
 template <typename R>
 __global__ void __launch_bounds__(256) k_beam_push_keys(Geo<R> g, BeamArgs<R> a, const int* __restrict__ perm,
-                                                        const int64_t* __restrict__ off, int64_t k0, int64_t k1) {
+                                                        const int64_t* __restrict__ off, int64_t k0, int64_t k1,
+                                                        int64_t* __restrict__ cnt) {
   const int64_t q1 = off[k1];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = off[k0] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < q1; q += stride)
-    boris_one<R>(g, a.fields, a.fpack, a.ring, a.qmh, a.dt, a.inv_dxi, a.xi_max, a.x, a.y, a.xi, a.ux, a.uy,
-                 a.uz, a.w, (int64_t)perm[q]);
+  // block-uniform trip count: every lane reaches the wavefront's key count
+  for (int64_t base = off[k0] + (int64_t)blockIdx.x * blockDim.x; base < q1; base += stride) {
+    const int64_t q = base + threadIdx.x;
+    const bool act = q < q1;
+    int key = 0;
+    if (act) {
+      const int64_t p = (int64_t)perm[q];
+      const BeamOld<R> b = beam_old<R>(a.x, a.y, a.xi, a.ux, a.uy, a.uz, a.w, p);
+      const BeamNew<R> n = boris_state(g, a.fields, a.fpack, a.ring, a.qmh, a.dt, a.inv_dxi, a.xi_max, b, a.x,
+                                       a.y, a.xi, a.ux, a.uy, a.uz, a.w, p);
+      key = beam_key(g, n.x, n.y, n.xi, n.lost ? R(0) : b.w, a.inv_dxi);
+    }
+    if (cnt) (void)wave_run_add(cnt, key, act);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -131,3 +131,45 @@ def test_beside_option_round_trip():
     assert get() == 0
     assert s.lib.qsa_set_option(s.ctx, 5, 2) != 0   # only 0 or 1
     assert get() == 0
+
+
+def test_beside_key_counts_survive_mixed_calls_fp64():
+    """The pushes beside the slice loop count the next deposit's keys; any
+    other path that moves the beam must drop those counts: beside steps
+    mixed with steps taken one after the other (graph replay), a sweep on
+    its own and a reload give what steps one after the other give."""
+    wl = W.small_3d(32, 16, 21).with_(
+        dt=20.0, species=(W.Species(Z=-1, alpha=0.05, ppc=2, sigma_par=1e-3, sigma_perp=1e-2),))
+    a, b = _sim(wl, True), _sim(wl, False)
+    plan = [("beside", 2), ("seq", 1), ("beside", 1), ("sweep", 0), ("beside", 1), ("seq", 2), ("beside", 1)]
+    for what, n in plan:
+        if what == "sweep":
+            a.slice_sweep()
+            b.slice_sweep()
+            continue
+        a.set_beam_beside(what == "beside")
+        a.beam_step(n)
+        b.beam_step(n)
+    _compare("mixed calls", a, b, 1e-10, 1e-11)
+    # a reload in between: the counts of the old beam must not be used
+    beams = W.beam(wl.with_(seed=wl.seed + 1))
+    a.set_beam_beside(True)
+    a.beam_step(1)
+    for k, bb in enumerate(beams):
+        a.load_beam(k, bb)
+        b.load_beam(k, bb)
+    a.beam_step(2)
+    b.beam_step(2)
+    _compare("after a reload", a, b, 1e-10, 1e-11)
+
+
+@pytest.mark.parametrize("blocks", [1, 7, 64])
+def test_beside_capped_grids_fp64(blocks):
+    """QSA_OPT_BESIDE_BLOCKS caps the deposit and push launches beside the
+    slice loop: each workgroup loops over several rows or particle ranges."""
+    wl = W.small_3d(32, 32, 19).with_(dt=20.0)
+    a, b = _sim(wl, True), _sim(wl, False)
+    a.set_beside_blocks(blocks)
+    a.beam_step(2)
+    b.beam_step(2)
+    _compare(f"beside blocks {blocks}", a, b, 1e-10, 1e-11)
