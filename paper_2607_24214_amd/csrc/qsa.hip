@@ -691,8 +691,8 @@ struct Engine {
       const int nb = beam_colour_rows(jlo, jhi, c->p.ny, colour);
       const int grid = (max_blocks > 0) ? std::min(nb, max_blocks) : nb;
       if (nb > 0)
-        QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_beam_rows<R>, dim3(grid), dim3(256), 2 * 2 * 4 * g.nx * sizeof(double),
-                   st, g, a, src, colour, jlo, jhi);
+        QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_beam_rows<R>, dim3(grid), dim3(BeamRowBlock<R>::THREADS),
+                   2 * 2 * 4 * g.nx * sizeof(double), st, g, a, src, colour, jlo, jhi);
     }
     HIP_OK(hipGetLastError());
     return QSA_OK;

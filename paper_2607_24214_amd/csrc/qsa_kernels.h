@@ -1611,10 +1611,18 @@ template <typename R>
 __device__ __forceinline__ void beam_row(const Geo<R>& g, const BeamDepArgs<R>& a, R* __restrict__ src,
                                          double* tile, int jb, int lb);
 
+// Threads per colour-pass block: the 2 x 2 x 4 x nx float64 tile (64 KB at
+// nx = 512) allows two blocks per CU, so the float32 kernel (within 128
+// VGPRs) takes 512 threads to keep four wavefronts per SIMD in flight.
+template <typename R>
+struct BeamRowBlock {
+  static constexpr int THREADS = sizeof(R) == 4 ? 512 : 256;
+};
+
 // Block k of a launch of gridDim.x blocks takes the colour's rows k,
 // k + gridDim.x, ... (one row per block when the grid covers them all).
 template <typename R>
-__global__ void __launch_bounds__(256) k_beam_rows(Geo<R> g, BeamDepArgs<R> a, R* __restrict__ src, int colour,
+__global__ void __launch_bounds__(BeamRowBlock<R>::THREADS) k_beam_rows(Geo<R> g, BeamDepArgs<R> a, R* __restrict__ src, int colour,
                                                    int jlo, int jhi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* tile = reinterpret_cast<double*>(smem_raw);   // float64 for either precision
