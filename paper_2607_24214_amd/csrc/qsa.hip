@@ -215,7 +215,7 @@ Layout make_layout(const qsa_params& p) {
     for (int i = 0; i < 6; ++i) S.cval[i] = c.take(p.n_plasma * rs);
   }
   const size_t nrows = (size_t)p.nxi * p.ny;
-  const size_t nkeys = nrows * (p.nx / QSA_BEAM_XCHUNK) + 1;   // sort keys, the last for inert particles
+  const size_t nkeys = nrows * (nx_chunks_of(p.nx)) + 1;   // sort keys, the last for inert particles
   for (int s = 0; s < QSA_MAX_SPECIES; ++s) {
     const size_t cap = (s < p.n_species) ? (size_t)p.beam_capacity[s] : 0;
     const bool used = s < p.n_species;
@@ -264,7 +264,7 @@ const char* validate(const qsa_params* p) {
   if (p->n_plasma <= 0 || p->n_plasma > (int64_t)1 << 30) return "n_plasma must be in [1, 2^30]";
   if (!(p->plasma_w > 0)) return "plasma_w must be > 0";
   if (p->n_species < 1 || p->n_species > QSA_MAX_SPECIES) return "n_species must be in [1, 4]";
-  if ((int64_t)p->nxi * p->ny * (p->nx / QSA_BEAM_XCHUNK) > ((int64_t)1 << 30))
+  if ((int64_t)p->nxi * p->ny * (nx_chunks_of(p->nx)) > ((int64_t)1 << 30))
     return "nxi * ny * nx / 8 must be <= 2^30";
   if (p->pipeline < 0 || p->pipeline > QSA_MAX_PIPELINE) return "pipeline must be in [0, 16]";
   if (p->adjoint_steps < 0 || p->adjoint_steps > 1024) return "adjoint_steps must be in [0, 1024]";
@@ -577,7 +577,7 @@ struct Engine {
   static qsa_status keys(qsa_ctx* c, int s) {
     const qsa_params& p = c->p;
     const Geo<R> g = geo(p);
-    const int64_t nkeys = (int64_t)p.nxi * p.ny * (p.nx / QSA_BEAM_XCHUNK) + 1;
+    const int64_t nkeys = (int64_t)p.nxi * p.ny * (nx_chunks_of(p.nx)) + 1;
     int64_t* off = c->at<int64_t>(c->L.doff[s]);
     const int64_t n = c->beam_n[s];
     if (c->L.cnt_next[s]) {
@@ -672,7 +672,7 @@ struct Engine {
                            beam_dep_args(c), s, n, c->at<int64_t>(c->L.cursor));
     }
     // consumed: the next push counts afresh
-    const int64_t nkeys = (int64_t)p.nxi * p.ny * (p.nx / QSA_BEAM_XCHUNK) + 1;
+    const int64_t nkeys = (int64_t)p.nxi * p.ny * (nx_chunks_of(p.nx)) + 1;
     for (int s = 0; s < p.n_species; ++s)
       if (c->L.cnt_next[s])
         hipLaunchKernelGGL(k_fill<int64_t>, dim3(fill_blocks(nkeys + 1)), dim3(256), 0, c->stream,
@@ -1042,7 +1042,7 @@ struct Engine {
     const Lane<R>* lanes = c->at<Lane<R>>(c->L.lane);
     const Dims d = dims_of(c);
     const int C = QSA_BEAM_CHUNK, nch = (p.nxi + C - 1) / C;
-    const int64_t keys_per_slab = (int64_t)p.ny * (p.nx / QSA_BEAM_XCHUNK);
+    const int64_t keys_per_slab = (int64_t)p.ny * (nx_chunks_of(p.nx));
     const int64_t key_end = (int64_t)p.nxi * keys_per_slab + 1;   // past the left-the-box key
     auto chunk_end = [&](int ch) { return std::min(p.nxi, (ch + 1) * C); };
     auto deposit = [&](int ch) -> qsa_status {

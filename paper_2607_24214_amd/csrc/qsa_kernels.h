@@ -1404,8 +1404,9 @@ __device__ __forceinline__ T wave_run_add(T* cnt, int key, bool active) {
 // particle with j = -1 (node slice 0 only) counts as row (0, l); nxi*ny*nxc
 // for a particle without a node in the grid or with nothing to deposit.
 #define QSA_BEAM_XCHUNK 8
+__host__ __device__ __forceinline__ int nx_chunks_of(int nx) { return nx >= QSA_BEAM_XCHUNK ? nx / QSA_BEAM_XCHUNK : 1; }
 template <typename R>
-__device__ __forceinline__ int nx_chunks(const Geo<R>& g) { return g.nx / QSA_BEAM_XCHUNK; }
+__device__ __forceinline__ int nx_chunks(const Geo<R>& g) { return nx_chunks_of(g.nx); }
 template <typename R>
 __device__ __forceinline__ int beam_key(const Geo<R>& g, R x, R y, double xi, R w, double inv_dxi) {
   const int nxc = nx_chunks(g);
