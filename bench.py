@@ -37,6 +37,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# one step at a time, the beam storage is re-sorted by deposit key every this
+# many steps (pair 512^2 x 2048 in float32: 1059.5 ms/step never, 1034.0 every
+# 4 or 3, 1042.9 every 2, over 10 steps after 2 of warm-up)
+RESORT_EVERY = 4
 TRAFFIC_FILES = (os.path.join(ROOT, "profiles", "traffic_push_pred_pair512_f32.json"),
                  os.path.join(ROOT, "profiles", "traffic_push_pred_cube256_f64.json"))
 KERNEL_SOURCES = ("paper_2607_24214_amd/csrc/qsa_kernels.h", "paper_2607_24214_amd/csrc/qsa_device.h")
@@ -438,6 +442,9 @@ def run_workload(wl, precision: str, pipeline: int, steps: int, warmup: int, arg
         sim.set_beam_beside(False)
     if args.beside_blocks is not None:
         sim.set_beside_blocks(args.beside_blocks)
+    resort = (args.resort_every if args.resort_every is not None else RESORT_EVERY) if pipeline == 1 else 0
+    if resort:
+        sim.set_resort_every(resort)
     if args.col_threads or args.plasma_threads or args.row_threads:
         sim.set_shapes(args.plasma_threads, args.row_threads, args.col_threads)
     tuned = None
@@ -530,6 +537,7 @@ def run_workload(wl, precision: str, pipeline: int, steps: int, warmup: int, arg
                       "dx": wl.dx, "plasma_per_slice": wl.n_plasma, "beam_particles": wl.n_beam_total,
                       "species": [{"Z": sp.Z, "alpha": sp.alpha, "ppc": sp.ppc} for sp in wl.species],
                       "gamma_b": wl.gamma_b, "n_corr": wl.n_corr, "steps_in_flight": depth, "autotuned": tuned,
+                      "resort_every": resort,
                       "step": f"beam source deposit + {wl.nxi}-slice sweep + Boris beam push"},
            "sweep_only": {"ms": 1e3 * t_sweep, "updates_per_s": wl.n_plasma * wl.nxi / t_sweep},
            "roofline": roofline, "diagnostics": diag}
@@ -565,6 +573,9 @@ def main():
                     help="skip the extra entries (the 256^3-class workload in float64 and float32)")
     ap.add_argument("--beside-blocks", type=int, default=None,
                     help="workgroups per launch of the beam work beside the slice loop (0 = the work's)")
+    ap.add_argument("--resort-every", type=int, default=None,
+                    help="one step at a time: reorder the beam storage by deposit key every n steps (0 = never; "
+                         f"default {RESORT_EVERY})")
     ap.add_argument("--no-beside", action="store_true",
                     help="one step at a time: deposit, sweep and push one after the other instead of the "
                          "beam work beside the slice loop")

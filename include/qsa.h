@@ -174,7 +174,8 @@ qsa_status qsa_load_plasma_weights(qsa_ctx* c, const double* w, int64_t n, int32
  * inert.  Float64 arrays, host (synchronizing) or device memory.  Any order;
  * with pipeline > 1 the library keeps the particles sorted by cell row
  * internally (each group of steps starts with that sort), and qsa_read_beam
- * still returns them in the order they were loaded. */
+ * still returns them in the order they were loaded (with pipeline = 1 too,
+ * unless QSA_OPT_RESORT_EVERY reorders the storage). */
 qsa_status qsa_load_beam(qsa_ctx* c, int32_t s, const double* x,
                          const double* y, const double* xi, const double* ux,
                          const double* uy, const double* uz, const double* w,
@@ -361,11 +362,27 @@ enum {
                             gathers are final); 0 (default): deposit, sweep,
                             push one after the other.  The results agree up to the
                             order of the deposit's additions.              */
-  QSA_OPT_BESIDE_BLOCKS = 6 /* workgroups per launch of the beam work beside
+  QSA_OPT_BESIDE_BLOCKS = 6, /* workgroups per launch of the beam work beside
                             the slice loop: 0 (default) as many as the work
                             has; n > 0 caps every such launch at n (each
                             workgroup then loops over its share), leaving
                             the rest of the chip to the slice loop       */
+  QSA_OPT_RESORT_EVERY = 7 /* contexts without steps in flight: n > 0
+                            reorders the beam's storage by deposit key (cell
+                            row, slab-major) before every n-th beam step of
+                            qsa_beam_step, counted from the last beam load
+                            (so the first step after a load re-sorts), which
+                            keeps the deposit's and the push's memory access
+                            coalesced as particles drift across cells; the
+                            step's sources and stored fields serve as
+                            scratch, so the largest beam_capacity times 8
+                            bytes must fit in them (else the setting is
+                            refused).  qsa_read_beam then returns particles
+                            in storage order, no longer the load order; the
+                            order within a cell row is unspecified.  0
+                            (default): never.  Refused for contexts with
+                            steps in flight (they sort the beam by cell row
+                            themselves and keep the load order). */
 };
 
 /* Set a context option (see QSA_OPT_*). */

@@ -311,6 +311,9 @@ struct qsa_ctx {
   hipGraphExec_t gx_step = nullptr, gx_sweep = nullptr;   // captured beam step / sweep
   bool use_graphs = true;
   bool beam_beside = false;   // one step at a time: the beam work beside the slice loop
+  int64_t resort_every = 0;   // one step at a time: the beam storage reordered by deposit key every n steps
+  int64_t beam_steps = 0;     // beam steps since the last beam load (the re-sort's clock)
+  bool resort_pending = false;   // the next deposit re-sorts the storage (direct launches only)
   bool pipe_ok = true;   // off after a drift violation, until the next beam load
   int pipe_max = 1;      // beam steps in flight when pipelining (<= L.nset)
   int tune_nt = 0;       // threads per plasma-row block (0: from the particles per row)
@@ -663,6 +666,8 @@ struct Engine {
   // (four launches by the parity of the row, see k_beam_rows).
   static qsa_status beam_perm_all(qsa_ctx* c, const Geo<R>& g) {
     const qsa_params& p = c->p;
+    const bool resort = c->resort_pending;   // set by a single step that is due for it
+    c->resort_pending = false;
     for (int s = 0; s < p.n_species; ++s) {
       qsa_status st = keys(c, s);
       if (st != QSA_OK) return st;
@@ -670,6 +675,7 @@ struct Engine {
       if (n > 0)
         hipLaunchKernelGGL(k_beam_perm<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
                            beam_dep_args(c), s, n, c->at<int64_t>(c->L.cursor));
+      if (resort && (st = resort_species(c, s)) != QSA_OK) return st;
     }
     // consumed: the next push counts afresh
     const int64_t nkeys = (int64_t)p.nxi * p.ny * (nx_chunks_of(p.nx)) + 1;
@@ -678,6 +684,56 @@ struct Engine {
         hipLaunchKernelGGL(k_fill<int64_t>, dim3(fill_blocks(nkeys + 1)), dim3(256), 0, c->stream,
                            c->at<int64_t>(c->L.cnt_next[s]), nkeys + 1, (int64_t)0);
     invalidate_counts(c);
+    HIP_OK(hipGetLastError());
+    return QSA_OK;
+  }
+
+  // Bytes of the step's sources and stored fields (adjacent in the workspace):
+  // the scratch of the storage re-sort, which runs before a step's deposit
+  // overwrites both.
+  static size_t resort_scratch(const qsa_ctx* c) {
+    const qsa_params& p = c->p;
+    const size_t plane = (size_t)p.nxi * p.nx * p.ny * sizeof(R);
+    const SetLayout& S = c->L.set[0];
+    return S.fields + N_STORED * plane - S.src;
+  }
+
+  // The storage of species s reordered by deposit key (one step at a time),
+  // right after the step's permutation to key order is made: as particles
+  // drift across cells their storage order departs from the order the
+  // deposit gathers them in, and the gathers (and the push's field reads)
+  // lose coalescing.  Every beam array is gathered through the permutation
+  // into the scratch (two float arrays per pass where it holds two) and
+  // copied back; the permutation becomes the identity.  The key offsets
+  // and counts stay valid (no particle moves).
+  static qsa_status resort_species(qsa_ctx* c, int s) {
+    const int64_t n = c->beam_n[s];
+    if (n == 0) return QSA_OK;
+    char* tmp = c->ws + c->L.set[0].src;
+    const int64_t npad = (n + 63) / 64 * 64;   // the second plane 256-byte aligned
+    const bool two = 2 * (size_t)npad * sizeof(R) <= resort_scratch(c);
+    const dim3 grid((unsigned)((n + 255) / 256));
+    int* perm = c->at<int>(c->L.perm[s]);
+    auto copy_back = [&](char* dst, const char* src, int64_t bytes) {
+      const int64_t blocks = std::min<int64_t>(std::max<int64_t>(((bytes >> 4) + 255) / 256, 1), 1 << 18);
+      hipLaunchKernelGGL(k_copy_bytes, dim3((unsigned)blocks), dim3(256), 0, c->stream,
+                         (const unsigned char*)src, (unsigned char*)dst, bytes);
+    };
+    R* t0 = reinterpret_cast<R*>(tmp);
+    R* t1 = t0 + npad;
+    for (int k = 0; k < 6; k += two ? 2 : 1) {
+      R* a0 = c->at<R>(c->L.beam[s][k]);
+      R* a1 = two ? c->at<R>(c->L.beam[s][k + 1]) : nullptr;
+      hipLaunchKernelGGL(k_gather_perm<R>, grid, dim3(256), 0, c->stream, (const R*)a0, (const R*)a1, t0, t1,
+                         (const int*)perm, n);
+      copy_back((char*)a0, (const char*)t0, n * (int64_t)sizeof(R));
+      if (two) copy_back((char*)a1, (const char*)t1, n * (int64_t)sizeof(R));
+    }
+    double* xi = c->at<double>(c->L.beam[s][6]);
+    hipLaunchKernelGGL(k_gather_perm<double>, grid, dim3(256), 0, c->stream, (const double*)xi,
+                       (const double*)nullptr, (double*)tmp, (double*)nullptr, (const int*)perm, n);
+    copy_back((char*)xi, (const char*)tmp, n * (int64_t)sizeof(double));
+    hipLaunchKernelGGL(k_iota32, grid, dim3(256), 0, c->stream, perm, n);
     HIP_OK(hipGetLastError());
     return QSA_OK;
   }
@@ -1549,8 +1605,18 @@ qsa_status run_group(qsa_ctx* c, int n) {
 // are off.
 qsa_status step_one(qsa_ctx* c, bool graphs) {
   qsa_status st = QSA_OK;
+  // a step due for the storage re-sort is enqueued directly (a captured
+  // step replays without it)
+  const bool resort = c->L.nset == 1 && c->resort_every > 0 && c->beam_steps % c->resort_every == 0;
+  ++c->beam_steps;
+  if (resort) {
+    c->resort_pending = true;
+    graphs = false;
+  }
   if (c->beam_beside && c->L.nset == 1) {
-    if ((st = run_step_beside(c)) != QSA_OK) return st;
+    st = run_step_beside(c);
+    c->resort_pending = false;
+    if (st != QSA_OK) return st;
     c->cur_set = 0;
     return QSA_OK;
   }
@@ -1558,8 +1624,10 @@ qsa_status step_one(qsa_ctx* c, bool graphs) {
   if (graphs && c->gx_step) {
     HIP_OK(hipGraphLaunch(c->gx_step, c->stream));
     c->swept = true;
-  } else if ((st = run_step(c)) != QSA_OK) {
-    return st;
+  } else {
+    st = run_step(c);
+    c->resort_pending = false;
+    if (st != QSA_OK) return st;
   }
   c->cur_set = 0;
   return QSA_OK;
@@ -1819,6 +1887,7 @@ qsa_status qsa_load_beam(qsa_ctx* c, int32_t s, const double* x, const double* y
   }
   c->beam_n[s] = n;
   c->pipe_ok = true;
+  c->beam_steps = 0;   // a loaded beam is re-sorted by the next step
   c->drop_graphs();
   qsa_status st = dispatch(c, [&] { return Engine<double>::loaded(c, s); },
                            [&] { return Engine<float>::loaded(c, s); });
@@ -1854,6 +1923,7 @@ qsa_status qsa_load_beam_range(qsa_ctx* c, int32_t s, int64_t first, const doubl
   }
   c->beam_n[s] = first + n;
   c->pipe_ok = true;
+  c->beam_steps = 0;   // a loaded beam is re-sorted by the next step
   c->drop_graphs();
   if (c->L.nset > 1 && n > 0) {
     // load indices of the new particles; the sort by cell row waits for the
@@ -1965,6 +2035,23 @@ qsa_status qsa_set_option(qsa_ctx* c, int32_t option, int64_t value) {
   if (option == QSA_OPT_BESIDE_BLOCKS) {
     if (value < 0 || value > 65536) return fail(c, QSA_E_INVALID, "beside blocks: 0 .. 65536");
     c->beside_blocks = (int)value;
+    return QSA_OK;
+  }
+  if (option == QSA_OPT_RESORT_EVERY) {
+    if (value < 0) return fail(c, QSA_E_INVALID, "re-sort period must be >= 0");
+    if (value > 0 && c->L.nset > 1)
+      return fail(c, QSA_E_INVALID, "contexts with steps in flight sort their beam by cell row already");
+    if (value > 0) {
+      int64_t cap = 0;
+      for (int s = 0; s < c->p.n_species; ++s) cap = std::max<int64_t>(cap, c->p.beam_capacity[s]);
+      const size_t have = (c->p.precision == QSA_FP32) ? Engine<float>::resort_scratch(c)
+                                                       : Engine<double>::resort_scratch(c);
+      if ((size_t)cap * 8 > have)
+        return fail(c, QSA_E_INVALID,
+                    "re-sort: the largest beam capacity times 8 bytes exceeds the sources and fields it "
+                    "reuses as scratch (" + std::to_string(have) + " bytes)");
+    }
+    c->resort_every = value;
     return QSA_OK;
   }
   if (option == QSA_OPT_COL_THREADS) {
@@ -2123,6 +2210,10 @@ qsa_status qsa_get_option(const qsa_ctx* c, int32_t option, int64_t* value) {
   }
   if (option == QSA_OPT_BESIDE_BLOCKS) {
     *value = c->beside_blocks;
+    return QSA_OK;
+  }
+  if (option == QSA_OPT_RESORT_EVERY) {
+    *value = c->resort_every;
     return QSA_OK;
   }
   if (option == QSA_OPT_PLASMA_THREADS || option == QSA_OPT_ROW_THREADS || option == QSA_OPT_COL_THREADS) {

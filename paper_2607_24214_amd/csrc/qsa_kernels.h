@@ -1480,6 +1480,38 @@ __global__ void __launch_bounds__(256) k_beam_perm(Geo<R> g, BeamDepArgs<R> a, i
   if (act) a.perm[s][slot] = (int)p;
 }
 
+// Storage re-sort of the beam by deposit key: d0[i] = s0[perm[i]] (and
+// d1[i] = s1[perm[i]] when s1 is given), i < n, two beam arrays per pass of
+// the permutation; then perm can become the identity.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather_perm(const T* __restrict__ s0, const T* __restrict__ s1,
+                                                     T* __restrict__ d0, T* __restrict__ d1,
+                                                     const int* __restrict__ perm, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int q = perm[i];
+  d0[i] = s0[q];
+  if (s1) d1[i] = s1[q];
+}
+
+// dst[0, bytes) = src[0, bytes): 16-byte vectors (both 16-byte aligned),
+// the tail byte by byte.
+__global__ void __launch_bounds__(256) k_copy_bytes(const unsigned char* __restrict__ src,
+                                                    unsigned char* __restrict__ dst, int64_t bytes) {
+  typedef unsigned int U4 __attribute__((ext_vector_type(4)));
+  const int64_t nv = bytes >> 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride)
+    reinterpret_cast<U4*>(dst)[i] = reinterpret_cast<const U4*>(src)[i];
+  const int64_t t = (nv << 4) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < bytes) dst[t] = src[t];
+}
+
+__global__ void __launch_bounds__(256) k_iota32(int* __restrict__ v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (int)i;
+}
+
 // Sources of one beam particle: (rho - J_z, J_x, J_y, J_z) times Z w/dV, its
 // cell and offsets.
 template <typename R>

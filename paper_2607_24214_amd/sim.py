@@ -185,6 +185,12 @@ class Sim:
         as many as the work has)."""
         self._check(self.lib.qsa_set_option(self.ctx, 6, int(n)))
 
+    def set_resort_every(self, n: int):
+        """One step at a time: reorder the beam storage by deposit key before
+        every n-th beam step (0 = never); read_beam then returns particles in
+        storage order."""
+        self._check(self.lib.qsa_set_option(self.ctx, 7, int(n)))
+
     def set_shapes(self, plasma_threads: int = 0, row_threads: int = 0, col_threads: int = 0):
         """Launch shapes (0 = default): threads per plasma-row block, per
         row-transform block and per column transform."""
