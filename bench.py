@@ -414,7 +414,25 @@ def load_beam_in_ranges(sim, wl, slices_per_range: int = 8):
     return time.perf_counter() - t0
 
 
-def run_workload(wl, precision: str, pipeline: int, steps: int, warmup: int, args, with_extras: bool):
+def lean_depth(wl, precision: str, most: int = 5, spare_gib: float = 8.0) -> int:
+    """Most beam steps in flight (up to `most`) of a lean pipeline (no second
+    copy of the beam) whose workspace fits the device's free memory with
+    `spare_gib` to spare; 1 (one step at a time) if none does."""
+    import ctypes as C
+    import torch
+    import paper_2607_24214_amd as Q
+    free, _ = torch.cuda.mem_get_info()
+    lib = Q.lib()
+    for n in range(most, 1, -1):
+        p = Q.params_from_workload(wl, precision=precision, pipeline=n, lean_pipeline=True)
+        need = lib.qsa_workspace_bytes(C.byref(p))
+        if need and need + spare_gib * 2**30 <= free:
+            return n
+    return 1
+
+
+def run_workload(wl, precision: str, pipeline: int, steps: int, warmup: int, args, with_extras: bool,
+                 lean: bool = False):
     """Load a workload, warm up, time exactly `steps` beam steps; then the
     dominant kernel's launches with HIP events, the sweep alone and the
     diagnostics.  Returns the measurement dict."""
@@ -424,8 +442,9 @@ def run_workload(wl, precision: str, pipeline: int, steps: int, warmup: int, arg
     rsize = 8 if precision == "f64" else 4
     log(f"workload {wl.name}: {wl.nx}x{wl.ny}x{wl.nxi}, plasma {wl.n_plasma}/slice, "
         f"beam {wl.n_beam_total}, precision {precision}, steps in flight {pipeline}")
-    sim = Q.Sim(Q.params_from_workload(wl, precision=precision, pipeline=pipeline))
-    log(f"workspace {sim.ws_bytes / 2**30:.2f} GiB")
+    lean = pipeline > 1 and lean
+    sim = Q.Sim(Q.params_from_workload(wl, precision=precision, pipeline=pipeline, lean_pipeline=lean))
+    log(f"workspace {sim.ws_bytes / 2**30:.2f} GiB" + (" (lean pipeline: no second beam copy)" if lean else ""))
     t = time.perf_counter()
     sim.load_plasma(W.plasma_template(wl))
     if wl.n_beam_total > 1 << 28:
@@ -537,7 +556,7 @@ def run_workload(wl, precision: str, pipeline: int, steps: int, warmup: int, arg
                       "dx": wl.dx, "plasma_per_slice": wl.n_plasma, "beam_particles": wl.n_beam_total,
                       "species": [{"Z": sp.Z, "alpha": sp.alpha, "ppc": sp.ppc} for sp in wl.species],
                       "gamma_b": wl.gamma_b, "n_corr": wl.n_corr, "steps_in_flight": depth, "autotuned": tuned,
-                      "resort_every": resort,
+                      "resort_every": resort, "lean_pipeline": lean,
                       "step": f"beam source deposit + {wl.nxi}-slice sweep + Boris beam push"},
            "sweep_only": {"ms": 1e3 * t_sweep, "updates_per_s": wl.n_plasma * wl.nxi / t_sweep},
            "roofline": roofline, "diagnostics": diag}
@@ -555,7 +574,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["f64", "f32"],
                     help="default: the workload's (float32 for pair512, float64 for cube256)")
     ap.add_argument("--pipeline", type=int, default=None,
-                    help="beam steps in flight (1 = one at a time; default 1 for pair512, 8 otherwise)")
+                    help="beam steps in flight (1 = one at a time; default for pair512: a lean pipeline as deep "
+                         "as the device's memory allows, at most 5; 8 otherwise)")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time its launch shapes and steps in flight first")
     ap.add_argument("--pre-steps", type=int, default=0,
@@ -573,6 +593,9 @@ def main():
                     help="skip the extra entries (the 256^3-class workload in float64 and float32)")
     ap.add_argument("--beside-blocks", type=int, default=None,
                     help="workgroups per launch of the beam work beside the slice loop (0 = the work's)")
+    ap.add_argument("--lean", action="store_true",
+                    help="steps in flight without a second copy of the beam (with --pipeline > 1; the pair512 "
+                         "default is a lean pipeline as deep as memory allows, at most 5)")
     ap.add_argument("--resort-every", type=int, default=None,
                     help="one step at a time: reorder the beam storage by deposit key every n steps (0 = never; "
                          f"default {RESORT_EVERY})")
@@ -630,8 +653,16 @@ def main():
     wl = W.CONFIGS[args.workload]()
     precision = args.precision or wl.precision
     wl = wl.with_(precision=precision)
-    pipeline = args.pipeline if args.pipeline is not None else (1 if args.workload == "pair512" else 8)
-    head = run_workload(wl, precision, pipeline, args.steps, args.warmup, args, with_extras=True)
+    if args.pipeline is not None:
+        pipeline, lean = args.pipeline, args.lean
+    elif args.workload == "pair512":
+        # the beam (128 GiB) cannot be held twice: as many lean steps in
+        # flight as the device's memory holds
+        pipeline = lean_depth(wl, precision)
+        lean = pipeline > 1
+    else:
+        pipeline, lean = 8, args.lean
+    head = run_workload(wl, precision, pipeline, args.steps, args.warmup, args, with_extras=True, lean=lean)
 
     extra = {}
     if not args.no_extra and args.workload != "cube256":

@@ -109,8 +109,9 @@ typedef struct {
   int64_t beam_capacity[QSA_MAX_SPECIES]; /* max particles per species (>= 0) */
   int32_t pipeline;      /* beam steps in flight in qsa_beam_step, 0..16 (0 and 1:
                             one step at a time).  With P > 1 the workspace holds
-                            P working sets (sources, fields, plasma state) and a
-                            copy of the beam; see qsa_beam_step.             */
+                            P working sets (sources, fields, plasma state) and,
+                            unless lean_pipeline, a copy of the beam; see
+                            qsa_beam_step.                                   */
   int32_t adjoint_steps; /* 0, or the most beam steps qsa_adjoint_sweep will
                             differentiate (the workspace then holds the beam
                             and the 7 field planes for every step, plasma
@@ -133,6 +134,24 @@ typedef struct {
                             extreme blazar jet regimes" section), loaded
                             with qsa_load_plasma_weights (until then all
                             plasma_w).  qsa_adjoint_sweep requires 0.      */
+  int32_t lean_pipeline; /* with pipeline > 1: 0 keeps a second copy of the
+                            beam (the group's sort target, the state a group
+                            that breaks the drift schedule is repeated from
+                            one step at a time, and the load order that
+                            qsa_read_beam returns); 1 keeps none, for beams
+                            too large to hold twice: each group's sort by
+                            cell row gathers every beam array through the
+                            sources and stored fields of working set 0 (so
+                            the largest beam_capacity times 8 bytes must fit
+                            in (4 + 7) nxi ny nx working-precision values,
+                            else the parameters are invalid), qsa_read_beam
+                            returns the particles in storage order (cell-row
+                            order after a group), qsa_autotune does not try
+                            steps in flight, and a group that breaks the
+                            drift schedule fails with QSA_E_STATE (the beam
+                            is then lost: the context keeps the error).
+                            Not with adjoint_steps > 0.  Ignored with
+                            pipeline <= 1.                                  */
 } qsa_params;
 
 /* Bytes of device workspace a context with these parameters needs; 0 if the

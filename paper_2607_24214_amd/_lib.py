@@ -52,6 +52,7 @@ class QSAParams(C.Structure):
         ("beam_capacity", C.c_int64 * QSA_MAX_SPECIES),
         ("pipeline", C.c_int32), ("adjoint_steps", C.c_int32), ("ckpt_every", C.c_int32),
         ("no_field_pack", C.c_int32), ("plasma_weights", C.c_int32),
+        ("lean_pipeline", C.c_int32),
     ]
 
 

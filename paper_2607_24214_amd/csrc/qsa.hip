@@ -136,6 +136,7 @@ struct Layout {
   size_t tmpl[4];
   size_t tmpl_qw;                   // template relative weights (plasma_weights)
   int nset;                         // working sets (beam steps in flight)
+  bool lean;                        // steps in flight without a second copy of the beam
   SetLayout set[QSA_MAX_PIPELINE];
   size_t rowoff[QSA_MAX_SPECIES];   // slab partition of the sorted beam (pipelining)
   size_t doff[QSA_MAX_SPECIES];     // sort-key offsets into perm of the current deposit
@@ -160,6 +161,9 @@ struct Carver {
   }
 };
 
+// Blocks of the key, permutation and gather passes over n beam particles.
+unsigned beam_blocks(int64_t n) { return (unsigned)((n + 256 * QSA_BEAM_UNROLL - 1) / (256 * QSA_BEAM_UNROLL)); }
+
 int pipeline_depth(const qsa_params& p) { return std::max(1, (int)p.pipeline); }
 
 // bytes of one node's packed beam-push fields (element size rs)
@@ -183,6 +187,7 @@ Layout make_layout(const qsa_params& p) {
   for (int i = 0; i < 4; ++i) L.tmpl[i] = c.take(p.n_plasma * (i < 2 ? 8 : rs));
   L.tmpl_qw = p.plasma_weights ? c.take(p.n_plasma * rs) : 0;
   L.nset = pipeline_depth(p);
+  L.lean = L.nset > 1 && p.lean_pipeline;
   for (int k = 0; k < L.nset; ++k) {
     SetLayout& S = L.set[k];
     for (int i = 0; i < 4; ++i) S.pl[i] = c.take(p.n_plasma * (i < 2 ? 8 : rs));
@@ -232,7 +237,7 @@ Layout make_layout(const qsa_params& p) {
     const size_t cap = (s < p.n_species) ? (size_t)p.beam_capacity[s] : 0;
     for (int k = 0; k < 6; ++k) L.beam[s][k] = c.take(cap * rs);
     L.beam[s][6] = c.take(cap * 8);
-    if (L.nset > 1) {
+    if (L.nset > 1 && !L.lean) {
       L.beam[s][7] = c.take(cap * 8);
       for (int k = 0; k < 6; ++k) L.snap[s][k] = c.take(cap * rs);
       L.snap[s][6] = c.take(cap * 8);
@@ -271,6 +276,18 @@ const char* validate(const qsa_params* p) {
   if (p->ckpt_every < 0 || p->ckpt_every > p->nxi) return "ckpt_every must be in [0, nxi]";
   if (p->no_field_pack != 0 && p->no_field_pack != 1) return "no_field_pack must be 0 or 1";
   if (p->plasma_weights != 0 && p->plasma_weights != 1) return "plasma_weights must be 0 or 1";
+  if (p->lean_pipeline != 0 && p->lean_pipeline != 1) return "lean_pipeline must be 0 or 1";
+  if (p->lean_pipeline && p->pipeline > 1 && p->adjoint_steps > 0)
+    return "lean_pipeline: the adjoint's bins follow the load order, which a lean pipeline does not keep";
+  if (p->lean_pipeline && p->pipeline > 1) {
+    // the group's sort gathers every beam array through the sources and
+    // stored fields of working set 0
+    const size_t rs = (p->precision == QSA_FP32) ? 4 : 8;
+    const size_t scratch = (size_t)(4 + N_STORED) * p->nxi * p->ny * p->nx * rs;
+    for (int s = 0; s < p->n_species; ++s)
+      if ((size_t)std::max<int64_t>(p->beam_capacity[s], 0) * 8 > scratch)
+        return "lean_pipeline: a beam capacity times 8 bytes exceeds the sources and fields of one working set";
+  }
   for (int s = 0; s < p->n_species; ++s) {
     if (p->beam_capacity[s] < 0 || p->beam_capacity[s] > INT32_MAX) return "beam capacity must be in [0, 2^31)";
     if (!(p->species[s].M > 0)) return "species mass must be > 0";
@@ -591,13 +608,13 @@ struct Engine {
       hipLaunchKernelGGL(k_counts_or_zero, dim3(fill_blocks(nkeys + 1)), dim3(256), 0, c->stream, valid,
                          (const int64_t*)c->at<int64_t>(c->L.cnt_next[s]), off, nkeys + 1);
       if (n > 0)
-        hipLaunchKernelGGL(k_beam_keys<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
+        hipLaunchKernelGGL(k_beam_keys<R>, dim3(beam_blocks(n)), dim3(256), 0, c->stream, g,
                            beam_dep_args(c), s, n, off, valid);
     } else {
       hipLaunchKernelGGL(k_fill<int64_t>, dim3(fill_blocks(nkeys + 1)), dim3(256), 0, c->stream, off, nkeys + 1,
                          (int64_t)0);
       if (n > 0)
-        hipLaunchKernelGGL(k_beam_keys<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
+        hipLaunchKernelGGL(k_beam_keys<R>, dim3(beam_blocks(n)), dim3(256), 0, c->stream, g,
                            beam_dep_args(c), s, n, off, (const int*)nullptr);
     }
     HIP_OK(hipGetLastError());
@@ -621,6 +638,14 @@ struct Engine {
                        geo(p), (const int64_t*)c->at<int64_t>(L.doff[s]), c->at<int64_t>(L.rowoff[s]));
     HIP_OK(hipGetLastError());
     if (n == 0) return QSA_OK;
+    if (L.lean) {
+      // no second copy of the beam: the permutation to key order, then
+      // every array gathered through it in place (via set 0's scratch)
+      hipLaunchKernelGGL(k_beam_perm<R>, dim3(beam_blocks(n)), dim3(256), 0, c->stream, geo(p), beam_dep_args(c), s,
+                         n, c->at<int64_t>(L.cursor));
+      HIP_OK(hipGetLastError());
+      return resort_species(c, s);
+    }
     BeamMove<R> m;
     for (int k = 0; k < 6; ++k) {
       m.src[k] = c->at<R>(L.beam[s][k]);
@@ -645,7 +670,7 @@ struct Engine {
   static qsa_status loaded(qsa_ctx* c, int s) {
     if (c->L.nset < 2) return QSA_OK;
     const int64_t n = c->beam_n[s];
-    if (n > 0) {
+    if (n > 0 && !c->L.lean) {
       hipLaunchKernelGGL(k_iota64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
                          c->at<int64_t>(c->L.beam[s][7]), n);
       HIP_OK(hipGetLastError());
@@ -673,7 +698,7 @@ struct Engine {
       if (st != QSA_OK) return st;
       const int64_t n = c->beam_n[s];
       if (n > 0)
-        hipLaunchKernelGGL(k_beam_perm<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
+        hipLaunchKernelGGL(k_beam_perm<R>, dim3(beam_blocks(n)), dim3(256), 0, c->stream, g,
                            beam_dep_args(c), s, n, c->at<int64_t>(c->L.cursor));
       if (resort && (st = resort_species(c, s)) != QSA_OK) return st;
     }
@@ -712,7 +737,7 @@ struct Engine {
     char* tmp = c->ws + c->L.set[0].src;
     const int64_t npad = (n + 63) / 64 * 64;   // the second plane 256-byte aligned
     const bool two = 2 * (size_t)npad * sizeof(R) <= resort_scratch(c);
-    const dim3 grid((unsigned)((n + 255) / 256));
+    const dim3 grid(beam_blocks(n));
     int* perm = c->at<int>(c->L.perm[s]);
     auto copy_back = [&](char* dst, const char* src, int64_t bytes) {
       const int64_t blocks = std::min<int64_t>(std::max<int64_t>(((bytes >> 4) + 255) / 256, 1), 1 << 18);
@@ -733,7 +758,7 @@ struct Engine {
     hipLaunchKernelGGL(k_gather_perm<double>, grid, dim3(256), 0, c->stream, (const double*)xi,
                        (const double*)nullptr, (double*)tmp, (double*)nullptr, (const int*)perm, n);
     copy_back((char*)xi, (const char*)tmp, n * (int64_t)sizeof(double));
-    hipLaunchKernelGGL(k_iota32, grid, dim3(256), 0, c->stream, perm, n);
+    hipLaunchKernelGGL(k_iota32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, perm, n);
     HIP_OK(hipGetLastError());
     return QSA_OK;
   }
@@ -1347,7 +1372,7 @@ struct Engine {
   // identity straight into a device destination, or through the sort buffer
   // for a host one.
   static qsa_status read_beam_array(qsa_ctx* c, int s, int k, double* dst, int64_t n, int on_device) {
-    if (c->L.nset < 2) return download(c, c->ws + c->L.beam[s][k], dst, n, on_device, k == 6);
+    if (c->L.nset < 2 || c->L.lean) return download(c, c->ws + c->L.beam[s][k], dst, n, on_device, k == 6);
     if (n == 0) return QSA_OK;
     double* out = on_device ? dst : c->at<double>(c->L.snap[s][6]);
     const int64_t* id = c->at<int64_t>(c->L.beam[s][7]);
@@ -1650,6 +1675,12 @@ qsa_status step_group(qsa_ctx* c, int n, bool graphs, bool* done) {
   HIP_OK(hipStreamSynchronize(c->stream));
   int e = 0;
   HIP_OK(hipMemcpy(&e, c->ws + c->L.err, sizeof(int), hipMemcpyDeviceToHost));
+  if ((e & ERR_DRIFT) && c->L.lean) {
+    c->sticky = QSA_E_STATE;
+    return fail(c, QSA_E_STATE,
+                "beam particles drifted beyond the steps-in-flight schedule, and a lean pipeline keeps no copy "
+                "of the beam to repeat the group from");
+  }
   if (e & ERR_DRIFT) {
     st = dispatch(c, [&] { return Engine<double>::restore(c); }, [&] { return Engine<float>::restore(c); });
     if (st != QSA_OK) return st;
@@ -1925,7 +1956,7 @@ qsa_status qsa_load_beam_range(qsa_ctx* c, int32_t s, int64_t first, const doubl
   c->pipe_ok = true;
   c->beam_steps = 0;   // a loaded beam is re-sorted by the next step
   c->drop_graphs();
-  if (c->L.nset > 1 && n > 0) {
+  if (c->L.nset > 1 && !c->L.lean && n > 0) {
     // load indices of the new particles; the sort by cell row waits for the
     // next group of steps in flight, which starts with it
     hipLaunchKernelGGL(k_iota64_from, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
@@ -2083,7 +2114,9 @@ qsa_status qsa_autotune(qsa_ctx* c, double* ms_per_step) {
     (void)hipEventDestroy(e0);
     return fail(c, QSA_E_DEVICE, "hipEventCreate failed");
   }
-  const int depth0 = (c->L.nset > 1 && c->pipe_ok) ? c->L.nset : 1;
+  // (trials with steps in flight put the beam back from its copy: none in a
+  // lean pipeline)
+  const int depth0 = (c->L.nset > 1 && c->pipe_ok && !c->L.lean) ? c->L.nset : 1;
   auto run = [&](int n, float* ms) {
     return dispatch(c, [&] { return Engine<double>::trial(c, n, e0, e1, ms); },
                     [&] { return Engine<float>::trial(c, n, e0, e1, ms); });
@@ -2175,7 +2208,7 @@ qsa_status qsa_adjoint_sweep(qsa_ctx* c, int32_t n_steps, int32_t n_bins, const 
     const int64_t n = c->beam_n[s];
     if (n == 0) continue;
     int* dst = c->at<int>(A.bin[s]);
-    if (c->L.nset > 1) {
+    if (c->L.nset > 1 && !c->L.lean) {
       // the library keeps this beam sorted: bins follow each particle's load index
       int* tmp = c->at<int>(A.bb[s][0]);
       HIP_OK(hipMemcpy(tmp, bins[s], n * sizeof(int), hipMemcpyHostToDevice));

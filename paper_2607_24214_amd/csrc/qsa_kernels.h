@@ -1398,6 +1398,37 @@ __device__ __forceinline__ T wave_run_add(T* cnt, int key, bool active) {
   return base + (T)(lane - head);
 }
 
+// U independent wave_run_add's (U groups of 64 particles per wavefront),
+// their atomics issued back to back before any result is waited for: one
+// wavefront then keeps U round trips to the counters in flight.
+template <typename T, int U>
+__device__ __forceinline__ void wave_run_add_u(T* cnt, const int (&key)[U], const bool (&active)[U],
+                                               T (&out)[U]) {
+  const int lane = threadIdx.x & 63;
+  int head[U];
+  T base[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = active[u] ? key[u] : -1;
+    const int prev = __shfl_up(k, 1);
+    const bool brk = (lane == 0) || (prev != k);
+    const unsigned long long b = __ballot(brk);
+    const unsigned long long above = (lane == 63) ? 0ull : (b >> (lane + 1)) << (lane + 1);
+    const int next = above ? __ffsll((long long)above) - 1 : 64;
+    const unsigned long long upto = (lane == 63) ? b : (b & ((2ull << lane) - 1ull));
+    head[u] = 63 - __clzll((long long)upto);
+    base[u] = 0;
+    if (active[u] && brk) base[u] = lane_atomic_add(cnt + key[u], (T)(next - lane));
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) out[u] = __shfl(base[u], head[u]) + (T)(lane - head[u]);
+}
+
+// Particles per thread of the key, permutation and gather passes over the
+// beam (consecutive blocks of 256 per unroll step: coalesced, and U loads and
+// counter round trips in flight per wavefront instead of one).
+#define QSA_BEAM_UNROLL 4
+
 // Sort key of a beam particle: cell row (j, l), j = floor(xi/dxi), then the
 // chunk of QSA_BEAM_XCHUNK cells along x holding its cell, so that a
 // wavefront of sorted particles gathers and deposits around a few cells.  A
@@ -1451,47 +1482,77 @@ struct BeamDepArgs {
 };
 
 // Keys of species s and their counts per row (cnt zeroed by the caller);
-// nothing when *skip is set (the counts are already there).
+// nothing when *skip is set (the counts are already there).  Block b takes
+// particles [b, b + 1) * 256 * QSA_BEAM_UNROLL.
 template <typename R>
 __global__ void __launch_bounds__(256) k_beam_keys(Geo<R> g, BeamDepArgs<R> a, int s, int64_t n,
                                                    int64_t* __restrict__ cnt, const int* __restrict__ skip) {
   if (skip && *skip) return;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool act = p < n;
-  int key = 0;
-  if (act) {
-    key = beam_key(g, a.x[s][p], a.y[s][p], a.xi[s][p], a.w[s][p], a.inv_dxi);
-    if (a.key[s]) a.key[s][p] = key;
+  constexpr int U = QSA_BEAM_UNROLL;
+  const int64_t p0 = (int64_t)blockIdx.x * (256 * U) + threadIdx.x;
+  int key[U];
+  bool act[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t p = p0 + 256 * u;
+    act[u] = p < n;
+    key[u] = act[u] ? beam_key(g, a.x[s][p], a.y[s][p], a.xi[s][p], a.w[s][p], a.inv_dxi) : 0;
+    if (act[u] && a.key[s]) a.key[s][p] = key[u];
   }
-  (void)wave_run_add(cnt, key, act);
+#pragma unroll
+  for (int u = 0; u < U; ++u) (void)wave_run_add(cnt, key[u], act[u]);
 }
 
 // Particle indices grouped by key: cur holds the exclusive offsets on entry.
+// Block b takes particles [b, b + 1) * 256 * QSA_BEAM_UNROLL.
 template <typename R>
 __global__ void __launch_bounds__(256) k_beam_perm(Geo<R> g, BeamDepArgs<R> a, int s, int64_t n,
                                                    int64_t* __restrict__ cur) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool act = p < n;
-  // the key kept by k_beam_keys, or the same key again (contexts without
-  // steps in flight keep no key array)
-  const int key = act ? (a.key[s] ? a.key[s][p] : beam_key(g, a.x[s][p], a.y[s][p], a.xi[s][p], a.w[s][p], a.inv_dxi))
-                      : 0;
-  const int64_t slot = wave_run_add(cur, key, act);
-  if (act) a.perm[s][slot] = (int)p;
+  constexpr int U = QSA_BEAM_UNROLL;
+  const int64_t p0 = (int64_t)blockIdx.x * (256 * U) + threadIdx.x;
+  int key[U];
+  bool act[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t p = p0 + 256 * u;
+    act[u] = p < n;
+    // the key kept by k_beam_keys, or the same key again (contexts without
+    // steps in flight keep no key array)
+    key[u] = act[u] ? (a.key[s] ? a.key[s][p] : beam_key(g, a.x[s][p], a.y[s][p], a.xi[s][p], a.w[s][p], a.inv_dxi))
+                    : 0;
+  }
+  int64_t slot[U];
+  wave_run_add_u<int64_t, U>(cur, key, act, slot);
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (act[u]) a.perm[s][slot[u]] = (int)(p0 + 256 * u);
 }
 
 // Storage re-sort of the beam by deposit key: d0[i] = s0[perm[i]] (and
 // d1[i] = s1[perm[i]] when s1 is given), i < n, two beam arrays per pass of
-// the permutation; then perm can become the identity.
+// the permutation; then perm can become the identity.  Block b takes
+// elements [b, b + 1) * 256 * QSA_BEAM_UNROLL.
 template <typename T>
 __global__ void __launch_bounds__(256) k_gather_perm(const T* __restrict__ s0, const T* __restrict__ s1,
                                                      T* __restrict__ d0, T* __restrict__ d1,
                                                      const int* __restrict__ perm, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int q = perm[i];
-  d0[i] = s0[q];
-  if (s1) d1[i] = s1[q];
+  constexpr int U = QSA_BEAM_UNROLL;
+  const int64_t i0 = (int64_t)blockIdx.x * (256 * U) + threadIdx.x;
+  int q[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) q[u] = (i0 + 256 * u < n) ? perm[i0 + 256 * u] : -1;
+  T v0[U], v1[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    v0[u] = (q[u] >= 0) ? s0[q[u]] : T(0);
+    v1[u] = (q[u] >= 0 && s1) ? s1[q[u]] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (q[u] < 0) continue;
+    d0[i0 + 256 * u] = v0[u];
+    if (s1) d1[i0 + 256 * u] = v1[u];
+  }
 }
 
 // dst[0, bytes) = src[0, bytes): 16-byte vectors (both 16-byte aligned),

@@ -34,14 +34,15 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
                 beam_capacity: Sequence[int], precision: str = "f64", n_corr: int = 3,
                 kappa2: float = 0.75, pipeline: int = 1, adjoint_steps: int = 0,
                 ckpt_every: int = 0, field_pack: bool = True,
-                plasma_weights: bool = False) -> L.QSAParams:
+                plasma_weights: bool = False, lean_pipeline: bool = False) -> L.QSAParams:
     """species: sequence of (Z, M); pipeline: beam steps in flight (1 = off);
     adjoint_steps: most steps qsa_adjoint_sweep differentiates (0 = none);
     ckpt_every: the adjoint's plasma checkpoint stride in slices (0 = 16);
     field_pack: keep the push's fields packed for every slice (without steps
     in flight; False saves 32-48 bytes per cell); plasma_weights: keep a
     weight per plasma macro-particle (Sim.load_plasma loads them when the
-    template's "w" is an array)."""
+    template's "w" is an array); lean_pipeline: steps in flight without a
+    second copy of the beam (read_beam then returns storage order)."""
     p = L.QSAParams()
     p.nx, p.ny, p.nxi = nx, ny, nxi
     p.precision = _PREC[precision]
@@ -54,6 +55,7 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
     p.ckpt_every = int(ckpt_every)
     p.no_field_pack = 0 if field_pack else 1
     p.plasma_weights = 1 if plasma_weights else 0
+    p.lean_pipeline = 1 if lean_pipeline else 0
     for i, (Z, M) in enumerate(species):
         p.species[i].Z = int(Z)
         p.species[i].M = float(M)
@@ -64,7 +66,8 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
 def params_from_workload(wl, precision: Optional[str] = None,
                          beam_capacity: Optional[Sequence[int]] = None,
                          pipeline: int = 1, adjoint_steps: int = 0,
-                         ckpt_every: Optional[int] = None, field_pack: bool = True) -> L.QSAParams:
+                         ckpt_every: Optional[int] = None, field_pack: bool = True,
+                         lean_pipeline: bool = False) -> L.QSAParams:
     """Parameters of a workload description (duck-typed: grid, species, loading)."""
     caps = beam_capacity or [wl.n_beam(s) for s in range(len(wl.species))]
     ck = getattr(wl, "ckpt_every", 0) if ckpt_every is None else ckpt_every
@@ -72,7 +75,7 @@ def params_from_workload(wl, precision: Optional[str] = None,
                        [(s.Z, s.M) for s in wl.species], wl.n_plasma,
                        wl.dx * wl.dy / wl.plasma_ppc, caps, precision or wl.precision,
                        wl.n_corr, wl.kappa2, pipeline, adjoint_steps, min(int(ck), wl.nxi), field_pack,
-                       getattr(wl, "plasma_w_spread", 0.0) > 0.0)
+                       getattr(wl, "plasma_w_spread", 0.0) > 0.0, lean_pipeline)
 
 
 class Sim:
