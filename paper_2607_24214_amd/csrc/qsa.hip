@@ -689,11 +689,13 @@ struct Engine {
   // Beam sources: particles grouped by cell row (keys, their offsets and a
   // permutation), each row deposited by one block into the dense sources
   // (four launches by the parity of the row, see k_beam_rows).
-  static qsa_status beam_perm_all(qsa_ctx* c, const Geo<R>& g) {
+  // sorted: the storage is in key order already, with the identity in perm
+  // and the key offsets in doff (a lean group's sort has just made them).
+  static qsa_status beam_perm_all(qsa_ctx* c, const Geo<R>& g, bool sorted = false) {
     const qsa_params& p = c->p;
     const bool resort = c->resort_pending;   // set by a single step that is due for it
     c->resort_pending = false;
-    for (int s = 0; s < p.n_species; ++s) {
+    for (int s = 0; s < p.n_species && !sorted; ++s) {
       qsa_status st = keys(c, s);
       if (st != QSA_OK) return st;
       const int64_t n = c->beam_n[s];
@@ -779,8 +781,8 @@ struct Engine {
     return QSA_OK;
   }
 
-  static qsa_status beam_deposit_all(qsa_ctx* c, const Geo<R>& g) {
-    qsa_status st = beam_perm_all(c, g);
+  static qsa_status beam_deposit_all(qsa_ctx* c, const Geo<R>& g, bool sorted = false) {
+    qsa_status st = beam_perm_all(c, g, sorted);
     if (st != QSA_OK) return st;
     R* src = c->at<R>(c->L.set[0].src);
     if ((st = fill(c, src, 4 * (int64_t)c->p.nxi * g.nperp, R(0))) != QSA_OK) return st;
@@ -1209,10 +1211,12 @@ struct Engine {
     const qsa_params& p = c->p;
     const Layout& L = c->L;
     const Geo<R> g = geo(p);
-    // the beam sorted by cell row; the sort buffer keeps a copy of it
+    // the beam sorted by cell row; the sort buffer keeps a copy of it (a
+    // lean sort instead leaves the storage in key order with the identity
+    // permutation, which the first deposit then uses as it stands)
     qsa_status st = sort_all(c);
     if (st != QSA_OK) return st;
-    if ((st = beam_deposit_all(c, g)) != QSA_OK) return st;   // lane 0's sources
+    if ((st = beam_deposit_all(c, g, L.lean)) != QSA_OK) return st;   // lane 0's sources
     for (int k = 1; k < n; ++k)
       if ((st = fill(c, c->at<R>(L.set[k].src), 4 * (int64_t)p.nxi * g.nperp, R(0))) != QSA_OK) return st;
     Dims d = dims_of(c);
