@@ -1244,7 +1244,7 @@ struct Engine {
       QSA_LAUNCH(c, QSA_K_BEAM_PUSH, k_pipe_push<R>, dim3(g.ny, 1, n), dim3(256), 0, bs, pipes, t, n);
       hipLaunchKernelGGL(k_pipe_scan<R>, dim3(g.ny, 1, n - 1), dim3(256), 0, bs, pipes, t, n);
       hipLaunchKernelGGL(k_pipe_place<R>, dim3(g.ny, 1, n - 1), dim3(256), 0, bs, pipes, t, n);
-      QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_pipe_deposit<R>, dim3(g.ny, 1, n - 1), dim3(256),
+      QSA_LAUNCH(c, QSA_K_BEAM_DEPOSIT, k_pipe_deposit<R>, dim3(g.ny, 1, n - 1), dim3(BeamRowBlock<R>::THREADS),
                  tile + (g.ny + 1 + 16) * sizeof(int), bs, pipes, t, n);
       hipLaunchKernelGGL(k_pipe_reduce<R>, dim3(nperp_blocks, 1, n - 1), dim3(256), 0, bs, pipes, t, n);
       HIP_OK(hipEventRecord(c->gdone[t % QSA_GEV], bs));

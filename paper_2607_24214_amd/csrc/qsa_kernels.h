@@ -2358,7 +2358,8 @@ __global__ void __launch_bounds__(256) k_pipe_place(const PipeBeam<R>* __restric
 
 // Block L deposits the particles now in cell row (jp, L).
 template <typename R>
-__global__ void __launch_bounds__(256) k_pipe_deposit(const PipeBeam<R>* __restrict__ tab, int tick, int nlanes) {
+__global__ void __launch_bounds__(BeamRowBlock<R>::THREADS) k_pipe_deposit(const PipeBeam<R>* __restrict__ tab,
+                                                                             int tick, int nlanes) {
   int lane, L;
   lane_block(lane, L);
   if (lane + 1 >= nlanes) return;   // the last lane feeds no one
