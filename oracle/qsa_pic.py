@@ -21,6 +21,11 @@ d_z -> -d_xi; the linearized forms are the paper's Eqs. (1)-(2)):
   lap B_z  = d_y J_x - d_x J_y         lap E_z = div J_perp
   lap B_x  = -d_y J_z - d_xi J_y       lap B_y = d_x J_z + d_xi J_x
   E_x = -d_x psi + B_y,  E_y = -d_y psi - B_x.
+A uniform external magnetic field B_0 along the propagation axis (the
+guide field of a magnetized plasma, one of the paper's outlook items) adds
+to B_z wherever a particle is pushed; it is static and curl-free, so it is
+no source of the wake, and it exerts no force along z, so the invariant
+below still holds.
 Plasma electrons conserve gamma - u_z = 1 + psi =: G, so in xi
   dx_perp/dxi = u_perp/G,
   du_x/dxi = gamma d_x psi/G - B_y - u_y B_z/G,
@@ -217,11 +222,13 @@ def _check_g(G: torch.Tensor):
         raise QSABreakdown("1 + psi <= %g or non-finite at a plasma particle" % BREAKDOWN_G)
 
 
-def plasma_rhs(g: Grid, F: Sequence[torch.Tensor], x, y, ux, uy):
+def plasma_rhs(g: Grid, F: Sequence[torch.Tensor], x, y, ux, uy, b0z: float = 0.0):
     """d/dxi of (x, y, u_x, u_y) with the six fields F = (psi, dxpsi, dypsi,
-    Bx, By, Bz) gathered at the particle."""
+    Bx, By, Bz) gathered at the particle; b0z is a uniform external magnetic
+    field along the propagation axis, added to the wake's B_z."""
     st = Stencil2(g, x, y)
     psi, dxp, dyp, bx, by, bz = (st.gather(f) for f in F)
+    bz = bz + b0z
     G = 1.0 + psi
     _check_g(G)
     gam = (1.0 + ux * ux + uy * uy + G * G) / (2.0 * G)
@@ -230,11 +237,11 @@ def plasma_rhs(g: Grid, F: Sequence[torch.Tensor], x, y, ux, uy):
             gam * dyp / G + bx + ux * bz / G)
 
 
-def rk2(g: Grid, h: float, Fa, Fb, Y):
+def rk2(g: Grid, h: float, Fa, Fb, Y, b0z: float = 0.0):
     """Midpoint rule: Y* = Y + (h/2) f(Y; Fa), Y' = Y + h f(Y*; Fb)."""
-    k1 = plasma_rhs(g, Fa, *Y)
+    k1 = plasma_rhs(g, Fa, *Y, b0z=b0z)
     Ys = tuple(a + 0.5 * h * b for a, b in zip(Y, k1))
-    k2 = plasma_rhs(g, Fb, *Ys)
+    k2 = plasma_rhs(g, Fb, *Ys, b0z=b0z)
     return tuple(a + h * b for a, b in zip(Y, k2))
 
 
@@ -243,11 +250,13 @@ def rk2(g: Grid, h: float, Fa, Fb, Y):
 # ---------------------------------------------------------------------------
 
 def slice_sweep(g: Grid, plasma: Dict, sources: torch.Tensor, n_corr: int = 3,
-                kappa2: float = 0.75, stats: Optional[Dict] = None) -> torch.Tensor:
+                kappa2: float = 0.75, stats: Optional[Dict] = None, b0z: float = 0.0) -> torch.Tensor:
     """Quasistatic plasma response to the given beam sources.
 
     plasma: template dict with x, y, ux, uy (tensors) and scalar w.
     sources: [4, nxi, ny, nx] beam (rho - J_z, J_x, J_y, J_z).
+    b0z: uniform external magnetic field along the propagation axis (it
+    enters the plasma push only; the stored B_z is the wake's).
     Returns fields [7, nxi, ny, nx] = psi, d_x psi, d_y psi, E_z, B_x, B_y, B_z.
     """
     sp = Spectral(g)
@@ -301,7 +310,7 @@ def slice_sweep(g: Grid, plasma: Dict, sources: torch.Tensor, n_corr: int = 3,
         for _ in range(n_corr):
             Fj = [psi, dxpsi, dypsi, Bx, By, Bz]
             Fh = [0.5 * (3.0 * a - b) for a, b in zip(Fj, Fm1)]
-            xt, yt, uxt, uyt = rk2(g, h, Fj, Fh, Y)
+            xt, yt, uxt, uyt = rk2(g, h, Fj, Fh, Y, b0z)
             stt = Stencil2(g, xt, yt)
             Gt = 1.0 + stt.gather(psi_p1)
             _check_g(Gt)
@@ -314,7 +323,7 @@ def slice_sweep(g: Grid, plasma: Dict, sources: torch.Tensor, n_corr: int = 3,
         # -- final advance to j+1 ---------------------------------------------
         Fj = [psi, dxpsi, dypsi, Bx, By, Bz]
         Fh = [0.5 * (3.0 * a - b) for a, b in zip(Fj, Fm1)]
-        x, y, ux, uy = rk2(g, h, Fj, Fh, Y)
+        x, y, ux, uy = rk2(g, h, Fj, Fh, Y, b0z)
         x = wrap(x, g.lx)
         y = wrap(y, g.ly)
         for f, v in zip((PSI, DXPSI, DYPSI, EZ, BX, BY, BZ),
@@ -389,11 +398,13 @@ def beam_sources(g: Grid, species: Sequence[Dict], Zs: Sequence[int]) -> torch.T
     return out
 
 
-def boris_push(g: Grid, b: Dict, Z: int, M: float, fields: torch.Tensor, dt: float) -> Dict:
+def boris_push(g: Grid, b: Dict, Z: int, M: float, fields: torch.Tensor, dt: float,
+               b0z: float = 0.0) -> Dict:
     """Advance one beam species by dt in the stored 3D fields (Boris 1970).
 
-    E = (-d_x psi + B_y, -d_y psi - B_x, E_z), B = (B_x, B_y, B_z) from the 3D
-    linear shape (zero outside the xi grid).  Positions use the new momentum;
+    E = (-d_x psi + B_y, -d_y psi - B_x, E_z), B = (B_x, B_y, B_z + b0z) from
+    the 3D linear shape (zero outside the xi grid) plus the uniform external
+    field b0z along the propagation axis.  Positions use the new momentum;
     dxi/dtau = 1 - v_z.  A particle reaching xi >= (nxi-1) dxi leaves the box:
     its weight becomes 0.
     """
@@ -405,7 +416,7 @@ def boris_push(g: Grid, b: Dict, Z: int, M: float, fields: torch.Tensor, dt: flo
     ez = st.gather(fields[EZ])
     bx = st.gather(fields[BX])
     by = st.gather(fields[BY])
-    bz = st.gather(fields[BZ])
+    bz = st.gather(fields[BZ]) + b0z
     ex = -dxp + by
     ey = -dyp - bx
     qh = (Z / M) * 0.5 * dt
@@ -461,15 +472,16 @@ class Sim:
         self.beams = [to_torch(b) for b in beams]
         self.Z = [s.Z for s in wl.species]
         self.M = [s.M for s in wl.species]
+        self.b0z = float(getattr(wl, "b0z", 0.0))
         self.fields = None
 
     def sweep(self) -> torch.Tensor:
         src = beam_sources(self.g, self.beams, self.Z)
-        self.fields = slice_sweep(self.g, self.plasma, src, self.wl.n_corr, self.wl.kappa2)
+        self.fields = slice_sweep(self.g, self.plasma, src, self.wl.n_corr, self.wl.kappa2, b0z=self.b0z)
         return self.fields
 
     def push(self):
-        self.beams = [boris_push(self.g, b, Z, M, self.fields, self.wl.dt)
+        self.beams = [boris_push(self.g, b, Z, M, self.fields, self.wl.dt, self.b0z)
                       for b, Z, M in zip(self.beams, self.Z, self.M)]
 
     def beam_step(self, n: int = 1):

@@ -71,6 +71,7 @@ class Workload:
     precision: str = "f64"
     n_bins: int = 0          # piecewise-constant xi amplitude bins (adjoint workload)
     ckpt_every: int = 16
+    b0z: float = 0.0         # uniform external magnetic field along the propagation axis (guide field)
 
     # derived sizes -------------------------------------------------------
     @property
