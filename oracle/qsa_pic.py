@@ -253,7 +253,9 @@ def slice_sweep(g: Grid, plasma: Dict, sources: torch.Tensor, n_corr: int = 3,
                 kappa2: float = 0.75, stats: Optional[Dict] = None, b0z: float = 0.0) -> torch.Tensor:
     """Quasistatic plasma response to the given beam sources.
 
-    plasma: template dict with x, y, ux, uy (tensors) and scalar w.
+    plasma: template dict with x, y, ux, uy (tensors) and w (a scalar or one
+    weight per particle); optional "ion": the immobile ions' density at the
+    nodes, [ny, nx] (uniform 1 when absent).
     sources: [4, nxi, ny, nx] beam (rho - J_z, J_x, J_y, J_z).
     b0z: uniform external magnetic field along the propagation axis (it
     enters the plasma push only; the stored B_z is the wake's).
@@ -268,6 +270,7 @@ def slice_sweep(g: Grid, plasma: Dict, sources: torch.Tensor, n_corr: int = 3,
     ux, uy = plasma["ux"].clone(), plasma["uy"].clone()
     w = plasma["w"]
     nw = -w * torch.ones_like(x)
+    ions = plasma.get("ion", 1.0)
     Sb, Jxb, Jyb, Jzb = sources[0], sources[1], sources[2], sources[3]
 
     e_half = 0.0      # <E_z> at j - 1/2
@@ -281,7 +284,7 @@ def slice_sweep(g: Grid, plasma: Dict, sources: torch.Tensor, n_corr: int = 3,
     for j in range(g.nxi):
         # -- psi stage ------------------------------------------------------
         st = Stencil2(g, x, y)
-        S = st.deposit(nw) + 1.0 + Sb[j]
+        S = st.deposit(nw) + ions + Sb[j]
         psi, dxpsi, dypsi = solve_psi(sp, S, psi0)
         # -- J stage ----------------------------------------------------------
         G = 1.0 + st.gather(psi)

@@ -62,6 +62,10 @@ class Workload:
     plasma_my: int = 2       # ... along y (1 in a slab)
     plasma_uth: float = 0.0  # thermal spread of u_x, u_y (0 = cold)
     plasma_w_spread: float = 0.0  # random plasma weights: w0 (1 + spread (2U - 1)), 0 = all w0
+    plasma_n0: float = 1.0   # plasma density profile n0 (1 + mod cos(2 pi (mod_mx x/Lx + mod_my y/Ly)))
+    plasma_mod: float = 0.0
+    plasma_mod_mx: int = 0
+    plasma_mod_my: int = 0
     dt: float = 5.0          # beam time step
     steps: int = 1
     seed: int = 0

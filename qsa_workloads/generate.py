@@ -32,7 +32,10 @@ def plasma_template(wl: Workload) -> Dict[str, np.ndarray]:
     (row l, column i) then lattice site; all weights dx*dy/ppc (unit density),
     or, with plasma_w_spread > 0, an array of random macro-particle weights
     dx*dy/ppc (1 + spread (2U - 1)), U uniform on [0, 1) from a stream of its
-    own.  Cold (u = 0) or u_x, u_y ~ N(0, u_th^2).
+    own.  With a density profile (plasma_n0 != 1 or plasma_mod != 0) every
+    weight is also multiplied by n(x_p, y_p) and "ion" holds the immobile
+    ions' density at the nodes, [ny, nx].  Cold (u = 0) or
+    u_x, u_y ~ N(0, u_th^2).
     """
     mx, my = wl.plasma_mx, wl.plasma_my
     ii = np.arange(wl.nx)
@@ -52,11 +55,31 @@ def plasma_template(wl: Workload) -> Dict[str, np.ndarray]:
         ux = np.zeros(n)
         uy = np.zeros(n)
     w = wl.dx * wl.dy / (mx * my)
+    profiled = wl.plasma_n0 != 1.0 or wl.plasma_mod != 0.0
     if wl.plasma_w_spread > 0.0:
         gw = _rng(wl.seed, 0, 1)
-        return {"x": x, "y": y, "ux": ux, "uy": uy,
-                "w": w * (1.0 + wl.plasma_w_spread * (2.0 * gw.random(n) - 1.0))}
-    return {"x": x, "y": y, "ux": ux, "uy": uy, "w": float(w)}
+        wa = w * (1.0 + wl.plasma_w_spread * (2.0 * gw.random(n) - 1.0))
+    elif profiled:
+        wa = np.full(n, w)
+    else:
+        return {"x": x, "y": y, "ux": ux, "uy": uy, "w": float(w)}
+    out = {"x": x, "y": y, "ux": ux, "uy": uy, "w": wa}
+    if profiled:
+        out["w"] = wa * plasma_density(wl, x, y)
+        xn, yn = np.meshgrid(ii * wl.dx, ll * wl.dy)   # [ny, nx] nodes
+        out["ion"] = plasma_density(wl, xn, yn)
+    return out
+
+
+def plasma_density(wl: Workload, x, y):
+    """The plasma's density profile n(x, y) = n0 (1 + a cos(2 pi (mx x/Lx +
+    my y/Ly))) in units of the reference density (the paper's outlook item
+    of plasma inhomogeneity; uniform n = 1 by default).  The electrons carry
+    it in their weights and the immobile ions match it at the nodes, so the
+    plasma enters the box neutral."""
+    lx, ly = wl.nx * wl.dx, wl.ny * wl.dy
+    ph = 2.0 * np.pi * (wl.plasma_mod_mx * np.asarray(x) / lx + wl.plasma_mod_my * np.asarray(y) / ly)
+    return wl.plasma_n0 * (1.0 + wl.plasma_mod * np.cos(ph))
 
 
 def beam_species(wl: Workload, s: int, j0: int = 0, j1: Optional[int] = None,
