@@ -152,6 +152,16 @@ typedef struct {
                             is then lost: the context keeps the error).
                             Not with adjoint_steps > 0.  Ignored with
                             pipeline <= 1.                                  */
+  double b0z;            /* uniform external magnetic field along the
+                            propagation axis (a guide field, in units of
+                            m_e c omega_p / e; 0: none).  Added to the wake's
+                            B_z in the plasma push and in the beam's Boris
+                            push; not a source of the wake, and not stored in
+                            the B_z that qsa_fields returns.  A static field
+                            along z exerts no force along z, so the plasma's
+                            gamma - u_z = 1 + psi still holds (the outlook of
+                            the paper's conclusion lists external magnetic
+                            fields).  Must be finite; 0 with adjoint_steps > 0. */
 } qsa_params;
 
 /* Bytes of device workspace a context with these parameters needs; 0 if the
@@ -184,6 +194,20 @@ qsa_status qsa_load_plasma(qsa_ctx* c, const double* x, const double* y,
  * value finite and >= 0, else QSA_E_NONFINITE) or device memory.
  * QSA_E_STATE without plasma_weights or before a template is loaded. */
 qsa_status qsa_load_plasma_weights(qsa_ctx* c, const double* w, int64_t n, int32_t on_device);
+
+/* Density of the immobile ions at the nodes, n_i[l * nx + i] at
+ * (x_i, y_l) = (i dx, l dy), in units of the reference density (contexts
+ * created with plasma_weights = 1; qsa_load_plasma resets it to 1
+ * everywhere).  With the electrons' weights of qsa_load_plasma_weights
+ * scaled by the same profile, this is an inhomogeneous plasma that enters
+ * the box neutral (plasma inhomogeneity is in the outlook of the paper's
+ * conclusion): the ions add n_i to rho - J_z of every slice.  Loading new
+ * weights and ions between beam steps makes the density change along the
+ * propagation distance.  n must equal nx * ny.  Float64, host
+ * (synchronizing; every value finite and >= 0, else QSA_E_NONFINITE) or
+ * device memory.  QSA_E_STATE without plasma_weights or before a template
+ * is loaded. */
+qsa_status qsa_load_ions(qsa_ctx* c, const double* n_i, int64_t n, int32_t on_device);
 
 /* Load n (<= capacity) particles of beam species s (the beam species of
  * the problem statement; flat-top loading as in the "PIC simulations"

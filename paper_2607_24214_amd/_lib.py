@@ -32,7 +32,7 @@ EXPORTS = ("qsa_workspace_bytes", "qsa_create", "qsa_load_plasma", "qsa_load_bea
            "qsa_batch_workspace_bytes",
            "qsa_batch_create",
            "qsa_batch_sweep", "qsa_batch_step", "qsa_batch_sync", "qsa_batch_destroy",
-           "qsa_batch_sweep_static", "qsa_load_plasma_weights", "qsa_dirichlet_solve")
+           "qsa_batch_sweep_static", "qsa_load_plasma_weights", "qsa_load_ions", "qsa_dirichlet_solve")
 
 KERNEL_CLASSES = {"push_pred": 0, "push_final": 1, "dep_S": 2, "dep_J": 3, "row_r2c": 4,
                   "col": 5, "row_c2r": 6, "beam_deposit": 7, "beam_push": 8}
@@ -52,7 +52,7 @@ class QSAParams(C.Structure):
         ("beam_capacity", C.c_int64 * QSA_MAX_SPECIES),
         ("pipeline", C.c_int32), ("adjoint_steps", C.c_int32), ("ckpt_every", C.c_int32),
         ("no_field_pack", C.c_int32), ("plasma_weights", C.c_int32),
-        ("lean_pipeline", C.c_int32),
+        ("lean_pipeline", C.c_int32), ("b0z", C.c_double),
     ]
 
 
@@ -80,6 +80,7 @@ def lib():
     L.qsa_create.argtypes = [C.POINTER(QSAParams), vp, C.c_size_t, vp, C.POINTER(vp)]
     L.qsa_load_plasma.argtypes = [vp, vp, vp, vp, vp, i64, i32]
     L.qsa_load_plasma_weights.argtypes = [vp, vp, i64, i32]
+    L.qsa_load_ions.argtypes = [vp, vp, i64, i32]
     L.qsa_dirichlet_solve.argtypes = [i32, i32, i32, i32, C.c_double, C.c_double, C.c_double, vp, vp, vp]
     L.qsa_load_beam.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, i64, i32]
     L.qsa_load_beam_range.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, i64, i32]
@@ -115,7 +116,7 @@ def lib():
                  "qsa_timing_begin", "qsa_timing_end", "qsa_set_option", "qsa_get_option", "qsa_autotune",
                  "qsa_adjoint_sweep", "qsa_batch_create",
                  "qsa_batch_sweep", "qsa_batch_step", "qsa_batch_sync", "qsa_batch_destroy",
-                 "qsa_batch_sweep_static", "qsa_load_plasma_weights", "qsa_dirichlet_solve"):
+                 "qsa_batch_sweep_static", "qsa_load_plasma_weights", "qsa_load_ions", "qsa_dirichlet_solve"):
         getattr(L, name).restype = i32
     _lib = L
     return L

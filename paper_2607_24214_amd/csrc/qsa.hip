@@ -135,6 +135,7 @@ struct Layout {
   size_t twx, twy, kx2, kdx, ky2, kdy;
   size_t tmpl[4];
   size_t tmpl_qw;                   // template relative weights (plasma_weights)
+  size_t ion;                       // ion density at the nodes (plasma_weights)
   int nset;                         // working sets (beam steps in flight)
   bool lean;                        // steps in flight without a second copy of the beam
   SetLayout set[QSA_MAX_PIPELINE];
@@ -186,6 +187,7 @@ Layout make_layout(const qsa_params& p) {
   // plasma x, y in float64 for either precision; u_x, u_y in R
   for (int i = 0; i < 4; ++i) L.tmpl[i] = c.take(p.n_plasma * (i < 2 ? 8 : rs));
   L.tmpl_qw = p.plasma_weights ? c.take(p.n_plasma * rs) : 0;
+  L.ion = p.plasma_weights ? c.take(nperp * rs) : 0;
   L.nset = pipeline_depth(p);
   L.lean = L.nset > 1 && p.lean_pipeline;
   for (int k = 0; k < L.nset; ++k) {
@@ -277,6 +279,8 @@ const char* validate(const qsa_params* p) {
   if (p->no_field_pack != 0 && p->no_field_pack != 1) return "no_field_pack must be 0 or 1";
   if (p->plasma_weights != 0 && p->plasma_weights != 1) return "plasma_weights must be 0 or 1";
   if (p->lean_pipeline != 0 && p->lean_pipeline != 1) return "lean_pipeline must be 0 or 1";
+  if (!std::isfinite(p->b0z)) return "b0z must be finite";
+  if (p->b0z != 0.0 && p->adjoint_steps > 0) return "b0z must be 0 with adjoint_steps > 0 (the adjoint takes no external field)";
   if (p->lean_pipeline && p->pipeline > 1 && p->adjoint_steps > 0)
     return "lean_pipeline: the adjoint's bins follow the load order, which a lean pipeline does not keep";
   if (p->lean_pipeline && p->pipeline > 1) {
@@ -497,6 +501,7 @@ struct Engine {
     g.lyd = p.ny * p.dy;
     g.inv_lxd = 1.0 / (p.nx * p.dx);
     g.inv_lyd = 1.0 / (p.ny * p.dy);
+    g.b0z = (R)p.b0z;
     return g;
   }
 
@@ -842,6 +847,7 @@ struct Engine {
       a.qw[i] = p.plasma_weights ? c->at<R>(S.qw[i]) : nullptr;
     }
     a.tqw = p.plasma_weights ? c->at<R>(L.tmpl_qw) : nullptr;
+    a.ion = p.plasma_weights ? c->at<R>(L.ion) : nullptr;
     a.twx = c->at<C2<R>>(L.twx);
     a.twy = c->at<C2<R>>(L.twy);
     a.kx2 = c->at<R>(L.kx2);
@@ -1871,6 +1877,11 @@ qsa_status qsa_load_plasma(qsa_ctx* c, const double* x, const double* y, const d
         c, [&] { return Engine<double>::fill(c, c->at<double>(c->L.tmpl_qw), n, 1.0); },
         [&] { return Engine<float>::fill(c, c->at<float>(c->L.tmpl_qw), n, 1.0f); });
     if (st != QSA_OK) return st;
+    // uniform ions until qsa_load_ions
+    const int64_t np = (int64_t)c->p.nx * c->p.ny;
+    st = dispatch(c, [&] { return Engine<double>::fill(c, c->at<double>(c->L.ion), np, 1.0); },
+                  [&] { return Engine<float>::fill(c, c->at<float>(c->L.ion), np, 1.0f); });
+    if (st != QSA_OK) return st;
   }
   c->plasma_loaded = true;
   c->drop_graphs();
@@ -1892,6 +1903,25 @@ qsa_status qsa_load_plasma_weights(qsa_ctx* c, const double* w, int64_t n, int32
   const double scale = 1.0 / c->p.plasma_w;
   qsa_status st = dispatch(c, [&] { return Engine<double>::upload_scaled(c, w, c->L.tmpl_qw, n, on_device, scale); },
                            [&] { return Engine<float>::upload_scaled(c, w, c->L.tmpl_qw, n, on_device, scale); });
+  if (st != QSA_OK) return st;
+  c->drop_graphs();
+  return leave(c);
+}
+
+qsa_status qsa_load_ions(qsa_ctx* c, const double* n_i, int64_t n, int32_t on_device) {
+  if (!c) return QSA_E_INVALID;
+  if (c->sticky != QSA_OK) return c->sticky;
+  if (!c->p.plasma_weights) return fail(c, QSA_E_STATE, "the context keeps no ion profile (plasma_weights = 0)");
+  if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
+  if (n != (int64_t)c->p.nx * c->p.ny) return fail(c, QSA_E_INVALID, "ion density count differs from nx * ny");
+  if (!n_i) return fail(c, QSA_E_INVALID, "null ion density array");
+  if (!on_device)
+    for (int64_t i = 0; i < n; ++i)
+      if (!std::isfinite(n_i[i]) || n_i[i] < 0) return fail(c, QSA_E_NONFINITE, "ion densities must be finite and >= 0");
+  qsa_status st0 = enter(c);
+  if (st0 != QSA_OK) return st0;
+  qsa_status st = dispatch(c, [&] { return Engine<double>::upload_scaled(c, n_i, c->L.ion, n, on_device, 1.0); },
+                           [&] { return Engine<float>::upload_scaled(c, n_i, c->L.ion, n, on_device, 1.0); });
   if (st != QSA_OK) return st;
   c->drop_graphs();
   return leave(c);

@@ -41,6 +41,7 @@ struct Geo {
   // precision: a float32 position in a box of a few c/omega_p resolves only
   // about 1e-6, coarser than a slice's displacement allows)
   double inv_dxd, inv_dyd, lxd, lyd, inv_lxd, inv_lyd;
+  R b0z;                        // uniform external B_z (guide field), 0 if none
 };
 
 // Wrap an integer cell index into [0, n) for n a power of two (the library

@@ -60,6 +60,7 @@ struct Lane {
   const double* tpos[2];  // plasma template x, y (float64 in either precision)
   const R* tmom[2];       // and u_x, u_y
   const R* tqw;           // and its weights relative to plasma_w (null: all 1)
+  const R* ion;           // immobile ions' density at the nodes [ny][nx] (null: all 1)
   const C2<R>* twx;     // transform tables
   const C2<R>* twy;
   const R* kx2;
@@ -699,7 +700,8 @@ __device__ __forceinline__ void lane_block(int& lane, int& b) {
 // stage position,
 //   dx_perp/dxi = u_perp/G,
 //   du_x/dxi = a_x - B_y,  a_x = gamma d_x psi/G - u_y B_z/G,
-//   du_y/dxi = a_y + B_x,  a_y = gamma d_y psi/G + u_x B_z/G.
+//   du_y/dxi = a_y + B_x,  a_y = gamma d_y psi/G + u_x B_z/G,
+// B_z being the wake's plus the uniform guide field g.b0z.
 // B_perp enters only through the last terms, and the midpoint position only
 // through u_perp/G: so the stage-1 a_x, a_y, the midpoint (x_s, y_s) and
 // G, d_x psi, d_y psi, B_z at the midpoint are the same in every predictor
@@ -735,7 +737,7 @@ __device__ __forceinline__ void rk2_full(const Geo<R>& g, const PlasmaArgs<R>& a
     if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
     const R iG = R(1) / G;
     const R gam = (R(1) + ux * ux + uy * uy + G * G) * R(0.5) * iG;
-    const R bz = gather(a.F0[5], s);
+    const R bz = gather(a.F0[5], s) + g.b0z;
     ax = gam * gather(a.F0[1], s) * iG - uy * bz * iG;
     ay = gam * gather(a.F0[2], s) * iG + ux * bz * iG;
     bx1 = gather(a.F0[3], s);
@@ -746,7 +748,7 @@ __device__ __forceinline__ void rk2_full(const Geo<R>& g, const PlasmaArgs<R>& a
   const Stencil<R> s = stencil2(g, xs, ys);
   const R gs = R(1) + gather(a.H[0], s);
   if (!(gs > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
-  const R pxs = gather(a.H[1], s), pys = gather(a.H[2], s), bzs = gather(a.H[5], s);
+  const R pxs = gather(a.H[1], s), pys = gather(a.H[2], s), bzs = gather(a.H[5], s) + g.b0z;
   const R bxh = gather(a.H[3], s), byh = gather(a.H[4], s);
   if (store) {
     a.cpos[0][p] = xs;
@@ -938,13 +940,24 @@ __global__ void __launch_bounds__(PlasmaBlock<R>::MAX) k_plasma_rows(const Lane<
   const int nt = blockDim.x, tid = threadIdx.x;
   const int tn = 4 * NC * g.nx;
   // rho - J_z: the block's tile starts from half the ion density on node
-  // rows r and r + 1 (k = 1, 2), so that every node row gets the ions'
-  // +1 once, from blocks r and r - 1, and the stored partial rows hold the
-  // small difference of ions and plasma instead of the plasma density
-  // (float32 partial rows then round that difference, not O(1) values)
+  // rows r and r + 1 (k = 1, 2), so that every node row gets its ions once,
+  // from blocks r and r - 1, and the stored partial rows hold the small
+  // difference of ions and plasma instead of the plasma density (float32
+  // partial rows then round that difference, not O(1) values).  The ions
+  // are uniform (density 1) or follow a density profile at the nodes.
   for (int t = tid; t < tn; t += nt) {
     const int k = t / g.nx;
-    tile[t] = (MODE == PL_DEP_S && (k == 1 || k == 2)) ? 0.5 : 0.0;
+    double v = 0.0;
+    if (MODE == PL_DEP_S && (k == 1 || k == 2)) {
+      if (L.ion) {
+        int row = r + k - 1;
+        if (row >= g.ny) row -= g.ny;
+        v = 0.5 * (double)L.ion[row * g.nx + (t - k * g.nx)];
+      } else {
+        v = 0.5;
+      }
+    }
+    tile[t] = v;
   }
   __syncthreads();
   const int p0 = a.prow[r], p1 = a.prow[r + 1];
@@ -1970,7 +1983,7 @@ __device__ __forceinline__ BeamNew<R> boris_state(const Geo<R>& g, const R* __re
   const R ex = -fd[0] + fd[4];
   const R ey = -fd[1] - fd[3];
   const R ez = fd[2];
-  const R bx = fd[3], by = fd[4], bz = fd[5];
+  const R bx = fd[3], by = fd[4], bz = fd[5] + g.b0z;   // wake B_z plus the guide field
   // half electric kick
   const R umx = ux + qh * ex, umy = uy + qh * ey, umz = uz + qh * ez;
   const R gm = sqrt(R(1) + umx * umx + umy * umy + umz * umz);

@@ -34,7 +34,8 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
                 beam_capacity: Sequence[int], precision: str = "f64", n_corr: int = 3,
                 kappa2: float = 0.75, pipeline: int = 1, adjoint_steps: int = 0,
                 ckpt_every: int = 0, field_pack: bool = True,
-                plasma_weights: bool = False, lean_pipeline: bool = False) -> L.QSAParams:
+                plasma_weights: bool = False, lean_pipeline: bool = False,
+                b0z: float = 0.0) -> L.QSAParams:
     """species: sequence of (Z, M); pipeline: beam steps in flight (1 = off);
     adjoint_steps: most steps qsa_adjoint_sweep differentiates (0 = none);
     ckpt_every: the adjoint's plasma checkpoint stride in slices (0 = 16);
@@ -42,7 +43,8 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
     in flight; False saves 32-48 bytes per cell); plasma_weights: keep a
     weight per plasma macro-particle (Sim.load_plasma loads them when the
     template's "w" is an array); lean_pipeline: steps in flight without a
-    second copy of the beam (read_beam then returns storage order)."""
+    second copy of the beam (read_beam then returns storage order); b0z: a
+    uniform external magnetic field along the propagation axis."""
     p = L.QSAParams()
     p.nx, p.ny, p.nxi = nx, ny, nxi
     p.precision = _PREC[precision]
@@ -56,6 +58,7 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
     p.no_field_pack = 0 if field_pack else 1
     p.plasma_weights = 1 if plasma_weights else 0
     p.lean_pipeline = 1 if lean_pipeline else 0
+    p.b0z = float(b0z)
     for i, (Z, M) in enumerate(species):
         p.species[i].Z = int(Z)
         p.species[i].M = float(M)
@@ -75,7 +78,9 @@ def params_from_workload(wl, precision: Optional[str] = None,
                        [(s.Z, s.M) for s in wl.species], wl.n_plasma,
                        wl.dx * wl.dy / wl.plasma_ppc, caps, precision or wl.precision,
                        wl.n_corr, wl.kappa2, pipeline, adjoint_steps, min(int(ck), wl.nxi), field_pack,
-                       getattr(wl, "plasma_w_spread", 0.0) > 0.0, lean_pipeline)
+                       (getattr(wl, "plasma_w_spread", 0.0) > 0.0 or getattr(wl, "plasma_n0", 1.0) != 1.0
+                        or getattr(wl, "plasma_mod", 0.0) != 0.0), lean_pipeline,
+                       float(getattr(wl, "b0z", 0.0)))
 
 
 class Sim:
@@ -135,6 +140,18 @@ class Sim:
         if per_particle:
             wa, wdev = _f64(w)
             self._check(self.lib.qsa_load_plasma_weights(self.ctx, C.c_void_p(_ptr(wa)), wa.shape[0], wdev))
+        ion = plasma.get("ion")
+        if ion is not None:
+            self.load_ions(ion)
+
+    def load_ions(self, ion):
+        """The immobile ions' density at the nodes, [ny, nx] (a context made
+        with plasma_weights)."""
+        if not self.params.plasma_weights:
+            raise ValueError("an ion density profile needs a context made with plasma_weights")
+        ia, idev = _f64(ion)
+        ia = ia.reshape(-1)
+        self._check(self.lib.qsa_load_ions(self.ctx, C.c_void_p(_ptr(ia)), ia.shape[0], idev))
 
     def load_beam(self, s: int, beam: Dict):
         arrs = [_f64(beam[k]) for k in ("x", "y", "xi", "ux", "uy", "uz", "w")]

@@ -135,3 +135,14 @@ def test_checkpoint_stride_validated():
     assert big != small       # checkpoint and segment storage follow the stride
     assert lib.qsa_workspace_bytes(C.byref(_params(adjoint_steps=2, ckpt_every=-1))) == 0
     assert lib.qsa_workspace_bytes(C.byref(_params(adjoint_steps=2, ckpt_every=129))) == 0
+
+
+def test_guide_field_validated():
+    from paper_2607_24214_amd import _lib as L
+    lib = L.lib()
+    assert lib.qsa_workspace_bytes(C.byref(_params(b0z=0.5))) == lib.qsa_workspace_bytes(C.byref(_params()))
+    assert lib.qsa_workspace_bytes(C.byref(_params(b0z=float("inf")))) == 0
+    assert lib.qsa_workspace_bytes(C.byref(_params(b0z=float("nan")))) == 0
+    # the adjoint takes no external field
+    assert lib.qsa_workspace_bytes(C.byref(_params(adjoint_steps=2, b0z=0.5))) == 0
+    assert lib.qsa_workspace_bytes(C.byref(_params(adjoint_steps=2))) > 0
