@@ -665,12 +665,22 @@ def main():
     head = run_workload(wl, precision, pipeline, args.steps, args.warmup, args, with_extras=True, lean=lean)
 
     extra = {}
+    keys = ("value", "ms_per_step", "steps", "warmup", "dtype", "config", "sweep_only", "roofline")
     if not args.no_extra and args.workload != "cube256":
         cube = W.cube256()
         for prec in ("f64", "f32"):
             e = run_workload(cube.with_(precision=prec), prec, 8, 16, 4, args, with_extras=False)
-            extra[f"{cube.name}_{prec}"] = {k: e[k] for k in ("value", "ms_per_step", "steps", "warmup", "dtype",
-                                                              "config", "sweep_only", "roofline")}
+            extra[f"{cube.name}_{prec}"] = {k: e[k] for k in keys}
+    if not args.no_extra and args.workload != "slab":
+        # the 64 x 128 slab (float64, 8 steps in flight): launch-bound at
+        # 256 plasma particles per slice, reported in absolute terms
+        slab = W.CONFIGS["slab"]()
+        try:
+            e = run_workload(slab, "f64", 8, 48, 8, args, with_extras=False)
+            extra[f"{slab.name}_f64"] = {k: e[k] for k in keys}
+        except Exception as exc:  # recorded in the line, the headline stands
+            log(f"slab workload failed: {exc!r}")
+            extra[f"{slab.name}_f64"] = {"error": repr(exc)}
         if not args.no_scan:
             # the 64-instance batched scan (float32), all instances on this GPU
             sc = scan_rate(64, 3, 1)
