@@ -26,6 +26,9 @@ guide field of a magnetized plasma, one of the paper's outlook items) adds
 to B_z wherever a particle is pushed; it is static and curl-free, so it is
 no source of the wake, and it exerts no force along z, so the invariant
 below still holds.
+Mobile ions (charge Z, mass M in m_e, momenta in units of M c), when the
+plasma has them, follow the same equations with G = 1 - (Z/M) psi and the
+accelerations scaled by -Z/M, and carry +Z w and Z w u/G.
 Plasma electrons conserve gamma - u_z = 1 + psi =: G, so in xi
   dx_perp/dxi = u_perp/G,
   du_x/dxi = gamma d_x psi/G - B_y - u_y B_z/G,
@@ -222,26 +225,28 @@ def _check_g(G: torch.Tensor):
         raise QSABreakdown("1 + psi <= %g or non-finite at a plasma particle" % BREAKDOWN_G)
 
 
-def plasma_rhs(g: Grid, F: Sequence[torch.Tensor], x, y, ux, uy, b0z: float = 0.0):
+def plasma_rhs(g: Grid, F: Sequence[torch.Tensor], x, y, ux, uy, b0z: float = 0.0, s=1.0):
     """d/dxi of (x, y, u_x, u_y) with the six fields F = (psi, dxpsi, dypsi,
     Bx, By, Bz) gathered at the particle; b0z is a uniform external magnetic
-    field along the propagation axis, added to the wake's B_z."""
+    field along the propagation axis, added to the wake's B_z.  s = -Z/M per
+    particle (1 for an electron; a mobile ion of charge Z and mass M has
+    G = 1 - (Z/M) psi and its accelerations scaled by -Z/M)."""
     st = Stencil2(g, x, y)
     psi, dxp, dyp, bx, by, bz = (st.gather(f) for f in F)
     bz = bz + b0z
-    G = 1.0 + psi
+    G = 1.0 + s * psi
     _check_g(G)
     gam = (1.0 + ux * ux + uy * uy + G * G) / (2.0 * G)
     return (ux / G, uy / G,
-            gam * dxp / G - by - uy * bz / G,
-            gam * dyp / G + bx + ux * bz / G)
+            s * (gam * dxp / G - by - uy * bz / G),
+            s * (gam * dyp / G + bx + ux * bz / G))
 
 
-def rk2(g: Grid, h: float, Fa, Fb, Y, b0z: float = 0.0):
+def rk2(g: Grid, h: float, Fa, Fb, Y, b0z: float = 0.0, s=1.0):
     """Midpoint rule: Y* = Y + (h/2) f(Y; Fa), Y' = Y + h f(Y*; Fb)."""
-    k1 = plasma_rhs(g, Fa, *Y, b0z=b0z)
+    k1 = plasma_rhs(g, Fa, *Y, b0z=b0z, s=s)
     Ys = tuple(a + 0.5 * h * b for a, b in zip(Y, k1))
-    k2 = plasma_rhs(g, Fb, *Ys, b0z=b0z)
+    k2 = plasma_rhs(g, Fb, *Ys, b0z=b0z, s=s)
     return tuple(a + h * b for a, b in zip(Y, k2))
 
 
@@ -250,12 +255,14 @@ def rk2(g: Grid, h: float, Fa, Fb, Y, b0z: float = 0.0):
 # ---------------------------------------------------------------------------
 
 def slice_sweep(g: Grid, plasma: Dict, sources: torch.Tensor, n_corr: int = 3,
-                kappa2: float = 0.75, stats: Optional[Dict] = None, b0z: float = 0.0) -> torch.Tensor:
+                kappa2: float = 0.75, stats: Optional[Dict] = None, b0z: float = 0.0,
+                ion_z: int = 1, ion_m: float = 0.0) -> torch.Tensor:
     """Quasistatic plasma response to the given beam sources.
 
     plasma: template dict with x, y, ux, uy (tensors) and w (a scalar or one
     weight per particle); optional "ion": the immobile ions' density at the
-    nodes, [ny, nx] (uniform 1 when absent).
+    nodes, [ny, nx] (uniform 1 when absent); optional "kind": 1 marks a
+    mobile ion of charge ion_z and mass ion_m (in m_e), 0 an electron.
     sources: [4, nxi, ny, nx] beam (rho - J_z, J_x, J_y, J_z).
     b0z: uniform external magnetic field along the propagation axis (it
     enters the plasma push only; the stored B_z is the wake's).
@@ -269,7 +276,15 @@ def slice_sweep(g: Grid, plasma: Dict, sources: torch.Tensor, n_corr: int = 3,
     x, y = plasma["x"].clone(), plasma["y"].clone()
     ux, uy = plasma["ux"].clone(), plasma["uy"].clone()
     w = plasma["w"]
-    nw = -w * torch.ones_like(x)
+    kind = plasma.get("kind")
+    if kind is not None and ion_m > 0.0:
+        mobile = kind > 0
+        charge = torch.where(mobile, torch.full_like(x, float(ion_z)), torch.full_like(x, -1.0))
+        s = torch.where(mobile, torch.full_like(x, -float(ion_z) / ion_m), torch.ones_like(x))
+    else:
+        charge = -torch.ones_like(x)
+        s = 1.0
+    nw = charge * w            # rho - J_z carried by each macro-particle
     ions = plasma.get("ion", 1.0)
     Sb, Jxb, Jyb, Jzb = sources[0], sources[1], sources[2], sources[3]
 
@@ -287,7 +302,7 @@ def slice_sweep(g: Grid, plasma: Dict, sources: torch.Tensor, n_corr: int = 3,
         S = st.deposit(nw) + ions + Sb[j]
         psi, dxpsi, dypsi = solve_psi(sp, S, psi0)
         # -- J stage ----------------------------------------------------------
-        G = 1.0 + st.gather(psi)
+        G = 1.0 + s * st.gather(psi)
         _check_g(G)
         gam = (1.0 + ux * ux + uy * uy + G * G) / (2.0 * G)
         uz = gam - G
@@ -313,9 +328,9 @@ def slice_sweep(g: Grid, plasma: Dict, sources: torch.Tensor, n_corr: int = 3,
         for _ in range(n_corr):
             Fj = [psi, dxpsi, dypsi, Bx, By, Bz]
             Fh = [0.5 * (3.0 * a - b) for a, b in zip(Fj, Fm1)]
-            xt, yt, uxt, uyt = rk2(g, h, Fj, Fh, Y, b0z)
+            xt, yt, uxt, uyt = rk2(g, h, Fj, Fh, Y, b0z, s)
             stt = Stencil2(g, xt, yt)
-            Gt = 1.0 + stt.gather(psi_p1)
+            Gt = 1.0 + s * stt.gather(psi_p1)
             _check_g(Gt)
             Jxt = stt.deposit(nw * uxt / Gt) + jxb1
             Jyt = stt.deposit(nw * uyt / Gt) + jyb1
@@ -326,7 +341,7 @@ def slice_sweep(g: Grid, plasma: Dict, sources: torch.Tensor, n_corr: int = 3,
         # -- final advance to j+1 ---------------------------------------------
         Fj = [psi, dxpsi, dypsi, Bx, By, Bz]
         Fh = [0.5 * (3.0 * a - b) for a, b in zip(Fj, Fm1)]
-        x, y, ux, uy = rk2(g, h, Fj, Fh, Y, b0z)
+        x, y, ux, uy = rk2(g, h, Fj, Fh, Y, b0z, s)
         x = wrap(x, g.lx)
         y = wrap(y, g.ly)
         for f, v in zip((PSI, DXPSI, DYPSI, EZ, BX, BY, BZ),
@@ -480,7 +495,9 @@ class Sim:
 
     def sweep(self) -> torch.Tensor:
         src = beam_sources(self.g, self.beams, self.Z)
-        self.fields = slice_sweep(self.g, self.plasma, src, self.wl.n_corr, self.wl.kappa2, b0z=self.b0z)
+        self.fields = slice_sweep(self.g, self.plasma, src, self.wl.n_corr, self.wl.kappa2, b0z=self.b0z,
+                                  ion_z=int(getattr(self.wl, "ion_z", 1)),
+                                  ion_m=float(getattr(self.wl, "ion_m", 0.0)))
         return self.fields
 
     def push(self):

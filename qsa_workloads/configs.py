@@ -76,6 +76,8 @@ class Workload:
     n_bins: int = 0          # piecewise-constant xi amplitude bins (adjoint workload)
     ckpt_every: int = 16
     b0z: float = 0.0         # uniform external magnetic field along the propagation axis (guide field)
+    ion_m: float = 0.0       # mass of mobile plasma ions in m_e (0: immobile ion background)
+    ion_z: int = 1           # their charge number
 
     # derived sizes -------------------------------------------------------
     @property
@@ -92,7 +94,9 @@ class Workload:
 
     @property
     def n_plasma(self) -> int:
-        return self.n_perp * self.plasma_ppc
+        """Plasma macro-particles per slice (electrons, and as many mobile
+        ions when ion_m > 0)."""
+        return self.n_perp * self.plasma_ppc * (2 if self.ion_m > 0.0 else 1)
 
     @property
     def beam_slices(self) -> int:

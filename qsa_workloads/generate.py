@@ -34,8 +34,10 @@ def plasma_template(wl: Workload) -> Dict[str, np.ndarray]:
     dx*dy/ppc (1 + spread (2U - 1)), U uniform on [0, 1) from a stream of its
     own.  With a density profile (plasma_n0 != 1 or plasma_mod != 0) every
     weight is also multiplied by n(x_p, y_p) and "ion" holds the immobile
-    ions' density at the nodes, [ny, nx].  Cold (u = 0) or
-    u_x, u_y ~ N(0, u_th^2).
+    ions' density at the nodes, [ny, nx].  With mobile ions (ion_m > 0) the
+    template holds the electrons, then as many ions on the same sites ("kind"
+    1, weights divided by the charge number ion_z), and "ion" is zero.  Cold
+    (u = 0) or u_x, u_y ~ N(0, u_th^2).
     """
     mx, my = wl.plasma_mx, wl.plasma_my
     ii = np.arange(wl.nx)
@@ -56,18 +58,32 @@ def plasma_template(wl: Workload) -> Dict[str, np.ndarray]:
         uy = np.zeros(n)
     w = wl.dx * wl.dy / (mx * my)
     profiled = wl.plasma_n0 != 1.0 or wl.plasma_mod != 0.0
+    mobile = wl.ion_m > 0.0
     if wl.plasma_w_spread > 0.0:
         gw = _rng(wl.seed, 0, 1)
         wa = w * (1.0 + wl.plasma_w_spread * (2.0 * gw.random(n) - 1.0))
-    elif profiled:
+    elif profiled or mobile:
         wa = np.full(n, w)
     else:
         return {"x": x, "y": y, "ux": ux, "uy": uy, "w": float(w)}
     out = {"x": x, "y": y, "ux": ux, "uy": uy, "w": wa}
+    xn, yn = np.meshgrid(ii * wl.dx, ll * wl.dy)   # [ny, nx] nodes
     if profiled:
         out["w"] = wa * plasma_density(wl, x, y)
-        xn, yn = np.meshgrid(ii * wl.dx, ll * wl.dy)   # [ny, nx] nodes
         out["ion"] = plasma_density(wl, xn, yn)
+    if mobile:
+        # mobile ions on the electrons' lattice sites, 1/Z of their number
+        # (neutral), thermal momenta at the electrons' temperature
+        # (u = p/(M c): spread u_th/sqrt(M)); no immobile background
+        if wl.plasma_uth > 0.0:
+            ui = (wl.plasma_uth / np.sqrt(wl.ion_m)) * _rng(wl.seed, 0, 2).standard_normal((2, n))
+        else:
+            ui = np.zeros((2, n))
+        out = {"x": np.concatenate([x, x]), "y": np.concatenate([y, y]),
+               "ux": np.concatenate([ux, ui[0]]), "uy": np.concatenate([uy, ui[1]]),
+               "w": np.concatenate([out["w"], out["w"] / wl.ion_z]),
+               "kind": np.concatenate([np.zeros(n, np.int32), np.ones(n, np.int32)]),
+               "ion": np.zeros(xn.shape)}
     return out
 
 

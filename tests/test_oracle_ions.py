@@ -1,0 +1,74 @@
+"""Pins of the oracle's mobile plasma ions (ion motion is in the outlook of
+the paper's conclusion).
+
+A cold plasma species s of charge q_s, mass M_s and density n_s keeps
+gamma - u_z = G_s = 1 - (q_s/M_s) psi, so behind a wide weak beam its
+J_z = q_s n_s (1 - G_s^2)/(2 G_s^2) = (q_s^2 n_s/M_s) psi to first order:
+the 1D wake psi'' = -J_z rings at omega^2 = sum_s q_s^2 n_s/M_s, the
+textbook plasma frequency of several species.  Electrons at density 1 with
+neutralizing ions of charge Z (density 1/Z) and mass M give
+omega^2 = 1 + Z/M and psi = (alpha beta/omega^2)(1 - cos(omega xi)).  Very
+heavy ions reproduce the immobile background."""
+import math
+
+import numpy as np
+import torch
+
+import qsa_workloads as W
+from oracle import qsa_pic as O
+
+
+def _wake(h, ion_z, ion_m, alpha=1e-4, length=8.0):
+    n = 4
+    nxi = int(round(length / h)) + 1
+    wl = W.Workload(name="wake1d_ions", nx=n, ny=n, nxi=nxi, dx=0.25, dy=0.25, dxi=h,
+                    gamma_b=100.0, species=(W.Species(Z=-1, alpha=alpha, ppc=8),),
+                    plasma_mx=2, plasma_my=2, beam_loading="lattice", seed=1, ion_m=ion_m, ion_z=ion_z)
+    s = O.Sim(wl, W.plasma_template(wl), W.beam(wl))
+    return wl, s.sweep()
+
+
+def test_wake_rings_at_the_two_species_plasma_frequency():
+    beta = math.sqrt(1 - 1e-4)
+    for z, m in ((1, 1.0), (1, 4.0), (2, 4.0)):
+        wl, f = _wake(0.05, z, m)
+        w2 = 1.0 + z / m
+        xis = np.arange(wl.nxi) * wl.dxi
+        lin = 1e-4 * beta / w2 * (1.0 - np.cos(math.sqrt(w2) * xis))
+        psi = f[O.PSI, :, 0, 0].numpy()
+        err = np.abs(psi - lin).max()
+        assert err < 5e-3 * 1e-4 / w2, (z, m, err)
+        # immobile ions would ring at omega = 1
+        assert np.abs(psi - 1e-4 * beta * (1.0 - np.cos(xis))).max() > 0.2e-4 / w2, (z, m)
+
+
+def test_pair_plasma_wake_converges_at_second_order():
+    # electron-positron plasma (Z = 1, M = 1): omega^2 = 2
+    beta = math.sqrt(1 - 1e-4)
+    errs = []
+    for h in (0.1, 0.05):
+        wl, f = _wake(h, 1, 1.0, alpha=1e-6)
+        xis = np.arange(wl.nxi) * h
+        lin = 1e-6 * beta / 2.0 * (1.0 - np.cos(math.sqrt(2.0) * xis))
+        errs.append(np.abs(f[O.PSI, :, 0, 0].numpy() - lin).max())
+    order = math.log2(errs[0] / errs[1])
+    assert 1.8 < order < 2.2, errs
+
+
+def test_very_heavy_ions_are_the_immobile_background():
+    # cold: ion thermal currents (u_th/sqrt(M)) would otherwise stay
+    base = W.small_3d(16, 8, 16, plasma_uth=0.0, dt=20.0,
+                      species=(W.Species(Z=-1, alpha=0.05, ppc=2, sigma_perp=1e-2),))
+    heavy = base.with_(ion_m=1e12)
+    a = O.Sim(base, W.plasma_template(base), W.beam(base))
+    b = O.Sim(heavy, W.plasma_template(heavy), W.beam(heavy))
+    a.beam_step(1)
+    b.beam_step(1)
+    fa, fb = a.sweep(), b.sweep()
+    scale = float(fa.abs().max())
+    assert float((fa - fb).abs().max()) <= 1e-9 * scale
+    # and light ions change the answer
+    light = base.with_(ion_m=4.0)
+    c = O.Sim(light, W.plasma_template(light), W.beam(light))
+    c.beam_step(1)
+    assert float((c.sweep() - fa).abs().max()) > 1e-3 * scale
