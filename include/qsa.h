@@ -162,6 +162,19 @@ typedef struct {
                             gamma - u_z = 1 + psi still holds (the outlook of
                             the paper's conclusion lists external magnetic
                             fields).  Must be finite; 0 with adjoint_steps > 0. */
+  double ion_m;          /* mass of mobile plasma ions in electron masses, or
+                            0 (the ions are an immobile background, density
+                            1 or the grid of qsa_load_ions).  With ion_m > 0
+                            (contexts with plasma_weights = 1) the plasma
+                            template may hold ions next to the electrons: a
+                            negative weight in qsa_load_plasma_weights marks
+                            one.  An ion keeps gamma - u_z = 1 - (Z/M) psi,
+                            is pushed with the electrons' equations scaled
+                            by -Z/M and carries +Z w (ion motion is in the
+                            outlook of the paper's conclusion).  Finite and
+                            >= 0.                                           */
+  int32_t ion_z;         /* their charge number, 1..64 (with ion_m > 0)      */
+  int32_t pad2_;
 } qsa_params;
 
 /* Bytes of device workspace a context with these parameters needs; 0 if the
@@ -191,7 +204,9 @@ qsa_status qsa_load_plasma(qsa_ctx* c, const double* x, const double* y,
  * plasma_w (area per particle times the local density, so that a uniform
  * plasma has w[i] = plasma_w); each particle deposits -w[i]/(dx dy) times
  * its shape.  n must equal n_plasma.  Float64, host (synchronizing; every
- * value finite and >= 0, else QSA_E_NONFINITE) or device memory.
+ * value finite and >= 0, else QSA_E_NONFINITE) or device memory.  With
+ * mobile ions (ion_m > 0) a negative w[i] makes particle i an ion of weight
+ * -w[i] (charge ion_z, mass ion_m); host values then need only be finite.
  * QSA_E_STATE without plasma_weights or before a template is loaded. */
 qsa_status qsa_load_plasma_weights(qsa_ctx* c, const double* w, int64_t n, int32_t on_device);
 

@@ -53,6 +53,7 @@ class QSAParams(C.Structure):
         ("pipeline", C.c_int32), ("adjoint_steps", C.c_int32), ("ckpt_every", C.c_int32),
         ("no_field_pack", C.c_int32), ("plasma_weights", C.c_int32),
         ("lean_pipeline", C.c_int32), ("b0z", C.c_double),
+        ("ion_m", C.c_double), ("ion_z", C.c_int32), ("pad2_", C.c_int32),
     ]
 
 

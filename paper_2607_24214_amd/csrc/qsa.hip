@@ -281,6 +281,9 @@ const char* validate(const qsa_params* p) {
   if (p->lean_pipeline != 0 && p->lean_pipeline != 1) return "lean_pipeline must be 0 or 1";
   if (!std::isfinite(p->b0z)) return "b0z must be finite";
   if (p->b0z != 0.0 && p->adjoint_steps > 0) return "b0z must be 0 with adjoint_steps > 0 (the adjoint takes no external field)";
+  if (!(p->ion_m >= 0.0) || !std::isfinite(p->ion_m)) return "ion_m must be finite and >= 0";
+  if (p->ion_m > 0.0 && !p->plasma_weights) return "mobile ions (ion_m > 0) need plasma_weights = 1";
+  if (p->ion_m > 0.0 && (p->ion_z < 1 || p->ion_z > 64)) return "ion_z must be in [1, 64]";
   if (p->lean_pipeline && p->pipeline > 1 && p->adjoint_steps > 0)
     return "lean_pipeline: the adjoint's bins follow the load order, which a lean pipeline does not keep";
   if (p->lean_pipeline && p->pipeline > 1) {
@@ -848,6 +851,7 @@ struct Engine {
     }
     a.tqw = p.plasma_weights ? c->at<R>(L.tmpl_qw) : nullptr;
     a.ion = p.plasma_weights ? c->at<R>(L.ion) : nullptr;
+    a.ion_s = p.ion_m > 0.0 ? (R)(-(double)p.ion_z / p.ion_m) : R(0);
     a.twx = c->at<C2<R>>(L.twx);
     a.twy = c->at<C2<R>>(L.twy);
     a.kx2 = c->at<R>(L.kx2);
@@ -1330,6 +1334,13 @@ struct Engine {
   }
 
   // float64 values times `scale` -> working precision at workspace offset off
+  static qsa_status scale_negative(qsa_ctx* c, size_t off, int64_t n, double z) {
+    if (n == 0) return QSA_OK;
+    hipLaunchKernelGGL(k_scale_negative<R>, dim3(fill_blocks(n)), dim3(256), 0, c->stream, c->at<R>(off), n, (R)z);
+    HIP_OK(hipGetLastError());
+    return QSA_OK;
+  }
+
   static qsa_status upload_scaled(qsa_ctx* c, const double* src, size_t off, int64_t n, int on_device,
                                   double scale) {
     if (n == 0) return QSA_OK;
@@ -1895,15 +1906,23 @@ qsa_status qsa_load_plasma_weights(qsa_ctx* c, const double* w, int64_t n, int32
   if (!c->plasma_loaded) return fail(c, QSA_E_STATE, "no plasma template loaded");
   if (n != c->p.n_plasma) return fail(c, QSA_E_INVALID, "weight count differs from n_plasma");
   if (!w) return fail(c, QSA_E_INVALID, "null weight array");
+  const bool mobile = c->p.ion_m > 0.0;
   if (!on_device)
     for (int64_t i = 0; i < n; ++i)
-      if (!std::isfinite(w[i]) || w[i] < 0) return fail(c, QSA_E_NONFINITE, "plasma weights must be finite and >= 0");
+      if (!std::isfinite(w[i]) || (w[i] < 0 && !mobile))
+        return fail(c, QSA_E_NONFINITE, "plasma weights must be finite and >= 0");
   qsa_status st0 = enter(c);
   if (st0 != QSA_OK) return st0;
   const double scale = 1.0 / c->p.plasma_w;
   qsa_status st = dispatch(c, [&] { return Engine<double>::upload_scaled(c, w, c->L.tmpl_qw, n, on_device, scale); },
                            [&] { return Engine<float>::upload_scaled(c, w, c->L.tmpl_qw, n, on_device, scale); });
   if (st != QSA_OK) return st;
+  if (mobile && c->p.ion_z != 1) {
+    // an ion's relative weight carries its charge: -Z |w|/plasma_w
+    st = dispatch(c, [&] { return Engine<double>::scale_negative(c, c->L.tmpl_qw, n, (double)c->p.ion_z); },
+                  [&] { return Engine<float>::scale_negative(c, c->L.tmpl_qw, n, (double)c->p.ion_z); });
+    if (st != QSA_OK) return st;
+  }
   c->drop_graphs();
   return leave(c);
 }

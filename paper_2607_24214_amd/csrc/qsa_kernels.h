@@ -61,6 +61,7 @@ struct Lane {
   const R* tmom[2];       // and u_x, u_y
   const R* tqw;           // and its weights relative to plasma_w (null: all 1)
   const R* ion;           // immobile ions' density at the nodes [ny][nx] (null: all 1)
+  R ion_s;                // -Z/M of the mobile ions (particles with a negative relative weight)
   const C2<R>* twx;     // transform tables
   const C2<R>* twy;
   const R* kx2;
@@ -143,6 +144,14 @@ __global__ void k_scaled_from_f64(const double* __restrict__ src, R* __restrict_
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t s = (int64_t)gridDim.x * blockDim.x;
   for (; i < n; i += s) dst[i] = (R)(src[i] * scale);
+}
+
+// Multiply the negative entries by z (a mobile ion's relative weight
+// becomes -Z times its weight).
+template <typename R>
+__global__ void k_scale_negative(R* __restrict__ p, int64_t n, R z) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (p[i] < R(0)) p[i] *= z;
 }
 
 template <typename R>
@@ -639,7 +648,9 @@ struct PlasmaArgs {
   R* uy;
   int np;
   R q;                // -w/(dx dy): rho - J_z per particle per unit area
-  const R* qw;        // per particle: its weight relative to w (null: all 1)
+  const R* qw;        // per particle: its weight relative to w (null: all 1);
+                      // negative for a mobile ion (-Z times its weight)
+  R ion_s;            // -Z/M of the mobile ions
   R* dep0;
   R* dep1;
   R* dep2;
@@ -667,6 +678,7 @@ __device__ __forceinline__ PlasmaArgs<R> plasma_args(const Lane<R>& L, int j) {
   a.np = L.np;
   a.q = L.q;
   a.qw = L.qw[set];
+  a.ion_s = L.ion_s;
   a.dep0 = L.dep;
   a.dep1 = L.dep + g.nperp;
   a.dep2 = L.dep + 2 * g.nperp;
@@ -701,7 +713,9 @@ __device__ __forceinline__ void lane_block(int& lane, int& b) {
 //   dx_perp/dxi = u_perp/G,
 //   du_x/dxi = a_x - B_y,  a_x = gamma d_x psi/G - u_y B_z/G,
 //   du_y/dxi = a_y + B_x,  a_y = gamma d_y psi/G + u_x B_z/G,
-// B_z being the wake's plus the uniform guide field g.b0z.
+// B_z being the wake's plus the uniform guide field g.b0z.  A mobile ion
+// (charge Z, mass M) has G = 1 - (Z/M) psi and both accelerations scaled by
+// s = -Z/M (s = 1 for an electron); species_scale gives s.
 // B_perp enters only through the last terms, and the midpoint position only
 // through u_perp/G: so the stage-1 a_x, a_y, the midpoint (x_s, y_s) and
 // G, d_x psi, d_y psi, B_z at the midpoint are the same in every predictor
@@ -709,31 +723,39 @@ __device__ __forceinline__ void lane_block(int& lane, int& b) {
 // values (and stores those eight when `store`); rk2_cached reloads them and
 // gathers only B_x, B_y at both stages.
 
-// The step from the cached parts and the four B_perp values.
 template <typename R>
-__device__ __forceinline__ void rk2_finish(R hh, double x, double y, R ux, R uy, R ax, R ay, R bx1, R by1,
+__device__ __forceinline__ R species_scale(const PlasmaArgs<R>& a, int p) {
+  return (a.qw && a.qw[p] < R(0)) ? a.ion_s : R(1);
+}
+
+// The step from the cached parts and the four B_perp values (sp: the
+// species' acceleration scale).
+template <typename R>
+__device__ __forceinline__ void rk2_finish(R hh, R sp, double x, double y, R ux, R uy, R ax, R ay, R bx1, R by1,
                                            R gs, R pxs, R pys, R bzs, R bxh, R byh, double& xn, double& yn,
                                            R& uxn, R& uyn) {
-  const R uxs = ux + R(0.5) * hh * (ax - by1);
-  const R uys = uy + R(0.5) * hh * (ay + bx1);
+  const R hs = hh * sp;
+  const R uxs = ux + R(0.5) * hs * (ax - by1);
+  const R uys = uy + R(0.5) * hs * (ay + bx1);
   const R iGs = R(1) / gs;
   const R gams = (R(1) + uxs * uxs + uys * uys + gs * gs) * R(0.5) * iGs;
   // positions advance in float64 by increments formed in R
   xn = x + (double)(hh * (uxs * iGs));
   yn = y + (double)(hh * (uys * iGs));
-  uxn = ux + hh * ((gams * pxs * iGs - uys * bzs * iGs) - byh);
-  uyn = uy + hh * ((gams * pys * iGs + uxs * bzs * iGs) + bxh);
+  uxn = ux + hs * ((gams * pxs * iGs - uys * bzs * iGs) - byh);
+  uyn = uy + hs * ((gams * pys * iGs + uxs * bzs * iGs) + bxh);
 }
 
 template <typename R>
 __device__ __forceinline__ void rk2_full(const Geo<R>& g, const PlasmaArgs<R>& a, int p, bool store, double x,
                                          double y, R ux, R uy, double& xn, double& yn, R& uxn, R& uyn) {
   const R hh = a.h;
+  const R sp = species_scale(a, p);
   R ax, ay, bx1, by1;
   double xs, ys;
   {
     const Stencil<R> s = stencil2(g, x, y);
-    const R G = R(1) + gather(a.F0[0], s);
+    const R G = R(1) + sp * gather(a.F0[0], s);
     if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
     const R iG = R(1) / G;
     const R gam = (R(1) + ux * ux + uy * uy + G * G) * R(0.5) * iG;
@@ -746,7 +768,7 @@ __device__ __forceinline__ void rk2_full(const Geo<R>& g, const PlasmaArgs<R>& a
     ys = y + (double)(R(0.5) * hh * (uy * iG));
   }
   const Stencil<R> s = stencil2(g, xs, ys);
-  const R gs = R(1) + gather(a.H[0], s);
+  const R gs = R(1) + sp * gather(a.H[0], s);
   if (!(gs > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
   const R pxs = gather(a.H[1], s), pys = gather(a.H[2], s), bzs = gather(a.H[5], s) + g.b0z;
   const R bxh = gather(a.H[3], s), byh = gather(a.H[4], s);
@@ -760,7 +782,7 @@ __device__ __forceinline__ void rk2_full(const Geo<R>& g, const PlasmaArgs<R>& a
     a.cval[4][p] = pys;
     a.cval[5][p] = bzs;
   }
-  rk2_finish(hh, x, y, ux, uy, ax, ay, bx1, by1, gs, pxs, pys, bzs, bxh, byh, xn, yn, uxn, uyn);
+  rk2_finish(hh, sp, x, y, ux, uy, ax, ay, bx1, by1, gs, pxs, pys, bzs, bxh, byh, xn, yn, uxn, uyn);
 }
 
 template <typename R>
@@ -773,7 +795,8 @@ __device__ __forceinline__ void rk2_cached(const Geo<R>& g, const PlasmaArgs<R>&
   const R bx1 = gather(a.F0[3], s1), by1 = gather(a.F0[4], s1);
   const Stencil<R> s2 = stencil2(g, xs, ys);
   const R bxh = gather(a.H[3], s2), byh = gather(a.H[4], s2);
-  rk2_finish(a.h, x, y, ux, uy, ax, ay, bx1, by1, gs, pxs, pys, bzs, bxh, byh, xn, yn, uxn, uyn);
+  rk2_finish(a.h, species_scale(a, p), x, y, ux, uy, ax, ay, bx1, by1, gs, pxs, pys, bzs, bxh, byh, xn, yn, uxn,
+             uyn);
 }
 
 // Value of lane i - N of the wavefront within its row of 16 lanes (DPP
@@ -897,7 +920,7 @@ __device__ __forceinline__ void plasma_particle(const Geo<R>& g, const PlasmaArg
     py = a.y[p];
     const R ux = a.ux[p], uy = a.uy[p];
     const Stencil<R> s = stencil2(g, px, py);
-    const R G = R(1) + gather(a.F0[0], s);
+    const R G = R(1) + species_scale(a, p) * gather(a.F0[0], s);
     if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
     const R gam = (R(1) + ux * ux + uy * uy + G * G) / (R(2) * G);
     const R qg = q / G;
@@ -911,7 +934,7 @@ __device__ __forceinline__ void plasma_particle(const Geo<R>& g, const PlasmaArg
     else
       rk2_cached(g, a, p, a.x[p], a.y[p], a.ux[p], a.uy[p], px, py, uxn, uyn);
     const Stencil<R> s = stencil2(g, px, py);
-    const R G = R(1) + gather(a.psit, s);
+    const R G = R(1) + species_scale(a, p) * gather(a.psit, s);
     if (!(G > R(QSA_GMIN))) atomicOr(a.err, ERR_BREAKDOWN);
     const R qg = q / G;
     v[0] = qg * uxn;

@@ -35,7 +35,7 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
                 kappa2: float = 0.75, pipeline: int = 1, adjoint_steps: int = 0,
                 ckpt_every: int = 0, field_pack: bool = True,
                 plasma_weights: bool = False, lean_pipeline: bool = False,
-                b0z: float = 0.0) -> L.QSAParams:
+                b0z: float = 0.0, ion_m: float = 0.0, ion_z: int = 1) -> L.QSAParams:
     """species: sequence of (Z, M); pipeline: beam steps in flight (1 = off);
     adjoint_steps: most steps qsa_adjoint_sweep differentiates (0 = none);
     ckpt_every: the adjoint's plasma checkpoint stride in slices (0 = 16);
@@ -44,7 +44,8 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
     weight per plasma macro-particle (Sim.load_plasma loads them when the
     template's "w" is an array); lean_pipeline: steps in flight without a
     second copy of the beam (read_beam then returns storage order); b0z: a
-    uniform external magnetic field along the propagation axis."""
+    uniform external magnetic field along the propagation axis; ion_m, ion_z:
+    mass (in m_e; 0 = immobile ions) and charge number of mobile plasma ions."""
     p = L.QSAParams()
     p.nx, p.ny, p.nxi = nx, ny, nxi
     p.precision = _PREC[precision]
@@ -59,6 +60,8 @@ def make_params(nx: int, ny: int, nxi: int, dx: float, dy: float, dxi: float, dt
     p.plasma_weights = 1 if plasma_weights else 0
     p.lean_pipeline = 1 if lean_pipeline else 0
     p.b0z = float(b0z)
+    p.ion_m = float(ion_m)
+    p.ion_z = int(ion_z)
     for i, (Z, M) in enumerate(species):
         p.species[i].Z = int(Z)
         p.species[i].M = float(M)
@@ -79,8 +82,9 @@ def params_from_workload(wl, precision: Optional[str] = None,
                        wl.dx * wl.dy / wl.plasma_ppc, caps, precision or wl.precision,
                        wl.n_corr, wl.kappa2, pipeline, adjoint_steps, min(int(ck), wl.nxi), field_pack,
                        (getattr(wl, "plasma_w_spread", 0.0) > 0.0 or getattr(wl, "plasma_n0", 1.0) != 1.0
-                        or getattr(wl, "plasma_mod", 0.0) != 0.0), lean_pipeline,
-                       float(getattr(wl, "b0z", 0.0)))
+                        or getattr(wl, "plasma_mod", 0.0) != 0.0 or getattr(wl, "ion_m", 0.0) > 0.0),
+                       lean_pipeline, float(getattr(wl, "b0z", 0.0)), float(getattr(wl, "ion_m", 0.0)),
+                       int(getattr(wl, "ion_z", 1)))
 
 
 class Sim:
@@ -137,6 +141,17 @@ class Sim:
             raise ValueError("per-particle plasma weights need a context made with plasma_weights")
         self._check(self.lib.qsa_load_plasma(self.ctx, *[C.c_void_p(_ptr(a)) for a, _ in arrs],
                                              n, on_dev))
+        kind = plasma.get("kind")
+        if kind is not None:
+            # the library marks a mobile ion (kind 1) by a negative weight
+            if torch.is_tensor(w) or torch.is_tensor(kind):
+                kt = torch.as_tensor(kind)
+                wt = torch.as_tensor(w, dtype=torch.float64, device=kt.device).expand(kt.shape)
+                w = torch.where(kt > 0, -wt, wt)
+            else:
+                sign = np.where(np.asarray(kind) > 0, -1.0, 1.0)
+                w = sign * np.broadcast_to(np.asarray(w, dtype=np.float64), sign.shape)
+            per_particle = True
         if per_particle:
             wa, wdev = _f64(w)
             self._check(self.lib.qsa_load_plasma_weights(self.ctx, C.c_void_p(_ptr(wa)), wa.shape[0], wdev))

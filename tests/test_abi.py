@@ -146,3 +146,14 @@ def test_guide_field_validated():
     # the adjoint takes no external field
     assert lib.qsa_workspace_bytes(C.byref(_params(adjoint_steps=2, b0z=0.5))) == 0
     assert lib.qsa_workspace_bytes(C.byref(_params(adjoint_steps=2))) > 0
+
+
+def test_mobile_ions_validated():
+    from paper_2607_24214_amd import _lib as L
+    lib = L.lib()
+    assert lib.qsa_workspace_bytes(C.byref(_params(ion_m=4.0, plasma_weights=True))) > 0
+    assert lib.qsa_workspace_bytes(C.byref(_params(ion_m=4.0))) == 0             # needs plasma_weights
+    assert lib.qsa_workspace_bytes(C.byref(_params(ion_m=-1.0, plasma_weights=True))) == 0
+    assert lib.qsa_workspace_bytes(C.byref(_params(ion_m=float("inf"), plasma_weights=True))) == 0
+    assert lib.qsa_workspace_bytes(C.byref(_params(ion_m=4.0, ion_z=0, plasma_weights=True))) == 0
+    assert lib.qsa_workspace_bytes(C.byref(_params(ion_m=4.0, ion_z=65, plasma_weights=True))) == 0
