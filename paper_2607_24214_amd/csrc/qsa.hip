@@ -218,7 +218,7 @@ Layout make_layout(const qsa_params& p) {
     S.pack_ring = (L.nset > 1) ? QSA_PACK_RING : (p.no_field_pack ? 0 : p.nxi);
     S.fpack = S.pack_ring ? c.take((size_t)S.pack_ring * nperp * pack_stride_bytes(rs)) : 0;
     S.base = (L.nset > 1) ? c.take((size_t)QSA_MAX_SPECIES * (p.ny + 1) * sizeof(int)) : 0;
-    for (int i = 0; i < 2; ++i) S.cpos[i] = c.take(p.n_plasma * sizeof(double));
+    for (int i = 0; i < 2; ++i) S.cpos[i] = c.take(p.n_plasma * rs);
     for (int i = 0; i < 6; ++i) S.cval[i] = c.take(p.n_plasma * rs);
   }
   const size_t nrows = (size_t)p.nxi * p.ny;
@@ -873,7 +873,7 @@ struct Engine {
     a.ode = c->at<double>(S.ode);
     a.fpack = S.fpack ? c->at<R>(S.fpack) : nullptr;
     a.pack_ring = S.pack_ring;
-    for (int i = 0; i < 2; ++i) a.cpos[i] = c->at<double>(S.cpos[i]);
+    for (int i = 0; i < 2; ++i) a.cpos[i] = c->at<R>(S.cpos[i]);
     for (int i = 0; i < 6; ++i) a.cval[i] = c->at<R>(S.cval[i]);
     return a;
   }

@@ -90,7 +90,9 @@ struct Lane {
                         // [pack_ring][ny][nx][pack_stride<R>()], slice j in slot
                         // j % pack_ring
   int pack_ring;        // QSA_PACK_RING (steps in flight) or nxi (every slice)
-  double* cpos[2];      // per plasma particle: the RK2 midpoint x, y of the slice
+  R* cpos[2];           // per plasma particle: the RK2 midpoint x, y of the slice
+                        // (float64), or in float32 its offset from x, y (formed
+                        // in float32, so x + offset is the midpoint exactly)
   R* cval[6];           // and the parts of its RK2 step that B_perp does not
                         // enter (see rk2_full), written by the first predictor
                         // pass of a slice, read by the later ones and the final
@@ -661,7 +663,7 @@ struct PlasmaArgs {
   R h;
   const int* prow;    // [ny + 1] first particle of each cell row (state sorted by cell)
   R* ppart;           // partial node rows [ny][4][NC][nx]
-  double* cpos[2];    // RK2 cache of the slice (see rk2_full)
+  R* cpos[2];         // RK2 cache of the slice (see rk2_full)
   R* cval[6];
 };
 
@@ -751,7 +753,7 @@ __device__ __forceinline__ void rk2_full(const Geo<R>& g, const PlasmaArgs<R>& a
                                          double y, R ux, R uy, double& xn, double& yn, R& uxn, R& uyn) {
   const R hh = a.h;
   const R sp = species_scale(a, p);
-  R ax, ay, bx1, by1;
+  R ax, ay, bx1, by1, dxs, dys;
   double xs, ys;
   {
     const Stencil<R> s = stencil2(g, x, y);
@@ -764,8 +766,10 @@ __device__ __forceinline__ void rk2_full(const Geo<R>& g, const PlasmaArgs<R>& a
     ay = gam * gather(a.F0[2], s) * iG + ux * bz * iG;
     bx1 = gather(a.F0[3], s);
     by1 = gather(a.F0[4], s);
-    xs = x + (double)(R(0.5) * hh * (ux * iG));
-    ys = y + (double)(R(0.5) * hh * (uy * iG));
+    dxs = R(0.5) * hh * (ux * iG);
+    dys = R(0.5) * hh * (uy * iG);
+    xs = x + (double)dxs;
+    ys = y + (double)dys;
   }
   const Stencil<R> s = stencil2(g, xs, ys);
   const R gs = R(1) + sp * gather(a.H[0], s);
@@ -773,8 +777,13 @@ __device__ __forceinline__ void rk2_full(const Geo<R>& g, const PlasmaArgs<R>& a
   const R pxs = gather(a.H[1], s), pys = gather(a.H[2], s), bzs = gather(a.H[5], s) + g.b0z;
   const R bxh = gather(a.H[3], s), byh = gather(a.H[4], s);
   if (store) {
-    a.cpos[0][p] = xs;
-    a.cpos[1][p] = ys;
+    if constexpr (sizeof(R) == 4) {
+      a.cpos[0][p] = dxs;
+      a.cpos[1][p] = dys;
+    } else {
+      a.cpos[0][p] = xs;
+      a.cpos[1][p] = ys;
+    }
     a.cval[0][p] = ax;
     a.cval[1][p] = ay;
     a.cval[2][p] = gs;
@@ -788,7 +797,14 @@ __device__ __forceinline__ void rk2_full(const Geo<R>& g, const PlasmaArgs<R>& a
 template <typename R>
 __device__ __forceinline__ void rk2_cached(const Geo<R>& g, const PlasmaArgs<R>& a, int p, double x, double y,
                                            R ux, R uy, double& xn, double& yn, R& uxn, R& uyn) {
-  const double xs = a.cpos[0][p], ys = a.cpos[1][p];
+  double xs, ys;
+  if constexpr (sizeof(R) == 4) {
+    xs = x + (double)a.cpos[0][p];
+    ys = y + (double)a.cpos[1][p];
+  } else {
+    xs = a.cpos[0][p];
+    ys = a.cpos[1][p];
+  }
   const R ax = a.cval[0][p], ay = a.cval[1][p], gs = a.cval[2][p];
   const R pxs = a.cval[3][p], pys = a.cval[4][p], bzs = a.cval[5][p];
   const Stencil<R> s1 = stencil2(g, x, y);
