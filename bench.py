@@ -557,6 +557,9 @@ def run_workload(wl, precision: str, pipeline: int, steps: int, warmup: int, arg
                       "species": [{"Z": sp.Z, "alpha": sp.alpha, "ppc": sp.ppc} for sp in wl.species],
                       "gamma_b": wl.gamma_b, "n_corr": wl.n_corr, "steps_in_flight": depth, "autotuned": tuned,
                       "resort_every": resort, "lean_pipeline": lean,
+                      "precision_note": ("float32 particle momenta, fields, spectra and beam state; plasma "
+                                         "positions, beam xi and the LDS deposit tiles in float64"
+                                         if precision == "f32" else "float64 throughout"),
                       "step": f"beam source deposit + {wl.nxi}-slice sweep + Boris beam push"},
            "sweep_only": {"ms": 1e3 * t_sweep, "updates_per_s": wl.n_plasma * wl.nxi / t_sweep},
            "roofline": roofline, "diagnostics": diag}
