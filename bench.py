@@ -8,12 +8,14 @@ per species, u_perp ~ N(0, 1), float32): the largest workload one GPU holds.
 A step is one beam step: the beam source deposit of its 4.29e9 particles,
 the quasistatic sweep over 2048 slices (K = 3 predictor-corrector
 iterations) and the Boris push.  The metric is plasma particle-slice
-updates per second over whole steps.  Its workspace (217 GiB) leaves no
-room for beam steps in flight, so steps run one at a time.
+updates per second over whole steps.  A second copy of its 128 GiB beam
+does not fit, so it runs as many beam steps in flight as the device's memory
+holds on a lean pipeline that keeps no copy (5; lane k of a group sweeps 8
+slices behind lane k - 1 in the same launches).
 
 The 3D workload 256 x 256 x 512 (float64 and float32, 8 beam steps in
-flight: lane k of a group sweeps 8 slices behind lane k - 1 in the same
-launches) is timed too, as extra entries.
+flight), the 64 x 128 slab and the 64-instance batched scan are timed too,
+as extra entries.
 
 Prints one JSON line with the measured rate, a roofline entry for the
 dominant kernel (timed with HIP events on the library's stream) and the
