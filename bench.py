@@ -386,6 +386,23 @@ def b_alg(wl, rsize: int) -> float:
     return state * rsize + grid * rsize / ppc
 
 
+# Floating-point operations per plasma particle-slice update of the sweep at
+# K = 3, counted from the kernels (a division counted as one operation): the
+# rho - J_z deposit 12, the J stage (psi gather, G, gamma, three deposits) 40,
+# the first predictor pass (two stencils, twelve gathers, the RK2 step, the
+# predicted psi and two deposits) 190, each later pass from the RK2 cache 105,
+# the final advance 90; plus the spectral solves (about 21 real 2D
+# transforms per slice at 2.5 N log2 N each) shared by the particles.
+FLOP_PARTICLE = 12 + 40 + 190 + 2 * 105 + 90
+FLOP_PEAK_TFS = {"f32": 157.3, "f64": 78.6}
+
+
+def flop_per_update(wl) -> float:
+    n = wl.nx * wl.ny
+    fft = 21 * 2.5 * n * math.log2(n)
+    return FLOP_PARTICLE + fft / wl.n_plasma
+
+
 def load_beam_in_ranges(sim, wl, slices_per_range: int = 8):
     """Generate the beam range by range of slices on host threads (numpy
     releases the GIL while it draws and fills arrays) and hand each range to
@@ -552,6 +569,8 @@ def run_workload(wl, precision: str, pipeline: int, steps: int, warmup: int, arg
         "path_alg_bytes_per_update": ba,
         "path_achieved_GB_s": path_gbs,
         "path_frac": path_gbs / HBM_PEAK_GBS,
+        "path_flop_per_update": flop_per_update(wl),
+        "path_alu_frac": value * flop_per_update(wl) / (FLOP_PEAK_TFS[precision] * 1e12),
     }
     out = {"value": value, "ms_per_step": ms_step, "steps": steps, "warmup": warmup, "dtype": precision,
            "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nxi": wl.nxi,
