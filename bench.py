@@ -43,8 +43,8 @@ HBM_PEAK_GBS = 8000.0
 # many steps (pair 512^2 x 2048 in float32: 1059.5 ms/step never, 1034.0 every
 # 4 or 3, 1042.9 every 2, over 10 steps after 2 of warm-up)
 RESORT_EVERY = 4
-TRAFFIC_FILES = (os.path.join(ROOT, "profiles", "traffic_push_pred_pair512_f32.json"),
-                 os.path.join(ROOT, "profiles", "traffic_push_pred_cube256_f64.json"))
+TRAFFIC_FILES = tuple(os.path.join(ROOT, "profiles", f"traffic_push_pred_{w}.json")
+                      for w in ("pair512_f32", "cube256_f64", "cube256_f32"))
 KERNEL_SOURCES = ("paper_2607_24214_amd/csrc/qsa_kernels.h", "paper_2607_24214_amd/csrc/qsa_device.h")
 
 
