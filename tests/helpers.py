@@ -87,3 +87,17 @@ def scale_floor(*refs, frac: float = 1e-3):
         for j in range(ref[names[0]].shape[0]):
             s = max(s, max(float(np.linalg.norm(ref[f][j])) for f in names))
     return frac * s
+
+
+def matched_kappa2(wl) -> float:
+    """Helmholtz shift of the B_perp iteration matched to the plasma: the
+    predicted current responds to B_perp with (3/4) n_eff, n_eff = sum over
+    the plasma species of Z^2 n/M (electrons at the mean density, plus
+    mobile ions of charge Z and mass M at 1/Z of it), so kappa^2 = 3 n_eff/4
+    zeroes the iteration's gain at k = 0 (3/4 for the unit-density plasma
+    of the benchmark workloads)."""
+    n0 = getattr(wl, "plasma_n0", 1.0)
+    n_eff = n0
+    if getattr(wl, "ion_m", 0.0) > 0.0:
+        n_eff += wl.ion_z * n0 / wl.ion_m
+    return 0.75 * n_eff

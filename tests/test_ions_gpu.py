@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import qsa_workloads as W
-from tests.helpers import OUT_FIELDS, run_gpu, run_oracle, slice_errors
+from tests.helpers import OUT_FIELDS, matched_kappa2, run_gpu, run_oracle, slice_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -15,7 +15,9 @@ def _wl(**kw):
     base = dict(dt=20.0, plasma_uth=0.01, ion_m=4.0, ion_z=1,
                 species=(W.Species(Z=-1, alpha=0.05, ppc=2, sigma_perp=1e-2),))
     base.update(kw)
-    return W.small_3d(32, 16, 24).with_(**base)
+    wl = W.small_3d(32, 16, 24).with_(**base)
+    # the B_perp iteration's shift matched to electrons plus mobile ions
+    return wl.with_(kappa2=matched_kappa2(wl))
 
 
 @pytest.mark.parametrize("kw,steps,prec,tol", [
@@ -60,3 +62,18 @@ def test_mobile_ions_steps_in_flight_match_one_at_a_time():
     err, where = slice_errors(out[1], out[0])
     print(f"[ions] 4 steps in flight vs one at a time: {err:.3e} at {where}", flush=True)
     assert err <= 1e-10, (err, where)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_slab_with_mobile_ions_guide_field_and_density(prec, tol):
+    """The slab geometry (ny = 1) with every plasma option at once: mobile
+    ions of charge 2, a guide field and a modulated density."""
+    wl = W.slab_electron().with_(nxi=64, ion_m=6.0, ion_z=2, b0z=0.4, plasma_uth=0.01,
+                                  plasma_n0=1.1, plasma_mod=0.25, plasma_mod_mx=2)
+    wl = wl.with_(kappa2=matched_kappa2(wl))
+    so, ref = run_oracle(wl, 1)
+    sg, got = run_gpu(wl, 1, precision=prec)
+    err, where = slice_errors(got, ref)
+    print(f"[ions] slab, all plasma options, {prec}: {err:.3e} at {where}", flush=True)
+    assert err <= tol, (err, where)
+    sg.close()

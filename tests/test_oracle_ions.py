@@ -72,3 +72,28 @@ def test_very_heavy_ions_are_the_immobile_background():
     c = O.Sim(light, W.plasma_template(light), W.beam(light))
     c.beam_step(1)
     assert float((c.sweep() - fa).abs().max()) > 1e-3 * scale
+
+
+def test_iteration_needs_the_shift_matched_to_the_plasma():
+    """With a denser plasma and mobile ions the B_perp iteration's gain at
+    k = 0 is (kappa^2 - 3 n_eff/4)/kappa^2: at the unit-density shift 3/4 and
+    n_eff = 1.1 + 2 (1.1/2)/6 = 1.47 the iteration diverges at first (K = 3
+    is hundreds of times off K = 30); at kappa^2 = 3 n_eff/4 it contracts:
+    K = 3 is within about 1% of K = 30 and K = 5 within 1e-4."""
+    from tests.helpers import matched_kappa2
+    wl = W.slab_electron().with_(nxi=48, ion_m=6.0, ion_z=2, plasma_n0=1.1, plasma_uth=0.01)
+    g = O.Grid.of(wl)
+    pl = O.to_torch(W.plasma_template(wl))
+    src = O.beam_sources(g, [O.to_torch(b) for b in W.beam(wl)], [-1])
+    k2 = matched_kappa2(wl)
+    assert abs(k2 - 0.75 * (1.1 + 2 * 1.1 / 6.0)) < 1e-12
+
+    def err(kappa2, k):
+        kw = dict(ion_z=wl.ion_z, ion_m=wl.ion_m)
+        fk = O.slice_sweep(g, pl, src, n_corr=k, kappa2=kappa2, **kw)
+        f30 = O.slice_sweep(g, pl, src, n_corr=30, kappa2=kappa2, **kw)
+        return float((fk[O.BY] - f30[O.BY]).norm() / f30[O.BY].norm())
+    matched, unit = err(k2, 3), err(0.75, 3)
+    assert matched < 2e-2, matched
+    assert err(k2, 5) < 1e-4
+    assert unit > 1000 * matched, (unit, matched)
