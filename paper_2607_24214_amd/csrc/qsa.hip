@@ -127,7 +127,7 @@ struct SetLayout {
   int pack_ring;  // slices fpack holds
   size_t hist;   // new-row count matrix of this set's slab pushes, and row starts
   size_t base;
-  size_t cpos[2], cval[6];  // RK2 cache of the slice's plasma particles
+  size_t rk2c;   // RK2 cache of the slice's plasma particles (8 values each)
 };
 
 // Byte offsets of every device array inside the workspace.
@@ -218,8 +218,7 @@ Layout make_layout(const qsa_params& p) {
     S.pack_ring = (L.nset > 1) ? QSA_PACK_RING : (p.no_field_pack ? 0 : p.nxi);
     S.fpack = S.pack_ring ? c.take((size_t)S.pack_ring * nperp * pack_stride_bytes(rs)) : 0;
     S.base = (L.nset > 1) ? c.take((size_t)QSA_MAX_SPECIES * (p.ny + 1) * sizeof(int)) : 0;
-    for (int i = 0; i < 2; ++i) S.cpos[i] = c.take(p.n_plasma * rs);
-    for (int i = 0; i < 6; ++i) S.cval[i] = c.take(p.n_plasma * rs);
+    S.rk2c = c.take(p.n_plasma * 8 * rs);
   }
   const size_t nrows = (size_t)p.nxi * p.ny;
   const size_t nkeys = nrows * (nx_chunks_of(p.nx)) + 1;   // sort keys, the last for inert particles
@@ -873,8 +872,7 @@ struct Engine {
     a.ode = c->at<double>(S.ode);
     a.fpack = S.fpack ? c->at<R>(S.fpack) : nullptr;
     a.pack_ring = S.pack_ring;
-    for (int i = 0; i < 2; ++i) a.cpos[i] = c->at<R>(S.cpos[i]);
-    for (int i = 0; i < 6; ++i) a.cval[i] = c->at<R>(S.cval[i]);
+    a.rk2c = c->at<R>(S.rk2c);
     return a;
   }
 

@@ -90,10 +90,11 @@ struct Lane {
                         // [pack_ring][ny][nx][pack_stride<R>()], slice j in slot
                         // j % pack_ring
   int pack_ring;        // QSA_PACK_RING (steps in flight) or nxi (every slice)
-  R* cpos[2];           // per plasma particle: the RK2 midpoint x, y of the slice
+  R* rk2c;              // RK2 cache of the slice, one record of 8 values per
+                        // plasma particle (see rk2_full): the midpoint x, y
                         // (float64), or in float32 its offset from x, y (formed
-                        // in float32, so x + offset is the midpoint exactly)
-  R* cval[6];           // and the parts of its RK2 step that B_perp does not
+                        // in float32, so x + offset is the midpoint exactly),
+                        // then the parts of its RK2 step that B_perp does not
                         // enter (see rk2_full), written by the first predictor
                         // pass of a slice, read by the later ones and the final
                         // advance
@@ -663,8 +664,7 @@ struct PlasmaArgs {
   R h;
   const int* prow;    // [ny + 1] first particle of each cell row (state sorted by cell)
   R* ppart;           // partial node rows [ny][4][NC][nx]
-  R* cpos[2];         // RK2 cache of the slice (see rk2_full)
-  R* cval[6];
+  R* rk2c;            // RK2 cache of the slice, 8 values per particle (see rk2_full)
 };
 
 template <typename R>
@@ -692,8 +692,7 @@ __device__ __forceinline__ PlasmaArgs<R> plasma_args(const Lane<R>& L, int j) {
   a.h = L.h;
   a.prow = L.prow;
   a.ppart = L.ppart;
-  for (int q = 0; q < 2; ++q) a.cpos[q] = L.cpos[q];
-  for (int q = 0; q < 6; ++q) a.cval[q] = L.cval[q];
+  a.rk2c = L.rk2c;
   return a;
 }
 
@@ -724,6 +723,44 @@ __device__ __forceinline__ void lane_block(int& lane, int& b) {
 // pass of a slice and in its final advance.  rk2_full gathers all twelve
 // values (and stores those eight when `store`); rk2_cached reloads them and
 // gathers only B_x, B_y at both stages.
+
+// A particle's RK2 cache record (8 values, 32 bytes in float32 and 64 in
+// float64, records aligned to their size): 16-byte vector stores and loads,
+// so that a wavefront moves its 64 consecutive records in 2 (or 4)
+// instructions instead of 8.
+template <typename R>
+__device__ __forceinline__ void rec8_store(R* __restrict__ r, const R (&v)[8]) {
+  if constexpr (sizeof(R) == 4) {
+    typedef float F4 __attribute__((ext_vector_type(4)));
+    F4* q = reinterpret_cast<F4*>(r);
+    q[0] = F4{v[0], v[1], v[2], v[3]};
+    q[1] = F4{v[4], v[5], v[6], v[7]};
+  } else {
+    typedef double D2 __attribute__((ext_vector_type(2)));
+    D2* q = reinterpret_cast<D2*>(r);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = D2{v[2 * k], v[2 * k + 1]};
+  }
+}
+template <typename R>
+__device__ __forceinline__ void rec8_load(const R* __restrict__ r, R (&v)[8]) {
+  if constexpr (sizeof(R) == 4) {
+    typedef float F4 __attribute__((ext_vector_type(4)));
+    const F4* q = reinterpret_cast<const F4*>(r);
+    const F4 a = q[0], b = q[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+    typedef double D2 __attribute__((ext_vector_type(2)));
+    const D2* q = reinterpret_cast<const D2*>(r);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const D2 t = q[k];
+      v[2 * k] = t.x;
+      v[2 * k + 1] = t.y;
+    }
+  }
+}
 
 template <typename R>
 __device__ __forceinline__ R species_scale(const PlasmaArgs<R>& a, int p) {
@@ -777,19 +814,21 @@ __device__ __forceinline__ void rk2_full(const Geo<R>& g, const PlasmaArgs<R>& a
   const R pxs = gather(a.H[1], s), pys = gather(a.H[2], s), bzs = gather(a.H[5], s) + g.b0z;
   const R bxh = gather(a.H[3], s), byh = gather(a.H[4], s);
   if (store) {
+    R rec[8];
     if constexpr (sizeof(R) == 4) {
-      a.cpos[0][p] = dxs;
-      a.cpos[1][p] = dys;
+      rec[0] = dxs;
+      rec[1] = dys;
     } else {
-      a.cpos[0][p] = xs;
-      a.cpos[1][p] = ys;
+      rec[0] = xs;
+      rec[1] = ys;
     }
-    a.cval[0][p] = ax;
-    a.cval[1][p] = ay;
-    a.cval[2][p] = gs;
-    a.cval[3][p] = pxs;
-    a.cval[4][p] = pys;
-    a.cval[5][p] = bzs;
+    rec[2] = ax;
+    rec[3] = ay;
+    rec[4] = gs;
+    rec[5] = pxs;
+    rec[6] = pys;
+    rec[7] = bzs;
+    rec8_store(a.rk2c + (size_t)p * 8, rec);
   }
   rk2_finish(hh, sp, x, y, ux, uy, ax, ay, bx1, by1, gs, pxs, pys, bzs, bxh, byh, xn, yn, uxn, uyn);
 }
@@ -797,16 +836,18 @@ __device__ __forceinline__ void rk2_full(const Geo<R>& g, const PlasmaArgs<R>& a
 template <typename R>
 __device__ __forceinline__ void rk2_cached(const Geo<R>& g, const PlasmaArgs<R>& a, int p, double x, double y,
                                            R ux, R uy, double& xn, double& yn, R& uxn, R& uyn) {
+  R rec[8];
+  rec8_load(a.rk2c + (size_t)p * 8, rec);
   double xs, ys;
   if constexpr (sizeof(R) == 4) {
-    xs = x + (double)a.cpos[0][p];
-    ys = y + (double)a.cpos[1][p];
+    xs = x + (double)rec[0];
+    ys = y + (double)rec[1];
   } else {
-    xs = a.cpos[0][p];
-    ys = a.cpos[1][p];
+    xs = rec[0];
+    ys = rec[1];
   }
-  const R ax = a.cval[0][p], ay = a.cval[1][p], gs = a.cval[2][p];
-  const R pxs = a.cval[3][p], pys = a.cval[4][p], bzs = a.cval[5][p];
+  const R ax = rec[2], ay = rec[3], gs = rec[4];
+  const R pxs = rec[5], pys = rec[6], bzs = rec[7];
   const Stencil<R> s1 = stencil2(g, x, y);
   const R bx1 = gather(a.F0[3], s1), by1 = gather(a.F0[4], s1);
   const Stencil<R> s2 = stencil2(g, xs, ys);
