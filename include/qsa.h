@@ -4,7 +4,7 @@
  * Physics and units (paper, "Quasistatic model" section): a relativistic beam
  * of species s (charge Z_s e, mass M_s m_e, density ratio alpha_s = n_bs/n_p,
  * common Lorentz factor gamma_b) crosses a plasma of initially cold or warm
- * electrons over immobile ions.  Comoving coordinates (xi, tau) = (ct - z, t);
+ * electrons over ions (immobile unless qsa_params.ion_m > 0).  Comoving coordinates (xi, tau) = (ct - z, t);
  * the plasma/field response is quasistatic in xi at fixed tau and the beam
  * evolves slowly in tau.  All quantities are normalized: lengths to c/omega_p,
  * times to 1/omega_p, densities to n_p, momenta u = p/(M m_e c), fields to
@@ -17,7 +17,10 @@
  * defined after its Eq. (2)), E_z, B_z and B_perp by FFT, and advances the
  * plasma macro-particles to the next slice with a predictor-corrector; the
  * beam is then advanced by one Boris step of length dt in the stored 3D
- * fields.
+ * fields.  Beyond the paper's runs (its conclusion's outlook) a context can
+ * add a uniform guide field along z (qsa_params.b0z), a plasma density
+ * profile with matching immobile ions (per-particle weights and
+ * qsa_load_ions), and mobile plasma ions (qsa_params.ion_z, ion_m).
  *
  * Memory and ownership
  *   - The caller owns one device workspace of qsa_workspace_bytes() bytes
