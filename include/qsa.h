@@ -8,8 +8,9 @@
  * coordinates (xi, tau) = (ct - z, t); the plasma/field response is
  * quasistatic in xi at fixed tau and the beam evolves slowly in tau.  All
  * quantities are normalized: lengths to c/omega_p, times to 1/omega_p,
- * densities to n_p, momenta u = p/(M m_e c), fields to m_e c omega_p/e.  The propagation axis is z (the paper's x); transverse
- * boundaries are periodic and xi is open ("PIC simulations" section).
+ * densities to n_p, momenta u = p/(M m_e c), fields to m_e c omega_p/e.
+ * The propagation axis is z (the paper's x); transverse boundaries are
+ * periodic and xi is open ("PIC simulations" section).
  *
  * One context = one simulation box on one GPU.  Per xi slice the library
  * deposits the plasma charge and current, solves the transverse
